@@ -1,0 +1,309 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by the mathematics:
+closed forms, identities, invariants, special cases and brute force.  No GPU."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.helpers import mink_cfg
+
+KS = dict(coords=1, a=0.9375, gam=4.0 / 3.0, n=(8, 8, 8), ng=3, recon=1, riemann=1,
+          bc=(0, 0, 1, 1, 2, 2), xlo=(0.0, 0.0, 0.0), xhi=(1.0, math.pi, 2 * math.pi))
+
+
+def _rand_points(rng, n):
+    x1 = rng.uniform(math.log(1.1), math.log(60.0), n)
+    x2 = rng.uniform(0.05, math.pi - 0.05, n)
+    return x1, x2
+
+
+# ---------------------------------------------------------------- geometry (Sec. 2.2)
+
+def test_ks_determinant_closed_form():
+    rng = np.random.default_rng(0)
+    for x1, x2 in zip(*_rand_points(rng, 200)):
+        gcov, gcon, gdet, alpha, _ = oracle.geom_point(KS, x1, x2)
+        r = math.exp(x1)
+        sig = r * r + KS["a"] ** 2 * math.cos(x2) ** 2
+        assert gdet == pytest.approx(r * sig * math.sin(x2), rel=1e-13)
+        assert np.allclose(gcov @ gcon, np.eye(4), atol=1e-12)
+        # g^{tt} = -(1 + 2r/Sigma) in Kerr-Schild (unchanged by x1 = ln r)
+        assert gcon[0, 0] == pytest.approx(-(1 + 2 * r / sig), rel=1e-13)
+        assert alpha == pytest.approx(1 / math.sqrt(1 + 2 * r / sig), rel=1e-13)
+
+
+def test_schwarzschild_limit_is_ingoing_eddington_finkelstein():
+    cfg = dict(KS, a=0.0)
+    for x1, x2 in [(0.3, 0.7), (2.0, 1.9), (1.1, 0.2)]:
+        gcov, *_ = oracle.geom_point(cfg, x1, x2)
+        r = math.exp(x1)
+        s2 = math.sin(x2) ** 2
+        want = np.zeros((4, 4))
+        want[0, 0] = -(1 - 2 / r)
+        want[0, 1] = want[1, 0] = (2 / r) * r
+        want[1, 1] = (1 + 2 / r) * r * r
+        want[2, 2] = r * r
+        want[3, 3] = r * r * s2
+        assert np.allclose(gcov, want, rtol=1e-14, atol=1e-14)
+
+
+def test_minkowski_connection_vanishes():
+    cfg = mink_cfg((4, 4, 4))
+    gcov, gcon, gdet, alpha, conn = oracle.geom_point(cfg, 0.3, 0.2)
+    assert np.all(conn == 0.0) and gdet == 1.0 and alpha == 1.0
+
+
+def test_connection_is_metric_compatible_and_symmetric():
+    """d_k g_mn = Gamma^l_{km} g_ln + Gamma^l_{kn} g_ml, checked against a 4th-order
+    centred difference of the metric; Gamma^l_{mn} = Gamma^l_{nm}."""
+    rng = np.random.default_rng(1)
+    h = 1e-3
+    for x1, x2 in zip(*_rand_points(rng, 40)):
+        gcov, gcon, gdet, alpha, conn = oracle.geom_point(KS, x1, x2)
+        assert np.allclose(conn, conn.transpose(0, 2, 1), atol=0, rtol=0)
+        dg = np.zeros((4, 4, 4))
+        for k, (ex1, ex2) in ((1, (1, 0)), (2, (0, 1))):
+            f = lambda s: oracle.geom_point(KS, x1 + s * h * ex1, x2 + s * h * ex2)[0]
+            dg[k] = (-f(2) + 8 * f(1) - 8 * f(-1) + f(-2)) / (12 * h)
+        rhs = np.einsum("lkm,ln->kmn", conn, gcov) + np.einsum("lkn,ml->kmn", conn, gcov)
+        scale = np.abs(gcov).max()
+        assert np.abs(rhs - dg).max() <= 1e-8 * scale
+
+
+def test_connection_trace_is_log_derivative_of_volume():
+    """Gamma^m_{m n} = d_n ln sqrt(-g), with sqrt(-g) = r Sigma sin(theta) in closed form"""
+    rng = np.random.default_rng(2)
+    a = KS["a"]
+    for x1, x2 in zip(*_rand_points(rng, 50)):
+        conn = oracle.geom_point(KS, x1, x2)[4]
+        r = math.exp(x1)
+        sig = r * r + a * a * math.cos(x2) ** 2
+        d1 = 1 + 2 * r * r / sig                                   # d/dx1 ln(r Sigma)
+        d2 = -2 * a * a * math.cos(x2) * math.sin(x2) / sig + math.cos(x2) / math.sin(x2)
+        tr = np.einsum("mmn->n", conn)
+        assert tr[0] == pytest.approx(0.0, abs=1e-13)
+        assert tr[3] == pytest.approx(0.0, abs=1e-13)
+        assert tr[1] == pytest.approx(d1, rel=1e-12)
+        assert tr[2] == pytest.approx(d2, rel=1e-11, abs=1e-12)
+
+
+# ------------------------------------------------------- primitives / fluxes (Sec. 2.3-2.5)
+
+def _random_state(rng, cfg):
+    x1, x2 = _rand_points(rng, 1)
+    gcov, gcon, gdet, alpha, conn = oracle.geom_point(cfg, x1[0], x2[0])
+    rho = math.exp(rng.normal(0, 2))
+    u = rho * 10 ** rng.uniform(-3, 1)
+    P = np.array([rho, u, *rng.normal(0, 1.5, 3)])
+    B = rng.normal(0, 1, 3) * math.sqrt(u)
+    return P, B, gcov, gcon, gdet, alpha, conn
+
+
+def _tmunu_from_fluxes(P, B, gcov, gcon, gdet, alpha, gam):
+    """T^mu_nu, u^mu read back from the oracle's U and F^j vectors"""
+    rows = [oracle.prim_to_flux(P, B, gcov, gcon, gdet, alpha, gam, d) / gdet for d in range(4)]
+    ucon = np.array([r[0] / P[0] for r in rows])
+    T = np.zeros((4, 4))
+    for m, r in enumerate(rows):
+        T[m, 0] = r[1] - r[0]
+        T[m, 1:] = r[2:5]
+    return T, ucon, rows
+
+
+def test_four_velocity_normalised_and_stress_tensor_invariants():
+    rng = np.random.default_rng(3)
+    gam = 4.0 / 3.0
+    for _ in range(300):
+        P, B, gcov, gcon, gdet, alpha, _ = _random_state(rng, KS)
+        T, ucon, rows = _tmunu_from_fluxes(P, B, gcov, gcon, gdet, alpha, gam)
+        terms = np.abs(np.outer(ucon, ucon) * gcov).sum()
+        assert ucon @ gcov @ ucon == pytest.approx(-1.0, abs=1e-14 * terms)
+        p = (gam - 1) * P[1]
+        # trace T^mu_mu = 3p - rho - u for any field (the b^2 terms cancel)
+        scale = np.abs(T).max()
+        assert np.trace(T) == pytest.approx(3 * p - P[0] - P[1], abs=1e-12 * scale)
+        # u is an eigenvector of T: T^m_n u^n = -(rho + u + b^2/2) u^m  (needs b.u = 0)
+        Tu = T @ ucon
+        lam = Tu / ucon
+        assert np.allclose(lam, lam[0], rtol=1e-9, atol=1e-9 * scale)
+        bsq = 2 * (-lam[0] - P[0] - P[1])
+        assert bsq >= -1e-10 * scale
+        # coordinate field is carried in U, induction flux is antisymmetric
+        bscale = np.abs(B).max() * ucon[0] ** 2
+        assert np.allclose(rows[0][5:8], B, rtol=0, atol=1e-13 * bscale)
+        Fb = np.array([r[5:8] for r in rows[1:]])
+        assert np.allclose(Fb, -Fb.T, atol=1e-12 * np.abs(Fb).max())
+
+
+def test_magnetic_energy_at_rest_in_minkowski():
+    """fluid at rest: T^t_t + rho u^t = -(u + B^2/2), so the energy carries +b^2/2"""
+    cfg = mink_cfg((4, 4, 4))
+    gcov, gcon, gdet, alpha, _ = oracle.geom_point(cfg, 0.0, 0.0)
+    P = np.array([2.0, 0.7, 0.0, 0.0, 0.0])
+    B = np.array([0.3, -0.4, 1.2])
+    U = oracle.prim_to_flux(P, B, gcov, gcon, gdet, alpha, 5 / 3, 0)
+    assert U[1] == pytest.approx(-(0.7 + 0.5 * (B @ B)), rel=1e-15)
+    assert U[0] == 2.0 and np.all(U[2:5] == 0.0)
+
+
+def test_wave_speeds_closed_forms():
+    cfg = mink_cfg((4, 4, 4))
+    gcov, gcon, gdet, alpha, _ = oracle.geom_point(cfg, 0.0, 0.0)
+    gam = 5.0 / 3.0
+    rho, u = 1.3, 0.9
+    p = (gam - 1) * u
+    w = rho + u + p
+    cs = math.sqrt(gam * p / w)
+    # hydro at rest: +-c_s; moving with v along x: relativistic velocity addition
+    for v in [0.0, 0.3, -0.7, 0.95]:
+        W = 1 / math.sqrt(1 - v * v)
+        P = np.array([rho, u, W * v, 0.0, 0.0])
+        vmax, vmin = oracle.vchar(P, np.zeros(3), gcov, gcon, alpha, gam, 1)
+        assert vmax == pytest.approx((v + cs) / (1 + v * cs), rel=1e-13)
+        assert vmin == pytest.approx((v - cs) / (1 - v * cs), rel=1e-13)
+    # field perpendicular to x at rest: the exact fast speed v_A^2 + c_s^2 (1 - v_A^2)
+    B = np.array([0.0, 0.8, 0.5])
+    P = np.array([rho, u, 0.0, 0.0, 0.0])
+    bsq = B @ B
+    va2 = bsq / (bsq + w)
+    vmax, vmin = oracle.vchar(P, B, gcov, gcon, alpha, gam, 1)
+    assert vmax == pytest.approx(math.sqrt(va2 + cs * cs * (1 - va2)), rel=1e-13)
+    assert vmin == pytest.approx(-vmax, rel=1e-15)
+
+
+def test_source_vanishes_in_minkowski():
+    cfg = mink_cfg((4, 4, 4))
+    gcov, gcon, gdet, alpha, conn = oracle.geom_point(cfg, 0.0, 0.0)
+    Q = oracle.source(np.array([1.0, 1.0, 0.3, 0.1, -0.2]), np.array([0.5, 0.2, 0.1]),
+                      gcov, gcon, gdet, alpha, conn, 4 / 3)
+    assert np.all(Q == 0.0)
+
+
+# ------------------------------------------------------------ reconstruction (Sec. 2.1)
+
+@pytest.mark.parametrize("recon", [oracle.PLM, oracle.PPM])
+def test_reconstruction_exact_for_linear_data(recon):
+    a = 0.3 + 1.7 * np.arange(6)
+    l, r = oracle.recon_face(recon, a)
+    assert l == pytest.approx(0.3 + 1.7 * 2.5, rel=1e-15)
+    assert r == pytest.approx(0.3 + 1.7 * 2.5, rel=1e-15)
+
+
+def test_ppm_exact_for_cubic_cell_averages():
+    """cell averages of a gently varying cubic: the PPM face value is the exact point
+    value at the face (4th-order interface formula, limiter inactive)"""
+    f = lambda x: 1.0 + 0.1 * x + 0.004 * x ** 2 + 0.0003 * x ** 3
+    F = lambda x: x + 0.05 * x ** 2 + 0.004 / 3 * x ** 3 + 0.0003 / 4 * x ** 4
+    avg = np.array([F(c + 0.5) - F(c - 0.5) for c in range(6)])
+    l, r = oracle.recon_face(oracle.PPM, avg)
+    assert l == pytest.approx(f(2.5), rel=1e-14)
+    assert r == pytest.approx(f(2.5), rel=1e-14)
+
+
+@pytest.mark.parametrize("recon", [oracle.PLM, oracle.PPM])
+def test_reconstruction_bounded_and_flat_at_extrema(recon):
+    rng = np.random.default_rng(4)
+    for _ in range(500):
+        a = np.sort(rng.normal(size=6)) * rng.choice([-1, 1])
+        l, r = oracle.recon_face(recon, a)
+        lo, hi = min(a[2], a[3]), max(a[2], a[3])
+        assert lo - 1e-14 <= l <= hi + 1e-14 and lo - 1e-14 <= r <= hi + 1e-14
+    # cell 2 is a local maximum: its face value equals its mean
+    l, r = oracle.recon_face(recon, np.array([0.0, 1.0, 3.0, 2.0, 1.0, 0.0]))
+    assert l == 3.0
+
+
+# ----------------------------------------------------------------- inversion (Sec. 2.6)
+
+def _c2p_sample(rng, cfg, gam):
+    """state with log-normal density, plasma beta log-uniform in [1e-2, 1e3] and Lorentz
+    factor log-uniform in [1, 20], random direction, random Kerr-Schild point"""
+    x1, x2 = _rand_points(rng, 1)
+    gcov, gcon, gdet, alpha, _ = oracle.geom_point(cfg, x1[0], x2[0])
+    rho = math.exp(rng.normal(0, 3))
+    u = rho * 10 ** rng.uniform(-2, 1)
+    G = 10 ** rng.uniform(0, math.log10(20))
+    n = rng.normal(size=3)
+    # utilde with g_ij ut^i ut^j = G^2 - 1
+    gij = gcov[1:, 1:]
+    n = n / math.sqrt(n @ gij @ n)
+    ut = n * math.sqrt(G * G - 1)
+    P = np.array([rho, u, *ut])
+    beta = 10 ** rng.uniform(-2, 3)
+    bdir = rng.normal(size=3)
+    bdir = bdir / math.sqrt(bdir @ gij @ bdir)
+    B = bdir * math.sqrt(2 * (gam - 1) * u / beta)
+    return P, B, gcov, gcon, gdet, alpha
+
+
+def test_cons2prim_round_trip():
+    rng = np.random.default_rng(5)
+    gam = 4.0 / 3.0
+    worst = 0.0
+    tiers = np.zeros(5, int)
+    for _ in range(3000):
+        P, B, gcov, gcon, gdet, alpha = _c2p_sample(rng, KS, gam)
+        U = oracle.prim_to_flux(P, B, gcov, gcon, gdet, alpha, gam, 0)
+        guess = P * (1 + 0.05 * rng.normal(size=5))
+        guess[0:2] = np.abs(guess[0:2])
+        Pr, tier, it = oracle.cons2prim(U, gcov, gcon, gdet, alpha, gam, guess, guess)
+        tiers[tier] += 1
+        if tier == 0:
+            gij = gcov[1:, 1:]
+            norm_u = math.sqrt(max(P[2:] @ gij @ P[2:], 1e-300))
+            err = max(abs(Pr[0] / P[0] - 1), abs(Pr[1] / P[1] - 1),
+                      math.sqrt(abs((Pr[2:] - P[2:]) @ gij @ (Pr[2:] - P[2:]))) / max(norm_u, 1.0))
+            worst = max(worst, err)
+    assert tiers[0] >= 0.99 * tiers.sum(), tiers
+    assert worst < 1e-9, worst
+
+
+def test_cons2prim_matches_bisection_brute_force():
+    rng = np.random.default_rng(6)
+    gam = 4.0 / 3.0
+    n = 0
+    for _ in range(400):
+        P, B, gcov, gcon, gdet, alpha = _c2p_sample(rng, KS, gam)
+        U = oracle.prim_to_flux(P, B, gcov, gcon, gdet, alpha, gam, 0)
+        Pn, tier, _ = oracle.cons2prim(U, gcov, gcon, gdet, alpha, gam, P * 1.01, P * 1.01)
+        Pb, rc = oracle.c2p_bisect(U, gcov, gcon, gdet, alpha, gam)
+        if tier == 0 and rc == 0:
+            n += 1
+            assert Pn[0] == pytest.approx(Pb[0], rel=1e-10)
+            assert Pn[1] == pytest.approx(Pb[1], rel=1e-8)
+    assert n > 350
+
+
+def test_cons2prim_rest_unmagnetised_closed_form():
+    """B = 0, v = 0 in Minkowski: rho = D and u = -(Q.n) - D, exactly"""
+    cfg = mink_cfg((4, 4, 4))
+    gcov, gcon, gdet, alpha, _ = oracle.geom_point(cfg, 0.0, 0.0)
+    U = np.array([1.7, -0.45, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.1])
+    P, tier, _ = oracle.cons2prim(U, gcov, gcon, gdet, alpha, 4 / 3, np.array([1.0, 1.0, 0.1, 0.0, 0.0]))
+    assert tier == 0
+    assert P[0] == pytest.approx(1.7, rel=1e-14)
+    assert P[1] == pytest.approx(0.45, rel=1e-13)
+    assert np.all(np.abs(P[2:]) < 1e-14)
+
+
+def test_entropy_backup_recovers_from_entropy():
+    """energy made inconsistent (negative thermal energy): the entropy tier recovers
+    rho and u = kappa rho^gamma/(gamma - 1) from the evolved entropy"""
+    rng = np.random.default_rng(7)
+    gam = 4.0 / 3.0
+    got = 0
+    for _ in range(50):
+        P, B, gcov, gcon, gdet, alpha = _c2p_sample(rng, KS, gam)
+        P[1] = 1e-6 * P[0]
+        U = oracle.prim_to_flux(P, B, gcov, gcon, gdet, alpha, gam, 0)
+        kappa = U[8] / U[0]
+        U2 = U.copy()
+        U2[1] += 0.2 * abs(U[1])                  # remove energy: no valid energy solution
+        Pr, tier, _ = oracle.cons2prim(U2, gcov, gcon, gdet, alpha, gam, P, P)
+        if tier == 3:
+            got += 1
+            assert Pr[1] == pytest.approx(kappa * Pr[0] ** gam / (gam - 1), rel=1e-12)
+        assert tier in (2, 3, 4)
+        assert np.all(np.isfinite(Pr))
+    assert got > 10
