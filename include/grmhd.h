@@ -1,0 +1,185 @@
+/*
+ * grmhd.h -- C ABI of libgrmhd.so, the MI355X (gfx950) GRMHD block update.
+ *
+ * The library advances the ideal GRMHD equations in conservative form (paper
+ * Sec. 2.4) on block-structured grids that are uniform in internal coordinates
+ * x1 = ln r, x2 = theta, x3 = phi around a Kerr black hole in Kerr-Schild form
+ * (Sec. 2.2), or on Cartesian Minkowski grids.  One step is the midpoint
+ * predictor/corrector of Sec. 2.1: reconstruction (PPM or PLM-MC), HLLE or LLF
+ * fluxes, edge EMFs as the four-flux average and constrained transport of the
+ * staggered field (Sec. 2.5), the geometric source (Sec. 2.5), the 2D Newton
+ * inversion with entropy backup (Sec. 2.6) and the floors of Sec. 2.7.  The
+ * Courant step dt = C0 / (sum_i v_i / dx_i) is taken per cell and reduced on
+ * the device (Sec. 2.1).
+ *
+ * Memory: every large buffer is device memory owned by the caller.  The library
+ * allocates no device memory; it keeps host-side metadata only.  grmhd_sizes()
+ * says how much the caller must provide.
+ *
+ * Layout of the state (per block b, blocks packed in table order):
+ *   a block of n1 x n2 x n3 cells is stored padded by ng ghost layers below and
+ *   ng + 1 above in every dimension, NPd = n_d + 2 ng + 1 cells, local index
+ *   (K * NP2 + J) * NP1 + I (x1 fastest).  With V_b = NP1 NP2 NP3 and
+ *   off_b = sum_{b' < b} V_b' (grmhd_block_layout):
+ *     prim [5 off_b + v V_b + local]   v = rho, u_g, utilde^1, utilde^2, utilde^3
+ *     bface[3 off_b + d V_b + local]   sqrt(-g) B^(d+1) on the LOWER d-face of the
+ *                                      cell (x1 face at i - 1/2 for d = 0, ...)
+ *
+ * Errors: every call returns GRMHD_OK (0) or a negative code; the message is
+ * available from grmhd_last_error() (thread-local).  Calls are ordered on the
+ * HIP stream given at init; calls that return host values synchronise it.
+ * A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef GRMHD_H
+#define GRMHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRMHD_ABI_VERSION 1
+
+enum { GRMHD_OK = 0, GRMHD_EINVAL = -1, GRMHD_ENOMEM = -2, GRMHD_EHIP = -3,
+       GRMHD_ESTATE = -4, GRMHD_EUNSUPPORTED = -5 };
+enum { GRMHD_MINK_CART = 0, GRMHD_KS_LOGSPH = 1 };
+enum { GRMHD_PLM_MC = 0, GRMHD_PPM = 1 };
+enum { GRMHD_LLF = 0, GRMHD_HLLE = 1 };
+enum { GRMHD_BC_OUTFLOW = 0, GRMHD_BC_POLAR = 1, GRMHD_BC_PERIODIC = 2 };
+enum { GRMHD_GUESS_PLAIN = 0, GRMHD_GUESS_MLP = 1 };
+
+/* One block of the grid (Sec. 3.3 block structure).  Origins are in cells of the
+ * effective grid; the blocks must tile the effective grid without overlap. */
+typedef struct {
+  int32_t lev[3];   /* refinement level per dimension (0 = effective resolution) */
+  int32_t lat;      /* local-time-stepping level (0 = fastest)                  */
+  int64_t org[3];   /* origin in cells of the effective grid                    */
+  int32_t n[3];     /* cells per dimension                                       */
+} grmhd_block_desc;
+
+typedef struct {
+  int32_t abi_version;        /* GRMHD_ABI_VERSION */
+  int32_t coords;             /* GRMHD_MINK_CART or GRMHD_KS_LOGSPH */
+  double spin_a;              /* black-hole spin a/M (Kerr-Schild only) */
+  double gamma_ad;            /* adiabatic index of p = (gamma - 1) u_g */
+  double xmin[3], xmax[3];    /* internal-coordinate extent of the effective grid */
+  int32_t n_eff[3];           /* effective cells per dimension */
+  int32_t n_ghost;            /* 2 (PLM) or 3 (PPM) */
+  int32_t n_blocks;
+  int32_t n_lat_levels;       /* 1 = global time step */
+  const grmhd_block_desc* blocks;  /* host array of n_blocks, copied at init */
+  int32_t recon, riemann;
+  int32_t bc[6];              /* x1lo, x1hi, x2lo, x2hi, x3lo, x3hi */
+  double courant;             /* C0 */
+  double rho_fl_c, rho_fl_p;  /* rho >= rho_fl_c r^rho_fl_p */
+  double u_fl_c, u_fl_p;      /* u_g >= u_fl_c r^u_fl_p */
+  double bsq_rho_max;         /* b^2/rho ceiling */
+  double bsq_u_max;           /* b^2/u_g ceiling */
+  double gamma_max;           /* Lorentz-factor ceiling */
+  int32_t c2p_guess;          /* GRMHD_GUESS_PLAIN or GRMHD_GUESS_MLP */
+  int32_t c2p_maxit;          /* Newton iteration cap (50) */
+  double c2p_tol;             /* Newton tolerance (1e-12) */
+  const void* mlp_weights;    /* device pointer to packed MLP weights, or NULL */
+  int32_t batched;            /* 0 = one launch per kernel and stage; 1 = step graph */
+  int32_t profile;            /* 1 = time each kernel class with HIP events on the stream */
+} grmhd_grid_desc;
+
+typedef struct {
+  double* prim;               /* device, layout above, interior filled at init */
+  double* bface;              /* device, layout above, interior faces filled at init */
+  void* work;                 /* device scratch of work_bytes */
+  size_t work_bytes;
+} grmhd_buffers;
+
+typedef struct {
+  int64_t real_zone_cycles;         /* sum over blocks of cells x steps taken */
+  int64_t lat_eff_zone_cycles;      /* cells x finest-level steps */
+  int64_t amr_lat_eff_zone_cycles;  /* effective-grid cells x finest-level steps */
+  int64_t steps_per_level[8];
+  int64_t c2p_iter_hist[64];        /* Newton iterations of accepted solves; 63 = bracketing tiers */
+  int64_t c2p_tier[5];              /* 0 first guess, 1 plain guess, 2 1D energy, 3 entropy, 4 failed */
+  int64_t floor_hits;
+  double dt_min;                    /* last time step */
+  double t_sim;                     /* simulated time since init */
+  double kernel_ms;                 /* device time of this call (HIP events) */
+  /* with desc.profile: device time and launch count per kernel class, in the order
+   * ghost fill, cell field, x1 flux, x2 flux, x3 flux, EMF, cell update, Courant */
+  double class_ms[8];
+  int64_t class_launches[8];
+} grmhd_step_stats;
+
+typedef struct grmhd_ctx grmhd_ctx;
+
+/* Sizes the caller must allocate for desc: prim and bface element counts (doubles)
+ * and the work buffer in bytes.  Returns GRMHD_EINVAL for an invalid desc. */
+int grmhd_sizes(const grmhd_grid_desc* desc, size_t* prim_elems, size_t* bface_elems,
+                size_t* work_bytes);
+
+/* Offset (in cells) and padded extents of block b in the prim/bface layout. */
+int grmhd_block_layout(const grmhd_grid_desc* desc, int32_t b, int64_t* cell_offset,
+                       int32_t np[3]);
+
+/* Build the context: block table, neighbour/ghost maps and geometry tables
+ * (metric, inverse, sqrt(-g), lapse at centres and faces; Christoffel symbols at
+ * centres, Sec. 2.2), all uploaded into bufs->work on hip_stream.  bufs must
+ * outlive the context.  The interior of prim/bface holds the initial state. */
+int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void* hip_stream,
+                    grmhd_ctx** out);
+
+/* Advance n_cycles steps (Sec. 2.1 midpoint method).  stats (host, nullable)
+ * receives counters for this call; passing it synchronises the stream. */
+int grmhd_step(grmhd_ctx* ctx, int32_t n_cycles, grmhd_step_stats* stats);
+
+/* Standalone inversion of a flat batch (Sec. 2.6), all pointers device memory:
+ *   U[9][n]     conserved state incl. sqrt(-g): rho u^t, T^t_t + rho u^t, T^t_i, B^i, kappa rho u^t
+ *   geom[15][n] g_tt g_t1 g_t3 g_11 g_13 g_22 g_33, g^tt g^t1 g^11 g^13 g^22 g^33,
+ *               sqrt(-g), lapse  (metrics with the Kerr-Schild sparsity pattern)
+ *   guess[5][n] first guess primitives; prev[5][n] plain guess and failure fallback
+ *   P[5][n] out primitives; iters[n], tier[n] out (tier as in grmhd_step_stats)
+ * No floors are applied.  ctx may be NULL. */
+typedef struct {
+  int64_t n;
+  const double* U;
+  const double* geom;
+  const double* guess;
+  const double* prev;
+  double* P;
+  int32_t* iters;
+  int32_t* tier;
+  double gamma_ad;
+  double tol;
+  int32_t maxit;
+} grmhd_c2p_batch;
+int grmhd_cons2prim(grmhd_ctx* ctx, const grmhd_c2p_batch* batch, void* hip_stream);
+
+/* Discrete divergence of the face field over all interior cells:
+ * sum_d (Bbar^d_+ - Bbar^d_-)/dx^d.  Writes max |div| and max |div| / (sum_d
+ * (|Bbar^d_+| + |Bbar^d_-|)/dx^d) to host scalars (synchronises); field (device,
+ * nullable) receives the per-cell value in the prim layout of variable 0. */
+int grmhd_divb(grmhd_ctx* ctx, double* max_abs, double* max_rel, double* field);
+
+/* Host-only planner introspection for bit-exact checks (no device needed): copies the
+ * ghost gather list for what = 0 (cell variables) or 1..3 (face component 1..3) as
+ * int32 quadruples (dst block, dst local index, src block | flags << 24, src local
+ * index); flags 1 = negate utilde^2 / the face value, 2 = clamp utilde^1 <= 0,
+ * 4 = clamp utilde^1 >= 0, 8 = zero (polar-axis face).  host_buf NULL queries the
+ * size in bytes. */
+int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes);
+
+/* Planner geometry at one internal-coordinate point (host only, no device needed):
+ * out[15] = g_tt g_t1 g_t3 g_11 g_13 g_22 g_33 g^tt g^t1 g^11 g^13 g^22 g^33 sqrt(-g)
+ * lapse; conn[40] (nullable) = Gamma^l_{mn} for m <= n at index l*10 + pair(m, n), pairs
+ * in the order (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3) (2,2) (2,3) (3,3).  The
+ * Kerr-Schild metric is the Kerr metric (Sec. 2.2) with x1 = ln r. */
+int grmhd_geometry_point(int32_t coords, double spin_a, double x1, double x2, double* out,
+                         double* conn);
+
+int grmhd_destroy(grmhd_ctx* ctx);
+const char* grmhd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

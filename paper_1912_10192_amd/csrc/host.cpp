@@ -1,0 +1,709 @@
+// host.cpp -- planner and C ABI of libgrmhd.so.
+//
+// The planner turns a grid descriptor into the integer and geometry tables the kernels
+// read: the packed block layout, per-column metric tables (Sec. 2.2), and gather lists
+// that fill every ghost cell and ghost face from its source (a neighbour block's
+// interior, or the physical boundary rule).  Everything large lives in the caller's
+// work buffer; this file allocates host memory only.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/grmhd.h"
+#include "device.h"
+#include "internal.h"
+
+using namespace grmhd;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                  \
+  do {                                                                             \
+    hipError_t e_ = (x);                                                           \
+    if (e_ != hipSuccess)                                                          \
+      return fail(GRMHD_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+// ------------------------------------------------------------------------ geometry
+
+namespace {
+
+template <typename T>
+void ks_gcov(double a, T x1, T x2, T g[4][4]) {
+  const T r = std::exp(x1);
+  const T s = std::sin(x2), c = std::cos(x2);
+  const T sig = r * r + a * a * c * c;
+  const T q = 2.0 * r / sig;
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < 4; n++) g[m][n] = T(0.0);
+  g[0][0] = -(1.0 - q);
+  g[0][1] = g[1][0] = q * r;
+  g[0][3] = g[3][0] = -a * q * s * s;
+  g[1][1] = (1.0 + q) * r * r;
+  g[1][3] = g[3][1] = -a * s * s * (1.0 + q) * r;
+  g[2][2] = sig;
+  g[3][3] = s * s * (sig + a * a * s * s * (1.0 + q));
+}
+
+// closed-form inverse of the Kerr-Schild metric in internal coordinates
+void ks_gcon(double a, double x1, double x2, double h[4][4]) {
+  const double r = std::exp(x1), s = std::sin(x2), c = std::cos(x2);
+  const double sig = r * r + a * a * c * c;
+  const double delta = r * r - 2.0 * r + a * a;
+  for (int m = 0; m < 4; m++)
+    for (int n = 0; n < 4; n++) h[m][n] = 0.0;
+  h[0][0] = -(1.0 + 2.0 * r / sig);
+  h[0][1] = h[1][0] = 2.0 / sig;            // (2r/Sigma) / r
+  h[1][1] = delta / (sig * r * r);
+  h[1][3] = h[3][1] = a / (sig * r);
+  h[2][2] = 1.0 / sig;
+  h[3][3] = 1.0 / (sig * s * s);
+}
+
+// out[0..14] in Metric order; conn (optional) [40] = Gamma^l_{mn}, m <= n, l*10 + pair.
+// Derivatives of the covariant metric by complex-step differentiation (exact to
+// rounding, no subtractive cancellation).
+void geometry_point(int coords, double a, double x1, double x2, double* out, double* conn) {
+  double g[4][4], h[4][4];
+  if (coords == GRMHD_MINK_CART) {
+    for (int m = 0; m < 4; m++)
+      for (int n = 0; n < 4; n++) g[m][n] = h[m][n] = (m == n) ? (m == 0 ? -1.0 : 1.0) : 0.0;
+  } else {
+    std::complex<double> gc[4][4];
+    ks_gcov<std::complex<double>>(a, std::complex<double>(x1, 0.0), std::complex<double>(x2, 0.0), gc);
+    for (int m = 0; m < 4; m++)
+      for (int n = 0; n < 4; n++) g[m][n] = gc[m][n].real();
+    ks_gcon(a, x1, x2, h);
+  }
+  out[G00] = g[0][0]; out[G01] = g[0][1]; out[G03] = g[0][3]; out[G11] = g[1][1];
+  out[G13] = g[1][3]; out[G22] = g[2][2]; out[G33] = g[3][3];
+  out[H00] = h[0][0]; out[H01] = h[0][1]; out[H11] = h[1][1]; out[H13] = h[1][3];
+  out[H22] = h[2][2]; out[H33] = h[3][3];
+  if (coords == GRMHD_MINK_CART) {
+    out[GDET] = 1.0;
+    out[ALPHA] = 1.0;
+  } else {
+    const double r = std::exp(x1), s = std::sin(x2), c = std::cos(x2);
+    const double sig = r * r + a * a * c * c;
+    out[GDET] = r * sig * std::fabs(s);
+    out[ALPHA] = 1.0 / std::sqrt(1.0 + 2.0 * r / sig);
+  }
+  if (!conn) return;
+  double dg[4][4][4] = {};
+  if (coords == GRMHD_KS_LOGSPH) {
+    const double hs = 1e-30;
+    std::complex<double> gc[4][4];
+    ks_gcov<std::complex<double>>(a, std::complex<double>(x1, hs), std::complex<double>(x2, 0.0), gc);
+    for (int m = 0; m < 4; m++)
+      for (int n = 0; n < 4; n++) dg[1][m][n] = gc[m][n].imag() / hs;
+    ks_gcov<std::complex<double>>(a, std::complex<double>(x1, 0.0), std::complex<double>(x2, hs), gc);
+    for (int m = 0; m < 4; m++)
+      for (int n = 0; n < 4; n++) dg[2][m][n] = gc[m][n].imag() / hs;
+  }
+  for (int l = 0; l < 4; l++) {
+    int p = 0;
+    for (int m = 0; m < 4; m++)
+      for (int n = m; n < 4; n++, p++) {
+        double acc = 0.0;
+        for (int k = 0; k < 4; k++) acc += h[l][k] * (dg[m][k][n] + dg[n][k][m] - dg[k][m][n]);
+        conn[l * 10 + p] = 0.5 * acc;
+      }
+  }
+}
+
+int imod(int64_t a, int64_t n) {
+  int64_t m = a % n;
+  return (int)(m < 0 ? m + n : m);
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Plan {
+  grmhd_grid_desc d;
+  std::vector<grmhd_block_desc> blocks;
+  std::vector<BlockInfo> info;
+  int64_t vtot = 0;          // total padded cells
+  int64_t n_interior = 0;
+  int32_t max_np[3] = {0, 0, 0}, max_n[3] = {0, 0, 0};
+  int32_t ti = 0, tj = 0;    // geometry table extents
+  int64_t ncol = 0;
+  std::vector<int32_t> owner;   // block id per effective cell
+  std::vector<GhostOp> ops[4];  // cells, x1 faces, x2 faces, x3 faces
+  // work-buffer offsets (bytes)
+  size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, total;
+};
+
+int validate(const grmhd_grid_desc* d) {
+  if (!d) return fail(GRMHD_EINVAL, "desc is NULL");
+  if (d->abi_version != GRMHD_ABI_VERSION) return fail(GRMHD_EINVAL, "abi_version mismatch");
+  if (d->coords != GRMHD_MINK_CART && d->coords != GRMHD_KS_LOGSPH)
+    return fail(GRMHD_EINVAL, "unknown coords");
+  if (d->n_ghost < 2 || d->n_ghost > 4) return fail(GRMHD_EINVAL, "n_ghost must be 2..4");
+  if (d->recon == GRMHD_PPM && d->n_ghost < 3) return fail(GRMHD_EINVAL, "PPM needs n_ghost >= 3");
+  if (d->recon != GRMHD_PLM_MC && d->recon != GRMHD_PPM) return fail(GRMHD_EINVAL, "unknown recon");
+  if (d->riemann != GRMHD_LLF && d->riemann != GRMHD_HLLE) return fail(GRMHD_EINVAL, "unknown riemann");
+  if (d->n_blocks < 1 || !d->blocks) return fail(GRMHD_EINVAL, "no blocks");
+  if (d->n_lat_levels != 1) return fail(GRMHD_EUNSUPPORTED, "only one time level is supported");
+  for (int k = 0; k < 3; k++)
+    if (d->n_eff[k] < 1 || !(d->xmax[k] > d->xmin[k])) return fail(GRMHD_EINVAL, "bad extent");
+  if (!(d->bc[0] == GRMHD_BC_OUTFLOW || d->bc[0] == GRMHD_BC_PERIODIC) || !(d->bc[1] == d->bc[0]))
+    return fail(GRMHD_EUNSUPPORTED, "x1 boundaries must be both outflow or both periodic");
+  if (!(d->bc[2] == GRMHD_BC_POLAR || d->bc[2] == GRMHD_BC_PERIODIC) || !(d->bc[3] == d->bc[2]))
+    return fail(GRMHD_EUNSUPPORTED, "x2 boundaries must be both polar or both periodic");
+  if (d->bc[4] != GRMHD_BC_PERIODIC || d->bc[5] != GRMHD_BC_PERIODIC)
+    return fail(GRMHD_EUNSUPPORTED, "x3 boundaries must be periodic");
+  if (d->bc[2] == GRMHD_BC_POLAR && (d->n_eff[2] % 2 != 0 && d->n_eff[2] != 1))
+    return fail(GRMHD_EINVAL, "polar boundary needs an even number of x3 cells");
+  if (d->bc[2] == GRMHD_BC_POLAR && d->coords != GRMHD_KS_LOGSPH)
+    return fail(GRMHD_EINVAL, "polar boundary needs spherical coordinates");
+  if (d->c2p_maxit < 1 || d->c2p_maxit > 62) return fail(GRMHD_EINVAL, "c2p_maxit must be 1..62");
+  if (!(d->c2p_tol > 0.0)) return fail(GRMHD_EINVAL, "c2p_tol must be positive");
+  if (!(d->courant > 0.0)) return fail(GRMHD_EINVAL, "courant must be positive");
+  if (d->c2p_guess != GRMHD_GUESS_PLAIN) return fail(GRMHD_EUNSUPPORTED, "only the plain guess");
+  for (int b = 0; b < d->n_blocks; b++) {
+    const grmhd_block_desc& bd = d->blocks[b];
+    for (int k = 0; k < 3; k++) {
+      if (bd.lev[k] != 0) return fail(GRMHD_EUNSUPPORTED, "refined blocks are not supported");
+      if (bd.n[k] < d->n_ghost && !(bd.n[k] == 1 && d->n_eff[k] == 1))
+        return fail(GRMHD_EINVAL, "block smaller than the ghost width");
+      if (bd.org[k] < 0 || bd.org[k] + bd.n[k] > d->n_eff[k])
+        return fail(GRMHD_EINVAL, "block outside the grid");
+    }
+    if (bd.lat != 0) return fail(GRMHD_EUNSUPPORTED, "LAT levels are not supported");
+  }
+  return GRMHD_OK;
+}
+
+// Composition of the physical boundary rules for a position outside the grid, applied
+// x3 first, then x2, then x1 (the order in which ghost layers are filled, so that edge
+// and corner ghosts take their values from already-filled layers).  kind 0 = cell,
+// 1..3 = face of that component.  Returns false if the value is identically zero.
+bool compose(const grmhd_grid_desc& d, int kind, int64_t& i, int64_t& j, int64_t& k, int& flags) {
+  const int64_t N1 = d.n_eff[0], N2 = d.n_eff[1], N3 = d.n_eff[2];
+  flags = 0;
+  // x3: periodic
+  if (kind == 3) {
+    if (k < 0 || k > N3) k = imod(k, N3);
+  } else if (k < 0 || k >= N3) {
+    k = imod(k, N3);
+  }
+  // x2
+  const bool polar = d.bc[2] == GRMHD_BC_POLAR;
+  if (kind == 2) {
+    if (polar && (j == 0 || j == N2)) return false;
+    if (j < 0 || j > N2) {
+      if (polar) {
+        j = j < 0 ? -j : 2 * N2 - j;
+        k = imod(k + N3 / 2, N3);
+        flags |= GF_FLIP;
+      } else {
+        j = imod(j, N2);
+      }
+    }
+  } else if (j < 0 || j >= N2) {
+    if (polar) {
+      j = j < 0 ? -1 - j : 2 * N2 - 1 - j;
+      k = imod(k + N3 / 2, N3);
+      if (kind == 0) flags |= GF_FLIP;
+    } else {
+      j = imod(j, N2);
+    }
+  }
+  // x1
+  const bool outflow = d.bc[0] == GRMHD_BC_OUTFLOW;
+  if (kind == 1) {
+    if (i < 0 || i > N1) {
+      if (outflow) i = i < 0 ? 0 : N1;
+      else i = imod(i, N1);
+    }
+  } else if (i < 0 || i >= N1) {
+    if (outflow) {
+      if (kind == 0) flags |= i < 0 ? GF_CLAMP_NEG : GF_CLAMP_POS;
+      i = i < 0 ? 0 : N1 - 1;
+    } else {
+      i = imod(i, N1);
+    }
+  }
+  return true;
+}
+
+int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
+  int rc = validate(desc);
+  if (rc) return rc;
+  p.d = *desc;
+  p.blocks.assign(desc->blocks, desc->blocks + desc->n_blocks);
+  p.d.blocks = nullptr;
+  const int g = desc->n_ghost;
+  const int nb = desc->n_blocks;
+  p.info.resize(nb);
+  int64_t off = 0;
+  for (int b = 0; b < nb; b++) {
+    BlockInfo& bi = p.info[b];
+    const grmhd_block_desc& bd = p.blocks[b];
+    bi.off = off;
+    for (int k = 0; k < 3; k++) {
+      bi.n[k] = bd.n[k];
+      bi.np[k] = bd.n[k] + 2 * g + 1;
+      p.max_np[k] = std::max(p.max_np[k], bi.np[k]);
+      p.max_n[k] = std::max(p.max_n[k], bi.n[k]);
+    }
+    bi.gorg[0] = (int32_t)bd.org[0];
+    bi.gorg[1] = (int32_t)bd.org[1];
+    bi.gorg[2] = (int32_t)bd.org[2];
+    bi.vol = bi.np[0] * bi.np[1] * bi.np[2];
+    bi.lat = bd.lat;
+    bi.pad = 0;
+    off += bi.vol;
+    p.n_interior += (int64_t)bd.n[0] * bd.n[1] * bd.n[2];
+  }
+  p.vtot = off;
+  if (p.vtot * 5 >= (int64_t(1) << 31) * 4) return fail(GRMHD_EINVAL, "grid too large");
+  p.ti = desc->n_eff[0] + 2 * g + 1;
+  p.tj = desc->n_eff[1] + 2 * g + 1;
+  p.ncol = (int64_t)p.ti * p.tj;
+  // ownership of effective cells; every cell must be covered exactly once
+  const int64_t N1 = desc->n_eff[0], N2 = desc->n_eff[1], N3 = desc->n_eff[2];
+  if (p.n_interior != N1 * N2 * N3) return fail(GRMHD_EINVAL, "blocks do not tile the grid");
+  p.owner.assign((size_t)(N1 * N2 * N3), -1);
+  for (int b = 0; b < nb; b++) {
+    const grmhd_block_desc& bd = p.blocks[b];
+    for (int64_t k = bd.org[2]; k < bd.org[2] + bd.n[2]; k++)
+      for (int64_t j = bd.org[1]; j < bd.org[1] + bd.n[1]; j++)
+        for (int64_t i = bd.org[0]; i < bd.org[0] + bd.n[0]; i++) {
+          int32_t& o = p.owner[(size_t)((k * N2 + j) * N1 + i)];
+          if (o != -1) return fail(GRMHD_EINVAL, "blocks overlap");
+          o = b;
+        }
+  }
+  if (with_maps) {
+    for (int kind = 0; kind < 4; kind++) p.ops[kind].clear();
+    for (int b = 0; b < nb; b++) {
+      const BlockInfo& bi = p.info[b];
+      const grmhd_block_desc& bd = p.blocks[b];
+      for (int kind = 0; kind < 4; kind++) {
+        for (int K = 0; K < bi.np[2]; K++)
+          for (int J = 0; J < bi.np[1]; J++)
+            for (int I = 0; I < bi.np[0]; I++) {
+              const int L3[3] = {I, J, K};
+              bool ghost = false;
+              for (int dd = 0; dd < 3; dd++) {
+                const int hi = (kind == dd + 1) ? g + bi.n[dd] : g + bi.n[dd] - 1;
+                if (L3[dd] < g || L3[dd] > hi) ghost = true;
+              }
+              if (!ghost) continue;
+              int64_t gi = bd.org[0] + I - g, gj = bd.org[1] + J - g, gk = bd.org[2] + K - g;
+              int flags = 0;
+              const bool nz = compose(p.d, kind, gi, gj, gk, flags);
+              // the source cell owning this position (a face at the upper grid edge
+              // belongs to the last cell)
+              int64_t ci = gi, cj = gj, ck = gk;
+              if (kind == 1 && ci == N1) ci = N1 - 1;
+              if (kind == 2 && cj == N2) cj = N2 - 1;
+              if (kind == 3 && ck == N3) ck = N3 - 1;
+              const int sb = p.owner[(size_t)((ck * N2 + cj) * N1 + ci)];
+              const grmhd_block_desc& sd = p.blocks[sb];
+              const BlockInfo& si = p.info[sb];
+              const int64_t li = gi - sd.org[0] + g, lj = gj - sd.org[1] + g, lk = gk - sd.org[2] + g;
+              GhostOp op;
+              op.dst_blk = b;
+              op.dst_loc = (int32_t)(((int64_t)K * bi.np[1] + J) * bi.np[0] + I);
+              if (!nz) flags = GF_ZERO;
+              op.src_blkf = sb | (flags << 24);
+              op.src_loc = nz ? (int32_t)((lk * si.np[1] + lj) * si.np[0] + li) : 0;
+              if (!nz) op.src_blkf = b | (flags << 24);
+              p.ops[kind].push_back(op);
+            }
+      }
+    }
+  }
+  // work-buffer layout
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  const size_t V = (size_t)p.vtot;
+  p.o_ps = take(5 * V * 8);
+  p.o_balt = take(3 * V * 8);
+  p.o_bc = take(3 * V * 8);
+  p.o_f = take(24 * V * 8);
+  p.o_e = take(3 * V * 8);
+  p.o_gc = take((size_t)NGEO_C * p.ncol * 8);
+  p.o_g1 = take((size_t)NGEO_F * p.ncol * 8);
+  p.o_g2 = take((size_t)NGEO_F * p.ncol * 8);
+  p.o_blk = take(nb * sizeof(BlockInfo));
+  for (int kind = 0; kind < 4; kind++) {
+    size_t count = with_maps ? p.ops[kind].size() : 0;
+    if (!with_maps) {
+      // the same count without building the lists
+      for (int b = 0; b < nb; b++) {
+        const BlockInfo& bi = p.info[b];
+        int64_t inside = 1;
+        for (int dd = 0; dd < 3; dd++) inside *= (kind == dd + 1) ? bi.n[dd] + 1 : bi.n[dd];
+        count += (size_t)(bi.vol - inside);
+      }
+    }
+    p.o_ops[kind] = take(count * sizeof(GhostOp));
+  }
+  p.o_cnt = take(sizeof(Counters));
+  p.total = o;
+  return GRMHD_OK;
+}
+
+void build_geometry(const Plan& p, std::vector<double>& gc, std::vector<double>& g1,
+                    std::vector<double>& g2) {
+  const grmhd_grid_desc& d = p.d;
+  const int g = d.n_ghost;
+  const double dx1 = (d.xmax[0] - d.xmin[0]) / d.n_eff[0];
+  const double dx2 = (d.xmax[1] - d.xmin[1]) / d.n_eff[1];
+  const bool polar = d.bc[2] == GRMHD_BC_POLAR;
+  gc.assign((size_t)NGEO_C * p.ncol, 0.0);
+  g1.assign((size_t)NGEO_F * p.ncol, 0.0);
+  g2.assign((size_t)NGEO_F * p.ncol, 0.0);
+  auto mirror = [&](double x2) {
+    if (polar && x2 < d.xmin[1]) return 2.0 * d.xmin[1] - x2;
+    if (polar && x2 > d.xmax[1]) return 2.0 * d.xmax[1] - x2;
+    return x2;
+  };
+  double tmp[NGEO_F], conn[40];
+  for (int J = 0; J < p.tj; J++)
+    for (int I = 0; I < p.ti; I++) {
+      const int64_t col = (int64_t)J * p.ti + I;
+      const double x1c = d.xmin[0] + (I - g + 0.5) * dx1, x1f = d.xmin[0] + (I - g) * dx1;
+      const double x2c = d.xmin[1] + (J - g + 0.5) * dx2, x2f = d.xmin[1] + (J - g) * dx2;
+      geometry_point(d.coords, d.spin_a, x1c, mirror(x2c), tmp, conn);
+      for (int q = 0; q < NGEO_F; q++) gc[q * p.ncol + col] = tmp[q];
+      for (int q = 0; q < 40; q++) gc[(CONN0 + q) * p.ncol + col] = conn[q];
+      const double r = d.coords == GRMHD_KS_LOGSPH ? std::exp(x1c) : 1.0;
+      gc[RHOFL * p.ncol + col] = d.rho_fl_c * std::pow(r, d.rho_fl_p);
+      gc[UFL * p.ncol + col] = d.u_fl_c * std::pow(r, d.u_fl_p);
+      geometry_point(d.coords, d.spin_a, x1f, mirror(x2c), tmp, nullptr);
+      for (int q = 0; q < NGEO_F; q++) g1[q * p.ncol + col] = tmp[q];
+      const bool axis = polar && (J == g || J == g + d.n_eff[1]);
+      if (axis) {
+        for (int q = 0; q < NGEO_F; q++) g2[q * p.ncol + col] = 0.0;   // sqrt(-g) = 0 on the axis
+        g2[ALPHA * p.ncol + col] = 1.0;
+      } else {
+        geometry_point(d.coords, d.spin_a, x1c, mirror(x2f), tmp, nullptr);
+        for (int q = 0; q < NGEO_F; q++) g2[q * p.ncol + col] = tmp[q];
+      }
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------- context
+
+enum { KC_GHOST, KC_BCELL, KC_FLUX1, KC_FLUX2, KC_FLUX3, KC_EMF, KC_UPDATE, KC_DT, KC_N };
+
+struct grmhd_ctx {
+  Plan plan;
+  bool profile = false;
+  std::vector<hipEvent_t> prof_ev;   // pairs (start, stop)
+  std::vector<int> prof_cls;
+  size_t prof_used = 0;
+  Launch L;
+  grmhd_buffers bufs;
+  hipStream_t stream;
+  double *ps, *balt, *bc, *f, *e;
+  GhostOp* ops[4];
+  int64_t nops[4];
+  bool b_in_alt = false;
+  hipEvent_t ev0, ev1;
+};
+
+extern "C" {
+
+int grmhd_sizes(const grmhd_grid_desc* desc, size_t* prim_elems, size_t* bface_elems,
+                size_t* work_bytes) {
+  Plan p;
+  int rc = build_plan(desc, p, false);
+  if (rc) return rc;
+  if (prim_elems) *prim_elems = (size_t)p.vtot * 5;
+  if (bface_elems) *bface_elems = (size_t)p.vtot * 3;
+  if (work_bytes) *work_bytes = p.total;
+  return GRMHD_OK;
+}
+
+int grmhd_block_layout(const grmhd_grid_desc* desc, int32_t b, int64_t* cell_offset,
+                       int32_t np[3]) {
+  int rc = validate(desc);
+  if (rc) return rc;
+  if (b < 0 || b >= desc->n_blocks) return fail(GRMHD_EINVAL, "block index out of range");
+  int64_t off = 0;
+  for (int q = 0; q < b; q++) {
+    int64_t v = 1;
+    for (int k = 0; k < 3; k++) v *= desc->blocks[q].n[k] + 2 * desc->n_ghost + 1;
+    off += v;
+  }
+  if (cell_offset) *cell_offset = off;
+  if (np)
+    for (int k = 0; k < 3; k++) np[k] = desc->blocks[b].n[k] + 2 * desc->n_ghost + 1;
+  return GRMHD_OK;
+}
+
+int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void* hip_stream,
+                    grmhd_ctx** out) {
+  if (!out || !bufs) return fail(GRMHD_EINVAL, "NULL argument");
+  *out = nullptr;
+  grmhd_ctx* c = new grmhd_ctx();
+  int rc = build_plan(desc, c->plan, true);
+  if (rc) { delete c; return rc; }
+  const Plan& p = c->plan;
+  if (!bufs->prim || !bufs->bface || !bufs->work) { delete c; return fail(GRMHD_EINVAL, "NULL buffer"); }
+  if (bufs->work_bytes < p.total) { delete c; return fail(GRMHD_EINVAL, "work buffer too small"); }
+  if (((uintptr_t)bufs->work & 255) != 0) { delete c; return fail(GRMHD_EINVAL, "work buffer not 256-byte aligned"); }
+  c->bufs = *bufs;
+  c->stream = (hipStream_t)hip_stream;
+  char* w = (char*)bufs->work;
+  c->ps = (double*)(w + p.o_ps);
+  c->balt = (double*)(w + p.o_balt);
+  c->bc = (double*)(w + p.o_bc);
+  c->f = (double*)(w + p.o_f);
+  c->e = (double*)(w + p.o_e);
+  std::vector<double> gc, g1, g2;
+  build_geometry(p, gc, g1, g2);
+  auto up = [&](size_t off, const void* src, size_t bytes) -> int {
+    if (bytes == 0) return GRMHD_OK;
+    HIPCHK(hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, c->stream));
+    return GRMHD_OK;
+  };
+  if ((rc = up(p.o_gc, gc.data(), gc.size() * 8)) ||
+      (rc = up(p.o_g1, g1.data(), g1.size() * 8)) ||
+      (rc = up(p.o_g2, g2.data(), g2.size() * 8)) ||
+      (rc = up(p.o_blk, p.info.data(), p.info.size() * sizeof(BlockInfo)))) {
+    delete c;
+    return rc;
+  }
+  for (int kind = 0; kind < 4; kind++) {
+    c->ops[kind] = (GhostOp*)(w + p.o_ops[kind]);
+    c->nops[kind] = (int64_t)p.ops[kind].size();
+    if ((rc = up(p.o_ops[kind], p.ops[kind].data(), p.ops[kind].size() * sizeof(GhostOp)))) {
+      delete c;
+      return rc;
+    }
+  }
+  Launch& L = c->L;
+  L.blk = (const BlockInfo*)(w + p.o_blk);
+  L.nblk = desc->n_blocks;
+  for (int k = 0; k < 3; k++) {
+    L.max_np[k] = p.max_np[k];
+    L.max_n[k] = p.max_n[k];
+    L.ph.dx[k] = (desc->xmax[k] - desc->xmin[k]) / desc->n_eff[k];
+  }
+  L.geo.c = (const double*)(w + p.o_gc);
+  L.geo.f1 = (const double*)(w + p.o_g1);
+  L.geo.f2 = (const double*)(w + p.o_g2);
+  L.geo.ncol = p.ncol;
+  L.geo.ti = p.ti;
+  L.ph.gam = desc->gamma_ad;
+  L.ph.courant = desc->courant;
+  L.ph.tol = desc->c2p_tol;
+  L.ph.bsq_rho_max = desc->bsq_rho_max;
+  L.ph.bsq_u_max = desc->bsq_u_max;
+  L.ph.gamma_max = desc->gamma_max;
+  L.ph.maxit = desc->c2p_maxit;
+  L.ph.ng = desc->n_ghost;
+  L.cnt = (Counters*)(w + p.o_cnt);
+  L.stream = c->stream;
+  c->profile = desc->profile != 0;
+  launch_counters_reset(L, true);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));   // host staging vectors go out of scope
+  HIPCHK(hipEventCreate(&c->ev0));
+  HIPCHK(hipEventCreate(&c->ev1));
+  *out = c;
+  return GRMHD_OK;
+}
+
+// kernel-class timing with event pairs on the library stream (desc.profile)
+static void prof_begin(grmhd_ctx* c, int cls) {
+  if (!c->profile) return;
+  if (c->prof_used + 2 > c->prof_ev.size()) {
+    const size_t add = 512;
+    for (size_t q = 0; q < add; q++) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      c->prof_ev.push_back(e);
+    }
+  }
+  (void)hipEventRecord(c->prof_ev[c->prof_used], c->stream);
+  c->prof_cls.push_back(cls);
+}
+static void prof_end(grmhd_ctx* c) {
+  if (!c->profile || c->prof_cls.size() * 2 != c->prof_used + 2) return;
+  (void)hipEventRecord(c->prof_ev[c->prof_used + 1], c->stream);
+  c->prof_used += 2;
+}
+
+static void fill_ghosts(grmhd_ctx* c, double* P, double* B) {
+  prof_begin(c, KC_GHOST);
+  launch_ghost_cells(c->L, c->ops[0], c->nops[0], P);
+  for (int k = 0; k < 3; k++) launch_ghost_faces(c->L, c->ops[k + 1], c->nops[k + 1], B, k);
+  prof_end(c);
+}
+
+static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double* Ps,
+                  const double* Bs, double factor, double* Pout, double* Bout) {
+  const Launch& L = c->L;
+  const int recon = c->plan.d.recon, riem = c->plan.d.riemann;
+  prof_begin(c, KC_BCELL);
+  launch_bcell(L, Bs, c->bc);
+  prof_end(c);
+  for (int dir = 1; dir <= 3; dir++) {
+    prof_begin(c, KC_FLUX1 + dir - 1);
+    launch_flux(L, dir, recon, riem, Ps, c->bc, Bs, c->f);
+    prof_end(c);
+  }
+  prof_begin(c, KC_EMF);
+  launch_emf(L, c->f, c->e);
+  prof_end(c);
+  prof_begin(c, KC_UPDATE);
+  launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout);
+  prof_end(c);
+}
+
+int grmhd_step(grmhd_ctx* c, int32_t n_cycles, grmhd_step_stats* stats) {
+  if (!c) return fail(GRMHD_EINVAL, "NULL context");
+  if (n_cycles < 0) return fail(GRMHD_EINVAL, "negative step count");
+  const Launch& L = c->L;
+  HIPCHK(hipEventRecord(c->ev0, c->stream));
+  launch_counters_reset(L, false);
+  double* P = c->bufs.prim;
+  for (int s = 0; s < n_cycles; s++) {
+    double* Bcur = c->b_in_alt ? c->balt : c->bufs.bface;
+    double* Both = c->b_in_alt ? c->bufs.bface : c->balt;
+    fill_ghosts(c, P, Bcur);
+    prof_begin(c, KC_DT);
+    launch_dt(L, P, Bcur);
+    prof_end(c);
+    stage(c, P, Bcur, P, Bcur, 0.5, c->ps, Both);        // predictor to t + dt/2
+    fill_ghosts(c, c->ps, Both);
+    stage(c, P, Bcur, c->ps, Both, 1.0, P, Both);         // corrector to t + dt
+    launch_tsim(L);
+    c->b_in_alt = !c->b_in_alt;
+  }
+  if (c->b_in_alt) {
+    launch_copy(L, c->balt, c->bufs.bface, c->plan.vtot * 3);
+    c->b_in_alt = false;
+  }
+  fill_ghosts(c, P, c->bufs.bface);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(c->ev1, c->stream));
+  double cls_ms[KC_N] = {};
+  int64_t cls_n[KC_N] = {};
+  if (c->profile) {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (size_t q = 0; q < c->prof_cls.size(); q++) {
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, c->prof_ev[2 * q], c->prof_ev[2 * q + 1]));
+      cls_ms[c->prof_cls[q]] += ms;
+      cls_n[c->prof_cls[q]] += 1;
+    }
+    c->prof_cls.clear();
+    c->prof_used = 0;
+  }
+  if (stats) {
+    Counters h;
+    HIPCHK(hipMemcpyAsync(&h, L.cnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    std::memset(stats, 0, sizeof(*stats));
+    const int64_t cells = c->plan.n_interior;
+    const int64_t eff = (int64_t)c->plan.d.n_eff[0] * c->plan.d.n_eff[1] * c->plan.d.n_eff[2];
+    stats->real_zone_cycles = cells * n_cycles;
+    stats->lat_eff_zone_cycles = cells * n_cycles;
+    stats->amr_lat_eff_zone_cycles = eff * n_cycles;
+    stats->steps_per_level[0] = n_cycles;
+    for (int q = 0; q < 64; q++) stats->c2p_iter_hist[q] = (int64_t)h.hist[q];
+    for (int q = 0; q < 5; q++) stats->c2p_tier[q] = (int64_t)h.tier[q];
+    stats->floor_hits = (int64_t)h.floors;
+    stats->dt_min = h.dt_last;
+    stats->t_sim = h.t_sim;
+    float ms = 0.0f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    stats->kernel_ms = ms;
+    for (int q = 0; q < KC_N; q++) {
+      stats->class_ms[q] = cls_ms[q];
+      stats->class_launches[q] = cls_n[q];
+    }
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_cons2prim(grmhd_ctx* c, const grmhd_c2p_batch* b, void* hip_stream) {
+  (void)c;
+  if (!b) return fail(GRMHD_EINVAL, "NULL batch");
+  if (b->n < 0) return fail(GRMHD_EINVAL, "negative batch size");
+  if (b->n > 0 && (!b->U || !b->geom || !b->guess || !b->prev || !b->P || !b->iters || !b->tier))
+    return fail(GRMHD_EINVAL, "NULL batch array");
+  if (b->maxit < 1 || b->maxit > 62 || !(b->tol > 0.0)) return fail(GRMHD_EINVAL, "bad tol/maxit");
+  launch_c2p_batch(b->n, b->U, b->geom, b->guess, b->prev, b->P, b->iters, b->tier, b->gamma_ad,
+                   b->tol, b->maxit, (hipStream_t)hip_stream);
+  HIPCHK(hipGetLastError());
+  return GRMHD_OK;
+}
+
+int grmhd_divb(grmhd_ctx* c, double* max_abs, double* max_rel, double* field) {
+  if (!c) return fail(GRMHD_EINVAL, "NULL context");
+  launch_counters_reset(c->L, false);
+  launch_divb(c->L, c->bufs.bface, field);
+  HIPCHK(hipGetLastError());
+  Counters h;
+  HIPCHK(hipMemcpyAsync(&h, c->L.cnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double a, r;
+  std::memcpy(&a, &h.divb_abs, 8);
+  std::memcpy(&r, &h.divb_rel, 8);
+  if (max_abs) *max_abs = a;
+  if (max_rel) *max_rel = r;
+  return GRMHD_OK;
+}
+
+int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes) {
+  if (!bytes) return fail(GRMHD_EINVAL, "NULL argument");
+  if (what < 0 || what > 3) return fail(GRMHD_EINVAL, "unknown table");
+  Plan p;
+  int rc = build_plan(desc, p, true);
+  if (rc) return rc;
+  const auto& v = p.ops[what];
+  const size_t need = v.size() * sizeof(GhostOp);
+  if (!host_buf) {
+    *bytes = need;
+    return GRMHD_OK;
+  }
+  if (*bytes < need) return fail(GRMHD_EINVAL, "buffer too small");
+  std::memcpy(host_buf, v.data(), need);
+  *bytes = need;
+  return GRMHD_OK;
+}
+
+int grmhd_destroy(grmhd_ctx* c) {
+  if (!c) return GRMHD_OK;
+  (void)hipEventDestroy(c->ev0);
+  (void)hipEventDestroy(c->ev1);
+  for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+  delete c;
+  return GRMHD_OK;
+}
+
+const char* grmhd_last_error(void) { return g_err.c_str(); }
+
+// host-side geometry of the planner at one point (for CPU checks of the tables):
+// out[15] metric entries in table order, conn[40] Christoffel symbols (nullable)
+int grmhd_geometry_point(int32_t coords, double spin_a, double x1, double x2, double* out,
+                         double* conn) {
+  if (!out) return fail(GRMHD_EINVAL, "NULL output");
+  if (coords != GRMHD_MINK_CART && coords != GRMHD_KS_LOGSPH) return fail(GRMHD_EINVAL, "coords");
+  geometry_point(coords, spin_a, x1, x2, out, conn);
+  return GRMHD_OK;
+}
+
+}  // extern "C"

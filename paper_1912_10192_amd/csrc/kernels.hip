@@ -1,0 +1,579 @@
+// kernels.hip -- HIP kernels of the GRMHD block update for gfx950 (CDNA4), FP64.
+//
+// One stage of the midpoint method (Sec. 2.1) runs as: ghost gather (cells, three face
+// components) -> cell-centred field -> face fluxes along x1, x2, x3 -> edge EMFs ->
+// cell update (constrained transport, conserved update with sources, inversion, floors).
+// All state is structure-of-arrays per block with x1 fastest, so every kernel reads and
+// writes consecutive doubles across the lanes of a wavefront.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "device.h"
+#include "internal.h"
+
+namespace grmhd {
+
+constexpr int NT = 256;   // threads per workgroup (four wavefronts)
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// add one to ctr[value] for every active lane, one atomic per distinct value per wave
+__device__ __forceinline__ void wave_histogram(unsigned long long* ctr, int value, bool active) {
+  unsigned long long mask = __ballot(active);
+  while (mask) {
+    const int leader = __ffsll((long long)mask) - 1;
+    const int v = __shfl(value, leader);
+    const unsigned long long same = __ballot(active && value == v);
+    if (lane_id() == leader) atomicAdd(&ctr[v], (unsigned long long)__popcll(same));
+    if (active && value == v) active = false;
+    mask = __ballot(active);
+  }
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ long long wave_sum(long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// decode a thread index of a box region (r0, r1, r2) starting at s into local coords
+struct Cell {
+  int I, J, K;
+  int64_t loc;
+};
+__device__ __forceinline__ bool region_cell(const BlockInfo& bi, int t, int r0, int r1, int r2,
+                                            int s0, int s1, int s2, Cell& c) {
+  if (t >= r0 * r1 * r2) return false;
+  const int i = t % r0;
+  const int q = t / r0;
+  const int j = q % r1;
+  const int k = q / r1;
+  c.I = s0 + i;
+  c.J = s1 + j;
+  c.K = s2 + k;
+  c.loc = ((int64_t)c.K * bi.np[1] + c.J) * bi.np[0] + c.I;
+  return true;
+}
+
+__device__ __forceinline__ int64_t geo_col(const GeoTab& G, const BlockInfo& bi, int J, int I) {
+  return (int64_t)(bi.gorg[1] + J) * G.ti + (bi.gorg[0] + I);
+}
+
+// ------------------------------------------------------------------ ghost gather
+
+__global__ __launch_bounds__(NT) void k_ghost_cells(const BlockInfo* __restrict__ blk,
+                                                    const GhostOp* __restrict__ ops, int64_t nops,
+                                                    double* __restrict__ P) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= nops) return;
+  const GhostOp op = ops[i];
+  const int sb = op.src_blkf & 0xFFFFFF, fl = (op.src_blkf >> 24) & 0xFF;
+  const BlockInfo d = blk[op.dst_blk], s = blk[sb];
+  const double* src = P + 5 * s.off + op.src_loc;
+  double* dst = P + 5 * d.off + op.dst_loc;
+#pragma unroll
+  for (int v = 0; v < 5; v++) {
+    double x = src[(int64_t)v * s.vol];
+    if (v == 3 && (fl & GF_FLIP)) x = -x;
+    if (v == 2 && (fl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
+    if (v == 2 && (fl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
+    dst[(int64_t)v * d.vol] = x;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_ghost_faces(const BlockInfo* __restrict__ blk,
+                                                    const GhostOp* __restrict__ ops, int64_t nops,
+                                                    double* __restrict__ B, int comp) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= nops) return;
+  const GhostOp op = ops[i];
+  const int sb = op.src_blkf & 0xFFFFFF, fl = (op.src_blkf >> 24) & 0xFF;
+  const BlockInfo d = blk[op.dst_blk], s = blk[sb];
+  double x = B[3 * s.off + (int64_t)comp * s.vol + op.src_loc];
+  if (fl & GF_ZERO) x = 0.0;
+  else if (fl & GF_FLIP) x = -x;
+  B[3 * d.off + (int64_t)comp * d.vol + op.dst_loc] = x;
+}
+
+// --------------------------------------------------------- cell-centred field
+
+// B^i at cell centres = average of the two face fields / sqrt(-g) (Sec. 2.5), for every
+// cell that has both faces in the padded block
+__global__ __launch_bounds__(NT) void k_bcell(Launch L, const double* __restrict__ B,
+                                              double* __restrict__ Bc) {
+  const BlockInfo bi = L.blk[blockIdx.y];
+  Cell c;
+  if (!region_cell(bi, blockIdx.x * NT + threadIdx.x, bi.np[0], bi.np[1], bi.np[2], 0, 0, 0, c))
+    return;
+  const int64_t V = bi.vol;
+  const double* b = B + 3 * bi.off;
+  double* o = Bc + 3 * bi.off;
+  const double gdet = L.geo.c[GDET * L.geo.ncol + geo_col(L.geo, bi, c.J, c.I)];
+  const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
+  if (c.I + 1 < bi.np[0]) o[c.loc] = 0.5 * (b[c.loc] + b[c.loc + 1]) / gdet;
+  if (c.J + 1 < bi.np[1]) o[V + c.loc] = 0.5 * (b[V + c.loc] + b[V + c.loc + s2]) / gdet;
+  if (c.K + 1 < bi.np[2]) o[2 * V + c.loc] = 0.5 * (b[2 * V + c.loc] + b[2 * V + c.loc + s3]) / gdet;
+}
+
+// ------------------------------------------------------------------ face fluxes
+
+// One thread per face along x^DIR.  Normal range [ng, ng + n], transverse range widened
+// by one ghost layer so the edge EMFs of every interior face have their four fluxes.
+template <int DIR, int RECON, int RIEMANN>
+__global__ __launch_bounds__(NT) void k_flux(Launch L, const double* __restrict__ P,
+                                             const double* __restrict__ Bc,
+                                             const double* __restrict__ B,
+                                             double* __restrict__ F) {
+  const BlockInfo bi = L.blk[blockIdx.y];
+  const int g = L.ph.ng;
+  const int r0 = DIR == 1 ? bi.n[0] + 1 : bi.n[0] + 2;
+  const int r1 = DIR == 2 ? bi.n[1] + 1 : bi.n[1] + 2;
+  const int r2 = DIR == 3 ? bi.n[2] + 1 : bi.n[2] + 2;
+  Cell c;
+  if (!region_cell(bi, blockIdx.x * NT + threadIdx.x, r0, r1, r2, DIR == 1 ? g : g - 1,
+                   DIR == 2 ? g : g - 1, DIR == 3 ? g : g - 1, c))
+    return;
+  const int64_t V = bi.vol;
+  const int64_t st = DIR == 1 ? 1 : (DIR == 2 ? (int64_t)bi.np[0] : (int64_t)bi.np[0] * bi.np[1]);
+  const int64_t col = geo_col(L.geo, bi, c.J, c.I);
+  const double* tab = DIR == 1 ? L.geo.f1 : (DIR == 2 ? L.geo.f2 : L.geo.c);
+  const Metric m = load_metric(tab, L.geo.ncol, col);
+  double* out = F + 24 * bi.off + (int64_t)(DIR - 1) * 8 * V + c.loc;
+  if (DIR == 2 && m.gdet == 0.0) {   // the polar axis carries no flux
+#pragma unroll
+    for (int q = 0; q < 8; q++) out[q * V] = 0.0;
+    return;
+  }
+  constexpr int t1 = DIR == 1 ? 1 : 0;   // transverse field components (0-based)
+  constexpr int t2 = DIR == 3 ? 1 : 2;
+  double PL[5], PR[5], BL[3], BR[3];
+  {
+    const double* p = P + 5 * bi.off + c.loc;
+    double s[6];
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+#pragma unroll
+      for (int k = 0; k < 6; k++)
+        s[k] = (RECON == 0 && (k == 0 || k == 5)) ? 0.0 : p[(int64_t)v * V + (k - 3) * st];
+      recon_face<RECON>(s, PL[v], PR[v]);
+    }
+    const double* bc = Bc + 3 * bi.off + c.loc;
+#pragma unroll
+    for (int k = 0; k < 6; k++)
+      s[k] = (RECON == 0 && (k == 0 || k == 5)) ? 0.0 : bc[(int64_t)t1 * V + (k - 3) * st];
+    recon_face<RECON>(s, BL[t1], BR[t1]);
+#pragma unroll
+    for (int k = 0; k < 6; k++)
+      s[k] = (RECON == 0 && (k == 0 || k == 5)) ? 0.0 : bc[(int64_t)t2 * V + (k - 3) * st];
+    recon_face<RECON>(s, BL[t2], BR[t2]);
+    const double bn = B[3 * bi.off + (int64_t)(DIR - 1) * V + c.loc] / m.gdet;
+    BL[DIR - 1] = bn;
+    BR[DIR - 1] = bn;
+  }
+  const double gam = L.ph.gam;
+  double UL[9], UR[9], FL[8], FR[8];
+  double vmaxL, vminL, vmaxR, vminR;
+  {
+    Fluid f;
+    fluid_state(PL, BL, m, f);
+    flux_vector<0>(PL, f, m, gam, UL);
+    flux_vector<DIR>(PL, f, m, gam, FL);
+    wave_speeds<DIR>(PL, f, m, gam, vmaxL, vminL);
+  }
+  {
+    Fluid f;
+    fluid_state(PR, BR, m, f);
+    flux_vector<0>(PR, f, m, gam, UR);
+    flux_vector<DIR>(PR, f, m, gam, FR);
+    wave_speeds<DIR>(PR, f, m, gam, vmaxR, vminR);
+  }
+  // conserved components in flux order: mass, energy, momenta, transverse field, entropy
+  constexpr int uidx[8] = {0, 1, 2, 3, 4, 5 + t1, 5 + t2, 8};
+  const double cmax = fmax(0.0, fmax(vmaxL, vmaxR));
+  const double cmin = -fmin(0.0, fmin(vminL, vminR));
+  if (RIEMANN == 0) {
+    const double cc = fmax(cmax, cmin);
+#pragma unroll
+    for (int q = 0; q < 8; q++) out[q * V] = 0.5 * (FL[q] + FR[q] - cc * (UR[uidx[q]] - UL[uidx[q]]));
+  } else {
+    if (cmax + cmin > 0.0) {
+      const double ic = 1.0 / (cmax + cmin);
+#pragma unroll
+      for (int q = 0; q < 8; q++)
+        out[q * V] = (cmin * FR[q] + cmax * FL[q] - cmax * cmin * (UR[uidx[q]] - UL[uidx[q]])) * ic;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; q++) out[q * V] = 0.5 * (FL[q] + FR[q]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ edge EMFs
+
+// E^1 at (i, j-1/2, k-1/2), E^2 at (i-1/2, j, k-1/2), E^3 at (i-1/2, j-1/2, k): the
+// average of the four face fluxes of B around the edge (Sec. 2.5); zero on the axis.
+__global__ __launch_bounds__(NT) void k_emf(Launch L, const double* __restrict__ F,
+                                            double* __restrict__ E) {
+  const BlockInfo bi = L.blk[blockIdx.y];
+  const int g = L.ph.ng;
+  Cell c;
+  if (!region_cell(bi, blockIdx.x * NT + threadIdx.x, bi.n[0] + 1, bi.n[1] + 1, bi.n[2] + 1, g, g,
+                   g, c))
+    return;
+  const int64_t V = bi.vol;
+  const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
+  const double* f = F + 24 * bi.off + c.loc;
+  const double* F1B2 = f + 5 * V;    // x1 flux of B^2
+  const double* F1B3 = f + 6 * V;    // x1 flux of B^3
+  const double* F2B1 = f + 13 * V;   // x2 flux of B^1
+  const double* F2B3 = f + 14 * V;   // x2 flux of B^3
+  const double* F3B1 = f + 21 * V;   // x3 flux of B^1
+  const double* F3B2 = f + 22 * V;   // x3 flux of B^2
+  const bool pole = L.geo.f2[GDET * L.geo.ncol + geo_col(L.geo, bi, c.J, c.I)] == 0.0;
+  double* e = E + 3 * bi.off + c.loc;
+  if (c.I < g + bi.n[0])
+    e[0] = pole ? 0.0 : 0.25 * (F3B2[0] + F3B2[-s2] - F2B3[-s3] - F2B3[0]);
+  if (c.J < g + bi.n[1]) e[V] = 0.25 * (F1B3[-s3] + F1B3[0] - F3B1[0] - F3B1[-1]);
+  if (c.K < g + bi.n[2])
+    e[2 * V] = pole ? 0.0 : 0.25 * (F2B1[-1] + F2B1[0] - F1B2[0] - F1B2[-s2]);
+}
+
+// ------------------------------------------------------------------ cell update
+
+template <bool STATS>
+__global__ __launch_bounds__(NT) void k_update(Launch L, const double* __restrict__ Pn,
+                                               const double* __restrict__ Bn,
+                                               const double* __restrict__ Ps,
+                                               const double* __restrict__ Bcs,
+                                               const double* __restrict__ F,
+                                               const double* __restrict__ E, double dt_factor,
+                                               double* __restrict__ Pout,
+                                               double* __restrict__ Bout) {
+  const BlockInfo bi = L.blk[blockIdx.y];
+  const int g = L.ph.ng;
+  Cell c;
+  const bool valid = region_cell(bi, blockIdx.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
+                                 g, g, c);
+  int tier = 0, iters = 0, hits = 0;
+  if (valid) {
+    const double dt = L.ph.courant * __longlong_as_double((long long)L.cnt->dt_bits);
+    const double dts = dt_factor * dt;
+    const int64_t V = bi.vol;
+    const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
+    const double dx1 = L.ph.dx[0], dx2 = L.ph.dx[1], dx3 = L.ph.dx[2];
+    const int64_t l = c.loc;
+    const double* e1 = E + 3 * bi.off;
+    const double* e2 = e1 + V;
+    const double* e3 = e2 + V;
+    const double* b1 = Bn + 3 * bi.off;
+    const double* b2 = b1 + V;
+    const double* b3 = b2 + V;
+    const GeoTab& G = L.geo;
+    const int64_t col = geo_col(G, bi, c.J, c.I);
+    const bool pole_lo = G.f2[GDET * G.ncol + col] == 0.0;
+    const bool pole_hi = G.f2[GDET * G.ncol + col + G.ti] == 0.0;
+    // constrained transport of the six faces of this cell (Sec. 2.5)
+    const double nb1lo = b1[l] + dts * ((e2[l + s3] - e2[l]) / dx3 - (e3[l + s2] - e3[l]) / dx2);
+    const double nb1hi =
+        b1[l + 1] + dts * ((e2[l + 1 + s3] - e2[l + 1]) / dx3 - (e3[l + 1 + s2] - e3[l + 1]) / dx2);
+    const double nb2lo = pole_lo ? 0.0
+        : b2[l] + dts * ((e3[l + 1] - e3[l]) / dx1 - (e1[l + s3] - e1[l]) / dx3);
+    const double nb2hi = pole_hi ? 0.0
+        : b2[l + s2] + dts * ((e3[l + s2 + 1] - e3[l + s2]) / dx1 - (e1[l + s2 + s3] - e1[l + s2]) / dx3);
+    const double nb3lo = b3[l] + dts * ((e1[l + s2] - e1[l]) / dx2 - (e2[l + 1] - e2[l]) / dx1);
+    const double nb3hi =
+        b3[l + s3] + dts * ((e1[l + s3 + s2] - e1[l + s3]) / dx2 - (e2[l + s3 + 1] - e2[l + s3]) / dx1);
+    double* o1 = Bout + 3 * bi.off;
+    double* o2 = o1 + V;
+    double* o3 = o2 + V;
+    o1[l] = nb1lo;
+    o2[l] = nb2lo;
+    o3[l] = nb3lo;
+    if (c.I == g + bi.n[0] - 1) o1[l + 1] = nb1hi;
+    if (c.J == g + bi.n[1] - 1) o2[l + s2] = nb2hi;
+    if (c.K == g + bi.n[2] - 1) o3[l + s3] = nb3hi;
+
+    const Metric m = load_metric(G.c, G.ncol, col);
+    // U^n recomputed from P^n (Sec. 2.5)
+    double U[9];
+    {
+      double P0[5], B0[3];
+#pragma unroll
+      for (int v = 0; v < 5; v++) P0[v] = Pn[5 * bi.off + (int64_t)v * V + l];
+      B0[0] = 0.5 * (b1[l] + b1[l + 1]) / m.gdet;
+      B0[1] = 0.5 * (b2[l] + b2[l + s2]) / m.gdet;
+      B0[2] = 0.5 * (b3[l] + b3[l + s3]) / m.gdet;
+      Fluid f;
+      fluid_state(P0, B0, m, f);
+      flux_vector<0>(P0, f, m, L.ph.gam, U);
+    }
+    double PS[5];
+#pragma unroll
+    for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * V + l];
+    double Q[4];
+    {
+      double BS[3];
+#pragma unroll
+      for (int i = 0; i < 3; i++) BS[i] = Bcs[3 * bi.off + (int64_t)i * V + l];
+      Fluid f;
+      fluid_state(PS, BS, m, f);
+      geometric_source(PS, f, m, G.c, G.ncol, col, L.ph.gam, Q);
+    }
+    const double* f1 = F + 24 * bi.off + l;
+    const double* f2 = f1 + 8 * V;
+    const double* f3 = f2 + 8 * V;
+    constexpr int fq[6] = {0, 1, 2, 3, 4, 7};
+    constexpr int uq[6] = {0, 1, 2, 3, 4, 8};
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+      const int64_t o = (int64_t)fq[k] * V;
+      const double div = (f1[o + 1] - f1[o]) / dx1 + (f2[o + s2] - f2[o]) / dx2 +
+                         (f3[o + s3] - f3[o]) / dx3;
+      const double q = (k >= 1 && k <= 4) ? Q[k - 1] : 0.0;
+      U[uq[k]] = U[uq[k]] - dts * div + dts * q;
+    }
+    U[5] = 0.5 * (nb1lo + nb1hi);
+    U[6] = 0.5 * (nb2lo + nb2hi);
+    U[7] = 0.5 * (nb3lo + nb3hi);
+    double Pnew[5];
+    tier = cons2prim(U, m, L.ph.gam, PS, PS, false, L.ph.tol, L.ph.maxit, Pnew, iters);
+    const double Bnew[3] = {U[5] / m.gdet, U[6] / m.gdet, U[7] / m.gdet};
+    hits = apply_floors(Pnew, Bnew, m, G.c[RHOFL * G.ncol + col], G.c[UFL * G.ncol + col],
+                        L.ph.bsq_rho_max, L.ph.bsq_u_max, L.ph.gamma_max);
+#pragma unroll
+    for (int v = 0; v < 5; v++) Pout[5 * bi.off + (int64_t)v * V + l] = Pnew[v];
+  }
+  if (STATS) {
+    wave_histogram(L.cnt->tier, tier, valid);
+    wave_histogram(L.cnt->hist, iters < 63 ? iters : 63, valid);
+    const long long h = wave_sum(valid ? hits : 0);
+    if (lane_id() == 0 && h) atomicAdd(&L.cnt->floors, (unsigned long long)h);
+  }
+}
+
+// ------------------------------------------------------------- Courant reduction
+
+// per cell 1/dt = sum_d max(|v+|, |v-|)/dx_d from the cell-centred state; the minimum
+// of dt over all cells is kept as IEEE bits (order-preserving for positive doubles)
+__global__ __launch_bounds__(NT) void k_dt(Launch L, const double* __restrict__ P,
+                                           const double* __restrict__ B) {
+  const BlockInfo bi = L.blk[blockIdx.y];
+  const int g = L.ph.ng;
+  Cell c;
+  const bool valid = region_cell(bi, blockIdx.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
+                                 g, g, c);
+  double dtc = __longlong_as_double(0x7FF0000000000000LL);
+  if (valid) {
+    const int64_t V = bi.vol, l = c.loc;
+    const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
+    const int64_t col = geo_col(L.geo, bi, c.J, c.I);
+    const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
+    double Pc[5], Bc[3];
+#pragma unroll
+    for (int v = 0; v < 5; v++) Pc[v] = P[5 * bi.off + (int64_t)v * V + l];
+    const double* b = B + 3 * bi.off;
+    Bc[0] = 0.5 * (b[l] + b[l + 1]) / m.gdet;
+    Bc[1] = 0.5 * (b[V + l] + b[V + l + s2]) / m.gdet;
+    Bc[2] = 0.5 * (b[2 * V + l] + b[2 * V + l + s3]) / m.gdet;
+    Fluid f;
+    fluid_state(Pc, Bc, m, f);
+    double vp, vm, inv = 0.0;
+    wave_speeds<1>(Pc, f, m, L.ph.gam, vp, vm);
+    inv += fmax(fabs(vp), fabs(vm)) / L.ph.dx[0];
+    wave_speeds<2>(Pc, f, m, L.ph.gam, vp, vm);
+    inv += fmax(fabs(vp), fabs(vm)) / L.ph.dx[1];
+    wave_speeds<3>(Pc, f, m, L.ph.gam, vp, vm);
+    inv += fmax(fabs(vp), fabs(vm)) / L.ph.dx[2];
+    dtc = 1.0 / inv;
+  }
+  dtc = wave_min(dtc);
+  if (lane_id() == 0) atomicMin(&L.cnt->dt_bits, (unsigned long long)__double_as_longlong(dtc));
+}
+
+__global__ void k_reset(Counters* cnt, int all) {
+  const int t = threadIdx.x;
+  if (t < 5) cnt->tier[t] = 0;
+  if (t < 64) cnt->hist[t] = 0;
+  if (t == 0) {
+    cnt->floors = 0;
+    cnt->divb_abs = 0;
+    cnt->divb_rel = 0;
+    cnt->dt_bits = 0x7FF0000000000000ULL;
+    if (all) {
+      cnt->t_sim = 0.0;
+      cnt->dt_last = 0.0;
+    }
+  }
+}
+
+__global__ void k_tsim(Counters* cnt, double courant) {
+  if (threadIdx.x == 0) {
+    const double dt = courant * __longlong_as_double((long long)cnt->dt_bits);
+    cnt->t_sim += dt;
+    cnt->dt_last = dt;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_copy(const double* __restrict__ s, double* __restrict__ d,
+                                             int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < n; i += (int64_t)gridDim.x * NT)
+    d[i] = s[i];
+}
+
+// ----------------------------------------------------------------- divergence
+
+__global__ __launch_bounds__(NT) void k_divb(Launch L, const double* __restrict__ B,
+                                             double* __restrict__ field) {
+  const BlockInfo bi = L.blk[blockIdx.y];
+  const int g = L.ph.ng;
+  Cell c;
+  const bool valid = region_cell(bi, blockIdx.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
+                                 g, g, c);
+  double a = 0.0, r = 0.0;
+  if (valid) {
+    const int64_t V = bi.vol, l = c.loc;
+    const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
+    const double* b = B + 3 * bi.off;
+    const double d1 = b[l + 1], d0 = b[l], e1 = b[V + l + s2], e0 = b[V + l];
+    const double f1 = b[2 * V + l + s3], f0 = b[2 * V + l];
+    const double dv = (d1 - d0) / L.ph.dx[0] + (e1 - e0) / L.ph.dx[1] + (f1 - f0) / L.ph.dx[2];
+    const double den = (fabs(d1) + fabs(d0)) / L.ph.dx[0] + (fabs(e1) + fabs(e0)) / L.ph.dx[1] +
+                       (fabs(f1) + fabs(f0)) / L.ph.dx[2];
+    if (field) field[5 * bi.off + l] = dv;
+    a = fabs(dv);
+    r = den > 0.0 ? a / den : 0.0;
+  }
+  a = wave_max(a);
+  r = wave_max(r);
+  if (lane_id() == 0) {
+    atomicMax(&L.cnt->divb_abs, (unsigned long long)__double_as_longlong(a));
+    atomicMax(&L.cnt->divb_rel, (unsigned long long)__double_as_longlong(r));
+  }
+}
+
+// ------------------------------------------------------------ batch inversion
+
+__global__ __launch_bounds__(NT) void k_c2p_batch(int64_t n, const double* __restrict__ U,
+                                                  const double* __restrict__ geom,
+                                                  const double* __restrict__ guess,
+                                                  const double* __restrict__ prev,
+                                                  double* __restrict__ P, int32_t* __restrict__ iters,
+                                                  int32_t* __restrict__ tier, double gam, double tol,
+                                                  int32_t maxit) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const Metric m = load_metric(geom, n, i);
+  double u[9], gs[5], pv[5], out[5];
+#pragma unroll
+  for (int q = 0; q < 9; q++) u[q] = U[q * n + i];
+  bool distinct = false;
+#pragma unroll
+  for (int v = 0; v < 5; v++) {
+    gs[v] = guess[v * n + i];
+    pv[v] = prev[v * n + i];
+    distinct |= gs[v] != pv[v];
+  }
+  int it = 0;
+  const int t = cons2prim(u, m, gam, gs, pv, distinct, tol, maxit, out, it);
+#pragma unroll
+  for (int v = 0; v < 5; v++) P[v * n + i] = out[v];
+  iters[i] = it;
+  tier[i] = t;
+}
+
+// ================================================================== launchers
+
+static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+void launch_ghost_cells(const Launch& L, const GhostOp* ops, int64_t nops, double* P) {
+  if (nops == 0) return;
+  hipLaunchKernelGGL(k_ghost_cells, dim3(cdiv(nops, NT)), dim3(NT), 0, L.stream, L.blk, ops, nops, P);
+}
+
+void launch_ghost_faces(const Launch& L, const GhostOp* ops, int64_t nops, double* B, int comp) {
+  if (nops == 0) return;
+  hipLaunchKernelGGL(k_ghost_faces, dim3(cdiv(nops, NT)), dim3(NT), 0, L.stream, L.blk, ops, nops,
+                     B, comp);
+}
+
+void launch_bcell(const Launch& L, const double* B, double* Bc) {
+  const int64_t r = (int64_t)L.max_np[0] * L.max_np[1] * L.max_np[2];
+  hipLaunchKernelGGL(k_bcell, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, B, Bc);
+}
+
+template <int DIR>
+static void flux_dir(const Launch& L, int recon, int riemann, const double* P, const double* Bc,
+                     const double* B, double* F) {
+  int64_t r = 1;
+  for (int d = 0; d < 3; d++) r *= (d == DIR - 1) ? L.max_n[d] + 1 : L.max_n[d] + 2;
+  const dim3 grid(cdiv(r, NT), L.nblk);
+  if (recon == 0 && riemann == 0)
+    hipLaunchKernelGGL((k_flux<DIR, 0, 0>), grid, dim3(NT), 0, L.stream, L, P, Bc, B, F);
+  else if (recon == 0)
+    hipLaunchKernelGGL((k_flux<DIR, 0, 1>), grid, dim3(NT), 0, L.stream, L, P, Bc, B, F);
+  else if (riemann == 0)
+    hipLaunchKernelGGL((k_flux<DIR, 1, 0>), grid, dim3(NT), 0, L.stream, L, P, Bc, B, F);
+  else
+    hipLaunchKernelGGL((k_flux<DIR, 1, 1>), grid, dim3(NT), 0, L.stream, L, P, Bc, B, F);
+}
+
+void launch_flux(const Launch& L, int dir, int recon, int riemann, const double* P,
+                 const double* Bc, const double* B, double* F) {
+  if (dir == 1) flux_dir<1>(L, recon, riemann, P, Bc, B, F);
+  else if (dir == 2) flux_dir<2>(L, recon, riemann, P, Bc, B, F);
+  else flux_dir<3>(L, recon, riemann, P, Bc, B, F);
+}
+
+void launch_emf(const Launch& L, const double* F, double* E) {
+  const int64_t r = (int64_t)(L.max_n[0] + 1) * (L.max_n[1] + 1) * (L.max_n[2] + 1);
+  hipLaunchKernelGGL(k_emf, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, F, E);
+}
+
+void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
+                   const double* Bcs, const double* F, const double* E, double dt_factor,
+                   double* Pout, double* Bout) {
+  const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
+  hipLaunchKernelGGL(k_update<true>, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, Pn, Bn,
+                     Ps, Bcs, F, E, dt_factor, Pout, Bout);
+}
+
+void launch_dt(const Launch& L, const double* P, const double* B) {
+  const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
+  hipLaunchKernelGGL(k_dt, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, P, B);
+}
+
+void launch_counters_reset(const Launch& L, bool all) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, L.stream, L.cnt, all ? 1 : 0);
+}
+
+void launch_tsim(const Launch& L) {
+  hipLaunchKernelGGL(k_tsim, dim3(1), dim3(64), 0, L.stream, L.cnt, L.ph.courant);
+}
+
+void launch_copy(const Launch& L, const double* src, double* dst, int64_t n) {
+  const unsigned nb = (unsigned)std::min<int64_t>(cdiv(n, NT), 4096);
+  hipLaunchKernelGGL(k_copy, dim3(nb), dim3(NT), 0, L.stream, src, dst, n);
+}
+
+void launch_divb(const Launch& L, const double* B, double* field) {
+  const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
+  hipLaunchKernelGGL(k_divb, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, B, field);
+}
+
+void launch_c2p_batch(int64_t n, const double* U, const double* geom, const double* guess,
+                      const double* prev, double* P, int32_t* iters, int32_t* tier, double gam,
+                      double tol, int32_t maxit, hipStream_t stream) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_c2p_batch, dim3(cdiv(n, NT)), dim3(NT), 0, stream, n, U, geom, guess, prev,
+                     P, iters, tier, gam, tol, maxit);
+}
+
+}  // namespace grmhd

@@ -1,0 +1,321 @@
+"""Python binding of libgrmhd.so (C ABI in include/grmhd.h).
+
+Argument marshalling only: every step of the update runs in the HIP library.  PyTorch
+provides device memory and the stream.  Importing this module does not load the
+library; the first call does, and raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libgrmhd.so")
+_lib = None
+
+ABI_VERSION = 1
+OK, EINVAL, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+MINK_CART, KS_LOGSPH = 0, 1
+PLM_MC, PPM = 0, 1
+LLF, HLLE = 0, 1
+BC_OUTFLOW, BC_POLAR, BC_PERIODIC = 0, 1, 2
+GUESS_PLAIN, GUESS_MLP = 0, 1
+
+# every symbol declared in include/grmhd.h
+EXPORTS = ("grmhd_sizes", "grmhd_block_layout", "grmhd_init_grid", "grmhd_step",
+           "grmhd_cons2prim", "grmhd_divb", "grmhd_plan_dump", "grmhd_geometry_point",
+           "grmhd_destroy", "grmhd_last_error")
+
+
+class BlockDesc(C.Structure):
+    _fields_ = [("lev", C.c_int32 * 3), ("lat", C.c_int32), ("org", C.c_int64 * 3),
+                ("n", C.c_int32 * 3)]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("abi_version", C.c_int32), ("coords", C.c_int32), ("spin_a", C.c_double),
+                ("gamma_ad", C.c_double), ("xmin", C.c_double * 3), ("xmax", C.c_double * 3),
+                ("n_eff", C.c_int32 * 3), ("n_ghost", C.c_int32), ("n_blocks", C.c_int32),
+                ("n_lat_levels", C.c_int32), ("blocks", C.POINTER(BlockDesc)),
+                ("recon", C.c_int32), ("riemann", C.c_int32), ("bc", C.c_int32 * 6),
+                ("courant", C.c_double), ("rho_fl_c", C.c_double), ("rho_fl_p", C.c_double),
+                ("u_fl_c", C.c_double), ("u_fl_p", C.c_double), ("bsq_rho_max", C.c_double),
+                ("bsq_u_max", C.c_double), ("gamma_max", C.c_double), ("c2p_guess", C.c_int32),
+                ("c2p_maxit", C.c_int32), ("c2p_tol", C.c_double), ("mlp_weights", C.c_void_p),
+                ("batched", C.c_int32), ("profile", C.c_int32)]
+
+
+KERNEL_CLASSES = ("ghost", "bcell", "flux1", "flux2", "flux3", "emf", "update", "dt")
+
+
+class Buffers(C.Structure):
+    _fields_ = [("prim", C.c_void_p), ("bface", C.c_void_p), ("work", C.c_void_p),
+                ("work_bytes", C.c_size_t)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("real_zone_cycles", C.c_int64), ("lat_eff_zone_cycles", C.c_int64),
+                ("amr_lat_eff_zone_cycles", C.c_int64), ("steps_per_level", C.c_int64 * 8),
+                ("c2p_iter_hist", C.c_int64 * 64), ("c2p_tier", C.c_int64 * 5),
+                ("floor_hits", C.c_int64), ("dt_min", C.c_double), ("t_sim", C.c_double),
+                ("kernel_ms", C.c_double), ("class_ms", C.c_double * 8),
+                ("class_launches", C.c_int64 * 8)]
+
+
+class C2PBatch(C.Structure):
+    _fields_ = [("n", C.c_int64), ("U", C.c_void_p), ("geom", C.c_void_p), ("guess", C.c_void_p),
+                ("prev", C.c_void_p), ("P", C.c_void_p), ("iters", C.c_void_p),
+                ("tier", C.c_void_p), ("gamma_ad", C.c_double), ("tol", C.c_double),
+                ("maxit", C.c_int32)]
+
+
+class GrmhdError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libgrmhd.so; raise if it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise GrmhdError(f"{SO_PATH} is not built; run paper_1912_10192_amd.build.build()")
+        L = C.CDLL(SO_PATH)
+        L.grmhd_sizes.argtypes = [C.POINTER(GridDesc), C.POINTER(C.c_size_t),
+                                  C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
+        L.grmhd_block_layout.argtypes = [C.POINTER(GridDesc), C.c_int32, C.POINTER(C.c_int64),
+                                         C.c_int32 * 3]
+        L.grmhd_init_grid.argtypes = [C.POINTER(GridDesc), C.POINTER(Buffers), C.c_void_p,
+                                      C.POINTER(C.c_void_p)]
+        L.grmhd_step.argtypes = [C.c_void_p, C.c_int32, C.POINTER(StepStats)]
+        L.grmhd_cons2prim.argtypes = [C.c_void_p, C.POINTER(C2PBatch), C.c_void_p]
+        L.grmhd_divb.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                 C.c_void_p]
+        L.grmhd_plan_dump.argtypes = [C.POINTER(GridDesc), C.c_int32, C.c_void_p,
+                                      C.POINTER(C.c_size_t)]
+        L.grmhd_geometry_point.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double,
+                                           C.c_void_p, C.c_void_p]
+        L.grmhd_destroy.argtypes = [C.c_void_p]
+        L.grmhd_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise GrmhdError(f"libgrmhd error {rc}: {lib().grmhd_last_error().decode()}")
+
+
+def uniform_blocks(n, block):
+    """blocks of size `block` tiling an n grid, x1 fastest in the block order"""
+    nb = [n[d] // block[d] for d in range(3)]
+    if any(nb[d] * block[d] != n[d] for d in range(3)):
+        raise ValueError("block size must divide the grid")
+    out = []
+    for k in range(nb[2]):
+        for j in range(nb[1]):
+            for i in range(nb[0]):
+                out.append(dict(org=(i * block[0], j * block[1], k * block[2]), n=tuple(block),
+                                lev=(0, 0, 0), lat=0))
+    return out
+
+
+class Desc:
+    """Owns a GridDesc and its block array built from a workload dict (configs.py)."""
+
+    def __init__(self, cfg: dict, blocks=None, batched=False, profile=False):
+        blocks = blocks if blocks is not None else uniform_blocks(cfg["n"], cfg.get("block", cfg["n"]))
+        self.cfg = cfg
+        self.blocks = (BlockDesc * len(blocks))()
+        for b, bd in enumerate(blocks):
+            for d in range(3):
+                self.blocks[b].lev[d] = bd["lev"][d]
+                self.blocks[b].org[d] = bd["org"][d]
+                self.blocks[b].n[d] = bd["n"][d]
+            self.blocks[b].lat = bd["lat"]
+        d = GridDesc()
+        d.abi_version = ABI_VERSION
+        d.coords = cfg["coords"]
+        d.spin_a = cfg.get("a", 0.0)
+        d.gamma_ad = cfg["gam"]
+        for k in range(3):
+            d.xmin[k] = cfg["xlo"][k]
+            d.xmax[k] = cfg["xhi"][k]
+            d.n_eff[k] = cfg["n"][k]
+        d.n_ghost = cfg["ng"]
+        d.n_blocks = len(blocks)
+        d.n_lat_levels = 1
+        d.blocks = C.cast(self.blocks, C.POINTER(BlockDesc))
+        d.recon = cfg["recon"]
+        d.riemann = cfg["riemann"]
+        for k in range(6):
+            d.bc[k] = cfg["bc"][k]
+        d.courant = cfg.get("courant", 0.8)
+        d.rho_fl_c = cfg.get("rho_fl_c", 0.0)
+        d.rho_fl_p = cfg.get("rho_fl_p", 0.0)
+        d.u_fl_c = cfg.get("u_fl_c", 0.0)
+        d.u_fl_p = cfg.get("u_fl_p", 0.0)
+        d.bsq_rho_max = cfg.get("bsq_rho_max", 1e300)
+        d.bsq_u_max = cfg.get("bsq_u_max", 1e300)
+        d.gamma_max = cfg.get("gamma_max", 1e150)
+        d.c2p_guess = GUESS_PLAIN
+        d.c2p_maxit = cfg.get("maxit", 50)
+        d.c2p_tol = cfg.get("tol", 1e-12)
+        d.mlp_weights = None
+        d.batched = 1 if batched else 0
+        d.profile = 1 if profile else 0
+        self.d = d
+
+    def sizes(self):
+        p, b, w = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        _check(lib().grmhd_sizes(C.byref(self.d), C.byref(p), C.byref(b), C.byref(w)))
+        return p.value, b.value, w.value
+
+    def layout(self, b):
+        off = C.c_int64()
+        np_ = (C.c_int32 * 3)()
+        _check(lib().grmhd_block_layout(C.byref(self.d), b, C.byref(off), np_))
+        return off.value, tuple(np_)
+
+    def plan_dump(self, what):
+        nbytes = C.c_size_t()
+        _check(lib().grmhd_plan_dump(C.byref(self.d), what, None, C.byref(nbytes)))
+        buf = np.zeros(nbytes.value // 4, dtype=np.int32)
+        _check(lib().grmhd_plan_dump(C.byref(self.d), what, buf.ctypes.data_as(C.c_void_p),
+                                     C.byref(nbytes)))
+        return buf.reshape(-1, 4)
+
+
+def geometry_point(coords, a, x1, x2):
+    out = np.zeros(15)
+    conn = np.zeros(40)
+    _check(lib().grmhd_geometry_point(coords, a, x1, x2, out.ctypes.data_as(C.c_void_p),
+                                      conn.ctypes.data_as(C.c_void_p)))
+    return out, conn
+
+
+# ------------------------------------------------------------------ state layout
+
+def scatter(desc: Desc, P, B1, B2, B3):
+    """global interior arrays -> packed per-block host arrays (prim, bface)"""
+    g = desc.cfg["ng"]
+    nprim, nbface, _ = desc.sizes()
+    prim = np.zeros(nprim)
+    bface = np.zeros(nbface)
+    for b in range(desc.d.n_blocks):
+        off, (n1p, n2p, n3p) = desc.layout(b)
+        V = n1p * n2p * n3p
+        bd = desc.blocks[b]
+        o = [bd.org[d] for d in range(3)]
+        n = [bd.n[d] for d in range(3)]
+        pv = prim[5 * off:5 * off + 5 * V].reshape(5, n3p, n2p, n1p)
+        bv = bface[3 * off:3 * off + 3 * V].reshape(3, n3p, n2p, n1p)
+        pv[:, g:g + n[2], g:g + n[1], g:g + n[0]] = P[:, o[2]:o[2] + n[2], o[1]:o[1] + n[1],
+                                                     o[0]:o[0] + n[0]]
+        bv[0, g:g + n[2], g:g + n[1], g:g + n[0] + 1] = B1[o[2]:o[2] + n[2], o[1]:o[1] + n[1],
+                                                          o[0]:o[0] + n[0] + 1]
+        bv[1, g:g + n[2], g:g + n[1] + 1, g:g + n[0]] = B2[o[2]:o[2] + n[2], o[1]:o[1] + n[1] + 1,
+                                                          o[0]:o[0] + n[0]]
+        bv[2, g:g + n[2] + 1, g:g + n[1], g:g + n[0]] = B3[o[2]:o[2] + n[2] + 1, o[1]:o[1] + n[1],
+                                                          o[0]:o[0] + n[0]]
+    return prim, bface
+
+
+def gather(desc: Desc, prim, bface):
+    """packed per-block host arrays -> global interior arrays (P, B1, B2, B3)"""
+    g = desc.cfg["ng"]
+    N1, N2, N3 = desc.cfg["n"]
+    P = np.zeros((5, N3, N2, N1))
+    B1 = np.zeros((N3, N2, N1 + 1))
+    B2 = np.zeros((N3, N2 + 1, N1))
+    B3 = np.zeros((N3 + 1, N2, N1))
+    for b in range(desc.d.n_blocks):
+        off, (n1p, n2p, n3p) = desc.layout(b)
+        V = n1p * n2p * n3p
+        bd = desc.blocks[b]
+        o = [bd.org[d] for d in range(3)]
+        n = [bd.n[d] for d in range(3)]
+        pv = prim[5 * off:5 * off + 5 * V].reshape(5, n3p, n2p, n1p)
+        bv = bface[3 * off:3 * off + 3 * V].reshape(3, n3p, n2p, n1p)
+        P[:, o[2]:o[2] + n[2], o[1]:o[1] + n[1], o[0]:o[0] + n[0]] = pv[:, g:g + n[2], g:g + n[1],
+                                                                        g:g + n[0]]
+        B1[o[2]:o[2] + n[2], o[1]:o[1] + n[1], o[0]:o[0] + n[0] + 1] = bv[0, g:g + n[2], g:g + n[1],
+                                                                          g:g + n[0] + 1]
+        B2[o[2]:o[2] + n[2], o[1]:o[1] + n[1] + 1, o[0]:o[0] + n[0]] = bv[1, g:g + n[2],
+                                                                          g:g + n[1] + 1, g:g + n[0]]
+        B3[o[2]:o[2] + n[2] + 1, o[1]:o[1] + n[1], o[0]:o[0] + n[0]] = bv[2, g:g + n[2] + 1,
+                                                                          g:g + n[1], g:g + n[0]]
+    return P, B1, B2, B3
+
+
+# ------------------------------------------------------------------ device grid
+
+class Grid:
+    """A grid on the GPU: caller-owned torch buffers plus the library context."""
+
+    def __init__(self, cfg: dict, state=None, blocks=None, batched=False, profile=False,
+                 device="cuda"):
+        import torch
+
+        self.torch = torch
+        self.desc = Desc(cfg, blocks=blocks, batched=batched, profile=profile)
+        nprim, nbface, nwork = self.desc.sizes()
+        self.device = torch.device(device)
+        self.prim = torch.zeros(nprim, dtype=torch.float64, device=self.device)
+        self.bface = torch.zeros(nbface, dtype=torch.float64, device=self.device)
+        self.work = torch.empty(nwork + 256, dtype=torch.uint8, device=self.device)
+        if state is not None:
+            self.set_state(*state)
+        wp = self.work.data_ptr()
+        wp_al = (wp + 255) & ~255
+        self.bufs = Buffers(self.prim.data_ptr(), self.bface.data_ptr(), wp_al, nwork)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.ctx = C.c_void_p()
+        _check(lib().grmhd_init_grid(C.byref(self.desc.d), C.byref(self.bufs),
+                                     C.c_void_p(self.stream.cuda_stream), C.byref(self.ctx)))
+
+    def close(self):
+        if self.ctx:
+            lib().grmhd_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, P, B1, B2, B3):
+        prim, bface = scatter(self.desc, P, B1, B2, B3)
+        self.prim.copy_(self.torch.from_numpy(prim))
+        self.bface.copy_(self.torch.from_numpy(bface))
+
+    def get_state(self):
+        self.torch.cuda.synchronize(self.device)
+        return gather(self.desc, self.prim.cpu().numpy(), self.bface.cpu().numpy())
+
+    def step(self, n=1, stats=True):
+        st = StepStats() if stats else None
+        _check(lib().grmhd_step(self.ctx, n, C.byref(st) if stats else None))
+        return st
+
+    def divb(self):
+        a, r = C.c_double(), C.c_double()
+        _check(lib().grmhd_divb(self.ctx, C.byref(a), C.byref(r), None))
+        return a.value, r.value
+
+
+def cons2prim_batch(U, geom, guess, prev, gam, tol=1e-12, maxit=50):
+    """flat-batch inversion on the GPU; all inputs float64 CUDA tensors [k][n]"""
+    import torch
+
+    n = U.shape[1]
+    P = torch.empty((5, n), dtype=torch.float64, device=U.device)
+    iters = torch.empty(n, dtype=torch.int32, device=U.device)
+    tier = torch.empty(n, dtype=torch.int32, device=U.device)
+    b = C2PBatch(n, U.data_ptr(), geom.data_ptr(), guess.data_ptr(), prev.data_ptr(), P.data_ptr(),
+                 iters.data_ptr(), tier.data_ptr(), gam, tol, maxit)
+    stream = torch.cuda.current_stream(U.device)
+    _check(lib().grmhd_cons2prim(None, C.byref(b), C.c_void_p(stream.cuda_stream)))
+    return P, iters, tier

@@ -1,0 +1,160 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the same seeded
+inputs.  Floating point bar (per step): rho pointwise relative <= 1e-11; u_g pointwise
+relative to rho + u_g of the cell <= 1e-11 (u_g is recovered as (W (1 - v^2) - rho)/gamma,
+so its rounding error scales with rho); utilde^i and the face fields norm-wise
+(max |diff| / max |oracle|) <= 1e-11."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_10192_amd import configs, grmhd, initdata
+from tests.helpers import mink_cfg, pad_global, random_periodic_state, unpad_global
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parity_err(gpu, orc):
+    """worst error of a GPU state against an oracle state (global interior arrays)"""
+    Pg, Bg = gpu[0], gpu[1:]
+    Po, Bo = orc[0], orc[1:]
+    errs = {}
+    errs["rho"] = float(np.max(np.abs(Pg[0] - Po[0]) / np.abs(Po[0])))
+    errs["u"] = float(np.max(np.abs(Pg[1] - Po[1]) / (np.abs(Po[0]) + np.abs(Po[1]))))
+    for v in (2, 3, 4):
+        s = np.abs(Po[v]).max()
+        errs[f"ut{v - 1}"] = float(np.abs(Pg[v] - Po[v]).max() / (s if s > 0 else 1.0))
+    for c in range(3):
+        s = np.abs(Bo[c]).max()
+        errs[f"B{c + 1}"] = float(np.abs(Bg[c] - Bo[c]).max() / (s if s > 0 else 1.0))
+    return errs
+
+
+def oracle_run(cfg, state, nsteps):
+    g = oracle.Grid(cfg)
+    Pp, Bp = pad_global(cfg, *state)
+    out = []
+    for _ in range(nsteps):
+        g.step(Pp, Bp, 1)
+        out.append(unpad_global(cfg, Pp, Bp))
+    return out, g
+
+
+def check_trajectory(cfg, state, nsteps, tol=TOL, blocks=None):
+    say(f"[parity] {cfg.get('name', 'grid')} n={cfg['n']} block={cfg.get('block')} steps={nsteps}")
+    ref, og = oracle_run(cfg, state, nsteps)
+    grid = grmhd.Grid(cfg, state=state, blocks=blocks)
+    worst = {}
+    for s in range(nsteps):
+        st = grid.step(1)
+        got = grid.get_state()
+        e = parity_err(got, ref[s])
+        say(f"  step {s}: " + " ".join(f"{k}={v:.2e}" for k, v in e.items()))
+        for k, v in e.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+        assert sum(st.c2p_tier) == 2 * int(np.prod(cfg["n"]))
+    assert max(worst.values()) <= tol, worst
+    return grid, ref
+
+
+def test_torus_tiny_plm_llf_trajectory():
+    cfg = dict(configs.TORUS_TINY)
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    grid, ref = check_trajectory(cfg, state, cfg["steps"])
+    a, r = grid.divb()
+    say(f"  divB max abs {a:.3e} rel {r:.3e}")
+    assert r < 1e-12
+
+
+def test_block_decomposition_is_bit_exact():
+    """one 64x32x32 block vs eight 32x16x16 blocks: identical bits"""
+    cfg1 = dict(configs.TORUS_TINY)
+    cfg8 = dict(cfg1, block=(32, 16, 16))
+    state = initdata.torus_state(cfg1["n"], **configs.TORUS_INIT)
+    say("[decomp] 1 vs 8 blocks, 3 steps")
+    g1 = grmhd.Grid(cfg1, state=state)
+    g8 = grmhd.Grid(cfg8, state=state)
+    g1.step(3)
+    g8.step(3)
+    s1, s8 = g1.get_state(), g8.get_state()
+    for a, b in zip(s1, s8):
+        assert np.array_equal(a, b)
+
+
+def test_torus_ppm_hlle_multiblock_trajectory():
+    cfg = configs.scaled(configs.TORUS_UNIFORM, (64, 32, 32), block=(16, 16, 16))
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    check_trajectory(cfg, state, 5)
+
+
+@pytest.mark.parametrize("recon,riemann", [(0, 0), (1, 1)])
+def test_minkowski_periodic_multiblock(recon, riemann):
+    cfg = dict(mink_cfg((12, 12, 12), recon=recon, riemann=riemann, ng=3), block=(4, 6, 12))
+    state = random_periodic_state(cfg["n"], seed=21)
+    check_trajectory(cfg, state, 4)
+
+
+def test_full_size_uniform_grid_single_step():
+    """the 256x128x128 grid in 128 blocks of 32^3 as benchmarked: one step, every cell"""
+    cfg = dict(configs.TORUS_UNIFORM)
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    check_trajectory(cfg, state, 1)
+
+
+def test_repeat_runs_bit_identical():
+    cfg = configs.scaled(configs.TORUS_UNIFORM, (64, 32, 32), block=(32, 16, 16))
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    say("[determinism] two runs of 4 steps")
+    outs = []
+    for _ in range(2):
+        g = grmhd.Grid(cfg, state=state)
+        g.step(4)
+        outs.append(g.get_state())
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_cons2prim_batch_round_trip():
+    import math
+    import torch
+
+    rng = np.random.default_rng(3)
+    gam = 4.0 / 3.0
+    n = 4096
+    KS = configs.scaled(configs.TORUS_TINY, (8, 8, 8))
+    U = np.zeros((9, n))
+    geom = np.zeros((15, n))
+    P0 = np.zeros((5, n))
+    want_tier = np.zeros(n, int)
+    for i in range(n):
+        x1 = rng.uniform(math.log(1.3), math.log(50.0))
+        x2 = rng.uniform(0.05, math.pi - 0.05)
+        gcov, gcon, gdet, alpha, _ = oracle.geom_point(KS, x1, x2)
+        rho = math.exp(rng.normal(0, 2))
+        u = rho * 10 ** rng.uniform(-2, 0.5)
+        ut = rng.normal(0, 1, 3) / np.sqrt(np.diag(gcov)[1:])
+        P = np.array([rho, u, *ut])
+        B = rng.normal(0, 1, 3) / np.sqrt(np.diag(gcov)[1:]) * math.sqrt(u)
+        U[:, i] = oracle.prim_to_flux(P, B, gcov, gcon, gdet, alpha, gam, 0)
+        geom[:, i] = [gcov[0, 0], gcov[0, 1], gcov[0, 3], gcov[1, 1], gcov[1, 3], gcov[2, 2],
+                      gcov[3, 3], gcon[0, 0], gcon[0, 1], gcon[1, 1], gcon[1, 3], gcon[2, 2],
+                      gcon[3, 3], gdet, alpha]
+        P0[:, i] = P
+        Po, want_tier[i], _ = oracle.cons2prim(U[:, i], gcov, gcon, gdet, alpha, gam, P * 1.02)
+    dev = torch.device("cuda")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    say("[c2p batch] n=4096")
+    Pg, iters, tier = grmhd.cons2prim_batch(t(U), t(geom), t(P0 * 1.02), t(P0 * 1.02), gam)
+    Pg = Pg.cpu().numpy()
+    tier = tier.cpu().numpy()
+    ok = tier == 0
+    assert ok.mean() > 0.99
+    assert np.array_equal(tier, want_tier)
+    rel = np.abs(Pg[0, ok] / P0[0, ok] - 1)
+    assert rel.max() < 1e-10
