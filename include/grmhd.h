@@ -176,6 +176,61 @@ int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, s
 int grmhd_geometry_point(int32_t coords, double spin_a, double x1, double x2, double* out,
                          double* conn);
 
+/* ------------------------------------------------------------------------------
+ * Learned first guess of the inversion (Sec. 2.6 solves the inversion iteratively;
+ * its starting point is free).  An MLP 8 -> 64 -> 64 -> 64 -> 2 (tanh) maps normalised
+ * features of a conserved state -- log D, asinh(tau/D), log1p(S^2/D^2), log1p(B^2/D),
+ * log1p((S.B)^2/D^3), lapse, adiabatic index, sqrt(det gamma_ij) -- to normalised
+ * log Gamma and log(W/D), W = (rho + u + p) Gamma^2.  Weights are FP32 masters
+ * (n_params floats: W1[8][64] b1[64] W2[64][64] b2 W3[64][64] b3 W4[64][2] b4[2]);
+ * products run on bfloat16 matrix cores with FP32 accumulation.  All pointers are
+ * device memory and every call is ordered on hip_stream.
+ * ------------------------------------------------------------------------------ */
+
+/* Parameter count, bytes of the packed inference blob (desc.mlp_weights), and floats
+ * of training scratch for a batch size. */
+int grmhd_mlp_sizes(int32_t batch, size_t* n_params, size_t* blob_bytes, size_t* work_floats);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, step >= 1) on the mean squared error
+ * of rows idx[batch] of X[n][8] (normalised features) against Y[n][2] (normalised
+ * targets).  params, adam_m, adam_v: n_params floats each, updated in place; loss
+ * (device float) receives the batch loss before the update. */
+int grmhd_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step,
+                         const float* X, const float* Y, const int32_t* idx, int32_t batch,
+                         float lr, float* work, float* loss, void* hip_stream);
+
+/* Gradients of the same loss without updating (grad_out: n_params floats). */
+int grmhd_mlp_gradients(const float* params, const float* X, const float* Y,
+                        const int32_t* idx, int32_t batch, float* work, float* grad_out,
+                        float* loss, void* hip_stream);
+
+/* Packs master parameters and norm[20] (feature means[8], stds[8], target means[2],
+ * stds[2]) into the inference blob (16-byte aligned, blob_bytes). */
+int grmhd_mlp_pack(const float* params, const float* norm, void* blob, void* hip_stream);
+
+/* Normalised outputs Y[n][2] of normalised features X[n][8] through a packed blob. */
+int grmhd_mlp_forward(const void* blob, const float* X, int64_t n, float* Y, void* hip_stream);
+
+/* U[9][n] from primitives P[5][n], cell-centred field B[3][n] (coordinate B^i) and
+ * geom[15][n] (layout of grmhd_c2p_batch), Sec. 2.3-2.5. */
+int grmhd_prim2cons_batch(int64_t n, const double* P, const double* B, const double* geom,
+                          double gamma_ad, double* U, void* hip_stream);
+
+/* Raw features X[n][8] of U[9][n] and, if P is non-NULL, raw targets Y[n][2] of P;
+ * ok[n] = 1 where every value is finite. */
+int grmhd_mlp_dataset(int64_t n, const double* U, const double* P, const double* geom,
+                      double gamma_ad, float* X, float* Y, int32_t* ok, void* hip_stream);
+
+/* Column-wise normalisation of A[n][cols] in place: with compute = 1 the means and
+ * standard deviations are computed first into mean/sd, else the given ones are used. */
+int grmhd_mlp_normalize(float* A, int64_t n, int32_t cols, float* mean, float* sd,
+                        int32_t compute, void* hip_stream);
+
+/* Every interior cell of the grid as flat batches (block order, then k, j, i):
+ * P[5][n] primitives, B[3][n] cell-centred coordinate field, geom[15][n] metric as in
+ * grmhd_c2p_batch; n = number of interior cells. */
+int grmhd_extract_cells(grmhd_ctx* ctx, double* P, double* B, double* geom);
+
 int grmhd_destroy(grmhd_ctx* ctx);
 const char* grmhd_last_error(void);
 

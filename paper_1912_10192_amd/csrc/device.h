@@ -69,9 +69,8 @@ __device__ __forceinline__ void fluid_state(const double P[5], const double B[3]
   const double u1 = P[2], u2 = P[3], u3 = P[4];
   const double qsq = m.g11 * u1 * u1 + 2.0 * m.g13 * u1 * u3 + m.g22 * u2 * u2 + m.g33 * u3 * u3;
   const double gamma = sqrt(1.0 + qsq);
-  const double beta1 = m.alpha * m.alpha * m.h01;
   f.ucon[0] = gamma / m.alpha;
-  f.ucon[1] = u1 - gamma * beta1 / m.alpha;
+  f.ucon[1] = u1 - gamma * (m.alpha * m.h01);   // beta^1/alpha = alpha g^{t1}
   f.ucon[2] = u2;
   f.ucon[3] = u3;
   lower4(m, f.ucon, f.ucov);
@@ -86,15 +85,21 @@ __device__ __forceinline__ void fluid_state(const double P[5], const double B[3]
           f.bcon[3] * f.bcov[3];
 }
 
+// entropy tracer kappa = p / rho^gamma of a state (one power per state)
+__device__ __forceinline__ double entropy_kappa(const double P[5], double gam) {
+  return (gam - 1.0) * P[1] / pow(P[0], gam);
+}
+
 // Conserved vector (D = 0) or flux along x^D (D = 1..3), times sqrt(-g):
 //   rho u^D, T^D_t + rho u^D, T^D_i, b^i u^D - b^D u^i, kappa rho u^D
 // with T^m_n = (rho + u + p + b^2) u^m u_n + delta^m_n (p + b^2/2) - b^m b_n.
 // The induction component along D itself (identically zero for D >= 1) is skipped:
 // out[5..6] hold the two other field components in increasing order and out[7] the
 // entropy; for D = 0 out[5..7] are the three field components and out[8] the entropy.
+
 template <int D>
 __device__ __forceinline__ void flux_vector(const double P[5], const Fluid& f, const Metric& m,
-                                            double gam, double* out) {
+                                            double gam, double kappa, double* out) {
   const double rho = P[0], u = P[1];
   const double p = (gam - 1.0) * u;
   const double w = rho + u + p;
@@ -108,7 +113,6 @@ __device__ __forceinline__ void flux_vector(const double P[5], const Fluid& f, c
   out[2] = g * (wb * ud * f.ucov[1] + (D == 1 ? pb : 0.0) - bd * f.bcov[1]);
   out[3] = g * (wb * ud * f.ucov[2] + (D == 2 ? pb : 0.0) - bd * f.bcov[2]);
   out[4] = g * (wb * ud * f.ucov[3] + (D == 3 ? pb : 0.0) - bd * f.bcov[3]);
-  const double kappa = p / pow(rho, gam);
   if (D == 0) {
     out[5] = g * (f.bcon[1] * ud - bd * f.ucon[1]);
     out[6] = g * (f.bcon[2] * ud - bd * f.ucon[2]);
@@ -142,7 +146,8 @@ __device__ __forceinline__ void wave_speeds(const double P[5], const Fluid& f, c
   double disc = B * B - 4.0 * A * C;
   disc = disc < 0.0 ? 0.0 : disc;
   const double sq = sqrt(disc);
-  const double vp = (B + sq) / (2.0 * A), vm = (B - sq) / (2.0 * A);
+  const double i2a = 0.5 / A;
+  const double vp = (B + sq) * i2a, vm = (B - sq) * i2a;
   vmax = vp > vm ? vp : vm;
   vmin = vp > vm ? vm : vp;
 }
@@ -292,17 +297,13 @@ __device__ __forceinline__ bool c2p_from_Wv(const C2PIn& s, double W, double vsq
   return c2p_prims(s, W, vsq, rho, u, gamma, P);
 }
 
-// 2D Newton in (W, v^2) (Noble et al. 2006) from a primitive guess.  Converged when
+// 2D Newton in (W, v^2) (Noble et al. 2006) from a guess (W0, v0).  Converged when
 // |dW| <= tol W and |dv^2| <= tol; one more iteration then polishes the root.
-__device__ __forceinline__ bool c2p_newton(const C2PIn& s, const Metric& m, const double G[5],
-                                           double tol, int maxit, double P[5], int& iters) {
-  const double qsq = m.g11 * G[2] * G[2] + 2.0 * m.g13 * G[2] * G[4] + m.g22 * G[3] * G[3] +
-                     m.g33 * G[4] * G[4];
-  const double gsq = 1.0 + qsq;
-  double W = (G[0] + s.gam * G[1]) * gsq;
-  double vsq = qsq / gsq;
+__device__ __forceinline__ bool c2p_newton_wv(const C2PIn& s, double W0, double v0, double tol,
+                                              int maxit, double P[5], int& iters) {
+  double W = W0, vsq = v0;
   iters = 0;
-  if (!(W > 0.0)) return false;
+  if (!(W > 0.0) || !(vsq >= 0.0) || !(vsq < 1.0)) return false;
   const double gm = (s.gam - 1.0) / s.gam;
   bool conv = false;
   int it;
@@ -318,9 +319,9 @@ __device__ __forceinline__ bool c2p_newton(const C2PIn& s, const Metric& m, cons
     const double J12 = BW * BW;
     const double J21 = -s.QdotBsq * iW3 - 1.0 + gm * (1.0 - vsq);
     const double J22 = -0.5 * s.Bsq + gm * (-W + s.D / (2.0 * sq));
-    const double det = J11 * J22 - J12 * J21;
-    const double dW = -(R1 * J22 - J12 * R2) / det;
-    const double dv = -(J11 * R2 - J21 * R1) / det;
+    const double idet = 1.0 / (J11 * J22 - J12 * J21);
+    const double dW = -(R1 * J22 - J12 * R2) * idet;
+    const double dv = -(J11 * R2 - J21 * R1) * idet;
     double Wn = W + dW, vn = vsq + dv;
     if (!(Wn > 0.0)) Wn = 0.5 * W;
     if (vn < 0.0) vn = 0.0;
@@ -336,9 +337,19 @@ __device__ __forceinline__ bool c2p_newton(const C2PIn& s, const Metric& m, cons
   return c2p_from_Wv(s, W, vsq, P);
 }
 
+// the plain guess: W and v^2 of a primitive state under this metric
+__device__ __forceinline__ void guess_from_prims(const C2PIn& s, const Metric& m, const double G[5],
+                                                 double& W, double& vsq) {
+  const double qsq = m.g11 * G[2] * G[2] + 2.0 * m.g13 * G[2] * G[4] + m.g22 * G[3] * G[3] +
+                     m.g33 * G[4] * G[4];
+  const double gsq = 1.0 + qsq;
+  W = (G[0] + s.gam * G[1]) * gsq;
+  vsq = qsq / gsq;
+}
+
 // one-variable energy equation in W (v^2 eliminated through the momentum equation),
 // bracketed and bisected to the last bit
-__device__ __noinline__ bool c2p_energy_1d(const C2PIn& s, double P[5]) {
+__device__ __forceinline__ bool c2p_energy_1d(const C2PIn& s, double P[5]) {
   double Wb = fabs(s.Qdotn) + s.D + s.Bsq;
   if (!(Wb > 0.0)) return false;
   int k;
@@ -378,7 +389,7 @@ __device__ __forceinline__ double entropy_W(const C2PIn& s, double vsq) {
   return (rho + s.gam / (s.gam - 1.0) * p) / (1.0 - vsq);
 }
 
-__device__ __noinline__ bool c2p_entropy(const C2PIn& s, double P[5]) {
+__device__ __forceinline__ bool c2p_entropy(const C2PIn& s, double P[5]) {
   if (!(s.kappa > 0.0) || !(s.D > 0.0)) return false;
   double lo = 0.0, hi = 1.0 - 0x1p-53;
   for (int k = 0; k < 300; k++) {
@@ -399,20 +410,54 @@ __device__ __noinline__ bool c2p_entropy(const C2PIn& s, double P[5]) {
   return c2p_prims(s, W, vsq, rho, u, gamma, P);
 }
 
-// full inversion with the fallback chain; returns the tier used (0..4)
+// Inversion with the fallback chain; returns the tier used (0..4).  Tier 0 starts from
+// (W0, v0) when `first` is set (the learned guess), else from the plain guess prev;
+// tier 1 retries from prev; tiers 2 and 3 are the bracketed energy and entropy solves;
+// tier 4 keeps prev.
+__device__ __forceinline__ int c2p_solve(const C2PIn& s, const Metric& m, bool first, double W0,
+                                         double v0, const double prev[5], double tol, int maxit,
+                                         double P[5], int& iters) {
+  double Wp, vp;
+  guess_from_prims(s, m, prev, Wp, vp);
+  if (first) {
+    if (c2p_newton_wv(s, W0, v0, tol, maxit, P, iters)) return 0;
+    if (c2p_newton_wv(s, Wp, vp, tol, maxit, P, iters)) return 1;
+  } else {
+    if (c2p_newton_wv(s, Wp, vp, tol, maxit, P, iters)) return 0;
+  }
+  iters = 63;
+  if (c2p_energy_1d(s, P)) return 2;
+  if (c2p_entropy(s, P)) return 3;
+  for (int v = 0; v < 5; v++) P[v] = prev[v];
+  return 4;
+}
+
+// inversion from primitive guesses: guess (tier 0) and prev (tier 1, fallback)
 __device__ __forceinline__ int cons2prim(const double U[9], const Metric& m, double gam,
                                          const double guess[5], const double prev[5],
                                          bool distinct_guess, double tol, int maxit,
                                          double P[5], int& iters) {
   C2PIn s;
   c2p_setup(U, m, gam, s);
-  if (c2p_newton(s, m, guess, tol, maxit, P, iters)) return 0;
-  if (distinct_guess && c2p_newton(s, m, prev, tol, maxit, P, iters)) return 1;
-  iters = 63;
-  if (c2p_energy_1d(s, P)) return 2;
-  if (c2p_entropy(s, P)) return 3;
-  for (int v = 0; v < 5; v++) P[v] = prev[v];
-  return 4;
+  if (!distinct_guess) return c2p_solve(s, m, false, 0.0, 0.0, prev, tol, maxit, P, iters);
+  double W0, v0;
+  guess_from_prims(s, m, guess, W0, v0);
+  return c2p_solve(s, m, true, W0, v0, prev, tol, maxit, P, iters);
+}
+
+// raw MLP features of an inversion input (see mlp.h); false if any is not finite
+__device__ __forceinline__ bool mlp_features(const C2PIn& s, const Metric& m, float x[8]) {
+  const double D = s.D;
+  const double tau = -s.Qdotn - D;
+  const double f[8] = {log(D), asinh(tau / D), log1p(s.Qtsq / (D * D)), log1p(s.Bsq / D),
+                       log1p(s.QdotBsq / (D * D * D)), m.alpha, s.gam, m.gdet / m.alpha};
+  bool ok = D > 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; k++) {
+    x[k] = (float)f[k];
+    ok = ok && isfinite(f[k]);
+  }
+  return ok;
 }
 
 // floors (Sec. 2.7): Lorentz-factor ceiling, then rho >= max(rho_fl, b^2/bsq_rho_max)

@@ -28,6 +28,8 @@ static int fail(int code, const std::string& msg) {
   return code;
 }
 
+int grmhd::set_error(int code, const char* msg) { return fail(code, msg); }
+
 #define HIPCHK(x)                                                                  \
   do {                                                                             \
     hipError_t e_ = (x);                                                           \
@@ -141,7 +143,7 @@ struct Plan {
   std::vector<int32_t> owner;   // block id per effective cell
   std::vector<GhostOp> ops[4];  // cells, x1 faces, x2 faces, x3 faces
   // work-buffer offsets (bytes)
-  size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, total;
+  size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, o_dtp, total;
 };
 
 int validate(const grmhd_grid_desc* d) {
@@ -170,7 +172,10 @@ int validate(const grmhd_grid_desc* d) {
   if (d->c2p_maxit < 1 || d->c2p_maxit > 62) return fail(GRMHD_EINVAL, "c2p_maxit must be 1..62");
   if (!(d->c2p_tol > 0.0)) return fail(GRMHD_EINVAL, "c2p_tol must be positive");
   if (!(d->courant > 0.0)) return fail(GRMHD_EINVAL, "courant must be positive");
-  if (d->c2p_guess != GRMHD_GUESS_PLAIN) return fail(GRMHD_EUNSUPPORTED, "only the plain guess");
+  if (d->c2p_guess != GRMHD_GUESS_PLAIN && d->c2p_guess != GRMHD_GUESS_MLP)
+    return fail(GRMHD_EINVAL, "unknown c2p_guess");
+  if (d->c2p_guess == GRMHD_GUESS_MLP && !d->mlp_weights)
+    return fail(GRMHD_EINVAL, "learned guess needs mlp_weights");
   for (int b = 0; b < d->n_blocks; b++) {
     const grmhd_block_desc& bd = d->blocks[b];
     for (int k = 0; k < 3; k++) {
@@ -354,6 +359,10 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
     p.o_ops[kind] = take(count * sizeof(GhostOp));
   }
   p.o_cnt = take(sizeof(Counters));
+  {
+    const int64_t r = (int64_t)p.max_n[0] * p.max_n[1] * p.max_n[2];
+    p.o_dtp = take((size_t)((r + 255) / 256) * nb * 8);
+  }
   p.total = o;
   return GRMHD_OK;
 }
@@ -413,10 +422,11 @@ struct grmhd_ctx {
   Launch L;
   grmhd_buffers bufs;
   hipStream_t stream;
-  double *ps, *balt, *bc, *f, *e;
+  double *ps, *balt, *bc, *f, *e, *dtp;
   GhostOp* ops[4];
   int64_t nops[4];
   bool b_in_alt = false;
+  const void* mlp = nullptr;   // packed MLP blob when the learned guess is on
   hipEvent_t ev0, ev1;
 };
 
@@ -469,6 +479,7 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   c->bc = (double*)(w + p.o_bc);
   c->f = (double*)(w + p.o_f);
   c->e = (double*)(w + p.o_e);
+  c->dtp = (double*)(w + p.o_dtp);
   std::vector<double> gc, g1, g2;
   build_geometry(p, gc, g1, g2);
   auto up = [&](size_t off, const void* src, size_t bytes) -> int {
@@ -515,6 +526,7 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   L.cnt = (Counters*)(w + p.o_cnt);
   L.stream = c->stream;
   c->profile = desc->profile != 0;
+  c->mlp = desc->c2p_guess == GRMHD_GUESS_MLP ? desc->mlp_weights : nullptr;
   launch_counters_reset(L, true);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->stream));   // host staging vectors go out of scope
@@ -552,7 +564,7 @@ static void fill_ghosts(grmhd_ctx* c, double* P, double* B) {
 }
 
 static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double* Ps,
-                  const double* Bs, double factor, double* Pout, double* Bout) {
+                  const double* Bs, double factor, double* Pout, double* Bout, double* dt_part) {
   const Launch& L = c->L;
   const int recon = c->plan.d.recon, riem = c->plan.d.riemann;
   prof_begin(c, KC_BCELL);
@@ -567,7 +579,7 @@ static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double
   launch_emf(L, c->f, c->e);
   prof_end(c);
   prof_begin(c, KC_UPDATE);
-  launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout);
+  launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, dt_part, c->mlp);
   prof_end(c);
 }
 
@@ -582,13 +594,17 @@ int grmhd_step(grmhd_ctx* c, int32_t n_cycles, grmhd_step_stats* stats) {
     double* Bcur = c->b_in_alt ? c->balt : c->bufs.bface;
     double* Both = c->b_in_alt ? c->bufs.bface : c->balt;
     fill_ghosts(c, P, Bcur);
-    prof_begin(c, KC_DT);
-    launch_dt(L, P, Bcur);
-    prof_end(c);
-    stage(c, P, Bcur, P, Bcur, 0.5, c->ps, Both);        // predictor to t + dt/2
+    if (s == 0) {   // the Courant step of later steps comes out of the previous corrector
+      prof_begin(c, KC_DT);
+      launch_dt(L, P, Bcur, c->dtp);
+      launch_dt_final(L, c->dtp);
+      prof_end(c);
+    }
+    stage(c, P, Bcur, P, Bcur, 0.5, c->ps, Both, nullptr);   // predictor to t + dt/2
     fill_ghosts(c, c->ps, Both);
-    stage(c, P, Bcur, c->ps, Both, 1.0, P, Both);         // corrector to t + dt
+    stage(c, P, Bcur, c->ps, Both, 1.0, P, Both, c->dtp);    // corrector to t + dt
     launch_tsim(L);
+    launch_dt_final(L, c->dtp);
     c->b_in_alt = !c->b_in_alt;
   }
   if (c->b_in_alt) {
@@ -682,6 +698,18 @@ int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, s
   if (*bytes < need) return fail(GRMHD_EINVAL, "buffer too small");
   std::memcpy(host_buf, v.data(), need);
   *bytes = need;
+  return GRMHD_OK;
+}
+
+int grmhd_extract_cells(grmhd_ctx* c, double* P, double* B, double* geom) {
+  if (!c || !P || !B || !geom) return fail(GRMHD_EINVAL, "NULL argument");
+  const auto& bl = c->plan.blocks;
+  for (const auto& b : bl)
+    for (int k = 0; k < 3; k++)
+      if (b.n[k] != bl[0].n[k]) return fail(GRMHD_EUNSUPPORTED, "extract needs equal block sizes");
+  if (c->b_in_alt) return fail(GRMHD_ESTATE, "state not in the caller's buffers");
+  launch_extract(c->L, c->bufs.prim, c->bufs.bface, c->plan.n_interior, P, B, geom);
+  HIPCHK(hipGetLastError());
   return GRMHD_OK;
 }
 

@@ -61,6 +61,9 @@ struct Launch {
   hipStream_t stream;
 };
 
+// records the message returned by grmhd_last_error() and returns code (host.cpp)
+int set_error(int code, const char* msg);
+
 // kernel launchers (kernels.hip)
 void launch_ghost_cells(const Launch& L, const GhostOp* ops, int64_t nops, double* P);
 void launch_ghost_faces(const Launch& L, const GhostOp* ops, int64_t nops, double* B, int comp);
@@ -68,14 +71,21 @@ void launch_bcell(const Launch& L, const double* B, double* Bc);
 void launch_flux(const Launch& L, int dir, int recon, int riemann, const double* P,
                  const double* Bc, const double* B, double* F);
 void launch_emf(const Launch& L, const double* F, double* E);
+// update of one stage; with dt_part non-null the kernel also writes per-workgroup minima
+// of the next Courant step (reduced by launch_dt_final)
+// (mlp non-null: learned first guess of the inversion from the packed MLP blob)
 void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
                    const double* Bcs, const double* F, const double* E, double dt_factor,
-                   double* Pout, double* Bout);
-void launch_dt(const Launch& L, const double* P, const double* B);
+                   double* Pout, double* Bout, double* dt_part, const void* mlp);
+int64_t dt_partials(const Launch& L);
+void launch_dt(const Launch& L, const double* P, const double* B, double* dt_part);
+void launch_dt_final(const Launch& L, const double* dt_part);
 void launch_counters_reset(const Launch& L, bool all);
 void launch_tsim(const Launch& L);
 void launch_copy(const Launch& L, const double* src, double* dst, int64_t n);
 void launch_divb(const Launch& L, const double* B, double* field);
+void launch_extract(const Launch& L, const double* Pin, const double* Bin, int64_t n, double* P,
+                    double* B, double* geom);
 void launch_c2p_batch(int64_t n, const double* U, const double* geom, const double* guess,
                       const double* prev, double* P, int32_t* iters, int32_t* tier, double gam,
                       double tol, int32_t maxit, hipStream_t stream);

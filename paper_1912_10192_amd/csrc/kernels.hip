@@ -11,10 +11,29 @@
 
 #include "device.h"
 #include "internal.h"
+#include "mlp.h"
 
 namespace grmhd {
 
 constexpr int NT = 256;   // threads per workgroup (four wavefronts)
+
+// optional occupancy targets (waves per SIMD) for the two heavy kernels
+#ifndef GRMHD_FLUX_WAVES
+#define GRMHD_FLUX_WAVES 4
+#endif
+#ifndef GRMHD_UPDATE_WAVES
+#define GRMHD_UPDATE_WAVES 0
+#endif
+#if GRMHD_FLUX_WAVES > 0
+#define FLUX_OCC __attribute__((amdgpu_waves_per_eu(GRMHD_FLUX_WAVES)))
+#else
+#define FLUX_OCC
+#endif
+#if GRMHD_UPDATE_WAVES > 0
+#define UPDATE_OCC __attribute__((amdgpu_waves_per_eu(GRMHD_UPDATE_WAVES)))
+#else
+#define UPDATE_OCC
+#endif
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -42,6 +61,24 @@ __device__ __forceinline__ double wave_max(double v) {
 __device__ __forceinline__ long long wave_sum(long long v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Remap the
+// dispatch order so that every XCD works on a contiguous range of (block, tile) indices:
+// neighbouring tiles of a block then share one L2 for their stencil halos.
+struct Tile {
+  int x, y;
+};
+__device__ __forceinline__ Tile xcd_tile() {
+  const int T = gridDim.x * gridDim.y;
+  const int i = blockIdx.y * gridDim.x + blockIdx.x;
+  const int x = i & 7, q = i >> 3;
+  const int full = T >> 3, rem = T & 7;
+  const int n = x < rem ? x * (full + 1) + q : rem * (full + 1) + (x - rem) * full + q;
+  Tile t;
+  t.x = n % gridDim.x;
+  t.y = n / gridDim.x;
+  return t;
 }
 
 // decode a thread index of a box region (r0, r1, r2) starting at s into local coords
@@ -109,9 +146,10 @@ __global__ __launch_bounds__(NT) void k_ghost_faces(const BlockInfo* __restrict_
 // cell that has both faces in the padded block
 __global__ __launch_bounds__(NT) void k_bcell(Launch L, const double* __restrict__ B,
                                               double* __restrict__ Bc) {
-  const BlockInfo bi = L.blk[blockIdx.y];
+  const Tile tl = xcd_tile();
+  const BlockInfo bi = L.blk[tl.y];
   Cell c;
-  if (!region_cell(bi, blockIdx.x * NT + threadIdx.x, bi.np[0], bi.np[1], bi.np[2], 0, 0, 0, c))
+  if (!region_cell(bi, tl.x * NT + threadIdx.x, bi.np[0], bi.np[1], bi.np[2], 0, 0, 0, c))
     return;
   const int64_t V = bi.vol;
   const double* b = B + 3 * bi.off;
@@ -128,17 +166,18 @@ __global__ __launch_bounds__(NT) void k_bcell(Launch L, const double* __restrict
 // One thread per face along x^DIR.  Normal range [ng, ng + n], transverse range widened
 // by one ghost layer so the edge EMFs of every interior face have their four fluxes.
 template <int DIR, int RECON, int RIEMANN>
-__global__ __launch_bounds__(NT) void k_flux(Launch L, const double* __restrict__ P,
+__global__ __launch_bounds__(NT) FLUX_OCC void k_flux(Launch L, const double* __restrict__ P,
                                              const double* __restrict__ Bc,
                                              const double* __restrict__ B,
                                              double* __restrict__ F) {
-  const BlockInfo bi = L.blk[blockIdx.y];
+  const Tile tl = xcd_tile();
+  const BlockInfo bi = L.blk[tl.y];
   const int g = L.ph.ng;
   const int r0 = DIR == 1 ? bi.n[0] + 1 : bi.n[0] + 2;
   const int r1 = DIR == 2 ? bi.n[1] + 1 : bi.n[1] + 2;
   const int r2 = DIR == 3 ? bi.n[2] + 1 : bi.n[2] + 2;
   Cell c;
-  if (!region_cell(bi, blockIdx.x * NT + threadIdx.x, r0, r1, r2, DIR == 1 ? g : g - 1,
+  if (!region_cell(bi, tl.x * NT + threadIdx.x, r0, r1, r2, DIR == 1 ? g : g - 1,
                    DIR == 2 ? g : g - 1, DIR == 3 ? g : g - 1, c))
     return;
   const int64_t V = bi.vol;
@@ -184,15 +223,17 @@ __global__ __launch_bounds__(NT) void k_flux(Launch L, const double* __restrict_
   {
     Fluid f;
     fluid_state(PL, BL, m, f);
-    flux_vector<0>(PL, f, m, gam, UL);
-    flux_vector<DIR>(PL, f, m, gam, FL);
+    const double kap = entropy_kappa(PL, gam);
+    flux_vector<0>(PL, f, m, gam, kap, UL);
+    flux_vector<DIR>(PL, f, m, gam, kap, FL);
     wave_speeds<DIR>(PL, f, m, gam, vmaxL, vminL);
   }
   {
     Fluid f;
     fluid_state(PR, BR, m, f);
-    flux_vector<0>(PR, f, m, gam, UR);
-    flux_vector<DIR>(PR, f, m, gam, FR);
+    const double kap = entropy_kappa(PR, gam);
+    flux_vector<0>(PR, f, m, gam, kap, UR);
+    flux_vector<DIR>(PR, f, m, gam, kap, FR);
     wave_speeds<DIR>(PR, f, m, gam, vmaxR, vminR);
   }
   // conserved components in flux order: mass, energy, momenta, transverse field, entropy
@@ -222,10 +263,11 @@ __global__ __launch_bounds__(NT) void k_flux(Launch L, const double* __restrict_
 // average of the four face fluxes of B around the edge (Sec. 2.5); zero on the axis.
 __global__ __launch_bounds__(NT) void k_emf(Launch L, const double* __restrict__ F,
                                             double* __restrict__ E) {
-  const BlockInfo bi = L.blk[blockIdx.y];
+  const Tile tl = xcd_tile();
+  const BlockInfo bi = L.blk[tl.y];
   const int g = L.ph.ng;
   Cell c;
-  if (!region_cell(bi, blockIdx.x * NT + threadIdx.x, bi.n[0] + 1, bi.n[1] + 1, bi.n[2] + 1, g, g,
+  if (!region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0] + 1, bi.n[1] + 1, bi.n[2] + 1, g, g,
                    g, c))
     return;
   const int64_t V = bi.vol;
@@ -248,36 +290,96 @@ __global__ __launch_bounds__(NT) void k_emf(Launch L, const double* __restrict__
 
 // ------------------------------------------------------------------ cell update
 
-template <bool STATS>
-__global__ __launch_bounds__(NT) void k_update(Launch L, const double* __restrict__ Pn,
+// minimum over the workgroup: wave minimum, then across the four waves through LDS;
+// thread 0 returns the result
+__device__ __forceinline__ double block_min(double v) {
+  __shared__ double part[NT / 64];
+  v = wave_min(v);
+  if (lane_id() == 0) part[threadIdx.x / 64] = v;
+  __syncthreads();
+  double r = part[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; w++) r = fmin(r, part[w]);
+  return r;
+}
+
+// per cell 1/dt = sum_d max(|v+|, |v-|)/dx_d from the cell-centred state (Sec. 2.1)
+__device__ __forceinline__ double cell_dt(const double P[5], const double B[3], const Metric& m,
+                                          const Phys& ph) {
+  Fluid f;
+  fluid_state(P, B, m, f);
+  double vp, vm, inv = 0.0;
+  wave_speeds<1>(P, f, m, ph.gam, vp, vm);
+  inv += fmax(fabs(vp), fabs(vm)) / ph.dx[0];
+  wave_speeds<2>(P, f, m, ph.gam, vp, vm);
+  inv += fmax(fabs(vp), fabs(vm)) / ph.dx[1];
+  wave_speeds<3>(P, f, m, ph.gam, vp, vm);
+  inv += fmax(fabs(vp), fabs(vm)) / ph.dx[2];
+  return 1.0 / inv;
+}
+
+// Learned first guess for the cells of one workgroup: every thread passes the inversion
+// input of its cell (or valid = false), every wavefront runs its 64 cells through the
+// MLP with matrix cores, and each thread gets back (W0, v0) and whether to use it.
+__device__ __forceinline__ bool mlp_guess_block(const MlpBlob* __restrict__ blob, const C2PIn& s,
+                                                const Metric& m, bool valid, double& W0,
+                                                double& v0) {
+  __shared__ float feat[NT * 8];
+  __shared__ float outv[NT * 2];
+  const int t = threadIdx.x, w = t / 64;
+  float x[8];
+  bool ok = valid && mlp_features(s, m, x);
+#pragma unroll
+  for (int k = 0; k < 8; k++) feat[t * 8 + k] = ok ? (x[k] - blob->xmean[k]) / blob->xstd[k] : 0.0f;
+  __syncthreads();
+  mlp_wave(blob, feat + w * 64 * 8, outv + w * 64 * 2);
+  __syncthreads();
+  if (!ok) return false;
+  const double lg = (double)(outv[t * 2] * blob->ystd[0] + blob->ymean[0]);
+  const double lw = (double)(outv[t * 2 + 1] * blob->ystd[1] + blob->ymean[1]);
+  const double G = exp(lg > 0.0 ? lg : 0.0);
+  W0 = s.D * exp(lw);
+  v0 = 1.0 - 1.0 / (G * G);
+  return isfinite(W0) && W0 > 0.0 && v0 >= 0.0 && v0 < 1.0;
+}
+
+template <bool STATS, bool NEXT_DT, bool MLP>
+__global__ __launch_bounds__(NT) UPDATE_OCC void k_update(Launch L, const double* __restrict__ Pn,
                                                const double* __restrict__ Bn,
                                                const double* __restrict__ Ps,
                                                const double* __restrict__ Bcs,
                                                const double* __restrict__ F,
                                                const double* __restrict__ E, double dt_factor,
                                                double* __restrict__ Pout,
-                                               double* __restrict__ Bout) {
-  const BlockInfo bi = L.blk[blockIdx.y];
+                                               double* __restrict__ Bout,
+                                               double* __restrict__ dt_part,
+                                               const MlpBlob* __restrict__ mlp) {
+  const Tile tl = xcd_tile();
+  const BlockInfo bi = L.blk[tl.y];
   const int g = L.ph.ng;
   Cell c;
-  const bool valid = region_cell(bi, blockIdx.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
+  const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
                                  g, g, c);
   int tier = 0, iters = 0, hits = 0;
+  double dtc = __longlong_as_double(0x7FF0000000000000LL);
+  const int64_t V = bi.vol;
+  const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
+  const int64_t l = c.loc;
+  const GeoTab& G = L.geo;
+  const int64_t col = valid ? geo_col(G, bi, c.J, c.I) : 0;
+  Metric m;
+  C2PIn cs;
+  double PS[5];
   if (valid) {
     const double dt = L.ph.courant * __longlong_as_double((long long)L.cnt->dt_bits);
     const double dts = dt_factor * dt;
-    const int64_t V = bi.vol;
-    const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
     const double dx1 = L.ph.dx[0], dx2 = L.ph.dx[1], dx3 = L.ph.dx[2];
-    const int64_t l = c.loc;
     const double* e1 = E + 3 * bi.off;
     const double* e2 = e1 + V;
     const double* e3 = e2 + V;
     const double* b1 = Bn + 3 * bi.off;
     const double* b2 = b1 + V;
     const double* b3 = b2 + V;
-    const GeoTab& G = L.geo;
-    const int64_t col = geo_col(G, bi, c.J, c.I);
     const bool pole_lo = G.f2[GDET * G.ncol + col] == 0.0;
     const bool pole_hi = G.f2[GDET * G.ncol + col + G.ti] == 0.0;
     // constrained transport of the six faces of this cell (Sec. 2.5)
@@ -301,7 +403,7 @@ __global__ __launch_bounds__(NT) void k_update(Launch L, const double* __restric
     if (c.J == g + bi.n[1] - 1) o2[l + s2] = nb2hi;
     if (c.K == g + bi.n[2] - 1) o3[l + s3] = nb3hi;
 
-    const Metric m = load_metric(G.c, G.ncol, col);
+    m = load_metric(G.c, G.ncol, col);
     // U^n recomputed from P^n (Sec. 2.5)
     double U[9];
     {
@@ -313,9 +415,8 @@ __global__ __launch_bounds__(NT) void k_update(Launch L, const double* __restric
       B0[2] = 0.5 * (b3[l] + b3[l + s3]) / m.gdet;
       Fluid f;
       fluid_state(P0, B0, m, f);
-      flux_vector<0>(P0, f, m, L.ph.gam, U);
+      flux_vector<0>(P0, f, m, L.ph.gam, entropy_kappa(P0, L.ph.gam), U);
     }
-    double PS[5];
 #pragma unroll
     for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * V + l];
     double Q[4];
@@ -343,13 +444,26 @@ __global__ __launch_bounds__(NT) void k_update(Launch L, const double* __restric
     U[5] = 0.5 * (nb1lo + nb1hi);
     U[6] = 0.5 * (nb2lo + nb2hi);
     U[7] = 0.5 * (nb3lo + nb3hi);
+    c2p_setup(U, m, L.ph.gam, cs);
+  }
+  bool first = false;
+  double W0 = 0.0, v0 = 0.0;
+  if (MLP) first = mlp_guess_block(mlp, cs, m, valid, W0, v0);
+  if (valid) {
     double Pnew[5];
-    tier = cons2prim(U, m, L.ph.gam, PS, PS, false, L.ph.tol, L.ph.maxit, Pnew, iters);
-    const double Bnew[3] = {U[5] / m.gdet, U[6] / m.gdet, U[7] / m.gdet};
+    tier = c2p_solve(cs, m, first, W0, v0, PS, L.ph.tol, L.ph.maxit, Pnew, iters);
+    // B^i = Bbar^i / sqrt(-g) with Bbar^i the face average; c2p_setup holds alpha B^i
+    const double ia = 1.0 / m.alpha;
+    const double Bnew[3] = {cs.B1 * ia, cs.B2 * ia, cs.B3 * ia};
     hits = apply_floors(Pnew, Bnew, m, G.c[RHOFL * G.ncol + col], G.c[UFL * G.ncol + col],
                         L.ph.bsq_rho_max, L.ph.bsq_u_max, L.ph.gamma_max);
 #pragma unroll
     for (int v = 0; v < 5; v++) Pout[5 * bi.off + (int64_t)v * V + l] = Pnew[v];
+    if (NEXT_DT) dtc = cell_dt(Pnew, Bnew, m, L.ph);
+  }
+  if (NEXT_DT) {
+    const double r = block_min(dtc);
+    if (threadIdx.x == 0) dt_part[(int64_t)tl.y * gridDim.x + tl.x] = r;
   }
   if (STATS) {
     wave_histogram(L.cnt->tier, tier, valid);
@@ -361,14 +475,15 @@ __global__ __launch_bounds__(NT) void k_update(Launch L, const double* __restric
 
 // ------------------------------------------------------------- Courant reduction
 
-// per cell 1/dt = sum_d max(|v+|, |v-|)/dx_d from the cell-centred state; the minimum
-// of dt over all cells is kept as IEEE bits (order-preserving for positive doubles)
+// the minimum cell time step over all interior cells, as per-workgroup partials
 __global__ __launch_bounds__(NT) void k_dt(Launch L, const double* __restrict__ P,
-                                           const double* __restrict__ B) {
-  const BlockInfo bi = L.blk[blockIdx.y];
+                                           const double* __restrict__ B,
+                                           double* __restrict__ dt_part) {
+  const Tile tl = xcd_tile();
+  const BlockInfo bi = L.blk[tl.y];
   const int g = L.ph.ng;
   Cell c;
-  const bool valid = region_cell(bi, blockIdx.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
+  const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
                                  g, g, c);
   double dtc = __longlong_as_double(0x7FF0000000000000LL);
   if (valid) {
@@ -383,19 +498,19 @@ __global__ __launch_bounds__(NT) void k_dt(Launch L, const double* __restrict__ 
     Bc[0] = 0.5 * (b[l] + b[l + 1]) / m.gdet;
     Bc[1] = 0.5 * (b[V + l] + b[V + l + s2]) / m.gdet;
     Bc[2] = 0.5 * (b[2 * V + l] + b[2 * V + l + s3]) / m.gdet;
-    Fluid f;
-    fluid_state(Pc, Bc, m, f);
-    double vp, vm, inv = 0.0;
-    wave_speeds<1>(Pc, f, m, L.ph.gam, vp, vm);
-    inv += fmax(fabs(vp), fabs(vm)) / L.ph.dx[0];
-    wave_speeds<2>(Pc, f, m, L.ph.gam, vp, vm);
-    inv += fmax(fabs(vp), fabs(vm)) / L.ph.dx[1];
-    wave_speeds<3>(Pc, f, m, L.ph.gam, vp, vm);
-    inv += fmax(fabs(vp), fabs(vm)) / L.ph.dx[2];
-    dtc = 1.0 / inv;
+    dtc = cell_dt(Pc, Bc, m, L.ph);
   }
-  dtc = wave_min(dtc);
-  if (lane_id() == 0) atomicMin(&L.cnt->dt_bits, (unsigned long long)__double_as_longlong(dtc));
+  const double r = block_min(dtc);
+  if (threadIdx.x == 0) dt_part[(int64_t)tl.y * gridDim.x + tl.x] = r;
+}
+
+// one workgroup reduces the partials into the step's dt (order-free minimum)
+__global__ __launch_bounds__(NT) void k_dt_final(Counters* cnt, const double* __restrict__ part,
+                                                 int64_t n) {
+  double v = __longlong_as_double(0x7FF0000000000000LL);
+  for (int64_t i = threadIdx.x; i < n; i += NT) v = fmin(v, part[i]);
+  const double r = block_min(v);
+  if (threadIdx.x == 0) cnt->dt_bits = (unsigned long long)__double_as_longlong(r);
 }
 
 __global__ void k_reset(Counters* cnt, int all) {
@@ -432,10 +547,11 @@ __global__ __launch_bounds__(NT) void k_copy(const double* __restrict__ s, doubl
 
 __global__ __launch_bounds__(NT) void k_divb(Launch L, const double* __restrict__ B,
                                              double* __restrict__ field) {
-  const BlockInfo bi = L.blk[blockIdx.y];
+  const Tile tl = xcd_tile();
+  const BlockInfo bi = L.blk[tl.y];
   const int g = L.ph.ng;
   Cell c;
-  const bool valid = region_cell(bi, blockIdx.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
+  const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
                                  g, g, c);
   double a = 0.0, r = 0.0;
   if (valid) {
@@ -457,6 +573,39 @@ __global__ __launch_bounds__(NT) void k_divb(Launch L, const double* __restrict_
     atomicMax(&L.cnt->divb_abs, (unsigned long long)__double_as_longlong(a));
     atomicMax(&L.cnt->divb_rel, (unsigned long long)__double_as_longlong(r));
   }
+}
+
+// -------------------------------------------------------------- cell extraction
+
+// interior cells as flat batches: P[5][n], B[3][n] (coordinate field), geom[15][n]; the
+// cells of block b start at b * (cells per block), order k, j, i (uniform block sizes)
+__global__ __launch_bounds__(NT) void k_extract(Launch L, const double* __restrict__ Pin,
+                                                const double* __restrict__ Bin, int64_t n,
+                                                double* __restrict__ P, double* __restrict__ B,
+                                                double* __restrict__ geom) {
+  const BlockInfo bi = L.blk[blockIdx.y];
+  const int g = L.ph.ng;
+  Cell c;
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (!region_cell(bi, t, bi.n[0], bi.n[1], bi.n[2], g, g, g, c)) return;
+  const int64_t o = (int64_t)blockIdx.y * bi.n[0] * bi.n[1] * bi.n[2] + t;
+  const int64_t V = bi.vol, l = c.loc;
+  const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
+  const int64_t col = geo_col(L.geo, bi, c.J, c.I);
+  for (int q = 0; q < NGEO_F; q++) geom[q * n + o] = L.geo.c[q * L.geo.ncol + col];
+  const double gdet = L.geo.c[GDET * L.geo.ncol + col];
+  for (int v = 0; v < 5; v++) P[v * n + o] = Pin[5 * bi.off + v * V + l];
+  const double* b = Bin + 3 * bi.off;
+  B[o] = 0.5 * (b[l] + b[l + 1]) / gdet;
+  B[n + o] = 0.5 * (b[V + l] + b[V + l + s2]) / gdet;
+  B[2 * n + o] = 0.5 * (b[2 * V + l] + b[2 * V + l + s3]) / gdet;
+}
+
+void launch_extract(const Launch& L, const double* Pin, const double* Bin, int64_t n, double* P,
+                    double* B, double* geom) {
+  const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
+  hipLaunchKernelGGL(k_extract, dim3((unsigned)((r + NT - 1) / NT), L.nblk), dim3(NT), 0, L.stream,
+                     L, Pin, Bin, n, P, B, geom);
 }
 
 // ------------------------------------------------------------ batch inversion
@@ -537,17 +686,38 @@ void launch_emf(const Launch& L, const double* F, double* E) {
   hipLaunchKernelGGL(k_emf, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, F, E);
 }
 
-void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
-                   const double* Bcs, const double* F, const double* E, double dt_factor,
-                   double* Pout, double* Bout) {
+int64_t dt_partials(const Launch& L) {
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
-  hipLaunchKernelGGL(k_update<true>, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, Pn, Bn,
-                     Ps, Bcs, F, E, dt_factor, Pout, Bout);
+  return (int64_t)cdiv(r, NT) * L.nblk;
 }
 
-void launch_dt(const Launch& L, const double* P, const double* B) {
+void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
+                   const double* Bcs, const double* F, const double* E, double dt_factor,
+                   double* Pout, double* Bout, double* dt_part, const void* mlp) {
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
-  hipLaunchKernelGGL(k_dt, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, P, B);
+  const dim3 grid(cdiv(r, NT), L.nblk);
+  const MlpBlob* blob = (const MlpBlob*)mlp;
+  if (dt_part && blob)
+    hipLaunchKernelGGL((k_update<true, true, true>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps,
+                       Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob);
+  else if (dt_part)
+    hipLaunchKernelGGL((k_update<true, true, false>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps,
+                       Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob);
+  else if (blob)
+    hipLaunchKernelGGL((k_update<true, false, true>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps,
+                       Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob);
+  else
+    hipLaunchKernelGGL((k_update<true, false, false>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps,
+                       Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob);
+}
+
+void launch_dt(const Launch& L, const double* P, const double* B, double* dt_part) {
+  const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
+  hipLaunchKernelGGL(k_dt, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, P, B, dt_part);
+}
+
+void launch_dt_final(const Launch& L, const double* dt_part) {
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(NT), 0, L.stream, L.cnt, dt_part, dt_partials(L));
 }
 
 void launch_counters_reset(const Launch& L, bool all) {

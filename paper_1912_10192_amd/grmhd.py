@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SO_PATH = os.path.join(_HERE, "libgrmhd.so")
+SO_PATH = os.environ.get("GRMHD_SO", os.path.join(_HERE, "libgrmhd.so"))
 _lib = None
 
 ABI_VERSION = 1
@@ -26,7 +26,9 @@ GUESS_PLAIN, GUESS_MLP = 0, 1
 # every symbol declared in include/grmhd.h
 EXPORTS = ("grmhd_sizes", "grmhd_block_layout", "grmhd_init_grid", "grmhd_step",
            "grmhd_cons2prim", "grmhd_divb", "grmhd_plan_dump", "grmhd_geometry_point",
-           "grmhd_destroy", "grmhd_last_error")
+           "grmhd_mlp_sizes", "grmhd_mlp_train_step", "grmhd_mlp_gradients", "grmhd_mlp_pack",
+           "grmhd_mlp_forward", "grmhd_prim2cons_batch", "grmhd_mlp_dataset",
+           "grmhd_mlp_normalize", "grmhd_extract_cells", "grmhd_destroy", "grmhd_last_error")
 
 
 class BlockDesc(C.Structure):
@@ -96,6 +98,17 @@ def lib():
                                       C.POINTER(C.c_size_t)]
         L.grmhd_geometry_point.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double,
                                            C.c_void_p, C.c_void_p]
+        vp, i32, i64, f32, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
+        L.grmhd_mlp_sizes.argtypes = [i32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
+                                      C.POINTER(C.c_size_t)]
+        L.grmhd_mlp_train_step.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, f32, vp, vp, vp]
+        L.grmhd_mlp_gradients.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
+        L.grmhd_mlp_pack.argtypes = [vp, vp, vp, vp]
+        L.grmhd_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.grmhd_prim2cons_batch.argtypes = [i64, vp, vp, vp, f64, vp, vp]
+        L.grmhd_mlp_dataset.argtypes = [i64, vp, vp, vp, f64, vp, vp, vp, vp]
+        L.grmhd_mlp_normalize.argtypes = [vp, i64, i32, vp, vp, i32, vp]
+        L.grmhd_extract_cells.argtypes = [vp, vp, vp, vp]
         L.grmhd_destroy.argtypes = [C.c_void_p]
         L.grmhd_last_error.restype = C.c_char_p
         _lib = L
@@ -124,7 +137,7 @@ def uniform_blocks(n, block):
 class Desc:
     """Owns a GridDesc and its block array built from a workload dict (configs.py)."""
 
-    def __init__(self, cfg: dict, blocks=None, batched=False, profile=False):
+    def __init__(self, cfg: dict, blocks=None, batched=False, profile=False, mlp_blob=None):
         blocks = blocks if blocks is not None else uniform_blocks(cfg["n"], cfg.get("block", cfg["n"]))
         self.cfg = cfg
         self.blocks = (BlockDesc * len(blocks))()
@@ -159,10 +172,11 @@ class Desc:
         d.bsq_rho_max = cfg.get("bsq_rho_max", 1e300)
         d.bsq_u_max = cfg.get("bsq_u_max", 1e300)
         d.gamma_max = cfg.get("gamma_max", 1e150)
-        d.c2p_guess = GUESS_PLAIN
+        d.c2p_guess = GUESS_MLP if mlp_blob is not None else GUESS_PLAIN
         d.c2p_maxit = cfg.get("maxit", 50)
         d.c2p_tol = cfg.get("tol", 1e-12)
-        d.mlp_weights = None
+        d.mlp_weights = mlp_blob.data_ptr() if mlp_blob is not None else None
+        self.mlp_blob = mlp_blob
         d.batched = 1 if batched else 0
         d.profile = 1 if profile else 0
         self.d = d
@@ -255,11 +269,11 @@ class Grid:
     """A grid on the GPU: caller-owned torch buffers plus the library context."""
 
     def __init__(self, cfg: dict, state=None, blocks=None, batched=False, profile=False,
-                 device="cuda"):
+                 mlp_blob=None, device="cuda"):
         import torch
 
         self.torch = torch
-        self.desc = Desc(cfg, blocks=blocks, batched=batched, profile=profile)
+        self.desc = Desc(cfg, blocks=blocks, batched=batched, profile=profile, mlp_blob=mlp_blob)
         nprim, nbface, nwork = self.desc.sizes()
         self.device = torch.device(device)
         self.prim = torch.zeros(nprim, dtype=torch.float64, device=self.device)
@@ -300,6 +314,16 @@ class Grid:
         _check(lib().grmhd_step(self.ctx, n, C.byref(st) if stats else None))
         return st
 
+    def extract_cells(self):
+        """every interior cell as flat batches (P[5][n], B[3][n], geom[15][n]) on the device"""
+        torch = self.torch
+        n = int(np.prod(self.desc.cfg["n"]))
+        P = torch.empty((5, n), dtype=torch.float64, device=self.device)
+        B = torch.empty((3, n), dtype=torch.float64, device=self.device)
+        G = torch.empty((15, n), dtype=torch.float64, device=self.device)
+        _check(lib().grmhd_extract_cells(self.ctx, P.data_ptr(), B.data_ptr(), G.data_ptr()))
+        return P, B, G
+
     def divb(self):
         a, r = C.c_double(), C.c_double()
         _check(lib().grmhd_divb(self.ctx, C.byref(a), C.byref(r), None))
@@ -319,3 +343,104 @@ def cons2prim_batch(U, geom, guess, prev, gam, tol=1e-12, maxit=50):
     stream = torch.cuda.current_stream(U.device)
     _check(lib().grmhd_cons2prim(None, C.byref(b), C.c_void_p(stream.cuda_stream)))
     return P, iters, tier
+
+
+# ------------------------------------------------------------------ learned guess
+
+def _stream(t):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def mlp_sizes(batch):
+    a, b, c = C.c_size_t(), C.c_size_t(), C.c_size_t()
+    _check(lib().grmhd_mlp_sizes(batch, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def prim2cons_batch(P, B, geom, gam):
+    import torch
+    n = P.shape[1]
+    U = torch.empty((9, n), dtype=torch.float64, device=P.device)
+    _check(lib().grmhd_prim2cons_batch(n, P.data_ptr(), B.data_ptr(), geom.data_ptr(), gam,
+                                       U.data_ptr(), _stream(P)))
+    return U
+
+
+def mlp_dataset(U, P, geom, gam):
+    """raw features X[n][8], raw targets Y[n][2] (or None) and the finite-mask"""
+    import torch
+    n = U.shape[1]
+    X = torch.empty((n, 8), dtype=torch.float32, device=U.device)
+    Y = torch.empty((n, 2), dtype=torch.float32, device=U.device) if P is not None else None
+    ok = torch.empty(n, dtype=torch.int32, device=U.device)
+    _check(lib().grmhd_mlp_dataset(n, U.data_ptr(), P.data_ptr() if P is not None else None,
+                                   geom.data_ptr(), gam, X.data_ptr(),
+                                   Y.data_ptr() if Y is not None else None, ok.data_ptr(),
+                                   _stream(U)))
+    return X, Y, ok
+
+
+def mlp_normalize(A, mean=None, sd=None):
+    """normalise columns of A in place; computes mean/sd when they are not given"""
+    import torch
+    n, cols = A.shape
+    compute = mean is None
+    if compute:
+        mean = torch.empty(cols, dtype=torch.float32, device=A.device)
+        sd = torch.empty(cols, dtype=torch.float32, device=A.device)
+    _check(lib().grmhd_mlp_normalize(A.data_ptr(), n, cols, mean.data_ptr(), sd.data_ptr(),
+                                     1 if compute else 0, _stream(A)))
+    return mean, sd
+
+
+def mlp_pack(params, norm):
+    import torch
+    _, nblob, _ = mlp_sizes(1)
+    blob = torch.zeros(nblob, dtype=torch.uint8, device=params.device)
+    _check(lib().grmhd_mlp_pack(params.data_ptr(), norm.data_ptr(), blob.data_ptr(), _stream(params)))
+    return blob
+
+
+def mlp_forward(blob, X):
+    import torch
+    n = X.shape[0]
+    Y = torch.empty((n, 2), dtype=torch.float32, device=X.device)
+    _check(lib().grmhd_mlp_forward(blob.data_ptr(), X.data_ptr(), n, Y.data_ptr(), _stream(X)))
+    return Y
+
+
+def mlp_gradients(params, X, Y, idx, work=None):
+    import torch
+    batch = idx.shape[0]
+    nparam, _, nwork = mlp_sizes(batch)
+    work = work if work is not None else torch.empty(nwork, dtype=torch.float32, device=X.device)
+    grad = torch.empty(nparam, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check(lib().grmhd_mlp_gradients(params.data_ptr(), X.data_ptr(), Y.data_ptr(), idx.data_ptr(),
+                                     batch, work.data_ptr(), grad.data_ptr(), loss.data_ptr(),
+                                     _stream(X)))
+    return grad, loss
+
+
+class MLPTrainer:
+    """FP32 master weights + Adam state on the device; every step runs in the library."""
+
+    def __init__(self, params, batch=4096):
+        import torch
+        self.torch = torch
+        self.batch = batch
+        self.params = params.clone().contiguous()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        _, _, nwork = mlp_sizes(batch)
+        self.work = torch.empty(nwork, dtype=torch.float32, device=params.device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=params.device)
+        self.t = 0
+
+    def step(self, X, Y, idx, lr):
+        self.t += 1
+        _check(lib().grmhd_mlp_train_step(self.params.data_ptr(), self.m.data_ptr(),
+                                          self.v.data_ptr(), self.t, X.data_ptr(), Y.data_ptr(),
+                                          idx.data_ptr(), idx.shape[0], lr, self.work.data_ptr(),
+                                          self.loss.data_ptr(), _stream(X)))
