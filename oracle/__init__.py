@@ -87,6 +87,11 @@ def lib():
         L.orc_divb.argtypes = [C.c_void_p, _dp, C.c_void_p]
         L.orc_last_flux.restype = C.POINTER(C.c_double)
         L.orc_last_flux.argtypes = [C.c_void_p]
+        L.orc_last_emf.restype = C.POINTER(C.c_double)
+        L.orc_last_emf.argtypes = [C.c_void_p]
+        L.orc_reinvert.restype = C.c_int
+        L.orc_reinvert.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_int, C.c_int, C.c_int, _dp,
+                                   C.POINTER(Stats)]
         _lib = L
     return _lib
 
@@ -166,6 +171,16 @@ class Grid:
         p = self.L.orc_last_flux(self.ptr)
         return np.ctypeslib.as_array(p, shape=(n,)).reshape(3, 9, self.np[2], self.np[1],
                                                             self.np[0]).copy()
+
+    def last_emf(self):
+        n = 3 * self.np[0] * self.np[1] * self.np[2]
+        p = self.L.orc_last_emf(self.ptr)
+        return np.ctypeslib.as_array(p, shape=(n,)).reshape(3, self.np[2], self.np[1],
+                                                            self.np[0]).copy()
+
+    def reinvert(self, P, Bold, Bnew, K, J, I, dU):
+        return self.L.orc_reinvert(self.ptr, P, Bold, Bnew, K, J, I,
+                                   np.ascontiguousarray(dU, dtype=float), C.byref(self.stats))
 
     def interior(self, A):
         g = self.cfg["ng"]

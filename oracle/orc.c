@@ -627,6 +627,7 @@ void orc_free(orc_ctx* c) {
 
 int orc_np(const orc_ctx* c, int dim) { return c->np[dim]; }
 const double* orc_last_flux(const orc_ctx* c) { return c->flux; }
+const double* orc_last_emf(const orc_ctx* c) { return c->emf; }
 
 /* ------------------------------------------------------------------------- */
 /* Physical boundaries                                                        */
@@ -1005,4 +1006,38 @@ double orc_divb(orc_ctx* c, const double* B, double* field) {
         if (fabs(dv) > mx) mx = fabs(dv);
       }
   return mx;
+}
+
+int orc_reinvert(orc_ctx* c, double* P, const double* Bold, const double* Bnew, int K, int J,
+                 int I, const double* dU, orc_stats* st) {
+  const size_t nc = c->ncell;
+  size_t id = IDX(c, K, J, I);
+  size_t col = COL(c, J, I);
+  const double *gcov, *gcon;
+  double gdet, alpha;
+  geom_of(c, 0, col, &gcov, &gcon, &gdet, &alpha);
+  double P0[5], Bc[3], U[9];
+  for (int v = 0; v < 5; v++) P0[v] = P[v * nc + id];
+  Bc[0] = 0.5 * (Bold[id] + Bold[IDX(c, K, J, I + 1)]) / gdet;
+  Bc[1] = 0.5 * (Bold[nc + id] + Bold[nc + IDX(c, K, J + 1, I)]) / gdet;
+  Bc[2] = 0.5 * (Bold[2 * nc + id] + Bold[2 * nc + IDX(c, K + 1, J, I)]) / gdet;
+  orc_prim_to_flux(P0, Bc, gcov, gcon, gdet, alpha, c->d.gam, 0, U);
+  static const int comps[6] = {0, 1, 2, 3, 4, 8};
+  for (int q = 0; q < 6; q++) U[comps[q]] += dU[comps[q]];
+  U[5] = 0.5 * (Bnew[id] + Bnew[IDX(c, K, J, I + 1)]);
+  U[6] = 0.5 * (Bnew[nc + id] + Bnew[nc + IDX(c, K, J + 1, I)]);
+  U[7] = 0.5 * (Bnew[2 * nc + id] + Bnew[2 * nc + IDX(c, K + 1, J, I)]);
+  double Pnew[5], Bn[3];
+  int it = 0;
+  int tier = orc_cons2prim(U, gcov, gcon, gdet, alpha, c->d.gam, P0, P0, c->d.tol, c->d.maxit,
+                           Pnew, &it);
+  for (int i = 0; i < 3; i++) Bn[i] = U[5 + i] / gdet;
+  int hits = apply_floors(c, Pnew, Bn, gcov, gcon, alpha, col);
+  for (int v = 0; v < 5; v++) P[v * nc + id] = Pnew[v];
+  if (st) {
+    st->tier[tier]++;
+    st->iter_hist[it < 63 ? it : 63]++;
+    st->floor_hits += hits;
+  }
+  return tier;
 }

@@ -102,6 +102,14 @@ double orc_step(orc_ctx* c, double* P, double* B, int nsteps, double dt_fixed, o
 double orc_divb(orc_ctx* c, const double* B, double* field);
 /* copy of the oracle's face fluxes of the last stage: [3][9][NP3][NP2][NP1] */
 const double* orc_last_flux(const orc_ctx* c);
+/* edge EMFs of the last stage: [3][NP3][NP2][NP1] (E1 at (i, j-1/2, k-1/2), ...) */
+const double* orc_last_emf(const orc_ctx* c);
+/* Re-invert one interior cell after a correction of its conserved state (the flux
+ * correction of local time stepping, Sec. 3.5): U = U(P, B_old) + dU for mass, energy,
+ * momenta and entropy, field components from the corrected faces B_new; inversion from
+ * the cell's P as guess, then floors.  Writes P of the cell; returns the tier. */
+int orc_reinvert(orc_ctx* c, double* P, const double* Bold, const double* Bnew, int K, int J,
+                 int I, const double* dU, orc_stats* st);
 
 #ifdef __cplusplus
 }

@@ -38,9 +38,10 @@ def mink_cfg(n, recon=1, riemann=1, ng=3, L=None, **kw):
     return cfg
 
 
-def random_periodic_state(n, seed=1, amp=0.1, bamp=0.3, vamp=0.3):
+def random_periodic_state(n, seed=1, amp=0.1, bamp=0.3, vamp=0.3, dx=None):
     """smooth random periodic state with a divergence-free face field built from a
-    random edge vector potential (discrete curl, so div B = 0 to round-off)."""
+    random edge vector potential (discrete curl with the grid spacing dx, default cubic
+    cells of size 1/n[0] as in mink_cfg, so div B = 0 to round-off)."""
     rng = np.random.default_rng(seed)
     N1, N2, N3 = n
     k, j, i = np.meshgrid(np.arange(N3), np.arange(N2), np.arange(N1), indexing="ij")
@@ -58,7 +59,7 @@ def random_periodic_state(n, seed=1, amp=0.1, bamp=0.3, vamp=0.3):
         P[2 + c] = vamp * smooth(1.0)
     # edge potentials A1(i, j-1/2, k-1/2), A2(i-1/2, j, k-1/2), A3(i-1/2, j-1/2, k), periodic
     A = [bamp * smooth(1.0) / (2 * np.pi) for _ in range(3)]
-    dx = (1.0 / N1, 1.0 / N2, 1.0 / N3)
+    dx = dx if dx is not None else (1.0 / N1, 1.0 / N1, 1.0 / N1)
     roll = np.roll
     # face fields on the periodic interior (upper boundary faces equal lower ones)
     b1 = (roll(A[2], -1, axis=1) - A[2]) / dx[1] - (roll(A[1], -1, axis=0) - A[1]) / dx[2]
