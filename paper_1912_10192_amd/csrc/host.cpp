@@ -141,9 +141,19 @@ struct Plan {
   int32_t ti = 0, tj = 0;    // geometry table extents
   int64_t ncol = 0;
   std::vector<int32_t> owner;   // block id per effective cell
-  std::vector<GhostOp> ops[4];  // cells, x1 faces, x2 faces, x3 faces
+  std::vector<GhostOp> ops[4];  // cells, x1 faces, x2 faces, x3 faces (sorted by dst level)
+  // local time stepping
+  int32_t nlev = 1;
+  std::vector<int32_t> lev_blocks;             // block ids sorted by level
+  std::vector<int64_t> lev_boff;               // offsets into lev_blocks per level (+1)
+  std::vector<int64_t> ops_off[4];             // offsets into ops[kind] per level (+1)
+  std::vector<SyncItem> items;                 // sorted by the slow block's level
+  std::vector<int64_t> item_off;               // offsets per level (+1)
+  std::vector<int64_t> lev_cells;              // interior cells per level
+  int32_t rs = 0, rs2 = 0;                     // register plane size and row stride
   // work-buffer offsets (bytes)
-  size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, o_dtp, total;
+  size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, o_dtp;
+  size_t o_pold, o_bold, o_reg, o_ubuf, o_lev, o_items, total;
 };
 
 int validate(const grmhd_grid_desc* d) {
@@ -156,7 +166,7 @@ int validate(const grmhd_grid_desc* d) {
   if (d->recon != GRMHD_PLM_MC && d->recon != GRMHD_PPM) return fail(GRMHD_EINVAL, "unknown recon");
   if (d->riemann != GRMHD_LLF && d->riemann != GRMHD_HLLE) return fail(GRMHD_EINVAL, "unknown riemann");
   if (d->n_blocks < 1 || !d->blocks) return fail(GRMHD_EINVAL, "no blocks");
-  if (d->n_lat_levels != 1) return fail(GRMHD_EUNSUPPORTED, "only one time level is supported");
+  if (d->n_lat_levels < 1 || d->n_lat_levels > 8) return fail(GRMHD_EINVAL, "n_lat_levels must be 1..8");
   for (int k = 0; k < 3; k++)
     if (d->n_eff[k] < 1 || !(d->xmax[k] > d->xmin[k])) return fail(GRMHD_EINVAL, "bad extent");
   if (!(d->bc[0] == GRMHD_BC_OUTFLOW || d->bc[0] == GRMHD_BC_PERIODIC) || !(d->bc[1] == d->bc[0]))
@@ -185,7 +195,7 @@ int validate(const grmhd_grid_desc* d) {
       if (bd.org[k] < 0 || bd.org[k] + bd.n[k] > d->n_eff[k])
         return fail(GRMHD_EINVAL, "block outside the grid");
     }
-    if (bd.lat != 0) return fail(GRMHD_EUNSUPPORTED, "LAT levels are not supported");
+    if (bd.lat < 0 || bd.lat >= d->n_lat_levels) return fail(GRMHD_EINVAL, "block lat out of range");
   }
   return GRMHD_OK;
 }
@@ -310,27 +320,125 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
               int64_t gi = bd.org[0] + I - g, gj = bd.org[1] + J - g, gk = bd.org[2] + K - g;
               int flags = 0;
               const bool nz = compose(p.d, kind, gi, gj, gk, flags);
+              GhostOp op;
+              op.dst_blk = b;
+              op.dst_loc = (int32_t)(((int64_t)K * bi.np[1] + J) * bi.np[0] + I);
+              if (!nz) {   // a polar-axis face: identically zero, no source
+                op.src_blkf = b | (GF_ZERO << 24);
+                op.src_loc = 0;
+                p.ops[kind].push_back(op);
+                continue;
+              }
               // the source cell owning this position (a face at the upper grid edge
               // belongs to the last cell)
               int64_t ci = gi, cj = gj, ck = gk;
               if (kind == 1 && ci == N1) ci = N1 - 1;
               if (kind == 2 && cj == N2) cj = N2 - 1;
               if (kind == 3 && ck == N3) ck = N3 - 1;
-              const int sb = p.owner[(size_t)((ck * N2 + cj) * N1 + ci)];
+              int sb = p.owner[(size_t)((ck * N2 + cj) * N1 + ci)];
+              // A face strictly inside the grid on a boundary between two blocks has two
+              // copies; take this block's own, else the copy of the block at this block's
+              // time level, else the block whose cell has it as its lower face.
+              if (kind > 0) {
+                const int64_t f = kind == 1 ? gi : (kind == 2 ? gj : gk);
+                const int64_t Nf = kind == 1 ? N1 : (kind == 2 ? N2 : N3);
+                if (f > 0 && f < Nf) {
+                  int64_t di = gi, dj = gj, dk = gk;
+                  if (kind == 1) di--;
+                  if (kind == 2) dj--;
+                  if (kind == 3) dk--;
+                  const int db = p.owner[(size_t)((dk * N2 + dj) * N1 + di)];
+                  if (db != sb) {
+                    const int lt = bd.lat;
+                    const bool use_d = db == b || (sb != b && p.blocks[sb].lat != lt &&
+                                                   p.blocks[db].lat == lt);
+                    if (use_d) sb = db;
+                  }
+                }
+              }
               const grmhd_block_desc& sd = p.blocks[sb];
               const BlockInfo& si = p.info[sb];
               const int64_t li = gi - sd.org[0] + g, lj = gj - sd.org[1] + g, lk = gk - sd.org[2] + g;
-              GhostOp op;
-              op.dst_blk = b;
-              op.dst_loc = (int32_t)(((int64_t)K * bi.np[1] + J) * bi.np[0] + I);
-              if (!nz) flags = GF_ZERO;
+              if (p.blocks[sb].lat > bd.lat) flags |= GF_SLOW;
+              if (p.blocks[sb].lat < bd.lat) flags |= GF_FAST;
               op.src_blkf = sb | (flags << 24);
-              op.src_loc = nz ? (int32_t)((lk * si.np[1] + lj) * si.np[0] + li) : 0;
-              if (!nz) op.src_blkf = b | (flags << 24);
+              op.src_loc = (int32_t)((lk * si.np[1] + lj) * si.np[0] + li);
               p.ops[kind].push_back(op);
             }
       }
     }
+  }
+  // local time stepping tables
+  p.nlev = desc->n_lat_levels;
+  {
+    const int L = p.nlev;
+    p.lev_blocks.clear();
+    p.lev_boff.assign(L + 1, 0);
+    p.lev_cells.assign(L, 0);
+    for (int l = 0; l < L; l++) {
+      p.lev_boff[l] = (int64_t)p.lev_blocks.size();
+      for (int b = 0; b < nb; b++)
+        if (p.blocks[b].lat == l) {
+          p.lev_blocks.push_back(b);
+          p.lev_cells[l] += (int64_t)p.blocks[b].n[0] * p.blocks[b].n[1] * p.blocks[b].n[2];
+        }
+    }
+    p.lev_boff[L] = (int64_t)p.lev_blocks.size();
+    if (with_maps) {
+      for (int kind = 0; kind < 4; kind++) {
+        std::stable_sort(p.ops[kind].begin(), p.ops[kind].end(),
+                         [&](const GhostOp& a, const GhostOp& c) {
+                           return p.blocks[a.dst_blk].lat < p.blocks[c.dst_blk].lat;
+                         });
+        p.ops_off[kind].assign(L + 1, 0);
+        for (const GhostOp& op : p.ops[kind]) p.ops_off[kind][p.blocks[op.dst_blk].lat + 1]++;
+        for (int l = 0; l < L; l++) p.ops_off[kind][l + 1] += p.ops_off[kind][l];
+      }
+    }
+    // neighbour checks: every block within one cell of a block (through the physical
+    // boundaries) differs by at most one level; x2 and x3 face neighbours share a level;
+    // x1 neighbours at another level cover the same x2-x3 extent
+    p.items.clear();
+    if (L > 1) {
+      for (int b = 0; b < nb; b++) {
+        const grmhd_block_desc& bd = p.blocks[b];
+        for (int dk = -1; dk <= 1; dk++)
+          for (int dj = -1; dj <= 1; dj++)
+            for (int di = -1; di <= 1; di++) {
+              if (!di && !dj && !dk) continue;
+              // probe the middle of the neighbouring region
+              int64_t gi = di < 0 ? bd.org[0] - 1 : (di > 0 ? bd.org[0] + bd.n[0] : bd.org[0] + bd.n[0] / 2);
+              int64_t gj = dj < 0 ? bd.org[1] - 1 : (dj > 0 ? bd.org[1] + bd.n[1] : bd.org[1] + bd.n[1] / 2);
+              int64_t gk = dk < 0 ? bd.org[2] - 1 : (dk > 0 ? bd.org[2] + bd.n[2] : bd.org[2] + bd.n[2] / 2);
+              int fl = 0;
+              compose(p.d, 0, gi, gj, gk, fl);
+              const int nbk = p.owner[(size_t)((gk * N2 + gj) * N1 + gi)];
+              const int dl = p.blocks[nbk].lat - bd.lat;
+              if (dl > 1 || dl < -1) return fail(GRMHD_EINVAL, "neighbouring time levels differ by more than one");
+              if (!di && (dj || dk) && (!dj || !dk) && dl != 0)
+                return fail(GRMHD_EUNSUPPORTED, "time-level interfaces must lie on x1 block faces");
+              if (di && !dj && !dk && dl == -1) {
+                const grmhd_block_desc& fd = p.blocks[nbk];
+                if (fd.org[1] != bd.org[1] || fd.org[2] != bd.org[2] || fd.n[1] != bd.n[1] || fd.n[2] != bd.n[2])
+                  return fail(GRMHD_EUNSUPPORTED, "x1 neighbours at another time level must match in x2, x3");
+                SyncItem it;
+                it.slow = b;
+                it.fast = nbk;
+                it.side = di > 0 ? 1 : 0;
+                it.pad = 0;
+                if (nbk != b) p.items.push_back(it);
+              }
+            }
+      }
+    }
+    std::stable_sort(p.items.begin(), p.items.end(), [&](const SyncItem& a, const SyncItem& c) {
+      return p.blocks[a.slow].lat < p.blocks[c.slow].lat;
+    });
+    p.item_off.assign(L + 1, 0);
+    for (const SyncItem& it : p.items) p.item_off[p.blocks[it.slow].lat + 1]++;
+    for (int l = 0; l < L; l++) p.item_off[l + 1] += p.item_off[l];
+    p.rs2 = p.max_n[1] + 1;
+    p.rs = (p.max_n[2] + 1) * p.rs2;
   }
   // work-buffer layout
   size_t o = 0;
@@ -359,6 +467,17 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
     p.o_ops[kind] = take(count * sizeof(GhostOp));
   }
   p.o_cnt = take(sizeof(Counters));
+  const bool lat = p.nlev > 1;
+  p.o_pold = take(lat ? 5 * V * 8 : 0);
+  p.o_bold = take(lat ? 3 * V * 8 : 0);
+  p.o_reg = take(lat ? (size_t)nb * 40 * p.rs * 8 : 0);
+  {
+    // sync items: at most two per block
+    const size_t nitems = lat ? (size_t)2 * nb : 0;
+    p.o_ubuf = take(nitems * p.max_n[1] * p.max_n[2] * 9 * 8);
+    p.o_items = take(nitems * sizeof(SyncItem));
+  }
+  p.o_lev = take((size_t)nb * sizeof(int32_t));
   {
     const int64_t r = (int64_t)p.max_n[0] * p.max_n[1] * p.max_n[2];
     p.o_dtp = take((size_t)((r + 255) / 256) * nb * 8);
@@ -427,6 +546,14 @@ struct grmhd_ctx {
   int64_t nops[4];
   bool b_in_alt = false;
   const void* mlp = nullptr;   // packed MLP blob when the learned guess is on
+  // local time stepping
+  double *pold = nullptr, *bold = nullptr, *reg = nullptr, *ubuf = nullptr;
+  int32_t* lev_list = nullptr;
+  SyncItem* items = nullptr;
+  bool batched = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
   hipEvent_t ev0, ev1;
 };
 
@@ -480,6 +607,13 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   c->f = (double*)(w + p.o_f);
   c->e = (double*)(w + p.o_e);
   c->dtp = (double*)(w + p.o_dtp);
+  c->pold = (double*)(w + p.o_pold);
+  c->bold = (double*)(w + p.o_bold);
+  c->reg = (double*)(w + p.o_reg);
+  c->ubuf = (double*)(w + p.o_ubuf);
+  c->lev_list = (int32_t*)(w + p.o_lev);
+  c->items = (SyncItem*)(w + p.o_items);
+  c->batched = desc->batched != 0;
   std::vector<double> gc, g1, g2;
   build_geometry(p, gc, g1, g2);
   auto up = [&](size_t off, const void* src, size_t bytes) -> int {
@@ -502,8 +636,14 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
       return rc;
     }
   }
+  if ((rc = up(p.o_lev, p.lev_blocks.data(), p.lev_blocks.size() * sizeof(int32_t))) ||
+      (rc = up(p.o_items, p.items.data(), p.items.size() * sizeof(SyncItem)))) {
+    delete c;
+    return rc;
+  }
   Launch& L = c->L;
   L.blk = (const BlockInfo*)(w + p.o_blk);
+  L.blist = nullptr;
   L.nblk = desc->n_blocks;
   for (int k = 0; k < 3; k++) {
     L.max_np[k] = p.max_np[k];
@@ -583,6 +723,83 @@ static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double
   prof_end(c);
 }
 
+// one block level of a substep: predictor and corrector with time-aware ghosts, then the
+// flux/EMF registers and the face field copied back from the stage buffer
+static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
+  const Plan& p = c->plan;
+  Launch L = base;
+  L.blist = c->lev_list + p.lev_boff[lev];
+  L.nblk = (int32_t)(p.lev_boff[lev + 1] - p.lev_boff[lev]);
+  if (L.nblk == 0) return;
+  const int recon = p.d.recon, riem = p.d.riemann;
+  double* P = c->bufs.prim;
+  double* B = c->bufs.bface;
+  const double scale = std::ldexp(1.0, lev);
+  const double period = std::ldexp(1.0, lev + 1);
+  const double t0 = s - std::fmod((double)s, period);
+  const double w_pred = (s - t0) / period;
+  const double w_corr = (s + 0.5 * scale - t0) / period;
+  launch_copy_blocks(L, P, c->pold, 5);
+  launch_copy_blocks(L, B, c->bold, 3);
+  auto ghosts = [&](double* Pdst, double* Bdst, const double* Pcur, const double* Bcur, double w) {
+    prof_begin(c, KC_GHOST);
+    const int64_t o0 = p.ops_off[0][lev], n0 = p.ops_off[0][lev + 1] - o0;
+    launch_ghost_cells_t(L, c->ops[0] + o0, n0, P, c->pold, Pcur, w, Pdst);
+    for (int k = 0; k < 3; k++) {
+      const int64_t o = p.ops_off[k + 1][lev], n = p.ops_off[k + 1][lev + 1] - o;
+      launch_ghost_faces_t(L, c->ops[k + 1] + o, n, B, c->bold, Bcur, w, Bdst, k);
+    }
+    prof_end(c);
+  };
+  auto stage_l = [&](const double* Ps, const double* Bs, double factor, double* Pout) {
+    prof_begin(c, KC_BCELL);
+    launch_bcell(L, Bs, c->bc);
+    prof_end(c);
+    for (int dir = 1; dir <= 3; dir++) {
+      prof_begin(c, KC_FLUX1 + dir - 1);
+      launch_flux(L, dir, recon, riem, Ps, c->bc, Bs, c->f);
+      prof_end(c);
+    }
+    prof_begin(c, KC_EMF);
+    launch_emf(L, c->f, c->e);
+    prof_end(c);
+    prof_begin(c, KC_UPDATE);
+    launch_update(L, P, B, Ps, c->bc, c->f, c->e, factor, Pout, c->balt, nullptr, c->mlp);
+    prof_end(c);
+  };
+  ghosts(P, B, P, B, w_pred);
+  stage_l(P, B, 0.5 * scale, c->ps);                 // predictor -> ps, balt
+  ghosts(c->ps, c->balt, c->ps, c->balt, w_corr);
+  stage_l(c->ps, c->balt, scale, P);                 // corrector -> P, balt
+  launch_registers(L, c->f, c->e, scale, (s % (2 << lev)) == 0 ? 1 : 0, c->reg, p.rs, p.rs2);
+  launch_copy_blocks(L, c->balt, B, 3);
+}
+
+static void lat_cycle(grmhd_ctx* c) {
+  const Plan& p = c->plan;
+  const Launch& L = c->L;
+  const int nsub = 1 << (p.nlev - 1);
+  prof_begin(c, KC_DT);
+  launch_dt(L, c->bufs.prim, c->bufs.bface, c->dtp);
+  {
+    const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
+    const int gridx = (int)((r + 255) / 256);
+    launch_dt_final_lat(L, c->dtp, (int64_t)gridx * L.nblk, gridx);
+  }
+  prof_end(c);
+  for (int s = 0; s < nsub; s++) {
+    for (int lev = p.nlev - 1; lev >= 0; lev--)
+      if (s % (1 << lev) == 0) lat_level_step(c, L, lev, s);
+    for (int lev = 1; lev < p.nlev; lev++)
+      if ((s + 1) % (1 << lev) == 0) {
+        const int64_t o = p.item_off[lev], n = p.item_off[lev + 1] - o;
+        launch_sync(L, c->items + o, (int)n, c->bufs.prim, c->bufs.bface, c->reg, p.rs, p.rs2,
+                    c->ubuf);
+      }
+  }
+  launch_tsim_cycle(L, (double)nsub);
+}
+
 int grmhd_step(grmhd_ctx* c, int32_t n_cycles, grmhd_step_stats* stats) {
   if (!c) return fail(GRMHD_EINVAL, "NULL context");
   if (n_cycles < 0) return fail(GRMHD_EINVAL, "negative step count");
@@ -590,7 +807,28 @@ int grmhd_step(grmhd_ctx* c, int32_t n_cycles, grmhd_step_stats* stats) {
   HIPCHK(hipEventRecord(c->ev0, c->stream));
   launch_counters_reset(L, false);
   double* P = c->bufs.prim;
-  for (int s = 0; s < n_cycles; s++) {
+  if (c->plan.nlev > 1) {
+    if (c->batched && !c->profile) {
+      if (!c->graph_exec) {
+        // capture one LAT cycle (every launch of it) into a graph on a private stream
+        if (!c->cap_stream) HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        Launch saved = c->L;
+        c->L.stream = c->cap_stream;
+        HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        lat_cycle(c);
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &c->graph);
+        c->L = saved;
+        if (e != hipSuccess) return fail(GRMHD_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+        HIPCHK(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+      }
+      for (int cyc = 0; cyc < n_cycles; cyc++) HIPCHK(hipGraphLaunch(c->graph_exec, c->stream));
+    } else {
+      for (int cyc = 0; cyc < n_cycles; cyc++) lat_cycle(c);
+    }
+    fill_ghosts(c, P, c->bufs.bface);
+  }
+  for (int s = 0; s < (c->plan.nlev > 1 ? 0 : n_cycles); s++) {
     double* Bcur = c->b_in_alt ? c->balt : c->bufs.bface;
     double* Both = c->b_in_alt ? c->bufs.bface : c->balt;
     fill_ghosts(c, P, Bcur);
@@ -632,12 +870,19 @@ int grmhd_step(grmhd_ctx* c, int32_t n_cycles, grmhd_step_stats* stats) {
     HIPCHK(hipMemcpyAsync(&h, L.cnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     std::memset(stats, 0, sizeof(*stats));
-    const int64_t cells = c->plan.n_interior;
-    const int64_t eff = (int64_t)c->plan.d.n_eff[0] * c->plan.d.n_eff[1] * c->plan.d.n_eff[2];
-    stats->real_zone_cycles = cells * n_cycles;
-    stats->lat_eff_zone_cycles = cells * n_cycles;
-    stats->amr_lat_eff_zone_cycles = eff * n_cycles;
-    stats->steps_per_level[0] = n_cycles;
+    const Plan& p = c->plan;
+    const int64_t cells = p.n_interior;
+    const int64_t eff = (int64_t)p.d.n_eff[0] * p.d.n_eff[1] * p.d.n_eff[2];
+    const int64_t nsub = (int64_t)1 << (p.nlev - 1);
+    int64_t real = 0;
+    for (int l = 0; l < p.nlev && l < 8; l++) {
+      const int64_t steps = (nsub >> l) * n_cycles;
+      stats->steps_per_level[l] = steps;
+      real += p.lev_cells[l] * steps;
+    }
+    stats->real_zone_cycles = real;
+    stats->lat_eff_zone_cycles = cells * nsub * n_cycles;
+    stats->amr_lat_eff_zone_cycles = eff * nsub * n_cycles;
     for (int q = 0; q < 64; q++) stats->c2p_iter_hist[q] = (int64_t)h.hist[q];
     for (int q = 0; q < 5; q++) stats->c2p_tier[q] = (int64_t)h.tier[q];
     stats->floor_hits = (int64_t)h.floors;
@@ -718,6 +963,9 @@ int grmhd_destroy(grmhd_ctx* c) {
   (void)hipEventDestroy(c->ev0);
   (void)hipEventDestroy(c->ev1);
   for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   delete c;
   return GRMHD_OK;
 }

@@ -20,7 +20,13 @@ struct BlockInfo {
 struct GhostOp {
   int32_t dst_blk, dst_loc, src_blkf, src_loc;
 };
-enum { GF_FLIP = 1, GF_CLAMP_NEG = 2, GF_CLAMP_POS = 4, GF_ZERO = 8 };
+enum { GF_FLIP = 1, GF_CLAMP_NEG = 2, GF_CLAMP_POS = 4, GF_ZERO = 8, GF_SLOW = 16, GF_FAST = 32 };
+
+// one plane shared by a slower block and its faster x1 neighbour (side 0 = the slow
+// block's lower x1 face, 1 = upper)
+struct SyncItem {
+  int32_t slow, fast, side, pad;
+};
 
 // geometry tables: SoA [quantity][column], column = j * ti + i
 struct GeoTab {
@@ -52,7 +58,8 @@ struct Phys {
 
 struct Launch {
   const BlockInfo* blk;   // device block table
-  int32_t nblk;
+  const int32_t* blist;   // device list of the blocks a launch covers (NULL = all)
+  int32_t nblk;           // blocks covered
   int32_t max_np[3];      // largest padded extents
   int32_t max_n[3];       // largest interior extents
   GeoTab geo;
@@ -86,6 +93,18 @@ void launch_copy(const Launch& L, const double* src, double* dst, int64_t n);
 void launch_divb(const Launch& L, const double* B, double* field);
 void launch_extract(const Launch& L, const double* Pin, const double* Bin, int64_t n, double* P,
                     double* B, double* geom);
+// local time stepping (lat.hip)
+void launch_ghost_cells_t(const Launch& L, const GhostOp* ops, int64_t nops, const double* main,
+                          const double* old, const double* cur, double w, double* dst);
+void launch_ghost_faces_t(const Launch& L, const GhostOp* ops, int64_t nops, const double* main,
+                          const double* old, const double* cur, double w, double* dst, int comp);
+void launch_copy_blocks(const Launch& L, const double* src, double* dst, int nvar);
+void launch_registers(const Launch& L, const double* F, const double* E, double dt_factor,
+                      int first, double* reg, int rs, int rs2);
+void launch_sync(const Launch& L, const SyncItem* items, int nitems, double* P, double* B,
+                 const double* reg, int rs, int rs2, double* Ubuf);
+void launch_dt_final_lat(const Launch& L, const double* part, int64_t n, int gridx);
+void launch_tsim_cycle(const Launch& L, double substeps);
 void launch_c2p_batch(int64_t n, const double* U, const double* geom, const double* guess,
                       const double* prev, double* P, int32_t* iters, int32_t* tier, double gam,
                       double tol, int32_t maxit, hipStream_t stream);

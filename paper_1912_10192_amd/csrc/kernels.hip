@@ -147,7 +147,7 @@ __global__ __launch_bounds__(NT) void k_ghost_faces(const BlockInfo* __restrict_
 __global__ __launch_bounds__(NT) void k_bcell(Launch L, const double* __restrict__ B,
                                               double* __restrict__ Bc) {
   const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[tl.y];
+  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
   Cell c;
   if (!region_cell(bi, tl.x * NT + threadIdx.x, bi.np[0], bi.np[1], bi.np[2], 0, 0, 0, c))
     return;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(NT) FLUX_OCC void k_flux(Launch L, const double* __
                                              const double* __restrict__ B,
                                              double* __restrict__ F) {
   const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[tl.y];
+  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
   const int g = L.ph.ng;
   const int r0 = DIR == 1 ? bi.n[0] + 1 : bi.n[0] + 2;
   const int r1 = DIR == 2 ? bi.n[1] + 1 : bi.n[1] + 2;
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(NT) FLUX_OCC void k_flux(Launch L, const double* __
 __global__ __launch_bounds__(NT) void k_emf(Launch L, const double* __restrict__ F,
                                             double* __restrict__ E) {
   const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[tl.y];
+  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
   const int g = L.ph.ng;
   Cell c;
   if (!region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0] + 1, bi.n[1] + 1, bi.n[2] + 1, g, g,
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(NT) UPDATE_OCC void k_update(Launch L, const double
                                                double* __restrict__ dt_part,
                                                const MlpBlob* __restrict__ mlp) {
   const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[tl.y];
+  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
   const int g = L.ph.ng;
   Cell c;
   const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
@@ -480,7 +480,7 @@ __global__ __launch_bounds__(NT) void k_dt(Launch L, const double* __restrict__ 
                                            const double* __restrict__ B,
                                            double* __restrict__ dt_part) {
   const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[tl.y];
+  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
   const int g = L.ph.ng;
   Cell c;
   const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
@@ -548,7 +548,7 @@ __global__ __launch_bounds__(NT) void k_copy(const double* __restrict__ s, doubl
 __global__ __launch_bounds__(NT) void k_divb(Launch L, const double* __restrict__ B,
                                              double* __restrict__ field) {
   const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[tl.y];
+  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
   const int g = L.ph.ng;
   Cell c;
   const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,

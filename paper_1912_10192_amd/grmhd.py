@@ -120,8 +120,9 @@ def _check(rc):
         raise GrmhdError(f"libgrmhd error {rc}: {lib().grmhd_last_error().decode()}")
 
 
-def uniform_blocks(n, block):
-    """blocks of size `block` tiling an n grid, x1 fastest in the block order"""
+def uniform_blocks(n, block, lats=None):
+    """blocks of size `block` tiling an n grid, x1 fastest in the block order; lats (one
+    time level per x1 block column) gives local time stepping levels by radius"""
     nb = [n[d] // block[d] for d in range(3)]
     if any(nb[d] * block[d] != n[d] for d in range(3)):
         raise ValueError("block size must divide the grid")
@@ -130,7 +131,7 @@ def uniform_blocks(n, block):
         for j in range(nb[1]):
             for i in range(nb[0]):
                 out.append(dict(org=(i * block[0], j * block[1], k * block[2]), n=tuple(block),
-                                lev=(0, 0, 0), lat=0))
+                                lev=(0, 0, 0), lat=int(lats[i]) if lats is not None else 0))
     return out
 
 
@@ -158,7 +159,7 @@ class Desc:
             d.n_eff[k] = cfg["n"][k]
         d.n_ghost = cfg["ng"]
         d.n_blocks = len(blocks)
-        d.n_lat_levels = 1
+        d.n_lat_levels = max(int(bd["lat"]) for bd in blocks) + 1
         d.blocks = C.cast(self.blocks, C.POINTER(BlockDesc))
         d.recon = cfg["recon"]
         d.riemann = cfg["riemann"]
@@ -444,3 +445,19 @@ class MLPTrainer:
                                           self.v.data_ptr(), self.t, X.data_ptr(), Y.data_ptr(),
                                           idx.data_ptr(), idx.shape[0], lr, self.work.data_ptr(),
                                           self.loss.data_ptr(), _stream(X)))
+
+
+def lat_levels_by_radius(cfg, edges):
+    """time level of each x1 block column from its inner radius: level l for
+    edges[l-1] <= r_inner < edges[l] (edges increasing), clipped so neighbours differ by
+    at most one level"""
+    import math
+    nb1 = cfg["n"][0] // cfg["block"][0]
+    dx1 = (cfg["xhi"][0] - cfg["xlo"][0]) / cfg["n"][0]
+    lats = []
+    for i in range(nb1):
+        r = math.exp(cfg["xlo"][0] + i * cfg["block"][0] * dx1)
+        lats.append(sum(1 for e in edges if r >= e))
+    for i in range(1, nb1):
+        lats[i] = min(lats[i], lats[i - 1] + 1)
+    return lats

@@ -125,3 +125,16 @@ def test_ghost_maps_match_oracle_fill(case):
             else:
                 sign = -1.0 if flags & 1 else 1.0
                 assert sign * got == want
+
+
+def test_lat_layout_checks():
+    cfg = configs.scaled(configs.TORUS_UNIFORM, (32, 16, 16), block=(8, 8, 8))
+    ok = grmhd.Desc(cfg, blocks=grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=[0, 1, 2, 2]))
+    ok.sizes()
+    with pytest.raises(grmhd.GrmhdError, match="more than one"):
+        grmhd.Desc(cfg, blocks=grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=[0, 2, 2, 2])).sizes()
+    bl = grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=[0, 1, 1, 1])
+    bl[-1]["lat"] = 0        # an x2/x3 neighbour at another level
+    with pytest.raises(grmhd.GrmhdError, match="x1 block faces"):
+        grmhd.Desc(cfg, blocks=bl).sizes()
+    assert grmhd.lat_levels_by_radius(configs.TORUS_UNIFORM, [2.4, 4.8, 9.6]) == [0, 0, 1, 2, 2, 3, 3, 3]
