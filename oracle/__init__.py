@@ -85,6 +85,12 @@ def lib():
         L.orc_step.argtypes = [C.c_void_p, _dp, _dp, C.c_int, C.c_double, C.POINTER(Stats)]
         L.orc_divb.restype = C.c_double
         L.orc_divb.argtypes = [C.c_void_p, _dp, C.c_void_p]
+        L.orc_stage_flux.argtypes = [C.c_void_p, _dp, _dp]
+        L.orc_stage_apply.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, _dp, _dp, C.c_void_p]
+        L.orc_flux_buffer.restype = C.POINTER(C.c_double)
+        L.orc_flux_buffer.argtypes = [C.c_void_p]
+        L.orc_emf_buffer.restype = C.POINTER(C.c_double)
+        L.orc_emf_buffer.argtypes = [C.c_void_p]
         L.orc_last_flux.restype = C.POINTER(C.c_double)
         L.orc_last_flux.argtypes = [C.c_void_p]
         L.orc_last_emf.restype = C.POINTER(C.c_double)
@@ -157,6 +163,24 @@ class Grid:
 
     def stage(self, Pn, Bn, Ps, Bs, dts, Pout, Bout):
         self.L.orc_stage(self.ptr, Pn, Bn, Ps, Bs, dts, Pout, Bout, C.byref(self.stats))
+
+    def stage_flux(self, Ps, Bs):
+        self.L.orc_stage_flux(self.ptr, Ps, Bs)
+
+    def stage_apply(self, Pn, Bn, Ps, dts, Pout, Bout):
+        self.L.orc_stage_apply(self.ptr, Pn, Bn, Ps, dts, Pout, Bout, C.byref(self.stats))
+
+    def flux_view(self):
+        """writable view of the flux buffer [3][9][NP3][NP2][NP1]"""
+        n = 27 * self.np[0] * self.np[1] * self.np[2]
+        p = self.L.orc_flux_buffer(self.ptr)
+        return np.ctypeslib.as_array(p, shape=(n,)).reshape(3, 9, self.np[2], self.np[1], self.np[0])
+
+    def emf_view(self):
+        """writable view of the EMF buffer [3][NP3][NP2][NP1]"""
+        n = 3 * self.np[0] * self.np[1] * self.np[2]
+        p = self.L.orc_emf_buffer(self.ptr)
+        return np.ctypeslib.as_array(p, shape=(n,)).reshape(3, self.np[2], self.np[1], self.np[0])
 
     def step(self, P, B, nsteps=1, dt_fixed=0.0):
         return self.L.orc_step(self.ptr, P, B, nsteps, dt_fixed, C.byref(self.stats))

@@ -58,6 +58,7 @@ class LatGrid:
         self.t = 0.0
         self.dt_min = 0.0
         self.steps = [0] * self.L
+        self.bdx = [list(self.dx) for _ in self.blocks]
         self.xnb = [self._x1_neighbours(i) for i in range(len(self.blocks))]
 
     # ------------------------------------------------------------------ layout
@@ -189,11 +190,11 @@ class LatGrid:
 
     def sync(self, s):
         g = self.g
-        dx1, dx2, dx3 = self.dx
         for i, b in enumerate(self.blocks):
             lat = b["lat"]
             if lat == 0 or (s + 1) % (2 ** lat) != 0:
                 continue
+            dx1 = self.bdx[i][0]
             n1, n2, n3 = b["n"]
             for side, opp, sgn in (("lo", "hi", -1.0), ("hi", "lo", 1.0)):
                 f = self.xnb[i].get(side)

@@ -628,6 +628,8 @@ void orc_free(orc_ctx* c) {
 int orc_np(const orc_ctx* c, int dim) { return c->np[dim]; }
 const double* orc_last_flux(const orc_ctx* c) { return c->flux; }
 const double* orc_last_emf(const orc_ctx* c) { return c->emf; }
+double* orc_flux_buffer(orc_ctx* c) { return c->flux; }
+double* orc_emf_buffer(orc_ctx* c) { return c->emf; }
 
 /* ------------------------------------------------------------------------- */
 /* Physical boundaries                                                        */
@@ -836,11 +838,14 @@ static int apply_floors(const orc_ctx* c, double* P, const double* Bcon, const d
   return hits;
 }
 
-void orc_stage(orc_ctx* c, const double* Pn, const double* Bn, const double* Ps,
-               const double* Bs, double dts, double* Pout, double* Bout, orc_stats* st) {
+#define FL(d, q, K, J, I) c->flux[((size_t)(d) * 9 + (q)) * nc + IDX(c, K, J, I)]
+#define EM(d, K, J, I) c->emf[(size_t)(d) * nc + IDX(c, K, J, I)]
+
+/* Steps 1-2 of a stage: cell-centred field, face fluxes and edge EMFs of the stage
+ * state, kept in the context until orc_stage_apply. */
+void orc_stage_flux(orc_ctx* c, const double* Ps, const double* Bs) {
   const int g = c->d.ng, n1 = c->d.n[0], n2 = c->d.n[1], n3 = c->d.n[2];
   const size_t nc = c->ncell;
-  const double *dx = c->dx;
   double* bc = c->bcell;
   cell_field(c, Bs, bc);
   /* 1. face fluxes; transverse range extends one ghost layer for the EMFs */
@@ -859,8 +864,6 @@ void orc_stage(orc_ctx* c, const double* Pn, const double* Bn, const double* Ps,
           for (int q = 0; q < 9; q++) c->flux[((size_t)d * 9 + q) * nc + id] = F[q];
         }
   }
-#define FL(d, q, K, J, I) c->flux[((size_t)(d) * 9 + (q)) * nc + IDX(c, K, J, I)]
-#define EM(d, K, J, I) c->emf[(size_t)(d) * nc + IDX(c, K, J, I)]
   /* 2. edge EMFs as the average of the four neighbouring face fluxes of B */
   for (int K = g; K <= g + n3; K++)
     for (int J = g; J <= g + n2; J++)
@@ -878,6 +881,16 @@ void orc_stage(orc_ctx* c, const double* Pn, const double* Bn, const double* Ps,
               : 0.25 * (FL(1, 5, K, J, I - 1) + FL(1, 5, K, J, I) - FL(0, 6, K, J, I)
                         - FL(0, 6, K, J - 1, I));
       }
+}
+
+/* Steps 3-4 of a stage from the fluxes and EMFs held in the context (as left by
+ * orc_stage_flux, possibly corrected in between). */
+void orc_stage_apply(orc_ctx* c, const double* Pn, const double* Bn, const double* Ps,
+                     double dts, double* Pout, double* Bout, orc_stats* st) {
+  const int g = c->d.ng, n1 = c->d.n[0], n2 = c->d.n[1], n3 = c->d.n[2];
+  const size_t nc = c->ncell;
+  const double *dx = c->dx;
+  const double* bc = c->bcell;
   /* 3. constrained transport of the face field */
   for (int K = g; K <= g + n3; K++)
     for (int J = g; J <= g + n2; J++)
@@ -938,8 +951,14 @@ void orc_stage(orc_ctx* c, const double* Pn, const double* Bn, const double* Ps,
           st->cells++;
         }
       }
+}
 #undef FL
 #undef EM
+
+void orc_stage(orc_ctx* c, const double* Pn, const double* Bn, const double* Ps,
+               const double* Bs, double dts, double* Pout, double* Bout, orc_stats* st) {
+  orc_stage_flux(c, Ps, Bs);
+  orc_stage_apply(c, Pn, Bn, Ps, dts, Pout, Bout, st);
 }
 
 double orc_dt(orc_ctx* c, const double* P, const double* B) {

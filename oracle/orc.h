@@ -94,6 +94,17 @@ double orc_dt(orc_ctx* c, const double* P, const double* B);
  * on (Ps,Bs) over dts; ghosts of Ps/Bs must be filled.  Pout/Bout ghosts untouched. */
 void   orc_stage(orc_ctx* c, const double* Pn, const double* Bn, const double* Ps,
                  const double* Bs, double dts, double* Pout, double* Bout, orc_stats* st);
+/* the same stage in two halves: orc_stage_flux evaluates the cell-centred field, the
+ * face fluxes and the edge EMFs of (Ps,Bs) into the context; orc_stage_apply performs
+ * the constrained transport and the cell update with whatever the context then holds
+ * (a caller may correct fluxes and EMFs in between through the buffers below). */
+void   orc_stage_flux(orc_ctx* c, const double* Ps, const double* Bs);
+void   orc_stage_apply(orc_ctx* c, const double* Pn, const double* Bn, const double* Ps,
+                       double dts, double* Pout, double* Bout, orc_stats* st);
+/* writable views of the context's flux [3][9][NP3][NP2][NP1] and EMF [3][NP3][NP2][NP1]
+ * buffers */
+double* orc_flux_buffer(orc_ctx* c);
+double* orc_emf_buffer(orc_ctx* c);
 /* nsteps full midpoint steps (BC fill, Courant dt, predictor, corrector).
  * dt_fixed > 0 overrides the Courant step.  Returns the last dt. */
 double orc_step(orc_ctx* c, double* P, double* B, int nsteps, double dt_fixed, orc_stats* st);

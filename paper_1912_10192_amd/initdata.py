@@ -205,3 +205,64 @@ def torus_state(n, a=0.9375, rin_grid=1.2, rout_grid=50.0, rin=6.0, rmax=12.0,
         insk = np.broadcast_to(ins[None], (N3, N2, N1))
         P[1] = np.where(insk, P[1] * (1.0 + amp * (2.0 * xi - 1.0)), P[1])
     return P, B1, B2, B3
+
+
+# --------------------------------------------------------------------------- block grids
+
+def coarsen_state(state, r):
+    """a state on a grid coarser by r[d] in {0, 1} per dimension: cell values as the mean
+    of the fine cells, face fields as the mean of the fine sub-faces (so a discretely
+    divergence-free field stays divergence-free).  state = global interior arrays."""
+    P, B1, B2, B3 = state
+    s = [1 + x for x in r]
+
+    def mean_cells(A):
+        acc = 0.0
+        for ok in range(s[2]):
+            for oj in range(s[1]):
+                for oi in range(s[0]):
+                    acc = acc + A[..., ok::s[2], oj::s[1], oi::s[0]]
+        return acc / (s[0] * s[1] * s[2])
+
+    def mean_faces(A, d):
+        acc = 0.0
+        cnt = 0
+        offs = [range(1) if x == d else range(s[x]) for x in range(3)]
+        for ok in offs[2]:
+            for oj in offs[1]:
+                for oi in offs[0]:
+                    acc = acc + A[ok::s[2], oj::s[1], oi::s[0]]
+                    cnt += 1
+        return acc / cnt
+
+    return mean_cells(P), mean_faces(B1, 0), mean_faces(B2, 1), mean_faces(B3, 2)
+
+
+def block_states(state, blocks, lmax):
+    """per-block interior arrays of a block grid from a state at the finest level:
+    block b at levels lev takes the state coarsened to its level (one factor of two per
+    level below lmax, applied level by level)"""
+    cache = {tuple(lmax): state}
+
+    def at(lev):
+        lev = tuple(lev)
+        if lev not in cache:
+            d = max(range(3), key=lambda x: lmax[x] - lev[x])
+            up = list(lev)
+            r = [0, 0, 0]
+            for x in range(3):
+                if lev[x] < lmax[x] and lmax[x] - lev[x] == lmax[d] - lev[d]:
+                    up[x] += 1
+                    r[x] = 1
+            cache[lev] = coarsen_state(at(up), r)
+        return cache[lev]
+
+    out = []
+    for b in blocks:
+        P, B1, B2, B3 = at(b.get("lev", (0, 0, 0)))
+        o, n = b["org"], b["n"]
+        out.append((P[:, o[2]:o[2] + n[2], o[1]:o[1] + n[1], o[0]:o[0] + n[0]].copy(),
+                    B1[o[2]:o[2] + n[2], o[1]:o[1] + n[1], o[0]:o[0] + n[0] + 1].copy(),
+                    B2[o[2]:o[2] + n[2], o[1]:o[1] + n[1] + 1, o[0]:o[0] + n[0]].copy(),
+                    B3[o[2]:o[2] + n[2] + 1, o[1]:o[1] + n[1], o[0]:o[0] + n[0]].copy()))
+    return out

@@ -1,0 +1,224 @@
+"""Pins of the oracle's static-refinement driver (CPU): reduction to the single-level
+driver, exactness of the transfer operators on linear data, conservation and div B across
+refinement and time-level jumps, and second-order convergence of a wave crossing
+refinement jumps."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.amr import AmrGrid, minmod
+from oracle.lat import LatGrid
+from paper_1912_10192_amd import configs, initdata
+from tests.helpers import mink_cfg, random_periodic_state
+from tests.test_oracle_lat import x1_blocks
+
+
+def band_blocks(lats=(0, 0), nx=(16, 16, 8)):
+    """periodic Minkowski box: a band of blocks refined by 2 in every dimension across
+    the middle half of x2, coarse bands above and below; two blocks along x1 per band,
+    with the given time levels"""
+    N1, N2, N3 = nx
+    c1, c2, c3 = N1 // 2, N2 // 2, N3 // 2
+    out = []
+    for org2, n2, lev in ((0, c2 // 4, (0, 0, 0)), (N2 // 4, N2 // 2, (1, 1, 1)),
+                          (3 * c2 // 4, c2 // 4, (0, 0, 0))):
+        for h in range(2):
+            if lev == (0, 0, 0):
+                out.append(dict(org=(h * c1 // 2, org2, 0), n=(c1 // 2, n2, c3), lev=lev, lat=lats[h]))
+            else:
+                out.append(dict(org=(h * N1 // 2, org2, 0), n=(N1 // 2, n2, N3), lev=lev, lat=lats[h]))
+    return out
+
+
+def amr_totals(g):
+    """sum of U over all interior cells times the cell volume of each block"""
+    tot = np.zeros(9)
+    gcov, gcon, gdet, alpha, _ = oracle.geom_point(g.cfg, 0.0, 0.0)
+    for i, (P, B1, B2, B3) in enumerate(g.get_blocks()):
+        vol = g.bdx[i][0] * g.bdx[i][1] * g.bdx[i][2]
+        n = g.blocks[i]["n"]
+        for k in range(n[2]):
+            for j in range(n[1]):
+                for ii in range(n[0]):
+                    Bc = np.array([0.5 * (B1[k, j, ii] + B1[k, j, ii + 1]),
+                                   0.5 * (B2[k, j, ii] + B2[k, j + 1, ii]),
+                                   0.5 * (B3[k, j, ii] + B3[k + 1, j, ii])])
+                    tot += vol * oracle.prim_to_flux(P[:, k, j, ii], Bc, gcov, gcon, gdet, alpha,
+                                                     g.cfg["gam"], 0)
+    return tot
+
+
+def test_single_refinement_level_equals_lat_driver():
+    cfg = mink_cfg((16, 6, 6), recon=1, riemann=1)
+    state = random_periodic_state(cfg["n"], seed=8, amp=0.05, vamp=0.2, bamp=0.2)
+    blocks = x1_blocks(cfg["n"], 4, [0, 1, 2, 1], nb2=2)
+    a = LatGrid(cfg, blocks)
+    a.set_state(*state)
+    b = AmrGrid(cfg, blocks)
+    b.set_state(*state)
+    for _ in range(2):
+        assert a.cycle() == b.cycle()
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(x, y)
+
+
+def test_prolongation_exact_for_linear_data_and_restriction_inverts_it():
+    cfg = mink_cfg((16, 16, 8), recon=1, riemann=1, L=(1.0, 1.0, 0.5))
+    g = AmrGrid(cfg, band_blocks())
+    G = g._vg((0, 0, 0))
+    VP, VB = G.zeros()
+    ng = cfg["ng"]
+    K, J, I = np.meshgrid(*[np.arange(s) - ng + 0.5 for s in VP.shape[1:]], indexing="ij")
+    coef = np.array([[1.0, 0.3, -0.2, 0.1], [2.0, -0.1, 0.4, 0.2], [0.1, 0.2, 0.3, -0.4],
+                     [-0.3, 0.1, 0.1, 0.1], [0.5, -0.2, 0.0, 0.3]])
+    for v in range(5):
+        VP[v] = coef[v, 0] + coef[v, 1] * I + coef[v, 2] * J + coef[v, 3] * K
+    # face fields: linear in the transverse coordinates, constant along the normal
+    VB[0] = 1.0 + 0.25 * J - 0.5 * K
+    VB[1] = -0.5 + 0.75 * I + 0.125 * K
+    VB[2] = 0.3 - 0.25 * I + 0.5 * J
+    FP, FB = g._vg((1, 1, 1)).zeros()
+    n = 0          # the lower-x1 coarse block of the lower band
+    g._put_prolong(FP, FB, n, VP, VB, (1, 1, 1))
+    o, m = g.blocks[n]["org"], g.blocks[n]["n"]
+    ks, js, is_ = [slice(ng + 2 * o[d], ng + 2 * (o[d] + m[d])) for d in (2, 1, 0)]
+    fk, fj, fi = np.meshgrid(*[(np.arange(2 * o[d], 2 * (o[d] + m[d])) + 0.5) / 2 for d in (2, 1, 0)],
+                             indexing="ij")
+    for v in range(5):
+        want = coef[v, 0] + coef[v, 1] * fi + coef[v, 2] * fj + coef[v, 3] * fk
+        assert np.allclose(FP[v, ks, js, is_], want, rtol=0, atol=1e-13)
+    # x1 faces of the fine cells: value at the transverse fine-cell centres
+    want = 1.0 + 0.25 * fj - 0.5 * fk
+    assert np.allclose(FB[0, ks, js, is_], want, rtol=0, atol=1e-13)
+    # restriction of the prolonged block gives the coarse values back (sqrt(-g) = 1)
+    gg = AmrGrid(cfg, [dict(org=tuple(2 * x for x in o), n=tuple(2 * x for x in m), lev=(1, 1, 1), lat=0),
+                       dict(org=(0, 0, 0), n=(1, 1, 1), lev=(0, 0, 0), lat=0)])
+    Pn, Bn = gg.ctx[0].zeros()
+    Pn[:, ng:ng + 2 * m[2], ng:ng + 2 * m[1], ng:ng + 2 * m[0]] = FP[:, ks, js, is_]
+    RP, RB = gg._vg((0, 0, 0)).zeros()
+    gg._put_restrict(RP, RB, 0, Pn, Bn, (1, 1, 1))
+    sl = (slice(None),) + tuple(slice(ng + o[d], ng + o[d] + m[d]) for d in (2, 1, 0))
+    assert np.allclose(RP[sl], VP[sl], rtol=0, atol=1e-13)
+
+
+def test_minmod_cases():
+    a = np.array([1.0, -1.0, 1.0, 2.0, -3.0, 0.0])
+    b = np.array([2.0, -0.5, -1.0, 2.0, -1.0, 1.0])
+    assert np.array_equal(minmod(a, b), np.array([1.0, -0.5, 0.0, 2.0, -1.0, 0.0]))
+
+
+@pytest.mark.parametrize("lats", [(0, 0), (0, 1)])
+def test_refinement_conserves_and_keeps_divb_in_periodic_box(lats):
+    cfg = mink_cfg((16, 16, 8), recon=1, riemann=1, L=(1.0, 1.0, 0.5))
+    g = AmrGrid(cfg, band_blocks(lats))
+    assert len(g.links) == 4
+    state = random_periodic_state(cfg["n"], seed=3, amp=0.05, vamp=0.2, bamp=0.2,
+                                  dx=(1 / 16, 1 / 16, 1 / 16))
+    g.set_blocks(initdata.block_states(state, g.blocks, g.Lmax))
+    t0 = amr_totals(g)
+    assert g.divb() < 1e-13
+    for _ in range(2):
+        g.cycle()
+    t1 = amr_totals(g)
+    scale = np.abs(t0[:5]).max()
+    assert np.abs(t1[:5] - t0[:5]).max() <= 1e-14 * scale, (t1 - t0)[:5]
+    assert g.divb() < 1e-13
+    # the coarse copy of every refinement face equals the mean of the fine faces
+    for c, f, d, side, e, lo, hi in g.links:
+        Ic, If = g._face_maps((c, f, d, side, e, lo, hi))
+        assert d == 1
+        ng = cfg["ng"]
+        oc, of = g.blocks[c]["org"], g.blocks[f]["org"]
+        for k in range(lo[2], hi[2]):
+            for i in range(lo[0], hi[0]):
+                fine = [g.B[f][1, ng + 2 * k + a - of[2], If, ng + 2 * i + b - of[0]]
+                        for a in (0, 1) for b in (0, 1)]
+                assert g.B[c][1, ng + k - oc[2], Ic, ng + i - oc[0]] == pytest.approx(
+                    np.mean(fine), rel=1e-14, abs=1e-15)
+
+
+def test_uniform_state_stays_uniform_across_refinement():
+    cfg = mink_cfg((16, 16, 8), recon=1, riemann=0, L=(1.0, 1.0, 0.5))
+    g = AmrGrid(cfg, band_blocks((0, 1)))
+    N = cfg["n"]
+    P = np.empty((5,) + tuple(reversed(N)))
+    P[:] = np.array([1.3, 0.7, 0.2, -0.1, 0.05])[:, None, None, None]
+    B1 = np.full((N[2], N[1], N[0] + 1), 0.4)
+    B2 = np.full((N[2], N[1] + 1, N[0]), -0.3)
+    B3 = np.full((N[2] + 1, N[1], N[0]), 0.2)
+    g.set_blocks(initdata.block_states((P, B1, B2, B3), g.blocks, g.Lmax))
+    g.cycle()
+    for i, (Pi, b1, b2, b3) in enumerate(g.get_blocks()):
+        for v in range(5):
+            assert np.abs(Pi[v] - P[v, 0, 0, 0]).max() <= 1e-14 * abs(P[v, 0, 0, 0])
+        assert np.abs(b1 - 0.4).max() <= 1e-15 and np.abs(b2 + 0.3).max() <= 1e-15
+        assert np.abs(b3 - 0.2).max() <= 1e-15
+
+
+def _wave_bands(N):
+    """fast wave along x2 through two refinement jumps (coarse-fine-coarse, periodic);
+    one period; L1 error of the primitives over all blocks"""
+    from tests.test_oracle_grid import _eigen
+    gam = 4.0 / 3.0
+    P0 = np.array([1.0, 1.0, 0.0, 0.0, 0.0])
+    Bvec = np.array([0.0, 1.0, 1.0])
+    lam, R, tb = _eigen(P0, Bvec, gam, 2)       # transverse field: B1 (row 5), B3 (row 6)
+    v = lam[6]
+    r = R[:, 6] / np.abs(R[:, 6]).max()
+    n = (4, N, 4)
+    cfg = mink_cfg(n, recon=1, riemann=1, L=(4.0 / N, 1.0, 4.0 / N))
+    blocks = [dict(org=(0, 0, 0), n=(2, N // 8, 2), lev=(0, 1, 0), lat=0),
+              dict(org=(0, N // 4, 0), n=(4, N // 2, 4), lev=(1, 2, 1), lat=0),
+              dict(org=(0, 3 * N // 8, 0), n=(2, N // 8, 2), lev=(0, 1, 0), lat=0)]
+    y = (np.arange(N) + 0.5) / N
+    yf = np.arange(N + 1) / N
+    prof = np.cos(2 * np.pi * y)[None, :, None] * np.ones((4, 1, 4))
+    P = np.empty((5, 4, N, 4))
+    for c in range(5):
+        P[c] = P0[c] + 1e-5 * r[c] * prof
+    # B1, B3 follow the wave at cell centres of their faces; B2 = B_normal is constant
+    b1 = Bvec[0] + 1e-5 * r[5] * prof
+    B1 = np.concatenate([b1, b1[:, :, :1]], axis=2)
+    B2 = np.full((4, N + 1, 4), Bvec[1])
+    b3 = Bvec[2] + 1e-5 * r[6] * prof
+    B3 = np.concatenate([b3, b3[:1]], axis=0)
+    g = AmrGrid(cfg, blocks)
+    g.set_blocks(initdata.block_states((P, B1, B2, B3), g.blocks, g.Lmax))
+    T = 1.0 / v
+    while g.t < T - 1e-12:
+        g.cycle()
+    err = 0.0
+    for i, (Pi, _, _, _) in enumerate(g.get_blocks()):
+        b = g.blocks[i]
+        dy = g.bdx[i][1]
+        yc = (b["org"][1] + np.arange(b["n"][1]) + 0.5) * dy
+        want = P0[:, None] + 1e-5 * r[:5, None] * np.cos(2 * np.pi * (yc - v * g.t))[None, :]
+        err += (np.abs(Pi[:, 0, :, 0] - want).sum(axis=1) * dy).sum()
+    return err
+
+
+def test_wave_through_refinement_jumps_second_order():
+    e1 = _wave_bands(32)
+    e2 = _wave_bands(64)
+    order = math.log2(e1 / e2)
+    assert order > 1.8, (e1, e2, order)
+
+
+def test_torus_polar_bands_run_and_keep_divb():
+    """Kerr-Schild torus on a coarse-polar / fine-equatorial block layout: every cell
+    stays finite and div B stays at round-off over a step with refinement faces in x2"""
+    eff = (32, 16, 16)
+    cfg = configs.scaled(configs.TORUS_UNIFORM, eff, ng=3)
+    blocks = [dict(org=(0, 0, 0), n=(16, 2, 8), lev=(0, 0, 0), lat=0),
+              dict(org=(0, 4, 0), n=(32, 8, 16), lev=(1, 1, 1), lat=0),
+              dict(org=(0, 6, 0), n=(16, 2, 8), lev=(0, 0, 0), lat=0)]
+    state = initdata.torus_state(eff, **configs.TORUS_INIT)
+    g = AmrGrid(cfg, blocks)
+    g.set_blocks(initdata.block_states(state, g.blocks, g.Lmax))
+    scale = max(np.abs(b).max() for blk in g.get_blocks() for b in blk[1:]) / min(g.bdx[1])
+    g.cycle()
+    for Pi, *_ in g.get_blocks():
+        assert np.isfinite(Pi).all()
+    assert g.divb() <= 1e-12 * scale
