@@ -50,12 +50,20 @@ enum { GRMHD_LLF = 0, GRMHD_HLLE = 1 };
 enum { GRMHD_BC_OUTFLOW = 0, GRMHD_BC_POLAR = 1, GRMHD_BC_PERIODIC = 2 };
 enum { GRMHD_GUESS_PLAIN = 0, GRMHD_GUESS_MLP = 1 };
 
-/* One block of the grid (Sec. 3.3 block structure).  Origins are in cells of the
- * effective grid; the blocks must tile the effective grid without overlap. */
+/* One block of the grid (Sec. 3.3 block structure; Sec. 3.4 coarsening toward the
+ * poles is refinement in some dimensions only).  The effective grid n_eff is the grid
+ * at the finest level of each dimension; a block at level l in dimension d has cells
+ * 2^(lmax_d - l) effective cells wide (lmax_d = the largest level of any block in d),
+ * and its origin and extent count cells of its own level.  The blocks must tile the
+ * domain without overlap.  Blocks that touch (through faces, edges, corners and the
+ * physical boundaries) differ by at most one level per dimension, never finer in one
+ * dimension and coarser in another; refined blocks start and end on cells of the
+ * coarser neighbour; blocks across a refinement face share a time level; no
+ * refinement jump lies across the polar axis. */
 typedef struct {
-  int32_t lev[3];   /* refinement level per dimension (0 = effective resolution) */
+  int32_t lev[3];   /* refinement level per dimension (0 = coarsest)            */
   int32_t lat;      /* local-time-stepping level (0 = fastest)                  */
-  int64_t org[3];   /* origin in cells of the effective grid                    */
+  int64_t org[3];   /* origin in cells of the block's own level                 */
   int32_t n[3];     /* cells per dimension                                       */
 } grmhd_block_desc;
 
@@ -164,8 +172,17 @@ int grmhd_divb(grmhd_ctx* ctx, double* max_abs, double* max_rel, double* field);
  * ghost gather list for what = 0 (cell variables) or 1..3 (face component 1..3) as
  * int32 quadruples (dst block, dst local index, src block | flags << 24, src local
  * index); flags 1 = negate utilde^2 / the face value, 2 = clamp utilde^1 <= 0,
- * 4 = clamp utilde^1 >= 0, 8 = zero (polar-axis face).  host_buf NULL queries the
- * size in bytes. */
+ * 4 = clamp utilde^1 >= 0, 8 = zero (polar-axis face), 16 / 32 = the source runs
+ * at a slower / faster time level.  what = 4..7: the ghost values that involve another
+ * refinement level (cells, face components 1..3) as int32 quadruples (dst block, dst
+ * local index, mode, first sample) -- mode bits 0-2 prolonged dimensions, bits 4-6
+ * child in the upper half per dimension, bit 8 mean of two face stencils, bits 16-23
+ * flags of the result; what = 8: their samples as int32 quadruples (block | flags <<
+ * 24, local index, averaged dimensions of a restriction, 0); what = 9: the refinement
+ * faces as 20 int32 each (coarse block, fine block, normal dimension, refined
+ * dimensions, patch lo[3], hi[3] in coarse local indices, coarse plane, fine plane,
+ * coarse origin[3], fine origin[3], positions, 0).  host_buf NULL queries the size in
+ * bytes. */
 int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes);
 
 /* Planner geometry at one internal-coordinate point (host only, no device needed):

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "libgrmhd.so")
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "lat.hip", "mlp.hip", "host.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "lat.hip", "amr.hip", "mlp.hip", "host.cpp")]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions stay off (plain scalar/vector FP32 only)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

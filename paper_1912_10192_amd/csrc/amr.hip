@@ -1,0 +1,299 @@
+// amr.hip -- kernels of static mesh refinement (paper Sec. 3.3; the per-direction
+// coarsening toward the poles of Sec. 3.4 is the same machinery with refinement in some
+// dimensions only).
+//
+// Blocks carry a refinement level per dimension, and neighbours differ by at most one
+// level.  The kernels here
+// (1) fill ghost values that come from another level: a coarse ghost is the
+//     restriction of the finer neighbour (sqrt(-g)-weighted mean of the primitives of
+//     the covered fine cells; arithmetic mean of the fine sub-faces of a face), a fine
+//     ghost the minmod-limited linear prolongation of the coarser neighbour's values
+//     (slopes from the parent's neighbours at its own level, child = parent +-
+//     slope/4 per refined dimension; a fine face that cuts a coarse cell in two takes
+//     the mean of the prolonged values on the two coarse faces bounding that cell);
+// (2) make the coarse side of every refinement face use the fine side's fluxes and
+//     edge EMFs (area and edge means), so both sides change the conserved totals and
+//     the face field by the same amount;
+// (3) after each update, give the coarse copy of every shared face the mean of the
+//     fine faces, the finer side owning shared faces.
+// Each value is read from the source block's state as the viewing block sees it at its
+// stage time (the time-level rules of local time stepping, as for plain copies).
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+#include "internal.h"
+
+namespace grmhd {
+
+constexpr int AT = 256;
+
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (a > 0.0 && b > 0.0) return fmin(a, b);
+  if (a < 0.0 && b < 0.0) return fmax(a, b);
+  return 0.0;
+}
+
+// a value of the source state at index q, by the time relation of its block
+__device__ __forceinline__ double timed(int fl, int64_t q, const double* __restrict__ main,
+                                        const double* __restrict__ old,
+                                        const double* __restrict__ cur, double w) {
+  if (fl & GF_SLOW) return old[q] + w * (main[q] - old[q]);
+  if (fl & GF_FAST) return main[q];
+  return cur[q];
+}
+
+__device__ double cell_value(const BlockInfo* __restrict__ blk, const GeoTab& G,
+                             const AmrSample& s, int v, const double* __restrict__ main,
+                             const double* __restrict__ old, const double* __restrict__ cur,
+                             double w) {
+  const int sb = s.blkf & 0xFFFFFF, fl = (s.blkf >> 24) & 0xFF;
+  const BlockInfo bi = blk[sb];
+  const int64_t base = 5 * bi.off + (int64_t)v * bi.vol;
+  double x;
+  if (s.mask == 0) {
+    x = timed(fl, base + s.loc, main, old, cur, w);
+  } else {
+    const int n0 = (s.mask & 1) ? 2 : 1, n1 = (s.mask & 2) ? 2 : 1, n2 = (s.mask & 4) ? 2 : 1;
+    double num = 0.0, den = 0.0;
+    for (int ok = 0; ok < n2; ok++)
+      for (int oj = 0; oj < n1; oj++)
+        for (int oi = 0; oi < n0; oi++) {
+          const int64_t l = s.loc + ((int64_t)ok * bi.np[1] + oj) * bi.np[0] + oi;
+          const int I = (int)(l % bi.np[0]), J = (int)((l / bi.np[0]) % bi.np[1]);
+          const double wg = G.c[GDET * G.ncol + geo_col(G, bi, J, I)];
+          num = __dadd_rn(num, __dmul_rn(wg, timed(fl, base + l, main, old, cur, w)));
+          den = __dadd_rn(den, wg);
+        }
+    x = num / den;
+  }
+  if (v == 3 && (fl & GF_FLIP)) x = -x;
+  if (v == 2 && (fl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
+  if (v == 2 && (fl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
+  return x;
+}
+
+__device__ double face_value(const BlockInfo* __restrict__ blk, const AmrSample& s, int comp,
+                             const double* __restrict__ main, const double* __restrict__ old,
+                             const double* __restrict__ cur, double w) {
+  const int sb = s.blkf & 0xFFFFFF, fl = (s.blkf >> 24) & 0xFF;
+  if (fl & GF_ZERO) return 0.0;
+  const BlockInfo bi = blk[sb];
+  const int64_t base = 3 * bi.off + (int64_t)comp * bi.vol;
+  double x;
+  if (s.mask == 0) {
+    x = timed(fl, base + s.loc, main, old, cur, w);
+  } else {
+    const int n0 = (s.mask & 1) ? 2 : 1, n1 = (s.mask & 2) ? 2 : 1, n2 = (s.mask & 4) ? 2 : 1;
+    double acc = 0.0;
+    for (int ok = 0; ok < n2; ok++)
+      for (int oj = 0; oj < n1; oj++)
+        for (int oi = 0; oi < n0; oi++)
+          acc += timed(fl, base + s.loc + ((int64_t)ok * bi.np[1] + oj) * bi.np[0] + oi, main,
+                       old, cur, w);
+    x = acc * (1.0 / (n0 * n1 * n2));
+  }
+  if (fl & GF_FLIP) x = -x;
+  return x;
+}
+
+__global__ __launch_bounds__(AT) void k_amr_cells(const BlockInfo* __restrict__ blk, GeoTab G,
+                                                  const AmrOp* __restrict__ ops, int64_t nops,
+                                                  const AmrSample* __restrict__ samp,
+                                                  const double* __restrict__ main,
+                                                  const double* __restrict__ old,
+                                                  const double* __restrict__ cur, double w,
+                                                  double* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * AT + threadIdx.x;
+  if (i >= nops) return;
+  const AmrOp op = ops[i];
+  const BlockInfo d = blk[op.dst_blk];
+  const AmrSample* S = samp + op.samp;
+  const int pd = op.mode & AM_PDIMS;
+  const int ofl = (op.mode >> AM_FLAGS_SHIFT) & 0xFF;
+  for (int v = 0; v < 5; v++) {
+    const double c = cell_value(blk, G, S[0], v, main, old, cur, w);
+    double x = c;
+    int k = 1;
+    for (int dd = 0; dd < 3; dd++) {
+      if (!((pd >> dd) & 1)) continue;
+      const double sm = cell_value(blk, G, S[k], v, main, old, cur, w);
+      const double sp = cell_value(blk, G, S[k + 1], v, main, old, cur, w);
+      k += 2;
+      const double sg = ((op.mode >> (AM_UPPER_SHIFT + dd)) & 1) ? 0.25 : -0.25;
+      x = x + sg * minmod(c - sm, sp - c);
+    }
+    if (v == 3 && (ofl & GF_FLIP)) x = -x;
+    if (v == 2 && (ofl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
+    if (v == 2 && (ofl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
+    dst[5 * d.off + (int64_t)v * d.vol + op.dst_loc] = x;
+  }
+}
+
+__global__ __launch_bounds__(AT) void k_amr_faces(const BlockInfo* __restrict__ blk,
+                                                  const AmrOp* __restrict__ ops, int64_t nops,
+                                                  const AmrSample* __restrict__ samp,
+                                                  const double* __restrict__ main,
+                                                  const double* __restrict__ old,
+                                                  const double* __restrict__ cur, double w,
+                                                  double* __restrict__ dst, int comp) {
+  const int64_t i = (int64_t)blockIdx.x * AT + threadIdx.x;
+  if (i >= nops) return;
+  const AmrOp op = ops[i];
+  const BlockInfo d = blk[op.dst_blk];
+  const AmrSample* S = samp + op.samp;
+  const int t = op.mode & AM_PDIMS & ~(1 << comp);
+  const int ofl = (op.mode >> AM_FLAGS_SHIFT) & 0xFF;
+  const int nst = 1 + 2 * __popc(t);
+  double st[2];
+  const int ns = (op.mode & AM_TWO) ? 2 : 1;
+  for (int q = 0; q < ns; q++) {
+    const AmrSample* R = S + q * nst;
+    const double c = face_value(blk, R[0], comp, main, old, cur, w);
+    double x = c;
+    int k = 1;
+    for (int dd = 0; dd < 3; dd++) {
+      if (!((t >> dd) & 1)) continue;
+      const double sm = face_value(blk, R[k], comp, main, old, cur, w);
+      const double sp = face_value(blk, R[k + 1], comp, main, old, cur, w);
+      k += 2;
+      const double sg = ((op.mode >> (AM_UPPER_SHIFT + dd)) & 1) ? 0.25 : -0.25;
+      x = x + sg * minmod(c - sm, sp - c);
+    }
+    st[q] = x;
+  }
+  double x = ns == 2 ? 0.5 * (st[0] + st[1]) : st[0];
+  if (ofl & GF_ZERO) x = 0.0;
+  else if (ofl & GF_FLIP) x = -x;
+  dst[3 * d.off + (int64_t)comp * d.vol + op.dst_loc] = x;
+}
+
+// ------------------------------------------------------------------ refinement faces
+
+struct LinkPos {
+  int kind;          // 0 face, 1 edge along a0, 2 edge along a1
+  int pc[3], pf[3];  // coarse local index, fine local index of the first child
+};
+
+__device__ __forceinline__ bool link_position(const AmrLink& lk, int g, int t, LinkPos& P) {
+  const int d = lk.d;
+  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
+  const int w0 = lk.hi[a0] - lk.lo[a0], w1 = lk.hi[a1] - lk.lo[a1];
+  const int nf = w0 * w1, ne0 = w0 * (w1 + 1), ne1 = w1 * (w0 + 1);
+  int i0, i1;
+  if (t < nf) {
+    P.kind = 0;
+    i0 = t % w0;
+    i1 = t / w0;
+  } else if (t < nf + ne0) {
+    P.kind = 1;
+    i0 = (t - nf) % w0;
+    i1 = (t - nf) / w0;
+  } else if (t < nf + ne0 + ne1) {
+    P.kind = 2;
+    i1 = (t - nf - ne0) % w1;
+    i0 = (t - nf - ne0) / w1;
+  } else {
+    return false;
+  }
+  P.pc[d] = lk.cplane;
+  P.pc[a0] = lk.lo[a0] + i0;
+  P.pc[a1] = lk.lo[a1] + i1;
+  P.pf[d] = lk.fplane;
+  for (int x = 0; x < 3; x++)
+    if (x != d) P.pf[x] = (P.pc[x] - g + lk.corg[x]) * (1 << ((lk.e >> x) & 1)) - lk.forg[x] + g;
+  return true;
+}
+
+__device__ __forceinline__ int64_t lidx(const BlockInfo& b, const int p[3]) {
+  return ((int64_t)p[2] * b.np[1] + p[1]) * b.np[0] + p[0];
+}
+
+__device__ __forceinline__ int64_t lstride(const BlockInfo& b, int x) {
+  return x == 0 ? 1 : (x == 1 ? (int64_t)b.np[0] : (int64_t)b.np[0] * b.np[1]);
+}
+
+// coarse fluxes on the shared faces <- area mean of the fine fluxes; coarse EMFs on the
+// shared edges <- mean of the fine EMFs along the coarse edge
+__global__ __launch_bounds__(AT) void k_amr_fix(Launch L, const AmrLink* __restrict__ links,
+                                                double* __restrict__ F, double* __restrict__ E) {
+  const AmrLink lk = links[blockIdx.y];
+  const int t = blockIdx.x * AT + threadIdx.x;
+  LinkPos P;
+  if (!link_position(lk, L.ph.ng, t, P)) return;
+  const BlockInfo c = L.blk[lk.coarse], f = L.blk[lk.fine];
+  const int d = lk.d;
+  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
+  const int64_t lc = lidx(c, P.pc), lf = lidx(f, P.pf);
+  if (P.kind == 0) {
+    const int n0 = ((lk.e >> a0) & 1) ? 2 : 1, n1 = ((lk.e >> a1) & 1) ? 2 : 1;
+    const int64_t s0 = lstride(f, a0), s1 = lstride(f, a1);
+    const double inv = 1.0 / (n0 * n1);
+    for (int q = 0; q < 8; q++) {
+      const double* src = F + 24 * f.off + (int64_t)(d * 8 + q) * f.vol + lf;
+      double acc = 0.0;
+      for (int o1 = 0; o1 < n1; o1++)
+        for (int o0 = 0; o0 < n0; o0++) acc += src[o1 * s1 + o0 * s0];
+      F[24 * c.off + (int64_t)(d * 8 + q) * c.vol + lc] = acc * inv;
+    }
+  } else {
+    const int a = P.kind == 1 ? a0 : a1;
+    const int na = ((lk.e >> a) & 1) ? 2 : 1;
+    const int64_t sa = lstride(f, a);
+    const double* src = E + 3 * f.off + (int64_t)a * f.vol + lf;
+    double acc = 0.0;
+    for (int o = 0; o < na; o++) acc += src[o * sa];
+    E[3 * c.off + (int64_t)a * c.vol + lc] = acc * (1.0 / na);
+  }
+}
+
+// coarse copy of the shared faces <- mean of the fine faces
+__global__ __launch_bounds__(AT) void k_amr_bsync(Launch L, const AmrLink* __restrict__ links,
+                                                  double* __restrict__ B) {
+  const AmrLink lk = links[blockIdx.y];
+  const int t = blockIdx.x * AT + threadIdx.x;
+  LinkPos P;
+  if (!link_position(lk, L.ph.ng, t, P) || P.kind != 0) return;
+  const BlockInfo c = L.blk[lk.coarse], f = L.blk[lk.fine];
+  const int d = lk.d;
+  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
+  const int n0 = ((lk.e >> a0) & 1) ? 2 : 1, n1 = ((lk.e >> a1) & 1) ? 2 : 1;
+  const int64_t s0 = lstride(f, a0), s1 = lstride(f, a1);
+  const double* src = B + 3 * f.off + (int64_t)d * f.vol + lidx(f, P.pf);
+  double acc = 0.0;
+  for (int o1 = 0; o1 < n1; o1++)
+    for (int o0 = 0; o0 < n0; o0++) acc += src[o1 * s1 + o0 * s0];
+  B[3 * c.off + (int64_t)d * c.vol + lidx(c, P.pc)] = acc * (1.0 / (n0 * n1));
+}
+
+// ------------------------------------------------------------------ launchers
+
+void launch_amr_cells(const Launch& L, const AmrOp* ops, int64_t nops, const AmrSample* samp,
+                      const double* main, const double* old, const double* cur, double w,
+                      double* dst) {
+  if (nops <= 0) return;
+  k_amr_cells<<<dim3((unsigned)((nops + AT - 1) / AT)), dim3(AT), 0, L.stream>>>(
+      L.blk, L.geo, ops, nops, samp, main, old, cur, w, dst);
+}
+
+void launch_amr_faces(const Launch& L, const AmrOp* ops, int64_t nops, const AmrSample* samp,
+                      const double* main, const double* old, const double* cur, double w,
+                      double* dst, int comp) {
+  if (nops <= 0) return;
+  k_amr_faces<<<dim3((unsigned)((nops + AT - 1) / AT)), dim3(AT), 0, L.stream>>>(
+      L.blk, ops, nops, samp, main, old, cur, w, dst, comp);
+}
+
+void launch_amr_fix(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* F,
+                    double* E) {
+  if (nlinks <= 0 || maxpos <= 0) return;
+  k_amr_fix<<<dim3((unsigned)((maxpos + AT - 1) / AT), (unsigned)nlinks), dim3(AT), 0, L.stream>>>(
+      L, links, F, E);
+}
+
+void launch_amr_bsync(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* B) {
+  if (nlinks <= 0 || maxpos <= 0) return;
+  k_amr_bsync<<<dim3((unsigned)((maxpos + AT - 1) / AT), (unsigned)nlinks), dim3(AT), 0,
+                L.stream>>>(L, links, B);
+}
+
+}  // namespace grmhd

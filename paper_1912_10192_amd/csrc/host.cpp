@@ -131,6 +131,12 @@ int imod(int64_t a, int64_t n) {
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
+struct GeoTable {
+  int32_t l0, l1;            // x1, x2 refinement levels
+  int32_t ti, tj;            // padded extents
+  int64_t base;              // first column
+};
+
 struct Plan {
   grmhd_grid_desc d;
   std::vector<grmhd_block_desc> blocks;
@@ -138,23 +144,37 @@ struct Plan {
   int64_t vtot = 0;          // total padded cells
   int64_t n_interior = 0;
   int32_t max_np[3] = {0, 0, 0}, max_n[3] = {0, 0, 0};
-  int32_t ti = 0, tj = 0;    // geometry table extents
+  int32_t lmax[3] = {0, 0, 0};  // finest refinement level per dimension
+  bool refined = false;         // blocks at more than one refinement level
+  std::vector<GeoTable> tables;
   int64_t ncol = 0;
-  std::vector<int32_t> owner;   // block id per effective cell
+  std::vector<int32_t> owner;   // block id per effective (finest-level) cell
   std::vector<GhostOp> ops[4];  // cells, x1 faces, x2 faces, x3 faces (sorted by dst level)
+  std::vector<AmrOp> aops[4];   // ghost values across refinement levels (sorted likewise)
+  std::vector<AmrSample> samples;
+  std::vector<AmrLink> links;   // refinement faces, sorted by time level
+  int32_t link_maxpos = 0;
   // local time stepping
   int32_t nlev = 1;
   std::vector<int32_t> lev_blocks;             // block ids sorted by level
   std::vector<int64_t> lev_boff;               // offsets into lev_blocks per level (+1)
   std::vector<int64_t> ops_off[4];             // offsets into ops[kind] per level (+1)
+  std::vector<int64_t> aops_off[4];            // offsets into aops[kind] per level (+1)
+  std::vector<int64_t> link_off;               // offsets into links per level (+1)
   std::vector<SyncItem> items;                 // sorted by the slow block's level
   std::vector<int64_t> item_off;               // offsets per level (+1)
   std::vector<int64_t> lev_cells;              // interior cells per level
   int32_t rs = 0, rs2 = 0;                     // register plane size and row stride
   // work-buffer offsets (bytes)
   size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, o_dtp;
+  size_t o_aops[4], o_samp, o_links;
   size_t o_pold, o_bold, o_reg, o_ubuf, o_lev, o_items, total;
 };
+
+// cells of the grid at refinement levels lev along each dimension
+void level_extent(const Plan& p, const int32_t* lev, int64_t N[3]) {
+  for (int k = 0; k < 3; k++) N[k] = (int64_t)p.d.n_eff[k] >> (p.lmax[k] - lev[k]);
+}
 
 int validate(const grmhd_grid_desc* d) {
   if (!d) return fail(GRMHD_EINVAL, "desc is NULL");
@@ -175,8 +195,6 @@ int validate(const grmhd_grid_desc* d) {
     return fail(GRMHD_EUNSUPPORTED, "x2 boundaries must be both polar or both periodic");
   if (d->bc[4] != GRMHD_BC_PERIODIC || d->bc[5] != GRMHD_BC_PERIODIC)
     return fail(GRMHD_EUNSUPPORTED, "x3 boundaries must be periodic");
-  if (d->bc[2] == GRMHD_BC_POLAR && (d->n_eff[2] % 2 != 0 && d->n_eff[2] != 1))
-    return fail(GRMHD_EINVAL, "polar boundary needs an even number of x3 cells");
   if (d->bc[2] == GRMHD_BC_POLAR && d->coords != GRMHD_KS_LOGSPH)
     return fail(GRMHD_EINVAL, "polar boundary needs spherical coordinates");
   if (d->c2p_maxit < 1 || d->c2p_maxit > 62) return fail(GRMHD_EINVAL, "c2p_maxit must be 1..62");
@@ -186,26 +204,39 @@ int validate(const grmhd_grid_desc* d) {
     return fail(GRMHD_EINVAL, "unknown c2p_guess");
   if (d->c2p_guess == GRMHD_GUESS_MLP && !d->mlp_weights)
     return fail(GRMHD_EINVAL, "learned guess needs mlp_weights");
+  int lmax[3] = {0, 0, 0};
+  for (int b = 0; b < d->n_blocks; b++)
+    for (int k = 0; k < 3; k++) {
+      const int l = d->blocks[b].lev[k];
+      if (l < 0 || l > 8) return fail(GRMHD_EINVAL, "block refinement level must be 0..8");
+      lmax[k] = std::max(lmax[k], l);
+    }
   for (int b = 0; b < d->n_blocks; b++) {
     const grmhd_block_desc& bd = d->blocks[b];
     for (int k = 0; k < 3; k++) {
-      if (bd.lev[k] != 0) return fail(GRMHD_EUNSUPPORTED, "refined blocks are not supported");
-      if (bd.n[k] < d->n_ghost && !(bd.n[k] == 1 && d->n_eff[k] == 1))
+      const int s = lmax[k] - bd.lev[k];
+      const int64_t N = (int64_t)d->n_eff[k] >> s;
+      if ((N << s) != d->n_eff[k] || N < 1)
+        return fail(GRMHD_EINVAL, "effective grid not divisible by the refinement ratio");
+      if (bd.n[k] < d->n_ghost && !(bd.n[k] == 1 && N == 1))
         return fail(GRMHD_EINVAL, "block smaller than the ghost width");
-      if (bd.org[k] < 0 || bd.org[k] + bd.n[k] > d->n_eff[k])
-        return fail(GRMHD_EINVAL, "block outside the grid");
+      if (bd.org[k] < 0 || bd.org[k] + bd.n[k] > N) return fail(GRMHD_EINVAL, "block outside the grid");
+      if (k == 2 && d->bc[2] == GRMHD_BC_POLAR && N % 2 != 0 && N != 1)
+        return fail(GRMHD_EINVAL, "polar boundary needs an even number of x3 cells at every level");
     }
     if (bd.lat < 0 || bd.lat >= d->n_lat_levels) return fail(GRMHD_EINVAL, "block lat out of range");
   }
   return GRMHD_OK;
 }
 
-// Composition of the physical boundary rules for a position outside the grid, applied
-// x3 first, then x2, then x1 (the order in which ghost layers are filled, so that edge
-// and corner ghosts take their values from already-filled layers).  kind 0 = cell,
-// 1..3 = face of that component.  Returns false if the value is identically zero.
-bool compose(const grmhd_grid_desc& d, int kind, int64_t& i, int64_t& j, int64_t& k, int& flags) {
-  const int64_t N1 = d.n_eff[0], N2 = d.n_eff[1], N3 = d.n_eff[2];
+// Composition of the physical boundary rules for a position outside the grid of extents
+// N (one refinement level), applied x3 first, then x2, then x1 (the order in which ghost
+// layers are filled, so that edge and corner ghosts take their values from
+// already-filled layers).  kind 0 = cell, 1..3 = face of that component.  Returns false
+// if the value is identically zero.
+bool compose(const grmhd_grid_desc& d, const int64_t N[3], int kind, int64_t& i, int64_t& j,
+             int64_t& k, int& flags) {
+  const int64_t N1 = N[0], N2 = N[1], N3 = N[2];
   flags = 0;
   // x3: periodic
   if (kind == 3) {
@@ -253,6 +284,346 @@ bool compose(const grmhd_grid_desc& d, int kind, int64_t& i, int64_t& j, int64_t
   return true;
 }
 
+// the block owning the cell (i, j, k) of the grid at refinement levels lev
+int owner_at(const Plan& p, const int32_t* lev, int64_t i, int64_t j, int64_t k) {
+  const int64_t N1 = p.d.n_eff[0], N2 = p.d.n_eff[1];
+  i <<= (p.lmax[0] - lev[0]);
+  j <<= (p.lmax[1] - lev[1]);
+  k <<= (p.lmax[2] - lev[2]);
+  return p.owner[(size_t)((k * N2 + j) * N1 + i)];
+}
+
+int32_t local_index(const BlockInfo& bi, int64_t li, int64_t lj, int64_t lk) {
+  return (int32_t)((lk * bi.np[1] + lj) * bi.np[0] + li);
+}
+
+// Refinement of block o relative to levels lev: +1 finer, -1 coarser per dimension.
+// Returns 0 same level, 1 finer by one level (in some dimensions), -1 coarser by one,
+// 2 anything else (a jump of more than one level, or finer and coarser mixed).
+int relation(const Plan& p, int o, const int32_t* lev, int r[3]) {
+  int up = 0, down = 0;
+  for (int k = 0; k < 3; k++) {
+    r[k] = p.blocks[o].lev[k] - lev[k];
+    if (r[k] > 1 || r[k] < -1) return 2;
+    if (r[k] > 0) up = 1;
+    if (r[k] < 0) down = 1;
+  }
+  if (up && down) return 2;
+  return up ? 1 : (down ? -1 : 0);
+}
+
+int time_flags(const Plan& p, int src, int viewer) {
+  if (p.blocks[src].lat > p.blocks[viewer].lat) return GF_SLOW;
+  if (p.blocks[src].lat < p.blocks[viewer].lat) return GF_FAST;
+  return 0;
+}
+
+// Of the blocks holding a copy of face (i, j, k) of component kind at levels lev (the
+// cells on either side of it), the one a viewing block reads: itself, else the finest,
+// then one at the viewer's time level, then the one listed last.
+int face_owner(const Plan& p, const int32_t* lev, const int64_t N[3], int kind, int64_t i,
+               int64_t j, int64_t k, int viewer) {
+  const int d = kind - 1;
+  int cand[2];
+  int nc = 0;
+  int64_t q[3] = {i, j, k};
+  if (q[d] < N[d]) cand[nc++] = owner_at(p, lev, q[0], q[1], q[2]);
+  q[d] -= 1;
+  if (q[d] >= 0) cand[nc++] = owner_at(p, lev, q[0], q[1], q[2]);
+  int best = cand[0];
+  for (int c = 0; c < nc; c++) {
+    const int o = cand[c];
+    if (o == viewer) return viewer;
+    auto key = [&](int b) {
+      const grmhd_block_desc& bd = p.blocks[b];
+      return std::make_tuple(bd.lev[0] + bd.lev[1] + bd.lev[2],
+                             bd.lat == p.blocks[viewer].lat ? 1 : 0, b);
+    };
+    if (key(o) > key(best)) best = o;
+  }
+  return best;
+}
+
+struct Resolver {
+  Plan& p;
+  int viewer;
+  std::string err;
+
+  // a cell value at position (i, j, k) of levels lev (inside the grid after the
+  // boundary composition, with its flags): the owning block's own cell, or the
+  // restriction of a finer owner; a coarser owner is an error
+  bool cell_sample(const int32_t* lev, int64_t i, int64_t j, int64_t k, int flags, AmrSample& s) {
+    const int o = owner_at(p, lev, i, j, k);
+    int r[3];
+    const int rel = relation(p, o, lev, r);
+    const grmhd_block_desc& od = p.blocks[o];
+    const BlockInfo& oi = p.info[o];
+    const int g = p.d.n_ghost;
+    s.blkf = o | ((flags | time_flags(p, o, viewer)) << 24);
+    s.pad = 0;
+    if (rel == 0) {
+      s.loc = local_index(oi, i - od.org[0] + g, j - od.org[1] + g, k - od.org[2] + g);
+      s.mask = 0;
+      return true;
+    }
+    if (rel != 1) {
+      err = "a refinement stencil reaches a block two levels away or a coarser block";
+      return false;
+    }
+    const int64_t fi = i << r[0], fj = j << r[1], fk = k << r[2];
+    const int64_t li = fi - od.org[0], lj = fj - od.org[1], lk = fk - od.org[2];
+    if (li < 0 || lj < 0 || lk < 0 || li + r[0] >= od.n[0] || lj + r[1] >= od.n[1] ||
+        lk + r[2] >= od.n[2]) {
+      err = "refined blocks must start and end on coarse cell boundaries";
+      return false;
+    }
+    s.loc = local_index(oi, li + g, lj + g, lk + g);
+    s.mask = r[0] | (r[1] << 1) | (r[2] << 2);
+    return true;
+  }
+
+  // a face value of component kind at position (i, j, k) of levels lev, after the
+  // boundary composition (zero: a polar-axis face)
+  bool face_sample(const int32_t* lev, const int64_t N[3], int kind, int64_t i, int64_t j,
+                   int64_t k, bool zero, int flags, AmrSample& s) {
+    s.pad = 0;
+    if (zero) {
+      s.blkf = viewer | (GF_ZERO << 24);
+      s.loc = 0;
+      s.mask = 0;
+      return true;
+    }
+    const int d = kind - 1;
+    const int o = face_owner(p, lev, N, kind, i, j, k, viewer);
+    int r[3];
+    const int rel = relation(p, o, lev, r);
+    const grmhd_block_desc& od = p.blocks[o];
+    const BlockInfo& oi = p.info[o];
+    const int g = p.d.n_ghost;
+    s.blkf = o | ((flags | time_flags(p, o, viewer)) << 24);
+    if (rel == 0) {
+      s.loc = local_index(oi, i - od.org[0] + g, j - od.org[1] + g, k - od.org[2] + g);
+      s.mask = 0;
+      return true;
+    }
+    if (rel != 1) {
+      err = "a refinement stencil reaches a block two levels away or a coarser block";
+      return false;
+    }
+    const int64_t li = (i << r[0]) - od.org[0], lj = (j << r[1]) - od.org[1],
+                  lk = (k << r[2]) - od.org[2];
+    const int64_t lq[3] = {li, lj, lk};
+    for (int x = 0; x < 3; x++) {
+      const bool bad = x == d ? (lq[x] < 0 || lq[x] > od.n[x]) : (lq[x] < 0 || lq[x] + r[x] >= od.n[x]);
+      if (bad) {
+        err = "refined blocks must start and end on coarse cell boundaries";
+        return false;
+      }
+    }
+    s.loc = local_index(oi, li + g, lj + g, lk + g);
+    s.mask = (r[0] | (r[1] << 1) | (r[2] << 2)) & ~(1 << d);
+    return true;
+  }
+};
+
+int build_ops(Plan& p) {
+  const int g = p.d.n_ghost;
+  const int nb = p.d.n_blocks;
+  for (int kind = 0; kind < 4; kind++) {
+    p.ops[kind].clear();
+    p.aops[kind].clear();
+  }
+  p.samples.clear();
+  const bool polar = p.d.bc[2] == GRMHD_BC_POLAR;
+  for (int b = 0; b < nb; b++) {
+    const BlockInfo& bi = p.info[b];
+    const grmhd_block_desc& bd = p.blocks[b];
+    Resolver R{p, b, std::string()};
+    int64_t N[3];
+    level_extent(p, bd.lev, N);
+    for (int kind = 0; kind < 4; kind++) {
+      for (int K = 0; K < bi.np[2]; K++)
+        for (int J = 0; J < bi.np[1]; J++)
+          for (int I = 0; I < bi.np[0]; I++) {
+            const int L3[3] = {I, J, K};
+            bool ghost = false;
+            for (int dd = 0; dd < 3; dd++) {
+              const int hi = (kind == dd + 1) ? g + bi.n[dd] : g + bi.n[dd] - 1;
+              if (L3[dd] < g || L3[dd] > hi) ghost = true;
+            }
+            if (!ghost) continue;
+            int64_t gi = bd.org[0] + I - g, gj = bd.org[1] + J - g, gk = bd.org[2] + K - g;
+            const bool across_pole = polar && (kind == 2 ? (gj < 0 || gj > N[1]) : (gj < 0 || gj >= N[1]));
+            int flags = 0;
+            const bool nz = compose(p.d, N, kind, gi, gj, gk, flags);
+            const int32_t dst_loc = local_index(bi, I, J, K);
+            if (!nz) {   // a polar-axis face: identically zero, no source
+              GhostOp op{b, dst_loc, b | (GF_ZERO << 24), 0};
+              p.ops[kind].push_back(op);
+              continue;
+            }
+            // the block this value comes from at the block's own level
+            const int src = kind == 0 ? owner_at(p, bd.lev, gi, gj, gk)
+                                      : face_owner(p, bd.lev, N, kind, gi, gj, gk, b);
+            int r[3];
+            const int rel = relation(p, src, bd.lev, r);
+            if (rel == 2) return fail(GRMHD_EINVAL, "neighbouring blocks differ by more than one refinement level");
+            if (rel != 0 && across_pole)
+              return fail(GRMHD_EUNSUPPORTED, "refinement jumps across the polar axis are not supported");
+            if (rel == 0) {
+              const grmhd_block_desc& sd = p.blocks[src];
+              const BlockInfo& si = p.info[src];
+              GhostOp op;
+              op.dst_blk = b;
+              op.dst_loc = dst_loc;
+              op.src_blkf = src | ((flags | time_flags(p, src, b)) << 24);
+              op.src_loc = local_index(si, gi - sd.org[0] + g, gj - sd.org[1] + g, gk - sd.org[2] + g);
+              p.ops[kind].push_back(op);
+              continue;
+            }
+            AmrOp op;
+            op.dst_blk = b;
+            op.dst_loc = dst_loc;
+            op.samp = (int32_t)p.samples.size();
+            op.mode = flags << AM_FLAGS_SHIFT;
+            AmrSample s;
+            if (rel == 1) {   // restriction of a finer neighbour
+              const bool ok = kind == 0 ? R.cell_sample(bd.lev, gi, gj, gk, 0, s)
+                                        : R.face_sample(bd.lev, N, kind, gi, gj, gk, false, 0, s);
+              if (!ok) return fail(GRMHD_EINVAL, R.err);
+              p.samples.push_back(s);
+              p.aops[kind].push_back(op);
+              continue;
+            }
+            // prolongation from a coarser neighbour at levels mu
+            const int32_t mu[3] = {bd.lev[0] + r[0], bd.lev[1] + r[1], bd.lev[2] + r[2]};
+            int64_t M[3];
+            level_extent(p, mu, M);
+            const int pr[3] = {-r[0], -r[1], -r[2]};
+            const int64_t q[3] = {gi, gj, gk};
+            int64_t c[3];
+            for (int x = 0; x < 3; x++) {
+              c[x] = q[x] >> pr[x];
+              if (pr[x]) op.mode |= 1 << x;
+            }
+            if (kind == 0) {
+              for (int x = 0; x < 3; x++)
+                if (pr[x] && (q[x] & 1)) op.mode |= 1 << (AM_UPPER_SHIFT + x);
+              if (!R.cell_sample(mu, c[0], c[1], c[2], 0, s)) return fail(GRMHD_EINVAL, R.err);
+              p.samples.push_back(s);
+              for (int x = 0; x < 3; x++) {
+                if (!pr[x]) continue;
+                for (int sg = -1; sg <= 1; sg += 2) {
+                  int64_t t[3] = {c[0], c[1], c[2]};
+                  t[x] += sg;
+                  int fl = 0;
+                  compose(p.d, M, 0, t[0], t[1], t[2], fl);
+                  if (!R.cell_sample(mu, t[0], t[1], t[2], fl, s)) return fail(GRMHD_EINVAL, R.err);
+                  p.samples.push_back(s);
+                }
+              }
+            } else {
+              const int d = kind - 1;
+              for (int x = 0; x < 3; x++)
+                if (x != d && pr[x] && (q[x] & 1)) op.mode |= 1 << (AM_UPPER_SHIFT + x);
+              const bool two = pr[d] && (q[d] & 1);
+              if (two) op.mode |= AM_TWO;
+              const int nst = two ? 2 : 1;
+              for (int st = 0; st < nst; st++) {
+                int64_t f0[3] = {c[0], c[1], c[2]};
+                if (pr[d]) f0[d] = (q[d] >> 1) + st;   // the coarse faces bounding the cut cell
+                else f0[d] = q[d];
+                for (int m = -1; m < 6; m++) {
+                  // m = -1: the coarse face; then (minus, plus) per prolonged transverse dim
+                  int x = -1, sg = 0;
+                  if (m >= 0) {
+                    x = m / 2;
+                    sg = (m & 1) ? 1 : -1;
+                    if (x == d || !pr[x]) continue;
+                  }
+                  int64_t t[3] = {f0[0], f0[1], f0[2]};
+                  if (x >= 0) t[x] += sg;
+                  int fl = 0;
+                  const bool fz = !compose(p.d, M, kind, t[0], t[1], t[2], fl);
+                  if (!R.face_sample(mu, M, kind, t[0], t[1], t[2], fz, fl, s))
+                    return fail(GRMHD_EINVAL, R.err);
+                  p.samples.push_back(s);
+                }
+              }
+            }
+            p.aops[kind].push_back(op);
+          }
+    }
+  }
+  if (p.samples.size() >= (size_t(1) << 31)) return fail(GRMHD_EINVAL, "too many refinement samples");
+  return GRMHD_OK;
+}
+
+// faces shared by a coarse block and a block one level finer
+int build_links(Plan& p) {
+  const int g = p.d.n_ghost;
+  const int nb = p.d.n_blocks;
+  p.links.clear();
+  p.link_maxpos = 0;
+  if (!p.refined) return GRMHD_OK;
+  const bool per[3] = {p.d.bc[0] == GRMHD_BC_PERIODIC, p.d.bc[2] == GRMHD_BC_PERIODIC, true};
+  for (int c = 0; c < nb; c++) {
+    const grmhd_block_desc& bc = p.blocks[c];
+    int64_t Nc[3];
+    level_extent(p, bc.lev, Nc);
+    for (int f = 0; f < nb; f++) {
+      const grmhd_block_desc& bf = p.blocks[f];
+      int e[3], emask = 0, ok = 1;
+      for (int x = 0; x < 3; x++) {
+        e[x] = bf.lev[x] - bc.lev[x];
+        if (e[x] < 0 || e[x] > 1) ok = 0;
+        emask |= (e[x] == 1 ? 1 : 0) << x;
+      }
+      if (!ok || !emask) continue;
+      int64_t lo_f[3], hi_f[3], lo_c[3], hi_c[3];
+      for (int x = 0; x < 3; x++) {
+        lo_f[x] = bf.org[x] >> e[x];
+        hi_f[x] = (bf.org[x] + bf.n[x]) >> e[x];
+        lo_c[x] = bc.org[x];
+        hi_c[x] = bc.org[x] + bc.n[x];
+      }
+      for (int d = 0; d < 3; d++) {
+        bool overlap = true;
+        for (int x = 0; x < 3; x++)
+          if (x != d && std::max(lo_f[x], lo_c[x]) >= std::min(hi_f[x], hi_c[x])) overlap = false;
+        if (!overlap) continue;
+        const bool below = hi_f[d] == lo_c[d] || (per[d] && lo_c[d] == 0 && hi_f[d] == Nc[d]);
+        const bool above = hi_c[d] == lo_f[d] || (per[d] && lo_f[d] == 0 && hi_c[d] == Nc[d]);
+        for (int side = 0; side < 2; side++) {
+          if (!(side == 0 ? below : above)) continue;
+          if (bc.lat != bf.lat)
+            return fail(GRMHD_EUNSUPPORTED, "blocks across a refinement face must share a time level");
+          AmrLink L;
+          L.coarse = c;
+          L.fine = f;
+          L.d = d;
+          L.e = emask;
+          for (int x = 0; x < 3; x++) {
+            L.lo[x] = (int32_t)(std::max(lo_f[x], lo_c[x]) - bc.org[x] + g);
+            L.hi[x] = (int32_t)(std::min(hi_f[x], hi_c[x]) - bc.org[x] + g);
+            L.corg[x] = (int32_t)bc.org[x];
+            L.forg[x] = (int32_t)bf.org[x];
+          }
+          L.cplane = side == 0 ? g : g + bc.n[d];
+          L.fplane = side == 0 ? g + bf.n[d] : g;
+          const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
+          const int w0 = L.hi[a0] - L.lo[a0], w1 = L.hi[a1] - L.lo[a1];
+          L.npos = w0 * w1 + w0 * (w1 + 1) + w1 * (w0 + 1);
+          L.pad = 0;
+          p.link_maxpos = std::max(p.link_maxpos, L.npos);
+          p.links.push_back(L);
+        }
+      }
+    }
+  }
+  return GRMHD_OK;
+}
+
 int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
   int rc = validate(desc);
   if (rc) return rc;
@@ -261,113 +632,82 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
   p.d.blocks = nullptr;
   const int g = desc->n_ghost;
   const int nb = desc->n_blocks;
+  for (int k = 0; k < 3; k++) p.lmax[k] = 0;
+  for (int b = 0; b < nb; b++)
+    for (int k = 0; k < 3; k++) p.lmax[k] = std::max(p.lmax[k], p.blocks[b].lev[k]);
+  p.refined = false;
+  for (int b = 0; b < nb; b++)
+    for (int k = 0; k < 3; k++)
+      if (p.blocks[b].lev[k] != p.lmax[k]) p.refined = true;
+  // the list sizes of a refined grid are only known once the lists are built
+  if (p.refined) with_maps = true;
+  // one geometry table per (x1, x2) level pair
+  p.tables.clear();
+  p.ncol = 0;
   p.info.resize(nb);
   int64_t off = 0;
+  p.n_interior = 0;
   for (int b = 0; b < nb; b++) {
     BlockInfo& bi = p.info[b];
     const grmhd_block_desc& bd = p.blocks[b];
+    int64_t N[3];
+    level_extent(p, bd.lev, N);
+    int t = -1;
+    for (size_t q = 0; q < p.tables.size(); q++)
+      if (p.tables[q].l0 == bd.lev[0] && p.tables[q].l1 == bd.lev[1]) t = (int)q;
+    if (t < 0) {
+      GeoTable T;
+      T.l0 = bd.lev[0];
+      T.l1 = bd.lev[1];
+      T.ti = (int32_t)(N[0] + 2 * g + 1);
+      T.tj = (int32_t)(N[1] + 2 * g + 1);
+      T.base = p.ncol;
+      p.ncol += (int64_t)T.ti * T.tj;
+      p.tables.push_back(T);
+      t = (int)p.tables.size() - 1;
+    }
     bi.off = off;
     for (int k = 0; k < 3; k++) {
       bi.n[k] = bd.n[k];
       bi.np[k] = bd.n[k] + 2 * g + 1;
       p.max_np[k] = std::max(p.max_np[k], bi.np[k]);
       p.max_n[k] = std::max(p.max_n[k], bi.n[k]);
+      bi.dx[k] = (desc->xmax[k] - desc->xmin[k]) / (double)N[k];
     }
     bi.gorg[0] = (int32_t)bd.org[0];
     bi.gorg[1] = (int32_t)bd.org[1];
     bi.gorg[2] = (int32_t)bd.org[2];
     bi.vol = bi.np[0] * bi.np[1] * bi.np[2];
     bi.lat = bd.lat;
-    bi.pad = 0;
+    bi.gti = p.tables[t].ti;
+    bi.gbase = p.tables[t].base;
     off += bi.vol;
     p.n_interior += (int64_t)bd.n[0] * bd.n[1] * bd.n[2];
   }
   p.vtot = off;
   if (p.vtot * 5 >= (int64_t(1) << 31) * 4) return fail(GRMHD_EINVAL, "grid too large");
-  p.ti = desc->n_eff[0] + 2 * g + 1;
-  p.tj = desc->n_eff[1] + 2 * g + 1;
-  p.ncol = (int64_t)p.ti * p.tj;
   // ownership of effective cells; every cell must be covered exactly once
   const int64_t N1 = desc->n_eff[0], N2 = desc->n_eff[1], N3 = desc->n_eff[2];
-  if (p.n_interior != N1 * N2 * N3) return fail(GRMHD_EINVAL, "blocks do not tile the grid");
+  if (N1 * N2 * N3 > (int64_t(1) << 31)) return fail(GRMHD_EINVAL, "effective grid too large");
   p.owner.assign((size_t)(N1 * N2 * N3), -1);
+  int64_t covered = 0;
   for (int b = 0; b < nb; b++) {
     const grmhd_block_desc& bd = p.blocks[b];
-    for (int64_t k = bd.org[2]; k < bd.org[2] + bd.n[2]; k++)
-      for (int64_t j = bd.org[1]; j < bd.org[1] + bd.n[1]; j++)
-        for (int64_t i = bd.org[0]; i < bd.org[0] + bd.n[0]; i++) {
+    const int s0 = p.lmax[0] - bd.lev[0], s1 = p.lmax[1] - bd.lev[1], s2 = p.lmax[2] - bd.lev[2];
+    for (int64_t k = bd.org[2] << s2; k < (bd.org[2] + bd.n[2]) << s2; k++)
+      for (int64_t j = bd.org[1] << s1; j < (bd.org[1] + bd.n[1]) << s1; j++)
+        for (int64_t i = bd.org[0] << s0; i < (bd.org[0] + bd.n[0]) << s0; i++) {
           int32_t& o = p.owner[(size_t)((k * N2 + j) * N1 + i)];
           if (o != -1) return fail(GRMHD_EINVAL, "blocks overlap");
           o = b;
+          covered++;
         }
   }
+  if (covered != N1 * N2 * N3) return fail(GRMHD_EINVAL, "blocks do not tile the grid");
   if (with_maps) {
-    for (int kind = 0; kind < 4; kind++) p.ops[kind].clear();
-    for (int b = 0; b < nb; b++) {
-      const BlockInfo& bi = p.info[b];
-      const grmhd_block_desc& bd = p.blocks[b];
-      for (int kind = 0; kind < 4; kind++) {
-        for (int K = 0; K < bi.np[2]; K++)
-          for (int J = 0; J < bi.np[1]; J++)
-            for (int I = 0; I < bi.np[0]; I++) {
-              const int L3[3] = {I, J, K};
-              bool ghost = false;
-              for (int dd = 0; dd < 3; dd++) {
-                const int hi = (kind == dd + 1) ? g + bi.n[dd] : g + bi.n[dd] - 1;
-                if (L3[dd] < g || L3[dd] > hi) ghost = true;
-              }
-              if (!ghost) continue;
-              int64_t gi = bd.org[0] + I - g, gj = bd.org[1] + J - g, gk = bd.org[2] + K - g;
-              int flags = 0;
-              const bool nz = compose(p.d, kind, gi, gj, gk, flags);
-              GhostOp op;
-              op.dst_blk = b;
-              op.dst_loc = (int32_t)(((int64_t)K * bi.np[1] + J) * bi.np[0] + I);
-              if (!nz) {   // a polar-axis face: identically zero, no source
-                op.src_blkf = b | (GF_ZERO << 24);
-                op.src_loc = 0;
-                p.ops[kind].push_back(op);
-                continue;
-              }
-              // the source cell owning this position (a face at the upper grid edge
-              // belongs to the last cell)
-              int64_t ci = gi, cj = gj, ck = gk;
-              if (kind == 1 && ci == N1) ci = N1 - 1;
-              if (kind == 2 && cj == N2) cj = N2 - 1;
-              if (kind == 3 && ck == N3) ck = N3 - 1;
-              int sb = p.owner[(size_t)((ck * N2 + cj) * N1 + ci)];
-              // A face strictly inside the grid on a boundary between two blocks has two
-              // copies; take this block's own, else the copy of the block at this block's
-              // time level, else the block whose cell has it as its lower face.
-              if (kind > 0) {
-                const int64_t f = kind == 1 ? gi : (kind == 2 ? gj : gk);
-                const int64_t Nf = kind == 1 ? N1 : (kind == 2 ? N2 : N3);
-                if (f > 0 && f < Nf) {
-                  int64_t di = gi, dj = gj, dk = gk;
-                  if (kind == 1) di--;
-                  if (kind == 2) dj--;
-                  if (kind == 3) dk--;
-                  const int db = p.owner[(size_t)((dk * N2 + dj) * N1 + di)];
-                  if (db != sb) {
-                    const int lt = bd.lat;
-                    const bool use_d = db == b || (sb != b && p.blocks[sb].lat != lt &&
-                                                   p.blocks[db].lat == lt);
-                    if (use_d) sb = db;
-                  }
-                }
-              }
-              const grmhd_block_desc& sd = p.blocks[sb];
-              const BlockInfo& si = p.info[sb];
-              const int64_t li = gi - sd.org[0] + g, lj = gj - sd.org[1] + g, lk = gk - sd.org[2] + g;
-              if (p.blocks[sb].lat > bd.lat) flags |= GF_SLOW;
-              if (p.blocks[sb].lat < bd.lat) flags |= GF_FAST;
-              op.src_blkf = sb | (flags << 24);
-              op.src_loc = (int32_t)((lk * si.np[1] + lj) * si.np[0] + li);
-              p.ops[kind].push_back(op);
-            }
-      }
-    }
+    if ((rc = build_ops(p))) return rc;
   }
+  if ((rc = build_links(p))) return rc;
   // local time stepping tables
   p.nlev = desc->n_lat_levels;
   {
@@ -393,15 +733,31 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
         p.ops_off[kind].assign(L + 1, 0);
         for (const GhostOp& op : p.ops[kind]) p.ops_off[kind][p.blocks[op.dst_blk].lat + 1]++;
         for (int l = 0; l < L; l++) p.ops_off[kind][l + 1] += p.ops_off[kind][l];
+        std::stable_sort(p.aops[kind].begin(), p.aops[kind].end(),
+                         [&](const AmrOp& a, const AmrOp& c) {
+                           return p.blocks[a.dst_blk].lat < p.blocks[c.dst_blk].lat;
+                         });
+        p.aops_off[kind].assign(L + 1, 0);
+        for (const AmrOp& op : p.aops[kind]) p.aops_off[kind][p.blocks[op.dst_blk].lat + 1]++;
+        for (int l = 0; l < L; l++) p.aops_off[kind][l + 1] += p.aops_off[kind][l];
       }
     }
+    std::stable_sort(p.links.begin(), p.links.end(), [&](const AmrLink& a, const AmrLink& c) {
+      return p.blocks[a.coarse].lat < p.blocks[c.coarse].lat;
+    });
+    p.link_off.assign(L + 1, 0);
+    for (const AmrLink& lk : p.links) p.link_off[p.blocks[lk.coarse].lat + 1]++;
+    for (int l = 0; l < L; l++) p.link_off[l + 1] += p.link_off[l];
     // neighbour checks: every block within one cell of a block (through the physical
-    // boundaries) differs by at most one level; x2 and x3 face neighbours share a level;
-    // x1 neighbours at another level cover the same x2-x3 extent
+    // boundaries) differs by at most one time level; x2 and x3 face neighbours share a
+    // time level; x1 neighbours at another time level have the same refinement level and
+    // cover the same x2-x3 extent
     p.items.clear();
     if (L > 1) {
       for (int b = 0; b < nb; b++) {
         const grmhd_block_desc& bd = p.blocks[b];
+        int64_t N[3];
+        level_extent(p, bd.lev, N);
         for (int dk = -1; dk <= 1; dk++)
           for (int dj = -1; dj <= 1; dj++)
             for (int di = -1; di <= 1; di++) {
@@ -411,16 +767,18 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
               int64_t gj = dj < 0 ? bd.org[1] - 1 : (dj > 0 ? bd.org[1] + bd.n[1] : bd.org[1] + bd.n[1] / 2);
               int64_t gk = dk < 0 ? bd.org[2] - 1 : (dk > 0 ? bd.org[2] + bd.n[2] : bd.org[2] + bd.n[2] / 2);
               int fl = 0;
-              compose(p.d, 0, gi, gj, gk, fl);
-              const int nbk = p.owner[(size_t)((gk * N2 + gj) * N1 + gi)];
+              compose(p.d, N, 0, gi, gj, gk, fl);
+              const int nbk = owner_at(p, bd.lev, gi, gj, gk);
               const int dl = p.blocks[nbk].lat - bd.lat;
               if (dl > 1 || dl < -1) return fail(GRMHD_EINVAL, "neighbouring time levels differ by more than one");
               if (!di && (dj || dk) && (!dj || !dk) && dl != 0)
                 return fail(GRMHD_EUNSUPPORTED, "time-level interfaces must lie on x1 block faces");
               if (di && !dj && !dk && dl == -1) {
                 const grmhd_block_desc& fd = p.blocks[nbk];
-                if (fd.org[1] != bd.org[1] || fd.org[2] != bd.org[2] || fd.n[1] != bd.n[1] || fd.n[2] != bd.n[2])
-                  return fail(GRMHD_EUNSUPPORTED, "x1 neighbours at another time level must match in x2, x3");
+                if (fd.org[1] != bd.org[1] || fd.org[2] != bd.org[2] || fd.n[1] != bd.n[1] ||
+                    fd.n[2] != bd.n[2] || fd.lev[0] != bd.lev[0] || fd.lev[1] != bd.lev[1] ||
+                    fd.lev[2] != bd.lev[2])
+                  return fail(GRMHD_EUNSUPPORTED, "x1 neighbours at another time level must match in x2, x3 and refinement");
                 SyncItem it;
                 it.slow = b;
                 it.fast = nbk;
@@ -465,7 +823,10 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
       }
     }
     p.o_ops[kind] = take(count * sizeof(GhostOp));
+    p.o_aops[kind] = take(p.aops[kind].size() * sizeof(AmrOp));
   }
+  p.o_samp = take(p.samples.size() * sizeof(AmrSample));
+  p.o_links = take(p.links.size() * sizeof(AmrLink));
   p.o_cnt = take(sizeof(Counters));
   const bool lat = p.nlev > 1;
   p.o_pold = take(lat ? 5 * V * 8 : 0);
@@ -490,8 +851,6 @@ void build_geometry(const Plan& p, std::vector<double>& gc, std::vector<double>&
                     std::vector<double>& g2) {
   const grmhd_grid_desc& d = p.d;
   const int g = d.n_ghost;
-  const double dx1 = (d.xmax[0] - d.xmin[0]) / d.n_eff[0];
-  const double dx2 = (d.xmax[1] - d.xmin[1]) / d.n_eff[1];
   const bool polar = d.bc[2] == GRMHD_BC_POLAR;
   gc.assign((size_t)NGEO_C * p.ncol, 0.0);
   g1.assign((size_t)NGEO_F * p.ncol, 0.0);
@@ -502,28 +861,35 @@ void build_geometry(const Plan& p, std::vector<double>& gc, std::vector<double>&
     return x2;
   };
   double tmp[NGEO_F], conn[40];
-  for (int J = 0; J < p.tj; J++)
-    for (int I = 0; I < p.ti; I++) {
-      const int64_t col = (int64_t)J * p.ti + I;
-      const double x1c = d.xmin[0] + (I - g + 0.5) * dx1, x1f = d.xmin[0] + (I - g) * dx1;
-      const double x2c = d.xmin[1] + (J - g + 0.5) * dx2, x2f = d.xmin[1] + (J - g) * dx2;
-      geometry_point(d.coords, d.spin_a, x1c, mirror(x2c), tmp, conn);
-      for (int q = 0; q < NGEO_F; q++) gc[q * p.ncol + col] = tmp[q];
-      for (int q = 0; q < 40; q++) gc[(CONN0 + q) * p.ncol + col] = conn[q];
-      const double r = d.coords == GRMHD_KS_LOGSPH ? std::exp(x1c) : 1.0;
-      gc[RHOFL * p.ncol + col] = d.rho_fl_c * std::pow(r, d.rho_fl_p);
-      gc[UFL * p.ncol + col] = d.u_fl_c * std::pow(r, d.u_fl_p);
-      geometry_point(d.coords, d.spin_a, x1f, mirror(x2c), tmp, nullptr);
-      for (int q = 0; q < NGEO_F; q++) g1[q * p.ncol + col] = tmp[q];
-      const bool axis = polar && (J == g || J == g + d.n_eff[1]);
-      if (axis) {
-        for (int q = 0; q < NGEO_F; q++) g2[q * p.ncol + col] = 0.0;   // sqrt(-g) = 0 on the axis
-        g2[ALPHA * p.ncol + col] = 1.0;
-      } else {
-        geometry_point(d.coords, d.spin_a, x1c, mirror(x2f), tmp, nullptr);
-        for (int q = 0; q < NGEO_F; q++) g2[q * p.ncol + col] = tmp[q];
+  for (const GeoTable& T : p.tables) {
+    const int32_t lev[3] = {T.l0, T.l1, p.lmax[2]};
+    int64_t N[3];
+    level_extent(p, lev, N);
+    const double dx1 = (d.xmax[0] - d.xmin[0]) / (double)N[0];
+    const double dx2 = (d.xmax[1] - d.xmin[1]) / (double)N[1];
+    for (int J = 0; J < T.tj; J++)
+      for (int I = 0; I < T.ti; I++) {
+        const int64_t col = T.base + (int64_t)J * T.ti + I;
+        const double x1c = d.xmin[0] + (I - g + 0.5) * dx1, x1f = d.xmin[0] + (I - g) * dx1;
+        const double x2c = d.xmin[1] + (J - g + 0.5) * dx2, x2f = d.xmin[1] + (J - g) * dx2;
+        geometry_point(d.coords, d.spin_a, x1c, mirror(x2c), tmp, conn);
+        for (int q = 0; q < NGEO_F; q++) gc[q * p.ncol + col] = tmp[q];
+        for (int q = 0; q < 40; q++) gc[(CONN0 + q) * p.ncol + col] = conn[q];
+        const double r = d.coords == GRMHD_KS_LOGSPH ? std::exp(x1c) : 1.0;
+        gc[RHOFL * p.ncol + col] = d.rho_fl_c * std::pow(r, d.rho_fl_p);
+        gc[UFL * p.ncol + col] = d.u_fl_c * std::pow(r, d.u_fl_p);
+        geometry_point(d.coords, d.spin_a, x1f, mirror(x2c), tmp, nullptr);
+        for (int q = 0; q < NGEO_F; q++) g1[q * p.ncol + col] = tmp[q];
+        const bool axis = polar && (J == g || J == g + N[1]);
+        if (axis) {
+          for (int q = 0; q < NGEO_F; q++) g2[q * p.ncol + col] = 0.0;   // sqrt(-g) = 0 on the axis
+          g2[ALPHA * p.ncol + col] = 1.0;
+        } else {
+          geometry_point(d.coords, d.spin_a, x1c, mirror(x2f), tmp, nullptr);
+          for (int q = 0; q < NGEO_F; q++) g2[q * p.ncol + col] = tmp[q];
+        }
       }
-    }
+  }
 }
 
 }  // namespace
@@ -544,6 +910,10 @@ struct grmhd_ctx {
   double *ps, *balt, *bc, *f, *e, *dtp;
   GhostOp* ops[4];
   int64_t nops[4];
+  AmrOp* aops[4];
+  int64_t naops[4];
+  AmrSample* samp = nullptr;
+  AmrLink* links = nullptr;
   bool b_in_alt = false;
   const void* mlp = nullptr;   // packed MLP blob when the learned guess is on
   // local time stepping
@@ -631,12 +1001,19 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   for (int kind = 0; kind < 4; kind++) {
     c->ops[kind] = (GhostOp*)(w + p.o_ops[kind]);
     c->nops[kind] = (int64_t)p.ops[kind].size();
-    if ((rc = up(p.o_ops[kind], p.ops[kind].data(), p.ops[kind].size() * sizeof(GhostOp)))) {
+    c->aops[kind] = (AmrOp*)(w + p.o_aops[kind]);
+    c->naops[kind] = (int64_t)p.aops[kind].size();
+    if ((rc = up(p.o_ops[kind], p.ops[kind].data(), p.ops[kind].size() * sizeof(GhostOp))) ||
+        (rc = up(p.o_aops[kind], p.aops[kind].data(), p.aops[kind].size() * sizeof(AmrOp)))) {
       delete c;
       return rc;
     }
   }
-  if ((rc = up(p.o_lev, p.lev_blocks.data(), p.lev_blocks.size() * sizeof(int32_t))) ||
+  c->samp = (AmrSample*)(w + p.o_samp);
+  c->links = (AmrLink*)(w + p.o_links);
+  if ((rc = up(p.o_samp, p.samples.data(), p.samples.size() * sizeof(AmrSample))) ||
+      (rc = up(p.o_links, p.links.data(), p.links.size() * sizeof(AmrLink))) ||
+      (rc = up(p.o_lev, p.lev_blocks.data(), p.lev_blocks.size() * sizeof(int32_t))) ||
       (rc = up(p.o_items, p.items.data(), p.items.size() * sizeof(SyncItem)))) {
     delete c;
     return rc;
@@ -648,13 +1025,11 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   for (int k = 0; k < 3; k++) {
     L.max_np[k] = p.max_np[k];
     L.max_n[k] = p.max_n[k];
-    L.ph.dx[k] = (desc->xmax[k] - desc->xmin[k]) / desc->n_eff[k];
   }
   L.geo.c = (const double*)(w + p.o_gc);
   L.geo.f1 = (const double*)(w + p.o_g1);
   L.geo.f2 = (const double*)(w + p.o_g2);
   L.geo.ncol = p.ncol;
-  L.geo.ti = p.ti;
   L.ph.gam = desc->gamma_ad;
   L.ph.courant = desc->courant;
   L.ph.tol = desc->c2p_tol;
@@ -700,6 +1075,9 @@ static void fill_ghosts(grmhd_ctx* c, double* P, double* B) {
   prof_begin(c, KC_GHOST);
   launch_ghost_cells(c->L, c->ops[0], c->nops[0], P);
   for (int k = 0; k < 3; k++) launch_ghost_faces(c->L, c->ops[k + 1], c->nops[k + 1], B, k);
+  launch_amr_cells(c->L, c->aops[0], c->naops[0], c->samp, P, nullptr, P, 0.0, P);
+  for (int k = 0; k < 3; k++)
+    launch_amr_faces(c->L, c->aops[k + 1], c->naops[k + 1], c->samp, B, nullptr, B, 0.0, B, k);
   prof_end(c);
 }
 
@@ -717,10 +1095,16 @@ static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double
   }
   prof_begin(c, KC_EMF);
   launch_emf(L, c->f, c->e);
+  launch_amr_fix(L, c->links, (int)c->plan.links.size(), c->plan.link_maxpos, c->f, c->e);
   prof_end(c);
   prof_begin(c, KC_UPDATE);
   launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, dt_part, c->mlp);
   prof_end(c);
+  if (!c->plan.links.empty()) {
+    prof_begin(c, KC_GHOST);
+    launch_amr_bsync(L, c->links, (int)c->plan.links.size(), c->plan.link_maxpos, Bout);
+    prof_end(c);
+  }
 }
 
 // one block level of a substep: predictor and corrector with time-aware ghosts, then the
@@ -749,6 +1133,12 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
       const int64_t o = p.ops_off[k + 1][lev], n = p.ops_off[k + 1][lev + 1] - o;
       launch_ghost_faces_t(L, c->ops[k + 1] + o, n, B, c->bold, Bcur, w, Bdst, k);
     }
+    const int64_t a0 = p.aops_off[0][lev], m0 = p.aops_off[0][lev + 1] - a0;
+    launch_amr_cells(L, c->aops[0] + a0, m0, c->samp, P, c->pold, Pcur, w, Pdst);
+    for (int k = 0; k < 3; k++) {
+      const int64_t o = p.aops_off[k + 1][lev], n = p.aops_off[k + 1][lev + 1] - o;
+      launch_amr_faces(L, c->aops[k + 1] + o, n, c->samp, B, c->bold, Bcur, w, Bdst, k);
+    }
     prof_end(c);
   };
   auto stage_l = [&](const double* Ps, const double* Bs, double factor, double* Pout) {
@@ -760,12 +1150,19 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
       launch_flux(L, dir, recon, riem, Ps, c->bc, Bs, c->f);
       prof_end(c);
     }
+    const int64_t lo = p.link_off[lev], nl = p.link_off[lev + 1] - lo;
     prof_begin(c, KC_EMF);
     launch_emf(L, c->f, c->e);
+    launch_amr_fix(L, c->links + lo, (int)nl, p.link_maxpos, c->f, c->e);
     prof_end(c);
     prof_begin(c, KC_UPDATE);
     launch_update(L, P, B, Ps, c->bc, c->f, c->e, factor, Pout, c->balt, nullptr, c->mlp);
     prof_end(c);
+    if (nl > 0) {
+      prof_begin(c, KC_GHOST);
+      launch_amr_bsync(L, c->links + lo, (int)nl, p.link_maxpos, c->balt);
+      prof_end(c);
+    }
   };
   ghosts(P, B, P, B, w_pred);
   stage_l(P, B, 0.5 * scale, c->ps);                 // predictor -> ps, balt
@@ -930,18 +1327,31 @@ int grmhd_divb(grmhd_ctx* c, double* max_abs, double* max_rel, double* field) {
 
 int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes) {
   if (!bytes) return fail(GRMHD_EINVAL, "NULL argument");
-  if (what < 0 || what > 3) return fail(GRMHD_EINVAL, "unknown table");
+  if (what < 0 || what > 9) return fail(GRMHD_EINVAL, "unknown table");
   Plan p;
   int rc = build_plan(desc, p, true);
   if (rc) return rc;
-  const auto& v = p.ops[what];
-  const size_t need = v.size() * sizeof(GhostOp);
+  const void* src;
+  size_t need;
+  if (what < 4) {
+    src = p.ops[what].data();
+    need = p.ops[what].size() * sizeof(GhostOp);
+  } else if (what < 8) {
+    src = p.aops[what - 4].data();
+    need = p.aops[what - 4].size() * sizeof(AmrOp);
+  } else if (what == 8) {
+    src = p.samples.data();
+    need = p.samples.size() * sizeof(AmrSample);
+  } else {
+    src = p.links.data();
+    need = p.links.size() * sizeof(AmrLink);
+  }
   if (!host_buf) {
     *bytes = need;
     return GRMHD_OK;
   }
   if (*bytes < need) return fail(GRMHD_EINVAL, "buffer too small");
-  std::memcpy(host_buf, v.data(), need);
+  if (need) std::memcpy(host_buf, src, need);
   *bytes = need;
   return GRMHD_OK;
 }

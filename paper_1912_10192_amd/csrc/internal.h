@@ -13,7 +13,9 @@ struct BlockInfo {
   int32_t gorg[3];  // geometry-table index of local index 0 in x1, x2 (x3 unused)
   int32_t vol;      // np1 np2 np3
   int32_t lat;
-  int32_t pad;
+  int32_t gti;      // row length of the block's geometry table
+  int64_t gbase;    // first column of the block's geometry table (one table per x1-x2 level)
+  double dx[3];     // cell spacing at the block's refinement level
 };
 
 // one ghost copy: destination (block, local), source (block | flags << 24, local)
@@ -22,19 +24,56 @@ struct GhostOp {
 };
 enum { GF_FLIP = 1, GF_CLAMP_NEG = 2, GF_CLAMP_POS = 4, GF_ZERO = 8, GF_SLOW = 16, GF_FAST = 32 };
 
+// A ghost value that involves another refinement level: a restriction of a finer
+// neighbour or a prolongation from a coarser one.  Samples are interior values of other
+// blocks (or of the block itself) at the source's own level; the op combines them.
+//   mode bits 0-2   prolonged dimensions (minmod slopes, or for a face component along
+//                   its normal: the face cuts or lies on a coarse face)
+//   mode bits 4-6   the child lies in the upper half of its parent along that dimension
+//   mode bit 8      a face cutting a coarse cell: mean of the stencils on its two faces
+//   mode bits 16-23 boundary flags applied to the result (GF_*)
+// Samples: cells -- centre, then (minus, plus) per prolonged dimension in increasing
+// order; faces -- per stencil, the coarse face then (minus, plus) per prolonged
+// transverse dimension.  Without prolonged dimensions a single sample.
+struct AmrOp {
+  int32_t dst_blk, dst_loc, mode, samp;
+};
+// block | flags << 24 (time and boundary flags of this value), local index of the value
+// (a cell, or a face of the op's component), and the dimensions averaged by a
+// restriction (0: the value itself)
+struct AmrSample {
+  int32_t blkf, loc, mask, pad;
+};
+enum { AM_PDIMS = 7, AM_UPPER_SHIFT = 4, AM_TWO = 256, AM_FLAGS_SHIFT = 16 };
+
+// A face shared by a coarse block and a block one level finer at the same time level:
+// the coarse fluxes and EMFs on it are replaced by the fine ones, and the coarse copy of
+// the face by the mean of the fine faces.  lo/hi bound the shared patch in the coarse
+// block's padded local indices (transverse dimensions); cplane/fplane are the local face
+// indices of the plane in the coarse and fine blocks; fmap maps a coarse local index to
+// the fine local index of its first child: fine = 2^e (coarse - ng + corg) - forg + ng.
+struct AmrLink {
+  int32_t coarse, fine, d, e;      // e: refined dimensions (bits)
+  int32_t lo[3], hi[3];
+  int32_t cplane, fplane;
+  int32_t corg[3], forg[3];
+  int32_t npos;                    // faces + edges handled for this link
+  int32_t pad;
+};
+
 // one plane shared by a slower block and its faster x1 neighbour (side 0 = the slow
 // block's lower x1 face, 1 = upper)
 struct SyncItem {
   int32_t slow, fast, side, pad;
 };
 
-// geometry tables: SoA [quantity][column], column = j * ti + i
+// geometry tables: SoA [quantity][column]; one table per pair of x1/x2 refinement
+// levels, column = gbase + j * gti + i of the block's table
 struct GeoTab {
   const double* c;    // centre: NGEO_C quantities
   const double* f1;   // x1 faces: NGEO_F
   const double* f2;   // x2 faces: NGEO_F (sqrt(-g) = 0 marks the polar axis)
-  int64_t ncol;
-  int32_t ti;
+  int64_t ncol;       // columns of all tables together (stride between quantities)
 };
 
 struct Counters {   // device counters of one grmhd_step call
@@ -49,12 +88,15 @@ struct Counters {   // device counters of one grmhd_step call
 };
 
 struct Phys {
-  double dx[3];
   double gam, courant, tol;
   double bsq_rho_max, bsq_u_max, gamma_max;
   int32_t maxit;
   int32_t ng;
 };
+
+__host__ __device__ inline int64_t geo_col(const GeoTab&, const BlockInfo& bi, int J, int I) {
+  return bi.gbase + (int64_t)(bi.gorg[1] + J) * bi.gti + (bi.gorg[0] + I);
+}
 
 struct Launch {
   const BlockInfo* blk;   // device block table
@@ -93,6 +135,16 @@ void launch_copy(const Launch& L, const double* src, double* dst, int64_t n);
 void launch_divb(const Launch& L, const double* B, double* field);
 void launch_extract(const Launch& L, const double* Pin, const double* Bin, int64_t n, double* P,
                     double* B, double* geom);
+// refinement levels (amr.hip)
+void launch_amr_cells(const Launch& L, const AmrOp* ops, int64_t nops, const AmrSample* samp,
+                      const double* main, const double* old, const double* cur, double w,
+                      double* dst);
+void launch_amr_faces(const Launch& L, const AmrOp* ops, int64_t nops, const AmrSample* samp,
+                      const double* main, const double* old, const double* cur, double w,
+                      double* dst, int comp);
+void launch_amr_fix(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* F,
+                    double* E);
+void launch_amr_bsync(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* B);
 // local time stepping (lat.hip)
 void launch_ghost_cells_t(const Launch& L, const GhostOp* ops, int64_t nops, const double* main,
                           const double* old, const double* cur, double w, double* dst);

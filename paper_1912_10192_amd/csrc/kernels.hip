@@ -100,9 +100,6 @@ __device__ __forceinline__ bool region_cell(const BlockInfo& bi, int t, int r0, 
   return true;
 }
 
-__device__ __forceinline__ int64_t geo_col(const GeoTab& G, const BlockInfo& bi, int J, int I) {
-  return (int64_t)(bi.gorg[1] + J) * G.ti + (bi.gorg[0] + I);
-}
 
 // ------------------------------------------------------------------ ghost gather
 
@@ -305,16 +302,16 @@ __device__ __forceinline__ double block_min(double v) {
 
 // per cell 1/dt = sum_d max(|v+|, |v-|)/dx_d from the cell-centred state (Sec. 2.1)
 __device__ __forceinline__ double cell_dt(const double P[5], const double B[3], const Metric& m,
-                                          const Phys& ph) {
+                                          const Phys& ph, const double dx[3]) {
   Fluid f;
   fluid_state(P, B, m, f);
   double vp, vm, inv = 0.0;
   wave_speeds<1>(P, f, m, ph.gam, vp, vm);
-  inv += fmax(fabs(vp), fabs(vm)) / ph.dx[0];
+  inv += fmax(fabs(vp), fabs(vm)) / dx[0];
   wave_speeds<2>(P, f, m, ph.gam, vp, vm);
-  inv += fmax(fabs(vp), fabs(vm)) / ph.dx[1];
+  inv += fmax(fabs(vp), fabs(vm)) / dx[1];
   wave_speeds<3>(P, f, m, ph.gam, vp, vm);
-  inv += fmax(fabs(vp), fabs(vm)) / ph.dx[2];
+  inv += fmax(fabs(vp), fabs(vm)) / dx[2];
   return 1.0 / inv;
 }
 
@@ -373,7 +370,7 @@ __global__ __launch_bounds__(NT) UPDATE_OCC void k_update(Launch L, const double
   if (valid) {
     const double dt = L.ph.courant * __longlong_as_double((long long)L.cnt->dt_bits);
     const double dts = dt_factor * dt;
-    const double dx1 = L.ph.dx[0], dx2 = L.ph.dx[1], dx3 = L.ph.dx[2];
+    const double dx1 = bi.dx[0], dx2 = bi.dx[1], dx3 = bi.dx[2];
     const double* e1 = E + 3 * bi.off;
     const double* e2 = e1 + V;
     const double* e3 = e2 + V;
@@ -381,7 +378,7 @@ __global__ __launch_bounds__(NT) UPDATE_OCC void k_update(Launch L, const double
     const double* b2 = b1 + V;
     const double* b3 = b2 + V;
     const bool pole_lo = G.f2[GDET * G.ncol + col] == 0.0;
-    const bool pole_hi = G.f2[GDET * G.ncol + col + G.ti] == 0.0;
+    const bool pole_hi = G.f2[GDET * G.ncol + col + bi.gti] == 0.0;
     // constrained transport of the six faces of this cell (Sec. 2.5)
     const double nb1lo = b1[l] + dts * ((e2[l + s3] - e2[l]) / dx3 - (e3[l + s2] - e3[l]) / dx2);
     const double nb1hi =
@@ -459,7 +456,7 @@ __global__ __launch_bounds__(NT) UPDATE_OCC void k_update(Launch L, const double
                         L.ph.bsq_rho_max, L.ph.bsq_u_max, L.ph.gamma_max);
 #pragma unroll
     for (int v = 0; v < 5; v++) Pout[5 * bi.off + (int64_t)v * V + l] = Pnew[v];
-    if (NEXT_DT) dtc = cell_dt(Pnew, Bnew, m, L.ph);
+    if (NEXT_DT) dtc = cell_dt(Pnew, Bnew, m, L.ph, bi.dx);
   }
   if (NEXT_DT) {
     const double r = block_min(dtc);
@@ -498,7 +495,7 @@ __global__ __launch_bounds__(NT) void k_dt(Launch L, const double* __restrict__ 
     Bc[0] = 0.5 * (b[l] + b[l + 1]) / m.gdet;
     Bc[1] = 0.5 * (b[V + l] + b[V + l + s2]) / m.gdet;
     Bc[2] = 0.5 * (b[2 * V + l] + b[2 * V + l + s3]) / m.gdet;
-    dtc = cell_dt(Pc, Bc, m, L.ph);
+    dtc = cell_dt(Pc, Bc, m, L.ph, bi.dx);
   }
   const double r = block_min(dtc);
   if (threadIdx.x == 0) dt_part[(int64_t)tl.y * gridDim.x + tl.x] = r;
@@ -560,9 +557,9 @@ __global__ __launch_bounds__(NT) void k_divb(Launch L, const double* __restrict_
     const double* b = B + 3 * bi.off;
     const double d1 = b[l + 1], d0 = b[l], e1 = b[V + l + s2], e0 = b[V + l];
     const double f1 = b[2 * V + l + s3], f0 = b[2 * V + l];
-    const double dv = (d1 - d0) / L.ph.dx[0] + (e1 - e0) / L.ph.dx[1] + (f1 - f0) / L.ph.dx[2];
-    const double den = (fabs(d1) + fabs(d0)) / L.ph.dx[0] + (fabs(e1) + fabs(e0)) / L.ph.dx[1] +
-                       (fabs(f1) + fabs(f0)) / L.ph.dx[2];
+    const double dv = (d1 - d0) / bi.dx[0] + (e1 - e0) / bi.dx[1] + (f1 - f0) / bi.dx[2];
+    const double den = (fabs(d1) + fabs(d0)) / bi.dx[0] + (fabs(e1) + fabs(e0)) / bi.dx[1] +
+                       (fabs(f1) + fabs(f0)) / bi.dx[2];
     if (field) field[5 * bi.off + l] = dv;
     a = fabs(dv);
     r = den > 0.0 ? a / den : 0.0;

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(LT) void k_sync_u(Launch L, const SyncItem* __restr
   const int64_t V = bi.vol;
   const int64_t l = ((int64_t)K * bi.np[1] + J) * bi.np[0] + I;
   const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
-  const int64_t col = (int64_t)(bi.gorg[1] + J) * L.geo.ti + (bi.gorg[0] + I);
+  const int64_t col = geo_col(L.geo, bi, J, I);
   const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
   double p[5], bc[3], U[9];
   for (int v = 0; v < 5; v++) p[v] = P[5 * bi.off + v * V + l];
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(LT) void k_sync_u(Launch L, const SyncItem* __restr
   constexpr int fq[6] = {0, 1, 2, 3, 4, 7};
   constexpr int uq[6] = {0, 1, 2, 3, 4, 8};
   for (int k = 0; k < 6; k++)
-    U[uq[k]] += (mine[fq[k] * rs + o] - theirs[fq[k] * rs + o]) / L.ph.dx[0] * sgn;
+    U[uq[k]] += (mine[fq[k] * rs + o] - theirs[fq[k] * rs + o]) / bi.dx[0] * sgn;
   double* u = Ubuf + ((int64_t)blockIdx.y * layer + t) * 9;
   for (int q = 0; q < 9; q++) u[q] = U[q];
 }
@@ -193,11 +193,11 @@ __global__ __launch_bounds__(LT) void k_sync_faces(Launch L, const SyncItem* __r
   const int64_t lc = ((int64_t)K * bi.np[1] + J) * bi.np[0] + Ic;
   if (kk < n3) {   // x2 faces of the layer, j in [g, g + n2]
     const double dE3 = theirs[9 * rs + o] - mine[9 * rs + o];
-    b[V + lc] += sgn * dE3 / L.ph.dx[0];
+    b[V + lc] += sgn * dE3 / bi.dx[0];
   }
   if (jj < n2) {   // x3 faces of the layer, k in [g, g + n3]
     const double dE2 = theirs[8 * rs + o] - mine[8 * rs + o];
-    b[2 * V + lc] -= sgn * dE2 / L.ph.dx[0];
+    b[2 * V + lc] -= sgn * dE2 / bi.dx[0];
   }
   if (kk < n3 && jj < n2) {
     const int64_t lf = ((int64_t)K * bi.np[1] + J) * bi.np[0] + If;
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(LT) void k_sync_c2p(Launch L, const SyncItem* __res
   const int64_t V = bi.vol;
   const int64_t l = ((int64_t)K * bi.np[1] + J) * bi.np[0] + I;
   const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
-  const int64_t col = (int64_t)(bi.gorg[1] + J) * L.geo.ti + (bi.gorg[0] + I);
+  const int64_t col = geo_col(L.geo, bi, J, I);
   const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
   double U[9], p[5];
   const double* u = Ubuf + ((int64_t)blockIdx.y * layer + t) * 9;

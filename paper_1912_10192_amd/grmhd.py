@@ -199,7 +199,7 @@ class Desc:
         buf = np.zeros(nbytes.value // 4, dtype=np.int32)
         _check(lib().grmhd_plan_dump(C.byref(self.d), what, buf.ctypes.data_as(C.c_void_p),
                                      C.byref(nbytes)))
-        return buf.reshape(-1, 4)
+        return buf.reshape(-1, 20 if what == 9 else 4)
 
 
 def geometry_point(coords, a, x1, x2):
@@ -264,6 +264,43 @@ def gather(desc: Desc, prim, bface):
     return P, B1, B2, B3
 
 
+def _block_views(desc: Desc, prim, bface, b):
+    off, (n1p, n2p, n3p) = desc.layout(b)
+    V = n1p * n2p * n3p
+    return (prim[5 * off:5 * off + 5 * V].reshape(5, n3p, n2p, n1p),
+            bface[3 * off:3 * off + 3 * V].reshape(3, n3p, n2p, n1p))
+
+
+def scatter_blocks(desc: Desc, states):
+    """per-block interior arrays (P[5][n3][n2][n1], B1[n3][n2][n1+1], B2[n3][n2+1][n1],
+    B3[n3+1][n2][n1]) -> packed host arrays (prim, bface)"""
+    g = desc.cfg["ng"]
+    nprim, nbface, _ = desc.sizes()
+    prim = np.zeros(nprim)
+    bface = np.zeros(nbface)
+    for b, (P, B1, B2, B3) in enumerate(states):
+        n = [desc.blocks[b].n[d] for d in range(3)]
+        pv, bv = _block_views(desc, prim, bface, b)
+        pv[:, g:g + n[2], g:g + n[1], g:g + n[0]] = P
+        bv[0, g:g + n[2], g:g + n[1], g:g + n[0] + 1] = B1
+        bv[1, g:g + n[2], g:g + n[1] + 1, g:g + n[0]] = B2
+        bv[2, g:g + n[2] + 1, g:g + n[1], g:g + n[0]] = B3
+    return prim, bface
+
+
+def gather_blocks(desc: Desc, prim, bface):
+    g = desc.cfg["ng"]
+    out = []
+    for b in range(desc.d.n_blocks):
+        n = [desc.blocks[b].n[d] for d in range(3)]
+        pv, bv = _block_views(desc, prim, bface, b)
+        out.append((pv[:, g:g + n[2], g:g + n[1], g:g + n[0]].copy(),
+                    bv[0, g:g + n[2], g:g + n[1], g:g + n[0] + 1].copy(),
+                    bv[1, g:g + n[2], g:g + n[1] + 1, g:g + n[0]].copy(),
+                    bv[2, g:g + n[2] + 1, g:g + n[1], g:g + n[0]].copy()))
+    return out
+
+
 # ------------------------------------------------------------------ device grid
 
 class Grid:
@@ -310,6 +347,16 @@ class Grid:
         self.torch.cuda.synchronize(self.device)
         return gather(self.desc, self.prim.cpu().numpy(), self.bface.cpu().numpy())
 
+    def set_blocks(self, states):
+        """per-block interior arrays (block grids with refinement levels)"""
+        prim, bface = scatter_blocks(self.desc, states)
+        self.prim.copy_(self.torch.from_numpy(prim))
+        self.bface.copy_(self.torch.from_numpy(bface))
+
+    def get_blocks(self):
+        self.torch.cuda.synchronize(self.device)
+        return gather_blocks(self.desc, self.prim.cpu().numpy(), self.bface.cpu().numpy())
+
     def step(self, n=1, stats=True):
         st = StepStats() if stats else None
         _check(lib().grmhd_step(self.ctx, n, C.byref(st) if stats else None))
@@ -318,7 +365,7 @@ class Grid:
     def extract_cells(self):
         """every interior cell as flat batches (P[5][n], B[3][n], geom[15][n]) on the device"""
         torch = self.torch
-        n = int(np.prod(self.desc.cfg["n"]))
+        n = sum(int(np.prod([bd.n[d] for d in range(3)])) for bd in self.desc.blocks)
         P = torch.empty((5, n), dtype=torch.float64, device=self.device)
         B = torch.empty((3, n), dtype=torch.float64, device=self.device)
         G = torch.empty((15, n), dtype=torch.float64, device=self.device)

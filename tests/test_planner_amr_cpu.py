@@ -1,0 +1,133 @@
+"""The planner's refinement tables checked on the CPU: replaying the exported ghost
+lists on packed host arrays reproduces the oracle's block views in every ghost cell and
+ghost face, with every index inside its block."""
+import numpy as np
+import pytest
+
+from oracle.amr import AmrGrid
+from paper_1912_10192_amd import configs, grmhd, initdata
+from tests.amr_emulate import Replay
+from tests.helpers import mink_cfg, random_periodic_state
+from tests.test_oracle_amr import band_blocks
+
+
+def polar_bands(eff, lat=(0, 0)):
+    """Kerr-Schild layout: coarse polar caps (two x1 blocks each), a refined equatorial
+    band (two x1 blocks, split in x3)"""
+    N1, N2, N3 = eff
+    c1, c2, c3 = N1 // 2, N2 // 2, N3 // 2
+    out = []
+    for org2, n2 in ((0, c2 // 4), (3 * c2 // 4, c2 // 4)):
+        for h in range(2):
+            out.append(dict(org=(h * c1 // 2, org2, 0), n=(c1 // 2, n2, c3), lev=(0, 0, 0), lat=lat[h]))
+    for h in range(2):
+        for kk in range(2):
+            out.append(dict(org=(h * N1 // 2, N2 // 4, kk * N3 // 2), n=(N1 // 2, N2 // 2, N3 // 2),
+                            lev=(1, 1, 1), lat=lat[h]))
+    return out
+
+
+def cases():
+    mk = mink_cfg((16, 32, 8), recon=1, riemann=1, L=(1.0, 2.0, 0.5))
+    ks = configs.scaled(configs.TORUS_UNIFORM, (32, 32, 16), ng=3)
+    return [("mink", mk, band_blocks((0, 0), (16, 32, 8))),
+            ("mink-lat", mk, band_blocks((0, 1), (16, 32, 8))),
+            ("ks", ks, polar_bands((32, 32, 16))), ("ks-lat", ks, polar_bands((32, 32, 16), (0, 1)))]
+
+
+@pytest.mark.parametrize("case", [c[0] for c in cases()])
+def test_replayed_ghosts_match_oracle_views(case):
+    name, cfg, blocks = [c for c in cases() if c[0] == case][0]
+    orc = AmrGrid(cfg, blocks)
+    if cfg["coords"] == 0:
+        state = random_periodic_state(cfg["n"], seed=5, amp=0.1, vamp=0.3, bamp=0.3,
+                                      dx=tuple(1.0 / cfg["n"][0] for _ in range(3)))
+    else:
+        state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    bs = initdata.block_states(state, orc.blocks, orc.Lmax)
+    orc.set_blocks(bs)
+    # slower blocks are read at the start of their step (time weight 0 at substep 0)
+    orc.Pold = [p.copy() for p in orc.P]
+    orc.Bold = [b.copy() for b in orc.B]
+    desc = grmhd.Desc(cfg, blocks=blocks)
+    assert len(desc.plan_dump(4)) > 0 and len(desc.plan_dump(9)) == 4 * (1 if "mink" in name else 2)
+    prim, bface = grmhd.scatter_blocks(desc, bs)
+    Replay(desc, cfg).fill(prim, bface)
+    g = cfg["ng"]
+    for i in range(len(blocks)):
+        if blocks[i]["lat"] != 0:
+            continue     # the oracle's view at substep 0 (blocks of the fastest level)
+        VP, VB = orc.patch(i, "pred", 0)
+        off, (n1p, n2p, n3p) = desc.layout(i)
+        V = n1p * n2p * n3p
+        P = prim[5 * off:5 * off + 5 * V].reshape(5, n3p, n2p, n1p)
+        B = bface[3 * off:3 * off + 3 * V].reshape(3, n3p, n2p, n1p)
+        n = blocks[i]["n"]
+        K, J, I = np.meshgrid(np.arange(n3p), np.arange(n2p), np.arange(n1p), indexing="ij")
+        ghost = (I < g) | (I >= g + n[0]) | (J < g) | (J >= g + n[1]) | (K < g) | (K >= g + n[2])
+        assert np.isfinite(VP[:, ghost]).all()
+        scale = np.abs(VP[:, ghost]).max(axis=1)[:, None]
+        assert np.all(np.abs(P[:, ghost] - VP[:, ghost]) <= 1e-14 * scale), name
+        for c in range(3):
+            hi = [g + n[d] + (1 if d == c else 0) for d in range(3)]
+            gf = (I < g) | (I >= hi[0]) | (J < g) | (J >= hi[1]) | (K < g) | (K >= hi[2])
+            assert np.isfinite(VB[c][gf]).all()
+            sc = np.abs(VB[c][gf]).max() + 1e-300
+            assert np.all(np.abs(B[c][gf] - VB[c][gf]) <= 1e-14 * sc), (name, c)
+
+
+def test_refinement_layout_checks():
+    cfg = mink_cfg((16, 32, 8), recon=1, riemann=1, L=(1.0, 2.0, 0.5))
+    bl = band_blocks((0, 0), (16, 32, 8))
+    bl[2] = dict(bl[2], org=(0, 9, 0), n=(8, 15, 8))    # a refined block off the coarse cells
+    with pytest.raises(grmhd.GrmhdError):
+        grmhd.Desc(cfg, blocks=bl).sizes()
+    bl = band_blocks((0, 1), (16, 32, 8))
+    bl[2] = dict(bl[2], lat=1)                           # refinement face across time levels
+    with pytest.raises(grmhd.GrmhdError, match="time level"):
+        grmhd.Desc(cfg, blocks=bl).sizes()
+
+
+@pytest.mark.parametrize("case", [c[0] for c in cases()])
+def test_refinement_faces_match_oracle_and_stay_in_bounds(case):
+    """the exported refinement faces are the oracle's, and every coarse and fine index the
+    flux-correction and face-copy kernels derive from them lies inside its block"""
+    name, cfg, blocks = [c for c in cases() if c[0] == case][0]
+    orc = AmrGrid(cfg, blocks)
+    desc = grmhd.Desc(cfg, blocks=blocks)
+    links = desc.plan_dump(9)
+    g = cfg["ng"]
+    mine = sorted((int(r[0]), int(r[1]), int(r[2])) for r in links)
+    want = sorted((c, f, d) for c, f, d, side, e, lo, hi in orc.links)
+    assert mine == want
+    for r in links:
+        c, f, d, e = (int(x) for x in r[:4])
+        lo, hi = r[4:7], r[7:10]
+        cplane, fplane = int(r[10]), int(r[11])
+        corg, forg, npos = r[12:15], r[15:18], int(r[18])
+        npc = [blocks[c]["n"][x] + 2 * g + 1 for x in range(3)]
+        npf = [blocks[f]["n"][x] + 2 * g + 1 for x in range(3)]
+        a0, a1 = (1, 2) if d == 0 else ((0, 2) if d == 1 else (0, 1))
+        w0, w1 = hi[a0] - lo[a0], hi[a1] - lo[a1]
+        assert npos == w0 * w1 + w0 * (w1 + 1) + w1 * (w0 + 1)
+        for t in range(npos):
+            nf, ne0 = w0 * w1, w0 * (w1 + 1)
+            if t < nf:
+                kind, i0, i1 = 0, t % w0, t // w0
+            elif t < nf + ne0:
+                kind, i0, i1 = 1, (t - nf) % w0, (t - nf) // w0
+            else:
+                kind, i1, i0 = 2, (t - nf - ne0) % w1, (t - nf - ne0) // w1
+            pc = [0, 0, 0]
+            pc[d], pc[a0], pc[a1] = cplane, lo[a0] + i0, lo[a1] + i1
+            pf = [0, 0, 0]
+            pf[d] = fplane
+            for x in (a0, a1):
+                pf[x] = (pc[x] - g + corg[x]) * (1 << ((e >> x) & 1)) - forg[x] + g
+            for x in range(3):
+                assert 0 <= pc[x] < npc[x]
+                top = pf[x] + (((e >> x) & 1) if x != d else 0)
+                assert 0 <= pf[x] and top < npf[x]
+            # the fine children lie in the fine block's interior faces / edges
+            for x in (a0, a1):
+                assert g <= pf[x] <= g + blocks[f]["n"][x]
