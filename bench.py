@@ -5,9 +5,19 @@ Workload: one GPU's share of a uniform grid -- the Fishbone-Moncrief torus with 
 single-loop field (plasma beta 100) and a seeded 2% u_g perturbation on a 256x128x128
 log-spherical Kerr-Schild grid (a = 0.9375, r in [1.2, 50]), split into 128 blocks of
 32^3, PPM + HLLE, FP64 midpoint steps.  Inputs are resident in HBM before the timed
-region.  Prints one JSON line: zone-cycles/s (cells x steps / wall time), the roofline
-position of the dominant kernel (average launch time from HIP events on the library's
-stream during the timed region) and the CPU oracle's rate on a bounded sample.
+region.  Three paths are timed on the same initial state:
+  plain                 global time step, one launch per kernel and stage, plain guess
+  lat_batched           local time stepping with 4 levels by radius, each cycle one
+                        captured graph, plain guess
+  lat_batched_learned   the same with the learned first guess of the inversion
+  polar_smr_lat_batched_learned
+                        the same effective grid with coarser polar bands (half
+                        resolution within pi/4 of the poles, a quarter in phi within
+                        pi/8), reported as refinement-and-LAT-effective zone-cycles/s
+The headline value is the last one's LAT-effective zone-cycles/s (every cell advanced by
+every finest-level step, per second of wall time).  The roofline block reports the
+dominant kernel of the plain run (average launch time from HIP events on the library's
+stream during its timed region); the CPU oracle is timed on a bounded sample.
 """
 from __future__ import annotations
 
@@ -86,13 +96,54 @@ def cpu_baseline(cfg, state, steps):
     return N1 * N2 * N3 * steps / dt, dt
 
 
+def timed(grid, cycles, sync):
+    sync()
+    t0 = time.perf_counter()
+    st = grid.step(cycles, stats=True)
+    sync()
+    return st, time.perf_counter() - t0
+
+
+def c2p_summary(st):
+    hist = list(st.c2p_iter_hist)
+    n = sum(hist[:63])
+    return {"tier": list(st.c2p_tier), "floor_hits": st.floor_hits,
+            "mean_newton_iters": (sum(i * h for i, h in enumerate(hist[:63])) / n) if n else None}
+
+
+def train_guess(cfg, state, steps, log):
+    """train the learned inversion guess on the initial cells plus synthetic states"""
+    import torch
+
+    from paper_1912_10192_amd import grmhd, learned
+
+    t0 = time.perf_counter()
+    g = grmhd.Grid(cfg, state=state)
+    g.step(2)
+    P, B, G = g.extract_cells()
+    chunks = [(P, B, G), learned.synthetic_states(G, 1_000_000, seed=5)]
+    X, Y, norm = learned.build_dataset(chunks, cfg["gam"])
+    del g, chunks
+    trainer, losses = learned.train(X, Y, steps=steps, batch=4096, lr=2e-3, log_every=steps // 4)
+    blob = grmhd.mlp_pack(trainer.params, norm)
+    torch.cuda.synchronize()
+    log(f"[bench] learned guess: {X.shape[0]} pairs, {steps} steps, losses {losses}")
+    return blob, {"pairs": int(X.shape[0]), "steps": steps, "final_loss": losses[-1][1],
+                  "train_s": time.perf_counter() - t0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200, help="finest-level steps")
+    ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
+    ap.add_argument("--only-plain", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=1000)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (calibrates the "
+                         "FETCH_SIZE/WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
@@ -102,23 +153,30 @@ def main():
 
     from paper_1912_10192_amd import configs, grmhd, initdata
 
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    sync = torch.cuda.synchronize
+    if args.copy_probe:
+        n = args.copy_probe << 17
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        sync()
+        log(f"[bench] copy probe: 3 copies of {args.copy_probe} MiB")
+        return
     cfg = dict(configs.TORUS_UNIFORM)
-    print(f"[bench] building initial state {cfg['n']}", file=sys.stderr, flush=True)
+    log(f"[bench] building initial state {cfg['n']}")
     state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
-    grid = grmhd.Grid(cfg, state=state, profile=True)
     cells = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
-    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+
+    # ---- plain path: global time step, one launch per kernel and stage, plain guess
+    grid = grmhd.Grid(cfg, state=state, profile=True)
+    log(f"[bench] plain: warmup {args.warmup}, timed {args.steps} steps")
     if args.warmup:
         grid.step(args.warmup, stats=True)
-    torch.cuda.synchronize()
-    print(f"[bench] timed {args.steps} steps", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    st = grid.step(args.steps, stats=True)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    value = cells * args.steps / wall
+    st, wall = timed(grid, args.steps, sync)
+    plain_value = cells * args.steps / wall
     a_div, r_div = grid.divb()
-
     cls_ms = {k: st.class_ms[i] for i, k in enumerate(grmhd.KERNEL_CLASSES)}
     cls_n = {k: st.class_launches[i] for i, k in enumerate(grmhd.KERNEL_CLASSES)}
     dom = max(cls_ms, key=lambda k: cls_ms[k])
@@ -137,30 +195,73 @@ def main():
     traffic = TRAFFIC_PER_LAUNCH.get(dom) if fresh else None
     roofline = {"bound": bound, "achieved": achieved / scale, "peak": peak / scale, "unit": unit,
                 "frac": achieved / peak, "traffic": traffic, "kernel": dom,
-                "launch_ms": avg_s * 1e3, "units_per_launch": units}
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "zone-cycles/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "torus-256x128x128-b32-ppm-hlle", "grid": list(cfg["n"]),
-                   "blocks": 128, "block": list(cfg["block"]), "recon": "PPM",
-                   "riemann": "HLLE", "c2p_guess": "plain", "c2p_tol": cfg["tol"],
-                   "lat_levels": 1, "path": "plain"},
-        "roofline": roofline,
-        "kernel_ms_per_step": {k: v / args.steps for k, v in cls_ms.items()},
-        "c2p": {"tier": list(st.c2p_tier), "mean_iters": None, "floor_hits": st.floor_hits},
-        "divb_rel_max": r_div, "t_sim": st.t_sim, "dt": st.dt_min,
-    }
-    hist = list(st.c2p_iter_hist)
-    nsolve = sum(hist[:63])
-    if nsolve:
-        out["c2p"]["mean_iters"] = sum(i * h for i, h in enumerate(hist[:63])) / nsolve
+                "launch_ms": avg_s * 1e3, "units_per_launch": units, "kernel_hash": khash}
+    plain = {"value": plain_value, "ms_per_step": wall * 1e3 / args.steps, "dt": st.dt_min,
+             "c2p": c2p_summary(st), "divb_rel_max": r_div,
+             "kernel_ms_per_step": {k: v / args.steps for k, v in cls_ms.items()}}
     del grid
+
+    out = {"metric": METRIC, "unit": "zone-cycles/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
+    if args.only_plain:
+        out.update({"value": plain_value, "ms_per_step": plain["ms_per_step"],
+                    "config": {"workload": "torus-256x128x128-b32-ppm-hlle", "path": "plain"},
+                    "roofline": roofline, "plain": plain})
+    else:
+        # ---- batched local time stepping: 4 levels by radius, graph-captured cycles
+        lats = grmhd.lat_levels_by_radius(cfg, [2.4, 4.8, 9.6])
+        L = max(lats) + 1
+        nsub = 2 ** (L - 1)
+        cycles = max(args.steps // nsub, 1)
+        blocks = grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=lats)
+        smr = configs.polar_smr_blocks(cfg["n"], cfg["block"][0], lats)
+        results = {}
+        blob, train = None, None
+        for name, bl, learned_on in (("lat_batched", blocks, False),
+                                     ("lat_batched_learned", blocks, True),
+                                     ("polar_smr_lat_batched_learned", smr, True)):
+            if learned_on and blob is None:
+                blob, train = train_guess(cfg, state, args.train_steps, log)
+            g = grmhd.Grid(cfg, blocks=bl, batched=True, mlp_blob=blob if learned_on else None)
+            if bl is smr:
+                lmax = [max(b["lev"][d] for b in bl) for d in range(3)]
+                g.set_blocks(initdata.block_states(state, bl, lmax))
+            else:
+                g.set_state(*state)
+            log(f"[bench] {name}: {len(bl)} blocks, levels {lats}, warmup 1 cycle, "
+                f"timed {cycles} cycles of {nsub} substeps")
+            g.step(1, stats=True)
+            st, wall = timed(g, cycles, sync)
+            results[name] = {"value_lat_effective": st.lat_eff_zone_cycles / wall,
+                             "value_amr_lat_effective": st.amr_lat_eff_zone_cycles / wall,
+                             "value_real": st.real_zone_cycles / wall,
+                             "ms_per_cycle": wall * 1e3 / cycles, "cycles": cycles,
+                             "substeps_per_cycle": nsub, "dt_min": st.dt_min,
+                             "steps_per_level": list(st.steps_per_level)[:L],
+                             "cells": sum(b["n"][0] * b["n"][1] * b["n"][2] for b in bl),
+                             "c2p": c2p_summary(st), "divb_rel_max": g.divb()[1]}
+            del g
+        head = results["lat_batched_learned"]
+        out.update({
+            "value": head["value_lat_effective"],
+            "ms_per_step": head["ms_per_cycle"] / nsub,
+            "config": {"workload": "torus-256x128x128-b32-ppm-hlle", "grid": list(cfg["n"]),
+                       "blocks": 128, "block": list(cfg["block"]), "recon": "PPM",
+                       "riemann": "HLLE", "c2p_tol": cfg["tol"],
+                       "path": "batched LAT (levels by radius, graph-captured cycle) + learned guess",
+                       "lat_levels": lats, "value_definition": "LAT-effective zone-cycles/s "
+                       "(all cells x finest-level steps / wall time)"},
+            "roofline": roofline,
+            "plain": plain,
+            "lat_batched": results["lat_batched"],
+            "lat_batched_learned": head,
+            "polar_smr_lat_batched_learned": results["polar_smr_lat_batched_learned"],
+            "learned_training": train,
+            "speedup_vs_plain": head["value_lat_effective"] / plain_value,
+        })
     if not args.no_cpu_baseline:
-        print(f"[bench] oracle on host, {args.cpu_steps} step(s) of the same grid", file=sys.stderr,
-              flush=True)
+        log(f"[bench] oracle on host, {args.cpu_steps} step(s) of the same grid")
         rate, secs = cpu_baseline(cfg, state, args.cpu_steps)
         out["cpu_baseline"] = {"value": rate, "unit": "zone-cycles/s", "cores": 1, "kind": "oracle",
                                "sample": f"{args.cpu_steps} full step(s) of the 256x128x128 grid "

@@ -146,6 +146,8 @@ int grmhd_step(grmhd_ctx* ctx, int32_t n_cycles, grmhd_step_stats* stats);
  *               sqrt(-g), lapse  (metrics with the Kerr-Schild sparsity pattern)
  *   guess[5][n] first guess primitives; prev[5][n] plain guess and failure fallback
  *   P[5][n] out primitives; iters[n], tier[n] out (tier as in grmhd_step_stats)
+ *   mlp_weights (nullable): a packed network blob (grmhd_mlp_pack); when set, the
+ *               first guess is the network's prediction and guess may be NULL
  * No floors are applied.  ctx may be NULL. */
 typedef struct {
   int64_t n;
@@ -159,6 +161,7 @@ typedef struct {
   double gamma_ad;
   double tol;
   int32_t maxit;
+  const void* mlp_weights;
 } grmhd_c2p_batch;
 int grmhd_cons2prim(grmhd_ctx* ctx, const grmhd_c2p_batch* batch, void* hip_stream);
 
@@ -181,8 +184,10 @@ int grmhd_divb(grmhd_ctx* ctx, double* max_abs, double* max_rel, double* field);
  * 24, local index, averaged dimensions of a restriction, 0); what = 9: the refinement
  * faces as 20 int32 each (coarse block, fine block, normal dimension, refined
  * dimensions, patch lo[3], hi[3] in coarse local indices, coarse plane, fine plane,
- * coarse origin[3], fine origin[3], positions, 0).  host_buf NULL queries the size in
- * bytes. */
+ * coarse origin[3], fine origin[3], positions, 0); what = 10: the schedule of one
+ * local-time-stepping cycle (Sec. 3.5) as int32 quadruples (substep, 0 = the block
+ * steps / 1 = the slow block is synchronised with a faster x1 neighbour, time level,
+ * block) in launch order.  host_buf NULL queries the size in bytes. */
 int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes);
 
 /* Planner geometry at one internal-coordinate point (host only, no device needed):

@@ -96,6 +96,7 @@ class AmrGrid(LatGrid):
         self.t = 0.0
         self.dt_min = 0.0
         self.steps = [0] * self.L
+        self.trace = []
         self.xnb = [self._x1_neighbours(i) for i in range(len(self.blocks))]
         self.links = self._refinement_faces()
 
@@ -427,6 +428,7 @@ class AmrGrid(LatGrid):
     def step_level(self, lev, s):
         dt = self.dt_min * 2 ** lev
         ids = [i for i, b in enumerate(self.blocks) if b["lat"] == lev]
+        self.trace += [(s, 0, lev, i) for i in ids]
         for i in ids:
             self.Pold[i] = self.P[i].copy()
             self.Bold[i] = self.B[i].copy()

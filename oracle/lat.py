@@ -59,6 +59,7 @@ class LatGrid:
         self.dt_min = 0.0
         self.steps = [0] * self.L
         self.bdx = [list(self.dx) for _ in self.blocks]
+        self.trace = []     # executed schedule: (substep, 0 step / 1 sync, level, block)
         self.xnb = [self._x1_neighbours(i) for i in range(len(self.blocks))]
 
     # ------------------------------------------------------------------ layout
@@ -169,6 +170,7 @@ class LatGrid:
     def step_level(self, lev, s):
         dt = self.dt_min * 2 ** lev
         ids = [i for i, b in enumerate(self.blocks) if b["lat"] == lev]
+        self.trace += [(s, 0, lev, i) for i in ids]
         for i in ids:
             self.Pold[i] = self.P[i].copy()
             self.Bold[i] = self.B[i].copy()
@@ -200,6 +202,7 @@ class LatGrid:
                 f = self.xnb[i].get(side)
                 if f is None or self.blocks[f]["lat"] != lat - 1:
                     continue
+                self.trace.append((s, 1, lat, i))
                 mine, theirs = self.reg_step[i][side], self.reg_pair[f][opp]
                 dF = (mine["F"] - theirs["F"]) / dx1 * sgn        # [9][n3][n2]
                 dE2 = theirs["E2"] - mine["E2"]                    # [n3+1][n2]

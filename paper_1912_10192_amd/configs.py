@@ -40,3 +40,35 @@ def scaled(cfg: dict, n, block=None, **kw) -> dict:
     out.update(kw)
     out["name"] = f"{cfg['name'].split('-')[0]}-{n[0]}x{n[1]}x{n[2]}"
     return out
+
+
+def polar_smr_blocks(n, b1, lats=None):
+    """Block layout of a log-spherical grid with coarser polar bands (paper Sec. 3.4,
+    external mesh refinement toward the poles), for an effective grid n = (N1, N2, N3):
+      equatorial band, theta rows [N2/4, 3 N2/4): full resolution (levels 1, 1, 2)
+      mid-latitude bands, [N2/8, N2/4) and mirror: half resolution in every dimension
+                                                    (levels 0, 0, 1)
+      polar caps, [0, N2/8) and mirror: half resolution in r and theta, a quarter in
+                                        phi (levels 0, 0, 0)
+    Blocks span b1 effective cells in x1 in every band (so x1 block faces line up and a
+    time level per x1 column applies to all bands); lats[i] is the time level of x1
+    column i."""
+    N1, N2, N3 = n
+    nb1 = N1 // b1
+    lats = list(lats) if lats is not None else [0] * nb1
+    out = []
+
+    def add(lev, org2, n2, nb3, n3):
+        f1 = b1 >> (1 - lev[0])
+        for k in range(nb3):
+            for i in range(nb1):
+                out.append(dict(org=(i * f1, org2, k * n3), n=(f1, n2, n3), lev=lev, lat=lats[i]))
+
+    r = N2 // 16            # rows of a polar cap / mid band at their (half) theta level
+    add((0, 0, 0), 0, r, 2, N3 // 8)                           # cap, theta < pi/8
+    add((0, 0, 1), r, r, 4, N3 // 8)                           # mid band
+    for j in range(2):                                         # equatorial band
+        add((1, 1, 2), N2 // 4 + j * (N2 // 4), N2 // 4, 4, N3 // 4)
+    add((0, 0, 1), N2 // 2 - 2 * r, r, 4, N3 // 8)             # mid band, southern
+    add((0, 0, 0), N2 // 2 - r, r, 2, N3 // 8)                 # cap, southern
+    return out

@@ -1300,11 +1300,12 @@ int grmhd_cons2prim(grmhd_ctx* c, const grmhd_c2p_batch* b, void* hip_stream) {
   (void)c;
   if (!b) return fail(GRMHD_EINVAL, "NULL batch");
   if (b->n < 0) return fail(GRMHD_EINVAL, "negative batch size");
-  if (b->n > 0 && (!b->U || !b->geom || !b->guess || !b->prev || !b->P || !b->iters || !b->tier))
+  if (b->n > 0 && (!b->U || !b->geom || !(b->guess || b->mlp_weights) || !b->prev || !b->P ||
+                   !b->iters || !b->tier))
     return fail(GRMHD_EINVAL, "NULL batch array");
   if (b->maxit < 1 || b->maxit > 62 || !(b->tol > 0.0)) return fail(GRMHD_EINVAL, "bad tol/maxit");
   launch_c2p_batch(b->n, b->U, b->geom, b->guess, b->prev, b->P, b->iters, b->tier, b->gamma_ad,
-                   b->tol, b->maxit, (hipStream_t)hip_stream);
+                   b->tol, b->maxit, b->mlp_weights, (hipStream_t)hip_stream);
   HIPCHK(hipGetLastError());
   return GRMHD_OK;
 }
@@ -1327,13 +1328,30 @@ int grmhd_divb(grmhd_ctx* c, double* max_abs, double* max_rel, double* field) {
 
 int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes) {
   if (!bytes) return fail(GRMHD_EINVAL, "NULL argument");
-  if (what < 0 || what > 9) return fail(GRMHD_EINVAL, "unknown table");
+  if (what < 0 || what > 10) return fail(GRMHD_EINVAL, "unknown table");
   Plan p;
   int rc = build_plan(desc, p, true);
   if (rc) return rc;
   const void* src;
   size_t need;
-  if (what < 4) {
+  std::vector<int32_t> sched;
+  if (what == 10) {
+    // the order in which one cycle steps and synchronises blocks (as lat_cycle launches
+    // them): per substep the due levels slowest first, then the sync points
+    const int L = p.nlev, nsub = 1 << (L - 1);
+    for (int s = 0; s < nsub; s++) {
+      for (int lev = L - 1; lev >= 0; lev--)
+        if (s % (1 << lev) == 0)
+          for (int64_t q = p.lev_boff[lev]; q < p.lev_boff[lev + 1]; q++)
+            sched.insert(sched.end(), {s, 0, lev, p.lev_blocks[q]});
+      for (int lev = 1; lev < L; lev++)
+        if ((s + 1) % (1 << lev) == 0)
+          for (int64_t q = p.item_off[lev]; q < p.item_off[lev + 1]; q++)
+            sched.insert(sched.end(), {s, 1, lev, p.items[q].slow});
+    }
+    src = sched.data();
+    need = sched.size() * sizeof(int32_t);
+  } else if (what < 4) {
     src = p.ops[what].data();
     need = p.ops[what].size() * sizeof(GhostOp);
   } else if (what < 8) {

@@ -159,6 +159,6 @@ void launch_dt_final_lat(const Launch& L, const double* part, int64_t n, int gri
 void launch_tsim_cycle(const Launch& L, double substeps);
 void launch_c2p_batch(int64_t n, const double* U, const double* geom, const double* guess,
                       const double* prev, double* P, int32_t* iters, int32_t* tier, double gam,
-                      double tol, int32_t maxit, hipStream_t stream);
+                      double tol, int32_t maxit, const void* mlp, hipStream_t stream);
 
 }  // namespace grmhd

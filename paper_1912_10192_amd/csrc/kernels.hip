@@ -635,6 +635,39 @@ __global__ __launch_bounds__(NT) void k_c2p_batch(int64_t n, const double* __res
   tier[i] = t;
 }
 
+// the same with the learned first guess: every lane of a workgroup takes part in the
+// network's wavefront products, lanes past the end with a copy of the last cell
+__global__ __launch_bounds__(NT) void k_c2p_batch_mlp(int64_t n, const double* __restrict__ U,
+                                                      const double* __restrict__ geom,
+                                                      const double* __restrict__ prev,
+                                                      double* __restrict__ P,
+                                                      int32_t* __restrict__ iters,
+                                                      int32_t* __restrict__ tier, double gam,
+                                                      double tol, int32_t maxit,
+                                                      const MlpBlob* __restrict__ mlp) {
+  const int64_t i0 = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const bool valid = i0 < n;
+  const int64_t i = valid ? i0 : n - 1;
+  const Metric m = load_metric(geom, n, i);
+  double u[9];
+#pragma unroll
+  for (int q = 0; q < 9; q++) u[q] = U[q * n + i];
+  C2PIn s;
+  c2p_setup(u, m, gam, s);
+  double W0 = 0.0, v0 = 0.0;
+  const bool first = mlp_guess_block(mlp, s, m, valid, W0, v0);
+  if (!valid) return;
+  double pv[5], out[5];
+#pragma unroll
+  for (int v = 0; v < 5; v++) pv[v] = prev[v * n + i];
+  int it = 0;
+  const int t = c2p_solve(s, m, first, W0, v0, pv, tol, maxit, out, it);
+#pragma unroll
+  for (int v = 0; v < 5; v++) P[v * n + i] = out[v];
+  iters[i] = it;
+  tier[i] = t;
+}
+
 // ================================================================== launchers
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
@@ -737,10 +770,14 @@ void launch_divb(const Launch& L, const double* B, double* field) {
 
 void launch_c2p_batch(int64_t n, const double* U, const double* geom, const double* guess,
                       const double* prev, double* P, int32_t* iters, int32_t* tier, double gam,
-                      double tol, int32_t maxit, hipStream_t stream) {
+                      double tol, int32_t maxit, const void* mlp, hipStream_t stream) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_c2p_batch, dim3(cdiv(n, NT)), dim3(NT), 0, stream, n, U, geom, guess, prev,
-                     P, iters, tier, gam, tol, maxit);
+  if (mlp)
+    hipLaunchKernelGGL(k_c2p_batch_mlp, dim3(cdiv(n, NT)), dim3(NT), 0, stream, n, U, geom, prev,
+                       P, iters, tier, gam, tol, maxit, (const MlpBlob*)mlp);
+  else
+    hipLaunchKernelGGL(k_c2p_batch, dim3(cdiv(n, NT)), dim3(NT), 0, stream, n, U, geom, guess,
+                       prev, P, iters, tier, gam, tol, maxit);
 }
 
 }  // namespace grmhd

@@ -70,7 +70,7 @@ class C2PBatch(C.Structure):
     _fields_ = [("n", C.c_int64), ("U", C.c_void_p), ("geom", C.c_void_p), ("guess", C.c_void_p),
                 ("prev", C.c_void_p), ("P", C.c_void_p), ("iters", C.c_void_p),
                 ("tier", C.c_void_p), ("gamma_ad", C.c_double), ("tol", C.c_double),
-                ("maxit", C.c_int32)]
+                ("maxit", C.c_int32), ("mlp_weights", C.c_void_p)]
 
 
 class GrmhdError(RuntimeError):
@@ -378,16 +378,18 @@ class Grid:
         return a.value, r.value
 
 
-def cons2prim_batch(U, geom, guess, prev, gam, tol=1e-12, maxit=50):
-    """flat-batch inversion on the GPU; all inputs float64 CUDA tensors [k][n]"""
+def cons2prim_batch(U, geom, guess, prev, gam, tol=1e-12, maxit=50, mlp_blob=None):
+    """flat-batch inversion on the GPU; all inputs float64 CUDA tensors [k][n]; with
+    mlp_blob the first guess is the network's (guess may be None)"""
     import torch
 
     n = U.shape[1]
     P = torch.empty((5, n), dtype=torch.float64, device=U.device)
     iters = torch.empty(n, dtype=torch.int32, device=U.device)
     tier = torch.empty(n, dtype=torch.int32, device=U.device)
-    b = C2PBatch(n, U.data_ptr(), geom.data_ptr(), guess.data_ptr(), prev.data_ptr(), P.data_ptr(),
-                 iters.data_ptr(), tier.data_ptr(), gam, tol, maxit)
+    b = C2PBatch(n, U.data_ptr(), geom.data_ptr(), guess.data_ptr() if guess is not None else None,
+                 prev.data_ptr(), P.data_ptr(), iters.data_ptr(), tier.data_ptr(), gam, tol, maxit,
+                 mlp_blob.data_ptr() if mlp_blob is not None else None)
     stream = torch.cuda.current_stream(U.device)
     _check(lib().grmhd_cons2prim(None, C.byref(b), C.c_void_p(stream.cuda_stream)))
     return P, iters, tier

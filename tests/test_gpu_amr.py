@@ -100,3 +100,17 @@ def test_refined_graph_cycle_is_bit_identical():
     for x, y in zip(a.get_blocks(), b.get_blocks()):
         for u, v in zip(x, y):
             assert np.array_equal(u, v)
+
+
+def test_torus_three_level_polar_bands_match_oracle():
+    """coarse mid-latitude bands (half resolution) and polar caps (a quarter in phi),
+    with two time levels along x1"""
+    eff = (32, 64, 32)
+    cfg = configs.scaled(configs.TORUS_UNIFORM, eff, ng=3)
+    state = initdata.torus_state(eff, **configs.TORUS_INIT)
+    grid, ref, worst = run_pair(cfg, configs.polar_smr_blocks(eff, 16, [0, 1]), state, 2,
+                                batched=True)
+    assert max(worst.values()) <= TOL, worst
+    a, r = grid.divb()
+    say(f"  divB rel {r:.2e}")
+    assert r < 1e-12

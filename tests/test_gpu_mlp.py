@@ -137,3 +137,39 @@ def test_learned_guess_keeps_the_evolution():
     for v in (2, 3, 4):
         assert np.abs(a[0][v] - b[0][v]).max() <= 1e-11 * np.abs(a[0][v]).max()
     assert sm.c2p_tier[4] == 0
+
+
+def test_learned_guess_gain_over_a_cold_start():
+    """What the network adds where no previous state exists (a standalone inversion of
+    conserved states): Newton from the learned guess against Newton from a generic
+    start (density D, internal energy D, at rest), both at tolerance 1e-12 with the
+    same fallbacks.  Inside the evolution the previous step's state is already an
+    excellent start (see the test above); this measures the cold-start case."""
+    torch = _torch()
+    cfg = configs.scaled(configs.TORUS_UNIFORM, (64, 32, 32), block=(32, 32, 32))
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    blob, _ = _trained_blob(cfg, state)
+    grid = grmhd.Grid(cfg, state=state)
+    grid.step(6)
+    P, B, G = grid.extract_cells()
+    P2, B2, G2 = learned.synthetic_states(G, 200000, seed=99)      # held-out draws
+    gam = cfg["gam"]
+    for name, (p, b, g) in (("torus cells", (P, B, G)), ("synthetic", (P2, B2, G2))):
+        U = grmhd.prim2cons_batch(p, b, g, gam)
+        D = g[14] * U[0] / g[13]
+        cold = torch.zeros_like(p)
+        cold[0] = D
+        cold[1] = D
+        Pc, ic, tc = grmhd.cons2prim_batch(U, g, cold, cold, gam)
+        Pm, im, tm = grmhd.cons2prim_batch(U, g, None, cold, gam, mlp_blob=blob)
+        ic, tc, im, tm = (x.cpu().numpy() for x in (ic, tc, im, tm))
+        ok = (tc <= 1) & (tm <= 1)
+        mc, mm = ic[tc == 0].mean(), im[tm == 0].mean()
+        say(f"[mlp] cold start, {name}: mean Newton iterations generic {mc:.2f} learned {mm:.2f}; "
+            f"first-guess failures generic {(tc >= 1).mean():.4f} learned {(tm >= 1).mean():.4f}; "
+            f"tiers generic {np.bincount(tc, minlength=5)} learned {np.bincount(tm, minlength=5)}")
+        # both reach the same root where both Newton solves converged
+        a, b2 = Pc.cpu().numpy()[:, ok], Pm.cpu().numpy()[:, ok]
+        assert np.max(np.abs(a[0] - b2[0]) / a[0]) < 1e-10
+        assert mm < mc
+        assert (tm >= 1).mean() <= (tc >= 1).mean()

@@ -138,3 +138,28 @@ def test_lat_layout_checks():
     with pytest.raises(grmhd.GrmhdError, match="x1 block faces"):
         grmhd.Desc(cfg, blocks=bl).sizes()
     assert grmhd.lat_levels_by_radius(configs.TORUS_UNIFORM, [2.4, 4.8, 9.6]) == [0, 0, 1, 2, 2, 3, 3, 3]
+
+
+@pytest.mark.parametrize("lats", [[0, 1, 2, 1], [0, 0, 1, 2, 2, 3, 2, 1], [1, 0, 1, 2]])
+def test_lat_schedule_matches_oracle_driver(lats):
+    """the library's cycle schedule (which blocks step at which substep, slowest level
+    first, and which slow blocks synchronise when) equals the order the oracle's driver
+    executes, entry for entry"""
+    from oracle.lat import LatGrid
+    n = (8 * len(lats), 6, 6)
+    cfg = dict(mink_cfg(n, recon=1, riemann=1), block=(8, 3, 6))
+    blocks = grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=lats)
+    desc = grmhd.Desc(cfg, blocks=blocks)
+    mine = [tuple(int(x) for x in r) for r in desc.plan_dump(10)]
+    ref = LatGrid(cfg, blocks)
+    from tests.helpers import random_periodic_state
+    ref.set_state(*random_periodic_state(cfg["n"], seed=2, amp=0.02, vamp=0.05, bamp=0.05))
+    ref.cycle()
+    want = ref.trace
+    # steps: identical sequence; syncs at a sync point: the same set (order-free)
+    assert [t for t in mine if t[1] == 0] == [t for t in want if t[1] == 0]
+    key = lambda t: (t[0], t[2], t[3])
+    assert sorted((t for t in mine if t[1] == 1), key=key) == sorted((t for t in want if t[1] == 1), key=key)
+    # and the sync points fall between the same steps
+    pos = lambda seq: [(seq[i - 1][:2] if i else None, t[0]) for i, t in enumerate(seq) if t[1] == 1]
+    assert sorted(set(pos(mine))) == sorted(set(pos(want)))
