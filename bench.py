@@ -171,6 +171,8 @@ def main():
 
     # ---- plain path: global time step, one launch per kernel and stage, plain guess
     grid = grmhd.Grid(cfg, state=state, profile=True)
+    tune = grid.autotune()
+    log(f"[bench] autotuned variants {tune}")
     log(f"[bench] plain: warmup {args.warmup}, timed {args.steps} steps")
     if args.warmup:
         grid.step(args.warmup, stats=True)
@@ -197,6 +199,7 @@ def main():
                 "frac": achieved / peak, "traffic": traffic, "kernel": dom,
                 "launch_ms": avg_s * 1e3, "units_per_launch": units, "kernel_hash": khash}
     plain = {"value": plain_value, "ms_per_step": wall * 1e3 / args.steps, "dt": st.dt_min,
+             "autotune": tune,
              "c2p": c2p_summary(st), "divb_rel_max": r_div,
              "kernel_ms_per_step": {k: v / args.steps for k, v in cls_ms.items()}}
     del grid
@@ -229,6 +232,7 @@ def main():
                 g.set_blocks(initdata.block_states(state, bl, lmax))
             else:
                 g.set_state(*state)
+            g.autotune()
             log(f"[bench] {name}: {len(bl)} blocks, levels {lats}, warmup 1 cycle, "
                 f"timed {cycles} cycles of {nsub} substeps")
             g.step(1, stats=True)

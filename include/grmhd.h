@@ -140,6 +140,17 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
  * receives counters for this call; passing it synchronises the stream. */
 int grmhd_step(grmhd_ctx* ctx, int32_t n_cycles, grmhd_step_stats* stats);
 
+/* Autotuner of the two heavy kernels.  The flux kernel (per direction) and the update
+ * kernel are built in occupancy variants (the minimum waves per SIMD the compiler must
+ * fit: flux 1, 2, 4; update 1, 2).  This times every variant on the context's current
+ * state (one predictor stage, three launches each after a warm-up) and keeps the
+ * fastest for all later launches; without a call the flux kernel uses 4 and the update
+ * 1.  choice (host, nullable) receives the chosen variant indices (flux x1, x2, x3,
+ * update); ms (host, nullable, 11 doubles) the mean milliseconds per variant (flux x1
+ * variants, x2, x3, then update).  The state is not modified; counters are reset;
+ * synchronises. */
+int grmhd_autotune(grmhd_ctx* ctx, int32_t choice[4], double* ms);
+
 /* Standalone inversion of a flat batch (Sec. 2.6), all pointers device memory:
  *   U[9][n]     conserved state incl. sqrt(-g): rho u^t, T^t_t + rho u^t, T^t_i, B^i, kappa rho u^t
  *   geom[15][n] g_tt g_t1 g_t3 g_11 g_13 g_22 g_33, g^tt g^t1 g^11 g^13 g^22 g^33,

@@ -1040,6 +1040,8 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   L.ph.ng = desc->n_ghost;
   L.cnt = (Counters*)(w + p.o_cnt);
   L.stream = c->stream;
+  for (int k = 0; k < 3; k++) L.var_flux[k] = NVAR_FLUX - 1;   // 4 waves per SIMD
+  L.var_upd = 0;
   c->profile = desc->profile != 0;
   c->mlp = desc->c2p_guess == GRMHD_GUESS_MLP ? desc->mlp_weights : nullptr;
   launch_counters_reset(L, true);
@@ -1292,6 +1294,86 @@ int grmhd_step(grmhd_ctx* c, int32_t n_cycles, grmhd_step_stats* stats) {
       stats->class_ms[q] = cls_ms[q];
       stats->class_launches[q] = cls_n[q];
     }
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_autotune(grmhd_ctx* c, int32_t choice[4], double* ms) {
+  if (!c) return fail(GRMHD_EINVAL, "NULL context");
+  if (c->b_in_alt) return fail(GRMHD_ESTATE, "state not in the caller's buffers");
+  Launch& L = c->L;
+  double* P = c->bufs.prim;
+  double* B = c->bufs.bface;
+  const bool prof = c->profile;
+  c->profile = false;
+  fill_ghosts(c, P, B);
+  launch_counters_reset(L, false);
+  launch_dt(L, P, B, c->dtp);
+  launch_dt_final(L, c->dtp);
+  launch_bcell(L, B, c->bc);
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  const int reps = 3;
+  auto time_it = [&](auto fn, double& out) -> int {
+    fn();   // warm-up (code object load, caches)
+    HIPCHK(hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; r++) fn();
+    HIPCHK(hipEventRecord(e1, c->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0.0f;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    out = t / reps;
+    return GRMHD_OK;
+  };
+  int rc = GRMHD_OK;
+  const int recon = c->plan.d.recon, riem = c->plan.d.riemann;
+  for (int dir = 1; dir <= 3 && !rc; dir++) {
+    double best = 1e300;
+    int arg = L.var_flux[dir - 1];
+    for (int v = 0; v < NVAR_FLUX && !rc; v++) {
+      L.var_flux[dir - 1] = v;
+      double t = 0.0;
+      rc = time_it([&] { launch_flux(L, dir, recon, riem, P, c->bc, B, c->f); }, t);
+      if (ms) ms[(dir - 1) * NVAR_FLUX + v] = t;
+      if (t < best) { best = t; arg = v; }
+    }
+    L.var_flux[dir - 1] = arg;
+  }
+  if (!rc) {
+    launch_emf(L, c->f, c->e);
+    double best = 1e300;
+    int arg = L.var_upd;
+    for (int v = 0; v < NVAR_UPD && !rc; v++) {
+      L.var_upd = v;
+      double t = 0.0;
+      rc = time_it([&] {
+        launch_update(L, P, B, P, c->bc, c->f, c->e, 0.5, c->ps, c->balt, nullptr, c->mlp);
+      }, t);
+      if (ms) ms[3 * NVAR_FLUX + v] = t;
+      if (t < best) { best = t; arg = v; }
+    }
+    L.var_upd = arg;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->profile = prof;
+  if (rc) return rc;
+  launch_counters_reset(L, false);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  // a captured cycle holds the previous choices: capture again on the next step
+  if (c->graph_exec) {
+    (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+  }
+  if (c->graph) {
+    (void)hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  if (choice) {
+    for (int k = 0; k < 3; k++) choice[k] = L.var_flux[k];
+    choice[3] = L.var_upd;
   }
   return GRMHD_OK;
 }

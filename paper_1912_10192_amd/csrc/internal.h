@@ -98,6 +98,9 @@ __host__ __device__ inline int64_t geo_col(const GeoTab&, const BlockInfo& bi, i
   return bi.gbase + (int64_t)(bi.gorg[1] + J) * bi.gti + (bi.gorg[0] + I);
 }
 
+// occupancy variants of the flux and update kernels (see kernels.hip)
+constexpr int NVAR_FLUX = 3, NVAR_UPD = 2;
+
 struct Launch {
   const BlockInfo* blk;   // device block table
   const int32_t* blist;   // device list of the blocks a launch covers (NULL = all)
@@ -108,6 +111,8 @@ struct Launch {
   Phys ph;
   Counters* cnt;
   hipStream_t stream;
+  int32_t var_flux[3];    // variant of the flux kernel per direction
+  int32_t var_upd;        // variant of the update kernel
 };
 
 // records the message returned by grmhd_last_error() and returns code (host.cpp)

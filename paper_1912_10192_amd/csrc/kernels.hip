@@ -17,23 +17,11 @@ namespace grmhd {
 
 constexpr int NT = 256;   // threads per workgroup (four wavefronts)
 
-// optional occupancy targets (waves per SIMD) for the two heavy kernels
-#ifndef GRMHD_FLUX_WAVES
-#define GRMHD_FLUX_WAVES 4
-#endif
-#ifndef GRMHD_UPDATE_WAVES
-#define GRMHD_UPDATE_WAVES 0
-#endif
-#if GRMHD_FLUX_WAVES > 0
-#define FLUX_OCC __attribute__((amdgpu_waves_per_eu(GRMHD_FLUX_WAVES)))
-#else
-#define FLUX_OCC
-#endif
-#if GRMHD_UPDATE_WAVES > 0
-#define UPDATE_OCC __attribute__((amdgpu_waves_per_eu(GRMHD_UPDATE_WAVES)))
-#else
-#define UPDATE_OCC
-#endif
+// The two heavy kernels come in occupancy variants: the minimum number of waves per
+// SIMD the compiler must fit (trading registers for latency hiding).  Which variant a
+// launch uses is the autotuner's choice (Launch::var_flux, Launch::var_upd).
+constexpr int FLUX_OCC[NVAR_FLUX] = {1, 2, 4};
+constexpr int UPD_OCC[NVAR_UPD] = {1, 2};
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
@@ -162,8 +150,8 @@ __global__ __launch_bounds__(NT) void k_bcell(Launch L, const double* __restrict
 
 // One thread per face along x^DIR.  Normal range [ng, ng + n], transverse range widened
 // by one ghost layer so the edge EMFs of every interior face have their four fluxes.
-template <int DIR, int RECON, int RIEMANN>
-__global__ __launch_bounds__(NT) FLUX_OCC void k_flux(Launch L, const double* __restrict__ P,
+template <int DIR, int RECON, int RIEMANN, int OCC>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_flux(Launch L, const double* __restrict__ P,
                                              const double* __restrict__ Bc,
                                              const double* __restrict__ B,
                                              double* __restrict__ F) {
@@ -340,8 +328,8 @@ __device__ __forceinline__ bool mlp_guess_block(const MlpBlob* __restrict__ blob
   return isfinite(W0) && W0 > 0.0 && v0 >= 0.0 && v0 < 1.0;
 }
 
-template <bool STATS, bool NEXT_DT, bool MLP>
-__global__ __launch_bounds__(NT) UPDATE_OCC void k_update(Launch L, const double* __restrict__ Pn,
+template <bool STATS, bool NEXT_DT, bool MLP, int OCC>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_update(Launch L, const double* __restrict__ Pn,
                                                const double* __restrict__ Bn,
                                                const double* __restrict__ Ps,
                                                const double* __restrict__ Bcs,
@@ -694,14 +682,23 @@ static void flux_dir(const Launch& L, int recon, int riemann, const double* P, c
   int64_t r = 1;
   for (int d = 0; d < 3; d++) r *= (d == DIR - 1) ? L.max_n[d] + 1 : L.max_n[d] + 2;
   const dim3 grid(cdiv(r, NT), L.nblk);
-  if (recon == 0 && riemann == 0)
-    hipLaunchKernelGGL((k_flux<DIR, 0, 0>), grid, dim3(NT), 0, L.stream, L, P, Bc, B, F);
-  else if (recon == 0)
-    hipLaunchKernelGGL((k_flux<DIR, 0, 1>), grid, dim3(NT), 0, L.stream, L, P, Bc, B, F);
-  else if (riemann == 0)
-    hipLaunchKernelGGL((k_flux<DIR, 1, 0>), grid, dim3(NT), 0, L.stream, L, P, Bc, B, F);
-  else
-    hipLaunchKernelGGL((k_flux<DIR, 1, 1>), grid, dim3(NT), 0, L.stream, L, P, Bc, B, F);
+  const int v = L.var_flux[DIR - 1];
+#define GRMHD_FLUX(RC, RM, V)                                                                \
+  hipLaunchKernelGGL((k_flux<DIR, RC, RM, FLUX_OCC[V]>), grid, dim3(NT), 0, L.stream, L, P, Bc, \
+                     B, F)
+#define GRMHD_FLUX_V(RC, RM) \
+  if (v == 0) GRMHD_FLUX(RC, RM, 0); else if (v == 1) GRMHD_FLUX(RC, RM, 1); else GRMHD_FLUX(RC, RM, 2)
+  if (recon == 0 && riemann == 0) {
+    GRMHD_FLUX_V(0, 0);
+  } else if (recon == 0) {
+    GRMHD_FLUX_V(0, 1);
+  } else if (riemann == 0) {
+    GRMHD_FLUX_V(1, 0);
+  } else {
+    GRMHD_FLUX_V(1, 1);
+  }
+#undef GRMHD_FLUX_V
+#undef GRMHD_FLUX
 }
 
 void launch_flux(const Launch& L, int dir, int recon, int riemann, const double* P,
@@ -727,18 +724,22 @@ void launch_update(const Launch& L, const double* Pn, const double* Bn, const do
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
   const dim3 grid(cdiv(r, NT), L.nblk);
   const MlpBlob* blob = (const MlpBlob*)mlp;
-  if (dt_part && blob)
-    hipLaunchKernelGGL((k_update<true, true, true>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps,
-                       Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob);
-  else if (dt_part)
-    hipLaunchKernelGGL((k_update<true, true, false>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps,
-                       Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob);
-  else if (blob)
-    hipLaunchKernelGGL((k_update<true, false, true>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps,
-                       Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob);
-  else
-    hipLaunchKernelGGL((k_update<true, false, false>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps,
-                       Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob);
+#define GRMHD_UPD(ND, ML, V)                                                                   \
+  hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V]>), grid, dim3(NT), 0, L.stream, L, Pn, \
+                     Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob)
+#define GRMHD_UPD_V(ND, ML) \
+  if (L.var_upd == 0) GRMHD_UPD(ND, ML, 0); else GRMHD_UPD(ND, ML, 1)
+  if (dt_part && blob) {
+    GRMHD_UPD_V(true, true);
+  } else if (dt_part) {
+    GRMHD_UPD_V(true, false);
+  } else if (blob) {
+    GRMHD_UPD_V(false, true);
+  } else {
+    GRMHD_UPD_V(false, false);
+  }
+#undef GRMHD_UPD_V
+#undef GRMHD_UPD
 }
 
 void launch_dt(const Launch& L, const double* P, const double* B, double* dt_part) {

@@ -28,7 +28,8 @@ EXPORTS = ("grmhd_sizes", "grmhd_block_layout", "grmhd_init_grid", "grmhd_step",
            "grmhd_cons2prim", "grmhd_divb", "grmhd_plan_dump", "grmhd_geometry_point",
            "grmhd_mlp_sizes", "grmhd_mlp_train_step", "grmhd_mlp_gradients", "grmhd_mlp_pack",
            "grmhd_mlp_forward", "grmhd_prim2cons_batch", "grmhd_mlp_dataset",
-           "grmhd_mlp_normalize", "grmhd_extract_cells", "grmhd_destroy", "grmhd_last_error")
+           "grmhd_mlp_normalize", "grmhd_extract_cells", "grmhd_destroy", "grmhd_last_error",
+           "grmhd_autotune")
 
 
 class BlockDesc(C.Structure):
@@ -91,6 +92,7 @@ def lib():
         L.grmhd_init_grid.argtypes = [C.POINTER(GridDesc), C.POINTER(Buffers), C.c_void_p,
                                       C.POINTER(C.c_void_p)]
         L.grmhd_step.argtypes = [C.c_void_p, C.c_int32, C.POINTER(StepStats)]
+        L.grmhd_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.grmhd_cons2prim.argtypes = [C.c_void_p, C.POINTER(C2PBatch), C.c_void_p]
         L.grmhd_divb.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.c_void_p]
@@ -371,6 +373,16 @@ class Grid:
         G = torch.empty((15, n), dtype=torch.float64, device=self.device)
         _check(lib().grmhd_extract_cells(self.ctx, P.data_ptr(), B.data_ptr(), G.data_ptr()))
         return P, B, G
+
+    def autotune(self):
+        """time the kernel variants on the current state and keep the fastest; returns
+        the chosen variants and the milliseconds per variant"""
+        choice = (C.c_int32 * 4)()
+        ms = (C.c_double * 11)()
+        _check(lib().grmhd_autotune(self.ctx, choice, ms))
+        return {"flux": [choice[k] for k in range(3)], "update": choice[3],
+                "flux_ms": [[ms[d * 3 + v] for v in range(3)] for d in range(3)],
+                "update_ms": [ms[9], ms[10]]}
 
     def divb(self):
         a, r = C.c_double(), C.c_double()

@@ -158,3 +158,21 @@ def test_cons2prim_batch_round_trip():
     assert np.array_equal(tier, want_tier)
     rel = np.abs(Pg[0, ok] / P0[0, ok] - 1)
     assert rel.max() < 1e-10
+
+
+def test_autotuned_variants_keep_the_result():
+    """the autotuner only picks among occupancy variants of the same arithmetic: a tuned
+    grid steps to the same state as an untuned one"""
+    cfg = configs.scaled(configs.TORUS_UNIFORM, (64, 32, 32), block=(32, 32, 32))
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    a = grmhd.Grid(cfg, state=state)
+    b = grmhd.Grid(cfg, state=state)
+    choice = b.autotune()
+    print(f"[tune] {choice}", file=sys.stderr, flush=True)
+    assert all(0 <= v < 3 for v in choice["flux"]) and choice["update"] in (0, 1)
+    a.step(2)
+    b.step(2)
+    same = all(np.array_equal(x, y) for x, y in zip(a.get_state(), b.get_state()))
+    print(f"[tune] bit-identical: {same}", file=sys.stderr, flush=True)
+    e = parity_err(b.get_state(), a.get_state())
+    assert max(e.values()) <= 1e-13, e
