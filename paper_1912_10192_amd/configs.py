@@ -72,3 +72,11 @@ def polar_smr_blocks(n, b1, lats=None):
     add((0, 0, 1), N2 // 2 - 2 * r, r, 4, N3 // 8)             # mid band, southern
     add((0, 0, 0), N2 // 2 - r, r, 2, N3 // 8)                 # cap, southern
     return out
+
+
+# Batched refinement + local time stepping: effective 512x256x256 with coarser polar
+# bands (polar_smr_blocks, 64-cell x1 block columns) and 4 time levels by the inner
+# radius of each x1 column (r < 2.4 -> 0, < 4.8 -> 1, < 9.6 -> 2, else 3)
+TORUS_AMR_LAT = dict(KS_TORUS_BASE, name="torus-eff512x256x256-polar-smr-lat4", n=(512, 256, 256),
+                     block=(64, 64, 64), ng=3, recon=1, riemann=1, cycles=25,
+                     lat_edges=(2.4, 4.8, 9.6))

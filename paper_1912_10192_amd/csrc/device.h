@@ -134,8 +134,10 @@ __device__ __forceinline__ void wave_speeds(const double P[5], const Fluid& f, c
                                             double gam, double& vmax, double& vmin) {
   const double p = (gam - 1.0) * P[1];
   const double w = P[0] + P[1] + p;
-  const double cs2 = gam * p / w;
-  const double va2 = f.bsq / (f.bsq + w);
+  const double wb = f.bsq + w;
+  const double r = 1.0 / (w * wb);          // one division for both ratios
+  const double cs2 = gam * p * wb * r;
+  const double va2 = f.bsq * w * r;
   const double cms2 = va2 + cs2 * (1.0 - va2);
   const double ut = f.ucon[0], ud = f.ucon[D];
   const double h0d = D == 1 ? m.h01 : 0.0;
@@ -186,9 +188,10 @@ __device__ __forceinline__ void recon_face(const double s[6], double& left, doub
     const double d2 = mc_lim(s[2] - s[1], s[3] - s[2]);
     const double d3 = mc_lim(s[3] - s[2], s[4] - s[3]);
     const double d4 = mc_lim(s[4] - s[3], s[5] - s[4]);
-    const double f15 = 0.5 * (s[1] + s[2]) - (d2 - d1) / 6.0;
-    const double f25 = 0.5 * (s[2] + s[3]) - (d3 - d2) / 6.0;
-    const double f35 = 0.5 * (s[3] + s[4]) - (d4 - d3) / 6.0;
+    constexpr double sixth = 1.0 / 6.0;   // a multiply instead of three divisions
+    const double f15 = 0.5 * (s[1] + s[2]) - (d2 - d1) * sixth;
+    const double f25 = 0.5 * (s[2] + s[3]) - (d3 - d2) * sixth;
+    const double f35 = 0.5 * (s[3] + s[4]) - (d4 - d3) * sixth;
     double l2 = f15, r2 = f25, l3 = f25, r3 = f35;
     ppm_limit(s[2], l2, r2);
     ppm_limit(s[3], l3, r3);

@@ -673,6 +673,7 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
       p.max_np[k] = std::max(p.max_np[k], bi.np[k]);
       p.max_n[k] = std::max(p.max_n[k], bi.n[k]);
       bi.dx[k] = (desc->xmax[k] - desc->xmin[k]) / (double)N[k];
+      bi.idx[k] = 1.0 / bi.dx[k];
     }
     bi.gorg[0] = (int32_t)bd.org[0];
     bi.gorg[1] = (int32_t)bd.org[1];

@@ -16,6 +16,7 @@ struct BlockInfo {
   int32_t gti;      // row length of the block's geometry table
   int64_t gbase;    // first column of the block's geometry table (one table per x1-x2 level)
   double dx[3];     // cell spacing at the block's refinement level
+  double idx[3];    // 1 / dx
 };
 
 // one ghost copy: destination (block, local), source (block | flags << 24, local)

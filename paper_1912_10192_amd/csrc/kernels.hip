@@ -290,16 +290,16 @@ __device__ __forceinline__ double block_min(double v) {
 
 // per cell 1/dt = sum_d max(|v+|, |v-|)/dx_d from the cell-centred state (Sec. 2.1)
 __device__ __forceinline__ double cell_dt(const double P[5], const double B[3], const Metric& m,
-                                          const Phys& ph, const double dx[3]) {
+                                          const Phys& ph, const double idx[3]) {
   Fluid f;
   fluid_state(P, B, m, f);
   double vp, vm, inv = 0.0;
   wave_speeds<1>(P, f, m, ph.gam, vp, vm);
-  inv += fmax(fabs(vp), fabs(vm)) / dx[0];
+  inv += fmax(fabs(vp), fabs(vm)) * idx[0];
   wave_speeds<2>(P, f, m, ph.gam, vp, vm);
-  inv += fmax(fabs(vp), fabs(vm)) / dx[1];
+  inv += fmax(fabs(vp), fabs(vm)) * idx[1];
   wave_speeds<3>(P, f, m, ph.gam, vp, vm);
-  inv += fmax(fabs(vp), fabs(vm)) / dx[2];
+  inv += fmax(fabs(vp), fabs(vm)) * idx[2];
   return 1.0 / inv;
 }
 
@@ -358,7 +358,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   if (valid) {
     const double dt = L.ph.courant * __longlong_as_double((long long)L.cnt->dt_bits);
     const double dts = dt_factor * dt;
-    const double dx1 = bi.dx[0], dx2 = bi.dx[1], dx3 = bi.dx[2];
+    const double ix1 = bi.idx[0], ix2 = bi.idx[1], ix3 = bi.idx[2];
     const double* e1 = E + 3 * bi.off;
     const double* e2 = e1 + V;
     const double* e3 = e2 + V;
@@ -368,16 +368,16 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     const bool pole_lo = G.f2[GDET * G.ncol + col] == 0.0;
     const bool pole_hi = G.f2[GDET * G.ncol + col + bi.gti] == 0.0;
     // constrained transport of the six faces of this cell (Sec. 2.5)
-    const double nb1lo = b1[l] + dts * ((e2[l + s3] - e2[l]) / dx3 - (e3[l + s2] - e3[l]) / dx2);
+    const double nb1lo = b1[l] + dts * ((e2[l + s3] - e2[l]) * ix3 - (e3[l + s2] - e3[l]) * ix2);
     const double nb1hi =
-        b1[l + 1] + dts * ((e2[l + 1 + s3] - e2[l + 1]) / dx3 - (e3[l + 1 + s2] - e3[l + 1]) / dx2);
+        b1[l + 1] + dts * ((e2[l + 1 + s3] - e2[l + 1]) * ix3 - (e3[l + 1 + s2] - e3[l + 1]) * ix2);
     const double nb2lo = pole_lo ? 0.0
-        : b2[l] + dts * ((e3[l + 1] - e3[l]) / dx1 - (e1[l + s3] - e1[l]) / dx3);
+        : b2[l] + dts * ((e3[l + 1] - e3[l]) * ix1 - (e1[l + s3] - e1[l]) * ix3);
     const double nb2hi = pole_hi ? 0.0
-        : b2[l + s2] + dts * ((e3[l + s2 + 1] - e3[l + s2]) / dx1 - (e1[l + s2 + s3] - e1[l + s2]) / dx3);
-    const double nb3lo = b3[l] + dts * ((e1[l + s2] - e1[l]) / dx2 - (e2[l + 1] - e2[l]) / dx1);
+        : b2[l + s2] + dts * ((e3[l + s2 + 1] - e3[l + s2]) * ix1 - (e1[l + s2 + s3] - e1[l + s2]) * ix3);
+    const double nb3lo = b3[l] + dts * ((e1[l + s2] - e1[l]) * ix2 - (e2[l + 1] - e2[l]) * ix1);
     const double nb3hi =
-        b3[l + s3] + dts * ((e1[l + s3 + s2] - e1[l + s3]) / dx2 - (e2[l + s3 + 1] - e2[l + s3]) / dx1);
+        b3[l + s3] + dts * ((e1[l + s3 + s2] - e1[l + s3]) * ix2 - (e2[l + s3 + 1] - e2[l + s3]) * ix1);
     double* o1 = Bout + 3 * bi.off;
     double* o2 = o1 + V;
     double* o3 = o2 + V;
@@ -395,9 +395,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
       double P0[5], B0[3];
 #pragma unroll
       for (int v = 0; v < 5; v++) P0[v] = Pn[5 * bi.off + (int64_t)v * V + l];
-      B0[0] = 0.5 * (b1[l] + b1[l + 1]) / m.gdet;
-      B0[1] = 0.5 * (b2[l] + b2[l + s2]) / m.gdet;
-      B0[2] = 0.5 * (b3[l] + b3[l + s3]) / m.gdet;
+      const double hg = 0.5 / m.gdet;
+      B0[0] = (b1[l] + b1[l + 1]) * hg;
+      B0[1] = (b2[l] + b2[l + s2]) * hg;
+      B0[2] = (b3[l] + b3[l + s3]) * hg;
       Fluid f;
       fluid_state(P0, B0, m, f);
       flux_vector<0>(P0, f, m, L.ph.gam, entropy_kappa(P0, L.ph.gam), U);
@@ -421,8 +422,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
 #pragma unroll
     for (int k = 0; k < 6; k++) {
       const int64_t o = (int64_t)fq[k] * V;
-      const double div = (f1[o + 1] - f1[o]) / dx1 + (f2[o + s2] - f2[o]) / dx2 +
-                         (f3[o + s3] - f3[o]) / dx3;
+      const double div = (f1[o + 1] - f1[o]) * ix1 + (f2[o + s2] - f2[o]) * ix2 +
+                         (f3[o + s3] - f3[o]) * ix3;
       const double q = (k >= 1 && k <= 4) ? Q[k - 1] : 0.0;
       U[uq[k]] = U[uq[k]] - dts * div + dts * q;
     }
@@ -444,7 +445,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                         L.ph.bsq_rho_max, L.ph.bsq_u_max, L.ph.gamma_max);
 #pragma unroll
     for (int v = 0; v < 5; v++) Pout[5 * bi.off + (int64_t)v * V + l] = Pnew[v];
-    if (NEXT_DT) dtc = cell_dt(Pnew, Bnew, m, L.ph, bi.dx);
+    if (NEXT_DT) dtc = cell_dt(Pnew, Bnew, m, L.ph, bi.idx);
   }
   if (NEXT_DT) {
     const double r = block_min(dtc);
@@ -483,7 +484,7 @@ __global__ __launch_bounds__(NT) void k_dt(Launch L, const double* __restrict__ 
     Bc[0] = 0.5 * (b[l] + b[l + 1]) / m.gdet;
     Bc[1] = 0.5 * (b[V + l] + b[V + l + s2]) / m.gdet;
     Bc[2] = 0.5 * (b[2 * V + l] + b[2 * V + l + s3]) / m.gdet;
-    dtc = cell_dt(Pc, Bc, m, L.ph, bi.dx);
+    dtc = cell_dt(Pc, Bc, m, L.ph, bi.idx);
   }
   const double r = block_min(dtc);
   if (threadIdx.x == 0) dt_part[(int64_t)tl.y * gridDim.x + tl.x] = r;

@@ -114,3 +114,34 @@ def test_torus_three_level_polar_bands_match_oracle():
     a, r = grid.divb()
     say(f"  divB rel {r:.2e}")
     assert r < 1e-12
+
+
+def test_full_size_refined_lat_grid_properties():
+    """The 512x256x256-effective polar-refined grid with four time levels, one batched
+    (graph-captured) cycle with the learned guess off: every cell finite, every inversion
+    converged without the last-resort tier, div B at round-off, the schedule's step counts
+    per level, and the refined-and-LAT-effective accounting."""
+    cfg = dict(configs.TORUS_AMR_LAT)
+    lats = grmhd.lat_levels_by_radius(cfg, cfg["lat_edges"])
+    blocks = configs.polar_smr_blocks(cfg["n"], cfg["block"][0], lats)
+    say(f"[amr] full size {cfg['n']}, {len(blocks)} blocks, levels {lats}")
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    lmax = [max(b["lev"][d] for b in blocks) for d in range(3)]
+    bs = initdata.block_states(state, blocks, lmax)
+    del state
+    grid = grmhd.Grid(cfg, blocks=blocks, batched=True)
+    grid.set_blocks(bs)
+    del bs
+    st = grid.step(1)
+    L = max(lats) + 1
+    assert list(st.steps_per_level)[:L] == [2 ** (L - 1 - l) for l in range(L)]
+    cells = sum(b["n"][0] * b["n"][1] * b["n"][2] for b in blocks)
+    eff = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
+    assert st.lat_eff_zone_cycles == cells * 2 ** (L - 1)
+    assert st.amr_lat_eff_zone_cycles == eff * 2 ** (L - 1)
+    assert st.c2p_tier[4] == 0
+    a, r = grid.divb()
+    say(f"  dt {st.dt_min:.4e} tiers {list(st.c2p_tier)} divB rel {r:.2e}")
+    assert r < 1e-12
+    for P, B1, B2, B3 in grid.get_blocks():
+        assert np.isfinite(P).all() and (P[0] > 0).all() and (P[1] > 0).all()
