@@ -267,10 +267,16 @@ __global__ __launch_bounds__(AT) void k_amr_bsync(Launch L, const AmrLink* __res
 
 // ------------------------------------------------------------------ launchers
 
+// Without a stored start state (a gather outside a time-stepping cycle, where every
+// block stands at the same time) samples flagged as slower read the main state too.
 void launch_amr_cells(const Launch& L, const AmrOp* ops, int64_t nops, const AmrSample* samp,
                       const double* main, const double* old, const double* cur, double w,
                       double* dst) {
   if (nops <= 0) return;
+  if (!old) {
+    old = main;
+    w = 0.0;
+  }
   k_amr_cells<<<dim3((unsigned)((nops + AT - 1) / AT)), dim3(AT), 0, L.stream>>>(
       L.blk, L.geo, ops, nops, samp, main, old, cur, w, dst);
 }
@@ -279,6 +285,10 @@ void launch_amr_faces(const Launch& L, const AmrOp* ops, int64_t nops, const Amr
                       const double* main, const double* old, const double* cur, double w,
                       double* dst, int comp) {
   if (nops <= 0) return;
+  if (!old) {
+    old = main;
+    w = 0.0;
+  }
   k_amr_faces<<<dim3((unsigned)((nops + AT - 1) / AT)), dim3(AT), 0, L.stream>>>(
       L.blk, ops, nops, samp, main, old, cur, w, dst, comp);
 }
