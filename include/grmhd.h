@@ -86,7 +86,10 @@ typedef struct {
   double bsq_rho_max;         /* b^2/rho ceiling */
   double bsq_u_max;           /* b^2/u_g ceiling */
   double gamma_max;           /* Lorentz-factor ceiling */
-  int32_t c2p_guess;          /* GRMHD_GUESS_PLAIN or GRMHD_GUESS_MLP */
+  int32_t c2p_guess;          /* GRMHD_GUESS_PLAIN (Newton from the cell's previous
+                                 primitives) or GRMHD_GUESS_MLP (the network's guess too:
+                                 Newton from whichever of the two has the smaller residual
+                                 misfit, then from the other) */
   int32_t c2p_maxit;          /* Newton iteration cap (50) */
   double c2p_tol;             /* Newton tolerance (1e-12) */
   const void* mlp_weights;    /* device pointer to packed MLP weights, or NULL */
@@ -107,7 +110,7 @@ typedef struct {
   int64_t amr_lat_eff_zone_cycles;  /* effective-grid cells x finest-level steps */
   int64_t steps_per_level[8];
   int64_t c2p_iter_hist[64];        /* Newton iterations of accepted solves; 63 = bracketing tiers */
-  int64_t c2p_tier[5];              /* 0 first guess, 1 plain guess, 2 1D energy, 3 entropy, 4 failed */
+  int64_t c2p_tier[5];              /* 0 first Newton start, 1 second start, 2 1D energy, 3 entropy, 4 failed */
   int64_t floor_hits;
   double dt_min;                    /* last time step */
   double t_sim;                     /* simulated time since init */
@@ -158,7 +161,9 @@ int grmhd_autotune(grmhd_ctx* ctx, int32_t choice[4], double* ms);
  *   guess[5][n] first guess primitives; prev[5][n] plain guess and failure fallback
  *   P[5][n] out primitives; iters[n], tier[n] out (tier as in grmhd_step_stats)
  *   mlp_weights (nullable): a packed network blob (grmhd_mlp_pack); when set, the
- *               first guess is the network's prediction and guess may be NULL
+ *               network's prediction replaces guess (which may then be NULL)
+ * With a first guess distinct from prev, Newton starts from whichever of the two has
+ * the smaller residual misfit and falls back to the other (tier 1).
  * No floors are applied.  ctx may be NULL. */
 typedef struct {
   int64_t n;

@@ -313,15 +313,17 @@ __device__ __forceinline__ bool c2p_newton_wv(const C2PIn& s, double W0, double 
   for (it = 1; it <= maxit; it++) {
     const double BW = s.Bsq + W;
     const double sq = sqrt(1.0 - vsq);
-    const double iW2 = 1.0 / (W * W);
+    const double isq = 1.0 / sq;
+    const double iW = 1.0 / W;            // one division for the powers of 1/W
+    const double iW2 = iW * iW;
     const double R1 = vsq * BW * BW - s.QdotBsq * (s.Bsq + 2.0 * W) * iW2 - s.Qtsq;
     const double R2 = -0.5 * s.Bsq * (1.0 + vsq) + 0.5 * s.QdotBsq * iW2 - W +
                       gm * (W * (1.0 - vsq) - s.D * sq) - s.Qdotn;
-    const double iW3 = iW2 / W;
+    const double iW3 = iW2 * iW;
     const double J11 = 2.0 * vsq * BW + 2.0 * s.QdotBsq * BW * iW3;
     const double J12 = BW * BW;
     const double J21 = -s.QdotBsq * iW3 - 1.0 + gm * (1.0 - vsq);
-    const double J22 = -0.5 * s.Bsq + gm * (-W + s.D / (2.0 * sq));
+    const double J22 = -0.5 * s.Bsq + gm * (-W + 0.5 * s.D * isq);
     const double idet = 1.0 / (J11 * J22 - J12 * J21);
     const double dW = -(R1 * J22 - J12 * R2) * idet;
     const double dv = -(J11 * R2 - J21 * R1) * idet;
@@ -413,16 +415,34 @@ __device__ __forceinline__ bool c2p_entropy(const C2PIn& s, double P[5]) {
   return c2p_prims(s, W, vsq, rho, u, gamma, P);
 }
 
-// Inversion with the fallback chain; returns the tier used (0..4).  Tier 0 starts from
-// (W0, v0) when `first` is set (the learned guess), else from the plain guess prev;
-// tier 1 retries from prev; tiers 2 and 3 are the bracketed energy and entropy solves;
-// tier 4 keeps prev.
+// size of the two residuals at a guess, each in its natural scale (momentum: (B^2 +
+// W)^2, energy: W); infinite for a guess outside W > 0, 0 <= v^2 < 1
+__device__ __forceinline__ double c2p_misfit(const C2PIn& s, double W, double vsq) {
+  if (!(W > 0.0) || !(vsq >= 0.0) || !(vsq < 1.0)) return __longlong_as_double(0x7FF0000000000000LL);
+  const double BW = s.Bsq + W;
+  const double iW = 1.0 / W;
+  const double R1 = vsq * BW * BW - s.QdotBsq * (s.Bsq + 2.0 * W) * iW * iW - s.Qtsq;
+  return fabs(R1) / (BW * BW) + fabs(c2p_R2(s, W, vsq)) * iW;
+}
+
+// Inversion with the fallback chain; returns the tier used (0..4).  With a second guess
+// (W0, v0) (`first`: the learned guess), tier 0 is Newton from whichever of it and the
+// plain guess prev has the smaller residual misfit, tier 1 Newton from the other;
+// without, tier 0 starts from prev.  Tiers 2 and 3 are the bracketed energy and entropy
+// solves; tier 4 keeps prev.
 __device__ __forceinline__ int c2p_solve(const C2PIn& s, const Metric& m, bool first, double W0,
                                          double v0, const double prev[5], double tol, int maxit,
                                          double P[5], int& iters) {
   double Wp, vp;
   guess_from_prims(s, m, prev, Wp, vp);
   if (first) {
+    if (c2p_misfit(s, Wp, vp) < c2p_misfit(s, W0, v0)) {
+      const double tw = W0, tv = v0;
+      W0 = Wp;
+      v0 = vp;
+      Wp = tw;
+      vp = tv;
+    }
     if (c2p_newton_wv(s, W0, v0, tol, maxit, P, iters)) return 0;
     if (c2p_newton_wv(s, Wp, vp, tol, maxit, P, iters)) return 1;
   } else {

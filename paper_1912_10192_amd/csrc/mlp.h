@@ -45,6 +45,14 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
 
 // Forward pass of one wavefront's 64 cells.  feat: LDS [64][8] normalised features of
 // this wave's cells; out: LDS [64][2] normalised outputs.  Every lane must call it.
+// tanh x = 1 - 2 / (exp 2x + 1) from the hardware exp2 and reciprocal (absolute error
+// ~1e-7, far below the BF16 rounding of the activations it feeds)
+__device__ __forceinline__ float tanh_fast(float x) {
+  const float xc = fminf(fmaxf(x, -15.0f), 15.0f);
+  const float e = __builtin_amdgcn_exp2f(xc * 2.8853900817779268f);   // 2 log2(e)
+  return 1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f);
+}
+
 __device__ __forceinline__ void mlp_wave(const MlpBlob* __restrict__ blob, const float* feat,
                                          float* out) {
   const int l = __lane_id();
@@ -65,7 +73,7 @@ __device__ __forceinline__ void mlp_wave(const MlpBlob* __restrict__ blob, const
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
       acc = mfma16(F[(0 + mt) * 64 + l], b[0], acc);
 #pragma unroll
-      for (int j = 0; j < 4; j++) acc[j] = tanhf(acc[j] + blob->b1[mt * 16 + 4 * grp + j]);
+      for (int j = 0; j < 4; j++) acc[j] = tanh_fast(acc[j] + blob->b1[mt * 16 + 4 * grp + j]);
       h[mt] = acc;
     }
     // layers 2 and 3: 64 -> 64
@@ -83,7 +91,7 @@ __device__ __forceinline__ void mlp_wave(const MlpBlob* __restrict__ blob, const
 #pragma unroll
         for (int ks = 0; ks < 4; ks++) acc = mfma16(F[(base + mt * 4 + ks) * 64 + l], b[ks], acc);
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[j] = tanhf(acc[j] + bias[mt * 16 + 4 * grp + j]);
+        for (int j = 0; j < 4; j++) acc[j] = tanh_fast(acc[j] + bias[mt * 16 + 4 * grp + j]);
         h[mt] = acc;
       }
     }
