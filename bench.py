@@ -45,11 +45,18 @@ BYTES_PER_UNIT = {
     "update": 8 * (5 + 3 + 5 + 3 + 6 * 3 + 3 + 5 + 3),
     "emf": 8 * (6 + 3), "bcell": 8 * (3 + 3), "dt": 8 * (5 + 3), "ghost": 8 * 2 * 8,
 }
-FLOPS_PER_UNIT: dict = {}
-KERNEL_HASH = None
-# HBM traffic per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (calibrated on the copy
-# kernel), keyed like FLOPS_PER_UNIT and valid for KERNEL_HASH only.
-TRAFFIC_PER_LAUNCH: dict = {}
+FLOPS_PER_UNIT = {
+    "update": 1569.1, "flux1": 1292.0, "flux2": 1242.6, "flux3": 1239.4, "emf": 9.8,
+    "bcell": 86.2, "dt": 330.0,
+}
+KERNEL_HASH = "7fccaf1770ab98f0"
+# HBM traffic per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by the reading of
+# the same counters for a 1 GiB device copy: fetch x2, write x1), keyed like
+# FLOPS_PER_UNIT and valid for KERNEL_HASH only.
+TRAFFIC_PER_LAUNCH = {
+    "update": 1.858e9, "flux1": 7.285e8, "flux2": 7.575e8, "flux3": 7.645e8, "emf": 3.782e8,
+    "bcell": 3.629e8,
+}
 
 
 def kernel_hash() -> str:
@@ -186,18 +193,23 @@ def main():
     units = units_per_launch(dom, cfg)
     khash = kernel_hash()
     fresh = KERNEL_HASH == khash
-    if fresh and dom in FLOPS_PER_UNIT:
-        bound, unit, peak = "alu", "TFLOP/s", PEAK["alu"]
-        achieved = FLOPS_PER_UNIT[dom] * units / avg_s
-        scale = 1e12
+    # the binding roof: the larger of the algorithmic byte time and flop time
+    alg_bytes = BYTES_PER_UNIT[dom] * units
+    alg_flops = FLOPS_PER_UNIT[dom] * units if fresh and dom in FLOPS_PER_UNIT else None
+    t_hbm = alg_bytes / PEAK["hbm"]
+    t_alu = alg_flops / PEAK["alu"] if alg_flops is not None else 0.0
+    if t_alu > t_hbm:
+        bound, unit, peak, achieved, scale = "alu", "TFLOP/s", PEAK["alu"], alg_flops / avg_s, 1e12
     else:
-        bound, unit, peak = "hbm", "GB/s", PEAK["hbm"]
-        achieved = BYTES_PER_UNIT[dom] * units / avg_s
-        scale = 1e9
+        bound, unit, peak, achieved, scale = "hbm", "GB/s", PEAK["hbm"], alg_bytes / avg_s, 1e9
     traffic = TRAFFIC_PER_LAUNCH.get(dom) if fresh else None
     roofline = {"bound": bound, "achieved": achieved / scale, "peak": peak / scale, "unit": unit,
                 "frac": achieved / peak, "traffic": traffic, "kernel": dom,
-                "launch_ms": avg_s * 1e3, "units_per_launch": units, "kernel_hash": khash}
+                "launch_ms": avg_s * 1e3, "units_per_launch": units, "kernel_hash": khash,
+                "alg_bytes_per_unit": BYTES_PER_UNIT[dom],
+                "fp64_flops_per_unit": FLOPS_PER_UNIT.get(dom) if fresh else None,
+                "hbm_frac": t_hbm / avg_s,
+                "alu_frac": (t_alu / avg_s) if alg_flops is not None else None}
     plain = {"value": plain_value, "ms_per_step": wall * 1e3 / args.steps, "dt": st.dt_min,
              "autotune": tune,
              "c2p": c2p_summary(st), "divb_rel_max": r_div,
