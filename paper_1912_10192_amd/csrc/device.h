@@ -85,9 +85,12 @@ __device__ __forceinline__ void fluid_state(const double P[5], const double B[3]
           f.bcon[3] * f.bcov[3];
 }
 
-// entropy tracer kappa = p / rho^gamma of a state (one power per state)
+// entropy tracer kappa = p / rho^gamma of a state (one power per state; for the
+// relativistic gamma = 4/3 the power is rho cbrt(rho), a cube root instead of a general
+// log/exp power)
 __device__ __forceinline__ double entropy_kappa(const double P[5], double gam) {
-  return (gam - 1.0) * P[1] / pow(P[0], gam);
+  const double rg = gam == 4.0 / 3.0 ? P[0] * cbrt(P[0]) : pow(P[0], gam);
+  return (gam - 1.0) * P[1] / rg;
 }
 
 // Conserved vector (D = 0) or flux along x^D (D = 1..3), times sqrt(-g):

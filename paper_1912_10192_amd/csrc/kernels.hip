@@ -328,7 +328,9 @@ __device__ __forceinline__ bool mlp_guess_block(const MlpBlob* __restrict__ blob
   return isfinite(W0) && W0 > 0.0 && v0 >= 0.0 && v0 < 1.0;
 }
 
-template <bool STATS, bool NEXT_DT, bool MLP, int OCC>
+// UN = 1: U^n(P^n) is computed and kept in `un` (6 conserved components per cell);
+// UN = 2: it is read back from there (the corrector of the same step, same P^n and B^n)
+template <bool STATS, bool NEXT_DT, bool MLP, int OCC, int UN>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_update(Launch L, const double* __restrict__ Pn,
                                                const double* __restrict__ Bn,
                                                const double* __restrict__ Ps,
@@ -338,7 +340,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                                                double* __restrict__ Pout,
                                                double* __restrict__ Bout,
                                                double* __restrict__ dt_part,
-                                               const MlpBlob* __restrict__ mlp) {
+                                               const MlpBlob* __restrict__ mlp,
+                                               double* __restrict__ un) {
   const Tile tl = xcd_tile();
   const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
   const int g = L.ph.ng;
@@ -389,9 +392,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     if (c.K == g + bi.n[2] - 1) o3[l + s3] = nb3hi;
 
     m = load_metric(G.c, G.ncol, col);
-    // U^n recomputed from P^n (Sec. 2.5)
+    // U^n recomputed from P^n (Sec. 2.5): by the predictor, and kept for the corrector
+    constexpr int fq[6] = {0, 1, 2, 3, 4, 7};
+    constexpr int uq[6] = {0, 1, 2, 3, 4, 8};
     double U[9];
-    {
+    double* uc = un + 6 * bi.off + l;
+    if (UN == 2) {
+#pragma unroll
+      for (int k = 0; k < 6; k++) U[uq[k]] = uc[(int64_t)k * V];
+    } else {
       double P0[5], B0[3];
 #pragma unroll
       for (int v = 0; v < 5; v++) P0[v] = Pn[5 * bi.off + (int64_t)v * V + l];
@@ -402,6 +411,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
       Fluid f;
       fluid_state(P0, B0, m, f);
       flux_vector<0>(P0, f, m, L.ph.gam, entropy_kappa(P0, L.ph.gam), U);
+#pragma unroll
+      for (int k = 0; k < 6; k++) uc[(int64_t)k * V] = U[uq[k]];
     }
 #pragma unroll
     for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * V + l];
@@ -417,8 +428,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     const double* f1 = F + 24 * bi.off + l;
     const double* f2 = f1 + 8 * V;
     const double* f3 = f2 + 8 * V;
-    constexpr int fq[6] = {0, 1, 2, 3, 4, 7};
-    constexpr int uq[6] = {0, 1, 2, 3, 4, 8};
 #pragma unroll
     for (int k = 0; k < 6; k++) {
       const int64_t o = (int64_t)fq[k] * V;
@@ -721,15 +730,18 @@ int64_t dt_partials(const Launch& L) {
 
 void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
                    const double* Bcs, const double* F, const double* E, double dt_factor,
-                   double* Pout, double* Bout, double* dt_part, const void* mlp) {
+                   double* Pout, double* Bout, double* dt_part, const void* mlp, double* un,
+                   bool reuse_un) {
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
   const dim3 grid(cdiv(r, NT), L.nblk);
   const MlpBlob* blob = (const MlpBlob*)mlp;
-#define GRMHD_UPD(ND, ML, V)                                                                   \
-  hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V]>), grid, dim3(NT), 0, L.stream, L, Pn, \
-                     Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob)
+#define GRMHD_UPD(ND, ML, V, U)                                                                 \
+  hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], U>), grid, dim3(NT), 0, L.stream, L, Pn, \
+                     Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob, un)
+#define GRMHD_UPD_U(ND, ML, V) \
+  if (reuse_un) GRMHD_UPD(ND, ML, V, 2); else GRMHD_UPD(ND, ML, V, 1)
 #define GRMHD_UPD_V(ND, ML) \
-  if (L.var_upd == 0) GRMHD_UPD(ND, ML, 0); else GRMHD_UPD(ND, ML, 1)
+  if (L.var_upd == 0) { GRMHD_UPD_U(ND, ML, 0); } else { GRMHD_UPD_U(ND, ML, 1); }
   if (dt_part && blob) {
     GRMHD_UPD_V(true, true);
   } else if (dt_part) {
@@ -740,6 +752,7 @@ void launch_update(const Launch& L, const double* Pn, const double* Bn, const do
     GRMHD_UPD_V(false, false);
   }
 #undef GRMHD_UPD_V
+#undef GRMHD_UPD_U
 #undef GRMHD_UPD
 }
 

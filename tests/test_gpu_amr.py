@@ -145,3 +145,21 @@ def test_full_size_refined_lat_grid_properties():
     assert r < 1e-12
     for P, B1, B2, B3 in grid.get_blocks():
         assert np.isfinite(P).all() and (P[0] > 0).all() and (P[1] > 0).all()
+
+
+def test_divb_stays_at_roundoff_over_100_cycles():
+    """div B across refinement and time-level faces after 100 cycles (the torus with
+    coarse polar caps and two time levels)"""
+    eff = (32, 32, 16)
+    cfg = configs.scaled(configs.TORUS_UNIFORM, eff, ng=3)
+    state = initdata.torus_state(eff, **configs.TORUS_INIT)
+    blocks = polar_bands(eff, (0, 1))
+    lmax = [max(b["lev"][d] for b in blocks) for d in range(3)]
+    grid = grmhd.Grid(cfg, blocks=blocks, batched=True)
+    grid.set_blocks(initdata.block_states(state, blocks, lmax))
+    st = grid.step(100)
+    a, r = grid.divb()
+    say(f"[amr] 100 cycles: t {st.t_sim:.3f} divB rel {r:.2e} tiers {list(st.c2p_tier)}")
+    assert r < 1e-12
+    for P, *_ in grid.get_blocks():
+        assert np.isfinite(P).all()

@@ -284,3 +284,23 @@ def test_unmagnetised_torus_stationary_second_order():
         body = i0 > 0.1
         errs.append(np.abs(i1 - i0)[body].mean())
     assert errs[0] / errs[1] > 3.0 and errs[1] / errs[2] > 3.0, errs
+
+
+def test_axisymmetric_torus_in_3d_stays_phi_independent():
+    """the unmagnetised torus on a 3D grid stays phi-independent to round-off and matches
+    the one-cell-in-phi run"""
+    cfg3 = _ks_cfg((32, 16, 8), ng=3, recon=1, riemann=1)
+    cfg1 = _ks_cfg((32, 16, 1), ng=3, recon=1, riemann=1)
+    s3 = initdata.torus_state(cfg3["n"], amp=0.0, beta=np.inf)
+    s1 = initdata.torus_state(cfg1["n"], amp=0.0, beta=np.inf)
+    g3, P3, B3 = _grid_with(cfg3, s3)
+    g1, P1, B1 = _grid_with(cfg1, s1)
+    dt = min(g3.dt(P3, B3), g1.dt(P1, B1))
+    g3.step(P3, B3, 5, dt_fixed=dt)
+    g1.step(P1, B1, 5, dt_fixed=dt)
+    a = unpad_global(cfg3, P3, B3)[0]
+    b = unpad_global(cfg1, P1, B1)[0]
+    for v in range(5):
+        scale = max(np.abs(b[v]).max(), 1e-300)
+        assert np.abs(a[v] - a[v][:1]).max() <= 1e-13 * scale
+        assert np.abs(a[v] - b[v]).max() <= 1e-13 * scale
