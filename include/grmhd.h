@@ -144,15 +144,23 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
 int grmhd_step(grmhd_ctx* ctx, int32_t n_cycles, grmhd_step_stats* stats);
 
 /* Autotuner of the two heavy kernels.  The flux kernel (per direction) and the update
- * kernel are built in occupancy variants (the minimum waves per SIMD the compiler must
- * fit: flux 1, 2, 4; update 1, 2).  This times every variant on the context's current
- * state (one predictor stage, three launches each after a warm-up) and keeps the
- * fastest for all later launches; without a call the flux kernel uses 4 and the update
- * 1.  choice (host, nullable) receives the chosen variant indices (flux x1, x2, x3,
- * update); ms (host, nullable, 11 doubles) the mean milliseconds per variant (flux x1
- * variants, x2, x3, then update).  The state is not modified; counters are reset;
- * synchronises. */
-int grmhd_autotune(grmhd_ctx* ctx, int32_t choice[4], double* ms);
+ * kernel are built in GRMHD_NVAR_FLUX / GRMHD_NVAR_UPD occupancy variants (the minimum
+ * waves per SIMD the compiler must fit: flux 1, 2, 4; update 1, 2), and the update in
+ * two forms: one fused kernel, or two (the conserved state of every cell through a
+ * buffer, then the inversion).  This times every variant and form on the context's
+ * current state (one predictor stage, three launches each after a warm-up) and keeps
+ * the fastest for all later launches; without a call the flux kernel uses 4 waves and
+ * the update is fused with 1.  choice (host, nullable, 5 ints) receives the chosen
+ * flux variants (x1, x2, x3), the update variant and the update form (0 fused, 1
+ * split); ms (host, nullable, 3 GRMHD_NVAR_FLUX + 2 GRMHD_NVAR_UPD doubles) the mean
+ * milliseconds per variant (flux x1 variants, x2, x3, fused update variants, split
+ * update variants).  The state is not modified; counters are reset; synchronises. */
+#define GRMHD_NVAR_FLUX 3
+#define GRMHD_NVAR_UPD 2
+int grmhd_autotune(grmhd_ctx* ctx, int32_t choice[5], double* ms);
+/* Sets the kernel variants directly (the layout of grmhd_autotune's choice), for
+ * reproducible runs; EINVAL for an index out of range. */
+int grmhd_set_variants(grmhd_ctx* ctx, const int32_t choice[5]);
 
 /* Standalone inversion of a flat batch (Sec. 2.6), all pointers device memory:
  *   U[9][n]     conserved state incl. sqrt(-g): rho u^t, T^t_t + rho u^t, T^t_i, B^i, kappa rho u^t

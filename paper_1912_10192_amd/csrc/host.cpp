@@ -167,7 +167,7 @@ struct Plan {
   int32_t rs = 0, rs2 = 0;                     // register plane size and row stride
   // work-buffer offsets (bytes)
   size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, o_dtp;
-  size_t o_aops[4], o_samp, o_links, o_un;
+  size_t o_aops[4], o_samp, o_links, o_un, o_u9;
   size_t o_pold, o_bold, o_reg, o_ubuf, o_lev, o_items, total;
 };
 
@@ -809,6 +809,7 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
   p.o_f = take(24 * V * 8);
   p.o_e = take(3 * V * 8);
   p.o_un = take(6 * V * 8);
+  p.o_u9 = take(9 * V * 8);
   p.o_gc = take((size_t)NGEO_C * p.ncol * 8);
   p.o_g1 = take((size_t)NGEO_F * p.ncol * 8);
   p.o_g2 = take((size_t)NGEO_F * p.ncol * 8);
@@ -909,7 +910,7 @@ struct grmhd_ctx {
   Launch L;
   grmhd_buffers bufs;
   hipStream_t stream;
-  double *ps, *balt, *bc, *f, *e, *dtp, *un;
+  double *ps, *balt, *bc, *f, *e, *dtp, *un, *u9;
   GhostOp* ops[4];
   int64_t nops[4];
   AmrOp* aops[4];
@@ -980,6 +981,7 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   c->e = (double*)(w + p.o_e);
   c->dtp = (double*)(w + p.o_dtp);
   c->un = (double*)(w + p.o_un);
+  c->u9 = (double*)(w + p.o_u9);
   c->pold = (double*)(w + p.o_pold);
   c->bold = (double*)(w + p.o_bold);
   c->reg = (double*)(w + p.o_reg);
@@ -1043,8 +1045,9 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   L.ph.ng = desc->n_ghost;
   L.cnt = (Counters*)(w + p.o_cnt);
   L.stream = c->stream;
-  for (int k = 0; k < 3; k++) L.var_flux[k] = NVAR_FLUX - 1;   // 4 waves per SIMD
+  for (int k = 0; k < 3; k++) L.var_flux[k] = 2;   // 4 waves per SIMD
   L.var_upd = 0;
+  L.split_upd = 0;
   c->profile = desc->profile != 0;
   c->mlp = desc->c2p_guess == GRMHD_GUESS_MLP ? desc->mlp_weights : nullptr;
   launch_counters_reset(L, true);
@@ -1105,7 +1108,7 @@ static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double
   prof_begin(c, KC_UPDATE);
   // the corrector (factor 1) reuses the U^n the predictor kept
   launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, dt_part, c->mlp, c->un,
-                factor == 1.0);
+                factor == 1.0, c->u9);
   prof_end(c);
   if (!c->plan.links.empty()) {
     prof_begin(c, KC_GHOST);
@@ -1164,7 +1167,7 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
     prof_end(c);
     prof_begin(c, KC_UPDATE);
     launch_update(L, P, B, Ps, c->bc, c->f, c->e, factor, Pout, c->balt, nullptr, c->mlp, c->un,
-                  Ps != P);
+                  Ps != P, c->u9);
     prof_end(c);
     if (nl > 0) {
       prof_begin(c, KC_GHOST);
@@ -1304,7 +1307,27 @@ int grmhd_step(grmhd_ctx* c, int32_t n_cycles, grmhd_step_stats* stats) {
   return GRMHD_OK;
 }
 
-int grmhd_autotune(grmhd_ctx* c, int32_t choice[4], double* ms) {
+int grmhd_set_variants(grmhd_ctx* c, const int32_t choice[5]) {
+  if (!c || !choice) return fail(GRMHD_EINVAL, "NULL argument");
+  for (int k = 0; k < 3; k++)
+    if (choice[k] < 0 || choice[k] >= NVAR_FLUX) return fail(GRMHD_EINVAL, "flux variant out of range");
+  if (choice[3] < 0 || choice[3] >= NVAR_UPD) return fail(GRMHD_EINVAL, "update variant out of range");
+  if (choice[4] != 0 && choice[4] != 1) return fail(GRMHD_EINVAL, "update form must be 0 or 1");
+  for (int k = 0; k < 3; k++) c->L.var_flux[k] = choice[k];
+  c->L.var_upd = choice[3];
+  c->L.split_upd = choice[4];
+  if (c->graph_exec) {
+    (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+  }
+  if (c->graph) {
+    (void)hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_autotune(grmhd_ctx* c, int32_t choice[5], double* ms) {
   if (!c) return fail(GRMHD_EINVAL, "NULL context");
   if (c->b_in_alt) return fail(GRMHD_ESTATE, "state not in the caller's buffers");
   Launch& L = c->L;
@@ -1349,18 +1372,25 @@ int grmhd_autotune(grmhd_ctx* c, int32_t choice[4], double* ms) {
   if (!rc) {
     launch_emf(L, c->f, c->e);
     double best = 1e300;
-    int arg = L.var_upd;
-    for (int v = 0; v < NVAR_UPD && !rc; v++) {
-      L.var_upd = v;
-      double t = 0.0;
-      rc = time_it([&] {
-        launch_update(L, P, B, P, c->bc, c->f, c->e, 0.5, c->ps, c->balt, nullptr, c->mlp, c->un,
-                      false);
-      }, t);
-      if (ms) ms[3 * NVAR_FLUX + v] = t;
-      if (t < best) { best = t; arg = v; }
-    }
+    int arg = L.var_upd, arg_split = L.split_upd;
+    for (int sp = 0; sp < 2 && !rc; sp++)
+      for (int v = 0; v < NVAR_UPD && !rc; v++) {
+        L.var_upd = v;
+        L.split_upd = sp;
+        double t = 0.0;
+        rc = time_it([&] {
+          launch_update(L, P, B, P, c->bc, c->f, c->e, 0.5, c->ps, c->balt, nullptr, c->mlp,
+                        c->un, false, c->u9);
+        }, t);
+        if (ms) ms[3 * NVAR_FLUX + sp * NVAR_UPD + v] = t;
+        if (t < best) {
+          best = t;
+          arg = v;
+          arg_split = sp;
+        }
+      }
     L.var_upd = arg;
+    L.split_upd = arg_split;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1381,6 +1411,7 @@ int grmhd_autotune(grmhd_ctx* c, int32_t choice[4], double* ms) {
   if (choice) {
     for (int k = 0; k < 3; k++) choice[k] = L.var_flux[k];
     choice[3] = L.var_upd;
+    choice[4] = L.split_upd;
   }
   return GRMHD_OK;
 }

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "../../include/grmhd.h"
+
 namespace grmhd {
 
 // one block as the kernels see it
@@ -100,7 +102,7 @@ __host__ __device__ inline int64_t geo_col(const GeoTab&, const BlockInfo& bi, i
 }
 
 // occupancy variants of the flux and update kernels (see kernels.hip)
-constexpr int NVAR_FLUX = 3, NVAR_UPD = 2;
+constexpr int NVAR_FLUX = GRMHD_NVAR_FLUX, NVAR_UPD = GRMHD_NVAR_UPD;
 
 struct Launch {
   const BlockInfo* blk;   // device block table
@@ -114,6 +116,7 @@ struct Launch {
   hipStream_t stream;
   int32_t var_flux[3];    // variant of the flux kernel per direction
   int32_t var_upd;        // variant of the update kernel
+  int32_t split_upd;      // 1: the update as two kernels (conserved state, then inversion)
 };
 
 // records the message returned by grmhd_last_error() and returns code (host.cpp)
@@ -132,7 +135,7 @@ void launch_emf(const Launch& L, const double* F, double* E);
 void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
                    const double* Bcs, const double* F, const double* E, double dt_factor,
                    double* Pout, double* Bout, double* dt_part, const void* mlp, double* un,
-                   bool reuse_un);
+                   bool reuse_un, double* ubuf);
 int64_t dt_partials(const Launch& L);
 void launch_dt(const Launch& L, const double* P, const double* B, double* dt_part);
 void launch_dt_final(const Launch& L, const double* dt_part);

@@ -20,6 +20,7 @@ constexpr int NT = 256;   // threads per workgroup (four wavefronts)
 // The two heavy kernels come in occupancy variants: the minimum number of waves per
 // SIMD the compiler must fit (trading registers for latency hiding).  Which variant a
 // launch uses is the autotuner's choice (Launch::var_flux, Launch::var_upd).
+// (variants asking for 6 or 8 waves spill and run 1.2-4x slower on MI355X; not built)
 constexpr int FLUX_OCC[NVAR_FLUX] = {1, 2, 4};
 constexpr int UPD_OCC[NVAR_UPD] = {1, 2};
 
@@ -328,134 +329,133 @@ __device__ __forceinline__ bool mlp_guess_block(const MlpBlob* __restrict__ blob
   return isfinite(W0) && W0 > 0.0 && v0 >= 0.0 && v0 < 1.0;
 }
 
-// UN = 1: U^n(P^n) is computed and kept in `un` (6 conserved components per cell);
-// UN = 2: it is read back from there (the corrector of the same step, same P^n and B^n)
-template <bool STATS, bool NEXT_DT, bool MLP, int OCC, int UN>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_update(Launch L, const double* __restrict__ Pn,
-                                               const double* __restrict__ Bn,
-                                               const double* __restrict__ Ps,
-                                               const double* __restrict__ Bcs,
-                                               const double* __restrict__ F,
-                                               const double* __restrict__ E, double dt_factor,
-                                               double* __restrict__ Pout,
-                                               double* __restrict__ Bout,
-                                               double* __restrict__ dt_part,
-                                               const MlpBlob* __restrict__ mlp,
-                                               double* __restrict__ un) {
-  const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
+// The conserved update of one interior cell (Sec. 2.5): constrained transport of its
+// faces (written to Bout), U^n from P^n, the geometric source at the stage state, the
+// flux divergence; leaves U (9 components, field from the new faces) and the stage
+// primitives PS.  UN = 1: U^n(P^n) is computed and kept in `un` (6 conserved components
+// per cell); UN = 2: it is read back from there (the corrector of the same step, same
+// P^n and B^n).
+template <int UN>
+__device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& bi, const Cell& c,
+                                              const Metric& m, int64_t col,
+                                              const double* __restrict__ Pn,
+                                              const double* __restrict__ Bn,
+                                              const double* __restrict__ Ps,
+                                              const double* __restrict__ Bcs,
+                                              const double* __restrict__ F,
+                                              const double* __restrict__ E, double dt_factor,
+                                              double* __restrict__ Bout, double* __restrict__ un,
+                                              double U[9], double PS[5]) {
   const int g = L.ph.ng;
-  Cell c;
-  const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
-                                 g, g, c);
-  int tier = 0, iters = 0, hits = 0;
-  double dtc = __longlong_as_double(0x7FF0000000000000LL);
   const int64_t V = bi.vol;
   const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
   const int64_t l = c.loc;
   const GeoTab& G = L.geo;
-  const int64_t col = valid ? geo_col(G, bi, c.J, c.I) : 0;
-  Metric m;
-  C2PIn cs;
-  double PS[5];
-  if (valid) {
-    const double dt = L.ph.courant * __longlong_as_double((long long)L.cnt->dt_bits);
-    const double dts = dt_factor * dt;
-    const double ix1 = bi.idx[0], ix2 = bi.idx[1], ix3 = bi.idx[2];
-    const double* e1 = E + 3 * bi.off;
-    const double* e2 = e1 + V;
-    const double* e3 = e2 + V;
-    const double* b1 = Bn + 3 * bi.off;
-    const double* b2 = b1 + V;
-    const double* b3 = b2 + V;
-    const bool pole_lo = G.f2[GDET * G.ncol + col] == 0.0;
-    const bool pole_hi = G.f2[GDET * G.ncol + col + bi.gti] == 0.0;
-    // constrained transport of the six faces of this cell (Sec. 2.5)
-    const double nb1lo = b1[l] + dts * ((e2[l + s3] - e2[l]) * ix3 - (e3[l + s2] - e3[l]) * ix2);
-    const double nb1hi =
-        b1[l + 1] + dts * ((e2[l + 1 + s3] - e2[l + 1]) * ix3 - (e3[l + 1 + s2] - e3[l + 1]) * ix2);
-    const double nb2lo = pole_lo ? 0.0
-        : b2[l] + dts * ((e3[l + 1] - e3[l]) * ix1 - (e1[l + s3] - e1[l]) * ix3);
-    const double nb2hi = pole_hi ? 0.0
-        : b2[l + s2] + dts * ((e3[l + s2 + 1] - e3[l + s2]) * ix1 - (e1[l + s2 + s3] - e1[l + s2]) * ix3);
-    const double nb3lo = b3[l] + dts * ((e1[l + s2] - e1[l]) * ix2 - (e2[l + 1] - e2[l]) * ix1);
-    const double nb3hi =
-        b3[l + s3] + dts * ((e1[l + s3 + s2] - e1[l + s3]) * ix2 - (e2[l + s3 + 1] - e2[l + s3]) * ix1);
-    double* o1 = Bout + 3 * bi.off;
-    double* o2 = o1 + V;
-    double* o3 = o2 + V;
-    o1[l] = nb1lo;
-    o2[l] = nb2lo;
-    o3[l] = nb3lo;
-    if (c.I == g + bi.n[0] - 1) o1[l + 1] = nb1hi;
-    if (c.J == g + bi.n[1] - 1) o2[l + s2] = nb2hi;
-    if (c.K == g + bi.n[2] - 1) o3[l + s3] = nb3hi;
+  const double dt = L.ph.courant * __longlong_as_double((long long)L.cnt->dt_bits);
+  const double dts = dt_factor * dt;
+  const double ix1 = bi.idx[0], ix2 = bi.idx[1], ix3 = bi.idx[2];
+  const double* e1 = E + 3 * bi.off;
+  const double* e2 = e1 + V;
+  const double* e3 = e2 + V;
+  const double* b1 = Bn + 3 * bi.off;
+  const double* b2 = b1 + V;
+  const double* b3 = b2 + V;
+  const bool pole_lo = G.f2[GDET * G.ncol + col] == 0.0;
+  const bool pole_hi = G.f2[GDET * G.ncol + col + bi.gti] == 0.0;
+  // constrained transport of the six faces of this cell (Sec. 2.5)
+  const double nb1lo = b1[l] + dts * ((e2[l + s3] - e2[l]) * ix3 - (e3[l + s2] - e3[l]) * ix2);
+  const double nb1hi =
+      b1[l + 1] + dts * ((e2[l + 1 + s3] - e2[l + 1]) * ix3 - (e3[l + 1 + s2] - e3[l + 1]) * ix2);
+  const double nb2lo = pole_lo ? 0.0
+      : b2[l] + dts * ((e3[l + 1] - e3[l]) * ix1 - (e1[l + s3] - e1[l]) * ix3);
+  const double nb2hi = pole_hi ? 0.0
+      : b2[l + s2] + dts * ((e3[l + s2 + 1] - e3[l + s2]) * ix1 - (e1[l + s2 + s3] - e1[l + s2]) * ix3);
+  const double nb3lo = b3[l] + dts * ((e1[l + s2] - e1[l]) * ix2 - (e2[l + 1] - e2[l]) * ix1);
+  const double nb3hi =
+      b3[l + s3] + dts * ((e1[l + s3 + s2] - e1[l + s3]) * ix2 - (e2[l + s3 + 1] - e2[l + s3]) * ix1);
+  double* o1 = Bout + 3 * bi.off;
+  double* o2 = o1 + V;
+  double* o3 = o2 + V;
+  o1[l] = nb1lo;
+  o2[l] = nb2lo;
+  o3[l] = nb3lo;
+  if (c.I == g + bi.n[0] - 1) o1[l + 1] = nb1hi;
+  if (c.J == g + bi.n[1] - 1) o2[l + s2] = nb2hi;
+  if (c.K == g + bi.n[2] - 1) o3[l + s3] = nb3hi;
 
-    m = load_metric(G.c, G.ncol, col);
-    // U^n recomputed from P^n (Sec. 2.5): by the predictor, and kept for the corrector
-    constexpr int fq[6] = {0, 1, 2, 3, 4, 7};
-    constexpr int uq[6] = {0, 1, 2, 3, 4, 8};
-    double U[9];
-    double* uc = un + 6 * bi.off + l;
-    if (UN == 2) {
+  // U^n recomputed from P^n (Sec. 2.5): by the predictor, and kept for the corrector
+  constexpr int fq[6] = {0, 1, 2, 3, 4, 7};
+  constexpr int uq[6] = {0, 1, 2, 3, 4, 8};
+  double* uc = un + 6 * bi.off + l;
+  if (UN == 2) {
 #pragma unroll
-      for (int k = 0; k < 6; k++) U[uq[k]] = uc[(int64_t)k * V];
-    } else {
-      double P0[5], B0[3];
+    for (int k = 0; k < 6; k++) U[uq[k]] = uc[(int64_t)k * V];
+  } else {
+    double P0[5], B0[3];
 #pragma unroll
-      for (int v = 0; v < 5; v++) P0[v] = Pn[5 * bi.off + (int64_t)v * V + l];
-      const double hg = 0.5 / m.gdet;
-      B0[0] = (b1[l] + b1[l + 1]) * hg;
-      B0[1] = (b2[l] + b2[l + s2]) * hg;
-      B0[2] = (b3[l] + b3[l + s3]) * hg;
-      Fluid f;
-      fluid_state(P0, B0, m, f);
-      flux_vector<0>(P0, f, m, L.ph.gam, entropy_kappa(P0, L.ph.gam), U);
+    for (int v = 0; v < 5; v++) P0[v] = Pn[5 * bi.off + (int64_t)v * V + l];
+    const double hg = 0.5 / m.gdet;
+    B0[0] = (b1[l] + b1[l + 1]) * hg;
+    B0[1] = (b2[l] + b2[l + s2]) * hg;
+    B0[2] = (b3[l] + b3[l + s3]) * hg;
+    Fluid f;
+    fluid_state(P0, B0, m, f);
+    flux_vector<0>(P0, f, m, L.ph.gam, entropy_kappa(P0, L.ph.gam), U);
 #pragma unroll
-      for (int k = 0; k < 6; k++) uc[(int64_t)k * V] = U[uq[k]];
-    }
-#pragma unroll
-    for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * V + l];
-    double Q[4];
-    {
-      double BS[3];
-#pragma unroll
-      for (int i = 0; i < 3; i++) BS[i] = Bcs[3 * bi.off + (int64_t)i * V + l];
-      Fluid f;
-      fluid_state(PS, BS, m, f);
-      geometric_source(PS, f, m, G.c, G.ncol, col, L.ph.gam, Q);
-    }
-    const double* f1 = F + 24 * bi.off + l;
-    const double* f2 = f1 + 8 * V;
-    const double* f3 = f2 + 8 * V;
-#pragma unroll
-    for (int k = 0; k < 6; k++) {
-      const int64_t o = (int64_t)fq[k] * V;
-      const double div = (f1[o + 1] - f1[o]) * ix1 + (f2[o + s2] - f2[o]) * ix2 +
-                         (f3[o + s3] - f3[o]) * ix3;
-      const double q = (k >= 1 && k <= 4) ? Q[k - 1] : 0.0;
-      U[uq[k]] = U[uq[k]] - dts * div + dts * q;
-    }
-    U[5] = 0.5 * (nb1lo + nb1hi);
-    U[6] = 0.5 * (nb2lo + nb2hi);
-    U[7] = 0.5 * (nb3lo + nb3hi);
-    c2p_setup(U, m, L.ph.gam, cs);
+    for (int k = 0; k < 6; k++) uc[(int64_t)k * V] = U[uq[k]];
   }
-  bool first = false;
-  double W0 = 0.0, v0 = 0.0;
-  if (MLP) first = mlp_guess_block(mlp, cs, m, valid, W0, v0);
-  if (valid) {
-    double Pnew[5];
-    tier = c2p_solve(cs, m, first, W0, v0, PS, L.ph.tol, L.ph.maxit, Pnew, iters);
-    // B^i = Bbar^i / sqrt(-g) with Bbar^i the face average; c2p_setup holds alpha B^i
-    const double ia = 1.0 / m.alpha;
-    const double Bnew[3] = {cs.B1 * ia, cs.B2 * ia, cs.B3 * ia};
-    hits = apply_floors(Pnew, Bnew, m, G.c[RHOFL * G.ncol + col], G.c[UFL * G.ncol + col],
-                        L.ph.bsq_rho_max, L.ph.bsq_u_max, L.ph.gamma_max);
 #pragma unroll
-    for (int v = 0; v < 5; v++) Pout[5 * bi.off + (int64_t)v * V + l] = Pnew[v];
-    if (NEXT_DT) dtc = cell_dt(Pnew, Bnew, m, L.ph, bi.idx);
+  for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * V + l];
+  double Q[4];
+  {
+    double BS[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) BS[i] = Bcs[3 * bi.off + (int64_t)i * V + l];
+    Fluid f;
+    fluid_state(PS, BS, m, f);
+    geometric_source(PS, f, m, G.c, G.ncol, col, L.ph.gam, Q);
   }
+  const double* f1 = F + 24 * bi.off + l;
+  const double* f2 = f1 + 8 * V;
+  const double* f3 = f2 + 8 * V;
+#pragma unroll
+  for (int k = 0; k < 6; k++) {
+    const int64_t o = (int64_t)fq[k] * V;
+    const double div = (f1[o + 1] - f1[o]) * ix1 + (f2[o + s2] - f2[o]) * ix2 +
+                       (f3[o + s3] - f3[o]) * ix3;
+    const double q = (k >= 1 && k <= 4) ? Q[k - 1] : 0.0;
+    U[uq[k]] = U[uq[k]] - dts * div + dts * q;
+  }
+  U[5] = 0.5 * (nb1lo + nb1hi);
+  U[6] = 0.5 * (nb2lo + nb2hi);
+  U[7] = 0.5 * (nb3lo + nb3hi);
+}
+
+// The inversion of one cell and its floors (Sec. 2.6, 2.7); writes the primitives and,
+// with NEXT_DT, returns the cell's Courant step of the next step in dtc
+template <bool NEXT_DT>
+__device__ __forceinline__ void invert_cell(const Launch& L, const BlockInfo& bi, const Cell& c,
+                                            const Metric& m, int64_t col, const C2PIn& cs,
+                                            bool first, double W0, double v0, const double PS[5],
+                                            double* __restrict__ Pout, int& tier, int& iters,
+                                            int& hits, double& dtc) {
+  const GeoTab& G = L.geo;
+  double Pnew[5];
+  tier = c2p_solve(cs, m, first, W0, v0, PS, L.ph.tol, L.ph.maxit, Pnew, iters);
+  // B^i = Bbar^i / sqrt(-g) with Bbar^i the face average; c2p_setup holds alpha B^i
+  const double ia = 1.0 / m.alpha;
+  const double Bnew[3] = {cs.B1 * ia, cs.B2 * ia, cs.B3 * ia};
+  hits = apply_floors(Pnew, Bnew, m, G.c[RHOFL * G.ncol + col], G.c[UFL * G.ncol + col],
+                      L.ph.bsq_rho_max, L.ph.bsq_u_max, L.ph.gamma_max);
+#pragma unroll
+  for (int v = 0; v < 5; v++) Pout[5 * bi.off + (int64_t)v * bi.vol + c.loc] = Pnew[v];
+  if (NEXT_DT) dtc = cell_dt(Pnew, Bnew, m, L.ph, bi.idx);
+}
+
+template <bool STATS, bool NEXT_DT>
+__device__ __forceinline__ void update_epilogue(const Launch& L, const Tile& tl, bool valid,
+                                                int tier, int iters, int hits, double dtc,
+                                                double* __restrict__ dt_part) {
   if (NEXT_DT) {
     const double r = block_min(dtc);
     if (threadIdx.x == 0) dt_part[(int64_t)tl.y * gridDim.x + tl.x] = r;
@@ -466,6 +466,98 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     const long long h = wave_sum(valid ? hits : 0);
     if (lane_id() == 0 && h) atomicAdd(&L.cnt->floors, (unsigned long long)h);
   }
+}
+
+// fused update: conserved update, optional learned guess, inversion, floors, next dt
+template <bool STATS, bool NEXT_DT, bool MLP, int OCC, int UN>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_update(
+    Launch L, const double* __restrict__ Pn, const double* __restrict__ Bn,
+    const double* __restrict__ Ps, const double* __restrict__ Bcs, const double* __restrict__ F,
+    const double* __restrict__ E, double dt_factor, double* __restrict__ Pout,
+    double* __restrict__ Bout, double* __restrict__ dt_part, const MlpBlob* __restrict__ mlp,
+    double* __restrict__ un) {
+  const Tile tl = xcd_tile();
+  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
+  const int g = L.ph.ng;
+  Cell c;
+  const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
+                                 g, g, c);
+  int tier = 0, iters = 0, hits = 0;
+  double dtc = __longlong_as_double(0x7FF0000000000000LL);
+  const int64_t col = valid ? geo_col(L.geo, bi, c.J, c.I) : 0;
+  Metric m;
+  C2PIn cs;
+  double PS[5];
+  if (valid) {
+    m = load_metric(L.geo.c, L.geo.ncol, col);
+    double U[9];
+    conserve_cell<UN>(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, un, U, PS);
+    c2p_setup(U, m, L.ph.gam, cs);
+  }
+  bool first = false;
+  double W0 = 0.0, v0 = 0.0;
+  if (MLP) first = mlp_guess_block(mlp, cs, m, valid, W0, v0);
+  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, Pout, tier, iters, hits, dtc);
+  update_epilogue<STATS, NEXT_DT>(L, tl, valid, tier, iters, hits, dtc, dt_part);
+}
+
+// split update, first half: the conserved state of every cell into ubuf [9][cell]
+template <int UN>
+__global__ __launch_bounds__(NT) void k_conserve(Launch L, const double* __restrict__ Pn,
+                                                 const double* __restrict__ Bn,
+                                                 const double* __restrict__ Ps,
+                                                 const double* __restrict__ Bcs,
+                                                 const double* __restrict__ F,
+                                                 const double* __restrict__ E, double dt_factor,
+                                                 double* __restrict__ Bout,
+                                                 double* __restrict__ un,
+                                                 double* __restrict__ ubuf) {
+  const Tile tl = xcd_tile();
+  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
+  const int g = L.ph.ng;
+  Cell c;
+  if (!region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g, g, g, c)) return;
+  const int64_t col = geo_col(L.geo, bi, c.J, c.I);
+  const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
+  double U[9], PS[5];
+  conserve_cell<UN>(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, un, U, PS);
+  double* u = ubuf + 9 * bi.off + c.loc;
+#pragma unroll
+  for (int q = 0; q < 9; q++) u[(int64_t)q * bi.vol] = U[q];
+}
+
+// split update, second half: inversion, floors, next dt from ubuf
+template <bool STATS, bool NEXT_DT, bool MLP, int OCC>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_invert(
+    Launch L, const double* __restrict__ Ps, const double* __restrict__ ubuf,
+    double* __restrict__ Pout, double* __restrict__ dt_part, const MlpBlob* __restrict__ mlp) {
+  const Tile tl = xcd_tile();
+  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
+  const int g = L.ph.ng;
+  Cell c;
+  const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
+                                 g, g, c);
+  int tier = 0, iters = 0, hits = 0;
+  double dtc = __longlong_as_double(0x7FF0000000000000LL);
+  const int64_t col = valid ? geo_col(L.geo, bi, c.J, c.I) : 0;
+  Metric m;
+  C2PIn cs;
+  double PS[5];
+  if (valid) {
+    m = load_metric(L.geo.c, L.geo.ncol, col);
+    double U[9];
+    const double* u = ubuf + 9 * bi.off + c.loc;
+#pragma unroll
+    for (int q = 0; q < 9; q++) U[q] = u[(int64_t)q * bi.vol];
+#pragma unroll
+    for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * bi.vol + c.loc];
+    c2p_setup(U, m, L.ph.gam, cs);
+  }
+  bool first = false;
+  double W0 = 0.0, v0 = 0.0;
+  if (MLP) first = mlp_guess_block(mlp, cs, m, valid, W0, v0);
+  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, Pout, tier, iters, hits, dtc);
+  update_epilogue<STATS, NEXT_DT>(L, tl, valid, tier, iters, hits, dtc, dt_part);
 }
 
 // ------------------------------------------------------------- Courant reduction
@@ -696,8 +788,12 @@ static void flux_dir(const Launch& L, int recon, int riemann, const double* P, c
 #define GRMHD_FLUX(RC, RM, V)                                                                \
   hipLaunchKernelGGL((k_flux<DIR, RC, RM, FLUX_OCC[V]>), grid, dim3(NT), 0, L.stream, L, P, Bc, \
                      B, F)
-#define GRMHD_FLUX_V(RC, RM) \
-  if (v == 0) GRMHD_FLUX(RC, RM, 0); else if (v == 1) GRMHD_FLUX(RC, RM, 1); else GRMHD_FLUX(RC, RM, 2)
+#define GRMHD_FLUX_V(RC, RM)                                              \
+  switch (v) {                                                            \
+    case 0: GRMHD_FLUX(RC, RM, 0); break;                                 \
+    case 1: GRMHD_FLUX(RC, RM, 1); break;                                 \
+    default: GRMHD_FLUX(RC, RM, 2); break;                                \
+  }
   if (recon == 0 && riemann == 0) {
     GRMHD_FLUX_V(0, 0);
   } else if (recon == 0) {
@@ -731,17 +827,45 @@ int64_t dt_partials(const Launch& L) {
 void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
                    const double* Bcs, const double* F, const double* E, double dt_factor,
                    double* Pout, double* Bout, double* dt_part, const void* mlp, double* un,
-                   bool reuse_un) {
+                   bool reuse_un, double* ubuf) {
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
   const dim3 grid(cdiv(r, NT), L.nblk);
   const MlpBlob* blob = (const MlpBlob*)mlp;
+  if (L.split_upd && ubuf) {
+    if (reuse_un)
+      hipLaunchKernelGGL((k_conserve<2>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps, Bcs, F, E,
+                         dt_factor, Bout, un, ubuf);
+    else
+      hipLaunchKernelGGL((k_conserve<1>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps, Bcs, F, E,
+                         dt_factor, Bout, un, ubuf);
+#define GRMHD_INV(ND, ML, V)                                                                   \
+  hipLaunchKernelGGL((k_invert<true, ND, ML, UPD_OCC[V]>), grid, dim3(NT), 0, L.stream, L, Ps, \
+                     ubuf, Pout, dt_part, blob)
+#define GRMHD_INV_V(ND, ML) \
+  if (L.var_upd == 0) { GRMHD_INV(ND, ML, 0); } else { GRMHD_INV(ND, ML, 1); }
+    if (dt_part && blob) {
+      GRMHD_INV_V(true, true);
+    } else if (dt_part) {
+      GRMHD_INV_V(true, false);
+    } else if (blob) {
+      GRMHD_INV_V(false, true);
+    } else {
+      GRMHD_INV_V(false, false);
+    }
+#undef GRMHD_INV_V
+#undef GRMHD_INV
+    return;
+  }
 #define GRMHD_UPD(ND, ML, V, U)                                                                 \
   hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], U>), grid, dim3(NT), 0, L.stream, L, Pn, \
                      Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob, un)
 #define GRMHD_UPD_U(ND, ML, V) \
   if (reuse_un) GRMHD_UPD(ND, ML, V, 2); else GRMHD_UPD(ND, ML, V, 1)
-#define GRMHD_UPD_V(ND, ML) \
-  if (L.var_upd == 0) { GRMHD_UPD_U(ND, ML, 0); } else { GRMHD_UPD_U(ND, ML, 1); }
+#define GRMHD_UPD_V(ND, ML)                                               \
+  switch (L.var_upd) {                                                    \
+    case 0: GRMHD_UPD_U(ND, ML, 0); break;                                \
+    default: GRMHD_UPD_U(ND, ML, 1); break;                               \
+  }
   if (dt_part && blob) {
     GRMHD_UPD_V(true, true);
   } else if (dt_part) {

@@ -29,7 +29,7 @@ EXPORTS = ("grmhd_sizes", "grmhd_block_layout", "grmhd_init_grid", "grmhd_step",
            "grmhd_mlp_sizes", "grmhd_mlp_train_step", "grmhd_mlp_gradients", "grmhd_mlp_pack",
            "grmhd_mlp_forward", "grmhd_prim2cons_batch", "grmhd_mlp_dataset",
            "grmhd_mlp_normalize", "grmhd_extract_cells", "grmhd_destroy", "grmhd_last_error",
-           "grmhd_autotune")
+           "grmhd_autotune", "grmhd_set_variants")
 
 
 class BlockDesc(C.Structure):
@@ -74,6 +74,12 @@ class C2PBatch(C.Structure):
                 ("maxit", C.c_int32), ("mlp_weights", C.c_void_p)]
 
 
+# occupancy variants of the flux and update kernels (minimum waves per SIMD), as built
+FLUX_WAVES = (1, 2, 4)
+UPDATE_WAVES = (1, 2)
+NVAR_FLUX, NVAR_UPD = len(FLUX_WAVES), len(UPDATE_WAVES)
+
+
 class GrmhdError(RuntimeError):
     pass
 
@@ -93,6 +99,7 @@ def lib():
                                       C.POINTER(C.c_void_p)]
         L.grmhd_step.argtypes = [C.c_void_p, C.c_int32, C.POINTER(StepStats)]
         L.grmhd_autotune.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.grmhd_set_variants.argtypes = [C.c_void_p, C.c_void_p]
         L.grmhd_cons2prim.argtypes = [C.c_void_p, C.POINTER(C2PBatch), C.c_void_p]
         L.grmhd_divb.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.c_void_p]
@@ -377,12 +384,20 @@ class Grid:
     def autotune(self):
         """time the kernel variants on the current state and keep the fastest; returns
         the chosen variants and the milliseconds per variant"""
-        choice = (C.c_int32 * 4)()
-        ms = (C.c_double * 11)()
+        nf, nu = NVAR_FLUX, NVAR_UPD
+        choice = (C.c_int32 * 5)()
+        ms = (C.c_double * (3 * nf + 2 * nu))()
         _check(lib().grmhd_autotune(self.ctx, choice, ms))
         return {"flux": [choice[k] for k in range(3)], "update": choice[3],
-                "flux_ms": [[ms[d * 3 + v] for v in range(3)] for d in range(3)],
-                "update_ms": [ms[9], ms[10]]}
+                "update_split": choice[4],
+                "flux_waves": FLUX_WAVES, "update_waves": UPDATE_WAVES,
+                "flux_ms": [[ms[d * nf + v] for v in range(nf)] for d in range(3)],
+                "update_ms": [ms[3 * nf + v] for v in range(nu)],
+                "update_split_ms": [ms[3 * nf + nu + v] for v in range(nu)]}
+
+    def set_variants(self, flux=(2, 2, 2), update=0, split=0):
+        choice = (C.c_int32 * 5)(flux[0], flux[1], flux[2], update, split)
+        _check(lib().grmhd_set_variants(self.ctx, choice))
 
     def divb(self):
         a, r = C.c_double(), C.c_double()
