@@ -154,6 +154,11 @@ struct Plan {
   std::vector<AmrSample> samples;
   std::vector<AmrLink> links;   // refinement faces, sorted by time level
   int32_t link_maxpos = 0;
+  // work lists of the stage kernels for blocks of uneven sizes: per block list (each
+  // time level, then all blocks) and region class, the (block, tile) items
+  bool use_wl = false;
+  std::vector<int2> wl;
+  std::vector<int64_t> wl_off;   // [(list * WL_N + class)], one more at the end
   // local time stepping
   int32_t nlev = 1;
   std::vector<int32_t> lev_blocks;             // block ids sorted by level
@@ -167,7 +172,7 @@ struct Plan {
   int32_t rs = 0, rs2 = 0;                     // register plane size and row stride
   // work-buffer offsets (bytes)
   size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, o_dtp;
-  size_t o_aops[4], o_samp, o_links, o_un, o_u9;
+  size_t o_aops[4], o_samp, o_links, o_un, o_u9, o_wl;
   size_t o_pold, o_bold, o_reg, o_ubuf, o_lev, o_items, total;
 };
 
@@ -798,6 +803,42 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
     for (int l = 0; l < L; l++) p.item_off[l + 1] += p.item_off[l];
     p.rs2 = p.max_n[1] + 1;
     p.rs = (p.max_n[2] + 1) * p.rs2;
+    // work lists when block sizes differ (equal sizes leave no idle tiles in the grid)
+    p.use_wl = false;
+    for (int b = 1; b < nb; b++)
+      for (int k = 0; k < 3; k++)
+        if (p.blocks[b].n[k] != p.blocks[0].n[k]) p.use_wl = true;
+    p.wl.clear();
+    p.wl_off.clear();
+    if (p.use_wl) {
+      auto region = [&](int b, int cls) -> int64_t {
+        const BlockInfo& bi = p.info[b];
+        switch (cls) {
+          case WL_BCELL: return (int64_t)bi.np[0] * bi.np[1] * bi.np[2];
+          case WL_EMF: return (int64_t)(bi.n[0] + 1) * (bi.n[1] + 1) * (bi.n[2] + 1);
+          case WL_CELLS: return (int64_t)bi.n[0] * bi.n[1] * bi.n[2];
+          default: {
+            const int d = cls - WL_FLUX1;
+            int64_t r = 1;
+            for (int e = 0; e < 3; e++) r *= e == d ? bi.n[e] + 1 : bi.n[e] + 2;
+            return r;
+          }
+        }
+      };
+      for (int list = 0; list <= L; list++) {
+        for (int cls = 0; cls < WL_N; cls++) {
+          p.wl_off.push_back((int64_t)p.wl.size());
+          const int64_t b0 = list < L ? p.lev_boff[list] : 0;
+          const int64_t b1 = list < L ? p.lev_boff[list + 1] : nb;
+          for (int64_t q = b0; q < b1; q++) {
+            const int b = list < L ? p.lev_blocks[q] : (int)q;
+            const int64_t nt = (region(b, cls) + STAGE_NT - 1) / STAGE_NT;
+            for (int64_t t = 0; t < nt; t++) p.wl.push_back(make_int2(b, (int)t));
+          }
+        }
+      }
+      p.wl_off.push_back((int64_t)p.wl.size());
+    }
   }
   // work-buffer layout
   size_t o = 0;
@@ -830,6 +871,7 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
   }
   p.o_samp = take(p.samples.size() * sizeof(AmrSample));
   p.o_links = take(p.links.size() * sizeof(AmrLink));
+  p.o_wl = take(p.wl.size() * sizeof(int2));
   p.o_cnt = take(sizeof(Counters));
   const bool lat = p.nlev > 1;
   p.o_pold = take(lat ? 5 * V * 8 : 0);
@@ -917,6 +959,7 @@ struct grmhd_ctx {
   int64_t naops[4];
   AmrSample* samp = nullptr;
   AmrLink* links = nullptr;
+  int2* wl = nullptr;
   bool b_in_alt = false;
   const void* mlp = nullptr;   // packed MLP blob when the learned guess is on
   // local time stepping
@@ -929,6 +972,21 @@ struct grmhd_ctx {
   hipGraphExec_t graph_exec = nullptr;
   hipEvent_t ev0, ev1;
 };
+
+// the work lists of block list `list` (a time level, or nlev for all blocks) into L
+static void set_work_lists(const grmhd_ctx* c, Launch& L, int list) {
+  const Plan& p = c->plan;
+  for (int cls = 0; cls < WL_N; cls++) {
+    if (!p.use_wl) {
+      L.wls[cls] = nullptr;
+      L.nwls[cls] = 0;
+      continue;
+    }
+    const int64_t o = p.wl_off[(size_t)list * WL_N + cls];
+    L.wls[cls] = c->wl + o;
+    L.nwls[cls] = (int32_t)(p.wl_off[(size_t)list * WL_N + cls + 1] - o);
+  }
+}
 
 extern "C" {
 
@@ -1016,6 +1074,11 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   }
   c->samp = (AmrSample*)(w + p.o_samp);
   c->links = (AmrLink*)(w + p.o_links);
+  c->wl = (int2*)(w + p.o_wl);
+  if ((rc = up(p.o_wl, p.wl.data(), p.wl.size() * sizeof(int2)))) {
+    delete c;
+    return rc;
+  }
   if ((rc = up(p.o_samp, p.samples.data(), p.samples.size() * sizeof(AmrSample))) ||
       (rc = up(p.o_links, p.links.data(), p.links.size() * sizeof(AmrLink))) ||
       (rc = up(p.o_lev, p.lev_blocks.data(), p.lev_blocks.size() * sizeof(int32_t))) ||
@@ -1048,6 +1111,8 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   for (int k = 0; k < 3; k++) L.var_flux[k] = 2;   // 4 waves per SIMD
   L.var_upd = 0;
   L.split_upd = 0;
+  set_work_lists(c, L, p.nlev);   // the all-blocks lists
+  L.wl = nullptr;
   c->profile = desc->profile != 0;
   c->mlp = desc->c2p_guess == GRMHD_GUESS_MLP ? desc->mlp_weights : nullptr;
   launch_counters_reset(L, true);
@@ -1124,6 +1189,7 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
   Launch L = base;
   L.blist = c->lev_list + p.lev_boff[lev];
   L.nblk = (int32_t)(p.lev_boff[lev + 1] - p.lev_boff[lev]);
+  set_work_lists(c, L, lev);
   if (L.nblk == 0) return;
   const int recon = p.d.recon, riem = p.d.riemann;
   double* P = c->bufs.prim;

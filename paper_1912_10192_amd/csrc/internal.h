@@ -101,6 +101,11 @@ __host__ __device__ inline int64_t geo_col(const GeoTab&, const BlockInfo& bi, i
   return bi.gbase + (int64_t)(bi.gorg[1] + J) * bi.gti + (bi.gorg[0] + I);
 }
 
+// region classes of the stage kernels' work lists: padded block, faces per direction,
+// edges, interior cells
+enum { WL_BCELL = 0, WL_FLUX1, WL_FLUX2, WL_FLUX3, WL_EMF, WL_CELLS, WL_N };
+constexpr int STAGE_NT = 256;   // threads per workgroup of the stage kernels
+
 // occupancy variants of the flux and update kernels (see kernels.hip)
 constexpr int NVAR_FLUX = GRMHD_NVAR_FLUX, NVAR_UPD = GRMHD_NVAR_UPD;
 
@@ -117,6 +122,12 @@ struct Launch {
   int32_t var_flux[3];    // variant of the flux kernel per direction
   int32_t var_upd;        // variant of the update kernel
   int32_t split_upd;      // 1: the update as two kernels (conserved state, then inversion)
+  // Work lists of (block, tile) items for blocks of uneven sizes, one per region class
+  // of the listed blocks (NULL: a rectangular grid of max tiles x blocks); wl is the
+  // list of the launch in flight, set by the launcher on its own copy.
+  const int2* wls[WL_N];
+  int32_t nwls[WL_N];
+  const int2* wl;
 };
 
 // records the message returned by grmhd_last_error() and returns code (host.cpp)

@@ -15,7 +15,7 @@
 
 namespace grmhd {
 
-constexpr int NT = 256;   // threads per workgroup (four wavefronts)
+constexpr int NT = STAGE_NT;   // threads per workgroup (four wavefronts)
 
 // The two heavy kernels come in occupancy variants: the minimum number of waves per
 // SIMD the compiler must fit (trading registers for latency hiding).  Which variant a
@@ -68,6 +68,33 @@ __device__ __forceinline__ Tile xcd_tile() {
   t.x = n % gridDim.x;
   t.y = n / gridDim.x;
   return t;
+}
+
+// The block and tile of this workgroup: from the launch's work list when it has one
+// (items of one block grouped on one XCD), else from the rectangular grid; slot is the
+// workgroup's index for per-workgroup partials.
+struct BlockTile {
+  int blk, tile;
+  int64_t slot;
+};
+__device__ __forceinline__ BlockTile block_tile(const Launch& L) {
+  BlockTile r;
+  if (L.wl) {
+    const int T = gridDim.x, i = blockIdx.x;
+    const int x = i & 7, q = i >> 3;
+    const int full = T >> 3, rem = T & 7;
+    const int n = x < rem ? x * (full + 1) + q : rem * (full + 1) + (x - rem) * full + q;
+    const int2 w = L.wl[n];
+    r.blk = w.x;
+    r.tile = w.y;
+    r.slot = n;
+  } else {
+    const Tile tl = xcd_tile();
+    r.blk = L.blist ? L.blist[tl.y] : tl.y;
+    r.tile = tl.x;
+    r.slot = (int64_t)tl.y * gridDim.x + tl.x;
+  }
+  return r;
 }
 
 // decode a thread index of a box region (r0, r1, r2) starting at s into local coords
@@ -132,10 +159,10 @@ __global__ __launch_bounds__(NT) void k_ghost_faces(const BlockInfo* __restrict_
 // cell that has both faces in the padded block
 __global__ __launch_bounds__(NT) void k_bcell(Launch L, const double* __restrict__ B,
                                               double* __restrict__ Bc) {
-  const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
+  const BlockTile bt = block_tile(L);
+  const BlockInfo bi = L.blk[bt.blk];
   Cell c;
-  if (!region_cell(bi, tl.x * NT + threadIdx.x, bi.np[0], bi.np[1], bi.np[2], 0, 0, 0, c))
+  if (!region_cell(bi, bt.tile * NT + threadIdx.x, bi.np[0], bi.np[1], bi.np[2], 0, 0, 0, c))
     return;
   const int64_t V = bi.vol;
   const double* b = B + 3 * bi.off;
@@ -156,14 +183,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
                                              const double* __restrict__ Bc,
                                              const double* __restrict__ B,
                                              double* __restrict__ F) {
-  const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
+  const BlockTile bt = block_tile(L);
+  const BlockInfo bi = L.blk[bt.blk];
   const int g = L.ph.ng;
   const int r0 = DIR == 1 ? bi.n[0] + 1 : bi.n[0] + 2;
   const int r1 = DIR == 2 ? bi.n[1] + 1 : bi.n[1] + 2;
   const int r2 = DIR == 3 ? bi.n[2] + 1 : bi.n[2] + 2;
   Cell c;
-  if (!region_cell(bi, tl.x * NT + threadIdx.x, r0, r1, r2, DIR == 1 ? g : g - 1,
+  if (!region_cell(bi, bt.tile * NT + threadIdx.x, r0, r1, r2, DIR == 1 ? g : g - 1,
                    DIR == 2 ? g : g - 1, DIR == 3 ? g : g - 1, c))
     return;
   const int64_t V = bi.vol;
@@ -249,11 +276,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
 // average of the four face fluxes of B around the edge (Sec. 2.5); zero on the axis.
 __global__ __launch_bounds__(NT) void k_emf(Launch L, const double* __restrict__ F,
                                             double* __restrict__ E) {
-  const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
+  const BlockTile bt = block_tile(L);
+  const BlockInfo bi = L.blk[bt.blk];
   const int g = L.ph.ng;
   Cell c;
-  if (!region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0] + 1, bi.n[1] + 1, bi.n[2] + 1, g, g,
+  if (!region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0] + 1, bi.n[1] + 1, bi.n[2] + 1, g, g,
                    g, c))
     return;
   const int64_t V = bi.vol;
@@ -453,12 +480,12 @@ __device__ __forceinline__ void invert_cell(const Launch& L, const BlockInfo& bi
 }
 
 template <bool STATS, bool NEXT_DT>
-__device__ __forceinline__ void update_epilogue(const Launch& L, const Tile& tl, bool valid,
+__device__ __forceinline__ void update_epilogue(const Launch& L, const BlockTile& bt, bool valid,
                                                 int tier, int iters, int hits, double dtc,
                                                 double* __restrict__ dt_part) {
   if (NEXT_DT) {
     const double r = block_min(dtc);
-    if (threadIdx.x == 0) dt_part[(int64_t)tl.y * gridDim.x + tl.x] = r;
+    if (threadIdx.x == 0) dt_part[bt.slot] = r;
   }
   if (STATS) {
     wave_histogram(L.cnt->tier, tier, valid);
@@ -476,11 +503,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     const double* __restrict__ E, double dt_factor, double* __restrict__ Pout,
     double* __restrict__ Bout, double* __restrict__ dt_part, const MlpBlob* __restrict__ mlp,
     double* __restrict__ un) {
-  const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
+  const BlockTile bt = block_tile(L);
+  const BlockInfo bi = L.blk[bt.blk];
   const int g = L.ph.ng;
   Cell c;
-  const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
+  const bool valid = region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
                                  g, g, c);
   int tier = 0, iters = 0, hits = 0;
   double dtc = __longlong_as_double(0x7FF0000000000000LL);
@@ -498,7 +525,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   double W0 = 0.0, v0 = 0.0;
   if (MLP) first = mlp_guess_block(mlp, cs, m, valid, W0, v0);
   if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, Pout, tier, iters, hits, dtc);
-  update_epilogue<STATS, NEXT_DT>(L, tl, valid, tier, iters, hits, dtc, dt_part);
+  update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, dtc, dt_part);
 }
 
 // split update, first half: the conserved state of every cell into ubuf [9][cell]
@@ -512,11 +539,11 @@ __global__ __launch_bounds__(NT) void k_conserve(Launch L, const double* __restr
                                                  double* __restrict__ Bout,
                                                  double* __restrict__ un,
                                                  double* __restrict__ ubuf) {
-  const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
+  const BlockTile bt = block_tile(L);
+  const BlockInfo bi = L.blk[bt.blk];
   const int g = L.ph.ng;
   Cell c;
-  if (!region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g, g, g, c)) return;
+  if (!region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g, g, g, c)) return;
   const int64_t col = geo_col(L.geo, bi, c.J, c.I);
   const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
   double U[9], PS[5];
@@ -531,11 +558,11 @@ template <bool STATS, bool NEXT_DT, bool MLP, int OCC>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_invert(
     Launch L, const double* __restrict__ Ps, const double* __restrict__ ubuf,
     double* __restrict__ Pout, double* __restrict__ dt_part, const MlpBlob* __restrict__ mlp) {
-  const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
+  const BlockTile bt = block_tile(L);
+  const BlockInfo bi = L.blk[bt.blk];
   const int g = L.ph.ng;
   Cell c;
-  const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
+  const bool valid = region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
                                  g, g, c);
   int tier = 0, iters = 0, hits = 0;
   double dtc = __longlong_as_double(0x7FF0000000000000LL);
@@ -557,7 +584,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   double W0 = 0.0, v0 = 0.0;
   if (MLP) first = mlp_guess_block(mlp, cs, m, valid, W0, v0);
   if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, Pout, tier, iters, hits, dtc);
-  update_epilogue<STATS, NEXT_DT>(L, tl, valid, tier, iters, hits, dtc, dt_part);
+  update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, dtc, dt_part);
 }
 
 // ------------------------------------------------------------- Courant reduction
@@ -773,9 +800,24 @@ void launch_ghost_faces(const Launch& L, const GhostOp* ops, int64_t nops, doubl
                      B, comp);
 }
 
+// The grid of a stage kernel over region class cls (r: cells of the largest block's
+// region): the launch's work list when it has one, else max tiles x blocks.  Lc is the
+// launch's copy that carries the list to the kernel.
+static dim3 stage_grid(const Launch& L, int cls, int64_t r, Launch& Lc) {
+  Lc = L;
+  Lc.wl = nullptr;
+  if (cls >= 0 && L.wls[cls]) {
+    Lc.wl = L.wls[cls];
+    return dim3((unsigned)L.nwls[cls]);
+  }
+  return dim3(cdiv(r, NT), L.nblk);
+}
+
 void launch_bcell(const Launch& L, const double* B, double* Bc) {
   const int64_t r = (int64_t)L.max_np[0] * L.max_np[1] * L.max_np[2];
-  hipLaunchKernelGGL(k_bcell, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, B, Bc);
+  Launch Lc;
+  const dim3 grid = stage_grid(L, WL_BCELL, r, Lc);
+  hipLaunchKernelGGL(k_bcell, grid, dim3(NT), 0, L.stream, Lc, B, Bc);
 }
 
 template <int DIR>
@@ -783,10 +825,11 @@ static void flux_dir(const Launch& L, int recon, int riemann, const double* P, c
                      const double* B, double* F) {
   int64_t r = 1;
   for (int d = 0; d < 3; d++) r *= (d == DIR - 1) ? L.max_n[d] + 1 : L.max_n[d] + 2;
-  const dim3 grid(cdiv(r, NT), L.nblk);
+  Launch Lc;
+  const dim3 grid = stage_grid(L, WL_FLUX1 + DIR - 1, r, Lc);
   const int v = L.var_flux[DIR - 1];
 #define GRMHD_FLUX(RC, RM, V)                                                                \
-  hipLaunchKernelGGL((k_flux<DIR, RC, RM, FLUX_OCC[V]>), grid, dim3(NT), 0, L.stream, L, P, Bc, \
+  hipLaunchKernelGGL((k_flux<DIR, RC, RM, FLUX_OCC[V]>), grid, dim3(NT), 0, L.stream, Lc, P, Bc, \
                      B, F)
 #define GRMHD_FLUX_V(RC, RM)                                              \
   switch (v) {                                                            \
@@ -816,7 +859,9 @@ void launch_flux(const Launch& L, int dir, int recon, int riemann, const double*
 
 void launch_emf(const Launch& L, const double* F, double* E) {
   const int64_t r = (int64_t)(L.max_n[0] + 1) * (L.max_n[1] + 1) * (L.max_n[2] + 1);
-  hipLaunchKernelGGL(k_emf, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, F, E);
+  Launch Lc;
+  const dim3 grid = stage_grid(L, WL_EMF, r, Lc);
+  hipLaunchKernelGGL(k_emf, grid, dim3(NT), 0, L.stream, Lc, F, E);
 }
 
 int64_t dt_partials(const Launch& L) {
@@ -829,17 +874,19 @@ void launch_update(const Launch& L, const double* Pn, const double* Bn, const do
                    double* Pout, double* Bout, double* dt_part, const void* mlp, double* un,
                    bool reuse_un, double* ubuf) {
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
-  const dim3 grid(cdiv(r, NT), L.nblk);
+  // with per-workgroup Courant partials the rectangular grid (the partials' layout)
+  Launch Lc;
+  const dim3 grid = stage_grid(L, dt_part ? -1 : WL_CELLS, r, Lc);
   const MlpBlob* blob = (const MlpBlob*)mlp;
   if (L.split_upd && ubuf) {
     if (reuse_un)
-      hipLaunchKernelGGL((k_conserve<2>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps, Bcs, F, E,
+      hipLaunchKernelGGL((k_conserve<2>), grid, dim3(NT), 0, L.stream, Lc, Pn, Bn, Ps, Bcs, F, E,
                          dt_factor, Bout, un, ubuf);
     else
-      hipLaunchKernelGGL((k_conserve<1>), grid, dim3(NT), 0, L.stream, L, Pn, Bn, Ps, Bcs, F, E,
+      hipLaunchKernelGGL((k_conserve<1>), grid, dim3(NT), 0, L.stream, Lc, Pn, Bn, Ps, Bcs, F, E,
                          dt_factor, Bout, un, ubuf);
 #define GRMHD_INV(ND, ML, V)                                                                   \
-  hipLaunchKernelGGL((k_invert<true, ND, ML, UPD_OCC[V]>), grid, dim3(NT), 0, L.stream, L, Ps, \
+  hipLaunchKernelGGL((k_invert<true, ND, ML, UPD_OCC[V]>), grid, dim3(NT), 0, L.stream, Lc, Ps, \
                      ubuf, Pout, dt_part, blob)
 #define GRMHD_INV_V(ND, ML) \
   if (L.var_upd == 0) { GRMHD_INV(ND, ML, 0); } else { GRMHD_INV(ND, ML, 1); }
@@ -857,7 +904,7 @@ void launch_update(const Launch& L, const double* Pn, const double* Bn, const do
     return;
   }
 #define GRMHD_UPD(ND, ML, V, U)                                                                 \
-  hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], U>), grid, dim3(NT), 0, L.stream, L, Pn, \
+  hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], U>), grid, dim3(NT), 0, L.stream, Lc, Pn, \
                      Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob, un)
 #define GRMHD_UPD_U(ND, ML, V) \
   if (reuse_un) GRMHD_UPD(ND, ML, V, 2); else GRMHD_UPD(ND, ML, V, 1)
