@@ -471,18 +471,24 @@ __device__ __forceinline__ int cons2prim(const double U[9], const Metric& m, dou
   return c2p_solve(s, m, true, W0, v0, prev, tol, maxit, P, iters);
 }
 
-// raw MLP features of an inversion input (see mlp.h); false if any is not finite
+// raw MLP features of an inversion input (see mlp.h); false if any is not finite.  The
+// ratios are formed in FP64 (their range can exceed FP32's), the logarithms in FP32:
+// the features feed BF16 products, far coarser than FP32 rounding.
 __device__ __forceinline__ bool mlp_features(const C2PIn& s, const Metric& m, float x[8]) {
   const double D = s.D;
+  const double iD = 1.0 / D;
   const double tau = -s.Qdotn - D;
-  const double f[8] = {log(D), asinh(tau / D), log1p(s.Qtsq / (D * D)), log1p(s.Bsq / D),
-                       log1p(s.QdotBsq / (D * D * D)), m.alpha, s.gam, m.gdet / m.alpha};
+  x[0] = logf((float)D);
+  x[1] = asinhf((float)(tau * iD));
+  x[2] = log1pf((float)(s.Qtsq * iD * iD));
+  x[3] = log1pf((float)(s.Bsq * iD));
+  x[4] = log1pf((float)(s.QdotBsq * iD * iD * iD));
+  x[5] = (float)m.alpha;
+  x[6] = (float)s.gam;
+  x[7] = (float)(m.gdet / m.alpha);
   bool ok = D > 0.0;
 #pragma unroll
-  for (int k = 0; k < 8; k++) {
-    x[k] = (float)f[k];
-    ok = ok && isfinite(f[k]);
-  }
+  for (int k = 0; k < 8; k++) ok = ok && isfinite(x[k]);
   return ok;
 }
 
