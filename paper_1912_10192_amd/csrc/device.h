@@ -211,29 +211,30 @@ __device__ __forceinline__ int sym_pair(int a, int b) {
   return lo * 4 - (lo * (lo + 1)) / 2 + hi;   // (0,0)=0 .. (3,3)=9
 }
 
-__device__ __forceinline__ void geometric_source(const double P[5], const Fluid& f,
-                                                 const Metric& m, const double* __restrict__ tab,
-                                                 int64_t ncol, int64_t col, double gam,
-                                                 double Q[4]) {
+// T^k_l of a state: (rho + u + p + b^2) u^k u_l + delta^k_l (p + b^2/2) - b^k b_l
+__device__ __forceinline__ void stress_energy(const double P[5], const Fluid& f, double gam,
+                                              double T[4][4]) {
   const double p = (gam - 1.0) * P[1];
   const double wb = P[0] + P[1] + p + f.bsq;
   const double pb = p + 0.5 * f.bsq;
-  double T[4][4];
 #pragma unroll
   for (int k = 0; k < 4; k++)
 #pragma unroll
     for (int l = 0; l < 4; l++)
       T[k][l] = wb * f.ucon[k] * f.ucov[l] + (k == l ? pb : 0.0) - f.bcon[k] * f.bcov[l];
+}
+
+// q_nu += T^k_l Gamma^l_{nu k} over l = l0, l0 + 1 (conn: the 20 coefficients
+// Gamma^l_{mn}, m <= n, of those two l); summed over l, then k, so that successive calls
+// for l0 = 0 and 2 add the terms in the order of the full contraction
+__device__ __forceinline__ void connection_contract(const double T[4][4], const double conn[20],
+                                                    int l0, double q[4]) {
 #pragma unroll
-  for (int nu = 0; nu < 4; nu++) {
-    double q = 0.0;
+  for (int nu = 0; nu < 4; nu++)
 #pragma unroll
-    for (int l = 0; l < 4; l++)
+    for (int dl = 0; dl < 2; dl++)
 #pragma unroll
-      for (int k = 0; k < 4; k++)
-        q += T[k][l] * tab[(CONN0 + l * 10 + sym_pair(nu, k)) * ncol + col];
-    Q[nu] = m.gdet * q;
-  }
+      for (int k = 0; k < 4; k++) q[nu] += T[k][l0 + dl] * conn[dl * 10 + sym_pair(nu, k)];
 }
 
 // ---------------------------------------------------------------- inversion

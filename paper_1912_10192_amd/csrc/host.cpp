@@ -171,7 +171,8 @@ struct Plan {
   std::vector<int64_t> lev_cells;              // interior cells per level
   int32_t rs = 0, rs2 = 0;                     // register plane size and row stride
   // work-buffer offsets (bytes)
-  size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, o_dtp;
+  size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, o_dtp, o_stp;
+  int64_t slots;   // workgroups of a full-grid stage launch: Courant and statistics partials
   size_t o_aops[4], o_samp, o_links, o_un, o_u9, o_wl;
   size_t o_pold, o_bold, o_reg, o_ubuf, o_lev, o_items, total;
 };
@@ -886,7 +887,9 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
   p.o_lev = take((size_t)nb * sizeof(int32_t));
   {
     const int64_t r = (int64_t)p.max_n[0] * p.max_n[1] * p.max_n[2];
-    p.o_dtp = take((size_t)((r + 255) / 256) * nb * 8);
+    p.slots = (r + 255) / 256 * nb;
+    p.o_dtp = take((size_t)p.slots * 2 * 8);   // two per workgroup for the div B maxima
+    p.o_stp = take((size_t)p.slots * NSTAT * 4);
   }
   p.total = o;
   return GRMHD_OK;
@@ -1107,6 +1110,8 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   L.ph.maxit = desc->c2p_maxit;
   L.ph.ng = desc->n_ghost;
   L.cnt = (Counters*)(w + p.o_cnt);
+  L.stat_part = (uint32_t*)(w + p.o_stp);
+  L.stat_stride = p.slots;
   L.stream = c->stream;
   for (int k = 0; k < 3; k++) L.var_flux[k] = 2;   // 4 waves per SIMD
   L.var_upd = 0;
@@ -1499,7 +1504,7 @@ int grmhd_cons2prim(grmhd_ctx* c, const grmhd_c2p_batch* b, void* hip_stream) {
 int grmhd_divb(grmhd_ctx* c, double* max_abs, double* max_rel, double* field) {
   if (!c) return fail(GRMHD_EINVAL, "NULL context");
   launch_counters_reset(c->L, false);
-  launch_divb(c->L, c->bufs.bface, field);
+  launch_divb(c->L, c->bufs.bface, field, c->dtp);
   HIPCHK(hipGetLastError());
   Counters h;
   HIPCHK(hipMemcpyAsync(&h, c->L.cnt, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));

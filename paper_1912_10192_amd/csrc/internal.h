@@ -106,6 +106,10 @@ __host__ __device__ inline int64_t geo_col(const GeoTab&, const BlockInfo& bi, i
 enum { WL_BCELL = 0, WL_FLUX1, WL_FLUX2, WL_FLUX3, WL_EMF, WL_CELLS, WL_N };
 constexpr int STAGE_NT = 256;   // threads per workgroup of the stage kernels
 
+// per-workgroup statistics records of the update kernels: inversion tier counts, Newton
+// iteration histogram, floor limits
+enum { ST_TIER = 0, ST_HIST = 5, ST_FLOORS = 69, NSTAT = 70 };
+
 // occupancy variants of the flux and update kernels (see kernels.hip)
 constexpr int NVAR_FLUX = GRMHD_NVAR_FLUX, NVAR_UPD = GRMHD_NVAR_UPD;
 
@@ -128,6 +132,9 @@ struct Launch {
   const int2* wls[WL_N];
   int32_t nwls[WL_N];
   const int2* wl;
+  // statistics records of the update kernels, [NSTAT][stat_stride] (one per workgroup)
+  uint32_t* stat_part;
+  int64_t stat_stride;
 };
 
 // records the message returned by grmhd_last_error() and returns code (host.cpp)
@@ -153,7 +160,9 @@ void launch_dt_final(const Launch& L, const double* dt_part);
 void launch_counters_reset(const Launch& L, bool all);
 void launch_tsim(const Launch& L);
 void launch_copy(const Launch& L, const double* src, double* dst, int64_t n);
-void launch_divb(const Launch& L, const double* B, double* field);
+// div B of the face field (field non-null: per cell), maxima through the per-workgroup
+// partials part [2][workgroups]
+void launch_divb(const Launch& L, const double* B, double* field, double* part);
 void launch_extract(const Launch& L, const double* Pin, const double* Bin, int64_t n, double* P,
                     double* B, double* geom);
 // refinement levels (amr.hip)

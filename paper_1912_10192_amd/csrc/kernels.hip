@@ -12,6 +12,7 @@
 #include "device.h"
 #include "internal.h"
 #include "mlp.h"
+#include "wave.h"
 
 namespace grmhd {
 
@@ -23,34 +24,6 @@ constexpr int NT = STAGE_NT;   // threads per workgroup (four wavefronts)
 // (variants asking for 6 or 8 waves spill and run 1.2-4x slower on MI355X; not built)
 constexpr int FLUX_OCC[NVAR_FLUX] = {1, 2, 4};
 constexpr int UPD_OCC[NVAR_UPD] = {1, 2};
-
-__device__ __forceinline__ int lane_id() { return __lane_id(); }
-
-// add one to ctr[value] for every active lane, one atomic per distinct value per wave
-__device__ __forceinline__ void wave_histogram(unsigned long long* ctr, int value, bool active) {
-  unsigned long long mask = __ballot(active);
-  while (mask) {
-    const int leader = __ffsll((long long)mask) - 1;
-    const int v = __shfl(value, leader);
-    const unsigned long long same = __ballot(active && value == v);
-    if (lane_id() == leader) atomicAdd(&ctr[v], (unsigned long long)__popcll(same));
-    if (active && value == v) active = false;
-    mask = __ballot(active);
-  }
-}
-
-__device__ __forceinline__ double wave_min(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-  return v;
-}
-__device__ __forceinline__ long long wave_sum(long long v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Remap the
 // dispatch order so that every XCD works on a contiguous range of (block, tile) indices:
@@ -197,36 +170,40 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   const int64_t st = DIR == 1 ? 1 : (DIR == 2 ? (int64_t)bi.np[0] : (int64_t)bi.np[0] * bi.np[1]);
   const int64_t col = geo_col(L.geo, bi, c.J, c.I);
   const double* tab = DIR == 1 ? L.geo.f1 : (DIR == 2 ? L.geo.f2 : L.geo.c);
+  // All loads of the face (metric, the six-cell lines of the five primitives and of the
+  // two transverse field components, the normal field) in one batch, closed by a
+  // scheduling barrier: otherwise they are issued variable by variable between the
+  // branches of the limiters, a memory round trip each.
   const Metric m = load_metric(tab, L.geo.ncol, col);
   double* out = F + 24 * bi.off + (int64_t)(DIR - 1) * 8 * V + c.loc;
+  constexpr int t1 = DIR == 1 ? 1 : 0;   // transverse field components (0-based)
+  constexpr int t2 = DIR == 3 ? 1 : 2;
+  constexpr int k0 = RECON == 0 ? 1 : 0, k1 = RECON == 0 ? 5 : 6;   // stencil used
+  double sp[5][6], sb[2][6];
+  const double* p = P + 5 * bi.off + c.loc;
+  const double* bc = Bc + 3 * bi.off + c.loc;
+#pragma unroll
+  for (int k = 0; k < 6; k++) {
+#pragma unroll
+    for (int v = 0; v < 5; v++)
+      sp[v][k] = (k < k0 || k >= k1) ? 0.0 : p[(int64_t)v * V + (k - 3) * st];
+    sb[0][k] = (k < k0 || k >= k1) ? 0.0 : bc[(int64_t)t1 * V + (k - 3) * st];
+    sb[1][k] = (k < k0 || k >= k1) ? 0.0 : bc[(int64_t)t2 * V + (k - 3) * st];
+  }
+  const double bface = B[3 * bi.off + (int64_t)(DIR - 1) * V + c.loc];
+  __builtin_amdgcn_sched_barrier(0);
   if (DIR == 2 && m.gdet == 0.0) {   // the polar axis carries no flux
 #pragma unroll
     for (int q = 0; q < 8; q++) out[q * V] = 0.0;
     return;
   }
-  constexpr int t1 = DIR == 1 ? 1 : 0;   // transverse field components (0-based)
-  constexpr int t2 = DIR == 3 ? 1 : 2;
   double PL[5], PR[5], BL[3], BR[3];
   {
-    const double* p = P + 5 * bi.off + c.loc;
-    double s[6];
 #pragma unroll
-    for (int v = 0; v < 5; v++) {
-#pragma unroll
-      for (int k = 0; k < 6; k++)
-        s[k] = (RECON == 0 && (k == 0 || k == 5)) ? 0.0 : p[(int64_t)v * V + (k - 3) * st];
-      recon_face<RECON>(s, PL[v], PR[v]);
-    }
-    const double* bc = Bc + 3 * bi.off + c.loc;
-#pragma unroll
-    for (int k = 0; k < 6; k++)
-      s[k] = (RECON == 0 && (k == 0 || k == 5)) ? 0.0 : bc[(int64_t)t1 * V + (k - 3) * st];
-    recon_face<RECON>(s, BL[t1], BR[t1]);
-#pragma unroll
-    for (int k = 0; k < 6; k++)
-      s[k] = (RECON == 0 && (k == 0 || k == 5)) ? 0.0 : bc[(int64_t)t2 * V + (k - 3) * st];
-    recon_face<RECON>(s, BL[t2], BR[t2]);
-    const double bn = B[3 * bi.off + (int64_t)(DIR - 1) * V + c.loc] / m.gdet;
+    for (int v = 0; v < 5; v++) recon_face<RECON>(sp[v], PL[v], PR[v]);
+    recon_face<RECON>(sb[0], BL[t1], BR[t1]);
+    recon_face<RECON>(sb[1], BL[t2], BR[t2]);
+    const double bn = bface / m.gdet;
     BL[DIR - 1] = bn;
     BR[DIR - 1] = bn;
   }
@@ -358,10 +335,15 @@ __device__ __forceinline__ bool mlp_guess_block(const MlpBlob* __restrict__ blob
 
 // The conserved update of one interior cell (Sec. 2.5): constrained transport of its
 // faces (written to Bout), U^n from P^n, the geometric source at the stage state, the
-// flux divergence; leaves U (9 components, field from the new faces) and the stage
-// primitives PS.  UN = 1: U^n(P^n) is computed and kept in `un` (6 conserved components
-// per cell); UN = 2: it is read back from there (the corrector of the same step, same
-// P^n and B^n).
+// flux divergence; leaves U (9 components, field from the new faces), the stage
+// primitives PS and the cell's density and internal-energy floors fl.  UN = 1: U^n(P^n)
+// is computed and kept in `un` (6 conserved components per cell); UN = 2: it is read
+// back from there (the corrector of the same step, same P^n and B^n).
+//
+// The cell's ~120 global loads are issued in four batches (cell inputs, two halves of
+// the connection coefficients, fluxes), each closed by a scheduling barrier: left to itself the
+// compiler interleaves them with the arithmetic in small groups, and each group then
+// costs a full memory round trip.
 template <int UN>
 __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& bi, const Cell& c,
                                               const Metric& m, int64_t col,
@@ -372,7 +354,7 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
                                               const double* __restrict__ F,
                                               const double* __restrict__ E, double dt_factor,
                                               double* __restrict__ Bout, double* __restrict__ un,
-                                              double U[9], double PS[5]) {
+                                              double U[9], double PS[5], double fl[2]) {
   const int g = L.ph.ng;
   const int64_t V = bi.vol;
   const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
@@ -387,19 +369,42 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
   const double* b1 = Bn + 3 * bi.off;
   const double* b2 = b1 + V;
   const double* b3 = b2 + V;
-  const bool pole_lo = G.f2[GDET * G.ncol + col] == 0.0;
-  const bool pole_hi = G.f2[GDET * G.ncol + col + bi.gti] == 0.0;
+  constexpr int fq[6] = {0, 1, 2, 3, 4, 7};
+  constexpr int uq[6] = {0, 1, 2, 3, 4, 8};
+  double* uc = un + 6 * bi.off + l;
+
+  // batch 1: faces and edges of the cell, polar flags, P^n (or the kept U^n), the stage
+  // state, floors (every address is inside the block's arrays, also at the poles)
+  const double glo = G.f2[GDET * G.ncol + col];
+  const double ghi = G.f2[GDET * G.ncol + col + bi.gti];
+  const double f1lo = b1[l], f1hi = b1[l + 1], f2lo = b2[l], f2hi = b2[l + s2];
+  const double f3lo = b3[l], f3hi = b3[l + s3];
+  const double e1a = e1[l], e1b = e1[l + s2], e1c = e1[l + s3], e1d = e1[l + s2 + s3];
+  const double e2a = e2[l], e2b = e2[l + 1], e2c = e2[l + s3], e2d = e2[l + 1 + s3];
+  const double e3a = e3[l], e3b = e3[l + 1], e3c = e3[l + s2], e3d = e3[l + 1 + s2];
+  double P0[5], BS[3];
+  if (UN == 2) {
+#pragma unroll
+    for (int k = 0; k < 6; k++) U[uq[k]] = uc[(int64_t)k * V];
+  } else {
+#pragma unroll
+    for (int v = 0; v < 5; v++) P0[v] = Pn[5 * bi.off + (int64_t)v * V + l];
+  }
+#pragma unroll
+  for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * V + l];
+#pragma unroll
+  for (int i = 0; i < 3; i++) BS[i] = Bcs[3 * bi.off + (int64_t)i * V + l];
+  fl[0] = G.c[RHOFL * G.ncol + col];
+  fl[1] = G.c[UFL * G.ncol + col];
+  __builtin_amdgcn_sched_barrier(0);
+
   // constrained transport of the six faces of this cell (Sec. 2.5)
-  const double nb1lo = b1[l] + dts * ((e2[l + s3] - e2[l]) * ix3 - (e3[l + s2] - e3[l]) * ix2);
-  const double nb1hi =
-      b1[l + 1] + dts * ((e2[l + 1 + s3] - e2[l + 1]) * ix3 - (e3[l + 1 + s2] - e3[l + 1]) * ix2);
-  const double nb2lo = pole_lo ? 0.0
-      : b2[l] + dts * ((e3[l + 1] - e3[l]) * ix1 - (e1[l + s3] - e1[l]) * ix3);
-  const double nb2hi = pole_hi ? 0.0
-      : b2[l + s2] + dts * ((e3[l + s2 + 1] - e3[l + s2]) * ix1 - (e1[l + s2 + s3] - e1[l + s2]) * ix3);
-  const double nb3lo = b3[l] + dts * ((e1[l + s2] - e1[l]) * ix2 - (e2[l + 1] - e2[l]) * ix1);
-  const double nb3hi =
-      b3[l + s3] + dts * ((e1[l + s3 + s2] - e1[l + s3]) * ix2 - (e2[l + s3 + 1] - e2[l + s3]) * ix1);
+  const double nb1lo = f1lo + dts * ((e2c - e2a) * ix3 - (e3c - e3a) * ix2);
+  const double nb1hi = f1hi + dts * ((e2d - e2b) * ix3 - (e3d - e3b) * ix2);
+  const double nb2lo = glo == 0.0 ? 0.0 : f2lo + dts * ((e3b - e3a) * ix1 - (e1c - e1a) * ix3);
+  const double nb2hi = ghi == 0.0 ? 0.0 : f2hi + dts * ((e3d - e3c) * ix1 - (e1d - e1b) * ix3);
+  const double nb3lo = f3lo + dts * ((e1b - e1a) * ix2 - (e2b - e2a) * ix1);
+  const double nb3hi = f3hi + dts * ((e1d - e1c) * ix2 - (e2d - e2c) * ix1);
   double* o1 = Bout + 3 * bi.off;
   double* o2 = o1 + V;
   double* o3 = o2 + V;
@@ -411,45 +416,62 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
   if (c.K == g + bi.n[2] - 1) o3[l + s3] = nb3hi;
 
   // U^n recomputed from P^n (Sec. 2.5): by the predictor, and kept for the corrector
-  constexpr int fq[6] = {0, 1, 2, 3, 4, 7};
-  constexpr int uq[6] = {0, 1, 2, 3, 4, 8};
-  double* uc = un + 6 * bi.off + l;
-  if (UN == 2) {
-#pragma unroll
-    for (int k = 0; k < 6; k++) U[uq[k]] = uc[(int64_t)k * V];
-  } else {
-    double P0[5], B0[3];
-#pragma unroll
-    for (int v = 0; v < 5; v++) P0[v] = Pn[5 * bi.off + (int64_t)v * V + l];
+  if (UN != 2) {
+    double B0[3];
     const double hg = 0.5 / m.gdet;
-    B0[0] = (b1[l] + b1[l + 1]) * hg;
-    B0[1] = (b2[l] + b2[l + s2]) * hg;
-    B0[2] = (b3[l] + b3[l + s3]) * hg;
+    B0[0] = (f1lo + f1hi) * hg;
+    B0[1] = (f2lo + f2hi) * hg;
+    B0[2] = (f3lo + f3hi) * hg;
     Fluid f;
     fluid_state(P0, B0, m, f);
     flux_vector<0>(P0, f, m, L.ph.gam, entropy_kappa(P0, L.ph.gam), U);
 #pragma unroll
     for (int k = 0; k < 6; k++) uc[(int64_t)k * V] = U[uq[k]];
   }
-#pragma unroll
-  for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * V + l];
+
+  // batches 2 and 3: the connection coefficients of the cell's column, Gamma^l_{nu k}
+  // for l = 0, 1 and then for l = 2, 3 -> geometric source
   double Q[4];
   {
-    double BS[3];
+    double T[4][4];
+    {
+      Fluid f;
+      fluid_state(PS, BS, m, f);
+      stress_energy(PS, f, L.ph.gam, T);
+    }
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < 3; i++) BS[i] = Bcs[3 * bi.off + (int64_t)i * V + l];
-    Fluid f;
-    fluid_state(PS, BS, m, f);
-    geometric_source(PS, f, m, G.c, G.ncol, col, L.ph.gam, Q);
+    for (int h = 0; h < 2; h++) {
+      double conn[20];
+#pragma unroll
+      for (int j = 0; j < 20; j++) conn[j] = G.c[(CONN0 + 20 * h + j) * G.ncol + col];
+      __builtin_amdgcn_sched_barrier(0);
+      connection_contract(T, conn, 2 * h, q);
+    }
+#pragma unroll
+    for (int nu = 0; nu < 4; nu++) Q[nu] = m.gdet * q[nu];
   }
-  const double* f1 = F + 24 * bi.off + l;
-  const double* f2 = f1 + 8 * V;
-  const double* f3 = f2 + 8 * V;
+
+  // batch 4: the fluxes on the six faces -> divergence
+  const double* x1 = F + 24 * bi.off + l;
+  const double* x2 = x1 + 8 * V;
+  const double* x3 = x2 + 8 * V;
+  double fx[6][6];
 #pragma unroll
   for (int k = 0; k < 6; k++) {
     const int64_t o = (int64_t)fq[k] * V;
-    const double div = (f1[o + 1] - f1[o]) * ix1 + (f2[o + s2] - f2[o]) * ix2 +
-                       (f3[o + s3] - f3[o]) * ix3;
+    fx[k][0] = x1[o + 1];
+    fx[k][1] = x1[o];
+    fx[k][2] = x2[o + s2];
+    fx[k][3] = x2[o];
+    fx[k][4] = x3[o + s3];
+    fx[k][5] = x3[o];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < 6; k++) {
+    const double div = (fx[k][0] - fx[k][1]) * ix1 + (fx[k][2] - fx[k][3]) * ix2 +
+                       (fx[k][4] - fx[k][5]) * ix3;
     const double q = (k >= 1 && k <= 4) ? Q[k - 1] : 0.0;
     U[uq[k]] = U[uq[k]] - dts * div + dts * q;
   }
@@ -464,21 +486,24 @@ template <bool NEXT_DT>
 __device__ __forceinline__ void invert_cell(const Launch& L, const BlockInfo& bi, const Cell& c,
                                             const Metric& m, int64_t col, const C2PIn& cs,
                                             bool first, double W0, double v0, const double PS[5],
-                                            double* __restrict__ Pout, int& tier, int& iters,
-                                            int& hits, double& dtc) {
-  const GeoTab& G = L.geo;
+                                            const double fl[2], double* __restrict__ Pout,
+                                            int& tier, int& iters, int& hits, double& dtc) {
   double Pnew[5];
   tier = c2p_solve(cs, m, first, W0, v0, PS, L.ph.tol, L.ph.maxit, Pnew, iters);
   // B^i = Bbar^i / sqrt(-g) with Bbar^i the face average; c2p_setup holds alpha B^i
   const double ia = 1.0 / m.alpha;
   const double Bnew[3] = {cs.B1 * ia, cs.B2 * ia, cs.B3 * ia};
-  hits = apply_floors(Pnew, Bnew, m, G.c[RHOFL * G.ncol + col], G.c[UFL * G.ncol + col],
-                      L.ph.bsq_rho_max, L.ph.bsq_u_max, L.ph.gamma_max);
+  hits = apply_floors(Pnew, Bnew, m, fl[0], fl[1], L.ph.bsq_rho_max, L.ph.bsq_u_max, L.ph.gamma_max);
 #pragma unroll
   for (int v = 0; v < 5; v++) Pout[5 * bi.off + (int64_t)v * bi.vol + c.loc] = Pnew[v];
   if (NEXT_DT) dtc = cell_dt(Pnew, Bnew, m, L.ph, bi.idx);
 }
 
+// Statistics of a workgroup (inversion tiers, Newton iteration numbers, floor limits):
+// counted in LDS, then written as one record per workgroup into the launch's partials
+// [NSTAT][slot] with plain stores; k_stats_final adds the records of a launch to the
+// counters.  (Atomics from every wave on the few counter addresses serialise and cost
+// more than the update itself.)
 template <bool STATS, bool NEXT_DT>
 __device__ __forceinline__ void update_epilogue(const Launch& L, const BlockTile& bt, bool valid,
                                                 int tier, int iters, int hits, double dtc,
@@ -488,10 +513,38 @@ __device__ __forceinline__ void update_epilogue(const Launch& L, const BlockTile
     if (threadIdx.x == 0) dt_part[bt.slot] = r;
   }
   if (STATS) {
-    wave_histogram(L.cnt->tier, tier, valid);
-    wave_histogram(L.cnt->hist, iters < 63 ? iters : 63, valid);
+    __shared__ uint32_t cnt[NSTAT];
+    for (int q = threadIdx.x; q < NSTAT; q += NT) cnt[q] = 0;
+    __syncthreads();
+    wave_count(cnt + ST_TIER, tier, valid);
+    wave_count(cnt + ST_HIST, iters < 63 ? iters : 63, valid);
     const long long h = wave_sum(valid ? hits : 0);
-    if (lane_id() == 0 && h) atomicAdd(&L.cnt->floors, (unsigned long long)h);
+    if (lane_id() == 0 && h) atomicAdd(&cnt[ST_FLOORS], (uint32_t)h);
+    __syncthreads();
+    for (int q = threadIdx.x; q < NSTAT; q += NT)
+      L.stat_part[(int64_t)q * L.stat_stride + bt.slot] = cnt[q];
+  }
+}
+
+// the sum over the n workgroup records of one launch, one workgroup per statistic
+__global__ __launch_bounds__(NT) void k_stats_final(Counters* __restrict__ cnt,
+                                                    const uint32_t* __restrict__ part,
+                                                    int64_t stride, int64_t n) {
+  __shared__ long long red[NT / 64];
+  const int q = blockIdx.x;
+  const uint32_t* p = part + (int64_t)q * stride;
+  long long s = 0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) s += p[i];
+  s = wave_sum(s);
+  if (lane_id() == 0) red[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; w++) t += red[w];
+    unsigned long long* dst = q < ST_HIST ? &cnt->tier[q - ST_TIER]
+                              : (q < ST_FLOORS ? &cnt->hist[q - ST_HIST] : &cnt->floors);
+    if (t) atomicAdd(dst, (unsigned long long)t);
   }
 }
 
@@ -514,17 +567,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   const int64_t col = valid ? geo_col(L.geo, bi, c.J, c.I) : 0;
   Metric m;
   C2PIn cs;
-  double PS[5];
+  double PS[5], fl[2];
   if (valid) {
     m = load_metric(L.geo.c, L.geo.ncol, col);
     double U[9];
-    conserve_cell<UN>(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, un, U, PS);
+    conserve_cell<UN>(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, un, U, PS, fl);
     c2p_setup(U, m, L.ph.gam, cs);
   }
   bool first = false;
   double W0 = 0.0, v0 = 0.0;
   if (MLP) first = mlp_guess_block(mlp, cs, m, valid, W0, v0);
-  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, Pout, tier, iters, hits, dtc);
+  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters, hits, dtc);
   update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, dtc, dt_part);
 }
 
@@ -546,8 +599,8 @@ __global__ __launch_bounds__(NT) void k_conserve(Launch L, const double* __restr
   if (!region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g, g, g, c)) return;
   const int64_t col = geo_col(L.geo, bi, c.J, c.I);
   const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
-  double U[9], PS[5];
-  conserve_cell<UN>(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, un, U, PS);
+  double U[9], PS[5], fl[2];
+  conserve_cell<UN>(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, un, U, PS, fl);
   double* u = ubuf + 9 * bi.off + c.loc;
 #pragma unroll
   for (int q = 0; q < 9; q++) u[(int64_t)q * bi.vol] = U[q];
@@ -569,7 +622,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   const int64_t col = valid ? geo_col(L.geo, bi, c.J, c.I) : 0;
   Metric m;
   C2PIn cs;
-  double PS[5];
+  double PS[5], fl[2];
   if (valid) {
     m = load_metric(L.geo.c, L.geo.ncol, col);
     double U[9];
@@ -578,12 +631,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     for (int q = 0; q < 9; q++) U[q] = u[(int64_t)q * bi.vol];
 #pragma unroll
     for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * bi.vol + c.loc];
+    fl[0] = L.geo.c[RHOFL * L.geo.ncol + col];
+    fl[1] = L.geo.c[UFL * L.geo.ncol + col];
     c2p_setup(U, m, L.ph.gam, cs);
   }
   bool first = false;
   double W0 = 0.0, v0 = 0.0;
   if (MLP) first = mlp_guess_block(mlp, cs, m, valid, W0, v0);
-  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, Pout, tier, iters, hits, dtc);
+  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters, hits, dtc);
   update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, dtc, dt_part);
 }
 
@@ -660,7 +715,8 @@ __global__ __launch_bounds__(NT) void k_copy(const double* __restrict__ s, doubl
 // ----------------------------------------------------------------- divergence
 
 __global__ __launch_bounds__(NT) void k_divb(Launch L, const double* __restrict__ B,
-                                             double* __restrict__ field) {
+                                             double* __restrict__ field,
+                                             double* __restrict__ part) {
   const Tile tl = xcd_tile();
   const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
   const int g = L.ph.ng;
@@ -681,11 +737,51 @@ __global__ __launch_bounds__(NT) void k_divb(Launch L, const double* __restrict_
     a = fabs(dv);
     r = den > 0.0 ? a / den : 0.0;
   }
+  // workgroup maxima as partials [2][slot] (reduced by k_divb_final)
+  __shared__ double red[2][NT / 64];
   a = wave_max(a);
   r = wave_max(r);
   if (lane_id() == 0) {
-    atomicMax(&L.cnt->divb_abs, (unsigned long long)__double_as_longlong(a));
-    atomicMax(&L.cnt->divb_rel, (unsigned long long)__double_as_longlong(r));
+    red[0][threadIdx.x / 64] = a;
+    red[1][threadIdx.x / 64] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 1; w < NT / 64; w++) {
+      a = fmax(a, red[0][w]);
+      r = fmax(r, red[1][w]);
+    }
+    const int64_t n = (int64_t)gridDim.x * gridDim.y;
+    const int64_t slot = (int64_t)tl.y * gridDim.x + tl.x;
+    part[slot] = a;
+    part[n + slot] = r;
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_divb_final(Counters* __restrict__ cnt,
+                                                   const double* __restrict__ part, int64_t n) {
+  __shared__ double red[2][NT / 64];
+  double a = 0.0, r = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += NT) {
+    a = fmax(a, part[i]);
+    r = fmax(r, part[n + i]);
+  }
+  a = wave_max(a);
+  r = wave_max(r);
+  if (lane_id() == 0) {
+    red[0][threadIdx.x / 64] = a;
+    red[1][threadIdx.x / 64] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 1; w < NT / 64; w++) {
+      a = fmax(a, red[0][w]);
+      r = fmax(r, red[1][w]);
+    }
+    atomicMax(&cnt->divb_abs, (unsigned long long)__double_as_longlong(a));
+    atomicMax(&cnt->divb_rel, (unsigned long long)__double_as_longlong(r));
   }
 }
 
@@ -869,6 +965,12 @@ int64_t dt_partials(const Launch& L) {
   return (int64_t)cdiv(r, NT) * L.nblk;
 }
 
+// the statistics records of an update launch on `grid` added to the counters
+static void stats_final(const Launch& L, dim3 grid) {
+  hipLaunchKernelGGL(k_stats_final, dim3(NSTAT), dim3(NT), 0, L.stream, L.cnt, L.stat_part,
+                     L.stat_stride, (int64_t)grid.x * grid.y);
+}
+
 void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
                    const double* Bcs, const double* F, const double* E, double dt_factor,
                    double* Pout, double* Bout, double* dt_part, const void* mlp, double* un,
@@ -901,6 +1003,7 @@ void launch_update(const Launch& L, const double* Pn, const double* Bn, const do
     }
 #undef GRMHD_INV_V
 #undef GRMHD_INV
+    stats_final(L, grid);
     return;
   }
 #define GRMHD_UPD(ND, ML, V, U)                                                                 \
@@ -925,6 +1028,7 @@ void launch_update(const Launch& L, const double* Pn, const double* Bn, const do
 #undef GRMHD_UPD_V
 #undef GRMHD_UPD_U
 #undef GRMHD_UPD
+  stats_final(L, grid);
 }
 
 void launch_dt(const Launch& L, const double* P, const double* B, double* dt_part) {
@@ -949,9 +1053,12 @@ void launch_copy(const Launch& L, const double* src, double* dst, int64_t n) {
   hipLaunchKernelGGL(k_copy, dim3(nb), dim3(NT), 0, L.stream, src, dst, n);
 }
 
-void launch_divb(const Launch& L, const double* B, double* field) {
+void launch_divb(const Launch& L, const double* B, double* field, double* part) {
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
-  hipLaunchKernelGGL(k_divb, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, B, field);
+  const dim3 grid(cdiv(r, NT), L.nblk);
+  hipLaunchKernelGGL(k_divb, grid, dim3(NT), 0, L.stream, L, B, field, part);
+  hipLaunchKernelGGL(k_divb_final, dim3(1), dim3(NT), 0, L.stream, L.cnt, part,
+                     (int64_t)grid.x * grid.y);
 }
 
 void launch_c2p_batch(int64_t n, const double* U, const double* geom, const double* guess,

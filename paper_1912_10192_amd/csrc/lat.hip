@@ -14,6 +14,7 @@
 
 #include "device.h"
 #include "internal.h"
+#include "wave.h"
 
 namespace grmhd {
 
@@ -216,35 +217,39 @@ __global__ __launch_bounds__(LT) void k_sync_c2p(Launch L, const SyncItem* __res
   const int g = L.ph.ng;
   const int t = blockIdx.x * LT + threadIdx.x;
   const int n2 = bi.n[1], n3 = bi.n[2];
-  if (t >= n2 * n3) return;
-  const int K = t / n2 + g, J = t % n2 + g;
-  const int I = it.side == 0 ? g : g + bi.n[0] - 1;
-  const int64_t V = bi.vol;
-  const int64_t l = ((int64_t)K * bi.np[1] + J) * bi.np[0] + I;
-  const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
-  const int64_t col = geo_col(L.geo, bi, J, I);
-  const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
-  double U[9], p[5];
-  const double* u = Ubuf + ((int64_t)blockIdx.y * layer + t) * 9;
-  for (int q = 0; q < 9; q++) U[q] = u[q];
-  const double* b = B + 3 * bi.off;
-  U[5] = 0.5 * (b[l] + b[l + 1]);
-  U[6] = 0.5 * (b[V + l] + b[V + l + s2]);
-  U[7] = 0.5 * (b[2 * V + l] + b[2 * V + l + s3]);
-  for (int v = 0; v < 5; v++) p[v] = P[5 * bi.off + v * V + l];
-  C2PIn cs;
-  c2p_setup(U, m, L.ph.gam, cs);
-  double Pn[5];
-  int iters = 0;
-  const int tier = c2p_solve(cs, m, false, 0.0, 0.0, p, L.ph.tol, L.ph.maxit, Pn, iters);
-  const double Bn[3] = {U[5] / m.gdet, U[6] / m.gdet, U[7] / m.gdet};
-  const int64_t gcol = col;
-  const int hits = apply_floors(Pn, Bn, m, L.geo.c[RHOFL * L.geo.ncol + gcol],
-                                L.geo.c[UFL * L.geo.ncol + gcol], L.ph.bsq_rho_max, L.ph.bsq_u_max,
-                                L.ph.gamma_max);
-  for (int v = 0; v < 5; v++) P[5 * bi.off + v * V + l] = Pn[v];
-  atomicAdd(&L.cnt->tier[tier], 1ULL);
-  if (hits) atomicAdd(&L.cnt->floors, (unsigned long long)hits);
+  const bool valid = t < n2 * n3;
+  int tier = 0, hits = 0;
+  if (valid) {
+    const int K = t / n2 + g, J = t % n2 + g;
+    const int I = it.side == 0 ? g : g + bi.n[0] - 1;
+    const int64_t V = bi.vol;
+    const int64_t l = ((int64_t)K * bi.np[1] + J) * bi.np[0] + I;
+    const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
+    const int64_t col = geo_col(L.geo, bi, J, I);
+    const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
+    double U[9], p[5];
+    const double* u = Ubuf + ((int64_t)blockIdx.y * layer + t) * 9;
+    for (int q = 0; q < 9; q++) U[q] = u[q];
+    const double* b = B + 3 * bi.off;
+    U[5] = 0.5 * (b[l] + b[l + 1]);
+    U[6] = 0.5 * (b[V + l] + b[V + l + s2]);
+    U[7] = 0.5 * (b[2 * V + l] + b[2 * V + l + s3]);
+    for (int v = 0; v < 5; v++) p[v] = P[5 * bi.off + v * V + l];
+    C2PIn cs;
+    c2p_setup(U, m, L.ph.gam, cs);
+    double Pn[5];
+    int iters = 0;
+    tier = c2p_solve(cs, m, false, 0.0, 0.0, p, L.ph.tol, L.ph.maxit, Pn, iters);
+    const double Bn[3] = {U[5] / m.gdet, U[6] / m.gdet, U[7] / m.gdet};
+    hits = apply_floors(Pn, Bn, m, L.geo.c[RHOFL * L.geo.ncol + col],
+                        L.geo.c[UFL * L.geo.ncol + col], L.ph.bsq_rho_max, L.ph.bsq_u_max,
+                        L.ph.gamma_max);
+    for (int v = 0; v < 5; v++) P[5 * bi.off + v * V + l] = Pn[v];
+  }
+  // one counter add per distinct value per wave (every lane of the wave takes part)
+  wave_count(L.cnt->tier, tier, valid);
+  const long long h = wave_sum(valid ? hits : 0);
+  if (lane_id() == 0 && h) atomicAdd(&L.cnt->floors, (unsigned long long)h);
 }
 
 // dt of a cycle: min over partials of the Courant step / 2^lat of the partial's block
