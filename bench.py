@@ -115,6 +115,7 @@ def c2p_summary(st):
     hist = list(st.c2p_iter_hist)
     n = sum(hist[:63])
     return {"tier": list(st.c2p_tier), "floor_hits": st.floor_hits,
+            "learned_guesses": st.mlp_guesses,
             "mean_newton_iters": (sum(i * h for i, h in enumerate(hist[:63])) / n) if n else None}
 
 

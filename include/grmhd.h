@@ -89,7 +89,10 @@ typedef struct {
   int32_t c2p_guess;          /* GRMHD_GUESS_PLAIN (Newton from the cell's previous
                                  primitives) or GRMHD_GUESS_MLP (the network's guess too:
                                  Newton from whichever of the two has the smaller residual
-                                 misfit, then from the other) */
+                                 misfit, then from the other).  Inside the update the
+                                 network runs for a group of 256 cells only if the plain
+                                 guess of one of them has a residual misfit above 1e-2;
+                                 the other groups start from the plain guess */
   int32_t c2p_maxit;          /* Newton iteration cap (50) */
   double c2p_tol;             /* Newton tolerance (1e-12) */
   const void* mlp_weights;    /* device pointer to packed MLP weights, or NULL */
@@ -112,6 +115,7 @@ typedef struct {
   int64_t c2p_iter_hist[64];        /* Newton iterations of accepted solves; 63 = bracketing tiers */
   int64_t c2p_tier[5];              /* 0 first Newton start, 1 second start, 2 1D energy, 3 entropy, 4 failed */
   int64_t floor_hits;
+  int64_t mlp_guesses;              /* inversions that started from the learned guess */
   double dt_min;                    /* last time step */
   double t_sim;                     /* simulated time since init */
   double kernel_ms;                 /* device time of this call (HIP events) */

@@ -1365,6 +1365,7 @@ int grmhd_step(grmhd_ctx* c, int32_t n_cycles, grmhd_step_stats* stats) {
     for (int q = 0; q < 64; q++) stats->c2p_iter_hist[q] = (int64_t)h.hist[q];
     for (int q = 0; q < 5; q++) stats->c2p_tier[q] = (int64_t)h.tier[q];
     stats->floor_hits = (int64_t)h.floors;
+    stats->mlp_guesses = (int64_t)h.mlp;
     stats->dt_min = h.dt_last;
     stats->t_sim = h.t_sim;
     float ms = 0.0f;

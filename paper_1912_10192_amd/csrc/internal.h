@@ -83,6 +83,7 @@ struct Counters {   // device counters of one grmhd_step call
   unsigned long long tier[5];
   unsigned long long hist[64];
   unsigned long long floors;
+  unsigned long long mlp;         // inversions started from the learned guess
   unsigned long long dt_bits;     // min over cells of 1/sum_d(v_d/dx_d), as IEEE bits
   unsigned long long divb_abs;    // max |div B| bits
   unsigned long long divb_rel;
@@ -107,8 +108,8 @@ enum { WL_BCELL = 0, WL_FLUX1, WL_FLUX2, WL_FLUX3, WL_EMF, WL_CELLS, WL_N };
 constexpr int STAGE_NT = 256;   // threads per workgroup of the stage kernels
 
 // per-workgroup statistics records of the update kernels: inversion tier counts, Newton
-// iteration histogram, floor limits
-enum { ST_TIER = 0, ST_HIST = 5, ST_FLOORS = 69, NSTAT = 70 };
+// iteration histogram, floor limits, inversions that used the learned guess
+enum { ST_TIER = 0, ST_HIST = 5, ST_FLOORS = 69, ST_MLP = 70, NSTAT = 71 };
 
 // occupancy variants of the flux and update kernels (see kernels.hip)
 constexpr int NVAR_FLUX = GRMHD_NVAR_FLUX, NVAR_UPD = GRMHD_NVAR_UPD;

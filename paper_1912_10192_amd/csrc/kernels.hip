@@ -333,6 +333,25 @@ __device__ __forceinline__ bool mlp_guess_block(const MlpBlob* __restrict__ blob
   return isfinite(W0) && W0 > 0.0 && v0 >= 0.0 && v0 < 1.0;
 }
 
+// The learned guess where it can pay: the network runs for a workgroup only if the plain
+// guess (the stage primitives) of some cell in it leaves a residual misfit (c2p_misfit)
+// above MLP_GATE.  Below that the plain guess is within a few Newton iterations of the
+// root, as close as the network's guess gets, and the inference would cost more than it
+// saves; large misfits come with cold starts, floors and strong jumps.
+constexpr double MLP_GATE = 1e-2;
+__device__ __forceinline__ bool learned_guess(const MlpBlob* __restrict__ blob, const C2PIn& s,
+                                              const Metric& m, bool valid, const double PS[5],
+                                              double& W0, double& v0) {
+  bool need = false;
+  if (valid) {
+    double Wp, vp;
+    guess_from_prims(s, m, PS, Wp, vp);
+    need = !(c2p_misfit(s, Wp, vp) < MLP_GATE);
+  }
+  if (!__syncthreads_or(need)) return false;
+  return mlp_guess_block(blob, s, m, valid, W0, v0);
+}
+
 // The conserved update of one interior cell (Sec. 2.5): constrained transport of its
 // faces (written to Bout), U^n from P^n, the geometric source at the stage state, the
 // flux divergence; leaves U (9 components, field from the new faces), the stage
@@ -506,8 +525,8 @@ __device__ __forceinline__ void invert_cell(const Launch& L, const BlockInfo& bi
 // more than the update itself.)
 template <bool STATS, bool NEXT_DT>
 __device__ __forceinline__ void update_epilogue(const Launch& L, const BlockTile& bt, bool valid,
-                                                int tier, int iters, int hits, double dtc,
-                                                double* __restrict__ dt_part) {
+                                                int tier, int iters, int hits, bool learned,
+                                                double dtc, double* __restrict__ dt_part) {
   if (NEXT_DT) {
     const double r = block_min(dtc);
     if (threadIdx.x == 0) dt_part[bt.slot] = r;
@@ -520,6 +539,8 @@ __device__ __forceinline__ void update_epilogue(const Launch& L, const BlockTile
     wave_count(cnt + ST_HIST, iters < 63 ? iters : 63, valid);
     const long long h = wave_sum(valid ? hits : 0);
     if (lane_id() == 0 && h) atomicAdd(&cnt[ST_FLOORS], (uint32_t)h);
+    const unsigned long long lm = __ballot(valid && learned);
+    if (lane_id() == 0 && lm) atomicAdd(&cnt[ST_MLP], (uint32_t)__popcll(lm));
     __syncthreads();
     for (int q = threadIdx.x; q < NSTAT; q += NT)
       L.stat_part[(int64_t)q * L.stat_stride + bt.slot] = cnt[q];
@@ -542,8 +563,10 @@ __global__ __launch_bounds__(NT) void k_stats_final(Counters* __restrict__ cnt,
     long long t = 0;
 #pragma unroll
     for (int w = 0; w < NT / 64; w++) t += red[w];
-    unsigned long long* dst = q < ST_HIST ? &cnt->tier[q - ST_TIER]
-                              : (q < ST_FLOORS ? &cnt->hist[q - ST_HIST] : &cnt->floors);
+    unsigned long long* dst = q < ST_HIST     ? &cnt->tier[q - ST_TIER]
+                              : q < ST_FLOORS ? &cnt->hist[q - ST_HIST]
+                              : q == ST_FLOORS ? &cnt->floors
+                                               : &cnt->mlp;
     if (t) atomicAdd(dst, (unsigned long long)t);
   }
 }
@@ -576,9 +599,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   }
   bool first = false;
   double W0 = 0.0, v0 = 0.0;
-  if (MLP) first = mlp_guess_block(mlp, cs, m, valid, W0, v0);
+  if (MLP) first = learned_guess(mlp, cs, m, valid, PS, W0, v0);
   if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters, hits, dtc);
-  update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, dtc, dt_part);
+  update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, first, dtc, dt_part);
 }
 
 // split update, first half: the conserved state of every cell into ubuf [9][cell]
@@ -637,9 +660,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   }
   bool first = false;
   double W0 = 0.0, v0 = 0.0;
-  if (MLP) first = mlp_guess_block(mlp, cs, m, valid, W0, v0);
+  if (MLP) first = learned_guess(mlp, cs, m, valid, PS, W0, v0);
   if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters, hits, dtc);
-  update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, dtc, dt_part);
+  update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, first, dtc, dt_part);
 }
 
 // ------------------------------------------------------------- Courant reduction
@@ -688,6 +711,7 @@ __global__ void k_reset(Counters* cnt, int all) {
   if (t < 64) cnt->hist[t] = 0;
   if (t == 0) {
     cnt->floors = 0;
+    cnt->mlp = 0;
     cnt->divb_abs = 0;
     cnt->divb_rel = 0;
     cnt->dt_bits = 0x7FF0000000000000ULL;

@@ -62,7 +62,7 @@ class StepStats(C.Structure):
     _fields_ = [("real_zone_cycles", C.c_int64), ("lat_eff_zone_cycles", C.c_int64),
                 ("amr_lat_eff_zone_cycles", C.c_int64), ("steps_per_level", C.c_int64 * 8),
                 ("c2p_iter_hist", C.c_int64 * 64), ("c2p_tier", C.c_int64 * 5),
-                ("floor_hits", C.c_int64), ("dt_min", C.c_double), ("t_sim", C.c_double),
+                ("floor_hits", C.c_int64), ("mlp_guesses", C.c_int64), ("dt_min", C.c_double), ("t_sim", C.c_double),
                 ("kernel_ms", C.c_double), ("class_ms", C.c_double * 8),
                 ("class_launches", C.c_int64 * 8)]
 
