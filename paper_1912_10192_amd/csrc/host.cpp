@@ -173,7 +173,7 @@ struct Plan {
   // work-buffer offsets (bytes)
   size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, o_dtp, o_stp;
   int64_t slots;   // workgroups of a full-grid stage launch: Courant and statistics partials
-  size_t o_aops[4], o_samp, o_links, o_un, o_u9, o_wl;
+  size_t o_aops[4], o_samp, o_links, o_u9, o_wl;
   size_t o_pold, o_bold, o_reg, o_ubuf, o_lev, o_items, total;
 };
 
@@ -850,7 +850,6 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
   p.o_bc = take(3 * V * 8);
   p.o_f = take(24 * V * 8);
   p.o_e = take(3 * V * 8);
-  p.o_un = take(6 * V * 8);
   p.o_u9 = take(9 * V * 8);
   p.o_gc = take((size_t)NGEO_C * p.ncol * 8);
   p.o_g1 = take((size_t)NGEO_F * p.ncol * 8);
@@ -955,7 +954,7 @@ struct grmhd_ctx {
   Launch L;
   grmhd_buffers bufs;
   hipStream_t stream;
-  double *ps, *balt, *bc, *f, *e, *dtp, *un, *u9;
+  double *ps, *balt, *bc, *f, *e, *dtp, *u9;
   GhostOp* ops[4];
   int64_t nops[4];
   AmrOp* aops[4];
@@ -1041,7 +1040,6 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   c->f = (double*)(w + p.o_f);
   c->e = (double*)(w + p.o_e);
   c->dtp = (double*)(w + p.o_dtp);
-  c->un = (double*)(w + p.o_un);
   c->u9 = (double*)(w + p.o_u9);
   c->pold = (double*)(w + p.o_pold);
   c->bold = (double*)(w + p.o_bold);
@@ -1176,9 +1174,7 @@ static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double
   launch_amr_fix(L, c->links, (int)c->plan.links.size(), c->plan.link_maxpos, c->f, c->e);
   prof_end(c);
   prof_begin(c, KC_UPDATE);
-  // the corrector (factor 1) reuses the U^n the predictor kept
-  launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, dt_part, c->mlp, c->un,
-                factor == 1.0, c->u9);
+  launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, dt_part, c->mlp, c->u9);
   prof_end(c);
   if (!c->plan.links.empty()) {
     prof_begin(c, KC_GHOST);
@@ -1237,8 +1233,7 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
     launch_amr_fix(L, c->links + lo, (int)nl, p.link_maxpos, c->f, c->e);
     prof_end(c);
     prof_begin(c, KC_UPDATE);
-    launch_update(L, P, B, Ps, c->bc, c->f, c->e, factor, Pout, c->balt, nullptr, c->mlp, c->un,
-                  Ps != P, c->u9);
+    launch_update(L, P, B, Ps, c->bc, c->f, c->e, factor, Pout, c->balt, nullptr, c->mlp, c->u9);
     prof_end(c);
     if (nl > 0) {
       prof_begin(c, KC_GHOST);
@@ -1452,7 +1447,7 @@ int grmhd_autotune(grmhd_ctx* c, int32_t choice[5], double* ms) {
         double t = 0.0;
         rc = time_it([&] {
           launch_update(L, P, B, P, c->bc, c->f, c->e, 0.5, c->ps, c->balt, nullptr, c->mlp,
-                        c->un, false, c->u9);
+                        c->u9);
         }, t);
         if (ms) ms[3 * NVAR_FLUX + sp * NVAR_UPD + v] = t;
         if (t < best) {

@@ -153,8 +153,7 @@ void launch_emf(const Launch& L, const double* F, double* E);
 // (mlp non-null: learned first guess of the inversion from the packed MLP blob)
 void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
                    const double* Bcs, const double* F, const double* E, double dt_factor,
-                   double* Pout, double* Bout, double* dt_part, const void* mlp, double* un,
-                   bool reuse_un, double* ubuf);
+                   double* Pout, double* Bout, double* dt_part, const void* mlp, double* ubuf);
 int64_t dt_partials(const Launch& L);
 void launch_dt(const Launch& L, const double* P, const double* B, double* dt_part);
 void launch_dt_final(const Launch& L, const double* dt_part);

@@ -355,15 +355,14 @@ __device__ __forceinline__ bool learned_guess(const MlpBlob* __restrict__ blob, 
 // The conserved update of one interior cell (Sec. 2.5): constrained transport of its
 // faces (written to Bout), U^n from P^n, the geometric source at the stage state, the
 // flux divergence; leaves U (9 components, field from the new faces), the stage
-// primitives PS and the cell's density and internal-energy floors fl.  UN = 1: U^n(P^n)
-// is computed and kept in `un` (6 conserved components per cell); UN = 2: it is read
-// back from there (the corrector of the same step, same P^n and B^n).
+// primitives PS and the cell's density and internal-energy floors fl.  U^n is
+// recomputed from P^n in both stages: the kernel is bound by its memory traffic, and
+// keeping U^n from the predictor for the corrector moved more bytes than it saved.
 //
 // The cell's ~120 global loads are issued in four batches (cell inputs, two halves of
 // the connection coefficients, fluxes), each closed by a scheduling barrier: left to itself the
 // compiler interleaves them with the arithmetic in small groups, and each group then
 // costs a full memory round trip.
-template <int UN>
 __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& bi, const Cell& c,
                                               const Metric& m, int64_t col,
                                               const double* __restrict__ Pn,
@@ -372,8 +371,8 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
                                               const double* __restrict__ Bcs,
                                               const double* __restrict__ F,
                                               const double* __restrict__ E, double dt_factor,
-                                              double* __restrict__ Bout, double* __restrict__ un,
-                                              double U[9], double PS[5], double fl[2]) {
+                                              double* __restrict__ Bout, double U[9],
+                                              double PS[5], double fl[2]) {
   const int g = L.ph.ng;
   const int64_t V = bi.vol;
   const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
@@ -390,9 +389,8 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
   const double* b3 = b2 + V;
   constexpr int fq[6] = {0, 1, 2, 3, 4, 7};
   constexpr int uq[6] = {0, 1, 2, 3, 4, 8};
-  double* uc = un + 6 * bi.off + l;
 
-  // batch 1: faces and edges of the cell, polar flags, P^n (or the kept U^n), the stage
+  // batch 1: faces and edges of the cell, polar flags, P^n, the stage
   // state, floors (every address is inside the block's arrays, also at the poles)
   const double glo = G.f2[GDET * G.ncol + col];
   const double ghi = G.f2[GDET * G.ncol + col + bi.gti];
@@ -402,13 +400,8 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
   const double e2a = e2[l], e2b = e2[l + 1], e2c = e2[l + s3], e2d = e2[l + 1 + s3];
   const double e3a = e3[l], e3b = e3[l + 1], e3c = e3[l + s2], e3d = e3[l + 1 + s2];
   double P0[5], BS[3];
-  if (UN == 2) {
 #pragma unroll
-    for (int k = 0; k < 6; k++) U[uq[k]] = uc[(int64_t)k * V];
-  } else {
-#pragma unroll
-    for (int v = 0; v < 5; v++) P0[v] = Pn[5 * bi.off + (int64_t)v * V + l];
-  }
+  for (int v = 0; v < 5; v++) P0[v] = Pn[5 * bi.off + (int64_t)v * V + l];
 #pragma unroll
   for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * V + l];
 #pragma unroll
@@ -434,8 +427,8 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
   if (c.J == g + bi.n[1] - 1) o2[l + s2] = nb2hi;
   if (c.K == g + bi.n[2] - 1) o3[l + s3] = nb3hi;
 
-  // U^n recomputed from P^n (Sec. 2.5): by the predictor, and kept for the corrector
-  if (UN != 2) {
+  // U^n from P^n (Sec. 2.5)
+  {
     double B0[3];
     const double hg = 0.5 / m.gdet;
     B0[0] = (f1lo + f1hi) * hg;
@@ -444,8 +437,6 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
     Fluid f;
     fluid_state(P0, B0, m, f);
     flux_vector<0>(P0, f, m, L.ph.gam, entropy_kappa(P0, L.ph.gam), U);
-#pragma unroll
-    for (int k = 0; k < 6; k++) uc[(int64_t)k * V] = U[uq[k]];
   }
 
   // batches 2 and 3: the connection coefficients of the cell's column, Gamma^l_{nu k}
@@ -572,13 +563,12 @@ __global__ __launch_bounds__(NT) void k_stats_final(Counters* __restrict__ cnt,
 }
 
 // fused update: conserved update, optional learned guess, inversion, floors, next dt
-template <bool STATS, bool NEXT_DT, bool MLP, int OCC, int UN>
+template <bool STATS, bool NEXT_DT, bool MLP, int OCC>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_update(
     Launch L, const double* __restrict__ Pn, const double* __restrict__ Bn,
     const double* __restrict__ Ps, const double* __restrict__ Bcs, const double* __restrict__ F,
     const double* __restrict__ E, double dt_factor, double* __restrict__ Pout,
-    double* __restrict__ Bout, double* __restrict__ dt_part, const MlpBlob* __restrict__ mlp,
-    double* __restrict__ un) {
+    double* __restrict__ Bout, double* __restrict__ dt_part, const MlpBlob* __restrict__ mlp) {
   const BlockTile bt = block_tile(L);
   const BlockInfo bi = L.blk[bt.blk];
   const int g = L.ph.ng;
@@ -594,7 +584,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   if (valid) {
     m = load_metric(L.geo.c, L.geo.ncol, col);
     double U[9];
-    conserve_cell<UN>(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, un, U, PS, fl);
+    conserve_cell(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, U, PS, fl);
     c2p_setup(U, m, L.ph.gam, cs);
   }
   bool first = false;
@@ -605,7 +595,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
 }
 
 // split update, first half: the conserved state of every cell into ubuf [9][cell]
-template <int UN>
 __global__ __launch_bounds__(NT) void k_conserve(Launch L, const double* __restrict__ Pn,
                                                  const double* __restrict__ Bn,
                                                  const double* __restrict__ Ps,
@@ -613,7 +602,6 @@ __global__ __launch_bounds__(NT) void k_conserve(Launch L, const double* __restr
                                                  const double* __restrict__ F,
                                                  const double* __restrict__ E, double dt_factor,
                                                  double* __restrict__ Bout,
-                                                 double* __restrict__ un,
                                                  double* __restrict__ ubuf) {
   const BlockTile bt = block_tile(L);
   const BlockInfo bi = L.blk[bt.blk];
@@ -623,7 +611,7 @@ __global__ __launch_bounds__(NT) void k_conserve(Launch L, const double* __restr
   const int64_t col = geo_col(L.geo, bi, c.J, c.I);
   const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
   double U[9], PS[5], fl[2];
-  conserve_cell<UN>(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, un, U, PS, fl);
+  conserve_cell(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, U, PS, fl);
   double* u = ubuf + 9 * bi.off + c.loc;
 #pragma unroll
   for (int q = 0; q < 9; q++) u[(int64_t)q * bi.vol] = U[q];
@@ -997,20 +985,15 @@ static void stats_final(const Launch& L, dim3 grid) {
 
 void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
                    const double* Bcs, const double* F, const double* E, double dt_factor,
-                   double* Pout, double* Bout, double* dt_part, const void* mlp, double* un,
-                   bool reuse_un, double* ubuf) {
+                   double* Pout, double* Bout, double* dt_part, const void* mlp, double* ubuf) {
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
   // with per-workgroup Courant partials the rectangular grid (the partials' layout)
   Launch Lc;
   const dim3 grid = stage_grid(L, dt_part ? -1 : WL_CELLS, r, Lc);
   const MlpBlob* blob = (const MlpBlob*)mlp;
   if (L.split_upd && ubuf) {
-    if (reuse_un)
-      hipLaunchKernelGGL((k_conserve<2>), grid, dim3(NT), 0, L.stream, Lc, Pn, Bn, Ps, Bcs, F, E,
-                         dt_factor, Bout, un, ubuf);
-    else
-      hipLaunchKernelGGL((k_conserve<1>), grid, dim3(NT), 0, L.stream, Lc, Pn, Bn, Ps, Bcs, F, E,
-                         dt_factor, Bout, un, ubuf);
+    hipLaunchKernelGGL(k_conserve, grid, dim3(NT), 0, L.stream, Lc, Pn, Bn, Ps, Bcs, F, E,
+                       dt_factor, Bout, ubuf);
 #define GRMHD_INV(ND, ML, V)                                                                   \
   hipLaunchKernelGGL((k_invert<true, ND, ML, UPD_OCC[V]>), grid, dim3(NT), 0, L.stream, Lc, Ps, \
                      ubuf, Pout, dt_part, blob)
@@ -1030,15 +1013,13 @@ void launch_update(const Launch& L, const double* Pn, const double* Bn, const do
     stats_final(L, grid);
     return;
   }
-#define GRMHD_UPD(ND, ML, V, U)                                                                 \
-  hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], U>), grid, dim3(NT), 0, L.stream, Lc, Pn, \
-                     Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob, un)
-#define GRMHD_UPD_U(ND, ML, V) \
-  if (reuse_un) GRMHD_UPD(ND, ML, V, 2); else GRMHD_UPD(ND, ML, V, 1)
+#define GRMHD_UPD(ND, ML, V)                                                                 \
+  hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V]>), grid, dim3(NT), 0, L.stream, Lc, Pn, \
+                     Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob)
 #define GRMHD_UPD_V(ND, ML)                                               \
   switch (L.var_upd) {                                                    \
-    case 0: GRMHD_UPD_U(ND, ML, 0); break;                                \
-    default: GRMHD_UPD_U(ND, ML, 1); break;                               \
+    case 0: GRMHD_UPD(ND, ML, 0); break;                                  \
+    default: GRMHD_UPD(ND, ML, 1); break;                                 \
   }
   if (dt_part && blob) {
     GRMHD_UPD_V(true, true);
@@ -1050,7 +1031,6 @@ void launch_update(const Launch& L, const double* Pn, const double* Bn, const do
     GRMHD_UPD_V(false, false);
   }
 #undef GRMHD_UPD_V
-#undef GRMHD_UPD_U
 #undef GRMHD_UPD
   stats_final(L, grid);
 }
