@@ -21,6 +21,32 @@ enum {
   NGEO_C
 };
 
+// Reciprocal and square roots from the hardware estimates (v_rcp_f64, v_rsq_f64)
+// refined by Newton-Raphson steps: r <- r + r (1 - b r) for 1/b, y <- y + y (1/2 - x y^2 / 2)
+// for 1/sqrt(x), and one Heron correction s <- s + (x - s^2) / (2 s) for sqrt(x).  A few
+// ulp from the correctly rounded values at about half the instructions of the IEEE
+// sequences; used where the result only feeds arithmetic (the face fluxes), with
+// arguments that are positive and finite there.
+__device__ __forceinline__ double rcp_nr(double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  r = fma(r, fma(-b, r, 1.0), r);
+  return fma(r, fma(-b, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  return fma(y, fma(-h * y, y, 0.5), y);
+}
+// sqrt(x) for x >= 0; 0 below 2^-1000 (where the estimate's range ends), an absolute
+// error under 1e-150
+__device__ __forceinline__ double sqrt_nr(double x) {
+  const double y = rsq_nr(x);
+  double s = x * y;
+  s = fma(0.5 * y, fma(-s, s, x), s);
+  return x > 0x1p-1000 ? s : 0.0;
+}
+
 struct Metric {
   double g00, g01, g03, g11, g13, g22, g33;
   double h00, h01, h11, h13, h22, h33;
@@ -64,19 +90,21 @@ struct Fluid {
 // four-velocity from the relative velocity utilde^i (Gamma = sqrt(1 + g_ij ut^i ut^j),
 // u^t = Gamma/alpha, u^i = ut^i - Gamma beta^i/alpha, beta^i = alpha^2 g^{ti}), and the
 // fluid-frame field b^t = B^i u_i, b^i = (B^i + b^t u^i)/u^t.
+// FAST: the square root and divisions through rsq_nr / rcp_nr.
+template <bool FAST = false>
 __device__ __forceinline__ void fluid_state(const double P[5], const double B[3], const Metric& m,
                                             Fluid& f) {
   const double u1 = P[2], u2 = P[3], u3 = P[4];
   const double qsq = m.g11 * u1 * u1 + 2.0 * m.g13 * u1 * u3 + m.g22 * u2 * u2 + m.g33 * u3 * u3;
-  const double gamma = sqrt(1.0 + qsq);
-  f.ucon[0] = gamma / m.alpha;
+  const double gamma = FAST ? sqrt_nr(1.0 + qsq) : sqrt(1.0 + qsq);
+  f.ucon[0] = FAST ? gamma * rcp_nr(m.alpha) : gamma / m.alpha;
   f.ucon[1] = u1 - gamma * (m.alpha * m.h01);   // beta^1/alpha = alpha g^{t1}
   f.ucon[2] = u2;
   f.ucon[3] = u3;
   lower4(m, f.ucon, f.ucov);
   const double bt = B[0] * f.ucov[1] + B[1] * f.ucov[2] + B[2] * f.ucov[3];
   f.bcon[0] = bt;
-  const double iut = 1.0 / f.ucon[0];
+  const double iut = FAST ? rcp_nr(f.ucon[0]) : 1.0 / f.ucon[0];
   f.bcon[1] = (B[0] + bt * f.ucon[1]) * iut;
   f.bcon[2] = (B[1] + bt * f.ucon[2]) * iut;
   f.bcon[3] = (B[2] + bt * f.ucon[3]) * iut;
@@ -88,9 +116,10 @@ __device__ __forceinline__ void fluid_state(const double P[5], const double B[3]
 // entropy tracer kappa = p / rho^gamma of a state (one power per state; for the
 // relativistic gamma = 4/3 the power is rho cbrt(rho), a cube root instead of a general
 // log/exp power)
+template <bool FAST = false>
 __device__ __forceinline__ double entropy_kappa(const double P[5], double gam) {
   const double rg = gam == 4.0 / 3.0 ? P[0] * cbrt(P[0]) : pow(P[0], gam);
-  return (gam - 1.0) * P[1] / rg;
+  return FAST ? (gam - 1.0) * P[1] * rcp_nr(rg) : (gam - 1.0) * P[1] / rg;
 }
 
 // Conserved vector (D = 0) or flux along x^D (D = 1..3), times sqrt(-g):
@@ -132,13 +161,13 @@ __device__ __forceinline__ void flux_vector(const double P[5], const Fluid& f, c
 
 // Fast-speed estimate along x^D: roots of A v^2 - B v + C = 0 from
 // (k.u)^2 = c_ms^2 (k.k + (k.u)^2), k = (-v, e_D), c_ms^2 = v_A^2 + c_s^2 (1 - v_A^2).
-template <int D>
+template <int D, bool FAST = false>
 __device__ __forceinline__ void wave_speeds(const double P[5], const Fluid& f, const Metric& m,
                                             double gam, double& vmax, double& vmin) {
   const double p = (gam - 1.0) * P[1];
   const double w = P[0] + P[1] + p;
   const double wb = f.bsq + w;
-  const double r = 1.0 / (w * wb);          // one division for both ratios
+  const double r = FAST ? rcp_nr(w * wb) : 1.0 / (w * wb);   // one division for both ratios
   const double cs2 = gam * p * wb * r;
   const double va2 = f.bsq * w * r;
   const double cms2 = va2 + cs2 * (1.0 - va2);
@@ -150,8 +179,8 @@ __device__ __forceinline__ void wave_speeds(const double P[5], const Fluid& f, c
   const double C = ud * ud * (1.0 - cms2) - cms2 * hdd;
   double disc = B * B - 4.0 * A * C;
   disc = disc < 0.0 ? 0.0 : disc;
-  const double sq = sqrt(disc);
-  const double i2a = 0.5 / A;
+  const double sq = FAST ? sqrt_nr(disc) : sqrt(disc);
+  const double i2a = FAST ? 0.5 * rcp_nr(A) : 0.5 / A;
   const double vp = (B + sq) * i2a, vm = (B - sq) * i2a;
   vmax = vp > vm ? vp : vm;
   vmin = vp > vm ? vm : vp;

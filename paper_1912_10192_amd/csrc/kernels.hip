@@ -203,7 +203,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     for (int v = 0; v < 5; v++) recon_face<RECON>(sp[v], PL[v], PR[v]);
     recon_face<RECON>(sb[0], BL[t1], BR[t1]);
     recon_face<RECON>(sb[1], BL[t2], BR[t2]);
-    const double bn = bface / m.gdet;
+    const double bn = bface * rcp_nr(m.gdet);
     BL[DIR - 1] = bn;
     BR[DIR - 1] = bn;
   }
@@ -212,19 +212,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   double vmaxL, vminL, vmaxR, vminR;
   {
     Fluid f;
-    fluid_state(PL, BL, m, f);
-    const double kap = entropy_kappa(PL, gam);
+    fluid_state<true>(PL, BL, m, f);
+    const double kap = entropy_kappa<true>(PL, gam);
     flux_vector<0>(PL, f, m, gam, kap, UL);
     flux_vector<DIR>(PL, f, m, gam, kap, FL);
-    wave_speeds<DIR>(PL, f, m, gam, vmaxL, vminL);
+    wave_speeds<DIR, true>(PL, f, m, gam, vmaxL, vminL);
   }
   {
     Fluid f;
-    fluid_state(PR, BR, m, f);
-    const double kap = entropy_kappa(PR, gam);
+    fluid_state<true>(PR, BR, m, f);
+    const double kap = entropy_kappa<true>(PR, gam);
     flux_vector<0>(PR, f, m, gam, kap, UR);
     flux_vector<DIR>(PR, f, m, gam, kap, FR);
-    wave_speeds<DIR>(PR, f, m, gam, vmaxR, vminR);
+    wave_speeds<DIR, true>(PR, f, m, gam, vmaxR, vminR);
   }
   // conserved components in flux order: mass, energy, momenta, transverse field, entropy
   constexpr int uidx[8] = {0, 1, 2, 3, 4, 5 + t1, 5 + t2, 8};
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     for (int q = 0; q < 8; q++) out[q * V] = 0.5 * (FL[q] + FR[q] - cc * (UR[uidx[q]] - UL[uidx[q]]));
   } else {
     if (cmax + cmin > 0.0) {
-      const double ic = 1.0 / (cmax + cmin);
+      const double ic = rcp_nr(cmax + cmin);
 #pragma unroll
       for (int q = 0; q < 8; q++)
         out[q * V] = (cmin * FR[q] + cmax * FL[q] - cmax * cmin * (UR[uidx[q]] - UL[uidx[q]])) * ic;
