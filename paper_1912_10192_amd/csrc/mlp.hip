@@ -7,8 +7,10 @@
 //   dW_l = H_{l-1}^T G_l, db_l = sum_rows G_l,
 //   G_{l-1} = (G_l W_l^T) * (1 - H_{l-1}^2)                       backward
 //   Adam on the FP32 master parameters.
-// Every product is one launch of k_gemm: 16x16 output tiles per wavefront, operands
-// rounded to bfloat16 on load, v_mfma_f32_16x16x16_bf16 over K.
+// Products over the features (forward, and the gradients passed down) are launches of
+// k_gemm: 16x16 output tiles per wavefront, operands rounded to bfloat16 on load,
+// v_mfma_f32_16x16x16_bf16 over K.  Products over the batch (the parameter gradients,
+// K = rows) split K across workgroups (k_wgrad) and add the chunks in order.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -117,14 +119,71 @@ __global__ __launch_bounds__(MT) void k_loss_final(const float* __restrict__ par
   if (threadIdx.x == 0) *loss = red[0] * scale;
 }
 
-// db[c] = sum_r G[r][c]  (one thread per column, fixed order)
-__global__ __launch_bounds__(MT) void k_colsum(const float* __restrict__ G, int rows, int cols,
-                                               float* __restrict__ db) {
-  const int c = blockIdx.x * MT + threadIdx.x;
-  if (c >= cols) return;
+// Parameter gradients reduce over the batch (K = rows, thousands) into at most 64 x 64
+// outputs: split K.  Workgroup c takes rows [c KC, (c + 1) KC) and writes its partial
+// dW = A^T G (A gathered through idx) as part[c][M][N] and, if db is wanted, its partial
+// column sums of G as part[c][M N + n]; k_wgrad_final adds the chunks in order.
+constexpr int KC = 256;
+__global__ __launch_bounds__(MT) void k_wgrad(int M, int N, int K, const float* __restrict__ A,
+                                              int lda, const int32_t* __restrict__ idx,
+                                              const float* __restrict__ G, int ldg, int colsum,
+                                              float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = lane & 15, grp = lane >> 4;
+  const int c = blockIdx.x;
+  const int k_lo = c * KC, k_hi = min(K, k_lo + KC);
+  const int tm = (M + 15) / 16, tn = (N + 15) / 16;
+  float* out = part + (int64_t)c * (M * N + (colsum ? N : 0));
+  // output tiles w, w + 4, ... of the tm x tn tile grid, 16 x 16 each
+  for (int tile = w; tile < tm * tn; tile += 4) {
+    const int m0 = (tile / tn) * 16, n0 = (tile % tn) * 16;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = k_lo; k0 < k_hi; k0 += 16) {
+      bf16x4 a, b;
+#pragma unroll
+      for (int j = 0; j < 4; j++) {
+        const int k = k0 + 4 * grp + j;
+        const int m = m0 + row, n = n0 + row;
+        float av = 0.f, bv = 0.f;
+        if (k < k_hi) {
+          if (m < M) av = A[(int64_t)(idx ? idx[k] : k) * lda + m];
+          if (n < N) bv = G[(int64_t)k * ldg + n];
+        }
+        a[j] = f2bf(av);
+        b[j] = f2bf(bv);
+      }
+      acc = mfma16(a, b, acc);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int m = m0 + 4 * grp + j, n = n0 + row;
+      if (m < M && n < N) out[m * N + n] = acc[j];
+    }
+  }
+  if (colsum) {
+    // column n = lane (N <= 64), rows k_lo + w, k_lo + w + 4, ... summed per wave
+    float s = 0.f;
+    if (lane < N)
+      for (int k = k_lo + w; k < k_hi; k += 4) s += G[(int64_t)k * ldg + lane];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && lane < N) out[M * N + lane] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+  }
+}
+
+// dW[m][n] (row stride ldw) and db[n] from the chunk partials, chunks in order
+__global__ __launch_bounds__(MT) void k_wgrad_final(int M, int N, int nchunk, int colsum,
+                                                    const float* __restrict__ part,
+                                                    float* __restrict__ dW, int ldw,
+                                                    float* __restrict__ db) {
+  const int i = blockIdx.x * MT + threadIdx.x;
+  const int per = M * N + (colsum ? N : 0);
+  if (i >= per) return;
   float s = 0.f;
-  for (int r = 0; r < rows; r++) s += G[(int64_t)r * cols + c];
-  db[c] = s;
+  for (int c = 0; c < nchunk; c++) s += part[(int64_t)c * per + i];
+  if (i < M * N) dW[(i / N) * ldw + i % N] = s;
+  else db[i - M * N] = s;
 }
 
 __global__ __launch_bounds__(MT) void k_adam(float* __restrict__ p, const float* __restrict__ g,
@@ -277,6 +336,18 @@ __global__ __launch_bounds__(MT) void k_normalize(float* __restrict__ A, int64_t
 
 static inline unsigned cdv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
+// dW (M x N, row stride ldw) = A^T G over the K rows (A gathered through idx), and db =
+// the column sums of G if db is non-null; part: workspace of wgrad_floats(K) floats
+static size_t wgrad_floats(int K) { return (size_t)cdv(K, KC) * (64 * 64 + 64); }
+static void wgrad(int M, int N, int K, const float* A, int lda, const int32_t* idx, const float* G,
+                  int ldg, float* dW, int ldw, float* db, float* part, hipStream_t st) {
+  const int nchunk = (int)cdv(K, KC), cs = db ? 1 : 0;
+  hipLaunchKernelGGL(k_wgrad, dim3(nchunk), dim3(MT), 0, st, M, N, K, A, lda, idx, G, ldg, cs,
+                     part);
+  hipLaunchKernelGGL(k_wgrad_final, dim3(cdv(M * N + N, MT)), dim3(MT), 0, st, M, N, nchunk, cs,
+                     part, dW, ldw, db);
+}
+
 static void gemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const int32_t* idx,
                  const float* B, int ldb, const float* bias, float* C, int ldc, hipStream_t st) {
   const dim3 grid(cdv(M, 16), cdv(N, 64));
@@ -304,7 +375,9 @@ int grmhd_mlp_sizes(int32_t batch, size_t* n_params, size_t* blob_bytes, size_t*
   if (blob_bytes) *blob_bytes = sizeof(MlpBlob);
   // activations H1..H3, Z4, G (two buffers), parameter gradients, loss partials
   const size_t b = (size_t)batch;
-  if (work_floats) *work_floats = 3 * b * 64 + b * 2 + 2 * b * 64 + MLP_NPARAM + cdv(b * 2, MT) + 64;
+  if (work_floats)
+    *work_floats = 3 * b * 64 + b * 2 + 2 * b * 64 + MLP_NPARAM + cdv(b * 2, MT) + 64 +
+                   wgrad_floats(batch);
   return GRMHD_OK;
 }
 
@@ -324,6 +397,7 @@ int grmhd_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t st
   float* Gb = Ga + (size_t)B * 64;
   float* grad = Gb + (size_t)B * 64;
   float* part = grad + MLP_NPARAM;
+  float* wpart = part + cdv((int64_t)B * 2, MT) + 64;
   const float* W1 = params + P_W1;
   const float* W2 = params + P_W2;
   const float* W3 = params + P_W3;
@@ -342,23 +416,19 @@ int grmhd_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t st
   hipLaunchKernelGGL(k_mse, dim3(np), dim3(MT), 0, st, Z4, Y, idx, B, 2, Ga, part);
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(MT), 0, st, part, (int)np, 1.0f / (float)(B * 2), loss);
   // backward: layer 4
-  gemm(true, false, 64, 2, B, H3, 64, nullptr, Ga, 2, nullptr, grad + P_W4, 2, st);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(MT), 0, st, Ga, B, 2, grad + P_B4);
+  wgrad(64, 2, B, H3, 64, nullptr, Ga, 2, grad + P_W4, 2, grad + P_B4, wpart, st);
   gemm(false, true, B, 64, 2, Ga, 2, nullptr, W4, 2, nullptr, Gb, 64, st);
   hipLaunchKernelGGL(k_tanh_back, dim3(cdv(nh, MT)), dim3(MT), 0, st, Gb, H3, nh);
   // layer 3
-  gemm(true, false, 64, 64, B, H2, 64, nullptr, Gb, 64, nullptr, grad + P_W3, 64, st);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(MT), 0, st, Gb, B, 64, grad + P_B3);
+  wgrad(64, 64, B, H2, 64, nullptr, Gb, 64, grad + P_W3, 64, grad + P_B3, wpart, st);
   gemm(false, true, B, 64, 64, Gb, 64, nullptr, W3, 64, nullptr, Ga, 64, st);
   hipLaunchKernelGGL(k_tanh_back, dim3(cdv(nh, MT)), dim3(MT), 0, st, Ga, H2, nh);
   // layer 2
-  gemm(true, false, 64, 64, B, H1, 64, nullptr, Ga, 64, nullptr, grad + P_W2, 64, st);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(MT), 0, st, Ga, B, 64, grad + P_B2);
+  wgrad(64, 64, B, H1, 64, nullptr, Ga, 64, grad + P_W2, 64, grad + P_B2, wpart, st);
   gemm(false, true, B, 64, 64, Ga, 64, nullptr, W2, 64, nullptr, Gb, 64, st);
   hipLaunchKernelGGL(k_tanh_back, dim3(cdv(nh, MT)), dim3(MT), 0, st, Gb, H1, nh);
   // layer 1 (inputs gathered through idx)
-  gemm(true, false, 8, 64, B, X, 8, idx, Gb, 64, nullptr, grad + P_W1, 64, st);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(MT), 0, st, Gb, B, 64, grad + P_B1);
+  wgrad(8, 64, B, X, 8, idx, Gb, 64, grad + P_W1, 64, grad + P_B1, wpart, st);
   // Adam
   const float b1t = (float)std::pow(0.9, step), b2t = (float)std::pow(0.999, step);
   hipLaunchKernelGGL(k_adam, dim3(cdv(MLP_NPARAM, MT)), dim3(MT), 0, st, params, grad, adam_m, adam_v,
@@ -382,6 +452,7 @@ int grmhd_mlp_gradients(const float* params, const float* X, const float* Y, con
   float* Ga = Z4 + (size_t)B * 2;
   float* Gb = Ga + (size_t)B * 64;
   float* part = Gb + (size_t)B * 64 + MLP_NPARAM;
+  float* wpart = part + cdv((int64_t)B * 2, MT) + 64;
   float* grad = grad_out;
   const float* W2 = params + P_W2;
   const float* W3 = params + P_W3;
@@ -397,20 +468,16 @@ int grmhd_mlp_gradients(const float* params, const float* X, const float* Y, con
   const unsigned np = cdv((int64_t)B * 2, MT);
   hipLaunchKernelGGL(k_mse, dim3(np), dim3(MT), 0, st, Z4, Y, idx, B, 2, Ga, part);
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(MT), 0, st, part, (int)np, 1.0f / (float)(B * 2), loss);
-  gemm(true, false, 64, 2, B, H3, 64, nullptr, Ga, 2, nullptr, grad + P_W4, 2, st);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(MT), 0, st, Ga, B, 2, grad + P_B4);
+  wgrad(64, 2, B, H3, 64, nullptr, Ga, 2, grad + P_W4, 2, grad + P_B4, wpart, st);
   gemm(false, true, B, 64, 2, Ga, 2, nullptr, W4, 2, nullptr, Gb, 64, st);
   hipLaunchKernelGGL(k_tanh_back, dim3(cdv(nh, MT)), dim3(MT), 0, st, Gb, H3, nh);
-  gemm(true, false, 64, 64, B, H2, 64, nullptr, Gb, 64, nullptr, grad + P_W3, 64, st);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(MT), 0, st, Gb, B, 64, grad + P_B3);
+  wgrad(64, 64, B, H2, 64, nullptr, Gb, 64, grad + P_W3, 64, grad + P_B3, wpart, st);
   gemm(false, true, B, 64, 64, Gb, 64, nullptr, W3, 64, nullptr, Ga, 64, st);
   hipLaunchKernelGGL(k_tanh_back, dim3(cdv(nh, MT)), dim3(MT), 0, st, Ga, H2, nh);
-  gemm(true, false, 64, 64, B, H1, 64, nullptr, Ga, 64, nullptr, grad + P_W2, 64, st);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(MT), 0, st, Ga, B, 64, grad + P_B2);
+  wgrad(64, 64, B, H1, 64, nullptr, Ga, 64, grad + P_W2, 64, grad + P_B2, wpart, st);
   gemm(false, true, B, 64, 64, Ga, 64, nullptr, W2, 64, nullptr, Gb, 64, st);
   hipLaunchKernelGGL(k_tanh_back, dim3(cdv(nh, MT)), dim3(MT), 0, st, Gb, H1, nh);
-  gemm(true, false, 8, 64, B, X, 8, idx, Gb, 64, nullptr, grad + P_W1, 64, st);
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(MT), 0, st, Gb, B, 64, grad + P_B1);
+  wgrad(8, 64, B, X, 8, idx, Gb, 64, grad + P_W1, 64, grad + P_B1, wpart, st);
   if (hipGetLastError() != hipSuccess) return mfail(GRMHD_EHIP, "kernel launch failed");
   return GRMHD_OK;
 }
