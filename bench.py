@@ -60,10 +60,14 @@ TRAFFIC_PER_LAUNCH = {
 
 
 def kernel_hash() -> str:
+    """hash of the sources the stage kernels are compiled from and of the compiler flags"""
+    from paper_1912_10192_amd import build
+
     h = hashlib.sha256()
-    for f in ("kernels.hip", "device.h", "internal.h"):
+    for f in ("kernels.hip", "device.h", "internal.h", "wave.h", "mlp.h"):
         with open(os.path.join(ROOT, "paper_1912_10192_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(build.FLAGS).encode())
     return h.hexdigest()[:16]
 
 

@@ -120,7 +120,8 @@ typedef struct {
   double t_sim;                     /* simulated time since init */
   double kernel_ms;                 /* device time of this call (HIP events) */
   /* with desc.profile: device time and launch count per kernel class, in the order
-   * ghost fill, cell field, x1 flux, x2 flux, x3 flux, EMF, cell update, Courant */
+   * ghost fill, cell field, x1 flux, x2 flux, x3 flux, EMF, cell update, Courant step and
+   * statistics reductions */
   double class_ms[8];
   int64_t class_launches[8];
 } grmhd_step_stats;

@@ -1174,7 +1174,11 @@ static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double
   launch_amr_fix(L, c->links, (int)c->plan.links.size(), c->plan.link_maxpos, c->f, c->e);
   prof_end(c);
   prof_begin(c, KC_UPDATE);
-  launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, dt_part, c->mlp, c->u9);
+  const int64_t nrec =
+      launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, dt_part, c->mlp, c->u9);
+  prof_end(c);
+  prof_begin(c, KC_DT);
+  launch_stats_final(L, nrec);
   prof_end(c);
   if (!c->plan.links.empty()) {
     prof_begin(c, KC_GHOST);
@@ -1233,7 +1237,11 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
     launch_amr_fix(L, c->links + lo, (int)nl, p.link_maxpos, c->f, c->e);
     prof_end(c);
     prof_begin(c, KC_UPDATE);
-    launch_update(L, P, B, Ps, c->bc, c->f, c->e, factor, Pout, c->balt, nullptr, c->mlp, c->u9);
+    const int64_t nrec =
+        launch_update(L, P, B, Ps, c->bc, c->f, c->e, factor, Pout, c->balt, nullptr, c->mlp, c->u9);
+    prof_end(c);
+    prof_begin(c, KC_DT);
+    launch_stats_final(L, nrec);
     prof_end(c);
     if (nl > 0) {
       prof_begin(c, KC_GHOST);

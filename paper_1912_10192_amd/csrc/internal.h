@@ -151,9 +151,12 @@ void launch_emf(const Launch& L, const double* F, double* E);
 // update of one stage; with dt_part non-null the kernel also writes per-workgroup minima
 // of the next Courant step (reduced by launch_dt_final)
 // (mlp non-null: learned first guess of the inversion from the packed MLP blob)
-void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
+// (returns the number of workgroups, whose statistics records launch_stats_final adds to
+// the counters)
+int64_t launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
                    const double* Bcs, const double* F, const double* E, double dt_factor,
                    double* Pout, double* Bout, double* dt_part, const void* mlp, double* ubuf);
+void launch_stats_final(const Launch& L, int64_t n);
 int64_t dt_partials(const Launch& L);
 void launch_dt(const Launch& L, const double* P, const double* B, double* dt_part);
 void launch_dt_final(const Launch& L, const double* dt_part);

@@ -538,7 +538,9 @@ __device__ __forceinline__ void update_epilogue(const Launch& L, const BlockTile
   }
 }
 
-// the sum over the n workgroup records of one launch, one workgroup per statistic
+// the sum over the n workgroup records of one launch: blockIdx.x is the statistic,
+// blockIdx.y one of gridDim.y interleaved shares of the records; one counter add per
+// workgroup with a nonzero share
 __global__ __launch_bounds__(NT) void k_stats_final(Counters* __restrict__ cnt,
                                                     const uint32_t* __restrict__ part,
                                                     int64_t stride, int64_t n) {
@@ -546,7 +548,8 @@ __global__ __launch_bounds__(NT) void k_stats_final(Counters* __restrict__ cnt,
   const int q = blockIdx.x;
   const uint32_t* p = part + (int64_t)q * stride;
   long long s = 0;
-  for (int64_t i = threadIdx.x; i < n; i += NT) s += p[i];
+  for (int64_t i = (int64_t)blockIdx.y * NT + threadIdx.x; i < n; i += (int64_t)NT * gridDim.y)
+    s += p[i];
   s = wave_sum(s);
   if (lane_id() == 0) red[threadIdx.x / 64] = s;
   __syncthreads();
@@ -977,13 +980,12 @@ int64_t dt_partials(const Launch& L) {
   return (int64_t)cdiv(r, NT) * L.nblk;
 }
 
-// the statistics records of an update launch on `grid` added to the counters
-static void stats_final(const Launch& L, dim3 grid) {
-  hipLaunchKernelGGL(k_stats_final, dim3(NSTAT), dim3(NT), 0, L.stream, L.cnt, L.stat_part,
-                     L.stat_stride, (int64_t)grid.x * grid.y);
+void launch_stats_final(const Launch& L, int64_t n) {
+  hipLaunchKernelGGL(k_stats_final, dim3(NSTAT, 16), dim3(NT), 0, L.stream, L.cnt, L.stat_part,
+                     L.stat_stride, n);
 }
 
-void launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
+int64_t launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
                    const double* Bcs, const double* F, const double* E, double dt_factor,
                    double* Pout, double* Bout, double* dt_part, const void* mlp, double* ubuf) {
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
@@ -1010,8 +1012,7 @@ void launch_update(const Launch& L, const double* Pn, const double* Bn, const do
     }
 #undef GRMHD_INV_V
 #undef GRMHD_INV
-    stats_final(L, grid);
-    return;
+    return (int64_t)grid.x * grid.y;
   }
 #define GRMHD_UPD(ND, ML, V)                                                                 \
   hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V]>), grid, dim3(NT), 0, L.stream, Lc, Pn, \
@@ -1032,7 +1033,7 @@ void launch_update(const Launch& L, const double* Pn, const double* Bn, const do
   }
 #undef GRMHD_UPD_V
 #undef GRMHD_UPD
-  stats_final(L, grid);
+  return (int64_t)grid.x * grid.y;
 }
 
 void launch_dt(const Launch& L, const double* P, const double* B, double* dt_part) {
