@@ -79,14 +79,30 @@ __global__ __launch_bounds__(LT) void k_ghost_faces_t(const BlockInfo* __restric
   dst[3 * d.off + (int64_t)comp * d.vol + op.dst_loc] = x;
 }
 
-// copy nvar variables of every listed block (interior and ghosts)
+// Copy the interior of every listed block: nvar = 5 primitives of the interior cells, or
+// nvar = 3 face components, each on and inside the block's boundary (normal index ng to
+// ng + n).  Ghost values are not copied: every reader of the copies (the ghost lists)
+// takes interior values only, and every ghost is refilled before the stage that uses it.
 __global__ __launch_bounds__(LT) void k_copy_blocks(Launch L, const double* __restrict__ src,
                                                     double* __restrict__ dst, int nvar) {
   const BlockInfo bi = list_block(L, blockIdx.y);
-  const int64_t n = (int64_t)nvar * bi.vol;
+  const int g = L.ph.ng;
+  const int64_t V = bi.vol;
   const int64_t base = (int64_t)nvar * bi.off;
-  for (int64_t i = (int64_t)blockIdx.x * LT + threadIdx.x; i < n; i += (int64_t)gridDim.x * LT)
-    dst[base + i] = src[base + i];
+  const bool faces = nvar == 3;
+  for (int v = 0; v < nvar; v++) {
+    const int r0 = bi.n[0] + (faces && v == 0 ? 1 : 0);
+    const int r1 = bi.n[1] + (faces && v == 1 ? 1 : 0);
+    const int r2 = bi.n[2] + (faces && v == 2 ? 1 : 0);
+    const int64_t n = (int64_t)r0 * r1 * r2;
+    for (int64_t t = (int64_t)blockIdx.x * LT + threadIdx.x; t < n; t += (int64_t)gridDim.x * LT) {
+      const int i = (int)(t % r0);
+      const int64_t q = t / r0;
+      const int j = (int)(q % r1), k = (int)(q / r1);
+      const int64_t l = ((int64_t)(k + g) * bi.np[1] + (j + g)) * bi.np[0] + (i + g);
+      dst[base + v * V + l] = src[base + v * V + l];
+    }
+  }
 }
 
 // ------------------------------------------------------------------ registers
@@ -298,7 +314,7 @@ void launch_ghost_faces_t(const Launch& L, const GhostOp* ops, int64_t nops, con
 }
 
 void launch_copy_blocks(const Launch& L, const double* src, double* dst, int nvar) {
-  const int64_t r = (int64_t)nvar * L.max_np[0] * L.max_np[1] * L.max_np[2];
+  const int64_t r = (int64_t)(L.max_n[0] + 1) * (L.max_n[1] + 1) * (L.max_n[2] + 1);
   const unsigned gx = std::min<unsigned>(cdv(r, LT), 256);
   hipLaunchKernelGGL(k_copy_blocks, dim3(gx, L.nblk), dim3(LT), 0, L.stream, L, src, dst, nvar);
 }

@@ -38,6 +38,20 @@ class Replay:
             N = [cfg["n"][d] >> (lmax[d] - bd.lev[d]) for d in range(3)]
             self.dx.append([(cfg["xhi"][d] - cfg["xlo"][d]) / N[d] for d in range(3)])
         self._gd = {}
+        self.outside = []   # sources read outside their block's interior (see interior())
+
+    def interior(self, b, loc, comp):
+        """whether local index loc of block b is an interior cell (comp None) or a face of
+        component comp on or inside the block's boundary (normal index g .. g + n)"""
+        n1p, n2p, _ = self.lay[b][1]
+        idx = (loc % n1p, (loc // n1p) % n2p, loc // (n1p * n2p))
+        g = self.cfg["ng"]
+        n = self.desc.blocks[b].n
+        return all(g <= idx[d] < g + n[d] + (1 if comp == d else 0) for d in range(3))
+
+    def _src(self, b, loc, comp):
+        if not self.interior(b, loc, comp):
+            self.outside.append((b, loc, comp))
 
     def vol(self, b):
         n = self.lay[b][1]
@@ -65,6 +79,7 @@ class Replay:
         V = n1p * n2p * n3p
         if mask == 0:
             assert 0 <= loc < V
+            self._src(b, loc, None)
             x = prim[5 * off + v * V + loc]
         else:
             num = den = 0.0
@@ -73,6 +88,7 @@ class Replay:
                     for oi in range(2 if mask & 1 else 1):
                         l = loc + (ok * n2p + oj) * n1p + oi
                         assert 0 <= l < V
+                        self._src(b, l, None)
                         w = self.gdet(b, l)
                         num = num + w * prim[5 * off + v * V + l]
                         den = den + w
@@ -94,6 +110,7 @@ class Replay:
         V = n1p * n2p * n3p
         if mask == 0:
             assert 0 <= loc < V
+            self._src(b, loc, comp)
             x = bface[3 * off + comp * V + loc]
         else:
             acc = 0.0
@@ -103,6 +120,7 @@ class Replay:
                     for oi in range(2 if mask & 1 else 1):
                         l = loc + (ok * n2p + oj) * n1p + oi
                         assert 0 <= l < V
+                        self._src(b, l, comp)
                         acc = acc + bface[3 * off + comp * V + l]
                         cnt += 1
             x = acc * (1.0 / cnt)
@@ -119,6 +137,8 @@ class Replay:
                 soff, _ = self.lay[sb]
                 Vd, Vs = self.vol(dst_b), self.vol(sb)
                 assert 0 <= dst_loc < Vd and 0 <= src_loc < Vs
+                if not (fl & GF_ZERO):
+                    self._src(sb, src_loc, None if kind == 0 else kind - 1)
                 if kind == 0:
                     for v in range(5):
                         x = prim[5 * soff + v * Vs + src_loc]

@@ -133,3 +133,27 @@ def test_refinement_faces_match_oracle_and_stay_in_bounds(case):
             # the fine children lie in the fine block's interior faces / edges
             for x in (a0, a1):
                 assert g <= pf[x] <= g + blocks[f]["n"][x]
+
+
+@pytest.mark.parametrize("case", [c[0] for c in cases()] + ["ks-lat-uniform", "mink-periodic"])
+def test_ghost_sources_are_interior_values(case):
+    """Every ghost list reads interior values only: cells of the source block's interior
+    and faces on or inside its boundary (plain copies, prolongation stencils and
+    restriction samples).  The time-stepping copies of the old state (which the
+    time-interpolated ghosts read) therefore cover the interior only."""
+    if case == "ks-lat-uniform":
+        cfg = configs.scaled(configs.TORUS_UNIFORM, (32, 16, 16), block=(8, 8, 8))
+        blocks = grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=[0, 1, 2, 2])
+    elif case == "mink-periodic":
+        cfg = dict(mink_cfg((12, 8, 8), recon=1, riemann=1), block=(4, 4, 4))
+        blocks = None
+    else:
+        _, cfg, blocks = [c for c in cases() if c[0] == case][0]
+    desc = grmhd.Desc(cfg, blocks=blocks)
+    nb = desc.d.n_blocks
+    sizes = [desc.layout(b) for b in range(nb)]
+    prim = np.zeros(5 * sum(int(np.prod(s[1])) for s in sizes))
+    bface = np.zeros(3 * sum(int(np.prod(s[1])) for s in sizes))
+    rp = Replay(desc, cfg)
+    rp.fill(prim, bface)
+    assert rp.outside == []
