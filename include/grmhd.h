@@ -129,7 +129,10 @@ typedef struct {
 typedef struct grmhd_ctx grmhd_ctx;
 
 /* Sizes the caller must allocate for desc: prim and bface element counts (doubles)
- * and the work buffer in bytes.  Returns GRMHD_EINVAL for an invalid desc. */
+ * and the work buffer in bytes.  Returns GRMHD_EINVAL for an invalid desc, and for
+ * grids whose packed arrays the ghost lists cannot index in 32 bits (a block's padded
+ * volume (n + 2 n_ghost + 1)^3 of 2^24 cells or more, or 5 x all padded cells of 2^32
+ * or more: about 8.6e8 padded cells, 34 GB per primitive array set). */
 int grmhd_sizes(const grmhd_grid_desc* desc, size_t* prim_elems, size_t* bface_elems,
                 size_t* work_bytes);
 

@@ -684,6 +684,8 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
     bi.gorg[0] = (int32_t)bd.org[0];
     bi.gorg[1] = (int32_t)bd.org[1];
     bi.gorg[2] = (int32_t)bd.org[2];
+    if ((int64_t)bi.np[0] * bi.np[1] * bi.np[2] >= (int64_t(1) << 24))
+      return fail(GRMHD_EINVAL, "block too large (padded volume must stay below 2^24 cells)");
     bi.vol = bi.np[0] * bi.np[1] * bi.np[2];
     bi.lat = bd.lat;
     bi.gti = p.tables[t].ti;
@@ -692,7 +694,8 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
     p.n_interior += (int64_t)bd.n[0] * bd.n[1] * bd.n[2];
   }
   p.vtot = off;
-  if (p.vtot * 5 >= (int64_t(1) << 31) * 4) return fail(GRMHD_EINVAL, "grid too large");
+  if (p.vtot * 5 >= (int64_t(1) << 32))
+    return fail(GRMHD_EINVAL, "grid too large (5 x padded cells must stay below 2^32)");
   // ownership of effective cells; every cell must be covered exactly once
   const int64_t N1 = desc->n_eff[0], N2 = desc->n_eff[1], N3 = desc->n_eff[2];
   if (N1 * N2 * N3 > (int64_t(1) << 31)) return fail(GRMHD_EINVAL, "effective grid too large");
@@ -955,7 +958,7 @@ struct grmhd_ctx {
   grmhd_buffers bufs;
   hipStream_t stream;
   double *ps, *balt, *bc, *f, *e, *dtp, *u9;
-  GhostOp* ops[4];
+  GhostIdx* ops[4];
   int64_t nops[4];
   AmrOp* aops[4];
   int64_t naops[4];
@@ -1062,12 +1065,28 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
     delete c;
     return rc;
   }
+  // the ghost lists resolved against the block table (element indices of the packed
+  // arrays); host staging kept until the stream synchronises below
+  std::vector<GhostIdx> gidx[4];
   for (int kind = 0; kind < 4; kind++) {
-    c->ops[kind] = (GhostOp*)(w + p.o_ops[kind]);
+    c->ops[kind] = (GhostIdx*)(w + p.o_ops[kind]);
     c->nops[kind] = (int64_t)p.ops[kind].size();
     c->aops[kind] = (AmrOp*)(w + p.o_aops[kind]);
     c->naops[kind] = (int64_t)p.aops[kind].size();
-    if ((rc = up(p.o_ops[kind], p.ops[kind].data(), p.ops[kind].size() * sizeof(GhostOp))) ||
+    std::vector<GhostIdx>& idx = gidx[kind];
+    idx.resize(p.ops[kind].size());
+    for (size_t i = 0; i < idx.size(); i++) {
+      const GhostOp& op = p.ops[kind][i];
+      const BlockInfo& d = p.info[op.dst_blk];
+      const BlockInfo& s = p.info[op.src_blkf & 0xFFFFFF];
+      const int64_t nv = kind == 0 ? 5 : 3, cv = kind == 0 ? 0 : kind - 1;
+      idx[i].dst = (uint32_t)(nv * d.off + cv * d.vol + op.dst_loc);
+      idx[i].src = (uint32_t)(nv * s.off + cv * s.vol + op.src_loc);
+      idx[i].dvol = (uint32_t)d.vol;
+      idx[i].svol_fl = (uint32_t)s.vol | ((uint32_t)(op.src_blkf >> 24) & 0xFFu) << 24;
+    }
+    static_assert(sizeof(GhostIdx) == sizeof(GhostOp), "ghost list layouts share their size");
+    if ((rc = up(p.o_ops[kind], idx.data(), idx.size() * sizeof(GhostIdx))) ||
         (rc = up(p.o_aops[kind], p.aops[kind].data(), p.aops[kind].size() * sizeof(AmrOp)))) {
       delete c;
       return rc;

@@ -27,6 +27,13 @@ struct GhostOp {
 };
 enum { GF_FLIP = 1, GF_CLAMP_NEG = 2, GF_CLAMP_POS = 4, GF_ZERO = 8, GF_SLOW = 16, GF_FAST = 32 };
 
+// A ghost copy as the kernels run it, resolved against the block table: element indices
+// into the packed arrays (cells: variable 0 of P, then strides dvol / svol per variable;
+// faces: the element of the list's component), svol_fl = source volume | flags << 24.
+struct GhostIdx {
+  uint32_t dst, src, dvol, svol_fl;
+};
+
 // A ghost value that involves another refinement level: a restriction of a finer
 // neighbour or a prolongation from a coarser one.  Samples are interior values of other
 // blocks (or of the block itself) at the source's own level; the op combines them.
@@ -142,8 +149,8 @@ struct Launch {
 int set_error(int code, const char* msg);
 
 // kernel launchers (kernels.hip)
-void launch_ghost_cells(const Launch& L, const GhostOp* ops, int64_t nops, double* P);
-void launch_ghost_faces(const Launch& L, const GhostOp* ops, int64_t nops, double* B, int comp);
+void launch_ghost_cells(const Launch& L, const GhostIdx* ops, int64_t nops, double* P);
+void launch_ghost_faces(const Launch& L, const GhostIdx* ops, int64_t nops, double* B, int comp);
 void launch_bcell(const Launch& L, const double* B, double* Bc);
 void launch_flux(const Launch& L, int dir, int recon, int riemann, const double* P,
                  const double* Bc, const double* B, double* F);
@@ -179,9 +186,9 @@ void launch_amr_fix(const Launch& L, const AmrLink* links, int nlinks, int maxpo
                     double* E);
 void launch_amr_bsync(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* B);
 // local time stepping (lat.hip)
-void launch_ghost_cells_t(const Launch& L, const GhostOp* ops, int64_t nops, const double* main,
+void launch_ghost_cells_t(const Launch& L, const GhostIdx* ops, int64_t nops, const double* main,
                           const double* old, const double* cur, double w, double* dst);
-void launch_ghost_faces_t(const Launch& L, const GhostOp* ops, int64_t nops, const double* main,
+void launch_ghost_faces_t(const Launch& L, const GhostIdx* ops, int64_t nops, const double* main,
                           const double* old, const double* cur, double w, double* dst, int comp);
 void launch_copy_blocks(const Launch& L, const double* src, double* dst, int nvar);
 void launch_registers(const Launch& L, const double* F, const double* E, double dt_factor,

@@ -92,38 +92,35 @@ __device__ __forceinline__ bool region_cell(const BlockInfo& bi, int t, int r0, 
 
 // ------------------------------------------------------------------ ghost gather
 
-__global__ __launch_bounds__(NT) void k_ghost_cells(const BlockInfo* __restrict__ blk,
-                                                    const GhostOp* __restrict__ ops, int64_t nops,
+__global__ __launch_bounds__(NT) void k_ghost_cells(const GhostIdx* __restrict__ ops, int64_t nops,
                                                     double* __restrict__ P) {
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (i >= nops) return;
-  const GhostOp op = ops[i];
-  const int sb = op.src_blkf & 0xFFFFFF, fl = (op.src_blkf >> 24) & 0xFF;
-  const BlockInfo d = blk[op.dst_blk], s = blk[sb];
-  const double* src = P + 5 * s.off + op.src_loc;
-  double* dst = P + 5 * d.off + op.dst_loc;
+  const GhostIdx op = ops[i];
+  const int fl = op.svol_fl >> 24;
+  const int64_t svol = op.svol_fl & 0xFFFFFF;
+  const double* src = P + op.src;
+  double* dst = P + op.dst;
 #pragma unroll
   for (int v = 0; v < 5; v++) {
-    double x = src[(int64_t)v * s.vol];
+    double x = src[v * svol];
     if (v == 3 && (fl & GF_FLIP)) x = -x;
     if (v == 2 && (fl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
     if (v == 2 && (fl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
-    dst[(int64_t)v * d.vol] = x;
+    dst[v * (int64_t)op.dvol] = x;
   }
 }
 
-__global__ __launch_bounds__(NT) void k_ghost_faces(const BlockInfo* __restrict__ blk,
-                                                    const GhostOp* __restrict__ ops, int64_t nops,
-                                                    double* __restrict__ B, int comp) {
+__global__ __launch_bounds__(NT) void k_ghost_faces(const GhostIdx* __restrict__ ops, int64_t nops,
+                                                    double* __restrict__ B) {
   const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (i >= nops) return;
-  const GhostOp op = ops[i];
-  const int sb = op.src_blkf & 0xFFFFFF, fl = (op.src_blkf >> 24) & 0xFF;
-  const BlockInfo d = blk[op.dst_blk], s = blk[sb];
-  double x = B[3 * s.off + (int64_t)comp * s.vol + op.src_loc];
+  const GhostIdx op = ops[i];
+  const int fl = op.svol_fl >> 24;
+  double x = B[op.src];
   if (fl & GF_ZERO) x = 0.0;
   else if (fl & GF_FLIP) x = -x;
-  B[3 * d.off + (int64_t)comp * d.vol + op.dst_loc] = x;
+  B[op.dst] = x;
 }
 
 // --------------------------------------------------------- cell-centred field
@@ -900,15 +897,15 @@ __global__ __launch_bounds__(NT) void k_c2p_batch_mlp(int64_t n, const double* _
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-void launch_ghost_cells(const Launch& L, const GhostOp* ops, int64_t nops, double* P) {
+void launch_ghost_cells(const Launch& L, const GhostIdx* ops, int64_t nops, double* P) {
   if (nops == 0) return;
-  hipLaunchKernelGGL(k_ghost_cells, dim3(cdiv(nops, NT)), dim3(NT), 0, L.stream, L.blk, ops, nops, P);
+  hipLaunchKernelGGL(k_ghost_cells, dim3(cdiv(nops, NT)), dim3(NT), 0, L.stream, ops, nops, P);
 }
 
-void launch_ghost_faces(const Launch& L, const GhostOp* ops, int64_t nops, double* B, int comp) {
+void launch_ghost_faces(const Launch& L, const GhostIdx* ops, int64_t nops, double* B, int comp) {
   if (nops == 0) return;
-  hipLaunchKernelGGL(k_ghost_faces, dim3(cdiv(nops, NT)), dim3(NT), 0, L.stream, L.blk, ops, nops,
-                     B, comp);
+  (void)comp;   // the list's element indices hold the component
+  hipLaunchKernelGGL(k_ghost_faces, dim3(cdiv(nops, NT)), dim3(NT), 0, L.stream, ops, nops, B);
 }
 
 // The grid of a stage kernel over region class cls (r: cells of the largest block's

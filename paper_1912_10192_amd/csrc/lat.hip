@@ -31,22 +31,20 @@ __device__ __forceinline__ BlockInfo list_block(const Launch& L, int y) {
 //   slower:     old + w (main - old)
 //   faster:     main
 // Physical-boundary flips and clamps apply afterwards.
-__global__ __launch_bounds__(LT) void k_ghost_cells_t(const BlockInfo* __restrict__ blk,
-                                                      const GhostOp* __restrict__ ops, int64_t nops,
-                                                      const double* __restrict__ main,
+__global__ __launch_bounds__(LT) void k_ghost_cells_t(const GhostIdx* __restrict__ ops,
+                                                      int64_t nops, const double* __restrict__ main,
                                                       const double* __restrict__ old,
                                                       const double* __restrict__ cur, double w,
                                                       double* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * LT + threadIdx.x;
   if (i >= nops) return;
-  const GhostOp op = ops[i];
-  const int sb = op.src_blkf & 0xFFFFFF, fl = (op.src_blkf >> 24) & 0xFF;
-  const BlockInfo d = blk[op.dst_blk], s = blk[sb];
-  const int64_t so = 5 * s.off + op.src_loc;
-  double* out = dst + 5 * d.off + op.dst_loc;
+  const GhostIdx op = ops[i];
+  const int fl = op.svol_fl >> 24;
+  const int64_t svol = op.svol_fl & 0xFFFFFF;
+  double* out = dst + op.dst;
 #pragma unroll
   for (int v = 0; v < 5; v++) {
-    const int64_t q = so + (int64_t)v * s.vol;
+    const int64_t q = op.src + v * svol;
     double x;
     if (fl & GF_SLOW) x = old[q] + w * (main[q] - old[q]);
     else if (fl & GF_FAST) x = main[q];
@@ -54,29 +52,27 @@ __global__ __launch_bounds__(LT) void k_ghost_cells_t(const BlockInfo* __restric
     if (v == 3 && (fl & GF_FLIP)) x = -x;
     if (v == 2 && (fl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
     if (v == 2 && (fl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
-    out[(int64_t)v * d.vol] = x;
+    out[v * (int64_t)op.dvol] = x;
   }
 }
 
-__global__ __launch_bounds__(LT) void k_ghost_faces_t(const BlockInfo* __restrict__ blk,
-                                                      const GhostOp* __restrict__ ops, int64_t nops,
-                                                      const double* __restrict__ main,
+__global__ __launch_bounds__(LT) void k_ghost_faces_t(const GhostIdx* __restrict__ ops,
+                                                      int64_t nops, const double* __restrict__ main,
                                                       const double* __restrict__ old,
                                                       const double* __restrict__ cur, double w,
-                                                      double* __restrict__ dst, int comp) {
+                                                      double* __restrict__ dst) {
   const int64_t i = (int64_t)blockIdx.x * LT + threadIdx.x;
   if (i >= nops) return;
-  const GhostOp op = ops[i];
-  const int sb = op.src_blkf & 0xFFFFFF, fl = (op.src_blkf >> 24) & 0xFF;
-  const BlockInfo d = blk[op.dst_blk], s = blk[sb];
-  const int64_t q = 3 * s.off + (int64_t)comp * s.vol + op.src_loc;
+  const GhostIdx op = ops[i];
+  const int fl = op.svol_fl >> 24;
+  const int64_t q = op.src;
   double x;
   if (fl & GF_SLOW) x = old[q] + w * (main[q] - old[q]);
   else if (fl & GF_FAST) x = main[q];
   else x = cur[q];
   if (fl & GF_ZERO) x = 0.0;
   else if (fl & GF_FLIP) x = -x;
-  dst[3 * d.off + (int64_t)comp * d.vol + op.dst_loc] = x;
+  dst[op.dst] = x;
 }
 
 // Copy the interior of every listed block: nvar = 5 primitives of the interior cells, or
@@ -299,18 +295,19 @@ __global__ void k_tsim_cycle(Counters* cnt, double courant, double substeps) {
 
 static inline unsigned cdv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-void launch_ghost_cells_t(const Launch& L, const GhostOp* ops, int64_t nops, const double* main,
+void launch_ghost_cells_t(const Launch& L, const GhostIdx* ops, int64_t nops, const double* main,
                           const double* old, const double* cur, double w, double* dst) {
   if (nops == 0) return;
-  hipLaunchKernelGGL(k_ghost_cells_t, dim3(cdv(nops, LT)), dim3(LT), 0, L.stream, L.blk, ops, nops,
-                     main, old, cur, w, dst);
+  hipLaunchKernelGGL(k_ghost_cells_t, dim3(cdv(nops, LT)), dim3(LT), 0, L.stream, ops, nops, main,
+                     old, cur, w, dst);
 }
 
-void launch_ghost_faces_t(const Launch& L, const GhostOp* ops, int64_t nops, const double* main,
+void launch_ghost_faces_t(const Launch& L, const GhostIdx* ops, int64_t nops, const double* main,
                           const double* old, const double* cur, double w, double* dst, int comp) {
   if (nops == 0) return;
-  hipLaunchKernelGGL(k_ghost_faces_t, dim3(cdv(nops, LT)), dim3(LT), 0, L.stream, L.blk, ops, nops,
-                     main, old, cur, w, dst, comp);
+  (void)comp;   // the list's element indices hold the component
+  hipLaunchKernelGGL(k_ghost_faces_t, dim3(cdv(nops, LT)), dim3(LT), 0, L.stream, ops, nops, main,
+                     old, cur, w, dst);
 }
 
 void launch_copy_blocks(const Launch& L, const double* src, double* dst, int nvar) {
