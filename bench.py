@@ -46,15 +46,15 @@ BYTES_PER_UNIT = {
     "emf": 8 * (6 + 3), "bcell": 8 * (3 + 3), "dt": 8 * (5 + 3), "ghost": 8 * 2 * 8,
 }
 FLOPS_PER_UNIT = {
-    "update": 1569.1, "flux1": 1292.0, "flux2": 1242.6, "flux3": 1239.4, "emf": 9.8,
+    "update": 1592.0, "flux1": 989.2, "flux2": 944.6, "flux3": 894.9, "emf": 9.8,
     "bcell": 86.2, "dt": 330.0,
 }
-KERNEL_HASH = "7fccaf1770ab98f0"
+KERNEL_HASH = "42d7f2a203de6d29"
 # HBM traffic per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by the reading of
 # the same counters for a 1 GiB device copy: fetch x2, write x1), keyed like
 # FLOPS_PER_UNIT and valid for KERNEL_HASH only.
 TRAFFIC_PER_LAUNCH = {
-    "update": 1.858e9, "flux1": 7.285e8, "flux2": 7.575e8, "flux3": 7.645e8, "emf": 3.782e8,
+    "update": 1.853e9, "flux1": 7.286e8, "flux2": 7.584e8, "flux3": 7.641e8, "emf": 3.782e8,
     "bcell": 3.629e8,
 }
 
