@@ -91,7 +91,7 @@ typedef struct {
                                  Newton from whichever of the two has the smaller residual
                                  misfit, then from the other).  Inside the update the
                                  network runs for a group of 256 cells only if the plain
-                                 guess of one of them has a residual misfit above 1e-2;
+                                 guess of one of them has a residual misfit above 1e-1;
                                  the other groups start from the plain guess */
   int32_t c2p_maxit;          /* Newton iteration cap (50) */
   double c2p_tol;             /* Newton tolerance (1e-12) */

@@ -332,10 +332,11 @@ __device__ __forceinline__ bool mlp_guess_block(const MlpBlob* __restrict__ blob
 
 // The learned guess where it can pay: the network runs for a workgroup only if the plain
 // guess (the stage primitives) of some cell in it leaves a residual misfit (c2p_misfit)
-// above MLP_GATE.  Below that the plain guess is within a few Newton iterations of the
-// root, as close as the network's guess gets, and the inference would cost more than it
-// saves; large misfits come with cold starts, floors and strong jumps.
-constexpr double MLP_GATE = 1e-2;
+// above MLP_GATE.  The network's guesses are typically within about 10% of the root
+// (Newton from them needs about 4.6 iterations to 1e-12 on the benchmark torus's cells);
+// a plain guess with a smaller misfit is the better start, and the inference would cost
+// more than it saves.  Large misfits come with cold starts, floors and strong jumps.
+constexpr double MLP_GATE = 1e-1;
 __device__ __forceinline__ bool learned_guess(const MlpBlob* __restrict__ blob, const C2PIn& s,
                                               const Metric& m, bool valid, const double PS[5],
                                               double& W0, double& v0) {

@@ -139,6 +139,35 @@ def test_learned_guess_keeps_the_evolution():
     assert sm.c2p_tier[4] == 0
 
 
+def test_learned_guess_runs_where_the_plain_guess_is_poor():
+    """The in-loop gate: with a strongly perturbed initial state (50% pressure noise,
+    velocity kicks) some workgroups' plain guesses are poor, the network runs there
+    (mlp_guesses > 0), and the evolution still matches the plain-guess run to the parity
+    bar, with no more fallbacks or failed inversions than the plain-guess run."""
+    cfg = configs.scaled(configs.TORUS_UNIFORM, (64, 32, 32), block=(32, 32, 32))
+    init = dict(configs.TORUS_INIT, amp=0.5)
+    state = initdata.torus_state(cfg["n"], **init)
+    rng = np.random.default_rng(11)
+    P = state[0].copy()
+    P[2:5] += 0.1 * rng.standard_normal(P[2:5].shape) * (P[0] > 1e-2)
+    state = (P, *state[1:])
+    blob, _ = _trained_blob(cfg, state, steps=300)
+    gp = grmhd.Grid(cfg, state=state)
+    gm = grmhd.Grid(cfg, state=state, mlp_blob=blob)
+    sp = gp.step(2)
+    sm = gm.step(2)
+    say(f"[mlp] gated learned starts {sm.mlp_guesses} of {sum(sm.c2p_tier)} inversions; "
+        f"tiers plain {list(sp.c2p_tier)} learned {list(sm.c2p_tier)}")
+    assert sm.mlp_guesses > 0 and sp.mlp_guesses == 0
+    assert sum(sm.c2p_tier[2:]) <= sum(sp.c2p_tier[2:]) and sm.c2p_tier[4] <= sp.c2p_tier[4]
+    a = gp.get_state()
+    b = gm.get_state()
+    assert np.max(np.abs(a[0][0] - b[0][0]) / a[0][0]) < 1e-11
+    assert np.max(np.abs(a[0][1] - b[0][1]) / (a[0][0] + a[0][1])) < 1e-11
+    for v in (2, 3, 4):
+        assert np.abs(a[0][v] - b[0][v]).max() <= 1e-11 * np.abs(a[0][v]).max()
+
+
 def test_learned_guess_gain_over_a_cold_start():
     """What the network adds where no previous state exists (a standalone inversion of
     conserved states): Newton from the learned guess against Newton from a generic
