@@ -11,9 +11,6 @@ SOURCES = [os.path.join(HERE, "csrc", f) for f in ("kernels.hip", "lat.hip", "am
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # packed FP32 instructions stay off (plain scalar/vector FP32 only)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         # instruction scheduling for latency hiding within a wave (the heavy kernels run
-         # at 2-3 waves per SIMD): 2-4% faster flux and update kernels than the default
-         "-mllvm", "-amdgpu-sched-strategy=max-ilp",
          "-Wall", "-Wno-unused-function"]
 
 

@@ -143,7 +143,16 @@ struct Launch {
   // statistics records of the update kernels, [NSTAT][stat_stride] (one per workgroup)
   uint32_t* stat_part;
   int64_t stat_stride;
+  // 1: every block divides into bricks of 32 x 2 x 4 cells (brick_cells): the fused update
+  // runs brick by brick with the column geometry staged in LDS
+  int32_t brick_upd;
 };
+
+// a block of n interior cells divides into update bricks of 32 x 2 x 4 (x1, x2, x3) cells;
+// the brick count then equals the number of 256-cell tiles
+__host__ __device__ inline bool brick_cells(const int32_t n[3]) {
+  return n[0] % 32 == 0 && n[1] % 2 == 0 && n[2] % 4 == 0;
+}
 
 // records the message returned by grmhd_last_error() and returns code (host.cpp)
 int set_error(int code, const char* msg);

@@ -361,8 +361,18 @@ __device__ __forceinline__ bool learned_guess(const MlpBlob* __restrict__ blob, 
 // the connection coefficients, fluxes), each closed by a scheduling barrier: left to itself the
 // compiler interleaves them with the arithmetic in small groups, and each group then
 // costs a full memory round trip.
+//
+// BRICK: the workgroup is a brick of 32 x 2 x 4 cells (x1, x2, x3), so the four cells of
+// each of its 64 (x1, x2) columns share the column's centre geometry (metric,
+// connection coefficients, floors: NGEO_C values).  Each thread loads a quarter of its
+// column's values with the cell inputs, the workgroup stages them in LDS (sgeo,
+// [NGEO_C][64]), and the metric, the connection coefficients and the floors are read
+// from there: a quarter of the geometry loads, and no memory round trip for the
+// connection coefficients.  Every thread of the workgroup must call it.  Without BRICK
+// the caller passes the metric in m.
+template <bool BRICK>
 __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& bi, const Cell& c,
-                                              const Metric& m, int64_t col,
+                                              Metric& m, double* sgeo, int64_t col,
                                               const double* __restrict__ Pn,
                                               const double* __restrict__ Bn,
                                               const double* __restrict__ Ps,
@@ -404,9 +414,30 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
   for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * V + l];
 #pragma unroll
   for (int i = 0; i < 3; i++) BS[i] = Bcs[3 * bi.off + (int64_t)i * V + l];
-  fl[0] = G.c[RHOFL * G.ncol + col];
-  fl[1] = G.c[UFL * G.ncol + col];
+  double gv[(NGEO_C + 3) / 4];   // BRICK: this thread's quarter of its column's geometry
+  const int cidx = threadIdx.x & 63, q0 = threadIdx.x >> 6;
+  if (BRICK) {
+#pragma unroll
+    for (int k = 0; k < (NGEO_C + 3) / 4; k++) {
+      const int q = q0 + 4 * k;
+      gv[k] = q < NGEO_C ? G.c[q * G.ncol + col] : 0.0;
+    }
+  } else {
+    fl[0] = G.c[RHOFL * G.ncol + col];
+    fl[1] = G.c[UFL * G.ncol + col];
+  }
   __builtin_amdgcn_sched_barrier(0);
+  if (BRICK) {
+#pragma unroll
+    for (int k = 0; k < (NGEO_C + 3) / 4; k++) {
+      const int q = q0 + 4 * k;
+      if (q < NGEO_C) sgeo[q * 64 + cidx] = gv[k];
+    }
+    __syncthreads();
+    m = load_metric(sgeo + cidx, 64, 0);
+    fl[0] = sgeo[RHOFL * 64 + cidx];
+    fl[1] = sgeo[UFL * 64 + cidx];
+  }
 
   // constrained transport of the six faces of this cell (Sec. 2.5)
   const double nb1lo = f1lo + dts * ((e2c - e2a) * ix3 - (e3c - e3a) * ix2);
@@ -452,8 +483,10 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
     for (int h = 0; h < 2; h++) {
       double conn[20];
 #pragma unroll
-      for (int j = 0; j < 20; j++) conn[j] = G.c[(CONN0 + 20 * h + j) * G.ncol + col];
-      __builtin_amdgcn_sched_barrier(0);
+      for (int j = 0; j < 20; j++)
+        conn[j] = BRICK ? sgeo[(CONN0 + 20 * h + j) * 64 + cidx]
+                        : G.c[(CONN0 + 20 * h + j) * G.ncol + col];
+      if (!BRICK) __builtin_amdgcn_sched_barrier(0);
       connection_contract(T, conn, 2 * h, q);
     }
 #pragma unroll
@@ -564,18 +597,33 @@ __global__ __launch_bounds__(NT) void k_stats_final(Counters* __restrict__ cnt,
 }
 
 // fused update: conserved update, optional learned guess, inversion, floors, next dt
-template <bool STATS, bool NEXT_DT, bool MLP, int OCC>
+// BRICK: workgroups are bricks of 32 x 2 x 4 cells (every block of the launch divides into
+// them, brick_cells), with the geometry of their 64 columns staged in LDS (conserve_cell).
+template <bool STATS, bool NEXT_DT, bool MLP, int OCC, bool BRICK>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_update(
     Launch L, const double* __restrict__ Pn, const double* __restrict__ Bn,
     const double* __restrict__ Ps, const double* __restrict__ Bcs, const double* __restrict__ F,
     const double* __restrict__ E, double dt_factor, double* __restrict__ Pout,
     double* __restrict__ Bout, double* __restrict__ dt_part, const MlpBlob* __restrict__ mlp) {
+  __shared__ double sgeo[BRICK ? NGEO_C * 64 : 1];
   const BlockTile bt = block_tile(L);
   const BlockInfo bi = L.blk[bt.blk];
   const int g = L.ph.ng;
   Cell c;
-  const bool valid = region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
-                                 g, g, c);
+  bool valid;
+  if (BRICK) {
+    // brick (b0, b1, b2) of the tile, x1 fastest; valid for the whole workgroup or none
+    const int nb0 = bi.n[0] >> 5, nb1 = bi.n[1] >> 1, nb2 = bi.n[2] >> 2;
+    const int t = threadIdx.x;
+    valid = bt.tile < nb0 * nb1 * nb2;
+    const int b0 = bt.tile % nb0, r = bt.tile / nb0, b1 = r % nb1, b2 = r / nb1;
+    c.I = g + b0 * 32 + (t & 31);
+    c.J = g + b1 * 2 + ((t >> 5) & 1);
+    c.K = g + b2 * 4 + (t >> 6);
+    c.loc = ((int64_t)c.K * bi.np[1] + c.J) * bi.np[0] + c.I;
+  } else {
+    valid = region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g, g, g, c);
+  }
   int tier = 0, iters = 0, hits = 0;
   double dtc = __longlong_as_double(0x7FF0000000000000LL);
   const int64_t col = valid ? geo_col(L.geo, bi, c.J, c.I) : 0;
@@ -583,9 +631,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   C2PIn cs;
   double PS[5], fl[2];
   if (valid) {
-    m = load_metric(L.geo.c, L.geo.ncol, col);
+    if (!BRICK) m = load_metric(L.geo.c, L.geo.ncol, col);
     double U[9];
-    conserve_cell(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, U, PS, fl);
+    conserve_cell<BRICK>(L, bi, c, m, sgeo, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, U, PS,
+                         fl);
     c2p_setup(U, m, L.ph.gam, cs);
   }
   bool first = false;
@@ -612,7 +661,9 @@ __global__ __launch_bounds__(NT) void k_conserve(Launch L, const double* __restr
   const int64_t col = geo_col(L.geo, bi, c.J, c.I);
   const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
   double U[9], PS[5], fl[2];
-  conserve_cell(L, bi, c, m, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, U, PS, fl);
+  Metric mc = m;
+  conserve_cell<false>(L, bi, c, mc, nullptr, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, U, PS,
+                       fl);
   double* u = ubuf + 9 * bi.off + c.loc;
 #pragma unroll
   for (int q = 0; q < 9; q++) u[(int64_t)q * bi.vol] = U[q];
@@ -1013,8 +1064,12 @@ int64_t launch_update(const Launch& L, const double* Pn, const double* Bn, const
     return (int64_t)grid.x * grid.y;
   }
 #define GRMHD_UPD(ND, ML, V)                                                                 \
-  hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V]>), grid, dim3(NT), 0, L.stream, Lc, Pn, \
-                     Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob)
+  if (L.brick_upd)                                                                          \
+    hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], true>), grid, dim3(NT), 0, L.stream, \
+                       Lc, Pn, Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob);      \
+  else                                                                                      \
+    hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], false>), grid, dim3(NT), 0,       \
+                       L.stream, Lc, Pn, Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob)
 #define GRMHD_UPD_V(ND, ML)                                               \
   switch (L.var_upd) {                                                    \
     case 0: GRMHD_UPD(ND, ML, 0); break;                                  \
