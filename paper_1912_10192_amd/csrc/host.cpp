@@ -1131,7 +1131,7 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   L.stat_stride = p.slots;
   L.brick_upd = 1;
   for (const BlockInfo& b : p.info)
-    if (!brick_cells(b.n)) L.brick_upd = 0;
+    if (!brick_x1(b.n)) L.brick_upd = 0;
   L.stream = c->stream;
   for (int k = 0; k < 3; k++) L.var_flux[k] = 2;   // 4 waves per SIMD
   L.var_upd = 0;

@@ -143,15 +143,20 @@ struct Launch {
   // statistics records of the update kernels, [NSTAT][stat_stride] (one per workgroup)
   uint32_t* stat_part;
   int64_t stat_stride;
-  // 1: every block divides into bricks of 32 x 2 x 4 cells (brick_cells): the fused update
-  // runs brick by brick with the column geometry staged in LDS
+  // 1: every block divides into update bricks (brick_x1): the fused update runs brick by
+  // brick with the column geometry staged in LDS
   int32_t brick_upd;
 };
 
-// a block of n interior cells divides into update bricks of 32 x 2 x 4 (x1, x2, x3) cells;
-// the brick count then equals the number of 256-cell tiles
-__host__ __device__ inline bool brick_cells(const int32_t n[3]) {
-  return n[0] % 32 == 0 && n[1] % 2 == 0 && n[2] % 4 == 0;
+// Update bricks of 256 cells: 64 (x1, x2) columns of 4 cells along x3, the columns as
+// 32 x 2 or 16 x 4 cells in x1 x x2.  brick_x1 is the brick's x1 width for a block of n
+// interior cells (32 where it divides, else 16), 0 if the block divides into neither;
+// the brick count then equals the number of 256-cell tiles.
+__host__ __device__ inline int brick_x1(const int32_t n[3]) {
+  if (n[2] % 4 != 0) return 0;
+  if (n[0] % 32 == 0 && n[1] % 2 == 0) return 32;
+  if (n[0] % 16 == 0 && n[1] % 4 == 0) return 16;
+  return 0;
 }
 
 // records the message returned by grmhd_last_error() and returns code (host.cpp)

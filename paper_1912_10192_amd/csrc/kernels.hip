@@ -362,8 +362,8 @@ __device__ __forceinline__ bool learned_guess(const MlpBlob* __restrict__ blob, 
 // compiler interleaves them with the arithmetic in small groups, and each group then
 // costs a full memory round trip.
 //
-// BRICK: the workgroup is a brick of 32 x 2 x 4 cells (x1, x2, x3), so the four cells of
-// each of its 64 (x1, x2) columns share the column's centre geometry (metric,
+// BRICK: the workgroup is a brick of 64 (x1, x2) columns of 4 cells along x3 (brick_x1),
+// so the four cells of each column share the column's centre geometry (metric,
 // connection coefficients, floors: NGEO_C values).  Each thread loads a quarter of its
 // column's values with the cell inputs, the workgroup stages them in LDS (sgeo,
 // [NGEO_C][64]), and the metric, the connection coefficients and the floors are read
@@ -597,8 +597,8 @@ __global__ __launch_bounds__(NT) void k_stats_final(Counters* __restrict__ cnt,
 }
 
 // fused update: conserved update, optional learned guess, inversion, floors, next dt
-// BRICK: workgroups are bricks of 32 x 2 x 4 cells (every block of the launch divides into
-// them, brick_cells), with the geometry of their 64 columns staged in LDS (conserve_cell).
+// BRICK: workgroups are bricks of 64 columns x 4 cells (every block of the launch divides
+// into them, brick_x1), with the geometry of their 64 columns staged in LDS (conserve_cell).
 template <bool STATS, bool NEXT_DT, bool MLP, int OCC, bool BRICK>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_update(
     Launch L, const double* __restrict__ Pn, const double* __restrict__ Bn,
@@ -612,13 +612,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   Cell c;
   bool valid;
   if (BRICK) {
-    // brick (b0, b1, b2) of the tile, x1 fastest; valid for the whole workgroup or none
-    const int nb0 = bi.n[0] >> 5, nb1 = bi.n[1] >> 1, nb2 = bi.n[2] >> 2;
+    // brick (b0, b1, b2) of the tile, x1 fastest, bx x by x 4 cells (bx by = 64, so the
+    // thread's column in the brick is t & 63); valid for the whole workgroup or none
+    const int bx = brick_x1(bi.n), by = 64 / bx;
+    const int nb0 = bi.n[0] / bx, nb1 = bi.n[1] / by, nb2 = bi.n[2] >> 2;
     const int t = threadIdx.x;
     valid = bt.tile < nb0 * nb1 * nb2;
     const int b0 = bt.tile % nb0, r = bt.tile / nb0, b1 = r % nb1, b2 = r / nb1;
-    c.I = g + b0 * 32 + (t & 31);
-    c.J = g + b1 * 2 + ((t >> 5) & 1);
+    c.I = g + b0 * bx + (t & (bx - 1));
+    c.J = g + b1 * by + ((t & 63) / bx);
     c.K = g + b2 * 4 + (t >> 6);
     c.loc = ((int64_t)c.K * bi.np[1] + c.J) * bi.np[0] + c.I;
   } else {
