@@ -219,7 +219,12 @@ int grmhd_divb(grmhd_ctx* ctx, double* max_abs, double* max_rel, double* field);
  * coarse origin[3], fine origin[3], positions, 0); what = 10: the schedule of one
  * local-time-stepping cycle (Sec. 3.5) as int32 quadruples (substep, 0 = the block
  * steps / 1 = the slow block is synchronised with a faster x1 neighbour, time level,
- * block) in launch order.  host_buf NULL queries the size in bytes. */
+ * block) in launch order; what = 11: the old state a level step saves for faster
+ * neighbours (the sources of time-interpolated ghosts, Sec. 3.5) as int32 quadruples
+ * (time level, 0 = primitives / 1 = face field, block, element offset in the block's
+ * part of the packed array: variable or component x padded volume + local index),
+ * per level and list sorted, without repeats.  host_buf NULL queries the size in
+ * bytes. */
 int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes);
 
 /* Planner geometry at one internal-coordinate point (host only, no device needed):

@@ -152,6 +152,7 @@ struct Plan {
   std::vector<GhostOp> ops[4];  // cells, x1 faces, x2 faces, x3 faces (sorted by dst level)
   std::vector<AmrOp> aops[4];   // ghost values across refinement levels (sorted likewise)
   std::vector<AmrSample> samples;
+  std::vector<uint8_t> samp_kind;   // the list (cells, x1/x2/x3 faces) of each sample
   std::vector<AmrLink> links;   // refinement faces, sorted by time level
   int32_t link_maxpos = 0;
   // work lists of the stage kernels for blocks of uneven sizes: per block list (each
@@ -169,12 +170,17 @@ struct Plan {
   std::vector<SyncItem> items;                 // sorted by the slow block's level
   std::vector<int64_t> item_off;               // offsets per level (+1)
   std::vector<int64_t> lev_cells;              // interior cells per level
+  // per time level, the elements of its blocks that a faster neighbour reads as the old
+  // state of a time-interpolated ghost: cells (element indices of the packed primitives)
+  // and faces (of the packed face field), sorted, without repeats
+  std::vector<uint32_t> slow_c, slow_f;
+  std::vector<int64_t> slow_c_off, slow_f_off; // offsets per level (+1)
   int32_t rs = 0, rs2 = 0;                     // register plane size and row stride
   // work-buffer offsets (bytes)
   size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, o_dtp, o_stp;
   int64_t slots;   // workgroups of a full-grid stage launch: Courant and statistics partials
   size_t o_aops[4], o_samp, o_links, o_u9, o_wl;
-  size_t o_pold, o_bold, o_reg, o_ubuf, o_lev, o_items, total;
+  size_t o_pold, o_bold, o_slow, o_reg, o_ubuf, o_lev, o_items, total;
 };
 
 // cells of the grid at refinement levels lev along each dimension
@@ -440,6 +446,11 @@ int build_ops(Plan& p) {
     p.aops[kind].clear();
   }
   p.samples.clear();
+  p.samp_kind.clear();
+  auto add_sample = [&](const AmrSample& s, int kind) {
+    p.samples.push_back(s);
+    p.samp_kind.push_back((uint8_t)kind);
+  };
   const bool polar = p.d.bc[2] == GRMHD_BC_POLAR;
   for (int b = 0; b < nb; b++) {
     const BlockInfo& bi = p.info[b];
@@ -497,7 +508,7 @@ int build_ops(Plan& p) {
               const bool ok = kind == 0 ? R.cell_sample(bd.lev, gi, gj, gk, 0, s)
                                         : R.face_sample(bd.lev, N, kind, gi, gj, gk, false, 0, s);
               if (!ok) return fail(GRMHD_EINVAL, R.err);
-              p.samples.push_back(s);
+              add_sample(s, kind);
               p.aops[kind].push_back(op);
               continue;
             }
@@ -516,7 +527,7 @@ int build_ops(Plan& p) {
               for (int x = 0; x < 3; x++)
                 if (pr[x] && (q[x] & 1)) op.mode |= 1 << (AM_UPPER_SHIFT + x);
               if (!R.cell_sample(mu, c[0], c[1], c[2], 0, s)) return fail(GRMHD_EINVAL, R.err);
-              p.samples.push_back(s);
+              add_sample(s, kind);
               for (int x = 0; x < 3; x++) {
                 if (!pr[x]) continue;
                 for (int sg = -1; sg <= 1; sg += 2) {
@@ -525,7 +536,7 @@ int build_ops(Plan& p) {
                   int fl = 0;
                   compose(p.d, M, 0, t[0], t[1], t[2], fl);
                   if (!R.cell_sample(mu, t[0], t[1], t[2], fl, s)) return fail(GRMHD_EINVAL, R.err);
-                  p.samples.push_back(s);
+                  add_sample(s, kind);
                 }
               }
             } else {
@@ -553,7 +564,7 @@ int build_ops(Plan& p) {
                   const bool fz = !compose(p.d, M, kind, t[0], t[1], t[2], fl);
                   if (!R.face_sample(mu, M, kind, t[0], t[1], t[2], fz, fl, s))
                     return fail(GRMHD_EINVAL, R.err);
-                  p.samples.push_back(s);
+                  add_sample(s, kind);
                 }
               }
             }
@@ -563,6 +574,54 @@ int build_ops(Plan& p) {
   }
   if (p.samples.size() >= (size_t(1) << 31)) return fail(GRMHD_EINVAL, "too many refinement samples");
   return GRMHD_OK;
+}
+
+// The old-state elements of each time level: every source of a ghost op or refinement
+// sample read with GF_SLOW (for a restriction, each averaged sub-element), grouped by
+// the source block's time level.
+void build_slow(Plan& p) {
+  const int L = p.nlev;
+  std::vector<std::vector<uint32_t>> sc(L), sf(L);
+  auto take = [&](int kind, int b, int64_t loc) {
+    const BlockInfo& bi = p.info[b];
+    if (kind == 0) {
+      for (int v = 0; v < 5; v++) sc[bi.lat].push_back((uint32_t)(5 * bi.off + v * bi.vol + loc));
+    } else {
+      sf[bi.lat].push_back((uint32_t)(3 * bi.off + (kind - 1) * bi.vol + loc));
+    }
+  };
+  for (int kind = 0; kind < 4; kind++)
+    for (const GhostOp& op : p.ops[kind]) {
+      const int fl = (op.src_blkf >> 24) & 0xFF;
+      if ((fl & GF_SLOW) && !(fl & GF_ZERO)) take(kind, op.src_blkf & 0xFFFFFF, op.src_loc);
+    }
+  for (size_t i = 0; i < p.samples.size(); i++) {
+    const AmrSample& s = p.samples[i];
+    const int fl = (s.blkf >> 24) & 0xFF;
+    if (!(fl & GF_SLOW) || (fl & GF_ZERO)) continue;
+    const int b = s.blkf & 0xFFFFFF;
+    const BlockInfo& bi = p.info[b];
+    const int n0 = (s.mask & 1) ? 2 : 1, n1 = (s.mask & 2) ? 2 : 1, n2 = (s.mask & 4) ? 2 : 1;
+    for (int ok = 0; ok < n2; ok++)
+      for (int oj = 0; oj < n1; oj++)
+        for (int oi = 0; oi < n0; oi++)
+          take(p.samp_kind[i], b, s.loc + ((int64_t)ok * bi.np[1] + oj) * bi.np[0] + oi);
+  }
+  p.slow_c.clear();
+  p.slow_f.clear();
+  p.slow_c_off.assign(L + 1, 0);
+  p.slow_f_off.assign(L + 1, 0);
+  for (int l = 0; l < L; l++) {
+    for (int w = 0; w < 2; w++) {
+      std::vector<uint32_t>& v = w ? sf[l] : sc[l];
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+      std::vector<uint32_t>& out = w ? p.slow_f : p.slow_c;
+      out.insert(out.end(), v.begin(), v.end());
+    }
+    p.slow_c_off[l + 1] = (int64_t)p.slow_c.size();
+    p.slow_f_off[l + 1] = (int64_t)p.slow_f.size();
+  }
 }
 
 // faces shared by a coarse block and a block one level finer
@@ -645,8 +704,9 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
   for (int b = 0; b < nb; b++)
     for (int k = 0; k < 3; k++)
       if (p.blocks[b].lev[k] != p.lmax[k]) p.refined = true;
-  // the list sizes of a refined grid are only known once the lists are built
-  if (p.refined) with_maps = true;
+  // the list sizes of a refined grid, and the saved old-state elements of a grid with
+  // several time levels, are only known once the lists are built
+  if (p.refined || desc->n_lat_levels > 1) with_maps = true;
   // one geometry table per (x1, x2) level pair
   p.tables.clear();
   p.ncol = 0;
@@ -758,6 +818,7 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
     p.link_off.assign(L + 1, 0);
     for (const AmrLink& lk : p.links) p.link_off[p.blocks[lk.coarse].lat + 1]++;
     for (int l = 0; l < L; l++) p.link_off[l + 1] += p.link_off[l];
+    if (with_maps && L > 1) build_slow(p);
     // neighbour checks: every block within one cell of a block (through the physical
     // boundaries) differs by at most one time level; x2 and x3 face neighbours share a
     // time level; x1 neighbours at another time level have the same refinement level and
@@ -879,6 +940,7 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
   const bool lat = p.nlev > 1;
   p.o_pold = take(lat ? 5 * V * 8 : 0);
   p.o_bold = take(lat ? 3 * V * 8 : 0);
+  p.o_slow = take((p.slow_c.size() + p.slow_f.size()) * sizeof(uint32_t));
   p.o_reg = take(lat ? (size_t)nb * 40 * p.rs * 8 : 0);
   {
     // sync items: at most two per block
@@ -969,6 +1031,7 @@ struct grmhd_ctx {
   const void* mlp = nullptr;   // packed MLP blob when the learned guess is on
   // local time stepping
   double *pold = nullptr, *bold = nullptr, *reg = nullptr, *ubuf = nullptr;
+  const uint32_t *slow_c = nullptr, *slow_f = nullptr;
   int32_t* lev_list = nullptr;
   SyncItem* items = nullptr;
   bool batched = false;
@@ -1045,6 +1108,8 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   c->dtp = (double*)(w + p.o_dtp);
   c->u9 = (double*)(w + p.o_u9);
   c->pold = (double*)(w + p.o_pold);
+  c->slow_c = (const uint32_t*)(w + p.o_slow);
+  c->slow_f = c->slow_c + p.slow_c.size();
   c->bold = (double*)(w + p.o_bold);
   c->reg = (double*)(w + p.o_reg);
   c->ubuf = (double*)(w + p.o_ubuf);
@@ -1102,7 +1167,10 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   if ((rc = up(p.o_samp, p.samples.data(), p.samples.size() * sizeof(AmrSample))) ||
       (rc = up(p.o_links, p.links.data(), p.links.size() * sizeof(AmrLink))) ||
       (rc = up(p.o_lev, p.lev_blocks.data(), p.lev_blocks.size() * sizeof(int32_t))) ||
-      (rc = up(p.o_items, p.items.data(), p.items.size() * sizeof(SyncItem)))) {
+      (rc = up(p.o_items, p.items.data(), p.items.size() * sizeof(SyncItem))) ||
+      (rc = up(p.o_slow, p.slow_c.data(), p.slow_c.size() * sizeof(uint32_t))) ||
+      (rc = up(p.o_slow + p.slow_c.size() * sizeof(uint32_t), p.slow_f.data(),
+               p.slow_f.size() * sizeof(uint32_t)))) {
     delete c;
     return rc;
   }
@@ -1226,8 +1294,11 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
   const double t0 = s - std::fmod((double)s, period);
   const double w_pred = (s - t0) / period;
   const double w_corr = (s + 0.5 * scale - t0) / period;
-  launch_copy_blocks(L, P, c->pold, 5);
-  launch_copy_blocks(L, B, c->bold, 3);
+  {
+    const int64_t oc = p.slow_c_off[lev], nc = p.slow_c_off[lev + 1] - oc;
+    const int64_t of = p.slow_f_off[lev], nf = p.slow_f_off[lev + 1] - of;
+    launch_copy_list(L, c->slow_c + oc, nc, P, c->pold, c->slow_f + of, nf, B, c->bold);
+  }
   auto ghosts = [&](double* Pdst, double* Bdst, const double* Pcur, const double* Bcur, double w) {
     prof_begin(c, KC_GHOST);
     const int64_t o0 = p.ops_off[0][lev], n0 = p.ops_off[0][lev + 1] - o0;
@@ -1545,7 +1616,7 @@ int grmhd_divb(grmhd_ctx* c, double* max_abs, double* max_rel, double* field) {
 
 int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes) {
   if (!bytes) return fail(GRMHD_EINVAL, "NULL argument");
-  if (what < 0 || what > 10) return fail(GRMHD_EINVAL, "unknown table");
+  if (what < 0 || what > 11) return fail(GRMHD_EINVAL, "unknown table");
   Plan p;
   int rc = build_plan(desc, p, true);
   if (rc) return rc;
@@ -1565,6 +1636,22 @@ int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, s
         if ((s + 1) % (1 << lev) == 0)
           for (int64_t q = p.item_off[lev]; q < p.item_off[lev + 1]; q++)
             sched.insert(sched.end(), {s, 1, lev, p.items[q].slow});
+    }
+    src = sched.data();
+    need = sched.size() * sizeof(int32_t);
+  } else if (what == 11) {
+    // the saved old-state elements per time level, as (level, list, block, element
+    // offset within the block's part of the packed array)
+    for (int w = 0; w < 2; w++) {
+      const std::vector<uint32_t>& v = w ? p.slow_f : p.slow_c;
+      const std::vector<int64_t>& o = w ? p.slow_f_off : p.slow_c_off;
+      const int64_t nv = w ? 3 : 5;
+      for (int l = 0; l + 1 < (int)o.size(); l++)
+        for (int64_t q = o[l]; q < o[l + 1]; q++) {
+          int b = 0;
+          while (b + 1 < (int)p.info.size() && nv * p.info[b + 1].off <= (int64_t)v[q]) b++;
+          sched.insert(sched.end(), {l, w, b, (int32_t)(v[q] - nv * p.info[b].off)});
+        }
     }
     src = sched.data();
     need = sched.size() * sizeof(int32_t);

@@ -205,6 +205,9 @@ void launch_ghost_cells_t(const Launch& L, const GhostIdx* ops, int64_t nops, co
 void launch_ghost_faces_t(const Launch& L, const GhostIdx* ops, int64_t nops, const double* main,
                           const double* old, const double* cur, double w, double* dst, int comp);
 void launch_copy_blocks(const Launch& L, const double* src, double* dst, int nvar);
+void launch_copy_list(const Launch& L, const uint32_t* ic, int64_t nc, const double* P,
+                      double* Pdst, const uint32_t* jf, int64_t nf, const double* B,
+                      double* Bdst);
 void launch_registers(const Launch& L, const double* F, const double* E, double dt_factor,
                       int first, double* reg, int rs, int rs2);
 void launch_sync(const Launch& L, const SyncItem* items, int nitems, double* P, double* B,

@@ -101,6 +101,25 @@ __global__ __launch_bounds__(LT) void k_copy_blocks(Launch L, const double* __re
   }
 }
 
+// Copy the listed elements: nc cells of the primitives (element indices ic), then nf
+// faces of the face field (indices jf).  The lists hold what faster neighbours read as
+// the old state of time-interpolated ghosts, a few cell layers along shared faces.
+__global__ __launch_bounds__(LT) void k_copy_list(const uint32_t* __restrict__ ic, int64_t nc,
+                                                  const double* __restrict__ P,
+                                                  double* __restrict__ Pdst,
+                                                  const uint32_t* __restrict__ jf, int64_t nf,
+                                                  const double* __restrict__ B,
+                                                  double* __restrict__ Bdst) {
+  const int64_t t = (int64_t)blockIdx.x * LT + threadIdx.x;
+  if (t < nc) {
+    const uint32_t q = ic[t];
+    Pdst[q] = P[q];
+  } else if (t < nc + nf) {
+    const uint32_t q = jf[t - nc];
+    Bdst[q] = B[q];
+  }
+}
+
 // ------------------------------------------------------------------ registers
 
 // per listed block and x1 side: dt-weighted corrector fluxes (8 components) on the x1
@@ -314,6 +333,14 @@ void launch_copy_blocks(const Launch& L, const double* src, double* dst, int nva
   const int64_t r = (int64_t)(L.max_n[0] + 1) * (L.max_n[1] + 1) * (L.max_n[2] + 1);
   const unsigned gx = std::min<unsigned>(cdv(r, LT), 256);
   hipLaunchKernelGGL(k_copy_blocks, dim3(gx, L.nblk), dim3(LT), 0, L.stream, L, src, dst, nvar);
+}
+
+void launch_copy_list(const Launch& L, const uint32_t* ic, int64_t nc, const double* P,
+                      double* Pdst, const uint32_t* jf, int64_t nf, const double* B,
+                      double* Bdst) {
+  if (nc + nf == 0) return;
+  hipLaunchKernelGGL(k_copy_list, dim3(cdv(nc + nf, LT)), dim3(LT), 0, L.stream, ic, nc, P, Pdst,
+                     jf, nf, B, Bdst);
 }
 
 void launch_registers(const Launch& L, const double* F, const double* E, double dt_factor,

@@ -11,7 +11,7 @@ import numpy as np
 
 from paper_1912_10192_amd import grmhd
 
-GF_FLIP, GF_CLAMP_NEG, GF_CLAMP_POS, GF_ZERO = 1, 2, 4, 8
+GF_FLIP, GF_CLAMP_NEG, GF_CLAMP_POS, GF_ZERO, GF_SLOW = 1, 2, 4, 8, 16
 
 
 def minmod(a, b):
@@ -39,6 +39,7 @@ class Replay:
             self.dx.append([(cfg["xhi"][d] - cfg["xlo"][d]) / N[d] for d in range(3)])
         self._gd = {}
         self.outside = []   # sources read outside their block's interior (see interior())
+        self.slow = set()   # sources read as the old state of a slower block: (b, loc, comp)
 
     def interior(self, b, loc, comp):
         """whether local index loc of block b is an interior cell (comp None) or a face of
@@ -49,9 +50,11 @@ class Replay:
         n = self.desc.blocks[b].n
         return all(g <= idx[d] < g + n[d] + (1 if comp == d else 0) for d in range(3))
 
-    def _src(self, b, loc, comp):
+    def _src(self, b, loc, comp, fl):
         if not self.interior(b, loc, comp):
             self.outside.append((b, loc, comp))
+        if fl & GF_SLOW:
+            self.slow.add((b, loc, comp))
 
     def vol(self, b):
         n = self.lay[b][1]
@@ -79,7 +82,7 @@ class Replay:
         V = n1p * n2p * n3p
         if mask == 0:
             assert 0 <= loc < V
-            self._src(b, loc, None)
+            self._src(b, loc, None, fl)
             x = prim[5 * off + v * V + loc]
         else:
             num = den = 0.0
@@ -88,7 +91,7 @@ class Replay:
                     for oi in range(2 if mask & 1 else 1):
                         l = loc + (ok * n2p + oj) * n1p + oi
                         assert 0 <= l < V
-                        self._src(b, l, None)
+                        self._src(b, l, None, fl)
                         w = self.gdet(b, l)
                         num = num + w * prim[5 * off + v * V + l]
                         den = den + w
@@ -110,7 +113,7 @@ class Replay:
         V = n1p * n2p * n3p
         if mask == 0:
             assert 0 <= loc < V
-            self._src(b, loc, comp)
+            self._src(b, loc, comp, fl)
             x = bface[3 * off + comp * V + loc]
         else:
             acc = 0.0
@@ -120,7 +123,7 @@ class Replay:
                     for oi in range(2 if mask & 1 else 1):
                         l = loc + (ok * n2p + oj) * n1p + oi
                         assert 0 <= l < V
-                        self._src(b, l, comp)
+                        self._src(b, l, comp, fl)
                         acc = acc + bface[3 * off + comp * V + l]
                         cnt += 1
             x = acc * (1.0 / cnt)
@@ -138,7 +141,7 @@ class Replay:
                 Vd, Vs = self.vol(dst_b), self.vol(sb)
                 assert 0 <= dst_loc < Vd and 0 <= src_loc < Vs
                 if not (fl & GF_ZERO):
-                    self._src(sb, src_loc, None if kind == 0 else kind - 1)
+                    self._src(sb, src_loc, None if kind == 0 else kind - 1, fl)
                 if kind == 0:
                     for v in range(5):
                         x = prim[5 * soff + v * Vs + src_loc]

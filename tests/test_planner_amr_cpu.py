@@ -157,3 +157,40 @@ def test_ghost_sources_are_interior_values(case):
     rp = Replay(desc, cfg)
     rp.fill(prim, bface)
     assert rp.outside == []
+
+
+@pytest.mark.parametrize("case", ["mink-lat", "ks-lat", "ks-smr3", "ks-lat-uniform"])
+def test_saved_old_state_is_what_slow_ghosts_read(case):
+    """A level step saves only the elements that faster neighbours read as its old state
+    (time-interpolated ghosts, Sec. 3.5).  The saved list, per time level, is exactly the
+    set of sources the replayed ghost lists read with the slower-source flag: cells for
+    every primitive, faces per component."""
+    if case == "ks-lat-uniform":
+        cfg = configs.scaled(configs.TORUS_UNIFORM, (32, 16, 16), block=(8, 8, 8))
+        blocks = grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=[0, 1, 2, 2])
+    else:
+        _, cfg, blocks = [c for c in cases() if c[0] == case][0]
+    desc = grmhd.Desc(cfg, blocks=blocks)
+    nb = desc.d.n_blocks
+    sizes = [desc.layout(b) for b in range(nb)]
+    prim = np.zeros(5 * sum(int(np.prod(s[1])) for s in sizes))
+    bface = np.zeros(3 * sum(int(np.prod(s[1])) for s in sizes))
+    rp = Replay(desc, cfg)
+    rp.fill(prim, bface)
+    assert rp.slow, "the case has time-interpolated ghosts"
+    want = set()
+    for b, loc, comp in rp.slow:
+        lat, V = desc.blocks[b].lat, rp.vol(b)
+        if comp is None:
+            want.update((lat, 0, b, v * V + loc) for v in range(5))
+        else:
+            want.add((lat, 1, b, comp * V + loc))
+    got = [tuple(int(x) for x in r) for r in desc.plan_dump(11)]
+    assert len(got) == len(set(got))
+    assert set(got) == want
+    # every listed element belongs to a block of the listed level
+    assert all(desc.blocks[b].lat == lat for lat, _, b, _ in got)
+    # per (level, list) the element indices increase
+    for key in {(lat, w) for lat, w, _, _ in got}:
+        seq = [(b, e) for lat, w, b, e in got if (lat, w) == key]
+        assert seq == sorted(seq)
