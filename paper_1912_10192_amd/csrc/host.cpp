@@ -305,6 +305,29 @@ int owner_at(const Plan& p, const int32_t* lev, int64_t i, int64_t j, int64_t k)
   return p.owner[(size_t)((k * N2 + j) * N1 + i)];
 }
 
+// Whether the stage kernels read padded cell x of a block: the face fluxes read cells
+// along their normal across the whole ghost depth and one ghost layer sideways (the
+// transverse fluxes of the boundary edges' EMFs).  So at most one index lies more than
+// one layer outside the interior, and none in the last padding layer (which only
+// completes the face layout).
+bool cell_read(const BlockInfo& bi, int g, const int x[3]) {
+  int far = 0;
+  for (int d = 0; d < 3; d++) {
+    if (x[d] < 0 || x[d] > 2 * g + bi.n[d] - 1) return false;
+    if (x[d] < g - 1 || x[d] > g + bi.n[d]) far++;
+  }
+  return far <= 1;
+}
+
+// Whether a ghost element is read: a cell by the rule above (kind 0), or a face of
+// component kind - 1 that bounds such a cell along its normal (the cell-centred field).
+bool ghost_read(const BlockInfo& bi, int g, int kind, const int x[3]) {
+  if (cell_read(bi, g, x)) return true;
+  if (kind == 0) return false;
+  const int y[3] = {x[0] - (kind == 1), x[1] - (kind == 2), x[2] - (kind == 3)};
+  return cell_read(bi, g, y);
+}
+
 int32_t local_index(const BlockInfo& bi, int64_t li, int64_t lj, int64_t lk) {
   return (int32_t)((lk * bi.np[1] + lj) * bi.np[0] + li);
 }
@@ -468,7 +491,7 @@ int build_ops(Plan& p) {
               const int hi = (kind == dd + 1) ? g + bi.n[dd] : g + bi.n[dd] - 1;
               if (L3[dd] < g || L3[dd] > hi) ghost = true;
             }
-            if (!ghost) continue;
+            if (!ghost || !ghost_read(bi, g, kind, L3)) continue;
             int64_t gi = bd.org[0] + I - g, gj = bd.org[1] + J - g, gk = bd.org[2] + K - g;
             const bool across_pole = polar && (kind == 2 ? (gj < 0 || gj > N[1]) : (gj < 0 || gj >= N[1]));
             int flags = 0;
@@ -922,12 +945,19 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
   for (int kind = 0; kind < 4; kind++) {
     size_t count = with_maps ? p.ops[kind].size() : 0;
     if (!with_maps) {
-      // the same count without building the lists
+      // the same count without building the lists: the read elements outside the
+      // interior (cells, or faces on and inside the block's boundary)
       for (int b = 0; b < nb; b++) {
         const BlockInfo& bi = p.info[b];
-        int64_t inside = 1;
-        for (int dd = 0; dd < 3; dd++) inside *= (kind == dd + 1) ? bi.n[dd] + 1 : bi.n[dd];
-        count += (size_t)(bi.vol - inside);
+        for (int K = 0; K < bi.np[2]; K++)
+          for (int J = 0; J < bi.np[1]; J++)
+            for (int I = 0; I < bi.np[0]; I++) {
+              const int x[3] = {I, J, K};
+              bool ghost = false;
+              for (int dd = 0; dd < 3; dd++)
+                if (x[dd] < g || x[dd] > g + bi.n[dd] - (kind == dd + 1 ? 0 : 1)) ghost = true;
+              if (ghost && ghost_read(bi, g, kind, x)) count++;
+            }
       }
     }
     p.o_ops[kind] = take(count * sizeof(GhostOp));
