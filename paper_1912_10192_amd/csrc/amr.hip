@@ -96,16 +96,12 @@ __device__ double face_value(const BlockInfo* __restrict__ blk, const AmrSample&
   return x;
 }
 
-__global__ __launch_bounds__(AT) void k_amr_cells(const BlockInfo* __restrict__ blk, GeoTab G,
-                                                  const AmrOp* __restrict__ ops, int64_t nops,
-                                                  const AmrSample* __restrict__ samp,
-                                                  const double* __restrict__ main,
-                                                  const double* __restrict__ old,
-                                                  const double* __restrict__ cur, double w,
-                                                  double* __restrict__ dst) {
-  const int64_t i = (int64_t)blockIdx.x * AT + threadIdx.x;
-  if (i >= nops) return;
-  const AmrOp op = ops[i];
+// a ghost cell from its refinement stencil (prolongation with minmod slopes, or a
+// restriction sample), then the physical-boundary flip and clamps
+__device__ void amr_cell_op(const BlockInfo* __restrict__ blk, const GeoTab& G, const AmrOp op,
+                            const AmrSample* __restrict__ samp, const double* __restrict__ main,
+                            const double* __restrict__ old, const double* __restrict__ cur,
+                            double w, double* __restrict__ dst) {
   const BlockInfo d = blk[op.dst_blk];
   const AmrSample* S = samp + op.samp;
   const int pd = op.mode & AM_PDIMS;
@@ -129,16 +125,12 @@ __global__ __launch_bounds__(AT) void k_amr_cells(const BlockInfo* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(AT) void k_amr_faces(const BlockInfo* __restrict__ blk,
-                                                  const AmrOp* __restrict__ ops, int64_t nops,
-                                                  const AmrSample* __restrict__ samp,
-                                                  const double* __restrict__ main,
-                                                  const double* __restrict__ old,
-                                                  const double* __restrict__ cur, double w,
-                                                  double* __restrict__ dst, int comp) {
-  const int64_t i = (int64_t)blockIdx.x * AT + threadIdx.x;
-  if (i >= nops) return;
-  const AmrOp op = ops[i];
+// a ghost face of component comp from its refinement stencil (the mean of two stencils
+// for a face cutting a coarse cell), then the flip or the axis zero
+__device__ void amr_face_op(const BlockInfo* __restrict__ blk, const AmrOp op,
+                            const AmrSample* __restrict__ samp, const double* __restrict__ main,
+                            const double* __restrict__ old, const double* __restrict__ cur,
+                            double w, double* __restrict__ dst, int comp) {
   const BlockInfo d = blk[op.dst_blk];
   const AmrSample* S = samp + op.samp;
   const int t = op.mode & AM_PDIMS & ~(1 << comp);
@@ -165,6 +157,28 @@ __global__ __launch_bounds__(AT) void k_amr_faces(const BlockInfo* __restrict__ 
   if (ofl & GF_ZERO) x = 0.0;
   else if (ofl & GF_FLIP) x = -x;
   dst[3 * d.off + (int64_t)comp * d.vol + op.dst_loc] = x;
+}
+
+// One thread per entry of the concatenated refinement lists (cells, then faces of
+// components 1..3).  With old == main and w = 0 slower sources read the main state.
+__global__ __launch_bounds__(AT) void k_amr_ghosts(const BlockInfo* __restrict__ blk, GeoTab G,
+                                                   AmrLists A, const AmrSample* __restrict__ samp,
+                                                   const double* __restrict__ Pmain,
+                                                   const double* __restrict__ Pold,
+                                                   const double* __restrict__ Pcur,
+                                                   double* __restrict__ Pdst,
+                                                   const double* __restrict__ Bmain,
+                                                   const double* __restrict__ Bold,
+                                                   const double* __restrict__ Bcur,
+                                                   double* __restrict__ Bdst, double w) {
+  const int64_t t = (int64_t)blockIdx.x * AT + threadIdx.x;
+  if (t >= A.end[3]) return;
+  if (t < A.end[0]) {
+    amr_cell_op(blk, G, A.ops[0][t], samp, Pmain, Pold, Pcur, w, Pdst);
+    return;
+  }
+  const int k = t < A.end[1] ? 1 : (t < A.end[2] ? 2 : 3);
+  amr_face_op(blk, A.ops[k][t - A.end[k - 1]], samp, Bmain, Bold, Bcur, w, Bdst, k - 1);
 }
 
 // ------------------------------------------------------------------ refinement faces
@@ -269,28 +283,18 @@ __global__ __launch_bounds__(AT) void k_amr_bsync(Launch L, const AmrLink* __res
 
 // Without a stored start state (a gather outside a time-stepping cycle, where every
 // block stands at the same time) samples flagged as slower read the main state too.
-void launch_amr_cells(const Launch& L, const AmrOp* ops, int64_t nops, const AmrSample* samp,
-                      const double* main, const double* old, const double* cur, double w,
-                      double* dst) {
-  if (nops <= 0) return;
-  if (!old) {
-    old = main;
+void launch_amr_ghosts(const Launch& L, const AmrLists& A, const AmrSample* samp,
+                       const double* Pmain, const double* Pold, const double* Pcur, double* Pdst,
+                       const double* Bmain, const double* Bold, const double* Bcur, double* Bdst,
+                       double w) {
+  if (A.end[3] <= 0) return;
+  if (!Pold || !Bold) {
+    Pold = Pmain;
+    Bold = Bmain;
     w = 0.0;
   }
-  k_amr_cells<<<dim3((unsigned)((nops + AT - 1) / AT)), dim3(AT), 0, L.stream>>>(
-      L.blk, L.geo, ops, nops, samp, main, old, cur, w, dst);
-}
-
-void launch_amr_faces(const Launch& L, const AmrOp* ops, int64_t nops, const AmrSample* samp,
-                      const double* main, const double* old, const double* cur, double w,
-                      double* dst, int comp) {
-  if (nops <= 0) return;
-  if (!old) {
-    old = main;
-    w = 0.0;
-  }
-  k_amr_faces<<<dim3((unsigned)((nops + AT - 1) / AT)), dim3(AT), 0, L.stream>>>(
-      L.blk, ops, nops, samp, main, old, cur, w, dst, comp);
+  k_amr_ghosts<<<dim3((unsigned)((A.end[3] + AT - 1) / AT)), dim3(AT), 0, L.stream>>>(
+      L.blk, L.geo, A, samp, Pmain, Pold, Pcur, Pdst, Bmain, Bold, Bcur, Bdst, w);
 }
 
 void launch_amr_fix(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* F,

@@ -1267,13 +1267,38 @@ static void prof_end(grmhd_ctx* c) {
   c->prof_used += 2;
 }
 
+// the ghost lists of the blocks of one time level (lev >= 0) or of all blocks
+static GhostLists ghost_lists(const grmhd_ctx* c, int lev) {
+  GhostLists G;
+  int64_t run = 0;
+  for (int k = 0; k < 4; k++) {
+    const int64_t o = lev < 0 ? 0 : c->plan.ops_off[k][lev];
+    const int64_t n = lev < 0 ? c->nops[k] : c->plan.ops_off[k][lev + 1] - o;
+    G.ops[k] = c->ops[k] + o;
+    run += n;
+    G.end[k] = run;
+  }
+  return G;
+}
+
+// the refinement lists likewise
+static AmrLists amr_lists(const grmhd_ctx* c, int lev) {
+  AmrLists A;
+  int64_t run = 0;
+  for (int k = 0; k < 4; k++) {
+    const int64_t o = lev < 0 ? 0 : c->plan.aops_off[k][lev];
+    const int64_t n = lev < 0 ? c->naops[k] : c->plan.aops_off[k][lev + 1] - o;
+    A.ops[k] = c->aops[k] + o;
+    run += n;
+    A.end[k] = run;
+  }
+  return A;
+}
+
 static void fill_ghosts(grmhd_ctx* c, double* P, double* B) {
   prof_begin(c, KC_GHOST);
-  launch_ghost_cells(c->L, c->ops[0], c->nops[0], P);
-  for (int k = 0; k < 3; k++) launch_ghost_faces(c->L, c->ops[k + 1], c->nops[k + 1], B, k);
-  launch_amr_cells(c->L, c->aops[0], c->naops[0], c->samp, P, nullptr, P, 0.0, P);
-  for (int k = 0; k < 3; k++)
-    launch_amr_faces(c->L, c->aops[k + 1], c->naops[k + 1], c->samp, B, nullptr, B, 0.0, B, k);
+  launch_ghosts(c->L, ghost_lists(c, -1), P, B);
+  launch_amr_ghosts(c->L, amr_lists(c, -1), c->samp, P, nullptr, P, P, B, nullptr, B, B, 0.0);
   prof_end(c);
 }
 
@@ -1331,18 +1356,9 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
   }
   auto ghosts = [&](double* Pdst, double* Bdst, const double* Pcur, const double* Bcur, double w) {
     prof_begin(c, KC_GHOST);
-    const int64_t o0 = p.ops_off[0][lev], n0 = p.ops_off[0][lev + 1] - o0;
-    launch_ghost_cells_t(L, c->ops[0] + o0, n0, P, c->pold, Pcur, w, Pdst);
-    for (int k = 0; k < 3; k++) {
-      const int64_t o = p.ops_off[k + 1][lev], n = p.ops_off[k + 1][lev + 1] - o;
-      launch_ghost_faces_t(L, c->ops[k + 1] + o, n, B, c->bold, Bcur, w, Bdst, k);
-    }
-    const int64_t a0 = p.aops_off[0][lev], m0 = p.aops_off[0][lev + 1] - a0;
-    launch_amr_cells(L, c->aops[0] + a0, m0, c->samp, P, c->pold, Pcur, w, Pdst);
-    for (int k = 0; k < 3; k++) {
-      const int64_t o = p.aops_off[k + 1][lev], n = p.aops_off[k + 1][lev + 1] - o;
-      launch_amr_faces(L, c->aops[k + 1] + o, n, c->samp, B, c->bold, Bcur, w, Bdst, k);
-    }
+    launch_ghosts_t(L, ghost_lists(c, lev), P, c->pold, Pcur, Pdst, B, c->bold, Bcur, Bdst, w);
+    launch_amr_ghosts(L, amr_lists(c, lev), c->samp, P, c->pold, Pcur, Pdst, B, c->bold, Bcur,
+                      Bdst, w);
     prof_end(c);
   };
   auto stage_l = [&](const double* Ps, const double* Bs, double factor, double* Pout) {

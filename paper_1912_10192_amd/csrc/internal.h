@@ -34,6 +34,13 @@ struct GhostIdx {
   uint32_t dst, src, dvol, svol_fl;
 };
 
+// The four ghost lists of one fill run as one launch: cells, then faces of components
+// 1..3; thread t takes entry t of their concatenation (end: running totals).
+struct GhostLists {
+  const GhostIdx* ops[4];
+  int64_t end[4];
+};
+
 // A ghost value that involves another refinement level: a restriction of a finer
 // neighbour or a prolongation from a coarser one.  Samples are interior values of other
 // blocks (or of the block itself) at the source's own level; the op combines them.
@@ -47,6 +54,11 @@ struct GhostIdx {
 // transverse dimension.  Without prolonged dimensions a single sample.
 struct AmrOp {
   int32_t dst_blk, dst_loc, mode, samp;
+};
+// the four refinement lists of one fill as one launch (as GhostLists)
+struct AmrLists {
+  const AmrOp* ops[4];
+  int64_t end[4];
 };
 // block | flags << 24 (time and boundary flags of this value), local index of the value
 // (a cell, or a face of the op's component), and the dimensions averaged by a
@@ -163,8 +175,7 @@ __host__ __device__ inline int brick_x1(const int32_t n[3]) {
 int set_error(int code, const char* msg);
 
 // kernel launchers (kernels.hip)
-void launch_ghost_cells(const Launch& L, const GhostIdx* ops, int64_t nops, double* P);
-void launch_ghost_faces(const Launch& L, const GhostIdx* ops, int64_t nops, double* B, int comp);
+void launch_ghosts(const Launch& L, const GhostLists& G, double* P, double* B);
 void launch_bcell(const Launch& L, const double* B, double* Bc);
 void launch_flux(const Launch& L, int dir, int recon, int riemann, const double* P,
                  const double* Bc, const double* B, double* F);
@@ -190,20 +201,17 @@ void launch_divb(const Launch& L, const double* B, double* field, double* part);
 void launch_extract(const Launch& L, const double* Pin, const double* Bin, int64_t n, double* P,
                     double* B, double* geom);
 // refinement levels (amr.hip)
-void launch_amr_cells(const Launch& L, const AmrOp* ops, int64_t nops, const AmrSample* samp,
-                      const double* main, const double* old, const double* cur, double w,
-                      double* dst);
-void launch_amr_faces(const Launch& L, const AmrOp* ops, int64_t nops, const AmrSample* samp,
-                      const double* main, const double* old, const double* cur, double w,
-                      double* dst, int comp);
+void launch_amr_ghosts(const Launch& L, const AmrLists& A, const AmrSample* samp,
+                       const double* Pmain, const double* Pold, const double* Pcur, double* Pdst,
+                       const double* Bmain, const double* Bold, const double* Bcur, double* Bdst,
+                       double w);
 void launch_amr_fix(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* F,
                     double* E);
 void launch_amr_bsync(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* B);
 // local time stepping (lat.hip)
-void launch_ghost_cells_t(const Launch& L, const GhostIdx* ops, int64_t nops, const double* main,
-                          const double* old, const double* cur, double w, double* dst);
-void launch_ghost_faces_t(const Launch& L, const GhostIdx* ops, int64_t nops, const double* main,
-                          const double* old, const double* cur, double w, double* dst, int comp);
+void launch_ghosts_t(const Launch& L, const GhostLists& G, const double* Pmain,
+                     const double* Pold, const double* Pcur, double* Pdst, const double* Bmain,
+                     const double* Bold, const double* Bcur, double* Bdst, double w);
 void launch_copy_blocks(const Launch& L, const double* src, double* dst, int nvar);
 void launch_copy_list(const Launch& L, const uint32_t* ic, int64_t nc, const double* P,
                       double* Pdst, const uint32_t* jf, int64_t nf, const double* B,

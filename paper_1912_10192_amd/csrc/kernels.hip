@@ -92,30 +92,30 @@ __device__ __forceinline__ bool region_cell(const BlockInfo& bi, int t, int r0, 
 
 // ------------------------------------------------------------------ ghost gather
 
-__global__ __launch_bounds__(NT) void k_ghost_cells(const GhostIdx* __restrict__ ops, int64_t nops,
-                                                    double* __restrict__ P) {
-  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (i >= nops) return;
-  const GhostIdx op = ops[i];
-  const int fl = op.svol_fl >> 24;
-  const int64_t svol = op.svol_fl & 0xFFFFFF;
-  const double* src = P + op.src;
-  double* dst = P + op.dst;
+// One thread per entry of the concatenated lists: a ghost cell (five primitives, with
+// the physical-boundary flip and clamps) or a ghost face (flip, or zero on the axis).
+__global__ __launch_bounds__(NT) void k_ghosts(GhostLists G, double* __restrict__ P,
+                                               double* __restrict__ B) {
+  const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (t >= G.end[3]) return;
+  if (t < G.end[0]) {
+    const GhostIdx op = G.ops[0][t];
+    const int fl = op.svol_fl >> 24;
+    const int64_t svol = op.svol_fl & 0xFFFFFF;
+    const double* src = P + op.src;
+    double* dst = P + op.dst;
 #pragma unroll
-  for (int v = 0; v < 5; v++) {
-    double x = src[v * svol];
-    if (v == 3 && (fl & GF_FLIP)) x = -x;
-    if (v == 2 && (fl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
-    if (v == 2 && (fl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
-    dst[v * (int64_t)op.dvol] = x;
+    for (int v = 0; v < 5; v++) {
+      double x = src[v * svol];
+      if (v == 3 && (fl & GF_FLIP)) x = -x;
+      if (v == 2 && (fl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
+      if (v == 2 && (fl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
+      dst[v * (int64_t)op.dvol] = x;
+    }
+    return;
   }
-}
-
-__global__ __launch_bounds__(NT) void k_ghost_faces(const GhostIdx* __restrict__ ops, int64_t nops,
-                                                    double* __restrict__ B) {
-  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
-  if (i >= nops) return;
-  const GhostIdx op = ops[i];
+  const int k = t < G.end[1] ? 1 : (t < G.end[2] ? 2 : 3);
+  const GhostIdx op = G.ops[k][t - G.end[k - 1]];
   const int fl = op.svol_fl >> 24;
   double x = B[op.src];
   if (fl & GF_ZERO) x = 0.0;
@@ -951,15 +951,9 @@ __global__ __launch_bounds__(NT) void k_c2p_batch_mlp(int64_t n, const double* _
 
 static inline unsigned cdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-void launch_ghost_cells(const Launch& L, const GhostIdx* ops, int64_t nops, double* P) {
-  if (nops == 0) return;
-  hipLaunchKernelGGL(k_ghost_cells, dim3(cdiv(nops, NT)), dim3(NT), 0, L.stream, ops, nops, P);
-}
-
-void launch_ghost_faces(const Launch& L, const GhostIdx* ops, int64_t nops, double* B, int comp) {
-  if (nops == 0) return;
-  (void)comp;   // the list's element indices hold the component
-  hipLaunchKernelGGL(k_ghost_faces, dim3(cdiv(nops, NT)), dim3(NT), 0, L.stream, ops, nops, B);
+void launch_ghosts(const Launch& L, const GhostLists& G, double* P, double* B) {
+  if (G.end[3] == 0) return;
+  hipLaunchKernelGGL(k_ghosts, dim3(cdiv(G.end[3], NT)), dim3(NT), 0, L.stream, G, P, B);
 }
 
 // The grid of a stage kernel over region class cls (r: cells of the largest block's

@@ -26,53 +26,52 @@ __device__ __forceinline__ BlockInfo list_block(const Launch& L, int y) {
 
 // ------------------------------------------------------------------ ghost gather
 
-// Ghost cells of the listed destination blocks.  Source per op relation:
+// The ghosts of one level's blocks from the concatenated lists (cells, then faces of
+// components 1..3).  Source per op relation:
 //   same level: `cur` (the main state for a predictor, the stage state for a corrector)
 //   slower:     old + w (main - old)
 //   faster:     main
-// Physical-boundary flips and clamps apply afterwards.
-__global__ __launch_bounds__(LT) void k_ghost_cells_t(const GhostIdx* __restrict__ ops,
-                                                      int64_t nops, const double* __restrict__ main,
-                                                      const double* __restrict__ old,
-                                                      const double* __restrict__ cur, double w,
-                                                      double* __restrict__ dst) {
-  const int64_t i = (int64_t)blockIdx.x * LT + threadIdx.x;
-  if (i >= nops) return;
-  const GhostIdx op = ops[i];
-  const int fl = op.svol_fl >> 24;
-  const int64_t svol = op.svol_fl & 0xFFFFFF;
-  double* out = dst + op.dst;
-#pragma unroll
-  for (int v = 0; v < 5; v++) {
-    const int64_t q = op.src + v * svol;
-    double x;
-    if (fl & GF_SLOW) x = old[q] + w * (main[q] - old[q]);
-    else if (fl & GF_FAST) x = main[q];
-    else x = cur[q];
-    if (v == 3 && (fl & GF_FLIP)) x = -x;
-    if (v == 2 && (fl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
-    if (v == 2 && (fl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
-    out[v * (int64_t)op.dvol] = x;
-  }
+// Physical-boundary flips, clamps and axis zeros apply afterwards.
+__device__ __forceinline__ double timed_value(int fl, int64_t q, const double* __restrict__ main,
+                                              const double* __restrict__ old,
+                                              const double* __restrict__ cur, double w) {
+  if (fl & GF_SLOW) return old[q] + w * (main[q] - old[q]);
+  if (fl & GF_FAST) return main[q];
+  return cur[q];
 }
 
-__global__ __launch_bounds__(LT) void k_ghost_faces_t(const GhostIdx* __restrict__ ops,
-                                                      int64_t nops, const double* __restrict__ main,
-                                                      const double* __restrict__ old,
-                                                      const double* __restrict__ cur, double w,
-                                                      double* __restrict__ dst) {
-  const int64_t i = (int64_t)blockIdx.x * LT + threadIdx.x;
-  if (i >= nops) return;
-  const GhostIdx op = ops[i];
+__global__ __launch_bounds__(LT) void k_ghosts_t(GhostLists G, const double* __restrict__ Pmain,
+                                                 const double* __restrict__ Pold,
+                                                 const double* __restrict__ Pcur,
+                                                 double* __restrict__ Pdst,
+                                                 const double* __restrict__ Bmain,
+                                                 const double* __restrict__ Bold,
+                                                 const double* __restrict__ Bcur,
+                                                 double* __restrict__ Bdst, double w) {
+  const int64_t t = (int64_t)blockIdx.x * LT + threadIdx.x;
+  if (t >= G.end[3]) return;
+  if (t < G.end[0]) {
+    const GhostIdx op = G.ops[0][t];
+    const int fl = op.svol_fl >> 24;
+    const int64_t svol = op.svol_fl & 0xFFFFFF;
+    double* out = Pdst + op.dst;
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      double x = timed_value(fl, op.src + v * svol, Pmain, Pold, Pcur, w);
+      if (v == 3 && (fl & GF_FLIP)) x = -x;
+      if (v == 2 && (fl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
+      if (v == 2 && (fl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
+      out[v * (int64_t)op.dvol] = x;
+    }
+    return;
+  }
+  const int k = t < G.end[1] ? 1 : (t < G.end[2] ? 2 : 3);
+  const GhostIdx op = G.ops[k][t - G.end[k - 1]];
   const int fl = op.svol_fl >> 24;
-  const int64_t q = op.src;
-  double x;
-  if (fl & GF_SLOW) x = old[q] + w * (main[q] - old[q]);
-  else if (fl & GF_FAST) x = main[q];
-  else x = cur[q];
+  double x = timed_value(fl, op.src, Bmain, Bold, Bcur, w);
   if (fl & GF_ZERO) x = 0.0;
   else if (fl & GF_FLIP) x = -x;
-  dst[op.dst] = x;
+  Bdst[op.dst] = x;
 }
 
 // Copy the interior of every listed block: nvar = 5 primitives of the interior cells, or
@@ -314,19 +313,12 @@ __global__ void k_tsim_cycle(Counters* cnt, double courant, double substeps) {
 
 static inline unsigned cdv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-void launch_ghost_cells_t(const Launch& L, const GhostIdx* ops, int64_t nops, const double* main,
-                          const double* old, const double* cur, double w, double* dst) {
-  if (nops == 0) return;
-  hipLaunchKernelGGL(k_ghost_cells_t, dim3(cdv(nops, LT)), dim3(LT), 0, L.stream, ops, nops, main,
-                     old, cur, w, dst);
-}
-
-void launch_ghost_faces_t(const Launch& L, const GhostIdx* ops, int64_t nops, const double* main,
-                          const double* old, const double* cur, double w, double* dst, int comp) {
-  if (nops == 0) return;
-  (void)comp;   // the list's element indices hold the component
-  hipLaunchKernelGGL(k_ghost_faces_t, dim3(cdv(nops, LT)), dim3(LT), 0, L.stream, ops, nops, main,
-                     old, cur, w, dst);
+void launch_ghosts_t(const Launch& L, const GhostLists& G, const double* Pmain,
+                     const double* Pold, const double* Pcur, double* Pdst, const double* Bmain,
+                     const double* Bold, const double* Bcur, double* Bdst, double w) {
+  if (G.end[3] == 0) return;
+  hipLaunchKernelGGL(k_ghosts_t, dim3(cdv(G.end[3], LT)), dim3(LT), 0, L.stream, G, Pmain, Pold,
+                     Pcur, Pdst, Bmain, Bold, Bcur, Bdst, w);
 }
 
 void launch_copy_blocks(const Launch& L, const double* src, double* dst, int nvar) {
