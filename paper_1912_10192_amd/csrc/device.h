@@ -232,6 +232,42 @@ __device__ __forceinline__ void recon_face(const double s[6], double& left, doub
   }
 }
 
+// face states of the faces between s[2], s[3] (l0, r0) and between s[3], s[4] (l1, r1)
+// from the seven-cell line s[0..6]: the same values as recon_face on each face, with the
+// slopes, interface values and limited parabola of the shared cells computed once
+template <int RECON>
+__device__ __forceinline__ void recon_pair(const double s[7], double& l0, double& r0, double& l1,
+                                           double& r1) {
+  if (RECON == 0) {
+    const double d2 = mc_lim(s[2] - s[1], s[3] - s[2]);
+    const double d3 = mc_lim(s[3] - s[2], s[4] - s[3]);
+    const double d4 = mc_lim(s[4] - s[3], s[5] - s[4]);
+    l0 = s[2] + 0.5 * d2;
+    r0 = s[3] - 0.5 * d3;
+    l1 = s[3] + 0.5 * d3;
+    r1 = s[4] - 0.5 * d4;
+  } else {
+    const double d1 = mc_lim(s[1] - s[0], s[2] - s[1]);
+    const double d2 = mc_lim(s[2] - s[1], s[3] - s[2]);
+    const double d3 = mc_lim(s[3] - s[2], s[4] - s[3]);
+    const double d4 = mc_lim(s[4] - s[3], s[5] - s[4]);
+    const double d5 = mc_lim(s[5] - s[4], s[6] - s[5]);
+    constexpr double sixth = 1.0 / 6.0;
+    const double f15 = 0.5 * (s[1] + s[2]) - (d2 - d1) * sixth;
+    const double f25 = 0.5 * (s[2] + s[3]) - (d3 - d2) * sixth;
+    const double f35 = 0.5 * (s[3] + s[4]) - (d4 - d3) * sixth;
+    const double f45 = 0.5 * (s[4] + s[5]) - (d5 - d4) * sixth;
+    double l2 = f15, r2 = f25, l3 = f25, r3 = f35, l4 = f35, r4 = f45;
+    ppm_limit(s[2], l2, r2);
+    ppm_limit(s[3], l3, r3);
+    ppm_limit(s[4], l4, r4);
+    l0 = r2;
+    r0 = l3;
+    l1 = r3;
+    r1 = l4;
+  }
+}
+
 // -------------------------------------------------------------- geometric source
 
 // Qbar_nu = sqrt(-g) T^k_l Gamma^l_{nu k} for nu = t, 1, 2, 3 (energy and momentum)

@@ -22,7 +22,10 @@ constexpr int NT = STAGE_NT;   // threads per workgroup (four wavefronts)
 // SIMD the compiler must fit (trading registers for latency hiding).  Which variant a
 // launch uses is the autotuner's choice (Launch::var_flux, Launch::var_upd).
 // (variants asking for 6 or 8 waves spill and run 1.2-4x slower on MI355X; not built)
-constexpr int FLUX_OCC[NVAR_FLUX] = {1, 2, 4};
+// flux variants: one face per thread at 1, 2, 4 waves per SIMD, then two faces per
+// thread along the normal at 1, 2
+constexpr int FLUX_OCC[NVAR_FLUX] = {1, 2, 4, 1, 2};
+constexpr bool FLUX_PAIR[NVAR_FLUX] = {false, false, false, true, true};
 constexpr int UPD_OCC[NVAR_UPD] = {1, 2};
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Remap the
@@ -146,6 +149,54 @@ __global__ __launch_bounds__(NT) void k_bcell(Launch L, const double* __restrict
 
 // ------------------------------------------------------------------ face fluxes
 
+// The flux of one face from its two reconstructed states: fluxes, conserved states and
+// fast magnetosonic speeds of both sides, then HLLE (RIEMANN 1) or LLF (0); stored at
+// out with stride V per component.
+template <int DIR, int RIEMANN>
+__device__ __forceinline__ void face_flux(const double PL[5], const double PR[5],
+                                          const double BL[3], const double BR[3], const Metric& m,
+                                          double gam, double* __restrict__ out, int64_t V) {
+  constexpr int t1 = DIR == 1 ? 1 : 0;   // transverse field components (0-based)
+  constexpr int t2 = DIR == 3 ? 1 : 2;
+  double UL[9], UR[9], FL[8], FR[8];
+  double vmaxL, vminL, vmaxR, vminR;
+  {
+    Fluid f;
+    fluid_state<true>(PL, BL, m, f);
+    const double kap = entropy_kappa<true>(PL, gam);
+    flux_vector<0>(PL, f, m, gam, kap, UL);
+    flux_vector<DIR>(PL, f, m, gam, kap, FL);
+    wave_speeds<DIR, true>(PL, f, m, gam, vmaxL, vminL);
+  }
+  {
+    Fluid f;
+    fluid_state<true>(PR, BR, m, f);
+    const double kap = entropy_kappa<true>(PR, gam);
+    flux_vector<0>(PR, f, m, gam, kap, UR);
+    flux_vector<DIR>(PR, f, m, gam, kap, FR);
+    wave_speeds<DIR, true>(PR, f, m, gam, vmaxR, vminR);
+  }
+  // conserved components in flux order: mass, energy, momenta, transverse field, entropy
+  constexpr int uidx[8] = {0, 1, 2, 3, 4, 5 + t1, 5 + t2, 8};
+  const double cmax = fmax(0.0, fmax(vmaxL, vmaxR));
+  const double cmin = -fmin(0.0, fmin(vminL, vminR));
+  if (RIEMANN == 0) {
+    const double cc = fmax(cmax, cmin);
+#pragma unroll
+    for (int q = 0; q < 8; q++) out[q * V] = 0.5 * (FL[q] + FR[q] - cc * (UR[uidx[q]] - UL[uidx[q]]));
+  } else {
+    if (cmax + cmin > 0.0) {
+      const double ic = rcp_nr(cmax + cmin);
+#pragma unroll
+      for (int q = 0; q < 8; q++)
+        out[q * V] = (cmin * FR[q] + cmax * FL[q] - cmax * cmin * (UR[uidx[q]] - UL[uidx[q]])) * ic;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; q++) out[q * V] = 0.5 * (FL[q] + FR[q]);
+    }
+  }
+}
+
 // One thread per face along x^DIR.  Normal range [ng, ng + n], transverse range widened
 // by one ghost layer so the edge EMFs of every interior face have their four fluxes.
 template <int DIR, int RECON, int RIEMANN, int OCC>
@@ -195,53 +246,88 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     return;
   }
   double PL[5], PR[5], BL[3], BR[3];
-  {
 #pragma unroll
-    for (int v = 0; v < 5; v++) recon_face<RECON>(sp[v], PL[v], PR[v]);
-    recon_face<RECON>(sb[0], BL[t1], BR[t1]);
-    recon_face<RECON>(sb[1], BL[t2], BR[t2]);
-    const double bn = bface * rcp_nr(m.gdet);
-    BL[DIR - 1] = bn;
-    BR[DIR - 1] = bn;
+  for (int v = 0; v < 5; v++) recon_face<RECON>(sp[v], PL[v], PR[v]);
+  recon_face<RECON>(sb[0], BL[t1], BR[t1]);
+  recon_face<RECON>(sb[1], BL[t2], BR[t2]);
+  const double bn = bface * rcp_nr(m.gdet);
+  BL[DIR - 1] = bn;
+  BR[DIR - 1] = bn;
+  face_flux<DIR, RIEMANN>(PL, PR, BL, BR, m, L.ph.gam, out, V);
+}
+
+// Two faces per thread along x^DIR (the faces at normal index ng + 2i and ng + 2i + 1,
+// the second only inside the normal range): the seven-cell line gives both faces' states
+// with the slopes, interface values and limited parabola of the shared cells computed
+// once.  Same arithmetic per face as k_flux.
+template <int DIR, int RECON, int RIEMANN, int OCC>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_flux_pair(
+    Launch L, const double* __restrict__ P, const double* __restrict__ Bc,
+    const double* __restrict__ B, double* __restrict__ F) {
+  const BlockTile bt = block_tile(L);
+  const BlockInfo bi = L.blk[bt.blk];
+  const int g = L.ph.ng;
+  const int nn = bi.n[DIR - 1] + 1;   // faces along the normal
+  const int r0 = DIR == 1 ? (nn + 1) / 2 : bi.n[0] + 2;
+  const int r1 = DIR == 2 ? (nn + 1) / 2 : bi.n[1] + 2;
+  const int r2 = DIR == 3 ? (nn + 1) / 2 : bi.n[2] + 2;
+  const int t = bt.tile * NT + threadIdx.x;
+  if (t >= r0 * r1 * r2) return;
+  const int ti = t % r0, tq = t / r0, tj = tq % r1, tk = tq / r1;
+  const int I = DIR == 1 ? g + 2 * ti : g - 1 + ti;
+  const int J = DIR == 2 ? g + 2 * tj : g - 1 + tj;
+  const int K = DIR == 3 ? g + 2 * tk : g - 1 + tk;
+  const int64_t loc = ((int64_t)K * bi.np[1] + J) * bi.np[0] + I;
+  const bool two = (DIR == 1 ? I : (DIR == 2 ? J : K)) + 1 <= g + bi.n[DIR - 1];
+  const int64_t V = bi.vol;
+  const int64_t st = DIR == 1 ? 1 : (DIR == 2 ? (int64_t)bi.np[0] : (int64_t)bi.np[0] * bi.np[1]);
+  const double* tab = DIR == 1 ? L.geo.f1 : (DIR == 2 ? L.geo.f2 : L.geo.c);
+  const Metric m0 = load_metric(tab, L.geo.ncol, geo_col(L.geo, bi, J, I));
+  double* out = F + 24 * bi.off + (int64_t)(DIR - 1) * 8 * V + loc;
+  constexpr int t1 = DIR == 1 ? 1 : 0;
+  constexpr int t2 = DIR == 3 ? 1 : 2;
+  constexpr int k0 = RECON == 0 ? 1 : 0, k1 = RECON == 0 ? 6 : 7;   // stencil used
+  double sp[5][7], sb[2][7];
+  const double* p = P + 5 * bi.off + loc;
+  const double* bc = Bc + 3 * bi.off + loc;
+#pragma unroll
+  for (int k = 0; k < 7; k++) {
+#pragma unroll
+    for (int v = 0; v < 5; v++)
+      sp[v][k] = (k < k0 || k >= k1) ? 0.0 : p[(int64_t)v * V + (k - 3) * st];
+    sb[0][k] = (k < k0 || k >= k1) ? 0.0 : bc[(int64_t)t1 * V + (k - 3) * st];
+    sb[1][k] = (k < k0 || k >= k1) ? 0.0 : bc[(int64_t)t2 * V + (k - 3) * st];
   }
+  const double* bf = B + 3 * bi.off + (int64_t)(DIR - 1) * V + loc;
+  const double bface0 = bf[0], bface1 = bf[st];
+  __builtin_amdgcn_sched_barrier(0);
+  double PL0[5], PR0[5], PL1[5], PR1[5], BL0[3], BR0[3], BL1[3], BR1[3];
+#pragma unroll
+  for (int v = 0; v < 5; v++) recon_pair<RECON>(sp[v], PL0[v], PR0[v], PL1[v], PR1[v]);
+  recon_pair<RECON>(sb[0], BL0[t1], BR0[t1], BL1[t1], BR1[t1]);
+  recon_pair<RECON>(sb[1], BL0[t2], BR0[t2], BL1[t2], BR1[t2]);
   const double gam = L.ph.gam;
-  double UL[9], UR[9], FL[8], FR[8];
-  double vmaxL, vminL, vmaxR, vminR;
-  {
-    Fluid f;
-    fluid_state<true>(PL, BL, m, f);
-    const double kap = entropy_kappa<true>(PL, gam);
-    flux_vector<0>(PL, f, m, gam, kap, UL);
-    flux_vector<DIR>(PL, f, m, gam, kap, FL);
-    wave_speeds<DIR, true>(PL, f, m, gam, vmaxL, vminL);
-  }
-  {
-    Fluid f;
-    fluid_state<true>(PR, BR, m, f);
-    const double kap = entropy_kappa<true>(PR, gam);
-    flux_vector<0>(PR, f, m, gam, kap, UR);
-    flux_vector<DIR>(PR, f, m, gam, kap, FR);
-    wave_speeds<DIR, true>(PR, f, m, gam, vmaxR, vminR);
-  }
-  // conserved components in flux order: mass, energy, momenta, transverse field, entropy
-  constexpr int uidx[8] = {0, 1, 2, 3, 4, 5 + t1, 5 + t2, 8};
-  const double cmax = fmax(0.0, fmax(vmaxL, vmaxR));
-  const double cmin = -fmin(0.0, fmin(vminL, vminR));
-  if (RIEMANN == 0) {
-    const double cc = fmax(cmax, cmin);
+  if (DIR == 2 && m0.gdet == 0.0) {   // the polar axis carries no flux
 #pragma unroll
-    for (int q = 0; q < 8; q++) out[q * V] = 0.5 * (FL[q] + FR[q] - cc * (UR[uidx[q]] - UL[uidx[q]]));
+    for (int q = 0; q < 8; q++) out[q * V] = 0.0;
   } else {
-    if (cmax + cmin > 0.0) {
-      const double ic = rcp_nr(cmax + cmin);
-#pragma unroll
-      for (int q = 0; q < 8; q++)
-        out[q * V] = (cmin * FR[q] + cmax * FL[q] - cmax * cmin * (UR[uidx[q]] - UL[uidx[q]])) * ic;
-    } else {
-#pragma unroll
-      for (int q = 0; q < 8; q++) out[q * V] = 0.5 * (FL[q] + FR[q]);
-    }
+    const double bn = bface0 * rcp_nr(m0.gdet);
+    BL0[DIR - 1] = bn;
+    BR0[DIR - 1] = bn;
+    face_flux<DIR, RIEMANN>(PL0, PR0, BL0, BR0, m0, gam, out, V);
   }
+  if (!two) return;
+  const Metric m1 =
+      DIR == 3 ? m0 : load_metric(tab, L.geo.ncol, geo_col(L.geo, bi, J + (DIR == 2), I + (DIR == 1)));
+  if (DIR == 2 && m1.gdet == 0.0) {
+#pragma unroll
+    for (int q = 0; q < 8; q++) out[st + q * V] = 0.0;
+    return;
+  }
+  const double bn = bface1 * rcp_nr(m1.gdet);
+  BL1[DIR - 1] = bn;
+  BR1[DIR - 1] = bn;
+  face_flux<DIR, RIEMANN>(PL1, PR1, BL1, BR1, m1, gam, out + st, V);
 }
 
 // ------------------------------------------------------------------ edge EMFs
@@ -979,19 +1065,28 @@ void launch_bcell(const Launch& L, const double* B, double* Bc) {
 template <int DIR>
 static void flux_dir(const Launch& L, int recon, int riemann, const double* P, const double* Bc,
                      const double* B, double* F) {
+  const int v = L.var_flux[DIR - 1];
+  // faces (or face pairs) of the largest block's region; a work list made for single
+  // faces covers the pairs' tiles too (the surplus tiles exit at once)
   int64_t r = 1;
-  for (int d = 0; d < 3; d++) r *= (d == DIR - 1) ? L.max_n[d] + 1 : L.max_n[d] + 2;
+  for (int d = 0; d < 3; d++)
+    r *= (d == DIR - 1) ? (FLUX_PAIR[v] ? (L.max_n[d] + 2) / 2 : L.max_n[d] + 1) : L.max_n[d] + 2;
   Launch Lc;
   const dim3 grid = stage_grid(L, WL_FLUX1 + DIR - 1, r, Lc);
-  const int v = L.var_flux[DIR - 1];
-#define GRMHD_FLUX(RC, RM, V)                                                                \
-  hipLaunchKernelGGL((k_flux<DIR, RC, RM, FLUX_OCC[V]>), grid, dim3(NT), 0, L.stream, Lc, P, Bc, \
-                     B, F)
+#define GRMHD_FLUX(RC, RM, V)                                                                  \
+  if constexpr (FLUX_PAIR[V])                                                                 \
+    hipLaunchKernelGGL((k_flux_pair<DIR, RC, RM, FLUX_OCC[V]>), grid, dim3(NT), 0, L.stream, Lc, \
+                       P, Bc, B, F);                                                          \
+  else                                                                                        \
+    hipLaunchKernelGGL((k_flux<DIR, RC, RM, FLUX_OCC[V]>), grid, dim3(NT), 0, L.stream, Lc, P, \
+                       Bc, B, F)
 #define GRMHD_FLUX_V(RC, RM)                                              \
   switch (v) {                                                            \
     case 0: GRMHD_FLUX(RC, RM, 0); break;                                 \
     case 1: GRMHD_FLUX(RC, RM, 1); break;                                 \
-    default: GRMHD_FLUX(RC, RM, 2); break;                                \
+    case 2: GRMHD_FLUX(RC, RM, 2); break;                                 \
+    case 3: GRMHD_FLUX(RC, RM, 3); break;                                 \
+    default: GRMHD_FLUX(RC, RM, 4); break;                                \
   }
   if (recon == 0 && riemann == 0) {
     GRMHD_FLUX_V(0, 0);

@@ -74,8 +74,10 @@ class C2PBatch(C.Structure):
                 ("maxit", C.c_int32), ("mlp_weights", C.c_void_p)]
 
 
-# occupancy variants of the flux and update kernels (minimum waves per SIMD), as built
-FLUX_WAVES = (1, 2, 4)
+# variants of the flux kernel (minimum waves per SIMD, faces per thread) and of the update
+# kernel (minimum waves per SIMD), as built
+FLUX_WAVES = (1, 2, 4, 1, 2)
+FLUX_FACES = (1, 1, 1, 2, 2)
 UPDATE_WAVES = (1, 2)
 NVAR_FLUX, NVAR_UPD = len(FLUX_WAVES), len(UPDATE_WAVES)
 
@@ -390,7 +392,7 @@ class Grid:
         _check(lib().grmhd_autotune(self.ctx, choice, ms))
         return {"flux": [choice[k] for k in range(3)], "update": choice[3],
                 "update_split": choice[4],
-                "flux_waves": FLUX_WAVES, "update_waves": UPDATE_WAVES,
+                "flux_waves": FLUX_WAVES, "flux_faces": FLUX_FACES, "update_waves": UPDATE_WAVES,
                 "flux_ms": [[ms[d * nf + v] for v in range(nf)] for d in range(3)],
                 "update_ms": [ms[3 * nf + v] for v in range(nu)],
                 "update_split_ms": [ms[3 * nf + nu + v] for v in range(nu)]}

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+from oracle.amr import AmrGrid
 from paper_1912_10192_amd import configs, grmhd, initdata
 from tests.helpers import mink_cfg, pad_global, random_periodic_state, unpad_global
 
@@ -161,21 +162,58 @@ def test_cons2prim_batch_round_trip():
 
 
 def test_autotuned_variants_keep_the_result():
-    """the autotuner only picks among occupancy variants of the same arithmetic: a tuned
-    grid steps to the same state as an untuned one"""
+    """the autotuner only picks among variants of the same arithmetic (occupancy, faces per
+    thread): a tuned grid steps to the same state as an untuned one"""
     cfg = configs.scaled(configs.TORUS_UNIFORM, (64, 32, 32), block=(32, 32, 32))
     state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
     a = grmhd.Grid(cfg, state=state)
     b = grmhd.Grid(cfg, state=state)
     choice = b.autotune()
     print(f"[tune] {choice}", file=sys.stderr, flush=True)
-    assert all(0 <= v < 3 for v in choice["flux"]) and choice["update"] in (0, 1)
+    assert all(0 <= v < grmhd.NVAR_FLUX for v in choice["flux"]) and choice["update"] in (0, 1)
     a.step(2)
     b.step(2)
     same = all(np.array_equal(x, y) for x, y in zip(a.get_state(), b.get_state()))
     print(f"[tune] bit-identical: {same}", file=sys.stderr, flush=True)
     e = parity_err(b.get_state(), a.get_state())
     assert max(e.values()) <= 1e-13, e
+
+
+@pytest.mark.parametrize("case", ["ppm-hlle", "plm-llf", "ppm-polar-smr"])
+def test_two_faces_per_thread_match_one(case):
+    """the flux kernels that take two faces per thread along the normal (reconstruction of
+    the shared cells done once) give the one-face kernels' fluxes: two steps agree to
+    rounding, on uniform blocks, with PLM + LLF, and on refined polar bands (blocks of
+    uneven sizes, launched through work lists)"""
+    if case == "ppm-polar-smr":
+        eff = (32, 64, 32)
+        cfg = configs.scaled(configs.TORUS_UNIFORM, eff, ng=3)
+        blocks = configs.polar_smr_blocks(eff, 16, [0, 0])
+    else:
+        base = dict(configs.TORUS_UNIFORM, recon=0, riemann=0) if case == "plm-llf" else configs.TORUS_UNIFORM
+        cfg = configs.scaled(base, (64, 32, 32), block=(32, 16, 16))
+        blocks = None
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    res = []
+    for flux in ((2, 2, 2), (3, 3, 3), (4, 4, 4)):
+        if blocks is None:
+            grid = grmhd.Grid(cfg, state=state)
+            grid.set_variants(flux=flux)
+            grid.step(2)
+            res.append(grid.get_state())
+        else:
+            ref = AmrGrid(cfg, blocks)
+            bs = initdata.block_states(state, ref.blocks, ref.Lmax)
+            grid = grmhd.Grid(cfg, blocks=blocks)
+            grid.set_blocks(bs)
+            grid.set_variants(flux=flux)
+            grid.step(2)
+            res.append([x for blk in grid.get_blocks() for x in blk])
+        del grid
+    for other in res[1:]:
+        for x, y in zip(res[0], other):
+            scale = np.abs(x).max() + 1e-300
+            assert np.abs(x - y).max() <= 1e-13 * scale, case
 
 
 def test_split_update_is_bit_identical_to_fused():
