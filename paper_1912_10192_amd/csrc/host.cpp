@@ -905,10 +905,12 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
           case WL_BCELL: return (int64_t)bi.np[0] * bi.np[1] * bi.np[2];
           case WL_EMF: return (int64_t)(bi.n[0] + 1) * (bi.n[1] + 1) * (bi.n[2] + 1);
           case WL_CELLS: return (int64_t)bi.n[0] * bi.n[1] * bi.n[2];
-          default: {
-            const int d = cls - WL_FLUX1;
+          default: {   // faces along x^(d+1), or pairs of them
+            const bool pair = cls >= WL_PAIR1;
+            const int d = pair ? cls - WL_PAIR1 : cls - WL_FLUX1;
             int64_t r = 1;
-            for (int e = 0; e < 3; e++) r *= e == d ? bi.n[e] + 1 : bi.n[e] + 2;
+            for (int e = 0; e < 3; e++)
+              r *= e == d ? (pair ? (bi.n[e] + 2) / 2 : bi.n[e] + 1) : bi.n[e] + 2;
             return r;
           }
         }

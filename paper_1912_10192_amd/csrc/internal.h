@@ -123,7 +123,8 @@ __host__ __device__ inline int64_t geo_col(const GeoTab&, const BlockInfo& bi, i
 
 // region classes of the stage kernels' work lists: padded block, faces per direction,
 // edges, interior cells
-enum { WL_BCELL = 0, WL_FLUX1, WL_FLUX2, WL_FLUX3, WL_EMF, WL_CELLS, WL_N };
+enum { WL_BCELL = 0, WL_FLUX1, WL_FLUX2, WL_FLUX3, WL_EMF, WL_CELLS, WL_PAIR1, WL_PAIR2, WL_PAIR3,
+       WL_N };
 constexpr int STAGE_NT = 256;   // threads per workgroup of the stage kernels
 
 // per-workgroup statistics records of the update kernels: inversion tier counts, Newton

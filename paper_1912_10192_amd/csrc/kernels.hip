@@ -1066,13 +1066,12 @@ template <int DIR>
 static void flux_dir(const Launch& L, int recon, int riemann, const double* P, const double* Bc,
                      const double* B, double* F) {
   const int v = L.var_flux[DIR - 1];
-  // faces (or face pairs) of the largest block's region; a work list made for single
-  // faces covers the pairs' tiles too (the surplus tiles exit at once)
+  // faces (or face pairs) of the largest block's region
   int64_t r = 1;
   for (int d = 0; d < 3; d++)
     r *= (d == DIR - 1) ? (FLUX_PAIR[v] ? (L.max_n[d] + 2) / 2 : L.max_n[d] + 1) : L.max_n[d] + 2;
   Launch Lc;
-  const dim3 grid = stage_grid(L, WL_FLUX1 + DIR - 1, r, Lc);
+  const dim3 grid = stage_grid(L, (FLUX_PAIR[v] ? WL_PAIR1 : WL_FLUX1) + DIR - 1, r, Lc);
 #define GRMHD_FLUX(RC, RM, V)                                                                  \
   if constexpr (FLUX_PAIR[V])                                                                 \
     hipLaunchKernelGGL((k_flux_pair<DIR, RC, RM, FLUX_OCC[V]>), grid, dim3(NT), 0, L.stream, Lc, \
