@@ -178,22 +178,23 @@ __device__ __forceinline__ void wave_speeds(const double P[5], const Fluid& f, c
   const double B = 2.0 * (ut * ud * (1.0 - cms2) - cms2 * h0d);
   const double C = ud * ud * (1.0 - cms2) - cms2 * hdd;
   double disc = B * B - 4.0 * A * C;
-  disc = disc < 0.0 ? 0.0 : disc;
+  disc = fmax(disc, 0.0);
   const double sq = FAST ? sqrt_nr(disc) : sqrt(disc);
   const double i2a = FAST ? 0.5 * rcp_nr(A) : 0.5 / A;
   const double vp = (B + sq) * i2a, vm = (B - sq) * i2a;
-  vmax = vp > vm ? vp : vm;
-  vmin = vp > vm ? vm : vp;
+  vmax = fmax(vp, vm);
+  vmin = fmin(vp, vm);
 }
 
 // ------------------------------------------------------------------ reconstruction
 
+// min(2|dm|, 2|dp|, |dm + dp|/2) with the sign of dm, zero at an extremum; min and
+// copysign map to single instructions (v_min_f64, a bit insert) where compare-and-select
+// forms take three each
 __device__ __forceinline__ double mc_lim(double dm, double dp) {
   if (dm * dp <= 0.0) return 0.0;
-  const double a = 2.0 * fabs(dm), b = 2.0 * fabs(dp), c = 0.5 * fabs(dm + dp);
-  double s = a < b ? a : b;
-  s = s < c ? s : c;
-  return dm > 0.0 ? s : -s;
+  const double s = fmin(2.0 * fmin(fabs(dm), fabs(dp)), 0.5 * fabs(dm + dp));
+  return copysign(s, dm);
 }
 
 // monotonised parabola of one cell (Colella & Woodward 1984)
