@@ -57,8 +57,15 @@ __device__ __forceinline__ void mlp_wave(const MlpBlob* __restrict__ blob, const
                                          float* out) {
   const int l = __lane_id();
   const int row = l & 15, grp = l >> 4;
-  const bf16x4* F = blob->frag;
+#pragma unroll 1
   for (int t = 0; t < 4; t++) {
+    // The weights and biases are re-read (from cache) for every tile of 16 cells: an
+    // opaque copy of the blob pointer keeps the compiler from hoisting all 40 fragments
+    // and the biases out of the loop, which would hold ~130 registers for the whole
+    // pass (and, inlined into the update kernel, cost it a wavefront per SIMD).
+    const MlpBlob* bp = blob;
+    asm volatile("" : "+s"(bp));
+    const bf16x4* F = bp->frag;
     const int cell = t * 16 + row;
     bf16x4 b[4];
 #pragma unroll
@@ -73,14 +80,14 @@ __device__ __forceinline__ void mlp_wave(const MlpBlob* __restrict__ blob, const
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
       acc = mfma16(F[(0 + mt) * 64 + l], b[0], acc);
 #pragma unroll
-      for (int j = 0; j < 4; j++) acc[j] = tanh_fast(acc[j] + blob->b1[mt * 16 + 4 * grp + j]);
+      for (int j = 0; j < 4; j++) acc[j] = tanh_fast(acc[j] + bp->b1[mt * 16 + 4 * grp + j]);
       h[mt] = acc;
     }
     // layers 2 and 3: 64 -> 64
 #pragma unroll
     for (int layer = 0; layer < 2; layer++) {
       const int base = 4 + layer * 16;
-      const float* bias = layer == 0 ? blob->b2 : blob->b3;
+      const float* bias = layer == 0 ? bp->b2 : bp->b3;
 #pragma unroll
       for (int ks = 0; ks < 4; ks++)
 #pragma unroll
@@ -104,8 +111,8 @@ __device__ __forceinline__ void mlp_wave(const MlpBlob* __restrict__ blob, const
 #pragma unroll
     for (int ks = 0; ks < 4; ks++) acc = mfma16(F[(36 + ks) * 64 + l], b[ks], acc);
     if (grp == 0) {
-      out[cell * 2 + 0] = acc[0] + blob->b4[0];
-      out[cell * 2 + 1] = acc[1] + blob->b4[1];
+      out[cell * 2 + 0] = acc[0] + bp->b4[0];
+      out[cell * 2 + 1] = acc[1] + bp->b4[1];
     }
   }
 }
