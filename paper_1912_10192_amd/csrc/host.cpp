@@ -1071,6 +1071,10 @@ struct grmhd_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   hipEvent_t ev0, ev1;
+  // two side streams (default priority) for the x2 and x3 face fluxes, with the events
+  // that fork them from the launch stream and join them back
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
 };
 
 // the work lists of block list `list` (a time level, or nlev for all blocks) into L
@@ -1245,6 +1249,11 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   HIPCHK(hipStreamSynchronize(c->stream));   // host staging vectors go out of scope
   HIPCHK(hipEventCreate(&c->ev0));
   HIPCHK(hipEventCreate(&c->ev1));
+  for (int k = 0; k < 2; k++) {
+    HIPCHK(hipStreamCreateWithFlags(&c->side[k], hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->join_ev[k], hipEventDisableTiming));
+  }
+  HIPCHK(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
   *out = c;
   return GRMHD_OK;
 }
@@ -1304,18 +1313,40 @@ static void fill_ghosts(grmhd_ctx* c, double* P, double* B) {
   prof_end(c);
 }
 
+// The face fluxes of a stage.  The three directions read the same inputs and write
+// disjoint parts of F: x1 runs on the launch stream and x2, x3 on the two side streams,
+// forked and joined by events (inside a captured cycle these become parallel graph
+// branches), so one direction's launch tail overlaps the others' work.  With per-class
+// profiling on they run one after the other on the launch stream.
+static void launch_fluxes(grmhd_ctx* c, const Launch& L, const double* Ps, const double* Bs) {
+  const int recon = c->plan.d.recon, riem = c->plan.d.riemann;
+  if (c->profile) {
+    for (int dir = 1; dir <= 3; dir++) {
+      prof_begin(c, KC_FLUX1 + dir - 1);
+      launch_flux(L, dir, recon, riem, Ps, c->bc, Bs, c->f);
+      prof_end(c);
+    }
+    return;
+  }
+  (void)hipEventRecord(c->fork_ev, L.stream);
+  for (int k = 0; k < 2; k++) (void)hipStreamWaitEvent(c->side[k], c->fork_ev, 0);
+  launch_flux(L, 1, recon, riem, Ps, c->bc, Bs, c->f);
+  for (int k = 0; k < 2; k++) {
+    Launch Ls = L;
+    Ls.stream = c->side[k];
+    launch_flux(Ls, k + 2, recon, riem, Ps, c->bc, Bs, c->f);
+    (void)hipEventRecord(c->join_ev[k], c->side[k]);
+    (void)hipStreamWaitEvent(L.stream, c->join_ev[k], 0);
+  }
+}
+
 static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double* Ps,
                   const double* Bs, double factor, double* Pout, double* Bout, double* dt_part) {
   const Launch& L = c->L;
-  const int recon = c->plan.d.recon, riem = c->plan.d.riemann;
   prof_begin(c, KC_BCELL);
   launch_bcell(L, Bs, c->bc);
   prof_end(c);
-  for (int dir = 1; dir <= 3; dir++) {
-    prof_begin(c, KC_FLUX1 + dir - 1);
-    launch_flux(L, dir, recon, riem, Ps, c->bc, Bs, c->f);
-    prof_end(c);
-  }
+  launch_fluxes(c, L, Ps, Bs);
   prof_begin(c, KC_EMF);
   launch_emf(L, c->f, c->e);
   launch_amr_fix(L, c->links, (int)c->plan.links.size(), c->plan.link_maxpos, c->f, c->e);
@@ -1343,7 +1374,6 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
   L.nblk = (int32_t)(p.lev_boff[lev + 1] - p.lev_boff[lev]);
   set_work_lists(c, L, lev);
   if (L.nblk == 0) return;
-  const int recon = p.d.recon, riem = p.d.riemann;
   double* P = c->bufs.prim;
   double* B = c->bufs.bface;
   const double scale = std::ldexp(1.0, lev);
@@ -1367,11 +1397,7 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
     prof_begin(c, KC_BCELL);
     launch_bcell(L, Bs, c->bc);
     prof_end(c);
-    for (int dir = 1; dir <= 3; dir++) {
-      prof_begin(c, KC_FLUX1 + dir - 1);
-      launch_flux(L, dir, recon, riem, Ps, c->bc, Bs, c->f);
-      prof_end(c);
-    }
+    launch_fluxes(c, L, Ps, Bs);
     const int64_t lo = p.link_off[lev], nl = p.link_off[lev + 1] - lo;
     prof_begin(c, KC_EMF);
     launch_emf(L, c->f, c->e);
@@ -1746,6 +1772,11 @@ int grmhd_destroy(grmhd_ctx* c) {
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  for (int k = 0; k < 2; k++) {
+    if (c->side[k]) (void)hipStreamDestroy(c->side[k]);
+    if (c->join_ev[k]) (void)hipEventDestroy(c->join_ev[k]);
+  }
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   delete c;
   return GRMHD_OK;
 }
