@@ -154,7 +154,7 @@ int grmhd_step(grmhd_ctx* ctx, int32_t n_cycles, grmhd_step_stats* stats);
 /* Autotuner of the two heavy kernels.  The flux kernel (per direction) is built in
  * GRMHD_NVAR_FLUX variants: one face per thread at a minimum of 1, 2, 4 waves per SIMD
  * the compiler must fit, then two faces per thread along the normal (the shared cells'
- * reconstruction done once) at 1, 2; the update kernel in GRMHD_NVAR_UPD occupancy
+ * reconstruction done once) at 2; the update kernel in GRMHD_NVAR_UPD occupancy
  * variants (1, 2 waves), and in
  * two forms: one fused kernel, or two (the conserved state of every cell through a
  * buffer, then the inversion).  This times every variant and form on the context's
@@ -165,7 +165,7 @@ int grmhd_step(grmhd_ctx* ctx, int32_t n_cycles, grmhd_step_stats* stats);
  * split); ms (host, nullable, 3 GRMHD_NVAR_FLUX + 2 GRMHD_NVAR_UPD doubles) the mean
  * milliseconds per variant (flux x1 variants, x2, x3, fused update variants, split
  * update variants).  The state is not modified; counters are reset; synchronises. */
-#define GRMHD_NVAR_FLUX 5
+#define GRMHD_NVAR_FLUX 4
 #define GRMHD_NVAR_UPD 2
 int grmhd_autotune(grmhd_ctx* ctx, int32_t choice[5], double* ms);
 /* Sets the kernel variants directly (the layout of grmhd_autotune's choice), for

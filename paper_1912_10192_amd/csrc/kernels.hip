@@ -23,9 +23,9 @@ constexpr int NT = STAGE_NT;   // threads per workgroup (four wavefronts)
 // launch uses is the autotuner's choice (Launch::var_flux, Launch::var_upd).
 // (variants asking for 6 or 8 waves spill and run 1.2-4x slower on MI355X; not built)
 // flux variants: one face per thread at 1, 2, 4 waves per SIMD, then two faces per
-// thread along the normal at 1, 2
-constexpr int FLUX_OCC[NVAR_FLUX] = {1, 2, 4, 1, 2};
-constexpr bool FLUX_PAIR[NVAR_FLUX] = {false, false, false, true, true};
+// thread along the normal at 2 (it fits 3 waves; asked for 4 it spills)
+constexpr int FLUX_OCC[NVAR_FLUX] = {1, 2, 4, 2};
+constexpr bool FLUX_PAIR[NVAR_FLUX] = {false, false, false, true};
 constexpr int UPD_OCC[NVAR_UPD] = {1, 2};
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Remap the
@@ -307,6 +307,23 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   recon_pair<RECON>(sb[0], BL0[t1], BR0[t1], BL1[t1], BR1[t1]);
   recon_pair<RECON>(sb[1], BL0[t2], BR0[t2], BL1[t2], BR1[t2]);
   const double gam = L.ph.gam;
+  // The second face's states wait in LDS while the first face's physics runs, so the
+  // registers hold one face's physics at a time (the compiler barrier keeps it from
+  // forwarding the stored values and holding them in registers after all).
+  __shared__ double park[14][NT];
+  {
+    const int tx = threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      park[v][tx] = PL1[v];
+      park[5 + v][tx] = PR1[v];
+    }
+    park[10][tx] = BL1[t1];
+    park[11][tx] = BL1[t2];
+    park[12][tx] = BR1[t1];
+    park[13][tx] = BR1[t2];
+  }
+  asm volatile("" ::: "memory");
   if (DIR == 2 && m0.gdet == 0.0) {   // the polar axis carries no flux
 #pragma unroll
     for (int q = 0; q < 8; q++) out[q * V] = 0.0;
@@ -317,6 +334,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     face_flux<DIR, RIEMANN>(PL0, PR0, BL0, BR0, m0, gam, out, V);
   }
   if (!two) return;
+  asm volatile("" ::: "memory");
+  {
+    const int tx = threadIdx.x;
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      PL1[v] = park[v][tx];
+      PR1[v] = park[5 + v][tx];
+    }
+    BL1[t1] = park[10][tx];
+    BL1[t2] = park[11][tx];
+    BR1[t1] = park[12][tx];
+    BR1[t2] = park[13][tx];
+  }
   const Metric m1 =
       DIR == 3 ? m0 : load_metric(tab, L.geo.ncol, geo_col(L.geo, bi, J + (DIR == 2), I + (DIR == 1)));
   if (DIR == 2 && m1.gdet == 0.0) {
@@ -1084,8 +1114,7 @@ static void flux_dir(const Launch& L, int recon, int riemann, const double* P, c
     case 0: GRMHD_FLUX(RC, RM, 0); break;                                 \
     case 1: GRMHD_FLUX(RC, RM, 1); break;                                 \
     case 2: GRMHD_FLUX(RC, RM, 2); break;                                 \
-    case 3: GRMHD_FLUX(RC, RM, 3); break;                                 \
-    default: GRMHD_FLUX(RC, RM, 4); break;                                \
+    default: GRMHD_FLUX(RC, RM, 3); break;                                \
   }
   if (recon == 0 && riemann == 0) {
     GRMHD_FLUX_V(0, 0);

@@ -76,8 +76,8 @@ class C2PBatch(C.Structure):
 
 # variants of the flux kernel (minimum waves per SIMD, faces per thread) and of the update
 # kernel (minimum waves per SIMD), as built
-FLUX_WAVES = (1, 2, 4, 1, 2)
-FLUX_FACES = (1, 1, 1, 2, 2)
+FLUX_WAVES = (1, 2, 4, 2)
+FLUX_FACES = (1, 1, 1, 2)
 UPDATE_WAVES = (1, 2)
 NVAR_FLUX, NVAR_UPD = len(FLUX_WAVES), len(UPDATE_WAVES)
 

@@ -195,7 +195,7 @@ def test_two_faces_per_thread_match_one(case):
         blocks = None
     state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
     res = []
-    for flux in ((2, 2, 2), (3, 3, 3), (4, 4, 4)):
+    for flux in ((2, 2, 2), (3, 3, 3)):
         if blocks is None:
             grid = grmhd.Grid(cfg, state=state)
             grid.set_variants(flux=flux)
