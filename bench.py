@@ -48,15 +48,15 @@ BYTES_PER_UNIT = {
 # (flux entries: the variant the autotuner picked in the profiled run -- one face per
 # thread for x1, two faces per thread for x2 and x3)
 FLOPS_PER_UNIT = {
-    "update": 1592.1, "flux1": 1013.0, "flux2": 899.8, "flux3": 828.9, "emf": 9.8,
+    "update": 1592.1, "flux1": 1013.0, "flux2": 899.8, "flux3": 840.7, "emf": 9.8,
     "bcell": 86.2, "dt": 330.0,
 }
-KERNEL_HASH = "9a3024527d9ba8ca"
+KERNEL_HASH = "956701109543ccfe"
 # HBM traffic per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by the reading of
 # the same counters for a 1 GiB device copy: fetch x2, write x1), keyed like
 # FLOPS_PER_UNIT and valid for KERNEL_HASH only.
 TRAFFIC_PER_LAUNCH = {
-    "update": 1.930e9, "flux1": 7.294e8, "flux2": 8.010e8, "flux3": 7.760e8, "emf": 3.782e8,
+    "update": 1.928e9, "flux1": 7.294e8, "flux2": 8.000e8, "flux3": 7.784e8, "emf": 3.782e8,
     "bcell": 3.629e8,
 }
 
