@@ -146,6 +146,30 @@ def train_guess(cfg, state, steps, log):
                   "train_s": time.perf_counter() - t0}
 
 
+def lat_learned_only(args, cfg, state, cells, sync, log):
+    """the headline path alone: batched LAT with the learned guess on the benchmark torus"""
+    from paper_1912_10192_amd import grmhd
+
+    lats = grmhd.lat_levels_by_radius(cfg, [2.4, 4.8, 9.6])
+    nsub = 2 ** max(lats)
+    cycles = max(args.steps // nsub, 1)
+    blob, train = train_guess(cfg, state, args.train_steps, log)
+    g = grmhd.Grid(cfg, blocks=grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=lats),
+                   batched=True, mlp_blob=blob)
+    g.set_state(*state)
+    g.autotune()
+    log(f"[bench] lat_batched_learned only: levels {lats}, timed {cycles} cycles")
+    g.step(1, stats=True)
+    st, wall = timed(g, cycles, sync)
+    print(json.dumps({"metric": METRIC, "unit": "zone-cycles/s", "n_gpus": 1,
+                      "steps": cycles * nsub, "value": st.lat_eff_zone_cycles / wall,
+                      "ms_per_cycle": wall * 1e3 / cycles, "higher_is_better": True,
+                      "dtype": "f64", "data": "synthetic", "learned_training": train,
+                      "config": {"workload": "torus-256x128x128-b32-ppm-hlle",
+                                 "path": "batched LAT + learned guess", "lat_levels": lats,
+                                 "cells": cells}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +178,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=1)
     ap.add_argument("--only-plain", action="store_true")
+    ap.add_argument("--only-lat-learned", action="store_true",
+                    help="only the headline path (batched LAT + learned guess, with its "
+                         "training), for profiling it on its own; no plain path and no roofline")
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates the "
@@ -182,6 +209,10 @@ def main():
     log(f"[bench] building initial state {cfg['n']}")
     state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
     cells = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
+
+    if args.only_lat_learned:
+        lat_learned_only(args, cfg, state, cells, sync, log)
+        return
 
     # ---- plain path: global time step, one launch per kernel and stage, plain guess
     grid = grmhd.Grid(cfg, state=state, profile=True)
