@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "zone-cycles/s on 1 MI355X: batched AMR/LAT + learned con2prim vs plain"
 PEAK = {"hbm": 8.0e12, "alu": 78.6e12}        # B/s; FP64 vector flop/s
 
-# Per-unit algorithmic figures of each kernel class (derivation in the design doc):
+# Per-unit algorithmic figures of each kernel class:
 # bytes = the unique HBM bytes a launch must move per unit (each input read once, each
 # output written once); flops = FP64 flops per unit executed by the kernel, counted with
 # the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters (FMA = 2) on this workload and
