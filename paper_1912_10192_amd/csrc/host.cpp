@@ -985,7 +985,7 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
     const int64_t r = (int64_t)p.max_n[0] * p.max_n[1] * p.max_n[2];
     p.slots = (r + 255) / 256 * nb;
     p.o_dtp = take((size_t)p.slots * 2 * 8);   // two per workgroup for the div B maxima
-    p.o_stp = take((size_t)p.slots * NSTAT * 4);
+    p.o_stp = take((size_t)STAT_COPIES * NSTAT * 8);
   }
   p.total = o;
   return GRMHD_OK;
@@ -1231,8 +1231,7 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   L.ph.maxit = desc->c2p_maxit;
   L.ph.ng = desc->n_ghost;
   L.cnt = (Counters*)(w + p.o_cnt);
-  L.stat_part = (uint32_t*)(w + p.o_stp);
-  L.stat_stride = p.slots;
+  L.stat_acc = (unsigned long long*)(w + p.o_stp);
   L.brick_upd = 1;
   for (const BlockInfo& b : p.info)
     if (!brick_x1(b.n)) L.brick_upd = 0;
@@ -1352,11 +1351,7 @@ static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double
   launch_amr_fix(L, c->links, (int)c->plan.links.size(), c->plan.link_maxpos, c->f, c->e);
   prof_end(c);
   prof_begin(c, KC_UPDATE);
-  const int64_t nrec =
-      launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, dt_part, c->mlp, c->u9);
-  prof_end(c);
-  prof_begin(c, KC_DT);
-  launch_stats_final(L, nrec);
+  launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, dt_part, c->mlp, c->u9);
   prof_end(c);
   if (!c->plan.links.empty()) {
     prof_begin(c, KC_GHOST);
@@ -1404,11 +1399,7 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
     launch_amr_fix(L, c->links + lo, (int)nl, p.link_maxpos, c->f, c->e);
     prof_end(c);
     prof_begin(c, KC_UPDATE);
-    const int64_t nrec =
-        launch_update(L, P, B, Ps, c->bc, c->f, c->e, factor, Pout, c->balt, nullptr, c->mlp, c->u9);
-    prof_end(c);
-    prof_begin(c, KC_DT);
-    launch_stats_final(L, nrec);
+    launch_update(L, P, B, Ps, c->bc, c->f, c->e, factor, Pout, c->balt, nullptr, c->mlp, c->u9);
     prof_end(c);
     if (nl > 0) {
       prof_begin(c, KC_GHOST);
@@ -1499,6 +1490,7 @@ int grmhd_step(grmhd_ctx* c, int32_t n_cycles, grmhd_step_stats* stats) {
     c->b_in_alt = false;
   }
   fill_ghosts(c, P, c->bufs.bface);
+  launch_stats_fold(L);   // the update statistics of every stage of the call
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(c->ev1, c->stream));
   double cls_ms[KC_N] = {};

@@ -127,9 +127,13 @@ enum { WL_BCELL = 0, WL_FLUX1, WL_FLUX2, WL_FLUX3, WL_EMF, WL_CELLS, WL_PAIR1, W
        WL_N };
 constexpr int STAGE_NT = 256;   // threads per workgroup of the stage kernels
 
-// per-workgroup statistics records of the update kernels: inversion tier counts, Newton
-// iteration histogram, floor limits, inversions that used the learned guess
+// statistics of the update kernels: inversion tier counts, Newton iteration histogram,
+// floor limits, inversions that used the learned guess.  Each workgroup adds its nonzero
+// counts into one of STAT_COPIES copies of the accumulators (by workgroup index, so few
+// workgroups meet on one address); launch_stats_fold adds the copies to the counters
+// and clears them.
 enum { ST_TIER = 0, ST_HIST = 5, ST_FLOORS = 69, ST_MLP = 70, NSTAT = 71 };
+constexpr int STAT_COPIES = 64;
 
 // occupancy variants of the flux and update kernels (see kernels.hip)
 constexpr int NVAR_FLUX = GRMHD_NVAR_FLUX, NVAR_UPD = GRMHD_NVAR_UPD;
@@ -153,9 +157,8 @@ struct Launch {
   const int2* wls[WL_N];
   int32_t nwls[WL_N];
   const int2* wl;
-  // statistics records of the update kernels, [NSTAT][stat_stride] (one per workgroup)
-  uint32_t* stat_part;
-  int64_t stat_stride;
+  // statistics accumulators of the update kernels, [STAT_COPIES][NSTAT]
+  unsigned long long* stat_acc;
   // 1: every block divides into update bricks (brick_x1): the fused update runs brick by
   // brick with the column geometry staged in LDS
   int32_t brick_upd;
@@ -184,12 +187,11 @@ void launch_emf(const Launch& L, const double* F, double* E);
 // update of one stage; with dt_part non-null the kernel also writes per-workgroup minima
 // of the next Courant step (reduced by launch_dt_final)
 // (mlp non-null: learned first guess of the inversion from the packed MLP blob)
-// (returns the number of workgroups, whose statistics records launch_stats_final adds to
-// the counters)
+// (returns the number of workgroups)
 int64_t launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
                    const double* Bcs, const double* F, const double* E, double dt_factor,
                    double* Pout, double* Bout, double* dt_part, const void* mlp, double* ubuf);
-void launch_stats_final(const Launch& L, int64_t n);
+void launch_stats_fold(const Launch& L);
 int64_t dt_partials(const Launch& L);
 void launch_dt(const Launch& L, const double* P, const double* B, double* dt_part);
 void launch_dt_final(const Launch& L, const double* dt_part);

@@ -657,10 +657,9 @@ __device__ __forceinline__ void invert_cell(const Launch& L, const BlockInfo& bi
 }
 
 // Statistics of a workgroup (inversion tiers, Newton iteration numbers, floor limits):
-// counted in LDS, then written as one record per workgroup into the launch's partials
-// [NSTAT][slot] with plain stores; k_stats_final adds the records of a launch to the
-// counters.  (Atomics from every wave on the few counter addresses serialise and cost
-// more than the update itself.)
+// counted in LDS, then added per workgroup into one copy of the accumulators (atomics
+// from every wave on the few counter addresses serialise and cost more than the update
+// itself; spread over the copies, a few dozen workgroups meet on one address per launch)
 template <bool STATS, bool NEXT_DT>
 __device__ __forceinline__ void update_epilogue(const Launch& L, const BlockTile& bt, bool valid,
                                                 int tier, int iters, int hits, bool learned,
@@ -680,36 +679,28 @@ __device__ __forceinline__ void update_epilogue(const Launch& L, const BlockTile
     const unsigned long long lm = __ballot(valid && learned);
     if (lane_id() == 0 && lm) atomicAdd(&cnt[ST_MLP], (uint32_t)__popcll(lm));
     __syncthreads();
+    unsigned long long* acc = L.stat_acc + (bt.slot & (STAT_COPIES - 1)) * NSTAT;
     for (int q = threadIdx.x; q < NSTAT; q += NT)
-      L.stat_part[(int64_t)q * L.stat_stride + bt.slot] = cnt[q];
+      if (cnt[q]) atomicAdd(&acc[q], (unsigned long long)cnt[q]);
   }
 }
 
-// the sum over the n workgroup records of one launch: blockIdx.x is the statistic,
-// blockIdx.y one of gridDim.y interleaved shares of the records; one counter add per
-// workgroup with a nonzero share
-__global__ __launch_bounds__(NT) void k_stats_final(Counters* __restrict__ cnt,
-                                                    const uint32_t* __restrict__ part,
-                                                    int64_t stride, int64_t n) {
-  __shared__ long long red[NT / 64];
-  const int q = blockIdx.x;
-  const uint32_t* p = part + (int64_t)q * stride;
-  long long s = 0;
-  for (int64_t i = (int64_t)blockIdx.y * NT + threadIdx.x; i < n; i += (int64_t)NT * gridDim.y)
-    s += p[i];
-  s = wave_sum(s);
-  if (lane_id() == 0) red[threadIdx.x / 64] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    long long t = 0;
-#pragma unroll
-    for (int w = 0; w < NT / 64; w++) t += red[w];
-    unsigned long long* dst = q < ST_HIST     ? &cnt->tier[q - ST_TIER]
-                              : q < ST_FLOORS ? &cnt->hist[q - ST_HIST]
-                              : q == ST_FLOORS ? &cnt->floors
-                                               : &cnt->mlp;
-    if (t) atomicAdd(dst, (unsigned long long)t);
+// the copies of the statistics accumulators added to the counters and cleared: one
+// thread per statistic
+__global__ __launch_bounds__(128) void k_stats_fold(Counters* __restrict__ cnt,
+                                                    unsigned long long* __restrict__ acc) {
+  const int q = threadIdx.x;
+  if (q >= NSTAT) return;
+  unsigned long long t = 0;
+  for (int c = 0; c < STAT_COPIES; c++) {
+    t += acc[c * NSTAT + q];
+    acc[c * NSTAT + q] = 0;
   }
+  unsigned long long* dst = q < ST_HIST     ? &cnt->tier[q - ST_TIER]
+                            : q < ST_FLOORS ? &cnt->hist[q - ST_HIST]
+                            : q == ST_FLOORS ? &cnt->floors
+                                             : &cnt->mlp;
+  *dst += t;
 }
 
 // fused update: conserved update, optional learned guess, inversion, floors, next dt
@@ -863,8 +854,9 @@ __global__ __launch_bounds__(NT) void k_dt_final(Counters* cnt, const double* __
   if (threadIdx.x == 0) cnt->dt_bits = (unsigned long long)__double_as_longlong(r);
 }
 
-__global__ void k_reset(Counters* cnt, int all) {
+__global__ void k_reset(Counters* cnt, unsigned long long* acc, int all) {
   const int t = threadIdx.x;
+  for (int q = t; q < STAT_COPIES * NSTAT; q += blockDim.x) acc[q] = 0;
   if (t < 5) cnt->tier[t] = 0;
   if (t < 64) cnt->hist[t] = 0;
   if (t == 0) {
@@ -1148,9 +1140,8 @@ int64_t dt_partials(const Launch& L) {
   return (int64_t)cdiv(r, NT) * L.nblk;
 }
 
-void launch_stats_final(const Launch& L, int64_t n) {
-  hipLaunchKernelGGL(k_stats_final, dim3(NSTAT, 16), dim3(NT), 0, L.stream, L.cnt, L.stat_part,
-                     L.stat_stride, n);
+void launch_stats_fold(const Launch& L) {
+  hipLaunchKernelGGL(k_stats_fold, dim3(1), dim3(128), 0, L.stream, L.cnt, L.stat_acc);
 }
 
 int64_t launch_update(const Launch& L, const double* Pn, const double* Bn, const double* Ps,
@@ -1218,7 +1209,7 @@ void launch_dt_final(const Launch& L, const double* dt_part) {
 }
 
 void launch_counters_reset(const Launch& L, bool all) {
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, L.stream, L.cnt, all ? 1 : 0);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, L.stream, L.cnt, L.stat_acc, all ? 1 : 0);
 }
 
 void launch_tsim(const Launch& L) {
