@@ -51,12 +51,12 @@ FLOPS_PER_UNIT = {
     "update": 1592.1, "flux1": 1013.0, "flux2": 899.8, "flux3": 840.7, "emf": 9.8,
     "bcell": 86.2, "dt": 330.0,
 }
-KERNEL_HASH = "956701109543ccfe"
+KERNEL_HASH = "4ccf50f64ad8e3e6"
 # HBM traffic per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by the reading of
 # the same counters for a 1 GiB device copy: fetch x2, write x1), keyed like
 # FLOPS_PER_UNIT and valid for KERNEL_HASH only.
 TRAFFIC_PER_LAUNCH = {
-    "update": 1.928e9, "flux1": 7.294e8, "flux2": 8.000e8, "flux3": 7.784e8, "emf": 3.782e8,
+    "update": 1.921e9, "flux1": 7.295e8, "flux2": 7.999e8, "flux3": 7.785e8, "emf": 3.782e8,
     "bcell": 3.629e8,
 }
 
