@@ -179,13 +179,17 @@ def test_autotuned_variants_keep_the_result():
     assert max(e.values()) <= 1e-13, e
 
 
-@pytest.mark.parametrize("case", ["ppm-hlle", "plm-llf", "ppm-polar-smr"])
+@pytest.mark.parametrize("case", ["ppm-hlle", "plm-llf", "ppm-polar-smr", "ppm-odd-blocks"])
 def test_two_faces_per_thread_match_one(case):
     """the flux kernels that take two faces per thread along the normal (reconstruction of
     the shared cells done once) give the one-face kernels' fluxes: two steps agree to
-    rounding, on uniform blocks, with PLM + LLF, and on refined polar bands (blocks of
-    uneven sizes, launched through work lists)"""
-    if case == "ppm-polar-smr":
+    rounding, on uniform blocks, with PLM + LLF, on refined polar bands (blocks of
+    uneven sizes, launched through work lists), and on blocks with an odd number of
+    cells per dimension (every last pair of a line then has both faces)"""
+    if case == "ppm-odd-blocks":
+        cfg = configs.scaled(configs.TORUS_UNIFORM, (30, 18, 14), block=(15, 9, 7))
+        blocks = None
+    elif case == "ppm-polar-smr":
         eff = (32, 64, 32)
         cfg = configs.scaled(configs.TORUS_UNIFORM, eff, ng=3)
         blocks = configs.polar_smr_blocks(eff, 16, [0, 0])
