@@ -179,14 +179,21 @@ def test_autotuned_variants_keep_the_result():
     assert max(e.values()) <= 1e-13, e
 
 
-@pytest.mark.parametrize("case", ["ppm-hlle", "plm-llf", "ppm-polar-smr", "ppm-odd-blocks"])
+@pytest.mark.parametrize("case", ["ppm-hlle", "plm-llf", "ppm-polar-smr", "ppm-odd-blocks",
+                                  "ppm-lat-batched"])
 def test_two_faces_per_thread_match_one(case):
     """the flux kernels that take two faces per thread along the normal (reconstruction of
     the shared cells done once) give the one-face kernels' fluxes: two steps agree to
     rounding, on uniform blocks, with PLM + LLF, on refined polar bands (blocks of
-    uneven sizes, launched through work lists), and on blocks with an odd number of
-    cells per dimension (every last pair of a line then has both faces)"""
-    if case == "ppm-odd-blocks":
+    uneven sizes, launched through work lists), on blocks with an odd number of cells
+    per dimension (every last pair of a line then has both faces), and in graph-captured
+    LAT cycles (the three directions on three streams)"""
+    batched = False
+    if case == "ppm-lat-batched":
+        cfg = configs.scaled(configs.TORUS_UNIFORM, (64, 32, 32), block=(16, 16, 16))
+        blocks = grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=[0, 1, 1, 1])
+        batched = True
+    elif case == "ppm-odd-blocks":
         cfg = configs.scaled(configs.TORUS_UNIFORM, (30, 18, 14), block=(15, 9, 7))
         blocks = None
     elif case == "ppm-polar-smr":
@@ -208,7 +215,7 @@ def test_two_faces_per_thread_match_one(case):
         else:
             ref = AmrGrid(cfg, blocks)
             bs = initdata.block_states(state, ref.blocks, ref.Lmax)
-            grid = grmhd.Grid(cfg, blocks=blocks)
+            grid = grmhd.Grid(cfg, blocks=blocks, batched=batched)
             grid.set_blocks(bs)
             grid.set_variants(flux=flux)
             grid.step(2)
