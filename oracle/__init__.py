@@ -84,7 +84,7 @@ def lib():
         L.orc_step.restype = C.c_double
         L.orc_step.argtypes = [C.c_void_p, _dp, _dp, C.c_int, C.c_double, C.POINTER(Stats)]
         L.orc_divb.restype = C.c_double
-        L.orc_divb.argtypes = [C.c_void_p, _dp, C.c_void_p]
+        L.orc_divb.argtypes = [C.c_void_p, _dp, C.c_void_p, C.c_void_p]
         L.orc_stage_flux.argtypes = [C.c_void_p, _dp, _dp]
         L.orc_stage_apply.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_double, _dp, _dp, C.c_void_p]
         L.orc_flux_buffer.restype = C.POINTER(C.c_double)
@@ -187,8 +187,15 @@ class Grid:
 
     def divb(self, B, field=None):
         if field is None:
-            return self.L.orc_divb(self.ptr, B, None)
-        return self.L.orc_divb(self.ptr, B, field.ctypes.data_as(C.c_void_p))
+            return self.L.orc_divb(self.ptr, B, None, None)
+        return self.L.orc_divb(self.ptr, B, field.ctypes.data_as(C.c_void_p), None)
+
+    def divb_rel(self, B, field=None):
+        """(max |div B|, max |div B| / sum_d (|B_+| + |B_-|)/dx_d) over interior cells"""
+        rel = C.c_double()
+        f = None if field is None else field.ctypes.data_as(C.c_void_p)
+        a = self.L.orc_divb(self.ptr, B, f, C.cast(C.byref(rel), C.c_void_p))
+        return a, rel.value
 
     def last_flux(self):
         n = 27 * self.np[0] * self.np[1] * self.np[2]

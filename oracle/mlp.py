@@ -101,9 +101,12 @@ def loss_and_grads(params, x, y, mode="f64"):
         W = params[2 * l]
         h = acts[l]
         if mode == "bf16":
-            grads[2 * l] = bf16(h).astype(np.float32).T @ g
+            # every product of the network takes bfloat16 operands (FP32 sums): the
+            # backward signal g is rounded like the activations and weights
+            gb = bf16(g).astype(np.float32)
+            grads[2 * l] = bf16(h).astype(np.float32).T @ gb
             grads[2 * l + 1] = g.sum(axis=0)
-            gh = g @ bf16(W).astype(np.float32).T
+            gh = gb @ bf16(W).astype(np.float32).T
         else:
             grads[2 * l] = h.T @ g
             grads[2 * l + 1] = g.sum(axis=0)

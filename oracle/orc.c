@@ -502,6 +502,24 @@ static int c2p_entropy(const c2p_in* s, double* P) {
   return 0;
 }
 
+/* How far a start (the (W, v^2) of primitives G) is from solving the two equations:
+ * |R1| / (B^2 + W)^2 + |R2| / W, each residual divided by the scale of its equation
+ * (infinite outside W > 0, 0 <= v^2 < 1).  Of two distinct starts, Newton goes first from
+ * the one with the smaller value. */
+static double c2p_start_misfit(const c2p_in* s, const double* gcov, const double* G) {
+  double qsq = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) qsq += gcov[(i + 1) * 4 + j + 1] * G[U1 + i] * G[U1 + j];
+  double gsq = 1.0 + qsq;
+  double W = (G[RHO] + s->gam * G[UU]) * gsq;
+  double vsq = qsq / gsq;
+  if (!(W > 0.0) || !(vsq >= 0.0) || !(vsq < 1.0)) return INFINITY;
+  double R1, R2;
+  c2p_residual(s, W, vsq, &R1, &R2);
+  double BW = s->Bsq + W;
+  return fabs(R1) / (BW * BW) + fabs(R2) / W;
+}
+
 int orc_cons2prim(const double* U, const double* gcov, const double* gcon, double gdet,
                   double alpha, double gam, const double* guess, const double* prev,
                   double tol, int maxit, double* P, int* iters) {
@@ -509,13 +527,20 @@ int orc_cons2prim(const double* U, const double* gcov, const double* gcon, doubl
   c2p_setup(U, gcov, gcon, gdet, alpha, gam, &s);
   double Pt[5];
   int it = 0;
-  if (c2p_newton(&s, gcov, guess, tol, maxit, Pt, &it) == 0) {
+  const int two = guess != prev && memcmp(guess, prev, 5 * sizeof(double)) != 0;
+  const double* first = guess;
+  const double* second = prev;
+  if (two && c2p_start_misfit(&s, gcov, prev) < c2p_start_misfit(&s, gcov, guess)) {
+    first = prev;
+    second = guess;
+  }
+  if (c2p_newton(&s, gcov, first, tol, maxit, Pt, &it) == 0) {
     memcpy(P, Pt, sizeof(Pt));
     *iters = it;
     return 0;
   }
-  if (guess != prev && memcmp(guess, prev, 5 * sizeof(double)) != 0) {
-    if (c2p_newton(&s, gcov, prev, tol, maxit, Pt, &it) == 0) {
+  if (two) {
+    if (c2p_newton(&s, gcov, second, tol, maxit, Pt, &it) == 0) {
       memcpy(P, Pt, sizeof(Pt));
       *iters = it;
       return 1;
@@ -1010,20 +1035,27 @@ double orc_step(orc_ctx* c, double* P, double* B, int nsteps, double dt_fixed, o
   return dt;
 }
 
-double orc_divb(orc_ctx* c, const double* B, double* field) {
+double orc_divb(orc_ctx* c, const double* B, double* field, double* max_rel) {
   const int g = c->d.ng, n1 = c->d.n[0], n2 = c->d.n[1], n3 = c->d.n[2];
   const size_t nc = c->ncell;
-  double mx = 0.0;
+  double mx = 0.0, mr = 0.0;
   for (int K = g; K < g + n3; K++)
     for (int J = g; J < g + n2; J++)
       for (int I = g; I < g + n1; I++) {
         size_t id = IDX(c, K, J, I);
-        double dv = (B[IDX(c, K, J, I + 1)] - B[id]) / c->dx[0]
-                    + (B[nc + IDX(c, K, J + 1, I)] - B[nc + id]) / c->dx[1]
-                    + (B[2 * nc + IDX(c, K + 1, J, I)] - B[2 * nc + id]) / c->dx[2];
+        double b1p = B[IDX(c, K, J, I + 1)], b1m = B[id];
+        double b2p = B[nc + IDX(c, K, J + 1, I)], b2m = B[nc + id];
+        double b3p = B[2 * nc + IDX(c, K + 1, J, I)], b3m = B[2 * nc + id];
+        double dv = (b1p - b1m) / c->dx[0] + (b2p - b2m) / c->dx[1] + (b3p - b3m) / c->dx[2];
+        /* the same sum with every term taken by magnitude: the scale the differences
+         * cancel against */
+        double scale = (fabs(b1p) + fabs(b1m)) / c->dx[0] + (fabs(b2p) + fabs(b2m)) / c->dx[1]
+                       + (fabs(b3p) + fabs(b3m)) / c->dx[2];
         if (field) field[id] = dv;
         if (fabs(dv) > mx) mx = fabs(dv);
+        if (scale > 0.0 && fabs(dv) / scale > mr) mr = fabs(dv) / scale;
       }
+  if (max_rel) *max_rel = mr;
   return mx;
 }
 

@@ -110,7 +110,7 @@ double* orc_emf_buffer(orc_ctx* c);
 double orc_step(orc_ctx* c, double* P, double* B, int nsteps, double dt_fixed, orc_stats* st);
 /* discrete div of the face field per interior cell (field may be NULL);
  * returns max |div| */
-double orc_divb(orc_ctx* c, const double* B, double* field);
+double orc_divb(orc_ctx* c, const double* B, double* field, double* max_rel);
 /* copy of the oracle's face fluxes of the last stage: [3][9][NP3][NP2][NP1] */
 const double* orc_last_flux(const orc_ctx* c);
 /* edge EMFs of the last stage: [3][NP3][NP2][NP1] (E1 at (i, j-1/2, k-1/2), ...) */

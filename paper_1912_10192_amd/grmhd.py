@@ -406,6 +406,16 @@ class Grid:
         _check(lib().grmhd_divb(self.ctx, C.byref(a), C.byref(r), None))
         return a.value, r.value
 
+    def divb_field(self):
+        """(max |div B|, its relative form, the per-cell values as a global interior
+        array [n3][n2][n1])"""
+        a, r = C.c_double(), C.c_double()
+        field = self.torch.zeros_like(self.prim)
+        _check(lib().grmhd_divb(self.ctx, C.byref(a), C.byref(r), C.c_void_p(field.data_ptr())))
+        self.torch.cuda.synchronize(self.device)
+        P, _, _, _ = gather(self.desc, field.cpu().numpy(), np.zeros(self.bface.numel()))
+        return a.value, r.value, P[0]
+
 
 def cons2prim_batch(U, geom, guess, prev, gam, tol=1e-12, maxit=50, mlp_blob=None):
     """flat-batch inversion on the GPU; all inputs float64 CUDA tensors [k][n]; with

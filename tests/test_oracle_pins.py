@@ -332,3 +332,23 @@ def test_entropy_backup_recovers_from_entropy():
         assert tier in (2, 3, 4)
         assert np.all(np.isfinite(Pr))
     assert got > 10
+
+
+def test_two_starts_newton_goes_first_from_the_smaller_misfit():
+    """with two distinct starts the one whose (W, v^2) leaves the smaller scaled residual
+    goes first: the exact state beats one with rho and u 1000 times too large in either
+    argument order (Newton from it converges at once, tier 0), while the far start alone
+    cannot converge in the same two iterations"""
+    rng = np.random.default_rng(8)
+    gam = 4.0 / 3.0
+    for _ in range(50):
+        P, B, gcov, gcon, gdet, alpha = _c2p_sample(rng, KS, gam)
+        U = oracle.prim_to_flux(P, B, gcov, gcon, gdet, alpha, gam, 0)
+        far = P.copy()
+        far[:2] *= 1000.0
+        for g0, p0 in ((P, far), (far, P)):
+            Pr, tier, it = oracle.cons2prim(U, gcov, gcon, gdet, alpha, gam, g0, p0, 1e-12, 2)
+            assert tier == 0 and it <= 2
+            assert Pr[0] == pytest.approx(P[0], rel=1e-9)
+        _, tier, _ = oracle.cons2prim(U, gcov, gcon, gdet, alpha, gam, far, far, 1e-12, 2)
+        assert tier != 0
