@@ -67,7 +67,8 @@ def test_forward_and_gradients_match_bf16_oracle():
 def test_adam_steps_match_oracle():
     """three training steps on the device (gradients, then the Adam update of the FP32
     masters) against the oracle's Adam applied to the same gradients in FP64: parameters
-    and both moment estimates agree to FP32 rounding"""
+    and both moment estimates agree to FP32 rounding (beta2 = 0.999 held in FP32 makes
+    1 - beta2 larger by 1.3e-5 relative, which the second moment carries)"""
     torch = _torch()
     dev = torch.device("cuda")
     rng = np.random.default_rng(1)
@@ -93,7 +94,7 @@ def test_adam_steps_match_oracle():
         for a, b in zip(m, state[1]):
             assert np.abs(a - b).max() <= 1e-6 * max(np.abs(b).max(), 1e-30), step
         for a, b in zip(v, state[2]):
-            assert np.abs(a - b).max() <= 1e-5 * max(np.abs(b).max(), 1e-30), step
+            assert np.abs(a - b).max() <= 5e-5 * max(np.abs(b).max(), 1e-30), step
 
 
 def test_device_dataset_matches_oracle_features():
