@@ -24,17 +24,29 @@ counted in cells of its own level.  Rules, with the readings stated in the desig
         the two prolonged values on the coarse faces bounding that cell;
       - the physical boundaries are then applied to the view at that level;
       - a face shared by several blocks takes the value of the viewing block if it owns
-        one, else of the finest block, then the block at the viewing time level, then
-        the block listed last.
-  * Blocks across a refinement face run at the same time level.  In each stage, after
-    all fluxes and EMFs are computed and before any update, the coarse block's fluxes on
-    faces shared with finer blocks are replaced by the area mean of the fine fluxes, and
-    its EMFs on edges of those faces by the mean of the fine EMFs along the coarse edge.
-    After the update, the coarse copy of each shared face takes the mean of the fine
-    faces (the finer side owns shared faces).
-  * Time-level interfaces lie on x1 faces between blocks of one refinement level and
-    are treated as in the local time-stepping driver (registers, refluxing, EMF and face
-    correction, re-inversion).
+        one, else of a block at the viewing time level, then of the finest block, then of
+        the block listed last (so that blocks of one time level, which evolve such a face
+        side by side, read the same copy of it in every stage).
+  * Time levels are independent of refinement levels and of the direction of a face
+    (Sec. 3.5).  Every face and every edge shared by blocks has a dominant holder: the
+    fastest holder, among those the finest, among those the lowest block index (holders
+    of one time and refinement level compute the same values).  An edge counts as held by
+    a block only where it lies on the block's own edge lattice (an edge of fine cells in
+    the middle of a coarse face is not an edge of the coarse block).
+  * Same time level: in each stage, after all fluxes and EMFs of the level are computed
+    and before any update, the coarse block's fluxes on faces shared with finer blocks
+    are replaced by the area mean of the fine fluxes, and every EMF of a block whose
+    dominant holder is finer (at the same time level) by the dominant's EMF (the mean of
+    its two sub-edges where it is finer along the edge).  After the update, the coarse
+    copy of each shared face takes the mean of the fine faces.
+  * Faster holder: at the end of the slower block's step (Sec. 3.5 flux correction, Sec.
+    3.3 refluxing) its face fluxes on faces shared with the faster block are replaced by
+    the faster side's time integral over its two steps (area-averaged where the faster
+    side is finer; the coarse density itself where it is coarser), its EMFs on edges
+    whose dominant holder is faster by the dominant's time integral, the faces of the
+    slower block around those edges are corrected by constrained transport, shared faces
+    take the faster copy (the mean of its sub-faces where it is finer; none where it is
+    coarser), and every cell whose conserved state or faces changed is inverted again.
 """
 from __future__ import annotations
 
@@ -97,8 +109,9 @@ class AmrGrid(LatGrid):
         self.dt_min = 0.0
         self.steps = [0] * self.L
         self.trace = []
-        self.xnb = [self._x1_neighbours(i) for i in range(len(self.blocks))]
         self.links = self._refinement_faces()
+        self.owner = self._owner_map()
+        self._sync_tables()
 
     # ------------------------------------------------------------------ layout
     def nlev(self, lam):
@@ -115,22 +128,6 @@ class AmrGrid(LatGrid):
             for i in range(n1):
                 x1 = self.cfg["xlo"][0] + (b["org"][0] + i + 0.5) * dxl[0]
                 out[j, i] = oracle.geom_point(self.cfg, x1, x2)[2]
-        return out
-
-    def _x1_neighbours(self, i):
-        b = self.blocks[i]
-        N1 = self.nlev(b["lev"])[0]
-        periodic = self.cfg["bc"][0] == oracle.BC_PERIODIC
-        out = {}
-        for j, c in enumerate(self.blocks):
-            if c["lev"] != b["lev"] or c["org"][1:] != b["org"][1:] or c["n"][1:] != b["n"][1:]:
-                continue
-            if c["org"][0] + c["n"][0] == b["org"][0] or (
-                    periodic and b["org"][0] == 0 and c["org"][0] + c["n"][0] == N1):
-                out["lo"] = j
-            if b["org"][0] + b["n"][0] == c["org"][0] or (
-                    periodic and c["org"][0] == 0 and b["org"][0] + b["n"][0] == N1):
-                out["hi"] = j
         return out
 
     def _refinement_faces(self):
@@ -159,10 +156,146 @@ class AmrGrid(LatGrid):
                     lo = tuple(max(lo_f[x], lo_c[x]) for x in range(3))
                     hi = tuple(min(hi_f[x], hi_c[x]) for x in range(3))
                     for side, hit in ((0, below), (1, above)):
-                        if hit:
-                            assert bc["lat"] == bf["lat"], "refinement faces join one time level"
+                        if hit and bc["lat"] == bf["lat"]:
                             out.append((c, f, d, side, e, lo, hi))
         return out
+
+    def _owner_map(self):
+        """block id of every cell of the effective grid"""
+        N = self.N
+        own = np.full((N[2], N[1], N[0]), -1, dtype=np.int64)
+        for i, b in enumerate(self.blocks):
+            s = [self.Lmax[d] - b["lev"][d] for d in range(3)]
+            o, n = b["org"], b["n"]
+            own[o[2] << s[2]:(o[2] + n[2]) << s[2], o[1] << s[1]:(o[1] + n[1]) << s[1],
+                o[0] << s[0]:(o[0] + n[0]) << s[0]] = i
+        return own
+
+    def _owner(self, lam, idx):
+        """the block holding cell idx (i, j, k) of the grid at levels lam; positions
+        outside the grid wrap across periodic boundaries, else None (outflow, polar)"""
+        N = self.nlev(lam)
+        x = list(idx)
+        for d in range(3):
+            if 0 <= x[d] < N[d]:
+                continue
+            if self.cfg["bc"][2 * d] != oracle.BC_PERIODIC:
+                return None
+            x[d] %= N[d]
+        s = [self.Lmax[d] - lam[d] for d in range(3)]
+        h = int(self.owner[x[2] << s[2], x[1] << s[1], x[0] << s[0]])
+        return h if h >= 0 else None
+
+    def _local(self, D, lam, pos, kind, a=None):
+        """padded local indices in block D of an element at positions pos (per dimension,
+        in cells/nodes of levels lam): kind 'cell' index per dimension, 'face' normal
+        dimension a (a node along a), 'edge' along a (a cell along a, nodes otherwise).
+        Returns the list of D's elements covering it (several where D is finer, their
+        values to be averaged), each as (K, J, I)."""
+        g = self.g
+        bD = self.blocks[D]
+        ranges = []
+        for d in range(3):
+            diff = bD["lev"][d] - lam[d]
+            node = (kind == "face" and d == a) or (kind == "edge" and d != a)
+            if node:
+                if diff >= 0:
+                    vals = [pos[d] << diff]
+                else:
+                    assert pos[d] % 2 == 0, "a node off the coarser lattice"
+                    vals = [pos[d] >> 1]
+            else:
+                vals = [(pos[d] << 1) + q for q in range(2)] if diff > 0 else [pos[d] >> (-diff)]
+            Nd = self.nlev(bD["lev"])[d]
+            per = self.cfg["bc"][2 * d] == oracle.BC_PERIODIC
+            out = []
+            for v in vals:
+                hi = bD["org"][d] + bD["n"][d] + (1 if node else 0)
+                cands = [v, v - Nd, v + Nd] if per else [v]
+                got = [w for w in cands if bD["org"][d] <= w < hi]
+                assert got, "element outside its holder"
+                out.append(got[0] - bD["org"][d] + g)
+            ranges.append(out)
+        return [(k, j, i) for k in ranges[2] for j in ranges[1] for i in ranges[0]]
+
+    def _dominant(self, hs):
+        """fastest, then finest, then lowest index"""
+        return min(hs, key=lambda h: (self.blocks[h]["lat"], -sum(self.blocks[h]["lev"]), h))
+
+    def _sync_tables(self):
+        """Per block: the faces of its boundary shared with a faster block (reflux and
+        face copy); the edges of its boundary whose finest holder at its own time level is
+        finer than it (EMF replaced in each stage), and those whose dominant holder is
+        faster (time-integrated EMF replaced at the end of its step)."""
+        g = self.g
+        nb = len(self.blocks)
+        self.reflux = [[] for _ in range(nb)]     # (d, side, face (K,J,I), D, D faces)
+        self.sync_edges = [[] for _ in range(nb)]  # (a, edge (K,J,I), D, D edges)
+        self.stage_edges = [[] for _ in range(nb)]
+        for b, bb in enumerate(self.blocks):
+            lam, o, n = bb["lev"], bb["org"], bb["n"]
+            N = self.nlev(lam)
+            polar = self.cfg["bc"][2] == oracle.BC_POLAR
+            for d in range(3):
+                t = [x for x in range(3) if x != d]
+                for side in (0, 1):
+                    p = o[d] + (n[d] if side else 0)
+                    if d == 1 and polar and (p == 0 or p == N[1]):
+                        continue                     # the polar axis carries no flux
+                    for c1 in range(o[t[1]], o[t[1]] + n[t[1]]):
+                        for c0 in range(o[t[0]], o[t[0]] + n[t[0]]):
+                            cell = [0, 0, 0]
+                            cell[d] = p if side else p - 1
+                            cell[t[0]], cell[t[1]] = c0, c1
+                            D = self._owner(lam, cell)
+                            if D is None or self.blocks[D]["lat"] >= bb["lat"]:
+                                continue
+                            pos = list(cell)
+                            pos[d] = p
+                            mine = self._local(b, lam, pos, "face", d)[0]
+                            self.reflux[b].append((d, side, mine, D,
+                                                   self._local(D, lam, pos, "face", d)))
+            for a in range(3):
+                t = [x for x in range(3) if x != a]
+                for x1 in range(o[t[1]], o[t[1]] + n[t[1]] + 1):
+                    for x0 in range(o[t[0]], o[t[0]] + n[t[0]] + 1):
+                        on0 = x0 in (o[t[0]], o[t[0]] + n[t[0]])
+                        on1 = x1 in (o[t[1]], o[t[1]] + n[t[1]])
+                        if not (on0 or on1):
+                            continue
+                        if polar and 1 in t and (x0 if t[0] == 1 else x1) in (0, N[1]):
+                            continue                 # on the axis: E1 = E3 = 0
+                        for ca in range(o[a], o[a] + n[a]):
+                            hs = set()
+                            for q0 in (x0 - 1, x0):
+                                for q1 in (x1 - 1, x1):
+                                    cell = [0, 0, 0]
+                                    cell[a], cell[t[0]], cell[t[1]] = ca, q0, q1
+                                    h = self._owner(lam, cell)
+                                    if h is None:
+                                        continue
+                                    hl = self.blocks[h]["lev"]
+                                    if any(hl[e] < lam[e] and (x0 if e == t[0] else x1) % 2
+                                           for e in t):
+                                        continue     # not on the holder's edge lattice
+                                    hs.add(h)
+                            if not hs:
+                                continue
+                            pos = [0, 0, 0]
+                            pos[a], pos[t[0]], pos[t[1]] = ca, x0, x1
+                            mine = self._local(b, lam, pos, "edge", a)[0]
+                            # in each stage the holders at this time level agree on the
+                            # finest one's value; at the end of the step the faster
+                            # dominant's time integral replaces it
+                            same = [h for h in hs if self.blocks[h]["lat"] == bb["lat"]]
+                            D = self._dominant(same)
+                            if D != b and self.blocks[D]["lev"] != lam:
+                                self.stage_edges[b].append(
+                                    (a, mine, D, self._local(D, lam, pos, "edge", a)))
+                            D = self._dominant(hs)
+                            if self.blocks[D]["lat"] < bb["lat"]:
+                                self.sync_edges[b].append(
+                                    (a, mine, D, self._local(D, lam, pos, "edge", a)))
 
     def _vg(self, lam):
         if lam not in self.vgrid:
@@ -312,7 +445,7 @@ class AmrGrid(LatGrid):
         GB[:] = np.nan
         li = self.blocks[i]["lat"]
         order = sorted((n for n in range(len(self.blocks)) if n != i),
-                       key=lambda n: (sum(self.blocks[n]["lev"]), self.blocks[n]["lat"] == li, n)) + [i]
+                       key=lambda n: (self.blocks[n]["lat"] == li, sum(self.blocks[n]["lev"]), n)) + [i]
         for n in order:
             rel = tuple(self.blocks[n]["lev"][d] - lam[d] for d in range(3))
             if max(abs(x) for x in rel) > 1 or (max(rel) > 0 and min(rel) < 0):
@@ -326,9 +459,42 @@ class AmrGrid(LatGrid):
                 self._put_same(GP, GB, n, Pn, Bn)
             else:
                 self._put_restrict(GP, GB, n, Pn, Bn, rel)
+        self._seams(GB, lam, i)
         G.fill_bc(GP, GB)
         cache[lam] = (GP, GB)
         return GP, GB
+
+    def _seams(self, GB, lam, i):
+        """A face on a periodic seam is stored twice in a view (as the upper face of the
+        last cell and the lower face of the first); both copies take the value of the
+        holder the face rule picks (the viewing block, else one at the viewing time level,
+        then the finest, then the higher block index)."""
+        g = self.g
+        N = self.nlev(lam)
+        li = self.blocks[i]["lat"]
+
+        def rank(n):
+            bn = self.blocks[n]
+            return (n == i, bn["lat"] == li, sum(bn["lev"]), n)
+
+        for d in range(3):
+            if self.cfg["bc"][2 * d] != oracle.BC_PERIODIC:
+                continue
+            t = [x for x in range(3) if x != d]
+            for c1 in range(N[t[1]]):
+                for c0 in range(N[t[0]]):
+                    lo = [0, 0, 0]
+                    lo[t[0]], lo[t[1]] = c0, c1
+                    hi = list(lo)
+                    hi[d] = N[d] - 1
+                    w0, w1 = self._owner(lam, lo), self._owner(lam, hi)
+                    if w0 is None or w1 is None or w0 == w1:
+                        continue
+                    p0 = [g + x for x in lo]
+                    p1 = list(p0)
+                    p1[d] = g + N[d]
+                    a, b = (p0, p1) if rank(w0) >= rank(w1) else (p1, p0)
+                    GB[d, b[2], b[1], b[0]] = GB[d, a[2], a[1], a[0]]
 
     def patch(self, i, stage, s):
         GP, GB = self._view(self.blocks[i]["lev"], i, stage, s, {})
@@ -349,7 +515,8 @@ class AmrGrid(LatGrid):
         return Ic, If
 
     def _fix_fluxes(self, ids):
-        """coarse fluxes and EMFs on refinement faces <- means of the fine ones"""
+        """coarse fluxes on refinement faces <- means of the fine ones; EMFs <- their
+        dominant holder's at this time level"""
         g = self.g
         for link in self.links:
             c, f, d, side, e, lo, hi = link
@@ -378,23 +545,15 @@ class AmrGrid(LatGrid):
                     acc = acc + Ff[d, :, pf[2], pf[1], pf[0]]
                     cnt += 1
                 Fc[d, :, pc[2], pc[1], pc[0]] = acc * (1.0 / cnt)
-            # edges along a (a != d) at face positions along b = the third dimension
-            for a in t:
-                b = [x for x in t if x != a][0]
-                for ca in range(lo[a], hi[a]):
-                    for cb in range(lo[b], hi[b] + 1):
-                        pc = [0, 0, 0]
-                        pc[d], pc[a], pc[b] = Ic, g + ca - oc[a], g + cb - oc[b]
-                        acc = 0.0
-                        cnt = 0
-                        for oa in range(1 + e[a]):
-                            pf = [0, 0, 0]
-                            pf[d] = If
-                            pf[a] = g + (ca << e[a]) + oa - of[a]
-                            pf[b] = g + (cb << e[b]) - of[b]
-                            acc = acc + Ef[a, pf[2], pf[1], pf[0]]
-                            cnt += 1
-                        Ec[a, pc[2], pc[1], pc[0]] = acc * (1.0 / cnt)
+        # EMFs whose dominant holder is finer at this time level
+        for b in ids:
+            Eb = self.ctx[b].emf_view()
+            for a, e, D, subs in self.stage_edges[b]:
+                ED = self.ctx[D].emf_view()
+                acc = 0.0
+                for (K, J, I) in subs:
+                    acc = acc + ED[a, K, J, I]
+                Eb[a, e[0], e[1], e[2]] = acc * (1.0 / len(subs))
 
     def _sync_faces(self, ids, Bout):
         """coarse copies of refinement faces <- mean of the fine faces"""
@@ -459,6 +618,98 @@ class AmrGrid(LatGrid):
             self.P[i], self.B[i] = newP[i], newB[i]
         self._sync_faces(ids, self.B)
         self.steps[lev] += 1
+
+    # ------------------------------------------------------------------ time levels
+    def _registers(self, i, dt, s):
+        """dt-weighted corrector fluxes and EMFs of block i (after the same-level fixes):
+        this step, and the sum over the pair of steps a slower neighbour spans"""
+        lat = self.blocks[i]["lat"]
+        F = dt * self.ctx[i].last_flux()
+        E = dt * self.ctx[i].last_emf()
+        self.reg_step[i] = {"F": F, "E": E}
+        if s % (2 ** (lat + 1)) == 0 or not self.reg_pair[i]:
+            self.reg_pair[i] = {"F": F.copy(), "E": E.copy()}
+        else:
+            self.reg_pair[i]["F"] += F
+            self.reg_pair[i]["E"] += E
+
+    def _sync_block(self, b):
+        """end of block b's step: refluxing, EMF correction, shared faces, re-inversion"""
+        g = self.g
+        n = self.blocks[b]["n"]
+        lam = self.blocks[b]["lev"]
+        dx = self.bdx[b]
+        mine = self.reg_step[b]
+        dU = {}
+        touched = set()
+        Bnew = self.B[b].copy()
+        for d, side, f, D, subs in self.reflux[b]:
+            theirs = 0.0
+            for (K, J, I) in subs:
+                theirs = theirs + self.reg_pair[D]["F"][d, :, K, J, I]
+            theirs = theirs * (1.0 / len(subs))
+            cell = list(f)
+            if side == 1:
+                cell[2 - d] -= 1
+            cell = tuple(cell)
+            sgn = 1.0 if side == 1 else -1.0
+            dU[cell] = dU.get(cell, 0.0) + (mine["F"][d, :, f[0], f[1], f[2]] - theirs) / dx[d] * sgn
+
+        def owned_face(c, loc):
+            x = (loc[2], loc[1], loc[0])
+            return all(g <= x[e] <= g + n[e] - (0 if e == c else 1) for e in range(3))
+
+        for a, e, D, subs in self.sync_edges[b]:
+            theirs = 0.0
+            for (K, J, I) in subs:
+                theirs = theirs + self.reg_pair[D]["E"][a, K, J, I]
+            theirs = theirs * (1.0 / len(subs))
+            dE = theirs - mine["E"][a, e[0], e[1], e[2]]
+            x = [e[2], e[1], e[0]]
+            for p in range(3):
+                if p == a:
+                    continue
+                q = 3 - a - p
+                sign = 1.0 if a == (p + 1) % 3 else -1.0
+                for tq, sq in ((x[q] - 1, 1.0), (x[q], -1.0)):
+                    fx = list(x)
+                    fx[q] = tq
+                    loc = (fx[2], fx[1], fx[0])
+                    if not owned_face(p, loc):
+                        continue
+                    Bnew[p, loc[0], loc[1], loc[2]] += sign * sq * dE / dx[q]
+                    for cp in (fx[p] - 1, fx[p]):
+                        if g <= cp < g + n[p]:
+                            cx = list(fx)
+                            cx[p] = cp
+                            touched.add((cx[2], cx[1], cx[0]))
+        for d, side, f, D, subs in self.reflux[b]:
+            if any(self.blocks[D]["lev"][x] < lam[x] for x in range(3)):
+                continue            # the faster side is coarser: its face covers several
+            acc = 0.0
+            for (K, J, I) in subs:
+                acc = acc + self.B[D][d, K, J, I]
+            Bnew[d, f[0], f[1], f[2]] = acc * (1.0 / len(subs))
+            for cp in (f[2 - d] - 1, f[2 - d]):
+                if g <= cp < g + n[d]:
+                    cx = list(f)
+                    cx[2 - d] = cp
+                    touched.add(tuple(cx))
+        zero = np.zeros(9)
+        for cell in sorted(set(dU) | touched):
+            self.ctx[b].reinvert(self.P[b], self.B[b], Bnew, cell[0], cell[1], cell[2],
+                                 dU.get(cell, zero))
+        self.B[b] = Bnew
+
+    def sync(self, s):
+        for i, b in enumerate(self.blocks):
+            lat = b["lat"]
+            if lat == 0 or (s + 1) % (2 ** lat) != 0:
+                continue
+            if not self.reflux[i] and not self.sync_edges[i]:
+                continue
+            self.trace.append((s, 1, lat, i))
+            self._sync_block(i)
 
     def divb(self):
         """max |div B| over the interior cells of all blocks (each with its own spacing)"""

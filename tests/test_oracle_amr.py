@@ -157,9 +157,10 @@ def test_uniform_state_stays_uniform_across_refinement():
         assert np.abs(b3 - 0.2).max() <= 1e-15
 
 
-def _wave_bands(N):
-    """fast wave along x2 through two refinement jumps (coarse-fine-coarse, periodic);
-    one period; L1 error of the primitives over all blocks"""
+def _wave_bands(N, lats=(0, 0, 0)):
+    """fast wave along x2 through two refinement jumps (coarse-fine-coarse, periodic),
+    the three bands at time levels lats; one period; L1 error of the primitives over all
+    blocks"""
     from tests.test_oracle_grid import _eigen
     gam = 4.0 / 3.0
     P0 = np.array([1.0, 1.0, 0.0, 0.0, 0.0])
@@ -169,9 +170,9 @@ def _wave_bands(N):
     r = R[:, 6] / np.abs(R[:, 6]).max()
     n = (4, N, 4)
     cfg = mink_cfg(n, recon=1, riemann=1, L=(4.0 / N, 1.0, 4.0 / N))
-    blocks = [dict(org=(0, 0, 0), n=(2, N // 8, 2), lev=(0, 1, 0), lat=0),
-              dict(org=(0, N // 4, 0), n=(4, N // 2, 4), lev=(1, 2, 1), lat=0),
-              dict(org=(0, 3 * N // 8, 0), n=(2, N // 8, 2), lev=(0, 1, 0), lat=0)]
+    blocks = [dict(org=(0, 0, 0), n=(2, N // 8, 2), lev=(0, 1, 0), lat=lats[0]),
+              dict(org=(0, N // 4, 0), n=(4, N // 2, 4), lev=(1, 2, 1), lat=lats[1]),
+              dict(org=(0, 3 * N // 8, 0), n=(2, N // 8, 2), lev=(0, 1, 0), lat=lats[2])]
     y = (np.arange(N) + 0.5) / N
     yf = np.arange(N + 1) / N
     prof = np.cos(2 * np.pi * y)[None, :, None] * np.ones((4, 1, 4))
@@ -199,11 +200,17 @@ def _wave_bands(N):
     return err
 
 
-def test_wave_through_refinement_jumps_second_order():
-    e1 = _wave_bands(32)
-    e2 = _wave_bands(64)
+@pytest.mark.parametrize("lats,bar", [((0, 0, 0), 1.8), ((1, 0, 1), 1.7), ((0, 1, 0), 1.7)])
+def test_wave_through_refinement_jumps_second_order(lats, bar):
+    """second order through refinement faces at one time level, and close to it through
+    refinement faces that are also time-level interfaces (the fine band faster, or
+    slower): there the slower side's corrector reads the faster side at its start time,
+    an O(dt) error confined to the interface layers; measured orders 1.74 and 1.80 (fine
+    band faster, N = 32/64/128), 1.83 and 1.76 (fine band slower)"""
+    e1 = _wave_bands(32, lats)
+    e2 = _wave_bands(64, lats)
     order = math.log2(e1 / e2)
-    assert order > 1.8, (e1, e2, order)
+    assert order > bar, (e1, e2, order)
 
 
 def test_torus_polar_bands_run_and_keep_divb():
@@ -222,3 +229,93 @@ def test_torus_polar_bands_run_and_keep_divb():
     for Pi, *_ in g.get_blocks():
         assert np.isfinite(Pi).all()
     assert g.divb() <= 1e-12 * scale
+
+
+# ---------------------------------------------------------------- time levels on any face
+
+def shared_face_mismatch(g):
+    """largest difference, over every face shared by two blocks, between the two blocks'
+    copies of it: equal copies for blocks of one refinement level, the coarse copy
+    against the mean of the fine sub-faces otherwise (relative to the largest |B|)"""
+    worst = 0.0
+    scale = max(np.abs(B).max() for B in g.B)
+    for b, bb in enumerate(g.blocks):
+        lam, o, n = bb["lev"], bb["org"], bb["n"]
+        for d in range(3):
+            t = [x for x in range(3) if x != d]
+            for side in (0, 1):
+                p = o[d] + (n[d] if side else 0)
+                for c1 in range(o[t[1]], o[t[1]] + n[t[1]]):
+                    for c0 in range(o[t[0]], o[t[0]] + n[t[0]]):
+                        cell = [0, 0, 0]
+                        cell[d] = p if side else p - 1
+                        cell[t[0]], cell[t[1]] = c0, c1
+                        D = g._owner(lam, cell)
+                        if D is None or D == b:
+                            continue
+                        if any(g.blocks[D]["lev"][x] < lam[x] for x in range(3)):
+                            continue
+                        pos = list(cell)
+                        pos[d] = p
+                        K, J, I = g._local(b, lam, pos, "face", d)[0]
+                        subs = g._local(D, lam, pos, "face", d)
+                        other = np.mean([g.B[D][d, k, j, i] for (k, j, i) in subs])
+                        worst = max(worst, abs(g.B[b][d, K, J, I] - other) / scale)
+    return worst
+
+
+def checker_blocks(nx, nb, lats):
+    """nb[0] x nb[1] x nb[2] equal blocks of a periodic box; lats(i, j, k) per block"""
+    n = [nx[d] // nb[d] for d in range(3)]
+    return [dict(org=(i * n[0], j * n[1], k * n[2]), n=tuple(n), lev=(0, 0, 0), lat=lats(i, j, k))
+            for k in range(nb[2]) for j in range(nb[1]) for i in range(nb[0])]
+
+
+def _check_conservation(cfg, blocks, cycles=2, dx=None):
+    g = AmrGrid(cfg, blocks)
+    state = random_periodic_state(cfg["n"], seed=3, amp=0.05, vamp=0.2, bamp=0.2, dx=dx)
+    g.set_blocks(initdata.block_states(state, g.blocks, g.Lmax))
+    t0 = amr_totals(g)
+    for _ in range(cycles):
+        g.cycle()
+    t1 = amr_totals(g)
+    scale = np.abs(t0[:5]).max()
+    assert np.abs(t1[:5] - t0[:5]).max() <= 2e-14 * scale, (t1 - t0)[:5]
+    assert g.divb() < 1e-12
+    assert shared_face_mismatch(g) < 1e-14
+    return g
+
+
+def test_time_levels_on_faces_of_every_direction_conserve():
+    """a periodic box of 2 x 2 x 2 blocks with the time levels of a checkerboard: every
+    block face, edge and corner is a time-level interface (x1, x2 and x3 faces; edges met
+    by blocks of both levels); mass, energy and momentum are conserved to round-off, div B
+    stays at round-off and every shared face has one value"""
+    cfg = mink_cfg((8, 8, 8), recon=1, riemann=1)
+    g = _check_conservation(cfg, checker_blocks((8, 8, 8), (2, 2, 2),
+                                                lambda i, j, k: (i + j + k) % 2))
+    assert any(g.sync_edges[b] for b in range(8)) and sum(len(r) for r in g.reflux) == 4 * 6 * 16
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+def test_three_time_levels_across_x2_or_x3(axis):
+    """levels 0, 1, 2, 1 in bands along x2 (or x3) of a periodic box"""
+    cfg = mink_cfg((8, 16, 16), recon=1, riemann=1, L=(1.0, 2.0, 2.0))
+    lv = [0, 1, 2, 1]
+    _check_conservation(cfg, checker_blocks((8, 16, 16), (1, 4, 4),
+                                            lambda i, j, k: lv[j] if axis == 1 else lv[k]),
+                        dx=(1 / 8, 1 / 8, 1 / 8))
+
+
+@pytest.mark.parametrize("lats", [(1, 0, 1), (0, 1, 0)])
+def test_refinement_faces_between_time_levels_conserve(lats):
+    """coarse / fine / coarse bands across x2 with the fine band faster (finer and faster)
+    or slower (finer and slower) than the coarse bands, and the two x1 halves of each band
+    at different levels too: refinement faces between different time levels"""
+    cfg = mink_cfg((16, 16, 8), recon=1, riemann=1, L=(1.0, 1.0, 0.5))
+    blocks = band_blocks((0, 0))
+    for k, b in enumerate(blocks):
+        band = k // 2
+        b["lat"] = lats[band] + (k % 2 if lats[band] == 0 else 0)
+    g = _check_conservation(cfg, blocks, dx=(1 / 16, 1 / 16, 1 / 16))
+    assert any(r for r in g.reflux)
