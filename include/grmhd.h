@@ -216,17 +216,27 @@ int grmhd_divb(grmhd_ctx* ctx, double* max_abs, double* max_rel, double* field);
  * child in the upper half per dimension, bit 8 mean of two face stencils, bits 16-23
  * flags of the result; what = 8: their samples as int32 quadruples (block | flags <<
  * 24, local index, averaged dimensions of a restriction, 0); what = 9: the refinement
- * faces as 20 int32 each (coarse block, fine block, normal dimension, refined
- * dimensions, patch lo[3], hi[3] in coarse local indices, coarse plane, fine plane,
- * coarse origin[3], fine origin[3], positions, 0); what = 10: the schedule of one
- * local-time-stepping cycle (Sec. 3.5) as int32 quadruples (substep, 0 = the block
- * steps / 1 = the slow block is synchronised with a faster x1 neighbour, time level,
- * block) in launch order; what = 11: the old state a level step saves for faster
- * neighbours (the sources of time-interpolated ghosts, Sec. 3.5) as int32 quadruples
- * (time level, 0 = primitives / 1 = face field, block, element offset in the block's
- * part of the packed array: variable or component x padded volume + local index),
- * per level and list sorted, without repeats.  host_buf NULL queries the size in
- * bytes. */
+ * faces between blocks of one time level (Sec. 3.3) as 13 int32 each (coarse block,
+ * fine block, normal dimension, side 0 = the coarse block's lower face / 1 = upper,
+ * refined dimensions e[3], shared patch lo[3], hi[3] in the coarse block's global
+ * cells); what = 10: the schedule of one local-time-stepping cycle (Sec. 3.5) as int32
+ * quadruples (substep, 0 = the block steps / 1 = the slower block is synchronised
+ * with faster neighbours, time level, block): steps in launch order, the
+ * synchronisations of one substep (independent of each other) in block order;
+ * what = 11: the old state a level step saves for faster neighbours (the sources of
+ * time-interpolated ghosts, Sec. 3.5) as int32 quadruples (time level, 0 = primitives
+ * / 1 = face field, block, element offset in the block's part of the packed array:
+ * variable or component x padded volume + local index), per level and list sorted,
+ * without repeats; what = 12: the faces each block refluxes at the end of its step
+ * (Sec. 3.5, 3.3) as 10 int32 (block, normal dimension, side, padded local face index,
+ * faster block, count n, that block's n covering faces, -1 padded to 4); what = 13:
+ * the block edges whose dominant holder (fastest, then finest, then lowest index) is
+ * faster, as 7 int32 (block, edge direction, local edge index, holder, count n, the
+ * holder's n covering edges, -1 padded to 2); what = 14: likewise the edges whose
+ * finest holder at the block's own time level is finer (EMF replaced in each stage);
+ * what = 15..19: the device lists built from them as raw structures (internal layout,
+ * for bounds checks).  Every table lists blocks in block order.  host_buf NULL queries
+ * the size in bytes. */
 int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes);
 
 /* Planner geometry at one internal-coordinate point (host only, no device needed):

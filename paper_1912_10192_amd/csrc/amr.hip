@@ -11,11 +11,14 @@
 //     (slopes from the parent's neighbours at its own level, child = parent +-
 //     slope/4 per refined dimension; a fine face that cuts a coarse cell in two takes
 //     the mean of the prolonged values on the two coarse faces bounding that cell);
-// (2) make the coarse side of every refinement face use the fine side's fluxes and
-//     edge EMFs (area and edge means), so both sides change the conserved totals and
-//     the face field by the same amount;
+// (2) within a time level, make the coarse side of every refinement face use the fine
+//     side's fluxes (area means) and every edge the EMF of its finest holder (edge
+//     means), so both sides change the conserved totals and the face field by the same
+//     amount;
 // (3) after each update, give the coarse copy of every shared face the mean of the
 //     fine faces, the finer side owning shared faces.
+// Across time levels the same corrections happen at the end of the slower block's step
+// from time-integrated registers (lat.hip).
 // Each value is read from the source block's state as the viewing block sees it at its
 // stage time (the time-level rules of local time stepping, as for plain copies).
 #include <hip/hip_runtime.h>
@@ -183,100 +186,22 @@ __global__ __launch_bounds__(AT) void k_amr_ghosts(const BlockInfo* __restrict__
 
 // ------------------------------------------------------------------ refinement faces
 
-struct LinkPos {
-  int kind;          // 0 face, 1 edge along a0, 2 edge along a1
-  int pc[3], pf[3];  // coarse local index, fine local index of the first child
-};
-
-__device__ __forceinline__ bool link_position(const AmrLink& lk, int g, int t, LinkPos& P) {
-  const int d = lk.d;
-  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
-  const int w0 = lk.hi[a0] - lk.lo[a0], w1 = lk.hi[a1] - lk.lo[a1];
-  const int nf = w0 * w1, ne0 = w0 * (w1 + 1), ne1 = w1 * (w0 + 1);
-  int i0, i1;
-  if (t < nf) {
-    P.kind = 0;
-    i0 = t % w0;
-    i1 = t / w0;
-  } else if (t < nf + ne0) {
-    P.kind = 1;
-    i0 = (t - nf) % w0;
-    i1 = (t - nf) / w0;
-  } else if (t < nf + ne0 + ne1) {
-    P.kind = 2;
-    i1 = (t - nf - ne0) % w1;
-    i0 = (t - nf - ne0) / w1;
-  } else {
-    return false;
-  }
-  P.pc[d] = lk.cplane;
-  P.pc[a0] = lk.lo[a0] + i0;
-  P.pc[a1] = lk.lo[a1] + i1;
-  P.pf[d] = lk.fplane;
-  for (int x = 0; x < 3; x++)
-    if (x != d) P.pf[x] = (P.pc[x] - g + lk.corg[x]) * (1 << ((lk.e >> x) & 1)) - lk.forg[x] + g;
-  return true;
-}
-
-__device__ __forceinline__ int64_t lidx(const BlockInfo& b, const int p[3]) {
-  return ((int64_t)p[2] * b.np[1] + p[1]) * b.np[0] + p[0];
-}
-
-__device__ __forceinline__ int64_t lstride(const BlockInfo& b, int x) {
-  return x == 0 ? 1 : (x == 1 ? (int64_t)b.np[0] : (int64_t)b.np[0] * b.np[1]);
-}
-
-// coarse fluxes on the shared faces <- area mean of the fine fluxes; coarse EMFs on the
-// shared edges <- mean of the fine EMFs along the coarse edge
-__global__ __launch_bounds__(AT) void k_amr_fix(Launch L, const AmrLink* __restrict__ links,
-                                                double* __restrict__ F, double* __restrict__ E) {
-  const AmrLink lk = links[blockIdx.y];
-  const int t = blockIdx.x * AT + threadIdx.x;
-  LinkPos P;
-  if (!link_position(lk, L.ph.ng, t, P)) return;
-  const BlockInfo c = L.blk[lk.coarse], f = L.blk[lk.fine];
-  const int d = lk.d;
-  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
-  const int64_t lc = lidx(c, P.pc), lf = lidx(f, P.pf);
-  if (P.kind == 0) {
-    const int n0 = ((lk.e >> a0) & 1) ? 2 : 1, n1 = ((lk.e >> a1) & 1) ? 2 : 1;
-    const int64_t s0 = lstride(f, a0), s1 = lstride(f, a1);
-    const double inv = 1.0 / (n0 * n1);
-    for (int q = 0; q < 8; q++) {
-      const double* src = F + 24 * f.off + (int64_t)(d * 8 + q) * f.vol + lf;
-      double acc = 0.0;
-      for (int o1 = 0; o1 < n1; o1++)
-        for (int o0 = 0; o0 < n0; o0++) acc += src[o1 * s1 + o0 * s0];
-      F[24 * c.off + (int64_t)(d * 8 + q) * c.vol + lc] = acc * inv;
-    }
-  } else {
-    const int a = P.kind == 1 ? a0 : a1;
-    const int na = ((lk.e >> a) & 1) ? 2 : 1;
-    const int64_t sa = lstride(f, a);
-    const double* src = E + 3 * f.off + (int64_t)a * f.vol + lf;
+// One item per thread: the mean of the item's sources, per component.  Fluxes of a
+// refinement face take the area mean of the finer block's fluxes, EMFs the finest
+// holder's (the mean of its two sub-edges where it is finer along the edge), coarse
+// copies of shared faces the mean of the fine faces.
+__global__ __launch_bounds__(AT) void k_means(const MeanItem* __restrict__ items, int64_t n,
+                                              double* __restrict__ X0, double* __restrict__ X1) {
+  const int64_t t = (int64_t)blockIdx.x * AT + threadIdx.x;
+  if (t >= n) return;
+  const MeanItem it = items[t];
+  double* X = it.kind == 0 ? X0 : X1;
+  const double inv = 1.0 / it.n;
+  for (int q = 0; q < it.ncomp; q++) {
     double acc = 0.0;
-    for (int o = 0; o < na; o++) acc += src[o * sa];
-    E[3 * c.off + (int64_t)a * c.vol + lc] = acc * (1.0 / na);
+    for (int i = 0; i < it.n; i++) acc = acc + X[it.src[i] + (int64_t)q * it.sstride];
+    X[it.dst + (int64_t)q * it.dstride] = acc * inv;
   }
-}
-
-// coarse copy of the shared faces <- mean of the fine faces
-__global__ __launch_bounds__(AT) void k_amr_bsync(Launch L, const AmrLink* __restrict__ links,
-                                                  double* __restrict__ B) {
-  const AmrLink lk = links[blockIdx.y];
-  const int t = blockIdx.x * AT + threadIdx.x;
-  LinkPos P;
-  if (!link_position(lk, L.ph.ng, t, P) || P.kind != 0) return;
-  const BlockInfo c = L.blk[lk.coarse], f = L.blk[lk.fine];
-  const int d = lk.d;
-  const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
-  const int n0 = ((lk.e >> a0) & 1) ? 2 : 1, n1 = ((lk.e >> a1) & 1) ? 2 : 1;
-  const int64_t s0 = lstride(f, a0), s1 = lstride(f, a1);
-  const double* src = B + 3 * f.off + (int64_t)d * f.vol + lidx(f, P.pf);
-  double acc = 0.0;
-  for (int o1 = 0; o1 < n1; o1++)
-    for (int o0 = 0; o0 < n0; o0++) acc += src[o1 * s1 + o0 * s0];
-  B[3 * c.off + (int64_t)d * c.vol + lidx(c, P.pc)] = acc * (1.0 / (n0 * n1));
 }
 
 // ------------------------------------------------------------------ launchers
@@ -297,17 +222,9 @@ void launch_amr_ghosts(const Launch& L, const AmrLists& A, const AmrSample* samp
       L.blk, L.geo, A, samp, Pmain, Pold, Pcur, Pdst, Bmain, Bold, Bcur, Bdst, w);
 }
 
-void launch_amr_fix(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* F,
-                    double* E) {
-  if (nlinks <= 0 || maxpos <= 0) return;
-  k_amr_fix<<<dim3((unsigned)((maxpos + AT - 1) / AT), (unsigned)nlinks), dim3(AT), 0, L.stream>>>(
-      L, links, F, E);
-}
-
-void launch_amr_bsync(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* B) {
-  if (nlinks <= 0 || maxpos <= 0) return;
-  k_amr_bsync<<<dim3((unsigned)((maxpos + AT - 1) / AT), (unsigned)nlinks), dim3(AT), 0,
-                L.stream>>>(L, links, B);
+void launch_means(const Launch& L, const MeanItem* items, int64_t n, double* X0, double* X1) {
+  if (n <= 0) return;
+  k_means<<<dim3((unsigned)((n + AT - 1) / AT)), dim3(AT), 0, L.stream>>>(items, n, X0, X1);
 }
 
 }  // namespace grmhd

@@ -153,8 +153,40 @@ struct Plan {
   std::vector<AmrOp> aops[4];   // ghost values across refinement levels (sorted likewise)
   std::vector<AmrSample> samples;
   std::vector<uint8_t> samp_kind;   // the list (cells, x1/x2/x3 faces) of each sample
-  std::vector<AmrLink> links;   // refinement faces, sorted by time level
-  int32_t link_maxpos = 0;
+  // refinement faces between blocks of one time level (the coarse side takes the fine
+  // side's fluxes in each stage), in the order the blocks are listed
+  struct Link {
+    int32_t c, f, d, side, e[3];
+    int64_t lo[3], hi[3];   // shared patch, coarse global cells (transverse dimensions)
+  };
+  std::vector<Link> links;
+  // Synchronisation tables, per block in block order (padded local indices):
+  //   reflux: a boundary face of block b shared with a faster block D, and the elements
+  //           of D covering it (its sub-faces where D is finer, the covering face where
+  //           it is coarser);
+  //   sync edges: a boundary edge of b whose dominant holder (fastest, then finest, then
+  //           lowest index) D is faster, and D's elements covering it;
+  //   stage edges: a boundary edge of b whose finest holder at b's time level is finer.
+  struct Reflux {
+    int32_t b, d, side, loc, D, n, sub[4];
+  };
+  struct EdgeRef {
+    int32_t b, a, loc, D, n, sub[2];
+  };
+  std::vector<Reflux> reflux;
+  std::vector<EdgeRef> sync_edges, stage_edges;
+  // device lists built from them: per time level (offsets, +1 at the end)
+  std::vector<MeanItem> fix;      // fluxes (kind 0) and EMFs (kind 1) of each stage
+  std::vector<int64_t> fix_off;
+  std::vector<MeanItem> bsync;    // coarse copies of refinement faces after each update
+  std::vector<int64_t> bsync_off;
+  std::vector<RegItem> regs;      // register elements of each level's corrector
+  std::vector<int64_t> reg_off;
+  int64_t nregF = 0, nregE = 0;
+  std::vector<SyncCell> scells;   // by the slow block's level
+  std::vector<int64_t> scell_off;
+  std::vector<SyncFace> sfaces;
+  std::vector<int64_t> sface_off;
   // work lists of the stage kernels for blocks of uneven sizes: per block list (each
   // time level, then all blocks) and region class, the (block, tile) items
   bool use_wl = false;
@@ -166,21 +198,17 @@ struct Plan {
   std::vector<int64_t> lev_boff;               // offsets into lev_blocks per level (+1)
   std::vector<int64_t> ops_off[4];             // offsets into ops[kind] per level (+1)
   std::vector<int64_t> aops_off[4];            // offsets into aops[kind] per level (+1)
-  std::vector<int64_t> link_off;               // offsets into links per level (+1)
-  std::vector<SyncItem> items;                 // sorted by the slow block's level
-  std::vector<int64_t> item_off;               // offsets per level (+1)
   std::vector<int64_t> lev_cells;              // interior cells per level
   // per time level, the elements of its blocks that a faster neighbour reads as the old
   // state of a time-interpolated ghost: cells (element indices of the packed primitives)
   // and faces (of the packed face field), sorted, without repeats
   std::vector<uint32_t> slow_c, slow_f;
   std::vector<int64_t> slow_c_off, slow_f_off; // offsets per level (+1)
-  int32_t rs = 0, rs2 = 0;                     // register plane size and row stride
   // work-buffer offsets (bytes)
   size_t o_ps, o_balt, o_bc, o_f, o_e, o_gc, o_g1, o_g2, o_blk, o_ops[4], o_cnt, o_dtp, o_stp;
   int64_t slots;   // workgroups of a full-grid stage launch: Courant and statistics partials
-  size_t o_aops[4], o_samp, o_links, o_u9, o_wl;
-  size_t o_pold, o_bold, o_slow, o_reg, o_ubuf, o_lev, o_items, total;
+  size_t o_aops[4], o_samp, o_fix, o_bsync, o_u9, o_wl;
+  size_t o_pold, o_bold, o_slow, o_regs, o_regf, o_rege, o_scell, o_sface, o_ubuf, o_lev, total;
 };
 
 // cells of the grid at refinement levels lev along each dimension
@@ -354,28 +382,54 @@ int time_flags(const Plan& p, int src, int viewer) {
 }
 
 // Of the blocks holding a copy of face (i, j, k) of component kind at levels lev (the
-// cells on either side of it), the one a viewing block reads: itself, else the finest,
-// then one at the viewer's time level, then the one listed last.
-int face_owner(const Plan& p, const int32_t* lev, const int64_t N[3], int kind, int64_t i,
-               int64_t j, int64_t k, int viewer) {
+// cells on either side of it), the one a viewing block reads: itself, else one at the
+// viewer's time level (blocks of one time level evolve such a face side by side and must
+// read one copy of it), then the finest, then the one listed last.
+int face_owner(const Plan& p, const int32_t* lev, const int64_t N[3], int kind, int64_t& i,
+               int64_t& j, int64_t& k, int viewer) {
   const int d = kind - 1;
+  // a face on a periodic seam (normal index 0 or N) lies between the first and the last
+  // cell along its normal
+  const bool per = d == 2 || p.d.bc[2 * d] == GRMHD_BC_PERIODIC;
   int cand[2];
   int nc = 0;
   int64_t q[3] = {i, j, k};
-  if (q[d] < N[d]) cand[nc++] = owner_at(p, lev, q[0], q[1], q[2]);
-  q[d] -= 1;
-  if (q[d] >= 0) cand[nc++] = owner_at(p, lev, q[0], q[1], q[2]);
+  if (q[d] < N[d] || per) {
+    int64_t r[3] = {q[0], q[1], q[2]};
+    r[d] = q[d] < N[d] ? q[d] : 0;
+    cand[nc++] = owner_at(p, lev, r[0], r[1], r[2]);
+  }
+  if (q[d] - 1 >= 0 || per) {
+    int64_t r[3] = {q[0], q[1], q[2]};
+    r[d] = q[d] - 1 >= 0 ? q[d] - 1 : N[d] - 1;
+    cand[nc++] = owner_at(p, lev, r[0], r[1], r[2]);
+  }
   int best = cand[0];
-  for (int c = 0; c < nc; c++) {
+  for (int c = 0; c < nc && best != viewer; c++) {
     const int o = cand[c];
-    if (o == viewer) return viewer;
+    if (o == viewer) {
+      best = viewer;
+      break;
+    }
     auto key = [&](int b) {
       const grmhd_block_desc& bd = p.blocks[b];
-      return std::make_tuple(bd.lev[0] + bd.lev[1] + bd.lev[2],
-                             bd.lat == p.blocks[viewer].lat ? 1 : 0, b);
+      return std::make_tuple(bd.lat == p.blocks[viewer].lat ? 1 : 0,
+                             bd.lev[0] + bd.lev[1] + bd.lev[2], b);
     };
     if (key(o) > key(best)) best = o;
   }
+  // the position in the chosen block's frame: the other representation of a seam face
+  // where the block lies at the other end of the grid
+  if (per && (q[d] == 0 || q[d] == N[d])) {
+    const grmhd_block_desc& bd = p.blocks[best];
+    const int s = lev[d] - bd.lev[d];
+    const int64_t lo = s >= 0 ? bd.org[d] << s : bd.org[d] >> (-s);
+    const int64_t hi = s >= 0 ? (bd.org[d] + bd.n[d]) << s : (bd.org[d] + bd.n[d]) >> (-s);
+    if (q[d] < lo || q[d] > hi) q[d] = q[d] == 0 ? N[d] : 0;
+  }
+  i = q[0];
+  j = q[1];
+  k = q[2];
   return best;
 }
 
@@ -647,27 +701,107 @@ void build_slow(Plan& p) {
   }
 }
 
-// faces shared by a coarse block and a block one level finer
-int build_links(Plan& p) {
+// ------------------------------------------------------------------ synchronisation
+
+static bool periodic_dim(const Plan& p, int d) {
+  return d == 2 || p.d.bc[2 * d] == GRMHD_BC_PERIODIC;
+}
+
+// The block holding cell x of the grid at levels lam; positions outside the grid wrap
+// across periodic boundaries; -1 beyond an outflow or polar boundary.
+static int holder(const Plan& p, const int32_t* lam, const int64_t x[3]) {
+  int64_t N[3], y[3];
+  level_extent(p, lam, N);
+  for (int d = 0; d < 3; d++) {
+    if (x[d] >= 0 && x[d] < N[d]) {
+      y[d] = x[d];
+      continue;
+    }
+    if (!periodic_dim(p, d)) return -1;
+    y[d] = imod(x[d], N[d]);
+  }
+  return owner_at(p, lam, y[0], y[1], y[2]);
+}
+
+// The elements of block D covering the element at position pos of levels lam (kind 0 a
+// cell, 1 a face with normal a, 2 an edge along a): one where D is as fine or coarser,
+// two or four sub-elements where it is finer (z slowest, x fastest).  Returns their
+// count, or -1 if one lies outside D or off D's lattice.
+static int cover(const Plan& p, int D, const int32_t* lam, const int64_t pos[3], int kind, int a,
+                 int32_t out[4]) {
+  const grmhd_block_desc& bd = p.blocks[D];
+  const BlockInfo& bi = p.info[D];
   const int g = p.d.n_ghost;
+  int64_t N[3];
+  level_extent(p, bd.lev, N);
+  int64_t loc[3][2];
+  int nv[3];
+  for (int d = 0; d < 3; d++) {
+    const int diff = bd.lev[d] - lam[d];
+    const bool node = (kind == 1 && d == a) || (kind == 2 && d != a);
+    int64_t v[2];
+    if (node) {
+      if (diff >= 0) {
+        v[0] = pos[d] << diff;
+      } else {
+        if (pos[d] & 1) return -1;
+        v[0] = pos[d] >> 1;
+      }
+      nv[d] = 1;
+    } else if (diff > 0) {
+      v[0] = pos[d] << 1;
+      v[1] = v[0] + 1;
+      nv[d] = 2;
+    } else {
+      v[0] = pos[d] >> (-diff);
+      nv[d] = 1;
+    }
+    const int64_t hi = bd.org[d] + bd.n[d] + (node ? 1 : 0);
+    for (int q = 0; q < nv[d]; q++) {
+      const int64_t cand[3] = {v[q], v[q] - N[d], v[q] + N[d]};
+      const int nc = periodic_dim(p, d) ? 3 : 1;
+      int64_t got = -1;
+      for (int c = 0; c < nc && got < 0; c++)
+        if (cand[c] >= bd.org[d] && cand[c] < hi) got = cand[c];
+      if (got < 0) return -1;
+      loc[d][q] = got - bd.org[d] + g;
+    }
+  }
+  int n = 0;
+  for (int k = 0; k < nv[2]; k++)
+    for (int j = 0; j < nv[1]; j++)
+      for (int i = 0; i < nv[0]; i++) out[n++] = local_index(bi, loc[0][i], loc[1][j], loc[2][k]);
+  return n;
+}
+
+// fastest, then finest, then lowest index
+static bool dominates(const Plan& p, int x, int y) {
+  const grmhd_block_desc &a = p.blocks[x], &b = p.blocks[y];
+  const int la = a.lev[0] + a.lev[1] + a.lev[2], lb = b.lev[0] + b.lev[1] + b.lev[2];
+  if (a.lat != b.lat) return a.lat < b.lat;
+  if (la != lb) return la > lb;
+  return x < y;
+}
+
+// Refinement faces between blocks of one time level: a block one level finer (in some
+// dimensions, equal in the others) touching a coarse block across a face.
+static void find_links(Plan& p) {
   const int nb = p.d.n_blocks;
   p.links.clear();
-  p.link_maxpos = 0;
-  if (!p.refined) return GRMHD_OK;
-  const bool per[3] = {p.d.bc[0] == GRMHD_BC_PERIODIC, p.d.bc[2] == GRMHD_BC_PERIODIC, true};
+  if (!p.refined) return;
   for (int c = 0; c < nb; c++) {
     const grmhd_block_desc& bc = p.blocks[c];
     int64_t Nc[3];
     level_extent(p, bc.lev, Nc);
     for (int f = 0; f < nb; f++) {
       const grmhd_block_desc& bf = p.blocks[f];
-      int e[3], emask = 0, ok = 1;
+      int e[3], any = 0, ok = 1;
       for (int x = 0; x < 3; x++) {
         e[x] = bf.lev[x] - bc.lev[x];
         if (e[x] < 0 || e[x] > 1) ok = 0;
-        emask |= (e[x] == 1 ? 1 : 0) << x;
+        any |= e[x];
       }
-      if (!ok || !emask) continue;
+      if (!ok || !any) continue;
       int64_t lo_f[3], hi_f[3], lo_c[3], hi_c[3];
       for (int x = 0; x < 3; x++) {
         lo_f[x] = bf.org[x] >> e[x];
@@ -680,35 +814,408 @@ int build_links(Plan& p) {
         for (int x = 0; x < 3; x++)
           if (x != d && std::max(lo_f[x], lo_c[x]) >= std::min(hi_f[x], hi_c[x])) overlap = false;
         if (!overlap) continue;
-        const bool below = hi_f[d] == lo_c[d] || (per[d] && lo_c[d] == 0 && hi_f[d] == Nc[d]);
-        const bool above = hi_c[d] == lo_f[d] || (per[d] && lo_f[d] == 0 && hi_c[d] == Nc[d]);
+        const bool per = periodic_dim(p, d);
+        const bool below = hi_f[d] == lo_c[d] || (per && lo_c[d] == 0 && hi_f[d] == Nc[d]);
+        const bool above = hi_c[d] == lo_f[d] || (per && lo_f[d] == 0 && hi_c[d] == Nc[d]);
         for (int side = 0; side < 2; side++) {
-          if (!(side == 0 ? below : above)) continue;
-          if (bc.lat != bf.lat)
-            return fail(GRMHD_EUNSUPPORTED, "blocks across a refinement face must share a time level");
-          AmrLink L;
-          L.coarse = c;
-          L.fine = f;
+          if (!(side == 0 ? below : above) || bc.lat != bf.lat) continue;
+          Plan::Link L;
+          L.c = c;
+          L.f = f;
           L.d = d;
-          L.e = emask;
+          L.side = side;
           for (int x = 0; x < 3; x++) {
-            L.lo[x] = (int32_t)(std::max(lo_f[x], lo_c[x]) - bc.org[x] + g);
-            L.hi[x] = (int32_t)(std::min(hi_f[x], hi_c[x]) - bc.org[x] + g);
-            L.corg[x] = (int32_t)bc.org[x];
-            L.forg[x] = (int32_t)bf.org[x];
+            L.e[x] = e[x];
+            L.lo[x] = std::max(lo_f[x], lo_c[x]);
+            L.hi[x] = std::min(hi_f[x], hi_c[x]);
           }
-          L.cplane = side == 0 ? g : g + bc.n[d];
-          L.fplane = side == 0 ? g + bf.n[d] : g;
-          const int a0 = d == 0 ? 1 : 0, a1 = d == 2 ? 1 : 2;
-          const int w0 = L.hi[a0] - L.lo[a0], w1 = L.hi[a1] - L.lo[a1];
-          L.npos = w0 * w1 + w0 * (w1 + 1) + w1 * (w0 + 1);
-          L.pad = 0;
-          p.link_maxpos = std::max(p.link_maxpos, L.npos);
           p.links.push_back(L);
         }
       }
     }
   }
+}
+
+// The reflux faces, sync edges and stage edges of every block (see Plan).
+static int sync_tables(Plan& p) {
+  const int nb = p.d.n_blocks;
+  const bool polar = p.d.bc[2] == GRMHD_BC_POLAR;
+  p.reflux.clear();
+  p.sync_edges.clear();
+  p.stage_edges.clear();
+  if (!p.refined && p.nlev == 1) return GRMHD_OK;   // one level of each kind: nothing shared
+  for (int b = 0; b < nb; b++) {
+    const grmhd_block_desc& bb = p.blocks[b];
+    const int32_t* lam = bb.lev;
+    int64_t N[3];
+    level_extent(p, lam, N);
+    const int64_t* o = bb.org;
+    const int32_t* n = bb.n;
+    for (int d = 0; d < 3; d++) {
+      const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      for (int side = 0; side < 2; side++) {
+        const int64_t pl = o[d] + (side ? n[d] : 0);
+        if (d == 1 && polar && (pl == 0 || pl == N[1])) continue;   // the axis carries no flux
+        for (int64_t c1 = o[t1]; c1 < o[t1] + n[t1]; c1++)
+          for (int64_t c0 = o[t0]; c0 < o[t0] + n[t0]; c0++) {
+            int64_t cell[3];
+            cell[d] = side ? pl : pl - 1;
+            cell[t0] = c0;
+            cell[t1] = c1;
+            const int D = holder(p, lam, cell);
+            if (D < 0 || p.blocks[D].lat >= bb.lat) continue;
+            int64_t pos[3] = {cell[0], cell[1], cell[2]};
+            pos[d] = pl;
+            Plan::Reflux r;
+            int32_t mine[4];
+            if (cover(p, b, lam, pos, 1, d, mine) != 1) return fail(GRMHD_EINVAL, "planner: a block face outside its block");
+            r.b = b;
+            r.d = d;
+            r.side = side;
+            r.loc = mine[0];
+            r.D = D;
+            for (int q = 0; q < 4; q++) r.sub[q] = -1;
+            r.n = cover(p, D, lam, pos, 1, d, r.sub);
+            if (r.n < 1) return fail(GRMHD_EINVAL, "planner: a shared face off the faster block's lattice");
+            p.reflux.push_back(r);
+          }
+      }
+    }
+    for (int a = 0; a < 3; a++) {
+      const int t0 = a == 0 ? 1 : 0, t1 = a == 2 ? 1 : 2;
+      for (int64_t x1 = o[t1]; x1 <= o[t1] + n[t1]; x1++)
+        for (int64_t x0 = o[t0]; x0 <= o[t0] + n[t0]; x0++) {
+          const bool on0 = x0 == o[t0] || x0 == o[t0] + n[t0];
+          const bool on1 = x1 == o[t1] || x1 == o[t1] + n[t1];
+          if (!on0 && !on1) continue;
+          if (polar && (t0 == 1 || t1 == 1)) {
+            const int64_t xt = t0 == 1 ? x0 : x1;
+            if (xt == 0 || xt == N[1]) continue;   // on the axis E1 = E3 = 0
+          }
+          for (int64_t ca = o[a]; ca < o[a] + n[a]; ca++) {
+            int hs[4], nh = 0;
+            for (int64_t q0 = x0 - 1; q0 <= x0; q0++)
+              for (int64_t q1 = x1 - 1; q1 <= x1; q1++) {
+                int64_t cell[3];
+                cell[a] = ca;
+                cell[t0] = q0;
+                cell[t1] = q1;
+                const int h = holder(p, lam, cell);
+                if (h < 0) continue;
+                const int32_t* hl = p.blocks[h].lev;
+                if ((hl[t0] < lam[t0] && (x0 & 1)) || (hl[t1] < lam[t1] && (x1 & 1))) continue;
+                bool dup = false;
+                for (int q = 0; q < nh; q++) dup |= hs[q] == h;
+                if (!dup) hs[nh++] = h;
+              }
+            if (nh == 0) continue;
+            int64_t pos[3];
+            pos[a] = ca;
+            pos[t0] = x0;
+            pos[t1] = x1;
+            int32_t mine[4];
+            if (cover(p, b, lam, pos, 2, a, mine) != 1) return fail(GRMHD_EINVAL, "planner: a block edge outside its block");
+            int Ds = -1, Da = -1;
+            for (int q = 0; q < nh; q++) {
+              if (p.blocks[hs[q]].lat == bb.lat && (Ds < 0 || dominates(p, hs[q], Ds))) Ds = hs[q];
+              if (Da < 0 || dominates(p, hs[q], Da)) Da = hs[q];
+            }
+            auto add = [&](std::vector<Plan::EdgeRef>& v, int D) -> int {
+              Plan::EdgeRef e;
+              e.b = b;
+              e.a = a;
+              e.loc = mine[0];
+              e.D = D;
+              int32_t sub[4] = {-1, -1, -1, -1};
+              e.n = cover(p, D, lam, pos, 2, a, sub);
+              if (e.n < 1 || e.n > 2) return fail(GRMHD_EINVAL, "planner: a shared edge off the holder's lattice");
+              e.sub[0] = sub[0];
+              e.sub[1] = sub[1];
+              v.push_back(e);
+              return GRMHD_OK;
+            };
+            const int32_t* ld = p.blocks[Ds].lev;
+            if (Ds != b && (ld[0] != lam[0] || ld[1] != lam[1] || ld[2] != lam[2]))
+              if (int rc = add(p.stage_edges, Ds)) return rc;
+            if (p.blocks[Da].lat < bb.lat)
+              if (int rc = add(p.sync_edges, Da)) return rc;
+          }
+        }
+    }
+  }
+  return GRMHD_OK;
+}
+
+static int x_range(const Plan::Link& lk, int d, int x) { return x == d ? 1 : 1 + lk.e[x]; }
+
+// The device lists of the tables above.
+static int sync_lists(Plan& p) {
+  const int L = p.nlev;
+  const int nb = p.d.n_blocks;
+  const int g = p.d.n_ghost;
+  auto lat = [&](int b) { return p.blocks[b].lat; };
+  // stage corrections at one time level
+  std::vector<std::vector<MeanItem>> fix(L), bs(L);
+  for (const Plan::Link& lk : p.links) {
+    const BlockInfo &ci = p.info[lk.c], &fi = p.info[lk.f];
+    const grmhd_block_desc &cd = p.blocks[lk.c], &fd = p.blocks[lk.f];
+    const int d = lk.d;
+    int64_t lo[3], hi[3];
+    for (int x = 0; x < 3; x++) {
+      lo[x] = x == d ? 0 : lk.lo[x];
+      hi[x] = x == d ? 1 : lk.hi[x];
+    }
+    for (int64_t ck = lo[2]; ck < hi[2]; ck++)
+      for (int64_t cj = lo[1]; cj < hi[1]; cj++)
+        for (int64_t ci_ = lo[0]; ci_ < hi[0]; ci_++) {
+          const int64_t cg[3] = {ci_, cj, ck};
+          int64_t pc[3];
+          for (int x = 0; x < 3; x++) pc[x] = g + cg[x] - cd.org[x];
+          pc[d] = g + (lk.side == 1 ? cd.n[d] : 0);
+          MeanItem mf{}, mb{};
+          mf.dst = 24 * ci.off + (int64_t)(d * 8) * ci.vol + local_index(ci, pc[0], pc[1], pc[2]);
+          mb.dst = 3 * ci.off + (int64_t)d * ci.vol + local_index(ci, pc[0], pc[1], pc[2]);
+          int n = 0;
+          const int r0 = x_range(lk, d, 0), r1 = x_range(lk, d, 1), r2 = x_range(lk, d, 2);
+          for (int ok = 0; ok < r2; ok++)
+            for (int oj = 0; oj < r1; oj++)
+              for (int oi = 0; oi < r0; oi++) {
+                const int64_t off[3] = {oi, oj, ok};
+                int64_t pf[3];
+                for (int x = 0; x < 3; x++) pf[x] = g + (cg[x] << lk.e[x]) + off[x] - fd.org[x];
+                pf[d] = g + (lk.side == 1 ? 0 : fd.n[d]);
+                const int32_t lf = local_index(fi, pf[0], pf[1], pf[2]);
+                mf.src[n] = 24 * fi.off + (int64_t)(d * 8) * fi.vol + lf;
+                mb.src[n] = 3 * fi.off + (int64_t)d * fi.vol + lf;
+                n++;
+              }
+          mf.n = mb.n = n;
+          mf.ncomp = 8;
+          mb.ncomp = 1;
+          mf.dstride = ci.vol;
+          mf.sstride = fi.vol;
+          mb.dstride = mb.sstride = 0;
+          mf.kind = 0;
+          mb.kind = 2;
+          fix[lat(lk.c)].push_back(mf);
+          bs[lat(lk.c)].push_back(mb);
+        }
+  }
+  for (const Plan::EdgeRef& e : p.stage_edges) {
+    const BlockInfo &bi = p.info[e.b], &di = p.info[e.D];
+    MeanItem m{};
+    m.dst = 3 * bi.off + (int64_t)e.a * bi.vol + e.loc;
+    for (int q = 0; q < e.n; q++) m.src[q] = 3 * di.off + (int64_t)e.a * di.vol + e.sub[q];
+    m.n = e.n;
+    m.ncomp = 1;
+    m.kind = 1;
+    fix[lat(e.b)].push_back(m);
+  }
+  auto flatten = [&](std::vector<std::vector<MeanItem>>& v, std::vector<MeanItem>& out,
+                     std::vector<int64_t>& off) {
+    out.clear();
+    off.assign(L + 1, 0);
+    for (int l = 0; l < L; l++) {
+      out.insert(out.end(), v[l].begin(), v[l].end());
+      off[l + 1] = (int64_t)out.size();
+    }
+  };
+  flatten(fix, p.fix, p.fix_off);
+  flatten(bs, p.bsync, p.bsync_off);
+  // register slots: (block, component, local index) of every flux and EMF the
+  // synchronisation reads, numbered by the block's time level
+  auto key = [](int b, int c, int32_t loc) { return ((int64_t)b * 3 + c) << 24 | (int64_t)loc; };
+  std::vector<int64_t> kf, ke;
+  for (const Plan::Reflux& r : p.reflux) {
+    kf.push_back(key(r.b, r.d, r.loc));
+    for (int q = 0; q < r.n; q++) kf.push_back(key(r.D, r.d, r.sub[q]));
+  }
+  for (const Plan::EdgeRef& e : p.sync_edges) {
+    ke.push_back(key(e.b, e.a, e.loc));
+    for (int q = 0; q < e.n; q++) ke.push_back(key(e.D, e.a, e.sub[q]));
+  }
+  auto order = [&](std::vector<int64_t>& k) {
+    std::sort(k.begin(), k.end(), [&](int64_t x, int64_t y) {
+      const int bx = (int)((x >> 24) / 3), by = (int)((y >> 24) / 3);
+      if (lat(bx) != lat(by)) return lat(bx) < lat(by);
+      return x < y;
+    });
+    k.erase(std::unique(k.begin(), k.end()), k.end());
+  };
+  order(kf);
+  order(ke);
+  p.nregF = (int64_t)kf.size();
+  p.nregE = (int64_t)ke.size();
+  auto slot = [](const std::vector<int64_t>& k, int64_t x, auto&& less) -> int32_t {
+    auto it = std::lower_bound(k.begin(), k.end(), x, less);
+    return (int32_t)(it - k.begin());
+  };
+  auto lessF = [&](int64_t x, int64_t y) {
+    const int bx = (int)((x >> 24) / 3), by = (int)((y >> 24) / 3);
+    if (lat(bx) != lat(by)) return lat(bx) < lat(by);
+    return x < y;
+  };
+  auto sF = [&](int b, int c, int32_t loc) { return slot(kf, key(b, c, loc), lessF); };
+  auto sE = [&](int b, int c, int32_t loc) { return slot(ke, key(b, c, loc), lessF); };
+  {
+    std::vector<std::vector<RegItem>> rl(L);
+    for (size_t i = 0; i < kf.size(); i++) {
+      const int b = (int)((kf[i] >> 24) / 3), c = (int)((kf[i] >> 24) % 3);
+      const int32_t loc = (int32_t)(kf[i] & 0xFFFFFF);
+      const BlockInfo& bi = p.info[b];
+      RegItem r{};
+      r.src = 24 * bi.off + (int64_t)(c * 8) * bi.vol + loc;
+      r.slot = (int32_t)i;
+      r.kind = 0;
+      r.stride = bi.vol;
+      rl[lat(b)].push_back(r);
+    }
+    for (size_t i = 0; i < ke.size(); i++) {
+      const int b = (int)((ke[i] >> 24) / 3), c = (int)((ke[i] >> 24) % 3);
+      const int32_t loc = (int32_t)(ke[i] & 0xFFFFFF);
+      const BlockInfo& bi = p.info[b];
+      RegItem r{};
+      r.src = 3 * bi.off + (int64_t)c * bi.vol + loc;
+      r.slot = (int32_t)i;
+      r.kind = 1;
+      r.stride = 0;
+      rl[lat(b)].push_back(r);
+    }
+    p.regs.clear();
+    p.reg_off.assign(L + 1, 0);
+    for (int l = 0; l < L; l++) {
+      p.regs.insert(p.regs.end(), rl[l].begin(), rl[l].end());
+      p.reg_off[l + 1] = (int64_t)p.regs.size();
+    }
+  }
+  // the synchronisation of each slower block
+  std::vector<std::vector<SyncCell>> cl(L);
+  std::vector<std::vector<SyncFace>> fl(L);
+  size_t ir = 0, ie = 0;
+  for (int b = 0; b < nb; b++) {
+    const BlockInfo& bi = p.info[b];
+    const int32_t* n = bi.n;
+    std::vector<std::pair<int32_t, std::vector<FluxTerm>>> dU;   // insertion order
+    std::vector<int32_t> touched;
+    std::vector<SyncFace> faces;
+    auto cell_terms = [&](int32_t loc) -> std::vector<FluxTerm>& {
+      for (auto& c : dU)
+        if (c.first == loc) return c.second;
+      dU.push_back({loc, {}});
+      return dU.back().second;
+    };
+    auto face_of = [&](int comp, int32_t loc) -> SyncFace& {
+      for (SyncFace& f : faces)
+        if (f.comp == comp && f.loc == loc) return f;
+      SyncFace f{};
+      f.blk = b;
+      f.comp = comp;
+      f.loc = loc;
+      faces.push_back(f);
+      return faces.back();
+    };
+    auto coords = [&](int32_t loc, int x[3]) {
+      x[0] = loc % bi.np[0];
+      x[1] = (loc / bi.np[0]) % bi.np[1];
+      x[2] = loc / (bi.np[0] * bi.np[1]);
+    };
+    const size_t r0 = ir, e0 = ie;
+    while (ir < p.reflux.size() && p.reflux[ir].b == b) {
+      const Plan::Reflux& r = p.reflux[ir++];
+      FluxTerm t{};
+      t.mine = sF(b, r.d, r.loc);
+      for (int q = 0; q < r.n; q++) t.th[q] = sF(r.D, r.d, r.sub[q]);
+      t.nth = r.n;
+      t.sgn = r.side == 1 ? 1 : -1;
+      t.dx = bi.dx[r.d];
+      int x[3];
+      coords(r.loc, x);
+      if (r.side == 1) x[r.d] -= 1;
+      cell_terms(local_index(bi, x[0], x[1], x[2])).push_back(t);
+    }
+    auto owned = [&](int c, const int x[3]) {
+      for (int e = 0; e < 3; e++)
+        if (x[e] < g || x[e] > g + n[e] - (e == c ? 0 : 1)) return false;
+      return true;
+    };
+    auto touch_face = [&](int c, const int x[3]) {
+      for (int cp = x[c] - 1; cp <= x[c]; cp++)
+        if (cp >= g && cp < g + n[c]) {
+          int y[3] = {x[0], x[1], x[2]};
+          y[c] = cp;
+          touched.push_back(local_index(bi, y[0], y[1], y[2]));
+        }
+    };
+    while (ie < p.sync_edges.size() && p.sync_edges[ie].b == b) {
+      const Plan::EdgeRef& e = p.sync_edges[ie++];
+      EdgeTerm t{};
+      t.mine = sE(b, e.a, e.loc);
+      for (int q = 0; q < e.n; q++) t.th[q] = sE(e.D, e.a, e.sub[q]);
+      t.nth = e.n;
+      int x[3];
+      coords(e.loc, x);
+      for (int pc = 0; pc < 3; pc++) {
+        if (pc == e.a) continue;
+        const int q = 3 - e.a - pc;
+        const int sign = e.a == (pc + 1) % 3 ? 1 : -1;
+        for (int w = 0; w < 2; w++) {
+          int fx[3] = {x[0], x[1], x[2]};
+          fx[q] = w == 0 ? x[q] - 1 : x[q];
+          if (!owned(pc, fx)) continue;
+          SyncFace& f = face_of(pc, local_index(bi, fx[0], fx[1], fx[2]));
+          if (f.nt >= 4) return fail(GRMHD_EINVAL, "planner: more than four edges on a face");
+          EdgeTerm tt = t;
+          tt.sgn = sign * (w == 0 ? 1 : -1);
+          tt.dx = bi.dx[q];
+          f.t[f.nt++] = tt;
+          touch_face(pc, fx);
+        }
+      }
+    }
+    for (size_t q = r0; q < ir; q++) {
+      const Plan::Reflux& r = p.reflux[q];
+      const int32_t* ld = p.blocks[r.D].lev;
+      const int32_t* lb = p.blocks[b].lev;
+      if (ld[0] < lb[0] || ld[1] < lb[1] || ld[2] < lb[2]) continue;   // the faster side is coarser
+      SyncFace& f = face_of(r.d, r.loc);
+      f.cblk = r.D;
+      f.ncopy = r.n;
+      for (int k = 0; k < 4; k++) f.csrc[k] = k < r.n ? r.sub[k] : 0;
+      int x[3];
+      coords(r.loc, x);
+      touch_face(r.d, x);
+    }
+    if (ir == r0 && ie == e0) continue;
+    std::vector<int32_t> all = touched;
+    for (auto& c : dU) all.push_back(c.first);
+    std::sort(all.begin(), all.end());
+    all.erase(std::unique(all.begin(), all.end()), all.end());
+    for (int32_t loc : all) {
+      SyncCell c{};
+      c.blk = b;
+      c.loc = loc;
+      for (auto& d : dU)
+        if (d.first == loc) {
+          if (d.second.size() > 3) return fail(GRMHD_EINVAL, "planner: more than three reflux faces on a cell");
+          c.nt = (int32_t)d.second.size();
+          for (size_t k = 0; k < d.second.size(); k++) c.t[k] = d.second[k];
+        }
+      cl[lat(b)].push_back(c);
+    }
+    fl[lat(b)].insert(fl[lat(b)].end(), faces.begin(), faces.end());
+  }
+  p.scells.clear();
+  p.sfaces.clear();
+  p.scell_off.assign(L + 1, 0);
+  p.sface_off.assign(L + 1, 0);
+  for (int l = 0; l < L; l++) {
+    p.scells.insert(p.scells.end(), cl[l].begin(), cl[l].end());
+    p.sfaces.insert(p.sfaces.end(), fl[l].begin(), fl[l].end());
+    p.scell_off[l + 1] = (int64_t)p.scells.size();
+    p.sface_off[l + 1] = (int64_t)p.sfaces.size();
+  }
+  if (p.nregF >= (int64_t(1) << 31) || p.nregE >= (int64_t(1) << 31))
+    return fail(GRMHD_EINVAL, "too many register elements");
   return GRMHD_OK;
 }
 
@@ -800,7 +1307,7 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
   if (with_maps) {
     if ((rc = build_ops(p))) return rc;
   }
-  if ((rc = build_links(p))) return rc;
+  find_links(p);
   // local time stepping tables
   p.nlev = desc->n_lat_levels;
   {
@@ -835,62 +1342,32 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
         for (int l = 0; l < L; l++) p.aops_off[kind][l + 1] += p.aops_off[kind][l];
       }
     }
-    std::stable_sort(p.links.begin(), p.links.end(), [&](const AmrLink& a, const AmrLink& c) {
-      return p.blocks[a.coarse].lat < p.blocks[c.coarse].lat;
-    });
-    p.link_off.assign(L + 1, 0);
-    for (const AmrLink& lk : p.links) p.link_off[p.blocks[lk.coarse].lat + 1]++;
-    for (int l = 0; l < L; l++) p.link_off[l + 1] += p.link_off[l];
     if (with_maps && L > 1) build_slow(p);
-    // neighbour checks: every block within one cell of a block (through the physical
-    // boundaries) differs by at most one time level; x2 and x3 face neighbours share a
-    // time level; x1 neighbours at another time level have the same refinement level and
-    // cover the same x2-x3 extent
-    p.items.clear();
+    // blocks that touch (across a face, an edge or a corner, and through the physical
+    // boundaries) differ by at most one time level
     if (L > 1) {
       for (int b = 0; b < nb; b++) {
         const grmhd_block_desc& bd = p.blocks[b];
         int64_t N[3];
         level_extent(p, bd.lev, N);
-        for (int dk = -1; dk <= 1; dk++)
-          for (int dj = -1; dj <= 1; dj++)
-            for (int di = -1; di <= 1; di++) {
-              if (!di && !dj && !dk) continue;
-              // probe the middle of the neighbouring region
-              int64_t gi = di < 0 ? bd.org[0] - 1 : (di > 0 ? bd.org[0] + bd.n[0] : bd.org[0] + bd.n[0] / 2);
-              int64_t gj = dj < 0 ? bd.org[1] - 1 : (dj > 0 ? bd.org[1] + bd.n[1] : bd.org[1] + bd.n[1] / 2);
-              int64_t gk = dk < 0 ? bd.org[2] - 1 : (dk > 0 ? bd.org[2] + bd.n[2] : bd.org[2] + bd.n[2] / 2);
+        for (int64_t k = bd.org[2] - 1; k <= bd.org[2] + bd.n[2]; k++)
+          for (int64_t j = bd.org[1] - 1; j <= bd.org[1] + bd.n[1]; j++)
+            for (int64_t i = bd.org[0] - 1; i <= bd.org[0] + bd.n[0]; i++) {
+              const bool in = i >= bd.org[0] && i < bd.org[0] + bd.n[0] && j >= bd.org[1] &&
+                              j < bd.org[1] + bd.n[1] && k >= bd.org[2] && k < bd.org[2] + bd.n[2];
+              if (in) continue;
+              int64_t gi = i, gj = j, gk = k;
               int fl = 0;
               compose(p.d, N, 0, gi, gj, gk, fl);
-              const int nbk = owner_at(p, bd.lev, gi, gj, gk);
-              const int dl = p.blocks[nbk].lat - bd.lat;
-              if (dl > 1 || dl < -1) return fail(GRMHD_EINVAL, "neighbouring time levels differ by more than one");
-              if (!di && (dj || dk) && (!dj || !dk) && dl != 0)
-                return fail(GRMHD_EUNSUPPORTED, "time-level interfaces must lie on x1 block faces");
-              if (di && !dj && !dk && dl == -1) {
-                const grmhd_block_desc& fd = p.blocks[nbk];
-                if (fd.org[1] != bd.org[1] || fd.org[2] != bd.org[2] || fd.n[1] != bd.n[1] ||
-                    fd.n[2] != bd.n[2] || fd.lev[0] != bd.lev[0] || fd.lev[1] != bd.lev[1] ||
-                    fd.lev[2] != bd.lev[2])
-                  return fail(GRMHD_EUNSUPPORTED, "x1 neighbours at another time level must match in x2, x3 and refinement");
-                SyncItem it;
-                it.slow = b;
-                it.fast = nbk;
-                it.side = di > 0 ? 1 : 0;
-                it.pad = 0;
-                if (nbk != b) p.items.push_back(it);
-              }
+              const int o = owner_at(p, bd.lev, gi, gj, gk);
+              const int dl = p.blocks[o].lat - bd.lat;
+              if (dl > 1 || dl < -1)
+                return fail(GRMHD_EINVAL, "neighbouring time levels differ by more than one");
             }
       }
     }
-    std::stable_sort(p.items.begin(), p.items.end(), [&](const SyncItem& a, const SyncItem& c) {
-      return p.blocks[a.slow].lat < p.blocks[c.slow].lat;
-    });
-    p.item_off.assign(L + 1, 0);
-    for (const SyncItem& it : p.items) p.item_off[p.blocks[it.slow].lat + 1]++;
-    for (int l = 0; l < L; l++) p.item_off[l + 1] += p.item_off[l];
-    p.rs2 = p.max_n[1] + 1;
-    p.rs = (p.max_n[2] + 1) * p.rs2;
+    if ((rc = sync_tables(p))) return rc;
+    if ((rc = sync_lists(p))) return rc;
     // work lists when block sizes differ (equal sizes leave no idle tiles in the grid)
     p.use_wl = false;
     for (int b = 1; b < nb; b++)
@@ -966,20 +1443,20 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
     p.o_aops[kind] = take(p.aops[kind].size() * sizeof(AmrOp));
   }
   p.o_samp = take(p.samples.size() * sizeof(AmrSample));
-  p.o_links = take(p.links.size() * sizeof(AmrLink));
+  p.o_fix = take(p.fix.size() * sizeof(MeanItem));
+  p.o_bsync = take(p.bsync.size() * sizeof(MeanItem));
   p.o_wl = take(p.wl.size() * sizeof(int2));
   p.o_cnt = take(sizeof(Counters));
   const bool lat = p.nlev > 1;
   p.o_pold = take(lat ? 5 * V * 8 : 0);
   p.o_bold = take(lat ? 3 * V * 8 : 0);
   p.o_slow = take((p.slow_c.size() + p.slow_f.size()) * sizeof(uint32_t));
-  p.o_reg = take(lat ? (size_t)nb * 40 * p.rs * 8 : 0);
-  {
-    // sync items: at most two per block
-    const size_t nitems = lat ? (size_t)2 * nb : 0;
-    p.o_ubuf = take(nitems * p.max_n[1] * p.max_n[2] * 9 * 8);
-    p.o_items = take(nitems * sizeof(SyncItem));
-  }
+  p.o_regs = take(p.regs.size() * sizeof(RegItem));
+  p.o_regf = take((size_t)p.nregF * 12 * 8);   // step and pair sets of six components
+  p.o_rege = take((size_t)p.nregE * 2 * 8);
+  p.o_scell = take(p.scells.size() * sizeof(SyncCell));
+  p.o_sface = take(p.sfaces.size() * sizeof(SyncFace));
+  p.o_ubuf = take(p.scells.size() * 9 * 8);
   p.o_lev = take((size_t)nb * sizeof(int32_t));
   {
     const int64_t r = (int64_t)p.max_n[0] * p.max_n[1] * p.max_n[2];
@@ -1057,15 +1534,17 @@ struct grmhd_ctx {
   AmrOp* aops[4];
   int64_t naops[4];
   AmrSample* samp = nullptr;
-  AmrLink* links = nullptr;
+  const MeanItem *fix = nullptr, *bsync = nullptr;
   int2* wl = nullptr;
   bool b_in_alt = false;
   const void* mlp = nullptr;   // packed MLP blob when the learned guess is on
   // local time stepping
-  double *pold = nullptr, *bold = nullptr, *reg = nullptr, *ubuf = nullptr;
+  double *pold = nullptr, *bold = nullptr, *regf = nullptr, *rege = nullptr, *ubuf = nullptr;
   const uint32_t *slow_c = nullptr, *slow_f = nullptr;
   int32_t* lev_list = nullptr;
-  SyncItem* items = nullptr;
+  const RegItem* regs = nullptr;
+  const SyncCell* scells = nullptr;
+  const SyncFace* sfaces = nullptr;
   bool batched = false;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -1147,10 +1626,13 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   c->slow_c = (const uint32_t*)(w + p.o_slow);
   c->slow_f = c->slow_c + p.slow_c.size();
   c->bold = (double*)(w + p.o_bold);
-  c->reg = (double*)(w + p.o_reg);
+  c->regf = (double*)(w + p.o_regf);
+  c->rege = (double*)(w + p.o_rege);
   c->ubuf = (double*)(w + p.o_ubuf);
   c->lev_list = (int32_t*)(w + p.o_lev);
-  c->items = (SyncItem*)(w + p.o_items);
+  c->regs = (const RegItem*)(w + p.o_regs);
+  c->scells = (const SyncCell*)(w + p.o_scell);
+  c->sfaces = (const SyncFace*)(w + p.o_sface);
   c->batched = desc->batched != 0;
   std::vector<double> gc, g1, g2;
   build_geometry(p, gc, g1, g2);
@@ -1194,16 +1676,20 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
     }
   }
   c->samp = (AmrSample*)(w + p.o_samp);
-  c->links = (AmrLink*)(w + p.o_links);
+  c->fix = (const MeanItem*)(w + p.o_fix);
+  c->bsync = (const MeanItem*)(w + p.o_bsync);
   c->wl = (int2*)(w + p.o_wl);
   if ((rc = up(p.o_wl, p.wl.data(), p.wl.size() * sizeof(int2)))) {
     delete c;
     return rc;
   }
   if ((rc = up(p.o_samp, p.samples.data(), p.samples.size() * sizeof(AmrSample))) ||
-      (rc = up(p.o_links, p.links.data(), p.links.size() * sizeof(AmrLink))) ||
+      (rc = up(p.o_fix, p.fix.data(), p.fix.size() * sizeof(MeanItem))) ||
+      (rc = up(p.o_bsync, p.bsync.data(), p.bsync.size() * sizeof(MeanItem))) ||
       (rc = up(p.o_lev, p.lev_blocks.data(), p.lev_blocks.size() * sizeof(int32_t))) ||
-      (rc = up(p.o_items, p.items.data(), p.items.size() * sizeof(SyncItem))) ||
+      (rc = up(p.o_regs, p.regs.data(), p.regs.size() * sizeof(RegItem))) ||
+      (rc = up(p.o_scell, p.scells.data(), p.scells.size() * sizeof(SyncCell))) ||
+      (rc = up(p.o_sface, p.sfaces.data(), p.sfaces.size() * sizeof(SyncFace))) ||
       (rc = up(p.o_slow, p.slow_c.data(), p.slow_c.size() * sizeof(uint32_t))) ||
       (rc = up(p.o_slow + p.slow_c.size() * sizeof(uint32_t), p.slow_f.data(),
                p.slow_f.size() * sizeof(uint32_t)))) {
@@ -1348,14 +1834,14 @@ static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double
   launch_fluxes(c, L, Ps, Bs);
   prof_begin(c, KC_EMF);
   launch_emf(L, c->f, c->e);
-  launch_amr_fix(L, c->links, (int)c->plan.links.size(), c->plan.link_maxpos, c->f, c->e);
+  launch_means(L, c->fix, (int64_t)c->plan.fix.size(), c->f, c->e);
   prof_end(c);
   prof_begin(c, KC_UPDATE);
   launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, dt_part, c->mlp, c->u9);
   prof_end(c);
-  if (!c->plan.links.empty()) {
+  if (!c->plan.bsync.empty()) {
     prof_begin(c, KC_GHOST);
-    launch_amr_bsync(L, c->links, (int)c->plan.links.size(), c->plan.link_maxpos, Bout);
+    launch_means(L, c->bsync, (int64_t)c->plan.bsync.size(), Bout, Bout);
     prof_end(c);
   }
 }
@@ -1393,17 +1879,18 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
     launch_bcell(L, Bs, c->bc);
     prof_end(c);
     launch_fluxes(c, L, Ps, Bs);
-    const int64_t lo = p.link_off[lev], nl = p.link_off[lev + 1] - lo;
+    const int64_t fo = p.fix_off[lev], nfix = p.fix_off[lev + 1] - fo;
+    const int64_t bo = p.bsync_off[lev], nbs = p.bsync_off[lev + 1] - bo;
     prof_begin(c, KC_EMF);
     launch_emf(L, c->f, c->e);
-    launch_amr_fix(L, c->links + lo, (int)nl, p.link_maxpos, c->f, c->e);
+    launch_means(L, c->fix + fo, nfix, c->f, c->e);
     prof_end(c);
     prof_begin(c, KC_UPDATE);
     launch_update(L, P, B, Ps, c->bc, c->f, c->e, factor, Pout, c->balt, nullptr, c->mlp, c->u9);
     prof_end(c);
-    if (nl > 0) {
+    if (nbs > 0) {
       prof_begin(c, KC_GHOST);
-      launch_amr_bsync(L, c->links + lo, (int)nl, p.link_maxpos, c->balt);
+      launch_means(L, c->bsync + bo, nbs, c->balt, c->balt);
       prof_end(c);
     }
   };
@@ -1411,7 +1898,8 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
   stage_l(P, B, 0.5 * scale, c->ps);                 // predictor -> ps, balt
   ghosts(c->ps, c->balt, c->ps, c->balt, w_corr);
   stage_l(c->ps, c->balt, scale, P);                 // corrector -> P, balt
-  launch_registers(L, c->f, c->e, scale, (s % (2 << lev)) == 0 ? 1 : 0, c->reg, p.rs, p.rs2);
+  launch_registers(L, c->regs + p.reg_off[lev], p.reg_off[lev + 1] - p.reg_off[lev], c->f, c->e,
+                   scale, (s % (2 << lev)) == 0 ? 1 : 0, c->regf, p.nregF, c->rege, p.nregE);
   launch_copy_blocks(L, c->balt, B, 3);
 }
 
@@ -1430,12 +1918,16 @@ static void lat_cycle(grmhd_ctx* c) {
   for (int s = 0; s < nsub; s++) {
     for (int lev = p.nlev - 1; lev >= 0; lev--)
       if (s % (1 << lev) == 0) lat_level_step(c, L, lev, s);
-    for (int lev = 1; lev < p.nlev; lev++)
-      if ((s + 1) % (1 << lev) == 0) {
-        const int64_t o = p.item_off[lev], n = p.item_off[lev + 1] - o;
-        launch_sync(L, c->items + o, (int)n, c->bufs.prim, c->bufs.bface, c->reg, p.rs, p.rs2,
-                    c->ubuf);
-      }
+    // the levels whose step ends here (1 .. m, independent of each other), one launch each
+    // of cells, faces and re-inversion over their concatenated lists
+    int m = 0;
+    while (m + 1 < p.nlev && (s + 1) % (1 << (m + 1)) == 0) m++;
+    if (m > 0) {
+      const int64_t co = p.scell_off[1], nc = p.scell_off[m + 1] - co;
+      const int64_t fo = p.sface_off[1], nf = p.sface_off[m + 1] - fo;
+      launch_sync(L, c->scells + co, nc, c->sfaces + fo, nf, c->bufs.prim, c->bufs.bface, c->regf,
+                  p.nregF, c->rege, p.nregE, c->ubuf);
+    }
   }
   launch_tsim_cycle(L, (double)nsub);
 }
@@ -1682,7 +2174,7 @@ int grmhd_divb(grmhd_ctx* c, double* max_abs, double* max_rel, double* field) {
 
 int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes) {
   if (!bytes) return fail(GRMHD_EINVAL, "NULL argument");
-  if (what < 0 || what > 11) return fail(GRMHD_EINVAL, "unknown table");
+  if (what < 0 || what > 19) return fail(GRMHD_EINVAL, "unknown table");
   Plan p;
   int rc = build_plan(desc, p, true);
   if (rc) return rc;
@@ -1698,10 +2190,14 @@ int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, s
         if (s % (1 << lev) == 0)
           for (int64_t q = p.lev_boff[lev]; q < p.lev_boff[lev + 1]; q++)
             sched.insert(sched.end(), {s, 0, lev, p.lev_blocks[q]});
-      for (int lev = 1; lev < L; lev++)
-        if ((s + 1) % (1 << lev) == 0)
-          for (int64_t q = p.item_off[lev]; q < p.item_off[lev + 1]; q++)
-            sched.insert(sched.end(), {s, 1, lev, p.items[q].slow});
+      std::vector<char> syncs(p.blocks.size(), 0);
+      for (const Plan::Reflux& r : p.reflux) syncs[r.b] = 1;
+      for (const Plan::EdgeRef& e : p.sync_edges) syncs[e.b] = 1;
+      for (size_t b = 0; b < p.blocks.size(); b++) {
+        const int lev = p.blocks[b].lat;
+        if (lev > 0 && syncs[b] && (s + 1) % (1 << lev) == 0)
+          sched.insert(sched.end(), {s, 1, lev, (int32_t)b});
+      }
     }
     src = sched.data();
     need = sched.size() * sizeof(int32_t);
@@ -1721,6 +2217,16 @@ int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, s
     }
     src = sched.data();
     need = sched.size() * sizeof(int32_t);
+  } else if (what >= 15 && what <= 19) {
+    // the device lists as uploaded (raw structures): 15 stage means, 16 face means,
+    // 17 register items, 18 sync cells, 19 sync faces
+    switch (what) {
+      case 15: src = p.fix.data(); need = p.fix.size() * sizeof(MeanItem); break;
+      case 16: src = p.bsync.data(); need = p.bsync.size() * sizeof(MeanItem); break;
+      case 17: src = p.regs.data(); need = p.regs.size() * sizeof(RegItem); break;
+      case 18: src = p.scells.data(); need = p.scells.size() * sizeof(SyncCell); break;
+      default: src = p.sfaces.data(); need = p.sfaces.size() * sizeof(SyncFace); break;
+    }
   } else if (what < 4) {
     src = p.ops[what].data();
     need = p.ops[what].size() * sizeof(GhostOp);
@@ -1730,9 +2236,26 @@ int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, s
   } else if (what == 8) {
     src = p.samples.data();
     need = p.samples.size() * sizeof(AmrSample);
+  } else if (what == 9) {
+    // refinement faces at one time level: coarse, fine, d, side, e[3], lo[3], hi[3]
+    for (const Plan::Link& lk : p.links)
+      sched.insert(sched.end(), {lk.c, lk.f, lk.d, lk.side, lk.e[0], lk.e[1], lk.e[2],
+                                 (int32_t)lk.lo[0], (int32_t)lk.lo[1], (int32_t)lk.lo[2],
+                                 (int32_t)lk.hi[0], (int32_t)lk.hi[1], (int32_t)lk.hi[2]});
+    src = sched.data();
+    need = sched.size() * sizeof(int32_t);
+  } else if (what == 12) {
+    // reflux faces: block, d, side, local face, faster block, count, its elements[4]
+    for (const Plan::Reflux& r : p.reflux)
+      sched.insert(sched.end(), {r.b, r.d, r.side, r.loc, r.D, r.n, r.sub[0], r.sub[1], r.sub[2], r.sub[3]});
+    src = sched.data();
+    need = sched.size() * sizeof(int32_t);
   } else {
-    src = p.links.data();
-    need = p.links.size() * sizeof(AmrLink);
+    // 13 sync edges, 14 stage edges: block, a, local edge, holder, count, its elements[2]
+    for (const Plan::EdgeRef& e : what == 13 ? p.sync_edges : p.stage_edges)
+      sched.insert(sched.end(), {e.b, e.a, e.loc, e.D, e.n, e.sub[0], e.sub[1]});
+    src = sched.data();
+    need = sched.size() * sizeof(int32_t);
   }
   if (!host_buf) {
     *bytes = need;

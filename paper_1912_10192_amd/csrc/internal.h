@@ -68,26 +68,61 @@ struct AmrSample {
 };
 enum { AM_PDIMS = 7, AM_UPPER_SHIFT = 4, AM_TWO = 256, AM_FLAGS_SHIFT = 16 };
 
-// A face shared by a coarse block and a block one level finer at the same time level:
-// the coarse fluxes and EMFs on it are replaced by the fine ones, and the coarse copy of
-// the face by the mean of the fine faces.  lo/hi bound the shared patch in the coarse
-// block's padded local indices (transverse dimensions); cplane/fplane are the local face
-// indices of the plane in the coarse and fine blocks; fmap maps a coarse local index to
-// the fine local index of its first child: fine = 2^e (coarse - ng + corg) - forg + ng.
-struct AmrLink {
-  int32_t coarse, fine, d, e;      // e: refined dimensions (bits)
-  int32_t lo[3], hi[3];
-  int32_t cplane, fplane;
-  int32_t corg[3], forg[3];
-  int32_t npos;                    // faces + edges handled for this link
-  int32_t pad;
+// A value that is the mean of n (1, 2 or 4) elements of one array, per component:
+//   X[dst + q dstride] = (sum_i X[src_i + q sstride]) / n,  q < ncomp.
+// Used where a block takes the values of a finer block of its own time level in each
+// stage: kind 0 the face fluxes of a refinement face (8 components), kind 1 the EMF of
+// an edge whose finest holder is finer (1 component), kind 2 the coarse copy of a
+// refinement face (the face field, after the update).  Sources are never destinations
+// of the same list, so the items of one list run in any order.
+struct MeanItem {
+  int64_t dst;
+  int64_t src[4];
+  int32_t n, ncomp, dstride, sstride;
+  int32_t kind, pad;
 };
 
-// one plane shared by a slower block and its faster x1 neighbour (side 0 = the slow
-// block's lower x1 face, 1 = upper)
-struct SyncItem {
-  int32_t slow, fast, side, pad;
+// One element a block's corrector contributes to the time-integrated registers: kind 0
+// the face flux at element src of F (the six conserved components 0-4 and 7, stride
+// apart), kind 1 the EMF at element src of E.  Slot `slot` of the flux or EMF registers:
+// step set = dt value, pair set = sum over the two steps a slower neighbour spans.
+struct RegItem {
+  int64_t src;
+  int32_t slot, kind, stride, pad;
 };
+
+// End of a slower block's step, per cell whose conserved state or faces change:
+// the cell (block, padded local index) and up to three flux corrections, one per
+// boundary face of the cell shared with a faster block:
+//   dU += (mine - mean(theirs)) / dx * sgn
+// with mine the step register of the block's own face and theirs the pair registers of
+// the faster block's sub-faces (nth of them).
+struct FluxTerm {
+  int32_t mine, th[4], nth, sgn, pad;
+  double dx;
+};
+struct SyncCell {
+  int32_t blk, loc, nt, pad;
+  FluxTerm t[3];
+};
+// ... and per face of the slower block that changes: constrained-transport corrections
+// from up to four edges whose dominant holder is faster,
+//   B += sgn (mean(theirs) - mine) / dx
+// or (ncopy > 0) the faster block's copy of a shared face: the mean of its ncopy faces
+// at local indices csrc of block cblk (the same component), which takes precedence.
+struct EdgeTerm {
+  int32_t mine, th[2], nth, sgn, pad;
+  double dx;
+};
+struct SyncFace {
+  int32_t blk, comp, loc, nt;
+  int32_t cblk, ncopy, csrc[4];
+  EdgeTerm t[4];
+};
+
+static_assert(sizeof(MeanItem) == 64 && sizeof(RegItem) == 24 && sizeof(SyncCell) == 136 &&
+                  sizeof(SyncFace) == 168,
+              "list layouts as exported by grmhd_plan_dump");
 
 // geometry tables: SoA [quantity][column]; one table per pair of x1/x2 refinement
 // levels, column = gbase + j * gti + i of the block's table
@@ -208,9 +243,8 @@ void launch_amr_ghosts(const Launch& L, const AmrLists& A, const AmrSample* samp
                        const double* Pmain, const double* Pold, const double* Pcur, double* Pdst,
                        const double* Bmain, const double* Bold, const double* Bcur, double* Bdst,
                        double w);
-void launch_amr_fix(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* F,
-                    double* E);
-void launch_amr_bsync(const Launch& L, const AmrLink* links, int nlinks, int maxpos, double* B);
+// the items of a mean list: kind 0 items on X0, the others on X1
+void launch_means(const Launch& L, const MeanItem* items, int64_t n, double* X0, double* X1);
 // local time stepping (lat.hip)
 void launch_ghosts_t(const Launch& L, const GhostLists& G, const double* Pmain,
                      const double* Pold, const double* Pcur, double* Pdst, const double* Bmain,
@@ -219,10 +253,14 @@ void launch_copy_blocks(const Launch& L, const double* src, double* dst, int nva
 void launch_copy_list(const Launch& L, const uint32_t* ic, int64_t nc, const double* P,
                       double* Pdst, const uint32_t* jf, int64_t nf, const double* B,
                       double* Bdst);
-void launch_registers(const Launch& L, const double* F, const double* E, double dt_factor,
-                      int first, double* reg, int rs, int rs2);
-void launch_sync(const Launch& L, const SyncItem* items, int nitems, double* P, double* B,
-                 const double* reg, int rs, int rs2, double* Ubuf);
+// registers of one level's corrector: regF [2][6][nf] (step, pair), regE [2][ne]
+void launch_registers(const Launch& L, const RegItem* items, int64_t n, const double* F,
+                      const double* E, double dt_factor, int first, double* regF, int64_t nf,
+                      double* regE, int64_t ne);
+// end-of-step synchronisation of slower blocks: cells and faces of the levels due
+void launch_sync(const Launch& L, const SyncCell* cells, int64_t ncell, const SyncFace* faces,
+                 int64_t nface, double* P, double* B, const double* regF, int64_t nf,
+                 const double* regE, int64_t ne, double* Ubuf);
 void launch_dt_final_lat(const Launch& L, const double* part, int64_t n, int gridx);
 void launch_tsim_cycle(const Launch& L, double substeps);
 void launch_c2p_batch(int64_t n, const double* U, const double* geom, const double* guess,

@@ -3,13 +3,15 @@
 // Blocks carry a time level; a level-l block steps with dt_min 2^l.  The kernels here
 // (1) fill ghosts whose sources run at another time level -- a slower neighbour is
 //     interpolated linearly in time between its stored start state and its end state,
-// (2) accumulate the time-integrated x1 fluxes and edge EMFs a block used on its x1
-//     boundary planes, over its own step and over two of its steps,
-// (3) at the end of a slower block's step, replace on each plane shared with a faster
-//     neighbour the fluxes and EMFs it used by the faster side's integrals: conserved
-//     update of the boundary cells, constrained-transport correction of the faces that
-//     touch the shared edges, the faster side's copy of the shared faces, and a new
-//     inversion of the corrected cells.
+// (2) accumulate the time-integrated fluxes and edge EMFs that synchronisation reads
+//     (listed elements on block boundaries), over a block's own step and over two of its
+//     steps,
+// (3) at the end of a slower block's step, replace the fluxes it used on faces shared
+//     with a faster block by the faster side's time integrals (area means where the
+//     faster side is finer), the EMFs of its edges whose dominant holder is faster by
+//     that holder's integrals with constrained-transport correction of the faces around
+//     them, give shared faces the faster copy, and invert every changed cell again.
+// Time levels are independent of refinement levels and of the direction of a face.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -121,149 +123,141 @@ __global__ __launch_bounds__(LT) void k_copy_list(const uint32_t* __restrict__ i
 
 // ------------------------------------------------------------------ registers
 
-// per listed block and x1 side: dt-weighted corrector fluxes (8 components) on the x1
-// boundary faces and EMFs E^2, E^3 on the x1 boundary edges; set 0 holds this step,
-// set 1 the sum over a pair of steps (restarted when `first` is set)
-__global__ __launch_bounds__(LT) void k_registers(Launch L, const double* __restrict__ F,
+// One listed element per thread, from the corrector of a level's blocks: the dt-weighted
+// face flux (six conserved components) or edge EMF, into the step set and the pair set
+// (restarted when `first` is set, else summed).
+__global__ __launch_bounds__(LT) void k_registers(const RegItem* __restrict__ items, int64_t n,
+                                                  const double* __restrict__ F,
                                                   const double* __restrict__ E, double dt_factor,
-                                                  int first, double* __restrict__ reg, int rs,
-                                                  int rs2) {
-  const int b = L.blist[blockIdx.y];
-  const BlockInfo bi = L.blk[b];
-  const int g = L.ph.ng;
-  const int t = blockIdx.x * LT + threadIdx.x;
-  const int n2 = bi.n[1], n3 = bi.n[2];
-  if (t >= 2 * (n3 + 1) * (n2 + 1)) return;
-  const int side = t / ((n3 + 1) * (n2 + 1));
-  const int r = t % ((n3 + 1) * (n2 + 1));
-  const int K = r / (n2 + 1), J = r % (n2 + 1);
-  const double dt = dt_factor * L.ph.courant * __longlong_as_double((long long)L.cnt->dt_bits);
-  const int I = side == 0 ? g : g + bi.n[0];
-  const int64_t V = bi.vol;
-  const int64_t loc = ((int64_t)(K + g) * bi.np[1] + (J + g)) * bi.np[0] + I;
-  double* st = reg + (((int64_t)b * 2 + 0) * 2 + side) * 10 * rs;
-  double* pr = reg + (((int64_t)b * 2 + 1) * 2 + side) * 10 * rs;
-  const int o = K * rs2 + J;
-  auto put = [&](int q, double v) {
-    st[q * rs + o] = v;
-    pr[q * rs + o] = first ? v : pr[q * rs + o] + v;
-  };
-  if (J < n2 && K < n3)
-    for (int q = 0; q < 8; q++) put(q, dt * F[24 * bi.off + (int64_t)q * V + loc]);
-  if (J < n2) put(8, dt * E[3 * bi.off + V + loc]);
-  if (K < n3) put(9, dt * E[3 * bi.off + 2 * V + loc]);
+                                                  double courant, const Counters* __restrict__ cnt,
+                                                  int first, double* __restrict__ regF, int64_t nf,
+                                                  double* __restrict__ regE, int64_t ne) {
+  const int64_t t = (int64_t)blockIdx.x * LT + threadIdx.x;
+  if (t >= n) return;
+  const RegItem it = items[t];
+  const double dt = dt_factor * courant * __longlong_as_double((long long)cnt->dt_bits);
+  if (it.kind == 0) {
+    constexpr int fq[6] = {0, 1, 2, 3, 4, 7};
+#pragma unroll
+    for (int q = 0; q < 6; q++) {
+      const double v = dt * F[it.src + (int64_t)fq[q] * it.stride];
+      const int64_t o = (int64_t)q * nf + it.slot;
+      regF[o] = v;
+      regF[6 * nf + o] = first ? v : regF[6 * nf + o] + v;
+    }
+  } else {
+    const double v = dt * E[it.src];
+    regE[it.slot] = v;
+    regE[ne + it.slot] = first ? v : regE[ne + it.slot] + v;
+  }
 }
 
-// ------------------------------------------------------------------ reflux
+// ------------------------------------------------------------------ synchronisation
 
-// conserved state of the boundary-layer cells of each sync item, before the face
-// corrections: U(P, B_old) plus the flux correction (mine - theirs)/dx1 * sign
-__global__ __launch_bounds__(LT) void k_sync_u(Launch L, const SyncItem* __restrict__ items,
-                                               const double* __restrict__ P,
+__device__ __forceinline__ int64_t cell_stride(const BlockInfo& bi, int d) {
+  return d == 0 ? 1 : (d == 1 ? (int64_t)bi.np[0] : (int64_t)bi.np[0] * bi.np[1]);
+}
+
+// Conserved state of each listed cell before its faces change: U(P, B) plus the flux
+// corrections (mine - mean(theirs)) / dx * sgn summed over the cell's terms.
+__global__ __launch_bounds__(LT) void k_sync_u(Launch L, const SyncCell* __restrict__ cells,
+                                               int64_t ncell, const double* __restrict__ P,
                                                const double* __restrict__ B,
-                                               const double* __restrict__ reg, int rs, int rs2,
-                                               double* __restrict__ Ubuf, int layer) {
-  const SyncItem it = items[blockIdx.y];
-  const BlockInfo bi = L.blk[it.slow];
-  const int g = L.ph.ng;
-  const int t = blockIdx.x * LT + threadIdx.x;
-  const int n2 = bi.n[1], n3 = bi.n[2];
-  if (t >= n2 * n3) return;
-  const int K = t / n2 + g, J = t % n2 + g;
-  const int I = it.side == 0 ? g : g + bi.n[0] - 1;
+                                               const double* __restrict__ regF, int64_t nf,
+                                               double* __restrict__ Ubuf) {
+  const int64_t t = (int64_t)blockIdx.x * LT + threadIdx.x;
+  if (t >= ncell) return;
+  const SyncCell sc = cells[t];
+  const BlockInfo bi = L.blk[sc.blk];
   const int64_t V = bi.vol;
-  const int64_t l = ((int64_t)K * bi.np[1] + J) * bi.np[0] + I;
-  const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
+  const int64_t l = sc.loc;
+  const int I = (int)(l % bi.np[0]);
+  const int J = (int)((l / bi.np[0]) % bi.np[1]);
   const int64_t col = geo_col(L.geo, bi, J, I);
   const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
   double p[5], bc[3], U[9];
   for (int v = 0; v < 5; v++) p[v] = P[5 * bi.off + v * V + l];
   const double* b = B + 3 * bi.off;
   bc[0] = 0.5 * (b[l] + b[l + 1]) / m.gdet;
-  bc[1] = 0.5 * (b[V + l] + b[V + l + s2]) / m.gdet;
-  bc[2] = 0.5 * (b[2 * V + l] + b[2 * V + l + s3]) / m.gdet;
+  bc[1] = 0.5 * (b[V + l] + b[V + l + cell_stride(bi, 1)]) / m.gdet;
+  bc[2] = 0.5 * (b[2 * V + l] + b[2 * V + l + cell_stride(bi, 2)]) / m.gdet;
   Fluid f;
   fluid_state(p, bc, m, f);
   flux_vector<0>(p, f, m, L.ph.gam, entropy_kappa(p, L.ph.gam), U);
-  const double* mine = reg + (((int64_t)it.slow * 2 + 0) * 2 + it.side) * 10 * rs;
-  const double* theirs = reg + (((int64_t)it.fast * 2 + 1) * 2 + (1 - it.side)) * 10 * rs;
-  const int o = (K - g) * rs2 + (J - g);
-  const double sgn = it.side == 1 ? 1.0 : -1.0;
-  constexpr int fq[6] = {0, 1, 2, 3, 4, 7};
   constexpr int uq[6] = {0, 1, 2, 3, 4, 8};
-  for (int k = 0; k < 6; k++)
-    U[uq[k]] += (mine[fq[k] * rs + o] - theirs[fq[k] * rs + o]) / bi.dx[0] * sgn;
-  double* u = Ubuf + ((int64_t)blockIdx.y * layer + t) * 9;
+  double dU[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < sc.nt; k++) {
+    const FluxTerm ft = sc.t[k];
+    const double inv = 1.0 / ft.nth;
+    const double sg = ft.sgn > 0 ? 1.0 : -1.0;
+    for (int q = 0; q < 6; q++) {
+      double th = 0.0;
+      for (int i = 0; i < ft.nth; i++) th = th + regF[6 * nf + (int64_t)q * nf + ft.th[i]];
+      th = th * inv;
+      dU[q] = dU[q] + (regF[(int64_t)q * nf + ft.mine] - th) / ft.dx * sg;
+    }
+  }
+  for (int q = 0; q < 6; q++) U[uq[q]] += dU[q];
+  double* u = Ubuf + t * 9;
   for (int q = 0; q < 9; q++) u[q] = U[q];
 }
 
-// constrained-transport correction of the slow side's faces touching the shared edges,
-// and the faster side's copy of the shared faces
-__global__ __launch_bounds__(LT) void k_sync_faces(Launch L, const SyncItem* __restrict__ items,
-                                                   double* __restrict__ B,
-                                                   const double* __restrict__ reg, int rs,
-                                                   int rs2) {
-  const SyncItem it = items[blockIdx.y];
-  const BlockInfo bi = L.blk[it.slow];
-  const BlockInfo fi = L.blk[it.fast];
-  const int g = L.ph.ng;
-  const int t = blockIdx.x * LT + threadIdx.x;
-  const int n2 = bi.n[1], n3 = bi.n[2];
-  if (t >= (n2 + 1) * (n3 + 1)) return;
-  const int kk = t / (n2 + 1), jj = t % (n2 + 1);
-  const int K = kk + g, J = jj + g;
-  const int Ic = it.side == 0 ? g : g + bi.n[0] - 1;
-  const int If = it.side == 0 ? g : g + bi.n[0];
-  const int Iff = it.side == 0 ? g + fi.n[0] : g;   // the same face in the faster block
-  const int64_t V = bi.vol;
-  const double sgn = it.side == 1 ? 1.0 : -1.0;
-  const double* mine = reg + (((int64_t)it.slow * 2 + 0) * 2 + it.side) * 10 * rs;
-  const double* theirs = reg + (((int64_t)it.fast * 2 + 1) * 2 + (1 - it.side)) * 10 * rs;
-  const int o = kk * rs2 + jj;
-  double* b = B + 3 * bi.off;
-  const int64_t lc = ((int64_t)K * bi.np[1] + J) * bi.np[0] + Ic;
-  if (kk < n3) {   // x2 faces of the layer, j in [g, g + n2]
-    const double dE3 = theirs[9 * rs + o] - mine[9 * rs + o];
-    b[V + lc] += sgn * dE3 / bi.dx[0];
+// New values of the listed faces: the faster block's copy of a shared face, else the
+// face plus the constrained-transport corrections sgn (mean(theirs) - mine) / dx of its
+// edges.  Every face is listed once and no item reads a face another item writes.
+__global__ __launch_bounds__(LT) void k_sync_faces(Launch L, const SyncFace* __restrict__ faces,
+                                                   int64_t nface, double* __restrict__ B,
+                                                   const double* __restrict__ regE, int64_t ne) {
+  const int64_t t = (int64_t)blockIdx.x * LT + threadIdx.x;
+  if (t >= nface) return;
+  const SyncFace sf = faces[t];
+  const BlockInfo bi = L.blk[sf.blk];
+  double* dst = B + 3 * bi.off + (int64_t)sf.comp * bi.vol + sf.loc;
+  if (sf.ncopy > 0) {
+    const BlockInfo ci = L.blk[sf.cblk];
+    const double* src = B + 3 * ci.off + (int64_t)sf.comp * ci.vol;
+    double acc = 0.0;
+    for (int i = 0; i < sf.ncopy; i++) acc = acc + src[sf.csrc[i]];
+    *dst = acc * (1.0 / sf.ncopy);
+    return;
   }
-  if (jj < n2) {   // x3 faces of the layer, k in [g, g + n3]
-    const double dE2 = theirs[8 * rs + o] - mine[8 * rs + o];
-    b[2 * V + lc] -= sgn * dE2 / bi.dx[0];
+  double x = *dst;
+  for (int k = 0; k < sf.nt; k++) {
+    const EdgeTerm et = sf.t[k];
+    double th = 0.0;
+    for (int i = 0; i < et.nth; i++) th = th + regE[ne + et.th[i]];
+    th = th * (1.0 / et.nth);
+    const double dE = th - regE[et.mine];
+    x += (et.sgn > 0 ? dE : -dE) / et.dx;
   }
-  if (kk < n3 && jj < n2) {
-    const int64_t lf = ((int64_t)K * bi.np[1] + J) * bi.np[0] + If;
-    const int64_t lff = ((int64_t)K * fi.np[1] + J) * fi.np[0] + Iff;
-    b[lf] = B[3 * fi.off + lff];
-  }
+  *dst = x;
 }
 
-// new inversion of the corrected boundary-layer cells (guess: their primitives), floors
-__global__ __launch_bounds__(LT) void k_sync_c2p(Launch L, const SyncItem* __restrict__ items,
-                                                 double* __restrict__ P,
+// New inversion of the listed cells (guess: their primitives) from the corrected
+// conserved state and the corrected faces, then floors.
+__global__ __launch_bounds__(LT) void k_sync_c2p(Launch L, const SyncCell* __restrict__ cells,
+                                                 int64_t ncell, double* __restrict__ P,
                                                  const double* __restrict__ B,
-                                                 const double* __restrict__ Ubuf, int layer) {
-  const SyncItem it = items[blockIdx.y];
-  const BlockInfo bi = L.blk[it.slow];
-  const int g = L.ph.ng;
-  const int t = blockIdx.x * LT + threadIdx.x;
-  const int n2 = bi.n[1], n3 = bi.n[2];
-  const bool valid = t < n2 * n3;
+                                                 const double* __restrict__ Ubuf) {
+  const int64_t t = (int64_t)blockIdx.x * LT + threadIdx.x;
+  const bool valid = t < ncell;
   int tier = 0, hits = 0;
   if (valid) {
-    const int K = t / n2 + g, J = t % n2 + g;
-    const int I = it.side == 0 ? g : g + bi.n[0] - 1;
+    const SyncCell sc = cells[t];
+    const BlockInfo bi = L.blk[sc.blk];
     const int64_t V = bi.vol;
-    const int64_t l = ((int64_t)K * bi.np[1] + J) * bi.np[0] + I;
-    const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
+    const int64_t l = sc.loc;
+    const int I = (int)(l % bi.np[0]);
+    const int J = (int)((l / bi.np[0]) % bi.np[1]);
     const int64_t col = geo_col(L.geo, bi, J, I);
     const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
     double U[9], p[5];
-    const double* u = Ubuf + ((int64_t)blockIdx.y * layer + t) * 9;
+    const double* u = Ubuf + t * 9;
     for (int q = 0; q < 9; q++) U[q] = u[q];
     const double* b = B + 3 * bi.off;
     U[5] = 0.5 * (b[l] + b[l + 1]);
-    U[6] = 0.5 * (b[V + l] + b[V + l + s2]);
-    U[7] = 0.5 * (b[2 * V + l] + b[2 * V + l + s3]);
+    U[6] = 0.5 * (b[V + l] + b[V + l + cell_stride(bi, 1)]);
+    U[7] = 0.5 * (b[2 * V + l] + b[2 * V + l + cell_stride(bi, 2)]);
     for (int v = 0; v < 5; v++) p[v] = P[5 * bi.off + v * V + l];
     C2PIn cs;
     c2p_setup(U, m, L.ph.gam, cs);
@@ -335,24 +329,27 @@ void launch_copy_list(const Launch& L, const uint32_t* ic, int64_t nc, const dou
                      jf, nf, B, Bdst);
 }
 
-void launch_registers(const Launch& L, const double* F, const double* E, double dt_factor,
-                      int first, double* reg, int rs, int rs2) {
-  const int64_t r = 2LL * (L.max_n[2] + 1) * (L.max_n[1] + 1);
-  hipLaunchKernelGGL(k_registers, dim3(cdv(r, LT), L.nblk), dim3(LT), 0, L.stream, L, F, E,
-                     dt_factor, first, reg, rs, rs2);
+void launch_registers(const Launch& L, const RegItem* items, int64_t n, const double* F,
+                      const double* E, double dt_factor, int first, double* regF, int64_t nf,
+                      double* regE, int64_t ne) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_registers, dim3(cdv(n, LT)), dim3(LT), 0, L.stream, items, n, F, E,
+                     dt_factor, L.ph.courant, L.cnt, first, regF, nf, regE, ne);
 }
 
-void launch_sync(const Launch& L, const SyncItem* items, int nitems, double* P, double* B,
-                 const double* reg, int rs, int rs2, double* Ubuf) {
-  if (nitems == 0) return;
-  const int layer = L.max_n[1] * L.max_n[2];
-  const int faces = (L.max_n[1] + 1) * (L.max_n[2] + 1);
-  hipLaunchKernelGGL(k_sync_u, dim3(cdv(layer, LT), nitems), dim3(LT), 0, L.stream, L, items, P, B,
-                     reg, rs, rs2, Ubuf, layer);
-  hipLaunchKernelGGL(k_sync_faces, dim3(cdv(faces, LT), nitems), dim3(LT), 0, L.stream, L, items, B,
-                     reg, rs, rs2);
-  hipLaunchKernelGGL(k_sync_c2p, dim3(cdv(layer, LT), nitems), dim3(LT), 0, L.stream, L, items, P, B,
-                     Ubuf, layer);
+void launch_sync(const Launch& L, const SyncCell* cells, int64_t ncell, const SyncFace* faces,
+                 int64_t nface, double* P, double* B, const double* regF, int64_t nf,
+                 const double* regE, int64_t ne, double* Ubuf) {
+  if (ncell + nface == 0) return;
+  if (ncell > 0)
+    hipLaunchKernelGGL(k_sync_u, dim3(cdv(ncell, LT)), dim3(LT), 0, L.stream, L, cells, ncell, P,
+                       B, regF, nf, Ubuf);
+  if (nface > 0)
+    hipLaunchKernelGGL(k_sync_faces, dim3(cdv(nface, LT)), dim3(LT), 0, L.stream, L, faces, nface,
+                       B, regE, ne);
+  if (ncell > 0)
+    hipLaunchKernelGGL(k_sync_c2p, dim3(cdv(ncell, LT)), dim3(LT), 0, L.stream, L, cells, ncell,
+                       P, B, Ubuf);
 }
 
 void launch_dt_final_lat(const Launch& L, const double* part, int64_t n, int gridx) {

@@ -204,13 +204,22 @@ class Desc:
         _check(lib().grmhd_block_layout(C.byref(self.d), b, C.byref(off), np_))
         return off.value, tuple(np_)
 
+    def plan_raw(self, what):
+        """raw bytes of a device list (plan_dump 15..19)"""
+        nbytes = C.c_size_t()
+        _check(lib().grmhd_plan_dump(C.byref(self.d), what, None, C.byref(nbytes)))
+        buf = np.zeros(nbytes.value, dtype=np.uint8)
+        _check(lib().grmhd_plan_dump(C.byref(self.d), what, buf.ctypes.data_as(C.c_void_p),
+                                     C.byref(nbytes)))
+        return buf
+
     def plan_dump(self, what):
         nbytes = C.c_size_t()
         _check(lib().grmhd_plan_dump(C.byref(self.d), what, None, C.byref(nbytes)))
         buf = np.zeros(nbytes.value // 4, dtype=np.int32)
         _check(lib().grmhd_plan_dump(C.byref(self.d), what, buf.ctypes.data_as(C.c_void_p),
                                      C.byref(nbytes)))
-        return buf.reshape(-1, 20 if what == 9 else 4)
+        return buf.reshape(-1, {9: 13, 12: 10, 13: 7, 14: 7}.get(what, 4))
 
 
 def geometry_point(coords, a, x1, x2):
