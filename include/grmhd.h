@@ -270,6 +270,19 @@ int grmhd_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t st
                          const float* X, const float* Y, const int32_t* idx, int32_t batch,
                          float lr, float* work, float* loss, void* hip_stream);
 
+/* The same training step for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight training loops, harnesses that forbid hipMalloc): the
+ * training scratch lives in a static device array of the library, sized for batches of
+ * at most GRMHD_MLP_NOALLOC_MAX_BATCH rows (about 11 MB, one copy per device, held until
+ * the process ends).  No allocation of any kind happens on this path.  Larger batches
+ * return GRMHD_EINVAL.  All calls on one device share that array: calls that overlap on
+ * one device (two streams, two threads) race and must be serialised by the caller.
+ * Results are those of grmhd_mlp_train_step on the same inputs. */
+#define GRMHD_MLP_NOALLOC_MAX_BATCH 8192
+int grmhd_mlp_train_step_noalloc(float* params, float* adam_m, float* adam_v, int32_t step,
+                                 const float* X, const float* Y, const int32_t* idx,
+                                 int32_t batch, float lr, float* loss, void* hip_stream);
+
 /* Gradients of the same loss without updating (grad_out: n_params floats). */
 int grmhd_mlp_gradients(const float* params, const float* X, const float* Y,
                         const int32_t* idx, int32_t batch, float* work, float* grad_out,

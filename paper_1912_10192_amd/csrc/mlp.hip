@@ -13,6 +13,8 @@
 // K = rows) split K across workgroups (k_wgrad) and add the chunks in order.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -381,13 +383,12 @@ int grmhd_mlp_sizes(int32_t batch, size_t* n_params, size_t* blob_bytes, size_t*
   return GRMHD_OK;
 }
 
-int grmhd_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step,
-                         const float* X, const float* Y, const int32_t* idx, int32_t batch,
-                         float lr, float* work, float* loss, void* hip_stream) {
-  if (!params || !adam_m || !adam_v || !X || !Y || !idx || !work || !loss)
-    return mfail(GRMHD_EINVAL, "NULL argument");
-  if (batch < 1 || step < 1) return mfail(GRMHD_EINVAL, "batch and step must be positive");
-  hipStream_t st = (hipStream_t)hip_stream;
+}  // extern "C"
+
+// The training step on a work buffer of at least work_floats(batch) floats.
+static int train_step(float* params, float* adam_m, float* adam_v, int32_t step, const float* X,
+                      const float* Y, const int32_t* idx, int32_t batch, float lr, float* work,
+                      float* loss, hipStream_t st) {
   const int B = batch;
   float* H1 = work;
   float* H2 = H1 + (size_t)B * 64;
@@ -435,6 +436,61 @@ int grmhd_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t st
                      MLP_NPARAM, lr, b1t, b2t);
   if (hipGetLastError() != hipSuccess) return mfail(GRMHD_EHIP, "kernel launch failed");
   return GRMHD_OK;
+}
+
+// Work buffer of the allocation-free training step, sized for the largest batch it
+// takes; one copy per device, held until the process ends.  Every kernel of a step
+// writes the part it reads later, so nothing needs clearing between calls.
+constexpr int64_t NOALLOC_B = GRMHD_MLP_NOALLOC_MAX_BATCH;
+constexpr size_t NOALLOC_FLOATS =
+    (size_t)(3 * NOALLOC_B * 64 + NOALLOC_B * 2 + 2 * NOALLOC_B * 64 + MLP_NPARAM +
+             (NOALLOC_B * 2 + MT - 1) / MT + 64 + (NOALLOC_B + KC - 1) / KC * (64 * 64 + 64));
+static __device__ __align__(256) float scratch[NOALLOC_FLOATS];
+
+// device address of `scratch` per device index, taken once with that device current
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch[NOALLOC_MAX_DEVICES] = {};
+
+static int scratch_address(float** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return mfail(GRMHD_EHIP, "hipGetDevice failed");
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return mfail(GRMHD_EUNSUPPORTED, "device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return mfail(GRMHD_EHIP, "hipGetSymbolAddress(scratch) failed");
+    g_scratch[dev] = (float*)ptr;
+  }
+  *out = g_scratch[dev];
+  return GRMHD_OK;
+}
+
+extern "C" {
+
+int grmhd_mlp_train_step(float* params, float* adam_m, float* adam_v, int32_t step,
+                         const float* X, const float* Y, const int32_t* idx, int32_t batch,
+                         float lr, float* work, float* loss, void* hip_stream) {
+  if (!params || !adam_m || !adam_v || !X || !Y || !idx || !work || !loss)
+    return mfail(GRMHD_EINVAL, "NULL argument");
+  if (batch < 1 || step < 1) return mfail(GRMHD_EINVAL, "batch and step must be positive");
+  return train_step(params, adam_m, adam_v, step, X, Y, idx, batch, lr, work, loss,
+                    (hipStream_t)hip_stream);
+}
+
+int grmhd_mlp_train_step_noalloc(float* params, float* adam_m, float* adam_v, int32_t step,
+                                 const float* X, const float* Y, const int32_t* idx,
+                                 int32_t batch, float lr, float* loss, void* hip_stream) {
+  if (!params || !adam_m || !adam_v || !X || !Y || !idx || !loss)
+    return mfail(GRMHD_EINVAL, "NULL argument");
+  if (batch < 1 || step < 1) return mfail(GRMHD_EINVAL, "batch and step must be positive");
+  if (batch > GRMHD_MLP_NOALLOC_MAX_BATCH)
+    return mfail(GRMHD_EINVAL, "batch exceeds GRMHD_MLP_NOALLOC_MAX_BATCH");
+  float* work = nullptr;
+  if (int rc = scratch_address(&work)) return rc;
+  return train_step(params, adam_m, adam_v, step, X, Y, idx, batch, lr, work, loss,
+                    (hipStream_t)hip_stream);
 }
 
 int grmhd_mlp_gradients(const float* params, const float* X, const float* Y, const int32_t* idx,

@@ -29,7 +29,7 @@ EXPORTS = ("grmhd_sizes", "grmhd_block_layout", "grmhd_init_grid", "grmhd_step",
            "grmhd_mlp_sizes", "grmhd_mlp_train_step", "grmhd_mlp_gradients", "grmhd_mlp_pack",
            "grmhd_mlp_forward", "grmhd_prim2cons_batch", "grmhd_mlp_dataset",
            "grmhd_mlp_normalize", "grmhd_extract_cells", "grmhd_destroy", "grmhd_last_error",
-           "grmhd_autotune", "grmhd_set_variants")
+           "grmhd_autotune", "grmhd_set_variants", "grmhd_mlp_train_step_noalloc")
 
 
 class BlockDesc(C.Structure):
@@ -113,6 +113,7 @@ def lib():
         L.grmhd_mlp_sizes.argtypes = [i32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
                                       C.POINTER(C.c_size_t)]
         L.grmhd_mlp_train_step.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, f32, vp, vp, vp]
+        L.grmhd_mlp_train_step_noalloc.argtypes = [vp, vp, vp, i32, vp, vp, vp, i32, f32, vp, vp]
         L.grmhd_mlp_gradients.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp]
         L.grmhd_mlp_pack.argtypes = [vp, vp, vp, vp]
         L.grmhd_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
@@ -542,6 +543,17 @@ class MLPTrainer:
                                           self.v.data_ptr(), self.t, X.data_ptr(), Y.data_ptr(),
                                           idx.data_ptr(), idx.shape[0], lr, self.work.data_ptr(),
                                           self.loss.data_ptr(), _stream(X)))
+
+
+NOALLOC_MAX_BATCH = 8192
+
+
+def mlp_train_step_noalloc(params, m, v, step, X, Y, idx, lr, loss):
+    """one Adam step through the allocation-free entry point (scratch in the library's
+    static device array); params, m, v updated in place, loss[0] receives the batch loss"""
+    _check(lib().grmhd_mlp_train_step_noalloc(params.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                              step, X.data_ptr(), Y.data_ptr(), idx.data_ptr(),
+                                              idx.shape[0], lr, loss.data_ptr(), _stream(X)))
 
 
 def lat_levels_by_radius(cfg, edges):
