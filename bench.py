@@ -1,23 +1,27 @@
 #!/usr/bin/env python3
-"""Benchmark of the GRMHD block update on one MI355X.
+"""Benchmark of the GRMHD block update with refinement and local time stepping on one
+MI355X.
 
-Workload: one GPU's share of a uniform grid -- the Fishbone-Moncrief torus with a
-single-loop field (plasma beta 100) and a seeded 2% u_g perturbation on a 256x128x128
-log-spherical Kerr-Schild grid (a = 0.9375, r in [1.2, 50]), split into 128 blocks of
-32^3, PPM + HLLE, FP64 midpoint steps.  Inputs are resident in HBM before the timed
-region.  Three paths are timed on the same initial state:
-  plain                 global time step, one launch per kernel and stage, plain guess
-  lat_batched           local time stepping with 4 levels by radius, each cycle one
-                        captured graph, plain guess
-  lat_batched_learned   the same with the learned first guess of the inversion
-  polar_smr_lat_batched_learned
-                        the same effective grid with coarser polar bands (half
-                        resolution within pi/4 of the poles, a quarter in phi within
-                        pi/8), reported as refinement-and-LAT-effective zone-cycles/s
-The headline value is the last one's LAT-effective zone-cycles/s (every cell advanced by
-every finest-level step, per second of wall time).  The roofline block reports the
-dominant kernel of the plain run (average launch time from HIP events on the library's
-stream during its timed region); the CPU oracle is timed on a bounded sample.
+Workload: the batched refinement + time-level grid -- the Fishbone-Moncrief torus with a
+single-loop field (plasma beta 100) and a seeded 2% u_g perturbation on an effective
+512x256x256 log-spherical Kerr-Schild grid (a = 0.9375, r in [1.2, 50]) in 1344 blocks
+of 64x32x32, 32x16x16 and 16x8x8 cells, phi halved per level toward each pole (3
+levels), 4 time levels by radius (dt ratios 1:2:4:8), PPM + HLLE, FP64 midpoint steps,
+inversion tolerance 1e-12.  A step is one LAT cycle (8 finest substeps).  Inputs are
+resident in HBM before the timed region.  Paths timed on the same initial state:
+  batched_learned   one launch per time level and kernel class over a work list of the
+                    level's blocks, each cycle one captured graph, learned first guess
+                    of the inversion (the headline)
+  batched           the same with the plain (previous-state) guess
+  plain             one launch per block and kernel class in the same LAT order (the
+                    paper's launch structure), plain guess
+  global_dt         the same blocks on one global time step, batched launches
+The headline value is real zone-cycles/s (cells x their own steps / wall time), the
+median of `runs` runs of exactly `steps` cycles; LAT-effective and refinement-and-LAT-
+effective rates are reported beside it.  The roofline block reports the dominant kernel
+class of a profiled batched run (HIP events on the library's stream), against the
+algorithmic bytes of the method's state.  The CPU oracle runs on a bounded sample on the
+host's cores.
 """
 from __future__ import annotations
 
@@ -25,6 +29,8 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
+import subprocess
 import sys
 import time
 
@@ -33,32 +39,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "zone-cycles/s on 1 MI355X: batched AMR/LAT + learned con2prim vs plain"
 PEAK = {"hbm": 8.0e12, "alu": 78.6e12}        # B/s; FP64 vector flop/s
+WORKLOAD = "torus-eff512x256x256-amr-lat4-1344blocks-ppm-hlle"
 
-# Per-unit algorithmic figures of each kernel class:
-# bytes = the unique HBM bytes a launch must move per unit (each input read once, each
-# output written once); flops = FP64 flops per unit executed by the kernel, counted with
-# the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters (FMA = 2) on this workload and
-# divided by the units of that launch.  Units: faces for flux kernels, interior cells
-# otherwise.  FLOPS entries are valid for the kernel source hash KERNEL_HASH only.
-BYTES_PER_UNIT = {
-    "flux1": 8 * (5 + 2 + 1 + 8), "flux2": 8 * (5 + 2 + 1 + 8), "flux3": 8 * (5 + 2 + 1 + 8),
-    "update": 8 * (5 + 3 + 5 + 3 + 6 * 3 + 3 + 5 + 3),
-    "emf": 8 * (6 + 3), "bcell": 8 * (3 + 3), "dt": 8 * (5 + 3), "ghost": 8 * 2 * 8,
-}
-# (flux entries: the variant the autotuner picked in the profiled run -- one face per
-# thread for x1, two faces per thread for x2 and x3)
-FLOPS_PER_UNIT = {
-    "update": 1592.1, "flux1": 1013.0, "flux2": 899.8, "flux3": 840.7, "emf": 9.8,
-    "bcell": 86.2, "dt": 330.0,
-}
-KERNEL_HASH = "4ccf50f64ad8e3e6"
-# HBM traffic per launch from rocprofv3 FETCH_SIZE/WRITE_SIZE (scaled by the reading of
-# the same counters for a 1 GiB device copy: fetch x2, write x1), keyed like
-# FLOPS_PER_UNIT and valid for KERNEL_HASH only.
-TRAFFIC_PER_LAUNCH = {
-    "update": 1.921e9, "flux1": 7.295e8, "flux2": 7.999e8, "flux3": 7.785e8, "emf": 3.782e8,
-    "bcell": 3.629e8,
-}
+# Algorithmic bytes per unit of each kernel class (units: interior cell-stages for the
+# update, faces for flux kernels).  The update's figure is the method's state only: per
+# zone-cycle 320 B (the predictor reads P^n, B^n and writes P*, B*: 128 B; the corrector
+# reads P*, B*, P^n, B^n and writes P^(n+1), B^(n+1): 192 B), 160 B per cell-stage on
+# average.  Flux kernels: the reconstructed state and the flux they write, 128 B per face
+# (their traffic is an intermediate of the split design).
+BYTES_PER_UNIT = {"update": 160, "flux1": 128, "flux2": 128, "flux3": 128}
+# The design's own bytes per update cell-stage (P^n, B^n, stage P and cell B, the fluxes
+# of six conserved components on one face per direction, 3 EMFs, P and B out).
+DESIGN_BYTES_UPDATE = 8 * (5 + 3 + 5 + 3 + 6 * 3 + 3 + 5 + 3)
+# FP64 flops per unit counted with SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 (FMA = 2) on the
+# kernels of hash KERNEL_HASH, and HBM traffic per unit from FETCH_SIZE / WRITE_SIZE
+# (scaled by the same counters' reading for a device copy of known size); None where not
+# measured on the current kernels.
+FLOPS_PER_UNIT = {}
+TRAFFIC_PER_UNIT = {}
+KERNEL_HASH = ""
 
 
 def kernel_hash() -> str:
@@ -73,26 +72,53 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def units_per_launch(cls, cfg):
-    nb = 1
-    for d in range(3):
-        nb *= cfg["n"][d] // cfg["block"][d]
-    b = cfg["block"]
-    if cls.startswith("flux"):
-        d = int(cls[-1]) - 1
-        u = 1
-        for e in range(3):
-            u *= b[e] + 1 if e == d else b[e] + 2
-        return nb * u
-    return nb * b[0] * b[1] * b[2]
+def units(cls, blocks, steps_per_level):
+    """units a kernel class processes over the cycles whose per-level step counts are
+    given: cell-stages for the update, faces (with the transverse ghost rows the flux
+    kernels also compute) for flux kernels"""
+    tot = 0
+    for b in blocks:
+        n = b["n"]
+        s = 2 * steps_per_level[b["lat"]]
+        if cls == "update":
+            tot += s * n[0] * n[1] * n[2]
+        elif cls.startswith("flux"):
+            d = int(cls[-1]) - 1
+            f = 1
+            for e in range(3):
+                f *= n[e] + 1 if e == d else n[e] + 2
+            tot += s * f
+    return tot
 
 
-def cpu_baseline(cfg, state, steps):
-    """the oracle, single-threaded, on the same initial state for `steps` steps"""
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "cpus_available": avail}
+
+
+def cpu_sample(steps):
+    """one oracle process: a 64x32x32 block of the torus (the workload's largest block
+    shape, PPM + HLLE, the same initial data at that resolution), `steps` steps; prints
+    its zone-cycles and seconds"""
     import numpy as np
 
     import oracle
+    from paper_1912_10192_amd import configs, initdata
 
+    cfg = configs.scaled(configs.TORUS_UNIFORM, (64, 32, 32), ng=3)
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
     g = oracle.Grid(cfg)
     ng = cfg["ng"]
     N1, N2, N3 = cfg["n"]
@@ -106,38 +132,72 @@ def cpu_baseline(cfg, state, steps):
     g.step(Pp, Bp, steps)
     dt = time.perf_counter() - t0
     assert np.isfinite(Pp).all()
-    return N1 * N2 * N3 * steps / dt, dt
+    print(json.dumps({"zone_cycles": N1 * N2 * N3 * steps, "seconds": dt}), flush=True)
 
 
-def timed(grid, cycles, sync):
-    sync()
+def cpu_baseline(steps, procs, log):
+    """the oracle as it stands (single-threaded C, one process per core) on independent
+    samples, started together: aggregate zone-cycles/s over `procs` processes"""
+    log(f"[bench] oracle: {procs} processes x {steps} steps of a 64x32x32 torus block")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-sample", str(steps)]
     t0 = time.perf_counter()
-    st = grid.step(cycles, stats=True)
-    sync()
-    return st, time.perf_counter() - t0
+    ps = [subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True) for _ in range(procs)]
+    outs = [p.communicate()[0] for p in ps]
+    wall = time.perf_counter() - t0
+    res = [json.loads(o.strip().splitlines()[-1]) for o in outs]
+    zc = sum(r["zone_cycles"] for r in res)
+    per = [r["zone_cycles"] / r["seconds"] for r in res]
+    return {"value": zc / wall, "unit": "zone-cycles/s", "cores": procs, "kind": "oracle",
+            "per_core": statistics.median(per),
+            "sample": f"{procs} independent single-threaded oracle processes, each {steps} "
+                      f"steps of a 64x32x32 block of the same torus (PPM + HLLE, FP64; the "
+                      f"workload's largest block shape), {wall:.1f} s wall",
+            "host": host_info()}
 
 
 def c2p_summary(st):
     hist = list(st.c2p_iter_hist)
     n = sum(hist[:63])
-    return {"tier": list(st.c2p_tier), "floor_hits": st.floor_hits,
-            "learned_guesses": st.mlp_guesses,
-            "mean_newton_iters": (sum(i * h for i, h in enumerate(hist[:63])) / n) if n else None}
+    out = {"tier": list(st.c2p_tier), "floor_hits": st.floor_hits,
+           "learned_guesses": st.mlp_guesses,
+           "mean_newton_iters": (sum(i * h for i, h in enumerate(hist[:63])) / n) if n else None}
+    tot = sum(st.c2p_tier)
+    out["tier_rates"] = [t / tot for t in st.c2p_tier] if tot else None
+    for q, name in ((0.5, "p50_newton_iters"), (0.99, "p99_newton_iters")):
+        acc, val = 0, None
+        for i, h in enumerate(hist[:63]):
+            acc += h
+            if n and acc >= q * n:
+                val = i
+                break
+        out[name] = val
+    return out
 
 
-def train_guess(cfg, state, steps, log):
-    """train the learned inversion guess on the initial cells plus synthetic states"""
+def train_guess(steps, log):
+    """the learned inversion guess trained on the device: 5 snapshots of the uniform
+    256x128x128 torus (steps 0, 50, 100, 150, 200, 2^20 seeded cells each) plus 5 M
+    synthetic states"""
     import torch
 
-    from paper_1912_10192_amd import grmhd, learned
+    from paper_1912_10192_amd import configs, grmhd, initdata, learned
 
     t0 = time.perf_counter()
-    g = grmhd.Grid(cfg, state=state)
-    g.step(2)
-    P, B, G = g.extract_cells()
-    chunks = [(P, B, G), learned.synthetic_states(G, 1_000_000, seed=5)]
+    cfg = dict(configs.TORUS_UNIFORM)
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    g = grmhd.Grid(cfg, state=state, batched=2)
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    chunks = []
+    for snap in range(5):
+        if snap:
+            g.step(50)
+        P, B, G = g.extract_cells()
+        idx = torch.randperm(P.shape[1], generator=gen)[:1 << 20].to(P.device)
+        chunks.append((P[:, idx].contiguous(), B[:, idx].contiguous(), G[:, idx].contiguous()))
+        last_G = G
+    chunks.append(learned.synthetic_states(last_G, 5_000_000, seed=5))
     X, Y, norm = learned.build_dataset(chunks, cfg["gam"])
-    del g, chunks
+    del g, chunks, last_G
     trainer, losses = learned.train(X, Y, steps=steps, batch=4096, lr=2e-3, log_every=steps // 4)
     blob = grmhd.mlp_pack(trainer.params, norm)
     torch.cuda.synchronize()
@@ -146,53 +206,123 @@ def train_guess(cfg, state, steps, log):
                   "train_s": time.perf_counter() - t0}
 
 
-def lat_learned_only(args, cfg, state, cells, sync, log):
-    """the headline path alone: batched LAT with the learned guess on the benchmark torus"""
+def run_leg(name, cfg, blocks, bs, batched, blob, steps, warmup, runs, sync, log, variants=None):
+    """warmup cycles, then `runs` timed runs of exactly `steps` cycles each; the median run.
+    Kernel variants: autotuned on the live state, or the given ones."""
     from paper_1912_10192_amd import grmhd
 
-    lats = grmhd.lat_levels_by_radius(cfg, [2.4, 4.8, 9.6])
-    nsub = 2 ** max(lats)
-    cycles = max(args.steps // nsub, 1)
-    blob, train = train_guess(cfg, state, args.train_steps, log)
-    g = grmhd.Grid(cfg, blocks=grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=lats),
-                   batched=True, mlp_blob=blob)
-    g.set_state(*state)
-    g.autotune()
-    log(f"[bench] lat_batched_learned only: levels {lats}, timed {cycles} cycles")
+    g = grmhd.Grid(cfg, blocks=blocks, batched=batched, mlp_blob=blob)
+    g.set_blocks(bs)
+    if variants is None:
+        tune = g.autotune()
+    else:
+        tune = None
+        g.set_variants(flux=variants["flux"], update=variants["update"], split=variants["update_split"])
+    L = max(b["lat"] for b in blocks) + 1
+    log(f"[bench] {name}: {len(blocks)} blocks, {L} time levels, batched={batched}, "
+        f"learned={blob is not None}; warmup {warmup}, {runs} runs of {steps} cycles")
+    if warmup:
+        g.step(warmup, stats=True)
+    walls, stats = [], []
+    for _ in range(runs):
+        sync()
+        t0 = time.perf_counter()
+        st = g.step(steps, stats=True)
+        sync()
+        walls.append(time.perf_counter() - t0)
+        stats.append(st)
+    i = sorted(range(runs), key=lambda k: walls[k])[runs // 2]
+    st, wall = stats[i], walls[i]
+    out = {"value_real": st.real_zone_cycles / wall,
+           "value_lat_effective": st.lat_eff_zone_cycles / wall,
+           "value_amr_lat_effective": st.amr_lat_eff_zone_cycles / wall,
+           "ms_per_cycle": wall * 1e3 / steps, "runs_ms_per_cycle": [w * 1e3 / steps for w in walls],
+           "cycles_per_run": steps, "substeps_per_cycle": 2 ** (L - 1), "dt_min": st.dt_min,
+           "steps_per_level": list(st.steps_per_level)[:L], "c2p": c2p_summary(st),
+           "divb_rel_max": g.divb()[1]}
+    if tune is not None:
+        out["autotune"] = {"flux": tune["flux"], "update": tune["update"],
+                           "update_split": tune["update_split"]}
+    del g
+    return out, tune
+
+
+def profiled_classes(cfg, blocks, bs, blob, tune, steps, sync, log):
+    """per kernel class time of the batched path (no graph; the HIP events time each class
+    on the library's stream, the flux directions one after another)"""
+    from paper_1912_10192_amd import grmhd
+
+    g = grmhd.Grid(cfg, blocks=blocks, batched=2, profile=True, mlp_blob=blob)
+    g.set_blocks(bs)
+    g.set_variants(flux=tune["flux"], update=tune["update"], split=tune["update_split"])
     g.step(1, stats=True)
-    st, wall = timed(g, cycles, sync)
-    print(json.dumps({"metric": METRIC, "unit": "zone-cycles/s", "n_gpus": 1,
-                      "steps": cycles * nsub, "value": st.lat_eff_zone_cycles / wall,
-                      "ms_per_cycle": wall * 1e3 / cycles, "higher_is_better": True,
-                      "dtype": "f64", "data": "synthetic", "learned_training": train,
-                      "config": {"workload": "torus-256x128x128-b32-ppm-hlle",
-                                 "path": "batched LAT + learned guess", "lat_levels": lats,
-                                 "cells": cells}}), flush=True)
+    st = g.step(steps, stats=True)
+    sync()
+    cls_ms = {k: st.class_ms[i] for i, k in enumerate(grmhd.KERNEL_CLASSES)}
+    cls_n = {k: st.class_launches[i] for i, k in enumerate(grmhd.KERNEL_CLASSES)}
+    L = max(b["lat"] for b in blocks) + 1
+    spl = list(st.steps_per_level)[:L]
+    log(f"[bench] profiled classes (ms per cycle): "
+        + " ".join(f"{k}={v / steps:.3f}" for k, v in cls_ms.items()))
+    del g
+    return cls_ms, cls_n, spl
+
+
+def roofline(cls_ms, cls_n, blocks, spl):
+    dom = max((k for k in cls_ms if k in BYTES_PER_UNIT), key=lambda k: cls_ms[k])
+    n_launch = max(cls_n[dom], 1)
+    avg_s = cls_ms[dom] * 1e-3 / n_launch
+    u = units(dom, blocks, spl) / n_launch                 # units per launch (mean)
+    khash = kernel_hash()
+    fresh = KERNEL_HASH == khash
+    alg_bytes = BYTES_PER_UNIT[dom] * u
+    flops = FLOPS_PER_UNIT.get(dom) if fresh else None
+    t_hbm = alg_bytes / PEAK["hbm"]
+    t_alu = flops * u / PEAK["alu"] if flops else 0.0
+    if t_alu > t_hbm:
+        bound, unit, peak, achieved, scale = "alu", "TFLOP/s", PEAK["alu"], flops * u / avg_s, 1e12
+    else:
+        bound, unit, peak, achieved, scale = "hbm", "GB/s", PEAK["hbm"], alg_bytes / avg_s, 1e9
+    traffic = TRAFFIC_PER_UNIT.get(dom) * u if fresh and dom in TRAFFIC_PER_UNIT else None
+    out = {"bound": bound, "achieved": achieved / scale, "peak": peak / scale, "unit": unit,
+           "frac": achieved / peak, "traffic": traffic, "kernel": dom,
+           "launch_ms": avg_s * 1e3, "launches": n_launch, "units_per_launch": u,
+           "alg_bytes_per_unit": BYTES_PER_UNIT[dom], "kernel_hash": khash,
+           "fp64_flops_per_unit": flops, "hbm_frac": t_hbm / avg_s,
+           "alu_frac": (t_alu / avg_s) if flops else None}
+    if dom == "update":
+        out["design_bytes_per_unit"] = DESIGN_BYTES_UPDATE
+        out["design_bytes_frac"] = DESIGN_BYTES_UPDATE * u / avg_s / PEAK["hbm"]
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200, help="finest-level steps")
-    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=10, help="LAT cycles per timed run")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed cycles first")
+    ap.add_argument("--runs", type=int, default=5, help="timed runs (the median is reported)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=1)
-    ap.add_argument("--only-plain", action="store_true")
-    ap.add_argument("--only-lat-learned", action="store_true",
-                    help="only the headline path (batched LAT + learned guess, with its "
-                         "training), for profiling it on its own; no plain path and no roofline")
+    ap.add_argument("--cpu-steps", type=int, default=40, help="oracle steps per process")
+    ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: the cores available, at most 16)")
+    ap.add_argument("--cpu-sample", type=int, default=0, help=argparse.SUPPRESS)
+    ap.add_argument("--only-headline", action="store_true",
+                    help="only the headline path (with its training), for profiling it alone")
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates the "
                          "FETCH_SIZE/WRITE_SIZE counters) and exit")
     args = ap.parse_args()
+    if args.cpu_sample:
+        cpu_sample(args.cpu_sample)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
 
-    from paper_1912_10192_amd import configs, grmhd, initdata
+    from paper_1912_10192_amd import configs, initdata
 
     log = lambda m: print(m, file=sys.stderr, flush=True)
     sync = torch.cuda.synchronize
@@ -205,129 +335,59 @@ def main():
         sync()
         log(f"[bench] copy probe: 3 copies of {args.copy_probe} MiB")
         return
-    cfg = dict(configs.TORUS_UNIFORM)
-    log(f"[bench] building initial state {cfg['n']}")
+
+    cfg = dict(configs.TORUS_AMR3)
+    blocks = configs.amr_lat_blocks(cfg["n"], lat_edges=cfg["lat_edges"])
+    lmax = [max(b["lev"][d] for b in blocks) for d in range(3)]
+    log(f"[bench] building initial state, effective {cfg['n']}, {len(blocks)} blocks")
     state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
-    cells = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
-
-    if args.only_lat_learned:
-        lat_learned_only(args, cfg, state, cells, sync, log)
-        return
-
-    # ---- plain path: global time step, one launch per kernel and stage, plain guess
-    grid = grmhd.Grid(cfg, state=state, profile=True)
-    tune = grid.autotune()
-    log(f"[bench] autotuned variants {tune}")
-    log(f"[bench] plain: warmup {args.warmup}, timed {args.steps} steps")
-    if args.warmup:
-        grid.step(args.warmup, stats=True)
-    st, wall = timed(grid, args.steps, sync)
-    a_div, r_div = grid.divb()
-    cls_ms = {k: st.class_ms[i] for i, k in enumerate(grmhd.KERNEL_CLASSES)}
-    cls_n = {k: st.class_launches[i] for i, k in enumerate(grmhd.KERNEL_CLASSES)}
-    dom = max(cls_ms, key=lambda k: cls_ms[k])
-    avg_s = cls_ms[dom] / max(cls_n[dom], 1) * 1e-3
-    units = units_per_launch(dom, cfg)
-    khash = kernel_hash()
-    fresh = KERNEL_HASH == khash
-    # the binding roof: the larger of the algorithmic byte time and flop time
-    alg_bytes = BYTES_PER_UNIT[dom] * units
-    alg_flops = FLOPS_PER_UNIT[dom] * units if fresh and dom in FLOPS_PER_UNIT else None
-    t_hbm = alg_bytes / PEAK["hbm"]
-    t_alu = alg_flops / PEAK["alu"] if alg_flops is not None else 0.0
-    if t_alu > t_hbm:
-        bound, unit, peak, achieved, scale = "alu", "TFLOP/s", PEAK["alu"], alg_flops / avg_s, 1e12
-    else:
-        bound, unit, peak, achieved, scale = "hbm", "GB/s", PEAK["hbm"], alg_bytes / avg_s, 1e9
-    traffic = TRAFFIC_PER_LAUNCH.get(dom) if fresh else None
-    roofline = {"bound": bound, "achieved": achieved / scale, "peak": peak / scale, "unit": unit,
-                "frac": achieved / peak, "traffic": traffic, "kernel": dom,
-                "launch_ms": avg_s * 1e3, "units_per_launch": units, "kernel_hash": khash,
-                "alg_bytes_per_unit": BYTES_PER_UNIT[dom],
-                "fp64_flops_per_unit": FLOPS_PER_UNIT.get(dom) if fresh else None,
-                "hbm_frac": t_hbm / avg_s,
-                "alu_frac": (t_alu / avg_s) if alg_flops is not None else None}
-    del grid
-    # the plain path's rate from a run without the per-class HIP events (which also keep
-    # the three flux directions in sequence); the profiled run above gives the classes
-    grid = grmhd.Grid(cfg, state=state)
-    grid.set_variants(flux=tune["flux"], update=tune["update"], split=tune["update_split"])
-    if args.warmup:
-        grid.step(args.warmup, stats=True)
-    st_u, wall_u = timed(grid, args.steps, sync)
-    del grid
-    plain_value = cells * args.steps / wall_u
-    plain = {"value": plain_value, "ms_per_step": wall_u * 1e3 / args.steps, "dt": st_u.dt_min,
-             "profiled_ms_per_step": wall * 1e3 / args.steps, "autotune": tune,
-             "c2p": c2p_summary(st), "divb_rel_max": r_div,
-             "kernel_ms_per_step": {k: v / args.steps for k, v in cls_ms.items()}}
-
+    bs = initdata.block_states(state, blocks, lmax)
+    del state
+    cells = sum(b["n"][0] * b["n"][1] * b["n"][2] for b in blocks)
+    blob, train = train_guess(args.train_steps, log)
+    head, tune = run_leg("batched_learned", cfg, blocks, bs, 1, blob, args.steps, args.warmup,
+                         args.runs, sync, log)
     out = {"metric": METRIC, "unit": "zone-cycles/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
-    if args.only_plain:
-        out.update({"value": plain_value, "ms_per_step": plain["ms_per_step"],
-                    "config": {"workload": "torus-256x128x128-b32-ppm-hlle", "path": "plain"},
-                    "roofline": roofline, "plain": plain})
-    else:
-        # ---- batched local time stepping: 4 levels by radius, graph-captured cycles
-        lats = grmhd.lat_levels_by_radius(cfg, [2.4, 4.8, 9.6])
-        L = max(lats) + 1
-        nsub = 2 ** (L - 1)
-        cycles = max(args.steps // nsub, 1)
-        blocks = grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=lats)
-        smr = configs.polar_smr_blocks(cfg["n"], cfg["block"][0], lats)
-        results = {}
-        blob, train = None, None
-        for name, bl, learned_on in (("lat_batched", blocks, False),
-                                     ("lat_batched_learned", blocks, True),
-                                     ("polar_smr_lat_batched_learned", smr, True)):
-            if learned_on and blob is None:
-                blob, train = train_guess(cfg, state, args.train_steps, log)
-            g = grmhd.Grid(cfg, blocks=bl, batched=True, mlp_blob=blob if learned_on else None)
-            if bl is smr:
-                lmax = [max(b["lev"][d] for b in bl) for d in range(3)]
-                g.set_blocks(initdata.block_states(state, bl, lmax))
-            else:
-                g.set_state(*state)
-            g.autotune()
-            log(f"[bench] {name}: {len(bl)} blocks, levels {lats}, warmup 1 cycle, "
-                f"timed {cycles} cycles of {nsub} substeps")
-            g.step(1, stats=True)
-            st, wall = timed(g, cycles, sync)
-            results[name] = {"value_lat_effective": st.lat_eff_zone_cycles / wall,
-                             "value_amr_lat_effective": st.amr_lat_eff_zone_cycles / wall,
-                             "value_real": st.real_zone_cycles / wall,
-                             "ms_per_cycle": wall * 1e3 / cycles, "cycles": cycles,
-                             "substeps_per_cycle": nsub, "dt_min": st.dt_min,
-                             "steps_per_level": list(st.steps_per_level)[:L],
-                             "cells": sum(b["n"][0] * b["n"][1] * b["n"][2] for b in bl),
-                             "c2p": c2p_summary(st), "divb_rel_max": g.divb()[1]}
-            del g
-        head = results["lat_batched_learned"]
+           "warmup": args.warmup, "runs": args.runs, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "value": head["value_real"], "ms_per_step": head["ms_per_cycle"],
+           "config": {"workload": WORKLOAD, "effective_grid": list(cfg["n"]),
+                      "blocks": len(blocks), "cells": cells,
+                      "block_shapes": ["64x32x32", "32x16x16", "16x8x8"],
+                      "time_levels": 4, "recon": "PPM", "riemann": "HLLE",
+                      "c2p_tol": cfg["tol"], "step": "one LAT cycle (8 finest substeps)",
+                      "path": "batched launches per time level, graph-captured cycle, "
+                              "learned first guess",
+                      "value_definition": "real zone-cycles/s (cells x their own steps / "
+                                          "wall time), median of the timed runs"},
+           "lat_effective": head["value_lat_effective"],
+           "amr_lat_effective": head["value_amr_lat_effective"],
+           "batched_learned": head}
+    if not args.only_headline:
+        batched, _ = run_leg("batched", cfg, blocks, bs, 1, None, args.steps, args.warmup,
+                             args.runs, sync, log)
+        plain, _ = run_leg("plain", cfg, blocks, bs, 0, None, args.steps, args.warmup,
+                           args.runs, sync, log, variants=tune)
+        flat = [dict(b, lat=0) for b in blocks]
+        gsteps = args.steps * head["substeps_per_cycle"]
+        glob, _ = run_leg("global_dt", cfg, flat, bs, 2, None, gsteps, args.warmup, args.runs,
+                          sync, log)
+        cls_ms, cls_n, spl = profiled_classes(cfg, blocks, bs, blob, tune, args.steps, sync, log)
         out.update({
-            "value": head["value_lat_effective"],
-            "ms_per_step": head["ms_per_cycle"] / nsub,
-            "config": {"workload": "torus-256x128x128-b32-ppm-hlle", "grid": list(cfg["n"]),
-                       "blocks": 128, "block": list(cfg["block"]), "recon": "PPM",
-                       "riemann": "HLLE", "c2p_tol": cfg["tol"],
-                       "path": "batched LAT (levels by radius, graph-captured cycle) + learned guess",
-                       "lat_levels": lats, "value_definition": "LAT-effective zone-cycles/s "
-                       "(all cells x finest-level steps / wall time)"},
-            "roofline": roofline,
-            "plain": plain,
-            "lat_batched": results["lat_batched"],
-            "lat_batched_learned": head,
-            "polar_smr_lat_batched_learned": results["polar_smr_lat_batched_learned"],
-            "learned_training": train,
-            "speedup_vs_plain": head["value_lat_effective"] / plain_value,
-        })
+            "roofline": roofline(cls_ms, cls_n, blocks, spl),
+            "kernel_ms_per_cycle": {k: v / args.steps for k, v in cls_ms.items()},
+            "batched": batched, "plain": plain, "global_dt": glob,
+            "speedup_vs_plain": head["value_real"] / plain["value_real"],
+            "batching_gain": batched["value_real"] / plain["value_real"],
+            "learned_gain": head["value_real"] / batched["value_real"],
+            "speedup_vs_global_dt_real": head["value_real"] / glob["value_real"],
+            "learned_training": train})
+    else:
+        out["learned_training"] = train
     if not args.no_cpu_baseline:
-        log(f"[bench] oracle on host, {args.cpu_steps} step(s) of the same grid")
-        rate, secs = cpu_baseline(cfg, state, args.cpu_steps)
-        out["cpu_baseline"] = {"value": rate, "unit": "zone-cycles/s", "cores": 1, "kind": "oracle",
-                               "sample": f"{args.cpu_steps} full step(s) of the 256x128x128 grid "
-                                         f"from the same initial state, single-threaded, {secs:.1f} s"}
+        avail = host_info()["cpus_available"] or 1
+        procs = args.cpu_procs or min(avail, 16)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps, procs, log)
     print(json.dumps(out), flush=True)
 
 

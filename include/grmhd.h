@@ -96,7 +96,11 @@ typedef struct {
   int32_t c2p_maxit;          /* Newton iteration cap (50) */
   double c2p_tol;             /* Newton tolerance (1e-12) */
   const void* mlp_weights;    /* device pointer to packed MLP weights, or NULL */
-  int32_t batched;            /* 0 = one launch per kernel and stage; 1 = step graph */
+  int32_t batched;            /* 0 = plain: one launch per block and kernel class (the
+                                 paper's per-block launches); 1 = batched: one launch per
+                                 time level and kernel class over a work list of the
+                                 level's blocks, LAT cycles captured as a hipGraph; 2 = the
+                                 batched launches without the graph */
   int32_t profile;            /* 1 = time each kernel class with HIP events on the stream */
 } grmhd_grid_desc;
 
@@ -201,8 +205,10 @@ int grmhd_cons2prim(grmhd_ctx* ctx, const grmhd_c2p_batch* batch, void* hip_stre
 
 /* Discrete divergence of the face field over all interior cells:
  * sum_d (Bbar^d_+ - Bbar^d_-)/dx^d.  Writes max |div| and max |div| / (sum_d
- * (|Bbar^d_+| + |Bbar^d_-|)/dx^d) to host scalars (synchronises); field (device,
- * nullable) receives the per-cell value in the prim layout of variable 0. */
+ * (|Bbar^d_+| + |Bbar^d_-|)/dx^d) to host scalars (synchronises), the relative form over
+ * cells where that scale is at least 2^-969 (subnormal face values carry no relative
+ * precision); field (device, nullable) receives the per-cell value in the prim layout
+ * of variable 0. */
 int grmhd_divb(grmhd_ctx* ctx, double* max_abs, double* max_rel, double* field);
 
 /* Host-only planner introspection for bit-exact checks (no device needed): copies the

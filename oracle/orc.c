@@ -1048,12 +1048,14 @@ double orc_divb(orc_ctx* c, const double* B, double* field, double* max_rel) {
         double b3p = B[2 * nc + IDX(c, K + 1, J, I)], b3m = B[2 * nc + id];
         double dv = (b1p - b1m) / c->dx[0] + (b2p - b2m) / c->dx[1] + (b3p - b3m) / c->dx[2];
         /* the same sum with every term taken by magnitude: the scale the differences
-         * cancel against */
+         * cancel against.  The relative form is taken where the scale is at least
+         * 2^-969 (2^53 times the smallest normal double): below it the face values are
+         * subnormal and carry no relative precision (a field-free region underflows). */
         double scale = (fabs(b1p) + fabs(b1m)) / c->dx[0] + (fabs(b2p) + fabs(b2m)) / c->dx[1]
                        + (fabs(b3p) + fabs(b3m)) / c->dx[2];
         if (field) field[id] = dv;
         if (fabs(dv) > mx) mx = fabs(dv);
-        if (scale > 0.0 && fabs(dv) / scale > mr) mr = fabs(dv) / scale;
+        if (scale >= ldexp(1.0, -969) && fabs(dv) / scale > mr) mr = fabs(dv) / scale;
       }
   if (max_rel) *max_rel = mr;
   return mx;

@@ -80,3 +80,85 @@ def polar_smr_blocks(n, b1, lats=None):
 TORUS_AMR_LAT = dict(KS_TORUS_BASE, name="torus-eff512x256x256-polar-smr-lat4", n=(512, 256, 256),
                      block=(64, 64, 64), ng=3, recon=1, riemann=1, cycles=25,
                      lat_edges=(2.4, 4.8, 9.6))
+
+
+def amr_lat_blocks(n, shapes=None, lat_edges=(2.4, 4.8, 9.6), xlo=None, xhi=None):
+    """Block layout of the batched refinement + local time stepping workload (paper Sec.
+    3.3, 3.4 external refinement toward the poles, 3.5) for an effective log-spherical
+    grid n = (N1, N2, N3) at the finest level of each dimension (levels 1, 1, 2):
+      equatorial band, theta rows [N2/4, 3 N2/4): full resolution; x1 [0, N1/4) in
+          blocks shapes["eq_in"], x1 [N1/4, N1) in blocks shapes["eq_out"];
+      mid-latitude bands [N2/8, N2/4) and mirror: half resolution in every dimension
+          (levels 0, 0, 1), blocks shapes["mid"];
+      polar caps [0, N2/8) and mirror: half resolution in r and theta and a quarter in
+          phi (levels 0, 0, 0), blocks shapes["cap"].
+    Every refinement jump is 2:1.  Default shapes (effective 512x256x256): 32x16x16
+    (512 blocks) and 64x32x32 (192) in the equatorial band, 32x16x16 (128) in the mid
+    bands, 16x8x8 (512) in the caps: 1344 blocks, 18,350,080 cells.  The time level of
+    a block is set by the radius of its inner x1 face (level = number of lat_edges at or
+    below it), then lowered where needed so that blocks that touch differ by at most one
+    level."""
+    import math
+
+    N1, N2, N3 = n
+    if shapes is None:
+        shapes = dict(eq_in=(N1 // 16, N2 // 16, N3 // 16), eq_out=(N1 // 8, N2 // 8, N3 // 8),
+                      mid=(N1 // 16, N2 // 16, N3 // 16), cap=(N1 // 32, N2 // 32, N3 // 32))
+    xlo = xlo if xlo is not None else KS_TORUS_BASE["xlo"][0]
+    xhi = xhi if xhi is not None else KS_TORUS_BASE["xhi"][0]
+    out = []
+
+    def tile(lev, ext, rows, x1r, shape):
+        b1, b2, b3 = shape
+        for k in range(0, ext[2], b3):
+            for j in range(rows[0], rows[1], b2):
+                for i in range(x1r[0], x1r[1], b1):
+                    out.append(dict(org=(i, j, k), n=(b1, b2, b3), lev=lev, lat=0))
+
+    # caps, mid bands and equator from the north pole down (levels' extents in cells)
+    ext0 = (N1 // 2, N2 // 2, N3 // 4)
+    ext1 = (N1 // 2, N2 // 2, N3 // 2)
+    ext2 = (N1, N2, N3)
+    tile((0, 0, 0), ext0, (0, N2 // 16), (0, N1 // 2), shapes["cap"])
+    tile((0, 0, 1), ext1, (N2 // 16, N2 // 8), (0, N1 // 2), shapes["mid"])
+    tile((1, 1, 2), ext2, (N2 // 4, 3 * N2 // 4), (0, N1 // 4), shapes["eq_in"])
+    tile((1, 1, 2), ext2, (N2 // 4, 3 * N2 // 4), (N1 // 4, N1), shapes["eq_out"])
+    tile((0, 0, 1), ext1, (3 * N2 // 8, 7 * N2 // 16), (0, N1 // 2), shapes["mid"])
+    tile((0, 0, 0), ext0, (7 * N2 // 16, N2 // 2), (0, N1 // 2), shapes["cap"])
+    # time levels by inner radius
+    lmax = (1, 1, 2)
+    dx1 = (xhi - xlo) / N1
+    for b in out:
+        i_eff = b["org"][0] << (lmax[0] - b["lev"][0])
+        r = math.exp(xlo + i_eff * dx1)
+        b["lat"] = sum(1 for e in lat_edges if r >= e)
+    # boxes in effective cells; touching blocks (phi periodic) differ by at most one level
+    import numpy as np
+    lo = np.array([[b["org"][d] << (lmax[d] - b["lev"][d]) for d in range(3)] for b in out])
+    hi = lo + np.array([[b["n"][d] << (lmax[d] - b["lev"][d]) for d in range(3)] for b in out])
+    touch = np.ones((len(out), len(out)), dtype=bool)
+    for d, Nd in enumerate(n):
+        a0, a1 = lo[:, d][:, None], hi[:, d][:, None]
+        b0, b1 = lo[:, d][None, :], hi[:, d][None, :]
+        t = (a0 <= b1) & (b0 <= a1)
+        if d == 2:
+            t |= (a0 == 0) & (b1 == Nd) | (b0 == 0) & (a1 == Nd)
+        touch &= t
+    lat = np.array([b["lat"] for b in out])
+    while True:
+        lim = np.where(touch, lat[None, :] + 1, 1 << 30).min(axis=1)
+        new = np.minimum(lat, lim)
+        if np.array_equal(new, lat):
+            break
+        lat = new
+    for b, l in zip(out, lat):
+        b["lat"] = int(l)
+    return out
+
+
+# Batched refinement + local time stepping as specified: effective 512x256x256 in 1344
+# blocks of 64x32x32, 32x16x16 and 16x8x8 (amr_lat_blocks), phi halved per level toward
+# each pole (3 levels), 4 time levels by radius, 25 cycles
+TORUS_AMR3 = dict(KS_TORUS_BASE, name="torus-eff512x256x256-amr-lat4-1344blocks", n=(512, 256, 256),
+                  block=(64, 32, 32), ng=3, recon=1, riemann=1, cycles=25,
+                  lat_edges=(2.4, 4.8, 9.6))

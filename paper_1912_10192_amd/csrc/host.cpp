@@ -8,11 +8,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/grmhd.h"
@@ -434,7 +440,7 @@ int face_owner(const Plan& p, const int32_t* lev, const int64_t N[3], int kind, 
 }
 
 struct Resolver {
-  Plan& p;
+  const Plan& p;
   int viewer;
   std::string err;
 
@@ -515,21 +521,29 @@ struct Resolver {
   }
 };
 
-int build_ops(Plan& p) {
+// The ghost lists of one block (samples numbered from 0 within the block).
+struct BlockOps {
+  std::vector<GhostOp> ops[4];
+  std::vector<AmrOp> aops[4];
+  std::vector<AmrSample> samples;
+  std::vector<uint8_t> samp_kind;
+  int rc = GRMHD_OK;
+  std::string err;
+};
+
+static int block_ops(const Plan& p, int b, BlockOps& out) {
   const int g = p.d.n_ghost;
-  const int nb = p.d.n_blocks;
-  for (int kind = 0; kind < 4; kind++) {
-    p.ops[kind].clear();
-    p.aops[kind].clear();
-  }
-  p.samples.clear();
-  p.samp_kind.clear();
+  auto fail = [&](int code, const std::string& msg) {
+    out.rc = code;
+    out.err = msg;
+    return code;
+  };
   auto add_sample = [&](const AmrSample& s, int kind) {
-    p.samples.push_back(s);
-    p.samp_kind.push_back((uint8_t)kind);
+    out.samples.push_back(s);
+    out.samp_kind.push_back((uint8_t)kind);
   };
   const bool polar = p.d.bc[2] == GRMHD_BC_POLAR;
-  for (int b = 0; b < nb; b++) {
+  {
     const BlockInfo& bi = p.info[b];
     const grmhd_block_desc& bd = p.blocks[b];
     Resolver R{p, b, std::string()};
@@ -553,7 +567,7 @@ int build_ops(Plan& p) {
             const int32_t dst_loc = local_index(bi, I, J, K);
             if (!nz) {   // a polar-axis face: identically zero, no source
               GhostOp op{b, dst_loc, b | (GF_ZERO << 24), 0};
-              p.ops[kind].push_back(op);
+              out.ops[kind].push_back(op);
               continue;
             }
             // the block this value comes from at the block's own level
@@ -572,13 +586,13 @@ int build_ops(Plan& p) {
               op.dst_loc = dst_loc;
               op.src_blkf = src | ((flags | time_flags(p, src, b)) << 24);
               op.src_loc = local_index(si, gi - sd.org[0] + g, gj - sd.org[1] + g, gk - sd.org[2] + g);
-              p.ops[kind].push_back(op);
+              out.ops[kind].push_back(op);
               continue;
             }
             AmrOp op;
             op.dst_blk = b;
             op.dst_loc = dst_loc;
-            op.samp = (int32_t)p.samples.size();
+            op.samp = (int32_t)out.samples.size();
             op.mode = flags << AM_FLAGS_SHIFT;
             AmrSample s;
             if (rel == 1) {   // restriction of a finer neighbour
@@ -586,7 +600,7 @@ int build_ops(Plan& p) {
                                         : R.face_sample(bd.lev, N, kind, gi, gj, gk, false, 0, s);
               if (!ok) return fail(GRMHD_EINVAL, R.err);
               add_sample(s, kind);
-              p.aops[kind].push_back(op);
+              out.aops[kind].push_back(op);
               continue;
             }
             // prolongation from a coarser neighbour at levels mu
@@ -645,11 +659,62 @@ int build_ops(Plan& p) {
                 }
               }
             }
-            p.aops[kind].push_back(op);
+            out.aops[kind].push_back(op);
           }
     }
   }
-  if (p.samples.size() >= (size_t(1) << 31)) return fail(GRMHD_EINVAL, "too many refinement samples");
+  return GRMHD_OK;
+}
+
+int build_ops(Plan& p) {
+  const int nb = p.d.n_blocks;
+  for (int kind = 0; kind < 4; kind++) {
+    p.ops[kind].clear();
+    p.aops[kind].clear();
+  }
+  p.samples.clear();
+  p.samp_kind.clear();
+  // blocks on worker threads, concatenated in block order (the lists do not depend on
+  // the threads)
+  std::vector<BlockOps> per(nb);
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    for (int b = next++; b < nb; b = next++) block_ops(p, b, per[b]);
+  };
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nt && (int)t < nb; t++) th.emplace_back(work);
+  work();
+  for (std::thread& t : th) t.join();
+  size_t tot[4] = {}, atot[4] = {}, stot = 0;
+  for (const BlockOps& o : per) {
+    if (o.rc) return fail(o.rc, o.err);
+    for (int k = 0; k < 4; k++) {
+      tot[k] += o.ops[k].size();
+      atot[k] += o.aops[k].size();
+    }
+    stot += o.samples.size();
+  }
+  if (stot >= (size_t(1) << 31)) return fail(GRMHD_EINVAL, "too many refinement samples");
+  for (int k = 0; k < 4; k++) {
+    p.ops[k].reserve(tot[k]);
+    p.aops[k].reserve(atot[k]);
+  }
+  p.samples.reserve(stot);
+  p.samp_kind.reserve(stot);
+  for (BlockOps& o : per) {
+    const int32_t base = (int32_t)p.samples.size();
+    for (int k = 0; k < 4; k++) {
+      p.ops[k].insert(p.ops[k].end(), o.ops[k].begin(), o.ops[k].end());
+      for (AmrOp op : o.aops[k]) {
+        op.samp += base;
+        p.aops[k].push_back(op);
+      }
+    }
+    p.samples.insert(p.samples.end(), o.samples.begin(), o.samples.end());
+    p.samp_kind.insert(p.samp_kind.end(), o.samp_kind.begin(), o.samp_kind.end());
+    o = BlockOps();
+  }
   return GRMHD_OK;
 }
 
@@ -1095,22 +1160,20 @@ static int sync_lists(Plan& p) {
   for (int b = 0; b < nb; b++) {
     const BlockInfo& bi = p.info[b];
     const int32_t* n = bi.n;
-    std::vector<std::pair<int32_t, std::vector<FluxTerm>>> dU;   // insertion order
+    std::map<int32_t, std::vector<FluxTerm>> dU;   // per cell, terms in table order
     std::vector<int32_t> touched;
     std::vector<SyncFace> faces;
-    auto cell_terms = [&](int32_t loc) -> std::vector<FluxTerm>& {
-      for (auto& c : dU)
-        if (c.first == loc) return c.second;
-      dU.push_back({loc, {}});
-      return dU.back().second;
-    };
+    std::unordered_map<int64_t, size_t> face_at;
+    auto cell_terms = [&](int32_t loc) -> std::vector<FluxTerm>& { return dU[loc]; };
     auto face_of = [&](int comp, int32_t loc) -> SyncFace& {
-      for (SyncFace& f : faces)
-        if (f.comp == comp && f.loc == loc) return f;
+      const int64_t k = (int64_t)comp << 32 | (uint32_t)loc;
+      auto it = face_at.find(k);
+      if (it != face_at.end()) return faces[it->second];
       SyncFace f{};
       f.blk = b;
       f.comp = comp;
       f.loc = loc;
+      face_at[k] = faces.size();
       faces.push_back(f);
       return faces.back();
     };
@@ -1194,12 +1257,12 @@ static int sync_lists(Plan& p) {
       SyncCell c{};
       c.blk = b;
       c.loc = loc;
-      for (auto& d : dU)
-        if (d.first == loc) {
-          if (d.second.size() > 3) return fail(GRMHD_EINVAL, "planner: more than three reflux faces on a cell");
-          c.nt = (int32_t)d.second.size();
-          for (size_t k = 0; k < d.second.size(); k++) c.t[k] = d.second[k];
-        }
+      auto d = dU.find(loc);
+      if (d != dU.end()) {
+        if (d->second.size() > 3) return fail(GRMHD_EINVAL, "planner: more than three reflux faces on a cell");
+        c.nt = (int32_t)d->second.size();
+        for (size_t k = 0; k < d->second.size(); k++) c.t[k] = d->second[k];
+      }
       cl[lat(b)].push_back(c);
     }
     fl[lat(b)].insert(fl[lat(b)].end(), faces.begin(), faces.end());
@@ -1325,21 +1388,20 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
     }
     p.lev_boff[L] = (int64_t)p.lev_blocks.size();
     if (with_maps) {
+      // a stable counting sort of each list by the destination block's time level
+      auto by_level = [&](auto& v, std::vector<int64_t>& off) {
+        off.assign(L + 1, 0);
+        for (const auto& op : v) off[p.blocks[op.dst_blk].lat + 1]++;
+        for (int l = 0; l < L; l++) off[l + 1] += off[l];
+        if (L == 1) return;
+        std::vector<int64_t> at(off.begin(), off.end() - 1);
+        std::remove_reference_t<decltype(v)> out(v.size());
+        for (const auto& op : v) out[at[p.blocks[op.dst_blk].lat]++] = op;
+        v.swap(out);
+      };
       for (int kind = 0; kind < 4; kind++) {
-        std::stable_sort(p.ops[kind].begin(), p.ops[kind].end(),
-                         [&](const GhostOp& a, const GhostOp& c) {
-                           return p.blocks[a.dst_blk].lat < p.blocks[c.dst_blk].lat;
-                         });
-        p.ops_off[kind].assign(L + 1, 0);
-        for (const GhostOp& op : p.ops[kind]) p.ops_off[kind][p.blocks[op.dst_blk].lat + 1]++;
-        for (int l = 0; l < L; l++) p.ops_off[kind][l + 1] += p.ops_off[kind][l];
-        std::stable_sort(p.aops[kind].begin(), p.aops[kind].end(),
-                         [&](const AmrOp& a, const AmrOp& c) {
-                           return p.blocks[a.dst_blk].lat < p.blocks[c.dst_blk].lat;
-                         });
-        p.aops_off[kind].assign(L + 1, 0);
-        for (const AmrOp& op : p.aops[kind]) p.aops_off[kind][p.blocks[op.dst_blk].lat + 1]++;
-        for (int l = 0; l < L; l++) p.aops_off[kind][l + 1] += p.aops_off[kind][l];
+        by_level(p.ops[kind], p.ops_off[kind]);
+        by_level(p.aops[kind], p.aops_off[kind]);
       }
     }
     if (with_maps && L > 1) build_slow(p);
@@ -1545,7 +1607,8 @@ struct grmhd_ctx {
   const RegItem* regs = nullptr;
   const SyncCell* scells = nullptr;
   const SyncFace* sfaces = nullptr;
-  bool batched = false;
+  bool batched = false;     // LAT cycles captured as a graph
+  bool per_block = false;   // one launch per block and kernel class (plain)
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -1555,6 +1618,57 @@ struct grmhd_ctx {
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
 };
+
+// The plan of the last grmhd_sizes call, handed to grmhd_init_grid when it is called
+// with the same grid structure (building the tables is the costly part of setting up a
+// large refined grid).  Keyed by every descriptor field the tables depend on; the
+// others are copied from the descriptor init receives.
+static std::mutex g_plan_mu;
+static std::vector<char> g_plan_key;
+static std::unique_ptr<Plan> g_plan;
+
+static std::vector<char> plan_key(const grmhd_grid_desc* d) {
+  std::vector<char> k;
+  auto put = [&](const void* x, size_t n) {
+    const char* c = (const char*)x;
+    k.insert(k.end(), c, c + n);
+  };
+  put(&d->abi_version, 4);
+  put(&d->coords, 4);
+  put(&d->spin_a, 8);
+  put(d->xmin, 24);
+  put(d->xmax, 24);
+  put(d->n_eff, 12);
+  put(&d->n_ghost, 4);
+  put(&d->n_blocks, 4);
+  put(&d->n_lat_levels, 4);
+  put(&d->recon, 4);
+  put(&d->riemann, 4);
+  put(d->bc, 24);
+  for (int b = 0; b < d->n_blocks; b++) {
+    const grmhd_block_desc& bd = d->blocks[b];
+    put(bd.lev, 12);
+    put(&bd.lat, 4);
+    put(bd.org, 24);
+    put(bd.n, 12);
+  }
+  return k;
+}
+
+static void keep_plan(const grmhd_grid_desc* d, std::unique_ptr<Plan> p) {
+  std::vector<char> k = plan_key(d);
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  g_plan_key.swap(k);
+  g_plan = std::move(p);
+}
+
+static std::unique_ptr<Plan> take_plan(const grmhd_grid_desc* d) {
+  std::vector<char> k = plan_key(d);
+  std::lock_guard<std::mutex> lock(g_plan_mu);
+  if (!g_plan || k != g_plan_key) return nullptr;
+  g_plan_key.clear();
+  return std::move(g_plan);
+}
 
 // the work lists of block list `list` (a time level, or nlev for all blocks) into L
 static void set_work_lists(const grmhd_ctx* c, Launch& L, int list) {
@@ -1575,12 +1689,13 @@ extern "C" {
 
 int grmhd_sizes(const grmhd_grid_desc* desc, size_t* prim_elems, size_t* bface_elems,
                 size_t* work_bytes) {
-  Plan p;
-  int rc = build_plan(desc, p, false);
+  std::unique_ptr<Plan> p(new Plan());
+  int rc = build_plan(desc, *p, false);
   if (rc) return rc;
-  if (prim_elems) *prim_elems = (size_t)p.vtot * 5;
-  if (bface_elems) *bface_elems = (size_t)p.vtot * 3;
-  if (work_bytes) *work_bytes = p.total;
+  if (prim_elems) *prim_elems = (size_t)p->vtot * 5;
+  if (bface_elems) *bface_elems = (size_t)p->vtot * 3;
+  if (work_bytes) *work_bytes = p->total;
+  if (p->refined || p->nlev > 1) keep_plan(desc, std::move(p));   // built with its lists
   return GRMHD_OK;
 }
 
@@ -1606,7 +1721,17 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   if (!out || !bufs) return fail(GRMHD_EINVAL, "NULL argument");
   *out = nullptr;
   grmhd_ctx* c = new grmhd_ctx();
-  int rc = build_plan(desc, c->plan, true);
+  int rc = validate(desc);
+  if (!rc) {
+    std::unique_ptr<Plan> kept = take_plan(desc);
+    if (kept) {
+      c->plan = std::move(*kept);
+      c->plan.d = *desc;
+      c->plan.d.blocks = nullptr;
+    } else {
+      rc = build_plan(desc, c->plan, true);
+    }
+  }
   if (rc) { delete c; return rc; }
   const Plan& p = c->plan;
   if (!bufs->prim || !bufs->bface || !bufs->work) { delete c; return fail(GRMHD_EINVAL, "NULL buffer"); }
@@ -1633,7 +1758,9 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   c->regs = (const RegItem*)(w + p.o_regs);
   c->scells = (const SyncCell*)(w + p.o_scell);
   c->sfaces = (const SyncFace*)(w + p.o_sface);
-  c->batched = desc->batched != 0;
+  if (desc->batched < 0 || desc->batched > 2) { delete c; return fail(GRMHD_EINVAL, "batched must be 0, 1 or 2"); }
+  c->batched = desc->batched == 1;
+  c->per_block = desc->batched == 0;
   std::vector<double> gc, g1, g2;
   build_geometry(p, gc, g1, g2);
   auto up = [&](size_t off, const void* src, size_t bytes) -> int {
@@ -1825,25 +1952,86 @@ static void launch_fluxes(grmhd_ctx* c, const Launch& L, const double* Ps, const
   }
 }
 
-static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double* Ps,
-                  const double* Bs, double factor, double* Pout, double* Bout, double* dt_part) {
-  const Launch& L = c->L;
+// Launches of the block-wise stage kernels over blocks hb[0..n) of a time level (their
+// device ids at dev): batched, one launch per kernel class for all of them (work lists
+// for uneven sizes); plain, one launch per block and kernel class (the paper's launch
+// structure), each sized to its block.
+}  // extern "C"
+
+template <class Fn>
+static void for_launches(grmhd_ctx* c, const Launch& L, const int32_t* hb, const int32_t* dev,
+                         int64_t n, Fn&& fn) {
+  if (!c->per_block) {
+    fn(L, int64_t(-1));
+    return;
+  }
+  for (int64_t q = 0; q < n; q++) {
+    Launch Lb = L;
+    Lb.blist = dev + q;
+    Lb.nblk = 1;
+    for (int cls = 0; cls < WL_N; cls++) {
+      Lb.wls[cls] = nullptr;
+      Lb.nwls[cls] = 0;
+    }
+    const BlockInfo& bi = c->plan.info[hb[q]];
+    for (int k = 0; k < 3; k++) {
+      Lb.max_n[k] = bi.n[k];
+      Lb.max_np[k] = bi.np[k];
+    }
+    fn(Lb, q);
+  }
+}
+
+extern "C" {
+
+// The kernels of one stage over the blocks of a time level (lev, or all blocks for a
+// grid without time levels): cell-centred field, face fluxes, EMFs, the same-level
+// refinement corrections, the update, the coarse copies of refinement faces.  With
+// dt_part the corrector also leaves the next Courant step's per-workgroup minima, a
+// segment of dt_partials / blocks per block in the plain launch structure.
+static void stage_kernels(grmhd_ctx* c, const Launch& L, int lev, const double* Pn,
+                          const double* Bn, const double* Ps, const double* Bs, double factor,
+                          double* Pout, double* Bout, double* dt_part) {
+  const Plan& p = c->plan;
+  const int lv = lev < 0 ? 0 : lev;
+  const int32_t* hb = p.lev_blocks.data() + p.lev_boff[lv];
+  const int32_t* dev = c->lev_list + p.lev_boff[lv];
+  const int64_t nb = p.lev_boff[lv + 1] - p.lev_boff[lv];
+  const int64_t fo = p.fix_off[lv], nfix = p.fix_off[lv + 1] - fo;
+  const int64_t bo = p.bsync_off[lv], nbs = p.bsync_off[lv + 1] - bo;
+  const int recon = p.d.recon, riem = p.d.riemann;
   prof_begin(c, KC_BCELL);
-  launch_bcell(L, Bs, c->bc);
+  for_launches(c, L, hb, dev, nb, [&](const Launch& Lb, int64_t) { launch_bcell(Lb, Bs, c->bc); });
   prof_end(c);
-  launch_fluxes(c, L, Ps, Bs);
+  if (c->per_block) {
+    for_launches(c, L, hb, dev, nb, [&](const Launch& Lb, int64_t) {
+      for (int dir = 1; dir <= 3; dir++) launch_flux(Lb, dir, recon, riem, Ps, c->bc, Bs, c->f);
+    });
+  } else {
+    launch_fluxes(c, L, Ps, Bs);
+  }
   prof_begin(c, KC_EMF);
-  launch_emf(L, c->f, c->e);
-  launch_means(L, c->fix, (int64_t)c->plan.fix.size(), c->f, c->e);
+  for_launches(c, L, hb, dev, nb, [&](const Launch& Lb, int64_t) { launch_emf(Lb, c->f, c->e); });
+  launch_means(L, c->fix + fo, nfix, c->f, c->e);
   prof_end(c);
   prof_begin(c, KC_UPDATE);
-  launch_update(L, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, dt_part, c->mlp, c->u9);
+  if (dt_part && c->per_block) launch_fill(L, dt_part, dt_partials(L), INFINITY);
+  const int64_t seg = dt_partials(L) / (L.nblk > 0 ? L.nblk : 1);
+  for_launches(c, L, hb, dev, nb, [&](const Launch& Lb, int64_t q) {
+    double* part = dt_part && q >= 0 ? dt_part + q * seg : dt_part;
+    launch_update(Lb, Pn, Bn, Ps, c->bc, c->f, c->e, factor, Pout, Bout, part, c->mlp, c->u9);
+  });
   prof_end(c);
-  if (!c->plan.bsync.empty()) {
+  if (nbs > 0) {
     prof_begin(c, KC_GHOST);
-    launch_means(L, c->bsync, (int64_t)c->plan.bsync.size(), Bout, Bout);
+    launch_means(L, c->bsync + bo, nbs, Bout, Bout);
     prof_end(c);
   }
+}
+
+static void stage(grmhd_ctx* c, const double* Pn, const double* Bn, const double* Ps,
+                  const double* Bs, double factor, double* Pout, double* Bout, double* dt_part) {
+  stage_kernels(c, c->L, -1, Pn, Bn, Ps, Bs, factor, Pout, Bout, dt_part);
 }
 
 // one block level of a substep: predictor and corrector with time-aware ghosts, then the
@@ -1874,30 +2062,10 @@ static void lat_level_step(grmhd_ctx* c, const Launch& base, int lev, int s) {
                       Bdst, w);
     prof_end(c);
   };
-  auto stage_l = [&](const double* Ps, const double* Bs, double factor, double* Pout) {
-    prof_begin(c, KC_BCELL);
-    launch_bcell(L, Bs, c->bc);
-    prof_end(c);
-    launch_fluxes(c, L, Ps, Bs);
-    const int64_t fo = p.fix_off[lev], nfix = p.fix_off[lev + 1] - fo;
-    const int64_t bo = p.bsync_off[lev], nbs = p.bsync_off[lev + 1] - bo;
-    prof_begin(c, KC_EMF);
-    launch_emf(L, c->f, c->e);
-    launch_means(L, c->fix + fo, nfix, c->f, c->e);
-    prof_end(c);
-    prof_begin(c, KC_UPDATE);
-    launch_update(L, P, B, Ps, c->bc, c->f, c->e, factor, Pout, c->balt, nullptr, c->mlp, c->u9);
-    prof_end(c);
-    if (nbs > 0) {
-      prof_begin(c, KC_GHOST);
-      launch_means(L, c->bsync + bo, nbs, c->balt, c->balt);
-      prof_end(c);
-    }
-  };
   ghosts(P, B, P, B, w_pred);
-  stage_l(P, B, 0.5 * scale, c->ps);                 // predictor -> ps, balt
+  stage_kernels(c, L, lev, P, B, P, B, 0.5 * scale, c->ps, c->balt, nullptr);   // -> ps, balt
   ghosts(c->ps, c->balt, c->ps, c->balt, w_corr);
-  stage_l(c->ps, c->balt, scale, P);                 // corrector -> P, balt
+  stage_kernels(c, L, lev, P, B, c->ps, c->balt, scale, P, c->balt, nullptr);   // -> P, balt
   launch_registers(L, c->regs + p.reg_off[lev], p.reg_off[lev + 1] - p.reg_off[lev], c->f, c->e,
                    scale, (s % (2 << lev)) == 0 ? 1 : 0, c->regf, p.nregF, c->rege, p.nregE);
   launch_copy_blocks(L, c->balt, B, 3);
@@ -1908,11 +2076,11 @@ static void lat_cycle(grmhd_ctx* c) {
   const Launch& L = c->L;
   const int nsub = 1 << (p.nlev - 1);
   prof_begin(c, KC_DT);
-  launch_dt(L, c->bufs.prim, c->bufs.bface, c->dtp);
   {
+    const int64_t np = launch_dt(L, c->bufs.prim, c->bufs.bface, c->dtp, true);
     const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
     const int gridx = (int)((r + 255) / 256);
-    launch_dt_final_lat(L, c->dtp, (int64_t)gridx * L.nblk, gridx);
+    launch_dt_final_lat(L, c->dtp, np, gridx, L.wls[WL_CELLS]);
   }
   prof_end(c);
   for (int s = 0; s < nsub; s++) {

@@ -228,11 +228,16 @@ int64_t launch_update(const Launch& L, const double* Pn, const double* Bn, const
                    double* Pout, double* Bout, double* dt_part, const void* mlp, double* ubuf);
 void launch_stats_fold(const Launch& L);
 int64_t dt_partials(const Launch& L);
-void launch_dt(const Launch& L, const double* P, const double* B, double* dt_part);
+// per-workgroup minima of the Courant step of the listed blocks; over the work list of
+// interior cells when work_list is set and the blocks have one (partials: one per item),
+// else over the rectangular grid of tiles x blocks (dt_partials); returns the partials
+int64_t launch_dt(const Launch& L, const double* P, const double* B, double* dt_part,
+                  bool work_list = false);
 void launch_dt_final(const Launch& L, const double* dt_part);
 void launch_counters_reset(const Launch& L, bool all);
 void launch_tsim(const Launch& L);
 void launch_copy(const Launch& L, const double* src, double* dst, int64_t n);
+void launch_fill(const Launch& L, double* x, int64_t n, double v);
 // div B of the face field (field non-null: per cell), maxima through the per-workgroup
 // partials part [2][workgroups]
 void launch_divb(const Launch& L, const double* B, double* field, double* part);
@@ -261,7 +266,10 @@ void launch_registers(const Launch& L, const RegItem* items, int64_t n, const do
 void launch_sync(const Launch& L, const SyncCell* cells, int64_t ncell, const SyncFace* faces,
                  int64_t nface, double* P, double* B, const double* regF, int64_t nf,
                  const double* regE, int64_t ne, double* Ubuf);
-void launch_dt_final_lat(const Launch& L, const double* part, int64_t n, int gridx);
+// dt of a cycle from n partials of launch_dt: min of partial / 2^lat of its block (the
+// block of partial i: work-list item i, or i / gridx on the rectangular grid)
+void launch_dt_final_lat(const Launch& L, const double* part, int64_t n, int gridx,
+                         const int2* wl);
 void launch_tsim_cycle(const Launch& L, double substeps);
 void launch_c2p_batch(int64_t n, const double* U, const double* geom, const double* guess,
                       const double* prev, double* P, int32_t* iters, int32_t* tier, double gam,

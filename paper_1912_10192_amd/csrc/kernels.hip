@@ -820,11 +820,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
 __global__ __launch_bounds__(NT) void k_dt(Launch L, const double* __restrict__ P,
                                            const double* __restrict__ B,
                                            double* __restrict__ dt_part) {
-  const Tile tl = xcd_tile();
-  const BlockInfo bi = L.blk[L.blist ? L.blist[tl.y] : tl.y];
+  const BlockTile bt = block_tile(L);
+  const BlockInfo bi = L.blk[bt.blk];
   const int g = L.ph.ng;
   Cell c;
-  const bool valid = region_cell(bi, tl.x * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
+  const bool valid = region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
                                  g, g, c);
   double dtc = __longlong_as_double(0x7FF0000000000000LL);
   if (valid) {
@@ -842,7 +842,7 @@ __global__ __launch_bounds__(NT) void k_dt(Launch L, const double* __restrict__ 
     dtc = cell_dt(Pc, Bc, m, L.ph, bi.idx);
   }
   const double r = block_min(dtc);
-  if (threadIdx.x == 0) dt_part[(int64_t)tl.y * gridDim.x + tl.x] = r;
+  if (threadIdx.x == 0) dt_part[bt.slot] = r;
 }
 
 // one workgroup reduces the partials into the step's dt (order-free minimum)
@@ -909,7 +909,9 @@ __global__ __launch_bounds__(NT) void k_divb(Launch L, const double* __restrict_
                        (fabs(f1) + fabs(f0)) / bi.dx[2];
     if (field) field[5 * bi.off + l] = dv;
     a = fabs(dv);
-    r = den > 0.0 ? a / den : 0.0;
+    // relative where the face values carry full precision (den >= 2^-969, 2^53 times the
+    // smallest normal double); a field-free region's subnormal values carry none
+    r = den >= 0x1p-969 ? a / den : 0.0;
   }
   // workgroup maxima as partials [2][slot] (reduced by k_divb_final)
   __shared__ double red[2][NT / 64];
@@ -1135,6 +1137,15 @@ void launch_emf(const Launch& L, const double* F, double* E) {
   hipLaunchKernelGGL(k_emf, grid, dim3(NT), 0, L.stream, Lc, F, E);
 }
 
+__global__ __launch_bounds__(NT) void k_fill(double* __restrict__ x, int64_t n, double v) {
+  const int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x;
+  if (i < n) x[i] = v;
+}
+
+void launch_fill(const Launch& L, double* x, int64_t n, double v) {
+  if (n > 0) hipLaunchKernelGGL(k_fill, dim3(cdiv(n, NT)), dim3(NT), 0, L.stream, x, n, v);
+}
+
 int64_t dt_partials(const Launch& L) {
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
   return (int64_t)cdiv(r, NT) * L.nblk;
@@ -1199,9 +1210,13 @@ int64_t launch_update(const Launch& L, const double* Pn, const double* Bn, const
   return (int64_t)grid.x * grid.y;
 }
 
-void launch_dt(const Launch& L, const double* P, const double* B, double* dt_part) {
+int64_t launch_dt(const Launch& L, const double* P, const double* B, double* dt_part,
+                  bool work_list) {
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
-  hipLaunchKernelGGL(k_dt, dim3(cdiv(r, NT), L.nblk), dim3(NT), 0, L.stream, L, P, B, dt_part);
+  Launch Lc;
+  const dim3 grid = stage_grid(L, work_list ? WL_CELLS : -1, r, Lc);
+  hipLaunchKernelGGL(k_dt, grid, dim3(NT), 0, L.stream, Lc, P, B, dt_part);
+  return (int64_t)grid.x * grid.y;
 }
 
 void launch_dt_final(const Launch& L, const double* dt_part) {

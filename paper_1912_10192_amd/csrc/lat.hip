@@ -279,11 +279,12 @@ __global__ __launch_bounds__(LT) void k_sync_c2p(Launch L, const SyncCell* __res
 // dt of a cycle: min over partials of the Courant step / 2^lat of the partial's block
 __global__ __launch_bounds__(LT) void k_dt_final_lat(Counters* cnt, const double* __restrict__ part,
                                                      int64_t n, int gridx,
-                                                     const BlockInfo* __restrict__ blk) {
+                                                     const BlockInfo* __restrict__ blk,
+                                                     const int2* __restrict__ wl) {
   __shared__ double red[LT];
   double v = __longlong_as_double(0x7FF0000000000000LL);
   for (int64_t i = threadIdx.x; i < n; i += LT) {
-    const int b = (int)(i / gridx);
+    const int b = wl ? wl[i].x : (int)(i / gridx);
     v = fmin(v, ldexp(part[i], -blk[b].lat));
   }
   red[threadIdx.x] = v;
@@ -352,8 +353,10 @@ void launch_sync(const Launch& L, const SyncCell* cells, int64_t ncell, const Sy
                        P, B, Ubuf);
 }
 
-void launch_dt_final_lat(const Launch& L, const double* part, int64_t n, int gridx) {
-  hipLaunchKernelGGL(k_dt_final_lat, dim3(1), dim3(LT), 0, L.stream, L.cnt, part, n, gridx, L.blk);
+void launch_dt_final_lat(const Launch& L, const double* part, int64_t n, int gridx,
+                         const int2* wl) {
+  hipLaunchKernelGGL(k_dt_final_lat, dim3(1), dim3(LT), 0, L.stream, L.cnt, part, n, gridx, L.blk,
+                     wl);
 }
 
 void launch_tsim_cycle(const Launch& L, double substeps) {

@@ -190,7 +190,7 @@ class Desc:
         d.c2p_tol = cfg.get("tol", 1e-12)
         d.mlp_weights = mlp_blob.data_ptr() if mlp_blob is not None else None
         self.mlp_blob = mlp_blob
-        d.batched = 1 if batched else 0
+        d.batched = int(batched) if not isinstance(batched, bool) else (1 if batched else 0)
         d.profile = 1 if profile else 0
         self.d = d
 

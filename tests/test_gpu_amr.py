@@ -117,13 +117,15 @@ def test_torus_three_level_polar_bands_match_oracle():
 
 
 def test_full_size_refined_lat_grid_properties():
-    """The 512x256x256-effective polar-refined grid with four time levels, one batched
+    """The 512x256x256-effective refined grid with four time levels as the batched
+    workload specifies it (1344 blocks of 64x32x32, 32x16x16 and 16x8x8), one batched
     (graph-captured) cycle with the learned guess off: every cell finite, every inversion
     converged without the last-resort tier, div B at round-off, the schedule's step counts
     per level, and the refined-and-LAT-effective accounting."""
-    cfg = dict(configs.TORUS_AMR_LAT)
-    lats = grmhd.lat_levels_by_radius(cfg, cfg["lat_edges"])
-    blocks = configs.polar_smr_blocks(cfg["n"], cfg["block"][0], lats)
+    cfg = dict(configs.TORUS_AMR3)
+    blocks = configs.amr_lat_blocks(cfg["n"], lat_edges=cfg["lat_edges"])
+    lats = sorted({b["lat"] for b in blocks})
+    assert len(blocks) == 1344 and lats == [0, 1, 2, 3]
     say(f"[amr] full size {cfg['n']}, {len(blocks)} blocks, levels {lats}")
     state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
     lmax = [max(b["lev"][d] for b in blocks) for d in range(3)]

@@ -73,3 +73,19 @@ def test_torus_fast_refined_equator_matches_oracle():
     state = initdata.torus_state(eff, **configs.TORUS_INIT)
     grid, ref, worst = run_pair(cfg, blocks, state, 2, batched=True)
     _check(grid, worst)
+
+
+def test_cfg3_shaped_layout_matches_oracle():
+    """the batched refinement + time-level workload's layout at reduced size: uneven
+    blocks (16x8x8 and 32x16x16 in the equatorial band, 16x4x8 mid-latitude and 16x4x4
+    cap blocks), phi halved per level toward each pole (3 levels), 4 time levels by
+    radius, refinement faces between time levels; one graph-captured cycle with the
+    learned guess off"""
+    eff = (128, 64, 16)
+    shapes = dict(eq_in=(16, 8, 8), eq_out=(32, 16, 16), mid=(16, 4, 8), cap=(16, 4, 4))
+    blocks = configs.amr_lat_blocks(eff, shapes)
+    assert max(b["lat"] for b in blocks) == 3
+    cfg = configs.scaled(configs.TORUS_UNIFORM, eff, ng=3)
+    state = initdata.torus_state(eff, **configs.TORUS_INIT)
+    grid, ref, worst = run_pair(cfg, blocks, state, 1, batched=True)
+    _check(grid, worst)

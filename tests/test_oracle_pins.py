@@ -352,3 +352,22 @@ def test_two_starts_newton_goes_first_from_the_smaller_misfit():
             assert Pr[0] == pytest.approx(P[0], rel=1e-9)
         _, tier, _ = oracle.cons2prim(U, gcov, gcon, gdet, alpha, gam, far, far, 1e-12, 2)
         assert tier != 0
+
+
+def test_relative_divb_skips_subnormal_fields():
+    """the relative div B maximum runs over cells whose face values carry full precision:
+    a field of subnormal values (a field-free region that underflowed) has an O(1)
+    relative rounding and is left out of the relative form, not out of the absolute one"""
+    from tests.helpers import mink_cfg
+    cfg = mink_cfg((4, 4, 4), recon=0, riemann=0)
+    g = oracle.Grid(cfg)
+    P, B = g.zeros()
+    ng = cfg["ng"]
+    B[0, ng:ng + 4, ng:ng + 4, ng:ng + 5] = 1.0
+    B[0, ng + 1, ng + 1, ng + 1] = 1.0 + 2.0 ** -40          # a planted divergence in a normal field
+    a, r = g.divb_rel(B)
+    assert a > 0 and r > 0
+    B[0, ng:ng + 4, ng:ng + 4, ng:ng + 5] = 5e-324 * 3.0     # subnormal field, exactly div-free
+    B[0, ng + 2, ng + 2, ng + 2] = 5e-324 * 4.0              # and one subnormal step of one ulp
+    a, r = g.divb_rel(B)
+    assert a > 0 and r == 0.0
