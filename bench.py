@@ -16,6 +16,8 @@ resident in HBM before the timed region.  Paths timed on the same initial state:
   plain             one launch per block and kernel class in the same LAT order (the
                     paper's launch structure), plain guess
   global_dt         the same blocks on one global time step, batched launches
+  disk5             the large tilted thin disk (effective 1024x384x384, density-refined,
+                    five time levels), batched launches + learned guess
 The headline value is real zone-cycles/s (cells x their own steps / wall time), the
 median of `runs` runs of exactly `steps` cycles; LAT-effective and refinement-and-LAT-
 effective rates are reported beside it.  The roofline block reports the dominant kernel
@@ -296,6 +298,27 @@ def roofline(cls_ms, cls_n, blocks, spl):
     return out
 
 
+def disk_leg(args, blob, sync, log):
+    """the large tilted thin disk: effective 1024x384x384 on r in [1.2, 1000], density-
+    refined blocks with phi-halved polar caps, five time levels (a cycle is 16 finest
+    substeps), batched launches + learned guess"""
+    from paper_1912_10192_amd import configs, initdata
+
+    cfg = dict(configs.DISK5)
+    blocks = configs.disk_blocks(cfg["n"])
+    procs = min(16, host_info()["cpus_available"] or 1)
+    t0 = time.perf_counter()
+    bs = initdata.disk_block_states(cfg, blocks, procs=procs)
+    log(f"[bench] disk5: {len(blocks)} blocks, initial data in {time.perf_counter() - t0:.1f} s")
+    cycles = max(1, args.steps // 5)
+    out, _ = run_leg("disk5_batched_learned", cfg, blocks, bs, 1, blob, cycles, 1,
+                     max(3, args.runs // 2), sync, log)
+    out["workload"] = cfg["name"]
+    out["blocks"] = len(blocks)
+    out["cells"] = sum(b["n"][0] * b["n"][1] * b["n"][2] for b in blocks)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,11 +395,12 @@ def main():
         gsteps = args.steps * head["substeps_per_cycle"]
         glob, _ = run_leg("global_dt", cfg, flat, bs, 2, None, gsteps, args.warmup, args.runs,
                           sync, log)
+        disk = disk_leg(args, blob, sync, log)
         cls_ms, cls_n, spl = profiled_classes(cfg, blocks, bs, blob, tune, args.steps, sync, log)
         out.update({
             "roofline": roofline(cls_ms, cls_n, blocks, spl),
             "kernel_ms_per_cycle": {k: v / args.steps for k, v in cls_ms.items()},
-            "batched": batched, "plain": plain, "global_dt": glob,
+            "batched": batched, "plain": plain, "global_dt": glob, "disk5": disk,
             "speedup_vs_plain": head["value_real"] / plain["value_real"],
             "batching_gain": batched["value_real"] / plain["value_real"],
             "learned_gain": head["value_real"] / batched["value_real"],

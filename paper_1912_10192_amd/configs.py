@@ -162,3 +162,148 @@ def amr_lat_blocks(n, shapes=None, lat_edges=(2.4, 4.8, 9.6), xlo=None, xhi=None
 TORUS_AMR3 = dict(KS_TORUS_BASE, name="torus-eff512x256x256-amr-lat4-1344blocks", n=(512, 256, 256),
                   block=(64, 32, 32), ng=3, recon=1, riemann=1, cycles=25,
                   lat_edges=(2.4, 4.8, 9.6))
+
+
+# Large single-GPU tilted thin disk: effective 1024x384x384 on r in [1.2, 1000] (disk_blocks)
+DISK5 = dict(KS_TORUS_BASE, name="disk-eff1024x384x384-tilt45-amr2-lat5", n=(1024, 384, 384),
+             block=(32, 24, 24), ng=3, recon=1, riemann=1, cycles=100,
+             xhi=(math.log(1000.0), math.pi, 2.0 * math.pi))
+
+
+def _touching(lo, hi, n):
+    """boolean matrices of block boxes [lo, hi) in effective cells: blocks that touch (share
+    a face, an edge or a corner; phi periodic), and blocks that meet across the polar axis
+    (both on the axis, touching in x1 and in phi after a shift by pi)"""
+    import numpy as np
+
+    t = np.ones((len(lo), len(lo)), dtype=bool)
+    for d, Nd in enumerate(n):
+        a0, a1 = lo[:, d][:, None], hi[:, d][:, None]
+        b0, b1 = lo[:, d][None, :], hi[:, d][None, :]
+        x = (a0 <= b1) & (b0 <= a1)
+        if d == 2:
+            x |= ((a0 == 0) & (b1 == Nd)) | ((b0 == 0) & (a1 == Nd))
+        t &= x
+    N2, N3 = n[1], n[2]
+    pole = np.zeros_like(t)
+    x1 = (lo[:, 0][:, None] <= hi[:, 0][None, :]) & (lo[:, 0][None, :] <= hi[:, 0][:, None])
+    s0 = (lo[:, 2] + N3 // 2) % N3
+    s1 = s0 + (hi[:, 2] - lo[:, 2])
+    ph = np.zeros_like(t)
+    for shift in (-N3, 0, N3):
+        ph |= (s0[:, None] + shift <= hi[:, 2][None, :]) & (lo[:, 2][None, :] <= s1[:, None] + shift)
+    for on in (lo[:, 1] == 0, hi[:, 1] == N2):
+        pole |= on[:, None] & on[None, :] & x1 & ph
+    return t, pole
+
+
+def disk_blocks(n, block=(32, 24, 24), init=None, levels=2, rho_min=1e-3, n_lat=5,
+                xlo=None, xhi=None):
+    """Block layout of the tilted thin disk (paper Sec. 3.3 refinement by density, Sec.
+    3.4 coarser phi toward the poles, Sec. 3.5 time levels) for an effective grid n at the
+    finest level: base blocks of `block` cells at refinement level 0 (n / 2^levels in r and
+    theta), each block split into 8 children of the same cell shape where its largest disk
+    density (at its cell centres) exceeds rho_min of the midplane maximum, `levels` times;
+    then refined until blocks that touch differ by at most one level, blocks that meet
+    across the polar axis have one level and no block outside the polar caps (theta <
+    pi/8 or > 7 pi/8) is finer than a cap block it touches; cap blocks take half the phi
+    cells (x3 level one lower).  Per-dimension refinement levels: (L, L, L + 1), caps (L, L, L).  Time
+    level: log2 of the block's Courant step over the smallest one, with the light speed in
+    flat proper lengths (r dx1, r dtheta, r sin(theta) dphi) as the signal speed, at most
+    n_lat - 1, then lowered until touching blocks differ by at most one level."""
+    import numpy as np
+
+    from paper_1912_10192_amd import initdata
+
+    p = dict(initdata.DISK_INIT, **(init or {}))
+    disk = initdata.Disk(**p)
+    xlo = xlo if xlo is not None else DISK5["xlo"]
+    xhi = xhi if xhi is not None else DISK5["xhi"]
+    N1, N2, N3 = n
+    L = levels
+    b1, b2, b3 = block
+    base = (N1 >> L, N2 >> L, N3 >> L)
+    nb = (base[0] // b1, base[1] // b2, base[2] // b3)
+
+    def box(t):
+        """effective-cell box of tree node (level, i, j, k)"""
+        l, i, j, k = t
+        s = 1 << (L - l)
+        lo = (i * b1 * s, j * b2 * s, k * b3 * s)
+        return lo, (lo[0] + b1 * s, lo[1] + b2 * s, lo[2] + b3 * s)
+
+    def centres(t, cap=False):
+        l, i, j, k = t
+        lo, hi = box(t)
+        m3 = b3 // 2 if cap else b3
+        out = []
+        for d, m in enumerate((b1, b2, m3)):
+            w = (hi[d] - lo[d]) / m
+            out.append(xlo[d] + (lo[d] + (np.arange(m) + 0.5) * w) * (xhi[d] - xlo[d]) / n[d])
+        return out
+
+    def dense(t):
+        x1, x2, x3 = centres(t)
+        X3, X2, X1 = np.meshgrid(x3, x2, x1, indexing="ij")
+        rho, _, _ = disk.state(np.exp(X1), X2, X3)
+        return float(rho.max()) > rho_min
+
+    nodes = [(0, i, j, k) for k in range(nb[2]) for j in range(nb[1]) for i in range(nb[0])]
+
+    def split(t):
+        l, i, j, k = t
+        return [(l + 1, 2 * i + a, 2 * j + c, 2 * k + e) for e in (0, 1) for c in (0, 1) for a in (0, 1)]
+
+    for lev in range(L):
+        nxt = []
+        for t in nodes:
+            nxt += split(t) if t[0] == lev and dense(t) else [t]
+        nodes = nxt
+    # 2:1 balance, one level across the pole, and polar-cap blocks (theta < pi/8 or >
+    # 7 pi/8) as fine as any block outside the caps that they touch (a cap block has half
+    # the phi cells, one x3 level lower, so a finer non-cap neighbour would be two x3
+    # levels away)
+    N2 = n[1]
+    while True:
+        lo = np.array([box(t)[0] for t in nodes])
+        hi = np.array([box(t)[1] for t in nodes])
+        lv = np.array([t[0] for t in nodes])
+        cap = (hi[:, 1] <= N2 // 8) | (lo[:, 1] >= N2 - N2 // 8)
+        T, P = _touching(lo, hi, n)
+        need = (T & (lv[None, :] - lv[:, None] >= 2)).any(axis=1)
+        need |= (P & (lv[None, :] > lv[:, None])).any(axis=1)
+        need |= cap & (T & (lv[None, :] > lv[:, None]) & ~cap[None, :]).any(axis=1)
+        if not need.any():
+            break
+        nxt = []
+        for t, nd in zip(nodes, need):
+            nxt += split(t) if nd else [t]
+        nodes = nxt
+    T, P = _touching(lo, hi, n)
+    T |= P
+    if b3 % 2:
+        cap[:] = False
+    # blocks, with time levels from the light-crossing Courant step
+    blocks, dts = [], []
+    for t, c in zip(nodes, cap):
+        l, i, j, k = t
+        m3 = b3 // 2 if c else b3
+        lev = (l, l, l if c else l + 1)
+        blocks.append(dict(org=(i * b1, j * b2, k * m3), n=(b1, b2, m3), lev=lev, lat=0))
+        x1, x2, x3 = centres(t, c)
+        r = np.exp(x1)[None, :]
+        th = x2[:, None]
+        dx = [(xhi[d] - xlo[d]) / (n[d] >> (L + (1 if d == 2 else 0) - lev[d])) for d in range(3)]
+        inv = 1.0 / (r * dx[0]) + 1.0 / (r * dx[1]) + 1.0 / (r * np.sin(th) * dx[2])
+        dts.append(float((1.0 / inv).min()))
+    dts = np.array(dts)
+    lat = np.clip(np.floor(np.log2(dts / dts.min())).astype(int), 0, n_lat - 1)
+    while True:
+        lim = np.where(T, lat[None, :] + 1, 1 << 30).min(axis=1)
+        new = np.minimum(lat, lim)
+        if np.array_equal(new, lat):
+            break
+        lat = new
+    for b, x in zip(blocks, lat):
+        b["lat"] = int(x)
+    return blocks

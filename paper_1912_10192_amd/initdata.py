@@ -266,3 +266,201 @@ def block_states(state, blocks, lmax):
                     B2[o[2]:o[2] + n[2], o[1]:o[1] + n[1] + 1, o[0]:o[0] + n[0]].copy(),
                     B3[o[2]:o[2] + n[2] + 1, o[1]:o[1] + n[1], o[0]:o[0] + n[0]].copy()))
     return out
+
+
+# --------------------------------------------------------------------- tilted thin disk
+
+DISK_INIT = dict(a=0.9375, gam=4.0 / 3.0, tilt=math.pi / 4, h_r=0.03, r_in=6.0, r_out=200.0,
+                 beta=10.0, amp=0.01, seed=20191221, rho_fl_c=1e-6, rho_fl_p=-1.5,
+                 u_fl_c=1e-9, u_fl_p=-10.0 / 3.0)
+
+
+def _smoothstep(x):
+    x = np.clip(x, 0.0, 1.0)
+    return x * x * (3.0 - 2.0 * x)
+
+
+class Disk:
+    """A thin disk in a frame tilted by `tilt` about the x axis of the hole's frame
+    (flat spherical positions x = r sin(th) cos(ph), ...):
+      rho = (R'/r_in)^(-3/2) exp(-z'^2 / (2 H^2)) T(R'),  H = h_r R',
+    T a C1 taper from 0 to 1 over [r_in, 1.1 r_in] and back to 0 over [0.9 r_out, r_out],
+    normalised to a midplane maximum of 1; p = rho h_r^2 / R'; Keplerian rotation
+    v = R'^(-1/2) about z'; a toroidal field about z' from the vector potential
+    A = A_R'(R', z') R'-hat, A_R' = sqrt(2 p_mid(R') / beta0) sqrt(pi) H erf(z' / (2H)),
+    whose curl is the toroidal field sqrt(2 p / beta0) (in flat space)."""
+
+    def __init__(self, a, gam, tilt, h_r, r_in, r_out, **_):
+        self.a, self.gam, self.h_r, self.r_in, self.r_out = a, gam, h_r, r_in, r_out
+        self.ct, self.st = math.cos(tilt), math.sin(tilt)
+        R = np.linspace(r_in, r_out, 200001)
+        self.norm = float(np.max(self._mid_raw(R)))
+
+    def _taper(self, R):
+        return (_smoothstep((R - self.r_in) / (0.1 * self.r_in))
+                * _smoothstep((self.r_out - R) / (0.1 * self.r_out)))
+
+    def _mid_raw(self, R):
+        return (np.maximum(R, 1e-300) / self.r_in) ** -1.5 * self._taper(R)
+
+    @staticmethod
+    def _trig(th, ph):
+        s, c = np.sin(th), np.cos(th)
+        s = np.where((th == 0.0) | (th == math.pi), 0.0, s)     # exactly on the axis
+        c = np.where(th == 0.0, 1.0, np.where(th == math.pi, -1.0, c))
+        return s, c, np.sin(ph), np.cos(ph)
+
+    def frame(self, r, th, ph):
+        """hole-frame Cartesian position and disk-frame (x', y', z')"""
+        s, c, sp, cp = self._trig(th, ph)
+        x, y, z = r * s * cp, r * s * sp, r * c
+        return (x, y, z), (x, self.ct * y + self.st * z, -self.st * y + self.ct * z)
+
+    def rho_mid(self, R):
+        return self._mid_raw(R) / self.norm
+
+    def state(self, r, th, ph):
+        """disk density, internal energy (gamma-law p = rho h_r^2 / R') and the hole-frame
+        Cartesian Keplerian velocity at points"""
+        (x, y, z), (xp, yp, zp) = self.frame(r, th, ph)
+        R = np.sqrt(xp * xp + yp * yp)
+        H = self.h_r * np.maximum(R, 1e-300)
+        rho = self.rho_mid(R) * np.exp(-zp * zp / (2.0 * H * H))
+        u = rho * self.h_r ** 2 / np.maximum(R, 1e-300) / (self.gam - 1.0)
+        v = np.maximum(R, 1e-300) ** -0.5
+        vxp, vyp = -v * yp / np.maximum(R, 1e-300), v * xp / np.maximum(R, 1e-300)
+        # back to the hole's frame (z' has no velocity)
+        vx, vy, vz = vxp, self.ct * vyp, self.st * vyp
+        return rho, u, (vx, vy, vz)
+
+    def potential(self, r, th, ph, beta0=1.0):
+        """hole-frame Cartesian vector potential A = A_R' R'-hat"""
+        (x, y, z), (xp, yp, zp) = self.frame(r, th, ph)
+        R = np.sqrt(xp * xp + yp * yp)
+        Rs = np.maximum(R, 1e-300)
+        H = self.h_r * Rs
+        pmid = self.rho_mid(R) * self.h_r ** 2 / Rs
+        from scipy.special import erf
+        AR = np.sqrt(2.0 * pmid / beta0) * math.sqrt(math.pi) * H * erf(zp / (2.0 * H))
+        axp, ayp = AR * xp / Rs, AR * yp / Rs
+        return axp, self.ct * ayp, self.st * ayp
+
+
+def _edge_integrals(disk, cfg, b, lmax):
+    """line integrals of the covariant vector potential along every edge of block b
+    (internal coordinates x1 = ln r, x2 = theta, x3 = phi), each the sum of the midpoint
+    values times length of the finest-level sub-edges it contains, so that a coarse
+    edge's integral is the sum of its fine sub-edges'.  Returns I1 [n3+1][n2+1][n1],
+    I2 [n3+1][n2][n1+1], I3 [n3][n2+1][n1+1]."""
+    N = cfg["n"]
+    lev, o, n = b["lev"], b["org"], b["n"]
+    f = [1 << (lmax[d] - lev[d]) for d in range(3)]
+    dxf = [(cfg["xhi"][d] - cfg["xlo"][d]) / N[d] for d in range(3)]
+
+    def coords(axis):
+        # finest-level sample coordinates: sub-edge midpoints along `axis`, nodes across;
+        # broadcast shapes [x3][x2][x1]
+        out = []
+        for d in range(3):
+            if d == axis:
+                c = (o[d] * f[d] + np.arange(n[d] * f[d]) + 0.5) * dxf[d]
+            else:
+                c = (o[d] + np.arange(n[d] + 1)) * f[d] * dxf[d]
+            shape = [1, 1, 1]
+            shape[2 - d] = -1
+            out.append((cfg["xlo"][d] + c).reshape(shape))
+        return out
+
+    res = []
+    for axis in range(3):
+        x1, x2, x3 = coords(axis)
+        r = np.exp(x1)
+        s, c, sp, cp = Disk._trig(x2, x3)
+        Ax, Ay, Az = disk.potential(r, x2, x3)
+        if axis == 0:     # d x / d ln r = position
+            Ai = Ax * (r * s * cp) + Ay * (r * s * sp) + Az * (r * c)
+        elif axis == 1:   # d x / d theta
+            Ai = Ax * (r * c * cp) + Ay * (r * c * sp) - Az * (r * s)
+        else:             # d x / d phi
+            Ai = -Ax * (r * s * sp) + Ay * (r * s * cp)
+        Ai = np.broadcast_to(Ai, (x3.size, x2.size, x1.size)) * dxf[axis]
+        shape = list(Ai.shape)
+        ax = 2 - axis
+        shape[ax:ax + 1] = [n[axis], f[axis]]
+        res.append(Ai.reshape(shape).sum(axis=ax + 1))
+    return res
+
+
+def _disk_block(args):
+    """one block of disk_block_states before the field is scaled: (P, B1, B2, B3, max p_g,
+    max b^2/2)"""
+    cfg, b, lmax, p = args
+    disk = Disk(**p)
+    N = cfg["n"]
+    lev, o, n = b["lev"], b["org"], b["n"]
+    Nl = [N[d] >> (lmax[d] - lev[d]) for d in range(3)]
+    dx = [(cfg["xhi"][d] - cfg["xlo"][d]) / Nl[d] for d in range(3)]
+    x1 = (cfg["xlo"][0] + (o[0] + np.arange(n[0]) + 0.5) * dx[0])[None, None, :]
+    x2 = (cfg["xlo"][1] + (o[1] + np.arange(n[1]) + 0.5) * dx[1])[None, :, None]
+    x3 = (cfg["xlo"][2] + (o[2] + np.arange(n[2]) + 0.5) * dx[2])[:, None, None]
+    shp = (n[2], n[1], n[0])
+    r = np.exp(x1)
+    rho_d, u_d, (vx, vy, vz) = disk.state(r, x2, x3)
+    rho_a = p["rho_fl_c"] * r ** p["rho_fl_p"]
+    u_a = p["u_fl_c"] * r ** p["u_fl_p"]
+    ins = np.broadcast_to(rho_d > rho_a, shp)
+    s, c, sp, cp = Disk._trig(x2, x3)
+    vr = vx * s * cp + vy * s * sp + vz * c
+    vth = vx * c * cp + vy * c * sp - vz * s
+    vph = -vx * sp + vy * cp
+    ut1 = np.where(ins, vr / r, 0.0)
+    ut2 = np.where(ins, vth / r, 0.0)
+    ut3 = np.where(ins, vph / np.maximum(r * s, 1e-300), 0.0)
+    rho = np.where(ins, rho_d, rho_a)
+    uu = np.where(ins, np.maximum(u_d, u_a), u_a)
+    if p["amp"] != 0.0:
+        kk, jj, ii = np.meshgrid(o[2] + np.arange(n[2]), o[1] + np.arange(n[1]),
+                                 o[0] + np.arange(n[0]), indexing="ij")
+        code = (lev[0] * 16 + lev[1]) * 16 + lev[2]
+        gidx = (((np.uint64(code) * np.uint64(Nl[2]) + kk.astype(np.uint64)) * np.uint64(Nl[1])
+                 + jj.astype(np.uint64)) * np.uint64(Nl[0]) + ii.astype(np.uint64))
+        xi = uniform01(p["seed"], gidx)
+        rho = np.where(ins, rho * (1.0 + p["amp"] * (2.0 * xi - 1.0)), rho)
+    P = np.stack([rho, uu, ut1, ut2, ut3])
+    I1, I2, I3 = _edge_integrals(disk, cfg, b, lmax)
+    a12, a13, a23 = dx[0] * dx[1], dx[0] * dx[2], dx[1] * dx[2]
+    B1 = (I3[:, 1:, :] - I3[:, :-1, :]) / a23 - (I2[1:, :, :] - I2[:-1, :, :]) / a23
+    B2 = (I1[1:, :, :] - I1[:-1, :, :]) / a13 - (I3[:, :, 1:] - I3[:, :, :-1]) / a13
+    B3 = (I2[:, :, 1:] - I2[:, :, :-1]) / a12 - (I1[:, 1:, :] - I1[:, :-1, :]) / a12
+    # field strength of this block (cell-centred coordinate field, Kerr-Schild b^2)
+    th = np.broadcast_to(x2[0], (n[1], n[0]))
+    rr = np.broadcast_to(r[0], (n[1], n[0]))
+    gdet = rr * (rr * rr + p["a"] ** 2 * np.cos(th) ** 2) * np.sin(th)
+    Bc = np.stack([0.5 * (B1[..., 1:] + B1[..., :-1]), 0.5 * (B2[:, 1:] + B2[:, :-1]),
+                   0.5 * (B3[1:] + B3[:-1])]) / gdet[None, None]
+    bsq = np.stack([_bsq(P[:, k], Bc[:, k], rr, th, p["a"]) for k in range(n[2])])
+    return P, B1, B2, B3, float(np.max((p["gam"] - 1.0) * uu)), float(np.max(0.5 * bsq))
+
+
+def disk_block_states(cfg, blocks, init=None, procs=1):
+    """per-block interior arrays of the tilted disk (prims at each block's cell centres,
+    face fields from the edge integrals of the vector potential, scaled to max p_g /
+    max(b^2/2) = beta over all blocks), with the atmosphere rho = rho_fl r^rho_fl_p,
+    u_g = u_fl r^u_fl_p outside the disk and a seeded density perturbation rho (1 + amp
+    (2 xi - 1)) in disk cells, xi keyed by the cell's index on its block's level grid
+    and the level.  procs > 1 builds the blocks in that many worker processes (the
+    result does not depend on it)."""
+    p = dict(DISK_INIT, **(init or {}))
+    lmax = [max(b["lev"][d] for b in blocks) for d in range(3)]
+    work = [(cfg, b, lmax, p) for b in blocks]
+    if procs > 1:
+        import multiprocessing as mp
+
+        with mp.get_context("spawn").Pool(procs) as pool:
+            out = pool.map(_disk_block, work, chunksize=max(1, len(work) // (8 * procs)))
+    else:
+        out = [_disk_block(w) for w in work]
+    pmax = max(o[4] for o in out)
+    bmax = max(o[5] for o in out)
+    scale = math.sqrt(pmax / (p["beta"] * bmax)) if bmax > 0.0 else 0.0
+    return [(P, scale * B1, scale * B2, scale * B3) for P, B1, B2, B3, _, _ in out]

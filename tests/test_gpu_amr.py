@@ -38,11 +38,14 @@ def block_err(got, want):
     return e
 
 
-def run_pair(cfg, blocks, state, cycles, batched=False):
+def run_pair(cfg, blocks, state, cycles, batched=False, bs=None):
+    """the GPU grid and the oracle's driver from one initial state (a global state on
+    the finest grid, or per-block states bs), `cycles` cycles; the worst differences"""
     say(f"[amr] n={cfg['n']} blocks={len(blocks)} lats={[b['lat'] for b in blocks]} "
         f"cycles={cycles} batched={batched}")
     ref = AmrGrid(cfg, blocks)
-    bs = initdata.block_states(state, ref.blocks, ref.Lmax)
+    if bs is None:
+        bs = initdata.block_states(state, ref.blocks, ref.Lmax)
     ref.set_blocks(bs)
     grid = grmhd.Grid(cfg, blocks=blocks, batched=batched)
     grid.set_blocks(bs)
