@@ -20,6 +20,7 @@ _lib = None
 MINK, KS = 0, 1
 PLM, PPM = 0, 1
 LLF, HLLE = 0, 1
+EMF_AVERAGE, EMF_UPWIND = 0, 1
 BC_OUTFLOW, BC_POLAR, BC_PERIODIC = 0, 1, 2
 
 
@@ -41,7 +42,7 @@ class Desc(C.Structure):
                 ("xlo", C.c_double * 3), ("xhi", C.c_double * 3), ("courant", C.c_double),
                 ("rho_fl_c", C.c_double), ("rho_fl_p", C.c_double), ("u_fl_c", C.c_double),
                 ("u_fl_p", C.c_double), ("bsq_rho_max", C.c_double), ("bsq_u_max", C.c_double),
-                ("gamma_max", C.c_double), ("tol", C.c_double)]
+                ("gamma_max", C.c_double), ("tol", C.c_double), ("emf", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -128,6 +129,7 @@ def make_desc(cfg: dict) -> Desc:
     d.bsq_u_max = cfg.get("bsq_u_max", 1e300)
     d.gamma_max = cfg.get("gamma_max", 1e150)
     d.tol = cfg.get("tol", 1e-12)
+    d.emf = cfg.get("emf", EMF_AVERAGE)
     return d
 
 

@@ -29,6 +29,7 @@ struct orc_ctx {
   double* u_fl;
   double* flux;           /* [3][9][ncell] */
   double* emf;            /* [3][ncell] */
+  double* eref;           /* [3][ncell] cell-centred EMFs of the stage state (upwinding) */
   double* bcell;          /* [3][ncell] cell-centred B^i of the stage state */
   double *P1, *B1, *P2, *B2;
 };
@@ -632,6 +633,7 @@ orc_ctx* orc_create(const orc_desc* d) {
     }
   c->flux = (double*)calloc(c->ncell * 27, sizeof(double));
   c->emf = (double*)calloc(c->ncell * 3, sizeof(double));
+  c->eref = (double*)calloc(c->ncell * 3, sizeof(double));
   c->bcell = (double*)calloc(c->ncell * 3, sizeof(double));
   c->P1 = (double*)calloc(c->ncell * 5, sizeof(double));
   c->B1 = (double*)calloc(c->ncell * 3, sizeof(double));
@@ -645,7 +647,7 @@ void orc_free(orc_ctx* c) {
   for (int k = 0; k < 3; k++) {
     free(c->gcov[k]); free(c->gcon[k]); free(c->gdet[k]); free(c->alpha[k]);
   }
-  free(c->conn); free(c->rho_fl); free(c->u_fl); free(c->flux); free(c->emf);
+  free(c->conn); free(c->rho_fl); free(c->u_fl); free(c->flux); free(c->emf); free(c->eref);
   free(c->bcell); free(c->P1); free(c->B1); free(c->P2); free(c->B2);
   free(c);
 }
@@ -864,6 +866,54 @@ static int apply_floors(const orc_ctx* c, double* P, const double* Bcon, const d
 }
 
 #define FL(d, q, K, J, I) c->flux[((size_t)(d) * 9 + (q)) * nc + IDX(c, K, J, I)]
+
+/* the value on the side the flow comes from: lo where the mass flux m is positive (flow
+ * toward the upper side), hi where it is negative, their mean where it vanishes */
+static double upwind(double lo, double hi, double m) {
+  if (m > 0.0) return lo;
+  if (m < 0.0) return hi;
+  return 0.5 * (lo + hi);
+}
+
+/* Gardiner & Stone's (2005) correction to the averaged EMF of the edge along x^(a+1) at
+ * padded position x (I, J, K), with (a, p, q) cyclic.  Around the edge lie the cells
+ * c[pp][qq] (pp, qq = 0 below, 1 above the edge in x^(p+1), x^(q+1)), two p-faces (normal
+ * p, at qq = 0, 1) carrying the face EMF -F_p(B^q) and two q-faces (normal q, at pp) with
+ * +F_q(B^p).  The gradients of the EMF between the edge and the cell centres, along p on
+ * each row and along q on each column, are taken from the row (column) upstream of the
+ * mass flux through the face between the two candidates; the correction is
+ *   1/4 [(dp_low - dp_high) + (dq_low - dq_high)],
+ * the dp at the lower/upper half of the edge in p (similarly q), which with the average
+ * gives the face's Riemann EMF for flows that vary along one direction only. */
+static double emf_upwind_correction(const orc_ctx* c, int a, const int x[3]) {
+  const size_t nc = c->ncell;
+  const int p = (a + 1) % 3, q = (a + 2) % 3;
+  double Ep[2], Eq[2], Mp[2], Mq[2], Er[2][2];
+  for (int s = 0; s < 2; s++) {
+    int y[3] = {x[0], x[1], x[2]};
+    y[q] -= 1 - s;   /* p-face at row s */
+    Ep[s] = -c->flux[((size_t)p * 9 + 5 + q) * nc + IDX(c, y[2], y[1], y[0])];
+    Mp[s] = c->flux[((size_t)p * 9 + 0) * nc + IDX(c, y[2], y[1], y[0])];
+    int z[3] = {x[0], x[1], x[2]};
+    z[p] -= 1 - s;   /* q-face at column s */
+    Eq[s] = c->flux[((size_t)q * 9 + 5 + p) * nc + IDX(c, z[2], z[1], z[0])];
+    Mq[s] = c->flux[((size_t)q * 9 + 0) * nc + IDX(c, z[2], z[1], z[0])];
+  }
+  for (int sp = 0; sp < 2; sp++)
+    for (int sq = 0; sq < 2; sq++) {
+      int y[3] = {x[0], x[1], x[2]};
+      y[p] -= 1 - sp;
+      y[q] -= 1 - sq;
+      Er[sp][sq] = c->eref[(size_t)a * nc + IDX(c, y[2], y[1], y[0])];
+    }
+  /* along p: upstream in q through the q-face of each column */
+  double dp_lo = upwind(Ep[0] - Er[0][0], Ep[1] - Er[0][1], Mq[0]);
+  double dp_hi = upwind(Er[1][0] - Ep[0], Er[1][1] - Ep[1], Mq[1]);
+  /* along q: upstream in p through the p-face of each row */
+  double dq_lo = upwind(Eq[0] - Er[0][0], Eq[1] - Er[1][0], Mp[0]);
+  double dq_hi = upwind(Er[0][1] - Eq[0], Er[1][1] - Eq[1], Mp[1]);
+  return 0.25 * ((dp_lo - dp_hi) + (dq_lo - dq_hi));
+}
 #define EM(d, K, J, I) c->emf[(size_t)(d) * nc + IDX(c, K, J, I)]
 
 /* Steps 1-2 of a stage: cell-centred field, face fluxes and edge EMFs of the stage
@@ -889,6 +939,28 @@ void orc_stage_flux(orc_ctx* c, const double* Ps, const double* Bs) {
           for (int q = 0; q < 9; q++) c->flux[((size_t)d * 9 + q) * nc + id] = F[q];
         }
   }
+  /* for upwinding, the EMF of each cell's own state: component a (edge along x^(a+1))
+   * is the flux of B^(p+1) along x^(q+1) with (a, p, q) cyclic, i.e. sqrt(-g) (b^p u^q -
+   * b^q u^p), on every cell next to a block edge */
+  if (c->d.emf == ORC_EMF_UPWIND) {
+    for (int K = g - 1; K <= g + n3; K++)
+      for (int J = g - 1; J <= g + n2; J++)
+        for (int I = g - 1; I <= g + n1; I++) {
+          size_t id = IDX(c, K, J, I);
+          size_t col = COL(c, J, I);
+          const double *gcov, *gcon;
+          double gdet, alpha, Pc[5], Bc[3];
+          geom_of(c, 0, col, &gcov, &gcon, &gdet, &alpha);
+          for (int v = 0; v < 5; v++) Pc[v] = Ps[v * nc + id];
+          for (int e = 0; e < 3; e++) Bc[e] = bc[e * nc + id];
+          for (int a = 0; a < 3; a++) {
+            int p = (a + 1) % 3, q = (a + 2) % 3;
+            double F[9];
+            orc_prim_to_flux(Pc, Bc, gcov, gcon, gdet, alpha, c->d.gam, q + 1, F);
+            c->eref[(size_t)a * nc + id] = F[5 + p];
+          }
+        }
+  }
   /* 2. edge EMFs as the average of the four neighbouring face fluxes of B */
   for (int K = g; K <= g + n3; K++)
     for (int J = g; J <= g + n2; J++)
@@ -905,6 +977,14 @@ void orc_stage_flux(orc_ctx* c, const double* Ps, const double* Bs) {
           EM(2, K, J, I) = pole ? 0.0
               : 0.25 * (FL(1, 5, K, J, I - 1) + FL(1, 5, K, J, I) - FL(0, 6, K, J, I)
                         - FL(0, 6, K, J - 1, I));
+        if (c->d.emf == ORC_EMF_UPWIND) {
+          int x[3] = {I, J, K};
+          int lim[3] = {I < g + n1, J < g + n2, K < g + n3};
+          for (int a = 0; a < 3; a++) {
+            if (!lim[a] || (a != 1 && pole)) continue;
+            EM(a, K, J, I) += emf_upwind_correction(c, a, x);
+          }
+        }
       }
 }
 

@@ -35,6 +35,10 @@ extern "C" {
 enum { ORC_MINK = 0, ORC_KS = 1 };
 enum { ORC_PLM = 0, ORC_PPM = 1 };
 enum { ORC_LLF = 0, ORC_HLLE = 1 };
+/* edge EMFs: the average of the four neighbouring face fluxes of B (Sec. 2.5), or that
+ * average corrected by the upwinded gradients of Gardiner & Stone (2005), which the
+ * paper applies by default (Sec. 2.5, Fig. 1) */
+enum { ORC_EMF_AVERAGE = 0, ORC_EMF_UPWIND = 1 };
 enum { ORC_BC_OUTFLOW = 0, ORC_BC_POLAR = 1, ORC_BC_PERIODIC = 2 };
 
 typedef struct {
@@ -44,6 +48,7 @@ typedef struct {
   double courant;
   double rho_fl_c, rho_fl_p, u_fl_c, u_fl_p, bsq_rho_max, bsq_u_max, gamma_max;
   double tol;
+  int32_t emf;   /* ORC_EMF_AVERAGE or ORC_EMF_UPWIND */
 } orc_desc;
 
 typedef struct {
