@@ -16,6 +16,7 @@ resident in HBM before the timed region.  Paths timed on the same initial state:
   plain             one launch per block and kernel class in the same LAT order (the
                     paper's launch structure), plain guess
   global_dt         the same blocks on one global time step, batched launches
+  emf_upwind        the headline path with Gardiner & Stone's upwinded edge EMFs
   disk5             the large tilted thin disk (effective 1024x384x384, density-refined,
                     five time levels), batched launches + learned guess
 The headline value is real zone-cycles/s (cells x their own steps / wall time), the
@@ -391,6 +392,8 @@ def main():
                              args.runs, sync, log)
         plain, _ = run_leg("plain", cfg, blocks, bs, 0, None, args.steps, args.warmup,
                            args.runs, sync, log, variants=tune)
+        upw, _ = run_leg("emf_upwind", dict(cfg, emf=1), blocks, bs, 1, blob, args.steps,
+                         args.warmup, args.runs, sync, log, variants=tune)
         flat = [dict(b, lat=0) for b in blocks]
         gsteps = args.steps * head["substeps_per_cycle"]
         glob, _ = run_leg("global_dt", cfg, flat, bs, 2, None, gsteps, args.warmup, args.runs,
@@ -401,6 +404,8 @@ def main():
             "roofline": roofline(cls_ms, cls_n, blocks, spl),
             "kernel_ms_per_cycle": {k: v / args.steps for k, v in cls_ms.items()},
             "batched": batched, "plain": plain, "global_dt": glob, "disk5": disk,
+            "emf_upwind": upw,
+            "emf_upwind_cost": head["value_real"] / upw["value_real"],
             "speedup_vs_plain": head["value_real"] / plain["value_real"],
             "batching_gain": batched["value_real"] / plain["value_real"],
             "learned_gain": head["value_real"] / batched["value_real"],

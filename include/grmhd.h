@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GRMHD_ABI_VERSION 1
+#define GRMHD_ABI_VERSION 2
 
 enum { GRMHD_OK = 0, GRMHD_EINVAL = -1, GRMHD_ENOMEM = -2, GRMHD_EHIP = -3,
        GRMHD_ESTATE = -4, GRMHD_EUNSUPPORTED = -5 };
@@ -49,6 +49,12 @@ enum { GRMHD_PLM_MC = 0, GRMHD_PPM = 1 };
 enum { GRMHD_LLF = 0, GRMHD_HLLE = 1 };
 enum { GRMHD_BC_OUTFLOW = 0, GRMHD_BC_POLAR = 1, GRMHD_BC_PERIODIC = 2 };
 enum { GRMHD_GUESS_PLAIN = 0, GRMHD_GUESS_MLP = 1 };
+/* edge EMFs (Sec. 2.5): the average of the four neighbouring face fluxes of B, or that
+ * average with the upwinded corrections of Gardiner & Stone (2005) that the paper applies
+ * by default (each corner takes the gradients of the EMF toward the neighbouring cell
+ * centres, where the EMF of the cell's own state sits, from the side upstream of the mass
+ * flux through the face between the candidates) */
+enum { GRMHD_EMF_AVERAGE = 0, GRMHD_EMF_UPWIND = 1 };
 
 /* One block of the grid (Sec. 3.3 block structure; Sec. 3.4 coarsening toward the
  * poles is refinement in some dimensions only).  The effective grid n_eff is the grid
@@ -58,8 +64,9 @@ enum { GRMHD_GUESS_PLAIN = 0, GRMHD_GUESS_MLP = 1 };
  * domain without overlap.  Blocks that touch (through faces, edges, corners and the
  * physical boundaries) differ by at most one level per dimension, never finer in one
  * dimension and coarser in another; refined blocks start and end on cells of the
- * coarser neighbour; blocks across a refinement face share a time level; no
- * refinement jump lies across the polar axis. */
+ * coarser neighbour; no refinement jump lies across the polar axis.  Time levels are
+ * independent of refinement levels and of the direction of a face; blocks that touch
+ * differ by at most one time level. */
 typedef struct {
   int32_t lev[3];   /* refinement level per dimension (0 = coarsest)            */
   int32_t lat;      /* local-time-stepping level (0 = fastest)                  */
@@ -102,6 +109,7 @@ typedef struct {
                                  level's blocks, LAT cycles captured as a hipGraph; 2 = the
                                  batched launches without the graph */
   int32_t profile;            /* 1 = time each kernel class with HIP events on the stream */
+  int32_t emf;                /* GRMHD_EMF_AVERAGE or GRMHD_EMF_UPWIND */
 } grmhd_grid_desc;
 
 typedef struct {

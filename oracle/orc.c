@@ -29,7 +29,8 @@ struct orc_ctx {
   double* u_fl;
   double* flux;           /* [3][9][ncell] */
   double* emf;            /* [3][ncell] */
-  double* eref;           /* [3][ncell] cell-centred EMFs of the stage state (upwinding) */
+  double* eref;           /* [4][ncell] cell-centred EMFs of the stage state and its
+                             conserved density sqrt(-g) rho u^t (upwinding) */
   double* bcell;          /* [3][ncell] cell-centred B^i of the stage state */
   double *P1, *B1, *P2, *B2;
 };
@@ -633,7 +634,7 @@ orc_ctx* orc_create(const orc_desc* d) {
     }
   c->flux = (double*)calloc(c->ncell * 27, sizeof(double));
   c->emf = (double*)calloc(c->ncell * 3, sizeof(double));
-  c->eref = (double*)calloc(c->ncell * 3, sizeof(double));
+  c->eref = (double*)calloc(c->ncell * 4, sizeof(double));
   c->bcell = (double*)calloc(c->ncell * 3, sizeof(double));
   c->P1 = (double*)calloc(c->ncell * 5, sizeof(double));
   c->B1 = (double*)calloc(c->ncell * 3, sizeof(double));
@@ -867,11 +868,19 @@ static int apply_floors(const orc_ctx* c, double* P, const double* Bcon, const d
 
 #define FL(d, q, K, J, I) c->flux[((size_t)(d) * 9 + (q)) * nc + IDX(c, K, J, I)]
 
+/* A mass flux counts as zero when it is at most this fraction of the largest conserved
+ * density sqrt(-g) rho u^t of the cells around the edge, i.e. where the coordinate
+ * velocity through the face is below it: such fluxes are rounding residuals of flows at
+ * rest through the face (symmetry planes, static atmospheres), whose sign no computation
+ * fixes. */
+#define UPWIND_REST 1e-12
+
 /* the value on the side the flow comes from: lo where the mass flux m is positive (flow
- * toward the upper side), hi where it is negative, their mean where it vanishes */
-static double upwind(double lo, double hi, double m) {
-  if (m > 0.0) return lo;
-  if (m < 0.0) return hi;
+ * toward the upper side), hi where it is negative, their mean where it is zero within
+ * rest (UPWIND_REST times the density scale) */
+static double upwind(double lo, double hi, double m, double rest) {
+  if (m > rest) return lo;
+  if (m < -rest) return hi;
   return 0.5 * (lo + hi);
 }
 
@@ -888,7 +897,7 @@ static double upwind(double lo, double hi, double m) {
 static double emf_upwind_correction(const orc_ctx* c, int a, const int x[3]) {
   const size_t nc = c->ncell;
   const int p = (a + 1) % 3, q = (a + 2) % 3;
-  double Ep[2], Eq[2], Mp[2], Mq[2], Er[2][2];
+  double Ep[2], Eq[2], Mp[2], Mq[2], Er[2][2], dmax = 0.0;
   for (int s = 0; s < 2; s++) {
     int y[3] = {x[0], x[1], x[2]};
     y[q] -= 1 - s;   /* p-face at row s */
@@ -905,13 +914,15 @@ static double emf_upwind_correction(const orc_ctx* c, int a, const int x[3]) {
       y[p] -= 1 - sp;
       y[q] -= 1 - sq;
       Er[sp][sq] = c->eref[(size_t)a * nc + IDX(c, y[2], y[1], y[0])];
+      dmax = fmax(dmax, fabs(c->eref[3 * nc + IDX(c, y[2], y[1], y[0])]));
     }
+  const double rest = UPWIND_REST * dmax;
   /* along p: upstream in q through the q-face of each column */
-  double dp_lo = upwind(Ep[0] - Er[0][0], Ep[1] - Er[0][1], Mq[0]);
-  double dp_hi = upwind(Er[1][0] - Ep[0], Er[1][1] - Ep[1], Mq[1]);
+  double dp_lo = upwind(Ep[0] - Er[0][0], Ep[1] - Er[0][1], Mq[0], rest);
+  double dp_hi = upwind(Er[1][0] - Ep[0], Er[1][1] - Ep[1], Mq[1], rest);
   /* along q: upstream in p through the p-face of each row */
-  double dq_lo = upwind(Eq[0] - Er[0][0], Eq[1] - Er[1][0], Mp[0]);
-  double dq_hi = upwind(Er[0][1] - Eq[0], Er[1][1] - Eq[1], Mp[1]);
+  double dq_lo = upwind(Eq[0] - Er[0][0], Eq[1] - Er[1][0], Mp[0], rest);
+  double dq_hi = upwind(Er[0][1] - Eq[0], Er[1][1] - Eq[1], Mp[1], rest);
   return 0.25 * ((dp_lo - dp_hi) + (dq_lo - dq_hi));
 }
 #define EM(d, K, J, I) c->emf[(size_t)(d) * nc + IDX(c, K, J, I)]
@@ -959,6 +970,9 @@ void orc_stage_flux(orc_ctx* c, const double* Ps, const double* Bs) {
             orc_prim_to_flux(Pc, Bc, gcov, gcon, gdet, alpha, c->d.gam, q + 1, F);
             c->eref[(size_t)a * nc + id] = F[5 + p];
           }
+          double U[9];
+          orc_prim_to_flux(Pc, Bc, gcov, gcon, gdet, alpha, c->d.gam, 0, U);
+          c->eref[3 * nc + id] = U[0];
         }
   }
   /* 2. edge EMFs as the average of the four neighbouring face fluxes of B */

@@ -248,6 +248,7 @@ int validate(const grmhd_grid_desc* d) {
   if (!(d->courant > 0.0)) return fail(GRMHD_EINVAL, "courant must be positive");
   if (d->c2p_guess != GRMHD_GUESS_PLAIN && d->c2p_guess != GRMHD_GUESS_MLP)
     return fail(GRMHD_EINVAL, "unknown c2p_guess");
+  if (d->emf != GRMHD_EMF_AVERAGE && d->emf != GRMHD_EMF_UPWIND) return fail(GRMHD_EINVAL, "unknown emf");
   if (d->c2p_guess == GRMHD_GUESS_MLP && !d->mlp_weights)
     return fail(GRMHD_EINVAL, "learned guess needs mlp_weights");
   int lmax[3] = {0, 0, 0};
@@ -1444,6 +1445,7 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
           case WL_BCELL: return (int64_t)bi.np[0] * bi.np[1] * bi.np[2];
           case WL_EMF: return (int64_t)(bi.n[0] + 1) * (bi.n[1] + 1) * (bi.n[2] + 1);
           case WL_CELLS: return (int64_t)bi.n[0] * bi.n[1] * bi.n[2];
+          case WL_EREF: return (int64_t)(bi.n[0] + 2) * (bi.n[1] + 2) * (bi.n[2] + 2);
           default: {   // faces along x^(d+1), or pairs of them
             const bool pair = cls >= WL_PAIR1;
             const int d = pair ? cls - WL_PAIR1 : cls - WL_FLUX1;
@@ -2011,7 +2013,14 @@ static void stage_kernels(grmhd_ctx* c, const Launch& L, int lev, const double* 
     launch_fluxes(c, L, Ps, Bs);
   }
   prof_begin(c, KC_EMF);
-  for_launches(c, L, hb, dev, nb, [&](const Launch& Lb, int64_t) { launch_emf(Lb, c->f, c->e); });
+  // upwinded EMFs read the cells' own-state EMFs and densities, kept in the split
+  // update's buffer (9 V per block, not in use until the update) as 4 V per block
+  const double* eref = p.d.emf == GRMHD_EMF_UPWIND ? c->u9 : nullptr;
+  if (eref)
+    for_launches(c, L, hb, dev, nb,
+                 [&](const Launch& Lb, int64_t) { launch_emf_ref(Lb, Ps, c->bc, c->u9); });
+  for_launches(c, L, hb, dev, nb,
+               [&](const Launch& Lb, int64_t) { launch_emf(Lb, c->f, c->e, eref); });
   launch_means(L, c->fix + fo, nfix, c->f, c->e);
   prof_end(c);
   prof_begin(c, KC_UPDATE);

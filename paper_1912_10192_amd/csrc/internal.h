@@ -158,8 +158,10 @@ __host__ __device__ inline int64_t geo_col(const GeoTab&, const BlockInfo& bi, i
 
 // region classes of the stage kernels' work lists: padded block, faces per direction,
 // edges, interior cells
+// (WL_EREF: the interior cells and one layer around them, whose own-state EMFs the
+// upwinded edge EMFs read)
 enum { WL_BCELL = 0, WL_FLUX1, WL_FLUX2, WL_FLUX3, WL_EMF, WL_CELLS, WL_PAIR1, WL_PAIR2, WL_PAIR3,
-       WL_N };
+       WL_EREF, WL_N };
 constexpr int STAGE_NT = 256;   // threads per workgroup of the stage kernels
 
 // statistics of the update kernels: inversion tier counts, Newton iteration histogram,
@@ -218,7 +220,11 @@ void launch_ghosts(const Launch& L, const GhostLists& G, double* P, double* B);
 void launch_bcell(const Launch& L, const double* B, double* Bc);
 void launch_flux(const Launch& L, int dir, int recon, int riemann, const double* P,
                  const double* Bc, const double* B, double* F);
-void launch_emf(const Launch& L, const double* F, double* E);
+// edge EMFs from the face fluxes; with eref (the cells' own-state EMFs and conserved
+// densities, [4][V] per block at 4 * off, from launch_emf_ref) the upwinded corrections
+// are added
+void launch_emf(const Launch& L, const double* F, double* E, const double* eref = nullptr);
+void launch_emf_ref(const Launch& L, const double* P, const double* Bc, double* eref);
 // update of one stage; with dt_part non-null the kernel also writes per-workgroup minima
 // of the next Courant step (reduced by launch_dt_final)
 // (mlp non-null: learned first guess of the inversion from the packed MLP blob)

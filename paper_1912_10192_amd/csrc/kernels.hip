@@ -364,8 +364,50 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
 
 // E^1 at (i, j-1/2, k-1/2), E^2 at (i-1/2, j, k-1/2), E^3 at (i-1/2, j-1/2, k): the
 // average of the four face fluxes of B around the edge (Sec. 2.5); zero on the axis.
+// With UPWIND, Gardiner & Stone's (2005) corrections are added (edge_upwind below).
+
+// A mass flux at most this fraction of the largest conserved density sqrt(-g) rho u^t of
+// the edge's four cells (a coordinate velocity through the face below it) counts as zero:
+// such fluxes are rounding residuals of flows at rest through the face (symmetry planes,
+// static atmospheres), whose sign no computation fixes.
+constexpr double UPWIND_REST = 1e-12;
+
+__device__ __forceinline__ double upwind_pick(double lo, double hi, double m, double rest) {
+  return m > rest ? lo : (m < -rest ? hi : 0.5 * (lo + hi));
+}
+
+// The correction for the edge along x^(a+1) at local index l, (a, p, q) cyclic, with
+// strides sp, sq of the cells along p and q.  Around the edge: two p-faces (rows qq = 0, 1
+// at l - (1 - qq) sq) with face EMF -F_p(B^q) and mass flux F_p(rho), two q-faces
+// (columns pp at l - (1 - pp) sp) with +F_q(B^p) and F_q(rho), and four cells with their
+// own-state EMFs (er) and conserved densities (dd).  Each gradient toward a cell centre
+// comes from the row (column) upstream of the mass flux through the face between the two
+// candidates.
+__device__ __forceinline__ double edge_upwind(const double* __restrict__ Fpb,
+                                              const double* __restrict__ Fpr,
+                                              const double* __restrict__ Fqb,
+                                              const double* __restrict__ Fqr,
+                                              const double* __restrict__ er,
+                                              const double* __restrict__ dd, int64_t sp,
+                                              int64_t sq) {
+  const double Ep0 = -Fpb[-sq], Ep1 = -Fpb[0];
+  const double Mp0 = Fpr[-sq], Mp1 = Fpr[0];
+  const double Eq0 = Fqb[-sp], Eq1 = Fqb[0];
+  const double Mq0 = Fqr[-sp], Mq1 = Fqr[0];
+  const double r00 = er[-sp - sq], r01 = er[-sp], r10 = er[-sq], r11 = er[0];
+  const double rest = UPWIND_REST * fmax(fmax(fabs(dd[-sp - sq]), fabs(dd[-sp])),
+                                         fmax(fabs(dd[-sq]), fabs(dd[0])));
+  const double dp_lo = upwind_pick(Ep0 - r00, Ep1 - r01, Mq0, rest);
+  const double dp_hi = upwind_pick(r10 - Ep0, r11 - Ep1, Mq1, rest);
+  const double dq_lo = upwind_pick(Eq0 - r00, Eq1 - r10, Mp0, rest);
+  const double dq_hi = upwind_pick(r01 - Eq0, r11 - Eq1, Mp1, rest);
+  return 0.25 * ((dp_lo - dp_hi) + (dq_lo - dq_hi));
+}
+
+template <bool UPWIND>
 __global__ __launch_bounds__(NT) void k_emf(Launch L, const double* __restrict__ F,
-                                            double* __restrict__ E) {
+                                            double* __restrict__ E,
+                                            const double* __restrict__ eref) {
   const BlockTile bt = block_tile(L);
   const BlockInfo bi = L.blk[bt.blk];
   const int g = L.ph.ng;
@@ -384,11 +426,56 @@ __global__ __launch_bounds__(NT) void k_emf(Launch L, const double* __restrict__
   const double* F3B2 = f + 22 * V;   // x3 flux of B^2
   const bool pole = L.geo.f2[GDET * L.geo.ncol + geo_col(L.geo, bi, c.J, c.I)] == 0.0;
   double* e = E + 3 * bi.off + c.loc;
-  if (c.I < g + bi.n[0])
-    e[0] = pole ? 0.0 : 0.25 * (F3B2[0] + F3B2[-s2] - F2B3[-s3] - F2B3[0]);
-  if (c.J < g + bi.n[1]) e[V] = 0.25 * (F1B3[-s3] + F1B3[0] - F3B1[0] - F3B1[-1]);
-  if (c.K < g + bi.n[2])
-    e[2 * V] = pole ? 0.0 : 0.25 * (F2B1[-1] + F2B1[0] - F1B2[0] - F1B2[-s2]);
+  const double* er = UPWIND ? eref + 4 * bi.off + c.loc : nullptr;   // [4][V] per block
+  const double* dd = UPWIND ? er + 3 * V : nullptr;
+  if (c.I < g + bi.n[0]) {
+    double x = pole ? 0.0 : 0.25 * (F3B2[0] + F3B2[-s2] - F2B3[-s3] - F2B3[0]);
+    // E^1: p = x2, q = x3
+    if (UPWIND && !pole) x += edge_upwind(F2B3, f + 8 * V, F3B2, f + 16 * V, er, dd, s2, s3);
+    e[0] = x;
+  }
+  if (c.J < g + bi.n[1]) {
+    double x = 0.25 * (F1B3[-s3] + F1B3[0] - F3B1[0] - F3B1[-1]);
+    // E^2: p = x3, q = x1
+    if (UPWIND) x += edge_upwind(F3B1, f + 16 * V, F1B3, f, er + V, dd, s3, 1);
+    e[V] = x;
+  }
+  if (c.K < g + bi.n[2]) {
+    double x = pole ? 0.0 : 0.25 * (F2B1[-1] + F2B1[0] - F1B2[0] - F1B2[-s2]);
+    // E^3: p = x1, q = x2
+    if (UPWIND && !pole) x += edge_upwind(F1B2, f, F2B1, f + 8 * V, er + 2 * V, dd, 1, s2);
+    e[2 * V] = x;
+  }
+}
+
+// The EMF of each cell's own state, component a = the flux of B^(p+1) along x^(q+1),
+// sqrt(-g) (b^p u^q - b^q u^p) with (a, p, q) cyclic, and as a fourth component the
+// conserved density sqrt(-g) rho u^t, on the interior cells and one layer around them
+// (the cells next to the block's edges); [4][V] per block
+__global__ __launch_bounds__(NT) void k_emf_ref(Launch L, const double* __restrict__ P,
+                                                const double* __restrict__ Bc,
+                                                double* __restrict__ eref) {
+  const BlockTile bt = block_tile(L);
+  const BlockInfo bi = L.blk[bt.blk];
+  const int g = L.ph.ng;
+  Cell c;
+  if (!region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0] + 2, bi.n[1] + 2, bi.n[2] + 2,
+                   g - 1, g - 1, g - 1, c))
+    return;
+  const int64_t V = bi.vol;
+  const Metric m = load_metric(L.geo.c, L.geo.ncol, geo_col(L.geo, bi, c.J, c.I));
+  double p[5], b[3];
+#pragma unroll
+  for (int v = 0; v < 5; v++) p[v] = P[5 * bi.off + v * V + c.loc];
+#pragma unroll
+  for (int v = 0; v < 3; v++) b[v] = Bc[3 * bi.off + v * V + c.loc];
+  Fluid fl;
+  fluid_state(p, b, m, fl);
+  double* o = eref + 4 * bi.off + c.loc;
+  o[0] = m.gdet * (fl.bcon[2] * fl.ucon[3] - fl.bcon[3] * fl.ucon[2]);
+  o[V] = m.gdet * (fl.bcon[3] * fl.ucon[1] - fl.bcon[1] * fl.ucon[3]);
+  o[2 * V] = m.gdet * (fl.bcon[1] * fl.ucon[2] - fl.bcon[2] * fl.ucon[1]);
+  o[3 * V] = m.gdet * p[0] * fl.ucon[0];
 }
 
 // ------------------------------------------------------------------ cell update
@@ -1130,11 +1217,21 @@ void launch_flux(const Launch& L, int dir, int recon, int riemann, const double*
   else flux_dir<3>(L, recon, riemann, P, Bc, B, F);
 }
 
-void launch_emf(const Launch& L, const double* F, double* E) {
+void launch_emf(const Launch& L, const double* F, double* E, const double* eref) {
   const int64_t r = (int64_t)(L.max_n[0] + 1) * (L.max_n[1] + 1) * (L.max_n[2] + 1);
   Launch Lc;
   const dim3 grid = stage_grid(L, WL_EMF, r, Lc);
-  hipLaunchKernelGGL(k_emf, grid, dim3(NT), 0, L.stream, Lc, F, E);
+  if (eref)
+    hipLaunchKernelGGL(k_emf<true>, grid, dim3(NT), 0, L.stream, Lc, F, E, eref);
+  else
+    hipLaunchKernelGGL(k_emf<false>, grid, dim3(NT), 0, L.stream, Lc, F, E, eref);
+}
+
+void launch_emf_ref(const Launch& L, const double* P, const double* Bc, double* eref) {
+  const int64_t r = (int64_t)(L.max_n[0] + 2) * (L.max_n[1] + 2) * (L.max_n[2] + 2);
+  Launch Lc;
+  const dim3 grid = stage_grid(L, WL_EREF, r, Lc);
+  hipLaunchKernelGGL(k_emf_ref, grid, dim3(NT), 0, L.stream, Lc, P, Bc, eref);
 }
 
 __global__ __launch_bounds__(NT) void k_fill(double* __restrict__ x, int64_t n, double v) {
