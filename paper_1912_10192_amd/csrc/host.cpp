@@ -29,6 +29,44 @@ using namespace grmhd;
 
 static thread_local std::string g_err;
 
+// An allocator whose resize leaves plain-data elements uninitialised, for the planner's
+// large lists: they are filled right after (in parallel), and zeroing them first would
+// touch every page once more on one thread.
+template <class T>
+struct NoInit : std::allocator<T> {
+  template <class U>
+  struct rebind {
+    using other = NoInit<U>;
+  };
+  NoInit() = default;
+  template <class U>
+  NoInit(const NoInit<U>&) {}
+  template <class U>
+  void construct(U* ptr) noexcept {
+    ::new ((void*)ptr) U;
+  }
+  template <class U, class... A>
+  void construct(U* ptr, A&&... a) {
+    ::new ((void*)ptr) U(std::forward<A>(a)...);
+  }
+};
+template <class T>
+using BigVec = std::vector<T, NoInit<T>>;
+
+// Runs f(i) for i in [0, n) on up to 16 worker threads (the calling thread included).
+template <class F>
+static void parallel_for(int64_t n, F&& f) {
+  std::atomic<int64_t> next{0};
+  auto work = [&]() {
+    for (int64_t i = next++; i < n; i = next++) f(i);
+  };
+  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nt && (int64_t)t < n; t++) th.emplace_back(work);
+  work();
+  for (std::thread& t : th) t.join();
+}
+
 static int fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
@@ -155,10 +193,10 @@ struct Plan {
   std::vector<GeoTable> tables;
   int64_t ncol = 0;
   std::vector<int32_t> owner;   // block id per effective (finest-level) cell
-  std::vector<GhostOp> ops[4];  // cells, x1 faces, x2 faces, x3 faces (sorted by dst level)
-  std::vector<AmrOp> aops[4];   // ghost values across refinement levels (sorted likewise)
-  std::vector<AmrSample> samples;
-  std::vector<uint8_t> samp_kind;   // the list (cells, x1/x2/x3 faces) of each sample
+  BigVec<GhostOp> ops[4];  // cells, x1 faces, x2 faces, x3 faces (by dst level, then block)
+  BigVec<AmrOp> aops[4];   // ghost values across refinement levels (ordered likewise)
+  BigVec<AmrSample> samples;   // in block order
+  BigVec<uint8_t> samp_kind;   // the list (cells, x1/x2/x3 faces) of each sample
   // refinement faces between blocks of one time level (the coarse side takes the fine
   // side's fluxes in each stage), in the order the blocks are listed
   struct Link {
@@ -669,53 +707,57 @@ static int block_ops(const Plan& p, int b, BlockOps& out) {
 
 int build_ops(Plan& p) {
   const int nb = p.d.n_blocks;
-  for (int kind = 0; kind < 4; kind++) {
-    p.ops[kind].clear();
-    p.aops[kind].clear();
-  }
-  p.samples.clear();
-  p.samp_kind.clear();
-  // blocks on worker threads, concatenated in block order (the lists do not depend on
-  // the threads)
+  // blocks on worker threads; their lists are then laid out by the destination block's
+  // time level and block order within a level (what the level launches take), with
+  // the samples in block order (the lists do not depend on the threads)
   std::vector<BlockOps> per(nb);
-  std::atomic<int> next{0};
-  auto work = [&]() {
-    for (int b = next++; b < nb; b = next++) block_ops(p, b, per[b]);
-  };
-  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  std::vector<std::thread> th;
-  for (unsigned t = 1; t < nt && (int)t < nb; t++) th.emplace_back(work);
-  work();
-  for (std::thread& t : th) t.join();
-  size_t tot[4] = {}, atot[4] = {}, stot = 0;
-  for (const BlockOps& o : per) {
+  parallel_for(nb, [&](int64_t b) { block_ops(p, (int)b, per[b]); });
+  for (const BlockOps& o : per)
     if (o.rc) return fail(o.rc, o.err);
-    for (int k = 0; k < 4; k++) {
-      tot[k] += o.ops[k].size();
-      atot[k] += o.aops[k].size();
-    }
-    stot += o.samples.size();
+  std::vector<int> order(nb);
+  for (int b = 0; b < nb; b++) order[b] = b;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return p.blocks[x].lat < p.blocks[y].lat; });
+  std::vector<size_t> at[4], aat[4], sat(nb);
+  size_t stot = 0;
+  for (int b = 0; b < nb; b++) {
+    sat[b] = stot;
+    stot += per[b].samples.size();
   }
   if (stot >= (size_t(1) << 31)) return fail(GRMHD_EINVAL, "too many refinement samples");
   for (int k = 0; k < 4; k++) {
-    p.ops[k].reserve(tot[k]);
-    p.aops[k].reserve(atot[k]);
+    at[k].assign(nb, 0);
+    aat[k].assign(nb, 0);
+    size_t t = 0, u = 0;
+    for (int b : order) {
+      at[k][b] = t;
+      aat[k][b] = u;
+      t += per[b].ops[k].size();
+      u += per[b].aops[k].size();
+    }
+    p.ops[k].clear();
+    p.aops[k].clear();
+    p.ops[k].resize(t);
+    p.aops[k].resize(u);
   }
-  p.samples.reserve(stot);
-  p.samp_kind.reserve(stot);
-  for (BlockOps& o : per) {
-    const int32_t base = (int32_t)p.samples.size();
+  p.samples.clear();
+  p.samp_kind.clear();
+  p.samples.resize(stot);
+  p.samp_kind.resize(stot);
+  parallel_for(nb, [&](int64_t b) {
+    BlockOps& o = per[b];
     for (int k = 0; k < 4; k++) {
-      p.ops[k].insert(p.ops[k].end(), o.ops[k].begin(), o.ops[k].end());
+      std::copy(o.ops[k].begin(), o.ops[k].end(), p.ops[k].begin() + at[k][b]);
+      AmrOp* dst = p.aops[k].data() + aat[k][b];
       for (AmrOp op : o.aops[k]) {
-        op.samp += base;
-        p.aops[k].push_back(op);
+        op.samp += (int32_t)sat[b];
+        *dst++ = op;
       }
     }
-    p.samples.insert(p.samples.end(), o.samples.begin(), o.samples.end());
-    p.samp_kind.insert(p.samp_kind.end(), o.samp_kind.begin(), o.samp_kind.end());
+    std::copy(o.samples.begin(), o.samples.end(), p.samples.begin() + sat[b]);
+    std::copy(o.samp_kind.begin(), o.samp_kind.end(), p.samp_kind.begin() + sat[b]);
     o = BlockOps();
-  }
+  });
   return GRMHD_OK;
 }
 
@@ -1389,16 +1431,11 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
     }
     p.lev_boff[L] = (int64_t)p.lev_blocks.size();
     if (with_maps) {
-      // a stable counting sort of each list by the destination block's time level
-      auto by_level = [&](auto& v, std::vector<int64_t>& off) {
+      // the lists are ordered by the destination block's time level: offsets per level
+      auto by_level = [&](const auto& v, std::vector<int64_t>& off) {
         off.assign(L + 1, 0);
         for (const auto& op : v) off[p.blocks[op.dst_blk].lat + 1]++;
         for (int l = 0; l < L; l++) off[l + 1] += off[l];
-        if (L == 1) return;
-        std::vector<int64_t> at(off.begin(), off.end() - 1);
-        std::remove_reference_t<decltype(v)> out(v.size());
-        for (const auto& op : v) out[at[p.blocks[op.dst_blk].lat]++] = op;
-        v.swap(out);
       };
       for (int kind = 0; kind < 4; kind++) {
         by_level(p.ops[kind], p.ops_off[kind]);
