@@ -331,8 +331,12 @@ def main():
     ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes (0: the cores available, at most 16)")
     ap.add_argument("--cpu-sample", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--only-headline", action="store_true",
-                    help="only the headline path (with its training), for profiling it alone")
+                    help="only the headline path (with its training) and the per-class profiled "
+                         "run that gives the roofline, for profiling them alone")
     ap.add_argument("--train-steps", type=int, default=1000)
+    ap.add_argument("--plain-guess", action="store_true",
+                    help="no learned guess: the headline path with the previous-state guess "
+                         "(for hardware-counter runs)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates the "
                          "FETCH_SIZE/WRITE_SIZE counters) and exit")
@@ -368,7 +372,7 @@ def main():
     bs = initdata.block_states(state, blocks, lmax)
     del state
     cells = sum(b["n"][0] * b["n"][1] * b["n"][2] for b in blocks)
-    blob, train = train_guess(args.train_steps, log)
+    blob, train = (None, None) if args.plain_guess else train_guess(args.train_steps, log)
     head, tune = run_leg("batched_learned", cfg, blocks, bs, 1, blob, args.steps, args.warmup,
                          args.runs, sync, log)
     out = {"metric": METRIC, "unit": "zone-cycles/s", "n_gpus": 1, "steps": args.steps,
@@ -412,7 +416,10 @@ def main():
             "speedup_vs_global_dt_real": head["value_real"] / glob["value_real"],
             "learned_training": train})
     else:
-        out["learned_training"] = train
+        cls_ms, cls_n, spl = profiled_classes(cfg, blocks, bs, blob, tune, args.steps, sync, log)
+        out.update({"roofline": roofline(cls_ms, cls_n, blocks, spl),
+                    "kernel_ms_per_cycle": {k: v / args.steps for k, v in cls_ms.items()},
+                    "learned_training": train})
     if not args.no_cpu_baseline:
         avail = host_info()["cpus_available"] or 1
         procs = args.cpu_procs or min(avail, 16)

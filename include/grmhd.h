@@ -249,7 +249,14 @@ int grmhd_divb(grmhd_ctx* ctx, double* max_abs, double* max_rel, double* field);
  * holder's n covering edges, -1 padded to 2); what = 14: likewise the edges whose
  * finest holder at the block's own time level is finer (EMF replaced in each stage);
  * what = 15..19: the device lists built from them as raw structures (internal layout,
- * for bounds checks).  Every table lists blocks in block order.  host_buf NULL queries
+ * for bounds checks); what = 20: the device ghost copy lists as uploaded, each ghost
+ * cell with the ghost faces at its local index that copy the faces at its source's
+ * local index unchanged, as 6 uint32 (destination and source element of primitive 0,
+ * destination and source element of face component 0, destination padded volume |
+ * carried face components (bits 0-2) << 24, source padded volume | cell flags << 24);
+ * what = 21..23: the faces of components 1..3 not carried that way, as 4 uint32
+ * (destination element, source element, destination padded volume, source padded
+ * volume | flags << 24); both in time-level order.  Every table lists blocks in block order.  host_buf NULL queries
  * the size in bytes. */
 int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes);
 

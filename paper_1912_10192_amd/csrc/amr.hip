@@ -45,34 +45,55 @@ __device__ __forceinline__ double timed(int fl, int64_t q, const double* __restr
   return cur[q];
 }
 
-__device__ double cell_value(const BlockInfo* __restrict__ blk, const GeoTab& G,
-                             const AmrSample& s, int v, const double* __restrict__ main,
-                             const double* __restrict__ old, const double* __restrict__ cur,
-                             double w) {
+// The five primitives of one cell sample (a cell of the source block, or for a
+// restriction the sqrt(-g)-weighted mean of the finer cells it covers), then the
+// physical-boundary flip and clamps.  The sample's block record, indices and weights are
+// decoded once for all five variables.
+__device__ __forceinline__ void cell_values(const BlockInfo* __restrict__ blk, const GeoTab& G,
+                            const AmrSample& s, const double* __restrict__ main,
+                            const double* __restrict__ old, const double* __restrict__ cur,
+                            double w, double x[5]) {
   const int sb = s.blkf & 0xFFFFFF, fl = (s.blkf >> 24) & 0xFF;
   const BlockInfo bi = blk[sb];
-  const int64_t base = 5 * bi.off + (int64_t)v * bi.vol;
-  double x;
+  const int64_t base = 5 * bi.off + s.loc;
   if (s.mask == 0) {
-    x = timed(fl, base + s.loc, main, old, cur, w);
+#pragma unroll
+    for (int v = 0; v < 5; v++) x[v] = timed(fl, base + (int64_t)v * bi.vol, main, old, cur, w);
   } else {
-    const int n0 = (s.mask & 1) ? 2 : 1, n1 = (s.mask & 2) ? 2 : 1, n2 = (s.mask & 4) ? 2 : 1;
-    double num = 0.0, den = 0.0;
-    for (int ok = 0; ok < n2; ok++)
-      for (int oj = 0; oj < n1; oj++)
-        for (int oi = 0; oi < n0; oi++) {
-          const int64_t l = s.loc + ((int64_t)ok * bi.np[1] + oj) * bi.np[0] + oi;
-          const int I = (int)(l % bi.np[0]), J = (int)((l / bi.np[0]) % bi.np[1]);
-          const double wg = G.c[GDET * G.ncol + geo_col(G, bi, J, I)];
-          num = __dadd_rn(num, __dmul_rn(wg, timed(fl, base + l, main, old, cur, w)));
-          den = __dadd_rn(den, wg);
-        }
-    x = num / den;
+    // the covered fine cells in (k, j, i) order (i fastest), their offsets and weights;
+    // entry m = 4 ok + 2 oj + oi, present where the mask refines its dimensions
+    int64_t off[8];
+    double wg[8];
+    double den = 0.0;
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+      const int oi = m & 1, oj = (m >> 1) & 1, ok = m >> 2;
+      const bool in = (!oi || (s.mask & 1)) && (!oj || (s.mask & 2)) && (!ok || (s.mask & 4));
+      off[m] = ((int64_t)ok * bi.np[1] + oj) * bi.np[0] + oi;
+      wg[m] = 0.0;
+      if (in) {
+        const int64_t l = s.loc + off[m];
+        const int I = (int)(l % bi.np[0]), J = (int)((l / bi.np[0]) % bi.np[1]);
+        wg[m] = G.c[GDET * G.ncol + geo_col(G, bi, J, I)];
+        den = __dadd_rn(den, wg[m]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      const int64_t bv = base + (int64_t)v * bi.vol;
+      double num = 0.0;
+#pragma unroll
+      for (int m = 0; m < 8; m++) {
+        const int oi = m & 1, oj = (m >> 1) & 1, ok = m >> 2;
+        const bool in = (!oi || (s.mask & 1)) && (!oj || (s.mask & 2)) && (!ok || (s.mask & 4));
+        if (in) num = __dadd_rn(num, __dmul_rn(wg[m], timed(fl, bv + off[m], main, old, cur, w)));
+      }
+      x[v] = num / den;
+    }
   }
-  if (v == 3 && (fl & GF_FLIP)) x = -x;
-  if (v == 2 && (fl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
-  if (v == 2 && (fl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
-  return x;
+  if (fl & GF_FLIP) x[3] = -x[3];
+  if ((fl & GF_CLAMP_NEG) && x[2] > 0.0) x[2] = 0.0;
+  if ((fl & GF_CLAMP_POS) && x[2] < 0.0) x[2] = 0.0;
 }
 
 __device__ double face_value(const BlockInfo* __restrict__ blk, const AmrSample& s, int comp,
@@ -100,32 +121,37 @@ __device__ double face_value(const BlockInfo* __restrict__ blk, const AmrSample&
 }
 
 // a ghost cell from its refinement stencil (prolongation with minmod slopes, or a
-// restriction sample), then the physical-boundary flip and clamps
+// restriction sample), then the physical-boundary flip and clamps; per variable the
+// same operations in the same order as one variable at a time
 __device__ void amr_cell_op(const BlockInfo* __restrict__ blk, const GeoTab& G, const AmrOp op,
                             const AmrSample* __restrict__ samp, const double* __restrict__ main,
                             const double* __restrict__ old, const double* __restrict__ cur,
                             double w, double* __restrict__ dst) {
-  const BlockInfo d = blk[op.dst_blk];
   const AmrSample* S = samp + op.samp;
   const int pd = op.mode & AM_PDIMS;
   const int ofl = (op.mode >> AM_FLAGS_SHIFT) & 0xFF;
-  for (int v = 0; v < 5; v++) {
-    const double c = cell_value(blk, G, S[0], v, main, old, cur, w);
-    double x = c;
-    int k = 1;
-    for (int dd = 0; dd < 3; dd++) {
-      if (!((pd >> dd) & 1)) continue;
-      const double sm = cell_value(blk, G, S[k], v, main, old, cur, w);
-      const double sp = cell_value(blk, G, S[k + 1], v, main, old, cur, w);
-      k += 2;
-      const double sg = ((op.mode >> (AM_UPPER_SHIFT + dd)) & 1) ? 0.25 : -0.25;
-      x = x + sg * minmod(c - sm, sp - c);
-    }
-    if (v == 3 && (ofl & GF_FLIP)) x = -x;
-    if (v == 2 && (ofl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
-    if (v == 2 && (ofl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
-    dst[5 * d.off + (int64_t)v * d.vol + op.dst_loc] = x;
+  double c[5], x[5];
+  cell_values(blk, G, S[0], main, old, cur, w, c);
+#pragma unroll
+  for (int v = 0; v < 5; v++) x[v] = c[v];
+  int k = 1;
+  for (int dd = 0; dd < 3; dd++) {
+    if (!((pd >> dd) & 1)) continue;
+    double sm[5], sp[5];
+    cell_values(blk, G, S[k], main, old, cur, w, sm);
+    cell_values(blk, G, S[k + 1], main, old, cur, w, sp);
+    k += 2;
+    const double sg = ((op.mode >> (AM_UPPER_SHIFT + dd)) & 1) ? 0.25 : -0.25;
+#pragma unroll
+    for (int v = 0; v < 5; v++) x[v] = x[v] + sg * minmod(c[v] - sm[v], sp[v] - c[v]);
   }
+  if (ofl & GF_FLIP) x[3] = -x[3];
+  if ((ofl & GF_CLAMP_NEG) && x[2] > 0.0) x[2] = 0.0;
+  if ((ofl & GF_CLAMP_POS) && x[2] < 0.0) x[2] = 0.0;
+  const BlockInfo d = blk[op.dst_blk];
+  double* o = dst + 5 * d.off + op.dst_loc;
+#pragma unroll
+  for (int v = 0; v < 5; v++) o[(int64_t)v * d.vol] = x[v];
 }
 
 // a ghost face of component comp from its refinement stencil (the mean of two stencils

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -53,14 +54,20 @@ struct NoInit : std::allocator<T> {
 template <class T>
 using BigVec = std::vector<T, NoInit<T>>;
 
-// Runs f(i) for i in [0, n) on up to 16 worker threads (the calling thread included).
+// Runs f(i) for i in [0, n) on up to 16 worker threads (the calling thread included);
+// GRMHD_PLANNER_THREADS in the environment sets a lower count (1: the calling thread
+// only).
 template <class F>
 static void parallel_for(int64_t n, F&& f) {
   std::atomic<int64_t> next{0};
   auto work = [&]() {
     for (int64_t i = next++; i < n; i = next++) f(i);
   };
-  const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (const char* env = std::getenv("GRMHD_PLANNER_THREADS")) {
+    const long v = std::strtol(env, nullptr, 10);
+    if (v >= 1) nt = std::min<unsigned>(nt, (unsigned)v);
+  }
   std::vector<std::thread> th;
   for (unsigned t = 1; t < nt && (int64_t)t < n; t++) th.emplace_back(work);
   work();
@@ -759,6 +766,81 @@ int build_ops(Plan& p) {
     o = BlockOps();
   });
   return GRMHD_OK;
+}
+
+// The device form of the ghost copy lists: per time level, every ghost cell with the
+// ghost faces at its local index that are plain copies from the same source element
+// (same source block and local index, no flip, no zero, the same time relation), and
+// the faces not carried that way.  Element indices are resolved against the block table.
+struct DevGhosts {
+  std::vector<GhostCF> cf;
+  std::vector<GhostIdx> lf[4];      // lf[1..3]
+  std::vector<int64_t> off[4];      // per level (+1): cf, lf[1..3]
+};
+
+static GhostIdx ghost_idx(const Plan& p, int kind, const GhostOp& op) {
+  const BlockInfo& d = p.info[op.dst_blk];
+  const BlockInfo& s = p.info[op.src_blkf & 0xFFFFFF];
+  const int64_t nv = kind == 0 ? 5 : 3, cv = kind == 0 ? 0 : kind - 1;
+  GhostIdx g;
+  g.dst = (uint32_t)(nv * d.off + cv * d.vol + op.dst_loc);
+  g.src = (uint32_t)(nv * s.off + cv * s.vol + op.src_loc);
+  g.dvol = (uint32_t)d.vol;
+  g.svol_fl = (uint32_t)s.vol | ((uint32_t)(op.src_blkf >> 24) & 0xFFu) << 24;
+  return g;
+}
+
+static void device_ghosts(const Plan& p, DevGhosts& g) {
+  const int L = std::max<int>(1, (int)p.ops_off[0].size() - 1);
+  for (int k = 0; k < 4; k++) g.off[k].assign(1, 0);
+  g.cf.reserve(p.ops[0].size());
+  for (int l = 0; l < L; l++) {
+    const int64_t c0 = p.ops_off[0].empty() ? 0 : p.ops_off[0][l];
+    const int64_t c1 = p.ops_off[0].empty() ? (int64_t)p.ops[0].size() : p.ops_off[0][l + 1];
+    int64_t j[4], je[4];
+    for (int k = 1; k < 4; k++) {
+      j[k] = p.ops_off[k].empty() ? 0 : p.ops_off[k][l];
+      je[k] = p.ops_off[k].empty() ? (int64_t)p.ops[k].size() : p.ops_off[k][l + 1];
+    }
+    // within a level the lists run in block order and, per block, in increasing local
+    // index: a merge by (block, local index)
+    auto before = [](const GhostOp& a, const GhostOp& b) {
+      return a.dst_blk != b.dst_blk ? a.dst_blk < b.dst_blk : a.dst_loc < b.dst_loc;
+    };
+    constexpr int kTime = GF_SLOW | GF_FAST;
+    for (int64_t i = c0; i < c1; i++) {
+      const GhostOp& c = p.ops[0][i];
+      const int cfl = (c.src_blkf >> 24) & 0xFF;
+      int fc = 0;
+      for (int k = 1; k < 4; k++) {
+        while (j[k] < je[k] && before(p.ops[k][j[k]], c)) g.lf[k].push_back(ghost_idx(p, k, p.ops[k][j[k]++]));
+        if (j[k] < je[k]) {
+          const GhostOp& f = p.ops[k][j[k]];
+          const int ffl = (f.src_blkf >> 24) & 0xFF;
+          if (f.dst_blk == c.dst_blk && f.dst_loc == c.dst_loc &&
+              (f.src_blkf & 0xFFFFFF) == (c.src_blkf & 0xFFFFFF) && f.src_loc == c.src_loc &&
+              (ffl & ~kTime) == 0 && (ffl & kTime) == (cfl & kTime)) {
+            fc |= 1 << (k - 1);
+            j[k]++;
+          }
+        }
+      }
+      const BlockInfo& d = p.info[c.dst_blk];
+      const BlockInfo& s = p.info[c.src_blkf & 0xFFFFFF];
+      GhostCF x;
+      x.dp = (uint32_t)(5 * d.off + c.dst_loc);
+      x.sp = (uint32_t)(5 * s.off + c.src_loc);
+      x.db = (uint32_t)(3 * d.off + c.dst_loc);
+      x.sb = (uint32_t)(3 * s.off + c.src_loc);
+      x.dvol_fc = (uint32_t)d.vol | (uint32_t)fc << 24;
+      x.svol_fl = (uint32_t)s.vol | (uint32_t)cfl << 24;
+      g.cf.push_back(x);
+    }
+    for (int k = 1; k < 4; k++)
+      while (j[k] < je[k]) g.lf[k].push_back(ghost_idx(p, k, p.ops[k][j[k]++]));
+    g.off[0].push_back((int64_t)g.cf.size());
+    for (int k = 1; k < 4; k++) g.off[k].push_back((int64_t)g.lf[k].size());
+  }
 }
 
 // The old-state elements of each time level: every source of a ghost op or refinement
@@ -1540,7 +1622,8 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
             }
       }
     }
-    p.o_ops[kind] = take(count * sizeof(GhostOp));
+    // cells with their carried faces (GhostCF), or the faces left over (at most all)
+    p.o_ops[kind] = take(count * (kind == 0 ? sizeof(GhostCF) : sizeof(GhostIdx)));
     p.o_aops[kind] = take(p.aops[kind].size() * sizeof(AmrOp));
   }
   p.o_samp = take(p.samples.size() * sizeof(AmrSample));
@@ -1630,8 +1713,9 @@ struct grmhd_ctx {
   grmhd_buffers bufs;
   hipStream_t stream;
   double *ps, *balt, *bc, *f, *e, *dtp, *u9;
-  GhostIdx* ops[4];
-  int64_t nops[4];
+  GhostCF* cf;                 // cells with carried faces, by time level
+  GhostIdx* ops[4];            // ops[1..3]: faces not carried by a cell, by time level
+  std::vector<int64_t> gh_off[4];   // per time level (+1): cf for 0, ops[k] for k = 1..3
   AmrOp* aops[4];
   int64_t naops[4];
   AmrSample* samp = nullptr;
@@ -1816,26 +1900,20 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   }
   // the ghost lists resolved against the block table (element indices of the packed
   // arrays); host staging kept until the stream synchronises below
-  std::vector<GhostIdx> gidx[4];
+  DevGhosts dg;
+  device_ghosts(p, dg);
+  c->cf = (GhostCF*)(w + p.o_ops[0]);
+  c->ops[0] = nullptr;
+  for (int k = 0; k < 4; k++) c->gh_off[k] = dg.off[k];
+  if ((rc = up(p.o_ops[0], dg.cf.data(), dg.cf.size() * sizeof(GhostCF)))) {
+    delete c;
+    return rc;
+  }
   for (int kind = 0; kind < 4; kind++) {
-    c->ops[kind] = (GhostIdx*)(w + p.o_ops[kind]);
-    c->nops[kind] = (int64_t)p.ops[kind].size();
+    if (kind) c->ops[kind] = (GhostIdx*)(w + p.o_ops[kind]);
     c->aops[kind] = (AmrOp*)(w + p.o_aops[kind]);
     c->naops[kind] = (int64_t)p.aops[kind].size();
-    std::vector<GhostIdx>& idx = gidx[kind];
-    idx.resize(p.ops[kind].size());
-    for (size_t i = 0; i < idx.size(); i++) {
-      const GhostOp& op = p.ops[kind][i];
-      const BlockInfo& d = p.info[op.dst_blk];
-      const BlockInfo& s = p.info[op.src_blkf & 0xFFFFFF];
-      const int64_t nv = kind == 0 ? 5 : 3, cv = kind == 0 ? 0 : kind - 1;
-      idx[i].dst = (uint32_t)(nv * d.off + cv * d.vol + op.dst_loc);
-      idx[i].src = (uint32_t)(nv * s.off + cv * s.vol + op.src_loc);
-      idx[i].dvol = (uint32_t)d.vol;
-      idx[i].svol_fl = (uint32_t)s.vol | ((uint32_t)(op.src_blkf >> 24) & 0xFFu) << 24;
-    }
-    static_assert(sizeof(GhostIdx) == sizeof(GhostOp), "ghost list layouts share their size");
-    if ((rc = up(p.o_ops[kind], idx.data(), idx.size() * sizeof(GhostIdx))) ||
+    if ((kind && (rc = up(p.o_ops[kind], dg.lf[kind].data(), dg.lf[kind].size() * sizeof(GhostIdx)))) ||
         (rc = up(p.o_aops[kind], p.aops[kind].data(), p.aops[kind].size() * sizeof(AmrOp)))) {
       delete c;
       return rc;
@@ -1933,10 +2011,15 @@ static void prof_end(grmhd_ctx* c) {
 static GhostLists ghost_lists(const grmhd_ctx* c, int lev) {
   GhostLists G;
   int64_t run = 0;
+  G.ops[0] = nullptr;
   for (int k = 0; k < 4; k++) {
-    const int64_t o = lev < 0 ? 0 : c->plan.ops_off[k][lev];
-    const int64_t n = lev < 0 ? c->nops[k] : c->plan.ops_off[k][lev + 1] - o;
-    G.ops[k] = c->ops[k] + o;
+    const std::vector<int64_t>& off = c->gh_off[k];
+    const int64_t o = lev < 0 ? 0 : off[lev];
+    const int64_t n = lev < 0 ? off.back() : off[lev + 1] - o;
+    if (k == 0)
+      G.cf = c->cf + o;
+    else
+      G.ops[k] = c->ops[k] + o;
     run += n;
     G.end[k] = run;
   }
@@ -2388,14 +2471,26 @@ int grmhd_divb(grmhd_ctx* c, double* max_abs, double* max_rel, double* field) {
 
 int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes) {
   if (!bytes) return fail(GRMHD_EINVAL, "NULL argument");
-  if (what < 0 || what > 19) return fail(GRMHD_EINVAL, "unknown table");
+  if (what < 0 || what > 23) return fail(GRMHD_EINVAL, "unknown table");
   Plan p;
   int rc = build_plan(desc, p, true);
   if (rc) return rc;
   const void* src;
   size_t need;
   std::vector<int32_t> sched;
-  if (what == 10) {
+  DevGhosts dg;
+  if (what >= 20) {
+    // the device ghost copy lists as uploaded: 20 cells with carried faces (GhostCF),
+    // 21..23 the faces of components 1..3 not carried (GhostIdx), each in level order
+    device_ghosts(p, dg);
+    if (what == 20) {
+      src = dg.cf.data();
+      need = dg.cf.size() * sizeof(GhostCF);
+    } else {
+      src = dg.lf[what - 20].data();
+      need = dg.lf[what - 20].size() * sizeof(GhostIdx);
+    }
+  } else if (what == 10) {
     // the order in which one cycle steps and synchronises blocks (as lat_cycle launches
     // them): per substep the due levels slowest first, then the sync points
     const int L = p.nlev, nsub = 1 << (L - 1);

@@ -34,9 +34,21 @@ struct GhostIdx {
   uint32_t dst, src, dvol, svol_fl;
 };
 
-// The four ghost lists of one fill run as one launch: cells, then faces of components
-// 1..3; thread t takes entry t of their concatenation (end: running totals).
+// A ghost cell copied together with the ghost faces at its local index that are plain
+// copies of the faces at its source's local index (same source block, no flip, no
+// zero, the same time relation): element indices of variable 0 of the primitives (dp,
+// sp) and of component 0 of the face field (db, sb); dvol_fc = destination volume |
+// carried face components (bits 0-2) << 24; svol_fl = source volume | the cell's flags
+// << 24.  One index record serves up to eight copied values.
+struct GhostCF {
+  uint32_t dp, sp, db, sb, dvol_fc, svol_fl;
+};
+
+// The lists of one fill run as one launch: the cells with their carried faces, then the
+// remaining faces of components 1..3 (ops[1..3]; ops[0] unused); thread t takes entry t
+// of their concatenation (end: running totals).
 struct GhostLists {
+  const GhostCF* cf;
   const GhostIdx* ops[4];
   int64_t end[4];
 };

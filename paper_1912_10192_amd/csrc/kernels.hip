@@ -102,19 +102,22 @@ __global__ __launch_bounds__(NT) void k_ghosts(GhostLists G, double* __restrict_
   const int64_t t = (int64_t)blockIdx.x * NT + threadIdx.x;
   if (t >= G.end[3]) return;
   if (t < G.end[0]) {
-    const GhostIdx op = G.ops[0][t];
-    const int fl = op.svol_fl >> 24;
-    const int64_t svol = op.svol_fl & 0xFFFFFF;
-    const double* src = P + op.src;
-    double* dst = P + op.dst;
+    const GhostCF op = G.cf[t];
+    const int fl = op.svol_fl >> 24, fc = op.dvol_fc >> 24;
+    const int64_t svol = op.svol_fl & 0xFFFFFF, dvol = op.dvol_fc & 0xFFFFFF;
+    const double* src = P + op.sp;
+    double* dst = P + op.dp;
 #pragma unroll
     for (int v = 0; v < 5; v++) {
       double x = src[v * svol];
       if (v == 3 && (fl & GF_FLIP)) x = -x;
       if (v == 2 && (fl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
       if (v == 2 && (fl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
-      dst[v * (int64_t)op.dvol] = x;
+      dst[v * dvol] = x;
     }
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+      if ((fc >> c) & 1) B[op.db + c * dvol] = B[op.sb + c * svol];
     return;
   }
   const int k = t < G.end[1] ? 1 : (t < G.end[2] ? 2 : 3);

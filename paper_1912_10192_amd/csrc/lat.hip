@@ -53,18 +53,21 @@ __global__ __launch_bounds__(LT) void k_ghosts_t(GhostLists G, const double* __r
   const int64_t t = (int64_t)blockIdx.x * LT + threadIdx.x;
   if (t >= G.end[3]) return;
   if (t < G.end[0]) {
-    const GhostIdx op = G.ops[0][t];
-    const int fl = op.svol_fl >> 24;
-    const int64_t svol = op.svol_fl & 0xFFFFFF;
-    double* out = Pdst + op.dst;
+    const GhostCF op = G.cf[t];
+    const int fl = op.svol_fl >> 24, fc = op.dvol_fc >> 24;
+    const int64_t svol = op.svol_fl & 0xFFFFFF, dvol = op.dvol_fc & 0xFFFFFF;
+    double* out = Pdst + op.dp;
 #pragma unroll
     for (int v = 0; v < 5; v++) {
-      double x = timed_value(fl, op.src + v * svol, Pmain, Pold, Pcur, w);
+      double x = timed_value(fl, op.sp + v * svol, Pmain, Pold, Pcur, w);
       if (v == 3 && (fl & GF_FLIP)) x = -x;
       if (v == 2 && (fl & GF_CLAMP_NEG) && x > 0.0) x = 0.0;
       if (v == 2 && (fl & GF_CLAMP_POS) && x < 0.0) x = 0.0;
-      out[v * (int64_t)op.dvol] = x;
+      out[v * dvol] = x;
     }
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+      if ((fc >> c) & 1) Bdst[op.db + c * dvol] = timed_value(fl, op.sb + c * svol, Bmain, Bold, Bcur, w);
     return;
   }
   const int k = t < G.end[1] ? 1 : (t < G.end[2] ? 2 : 3);

@@ -222,7 +222,7 @@ class Desc:
         buf = np.zeros(nbytes.value // 4, dtype=np.int32)
         _check(lib().grmhd_plan_dump(C.byref(self.d), what, buf.ctypes.data_as(C.c_void_p),
                                      C.byref(nbytes)))
-        return buf.reshape(-1, {9: 13, 12: 10, 13: 7, 14: 7}.get(what, 4))
+        return buf.reshape(-1, {9: 13, 12: 10, 13: 7, 14: 7, 20: 6}.get(what, 4))
 
 
 def geometry_point(coords, a, x1, x2):

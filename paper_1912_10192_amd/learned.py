@@ -93,12 +93,13 @@ def train(X, Y, steps=2000, batch=4096, lr=1e-3, seed=7, log_every=0):
     import torch
 
     trainer = grmhd.MLPTrainer(init_params(seed, X.device), batch=batch)
-    gen = torch.Generator(device=X.device)
-    gen.manual_seed(seed)
     n = X.shape[0]
+    # every step's batch rows drawn up front on the host (seeded), one upload
+    rows = np.random.default_rng(seed).integers(0, n, size=(steps, batch), dtype=np.int32)
+    rows = torch.from_numpy(rows).to(X.device)
     losses = []
     for s in range(steps):
-        idx = torch.randint(0, n, (batch,), generator=gen, device=X.device, dtype=torch.int32)
+        idx = rows[s]
         rate = 0.5 * lr * (1.0 + math.cos(math.pi * s / steps))
         trainer.step(X, Y, idx, rate)
         if log_every and (s % log_every == 0 or s == steps - 1):

@@ -188,3 +188,76 @@ def test_saved_old_state_is_what_slow_ghosts_read(case):
     for key in {(lat, w) for lat, w, _, _ in got}:
         seq = [(b, e) for lat, w, b, e in got if (lat, w) == key]
         assert seq == sorted(seq)
+
+
+def _case_desc(case):
+    if case == "ks-lat-uniform":
+        cfg = configs.scaled(configs.TORUS_UNIFORM, (32, 16, 16), block=(8, 8, 8))
+        blocks = grmhd.uniform_blocks(cfg["n"], cfg["block"], lats=[0, 1, 2, 2])
+    elif case == "mink-periodic":
+        cfg = dict(mink_cfg((12, 8, 8), recon=1, riemann=1), block=(4, 4, 4))
+        blocks = None
+    elif case == "ks-uniform":
+        cfg = configs.scaled(configs.TORUS_UNIFORM, (32, 16, 16), block=(16, 8, 8))
+        blocks = None
+    else:
+        _, cfg, blocks = [c for c in cases() if c[0] == case][0]
+    return grmhd.Desc(cfg, blocks=blocks)
+
+
+@pytest.mark.parametrize("case", [c[0] for c in cases()] + ["ks-lat-uniform", "mink-periodic",
+                                                            "ks-uniform"])
+def test_device_ghost_lists_are_the_ghost_copies(case):
+    """The uploaded ghost copy lists (each ghost cell carrying the ghost faces at its
+    local index that copy its source's faces unchanged, then the other faces) expand to
+    exactly the planner's element lists, copy for copy, with sources, flags and volumes;
+    entries run in time-level order; and most faces ride with their cell."""
+    desc = _case_desc(case)
+    nb = desc.d.n_blocks
+    vol = [int(np.prod(desc.layout(b)[1])) for b in range(nb)]
+    off = np.concatenate([[0], np.cumsum(vol)[:-1]]).astype(np.int64)
+    lat = np.array([desc.blocks[b].lat for b in range(nb)])
+    time_bits = 16 | 32
+
+    def element_list(what):
+        ops = desc.plan_dump(what).astype(np.int64)
+        db, dl, sf, sl = ops.T
+        sb, fl = sf & 0xFFFFFF, sf >> 24
+        nv, cv = (5, 0) if what == 0 else (3, what - 1)
+        dst = nv * off[db] + cv * np.array(vol)[db] + dl
+        src = nv * off[sb] + cv * np.array(vol)[sb] + sl
+        return dst, src, fl, np.array(vol)[db], np.array(vol)[sb], lat[db]
+
+    cf = desc.plan_dump(20).view(np.uint32).astype(np.int64)
+    dp, sp, dbf, sbf, dvfc, svfl = cf.T
+    dvol, fc = dvfc & 0xFFFFFF, dvfc >> 24
+    svol, cfl = svfl & 0xFFFFFF, svfl >> 24
+    # cells: the CF entries in order are the planner's cell list
+    dst, src, fl, dv, sv, lv = element_list(0)
+    assert np.array_equal(dp, dst) and np.array_equal(sp, src) and np.array_equal(cfl, fl)
+    assert np.array_equal(dvol, dv) and np.array_equal(svol, sv)
+    assert np.all(np.diff(lv) >= 0)
+    blk = np.searchsorted(off * 5, dp, side="right") - 1     # the destination block
+    assert np.array_equal(dbf, 3 * off[blk] + (dp - 5 * off[blk]))
+    carried = 0
+    total = 0
+    for k in (1, 2, 3):
+        want = element_list(k)
+        left = desc.plan_dump(20 + k).view(np.uint32).astype(np.int64)
+        got_dst = [left[:, 0]]
+        got_src = [left[:, 1]]
+        got_fl = [left[:, 3] >> 24]
+        sel = ((fc >> (k - 1)) & 1) == 1
+        got_dst.append(dbf[sel] + (k - 1) * dvol[sel])
+        got_src.append(sbf[sel] + (k - 1) * svol[sel])
+        got_fl.append(cfl[sel] & time_bits)
+        carried += int(sel.sum())
+        total += len(want[0])
+        got = sorted(zip(np.concatenate(got_dst), np.concatenate(got_src), np.concatenate(got_fl)))
+        exp = sorted(zip(want[0], want[1], want[2]))
+        assert got == exp, k
+        # the faces left over keep the level order
+        lv_left = lat[np.searchsorted(off * 3, left[:, 0], side="right") - 1]
+        assert np.all(np.diff(lv_left) >= 0)
+    print(f"{case}: {carried} of {total} ghost faces carried by their cell")
+    assert carried >= 0.5 * total
