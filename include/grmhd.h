@@ -53,7 +53,9 @@ enum { GRMHD_GUESS_PLAIN = 0, GRMHD_GUESS_MLP = 1 };
  * average with the upwinded corrections of Gardiner & Stone (2005) that the paper applies
  * by default (each corner takes the gradients of the EMF toward the neighbouring cell
  * centres, where the EMF of the cell's own state sits, from the side upstream of the mass
- * flux through the face between the candidates) */
+ * flux through the face between the candidates; a mass flux within 1e-12 of the largest
+ * conserved density sqrt(-g) rho u^t of the edge's cells counts as zero and takes the
+ * mean of both sides) */
 enum { GRMHD_EMF_AVERAGE = 0, GRMHD_EMF_UPWIND = 1 };
 
 /* One block of the grid (Sec. 3.3 block structure; Sec. 3.4 coarsening toward the
