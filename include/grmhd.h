@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GRMHD_ABI_VERSION 2
+#define GRMHD_ABI_VERSION 3
 
 enum { GRMHD_OK = 0, GRMHD_EINVAL = -1, GRMHD_ENOMEM = -2, GRMHD_EHIP = -3,
        GRMHD_ESTATE = -4, GRMHD_EUNSUPPORTED = -5 };
@@ -138,6 +138,7 @@ typedef struct {
    * statistics reductions */
   double class_ms[8];
   int64_t class_launches[8];
+  int64_t bad_states;               /* cells an update left non-finite or with rho <= 0 or u <= 0 */
 } grmhd_step_stats;
 
 typedef struct grmhd_ctx grmhd_ctx;
@@ -162,7 +163,11 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
                     grmhd_ctx** out);
 
 /* Advance n_cycles steps (Sec. 2.1 midpoint method).  stats (host, nullable)
- * receives counters for this call; passing it synchronises the stream. */
+ * receives counters for this call; passing it synchronises the stream.  With stats,
+ * the call also checks the state: if any update (the floors applied) left a cell with a
+ * non-finite primitive or face-centred field, rho <= 0 or u <= 0, it returns
+ * GRMHD_ESTATE (the counters are filled and the steps were taken; the state is not
+ * usable).  Without stats nothing is checked. */
 int grmhd_step(grmhd_ctx* ctx, int32_t n_cycles, grmhd_step_stats* stats);
 
 /* Autotuner of the two heavy kernels.  The flux kernel (per direction) is built in

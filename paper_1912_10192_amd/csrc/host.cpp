@@ -2326,6 +2326,10 @@ int grmhd_step(grmhd_ctx* c, int32_t n_cycles, grmhd_step_stats* stats) {
       stats->class_ms[q] = cls_ms[q];
       stats->class_launches[q] = cls_n[q];
     }
+    stats->bad_states = (int64_t)h.bad;
+    if (h.bad)
+      return fail(GRMHD_ESTATE, std::to_string(h.bad) +
+                                    " cell updates left a non-finite state or rho <= 0 or u <= 0");
   }
   return GRMHD_OK;
 }

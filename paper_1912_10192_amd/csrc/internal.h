@@ -150,6 +150,7 @@ struct Counters {   // device counters of one grmhd_step call
   unsigned long long hist[64];
   unsigned long long floors;
   unsigned long long mlp;         // inversions started from the learned guess
+  unsigned long long bad;         // cells left non-finite or with rho <= 0 or u <= 0
   unsigned long long dt_bits;     // min over cells of 1/sum_d(v_d/dx_d), as IEEE bits
   unsigned long long divb_abs;    // max |div B| bits
   unsigned long long divb_rel;
@@ -181,7 +182,7 @@ constexpr int STAGE_NT = 256;   // threads per workgroup of the stage kernels
 // counts into one of STAT_COPIES copies of the accumulators (by workgroup index, so few
 // workgroups meet on one address); launch_stats_fold adds the copies to the counters
 // and clears them.
-enum { ST_TIER = 0, ST_HIST = 5, ST_FLOORS = 69, ST_MLP = 70, NSTAT = 71 };
+enum { ST_TIER = 0, ST_HIST = 5, ST_FLOORS = 69, ST_MLP = 70, ST_BAD = 71, NSTAT = 72 };
 constexpr int STAT_COPIES = 64;
 
 // occupancy variants of the flux and update kernels (see kernels.hip)

@@ -728,19 +728,27 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
 }
 
 // The inversion of one cell and its floors (Sec. 2.6, 2.7); writes the primitives and,
-// with NEXT_DT, returns the cell's Courant step of the next step in dtc
+// with NEXT_DT, returns the cell's Courant step of the next step in dtc; bad = 1 when the
+// result is not a physical state (a non-finite value, rho <= 0 or u <= 0)
 template <bool NEXT_DT>
 __device__ __forceinline__ void invert_cell(const Launch& L, const BlockInfo& bi, const Cell& c,
                                             const Metric& m, int64_t col, const C2PIn& cs,
                                             bool first, double W0, double v0, const double PS[5],
                                             const double fl[2], double* __restrict__ Pout,
-                                            int& tier, int& iters, int& hits, double& dtc) {
+                                            int& tier, int& iters, int& hits, int& bad,
+                                            double& dtc) {
   double Pnew[5];
   tier = c2p_solve(cs, m, first, W0, v0, PS, L.ph.tol, L.ph.maxit, Pnew, iters);
   // B^i = Bbar^i / sqrt(-g) with Bbar^i the face average; c2p_setup holds alpha B^i
   const double ia = 1.0 / m.alpha;
   const double Bnew[3] = {cs.B1 * ia, cs.B2 * ia, cs.B3 * ia};
   hits = apply_floors(Pnew, Bnew, m, fl[0], fl[1], L.ph.bsq_rho_max, L.ph.bsq_u_max, L.ph.gamma_max);
+  bool ok = Pnew[0] > 0.0 && Pnew[1] > 0.0;
+#pragma unroll
+  for (int v = 0; v < 5; v++) ok = ok && isfinite(Pnew[v]);
+#pragma unroll
+  for (int v = 0; v < 3; v++) ok = ok && isfinite(Bnew[v]);
+  bad = ok ? 0 : 1;
 #pragma unroll
   for (int v = 0; v < 5; v++) Pout[5 * bi.off + (int64_t)v * bi.vol + c.loc] = Pnew[v];
   if (NEXT_DT) dtc = cell_dt(Pnew, Bnew, m, L.ph, bi.idx);
@@ -752,8 +760,9 @@ __device__ __forceinline__ void invert_cell(const Launch& L, const BlockInfo& bi
 // itself; spread over the copies, a few dozen workgroups meet on one address per launch)
 template <bool STATS, bool NEXT_DT>
 __device__ __forceinline__ void update_epilogue(const Launch& L, const BlockTile& bt, bool valid,
-                                                int tier, int iters, int hits, bool learned,
-                                                double dtc, double* __restrict__ dt_part) {
+                                                int tier, int iters, int hits, int bad,
+                                                bool learned, double dtc,
+                                                double* __restrict__ dt_part) {
   if (NEXT_DT) {
     const double r = block_min(dtc);
     if (threadIdx.x == 0) dt_part[bt.slot] = r;
@@ -768,6 +777,8 @@ __device__ __forceinline__ void update_epilogue(const Launch& L, const BlockTile
     if (lane_id() == 0 && h) atomicAdd(&cnt[ST_FLOORS], (uint32_t)h);
     const unsigned long long lm = __ballot(valid && learned);
     if (lane_id() == 0 && lm) atomicAdd(&cnt[ST_MLP], (uint32_t)__popcll(lm));
+    const unsigned long long bm = __ballot(valid && bad);
+    if (lane_id() == 0 && bm) atomicAdd(&cnt[ST_BAD], (uint32_t)__popcll(bm));
     __syncthreads();
     unsigned long long* acc = L.stat_acc + (bt.slot & (STAT_COPIES - 1)) * NSTAT;
     for (int q = threadIdx.x; q < NSTAT; q += NT)
@@ -789,7 +800,8 @@ __global__ __launch_bounds__(128) void k_stats_fold(Counters* __restrict__ cnt,
   unsigned long long* dst = q < ST_HIST     ? &cnt->tier[q - ST_TIER]
                             : q < ST_FLOORS ? &cnt->hist[q - ST_HIST]
                             : q == ST_FLOORS ? &cnt->floors
-                                             : &cnt->mlp;
+                            : q == ST_MLP    ? &cnt->mlp
+                                             : &cnt->bad;
   *dst += t;
 }
 
@@ -823,7 +835,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   } else {
     valid = region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g, g, g, c);
   }
-  int tier = 0, iters = 0, hits = 0;
+  int tier = 0, iters = 0, hits = 0, bad = 0;
   double dtc = __longlong_as_double(0x7FF0000000000000LL);
   const int64_t col = valid ? geo_col(L.geo, bi, c.J, c.I) : 0;
   Metric m;
@@ -839,8 +851,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   bool first = false;
   double W0 = 0.0, v0 = 0.0;
   if (MLP) first = learned_guess(mlp, cs, m, valid, PS, W0, v0);
-  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters, hits, dtc);
-  update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, first, dtc, dt_part);
+  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters, hits, bad, dtc);
+  update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, bad, first, dtc, dt_part);
 }
 
 // split update, first half: the conserved state of every cell into ubuf [9][cell]
@@ -879,7 +891,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   Cell c;
   const bool valid = region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g,
                                  g, g, c);
-  int tier = 0, iters = 0, hits = 0;
+  int tier = 0, iters = 0, hits = 0, bad = 0;
   double dtc = __longlong_as_double(0x7FF0000000000000LL);
   const int64_t col = valid ? geo_col(L.geo, bi, c.J, c.I) : 0;
   Metric m;
@@ -900,8 +912,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   bool first = false;
   double W0 = 0.0, v0 = 0.0;
   if (MLP) first = learned_guess(mlp, cs, m, valid, PS, W0, v0);
-  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters, hits, dtc);
-  update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, first, dtc, dt_part);
+  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters, hits, bad, dtc);
+  update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, bad, first, dtc, dt_part);
 }
 
 // ------------------------------------------------------------- Courant reduction
@@ -952,6 +964,7 @@ __global__ void k_reset(Counters* cnt, unsigned long long* acc, int all) {
   if (t == 0) {
     cnt->floors = 0;
     cnt->mlp = 0;
+    cnt->bad = 0;
     cnt->divb_abs = 0;
     cnt->divb_rel = 0;
     cnt->dt_bits = 0x7FF0000000000000ULL;

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.environ.get("GRMHD_SO", os.path.join(_HERE, "libgrmhd.so"))
 _lib = None
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 OK, EINVAL, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MINK_CART, KS_LOGSPH = 0, 1
 PLM_MC, PPM = 0, 1
@@ -65,7 +65,7 @@ class StepStats(C.Structure):
                 ("c2p_iter_hist", C.c_int64 * 64), ("c2p_tier", C.c_int64 * 5),
                 ("floor_hits", C.c_int64), ("mlp_guesses", C.c_int64), ("dt_min", C.c_double), ("t_sim", C.c_double),
                 ("kernel_ms", C.c_double), ("class_ms", C.c_double * 8),
-                ("class_launches", C.c_int64 * 8)]
+                ("class_launches", C.c_int64 * 8), ("bad_states", C.c_int64)]
 
 
 class C2PBatch(C.Structure):
