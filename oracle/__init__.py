@@ -18,7 +18,7 @@ _SO = os.path.join(_HERE, "liborc.so")
 _lib = None
 
 MINK, KS = 0, 1
-PLM, PPM = 0, 1
+PLM, PPM, PLM_MINMOD = 0, 1, 2
 LLF, HLLE = 0, 1
 EMF_AVERAGE, EMF_UPWIND = 0, 1
 BC_OUTFLOW, BC_POLAR, BC_PERIODIC = 0, 1, 2

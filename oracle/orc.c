@@ -274,6 +274,12 @@ static double mc_slope(double dm, double dp) {
   return dm > 0.0 ? m : -m;
 }
 
+/* MINMOD limited slope: the smaller of the two one-sided differences, zero at extrema */
+static double minmod_slope(double dm, double dp) {
+  if (dm * dp <= 0.0) return 0.0;
+  return fabs(dm) < fabs(dp) ? dm : dp;
+}
+
 /* PPM (Colella & Woodward 1984) limited parabola of cell with values am, a0, ap
  * and unlimited face values fl, fr; writes the monotonised face values. */
 static void ppm_cell(double a0, double fl, double fr, double* ol, double* or_) {
@@ -302,6 +308,11 @@ void orc_recon_face(int recon, const double* a, double* left, double* right) {
   if (recon == ORC_PLM) {
     *left = a[2] + 0.5 * mc_slope(a[2] - a[1], a[3] - a[2]);
     *right = a[3] - 0.5 * mc_slope(a[3] - a[2], a[4] - a[3]);
+    return;
+  }
+  if (recon == ORC_PLM_MINMOD) {
+    *left = a[2] + 0.5 * minmod_slope(a[2] - a[1], a[3] - a[2]);
+    *right = a[3] - 0.5 * minmod_slope(a[3] - a[2], a[4] - a[3]);
     return;
   }
   double f15 = ppm_face(a, 1), f25 = ppm_face(a, 2), f35 = ppm_face(a, 3);

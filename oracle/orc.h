@@ -33,7 +33,9 @@ extern "C" {
 #endif
 
 enum { ORC_MINK = 0, ORC_KS = 1 };
-enum { ORC_PLM = 0, ORC_PPM = 1 };
+/* reconstruction (Sec. 2.1): piecewise linear with the monotonised-central limiter,
+ * PPM, or piecewise linear with the MINMOD limiter (the shock tubes of Sec. 7.2) */
+enum { ORC_PLM = 0, ORC_PPM = 1, ORC_PLM_MINMOD = 2 };
 enum { ORC_LLF = 0, ORC_HLLE = 1 };
 /* edge EMFs: the average of the four neighbouring face fluxes of B (Sec. 2.5), or that
  * average corrected by the upwinded gradients of Gardiner & Stone (2005), which the

@@ -164,6 +164,13 @@ TORUS_AMR3 = dict(KS_TORUS_BASE, name="torus-eff512x256x256-amr-lat4-1344blocks"
                   lat_edges=(2.4, 4.8, 9.6))
 
 
+# The off-centre spherical explosion through the polar axis (Sec. 7.3) at a size the
+# oracle steps in seconds: r in [5, 20] around the explosion centred at r = 10.4
+EXPLOSION = dict(KS_TORUS_BASE, name="explosion-48x48x16-ppm-hlle", n=(48, 48, 16),
+                 block=(24, 24, 16), ng=3, recon=1, riemann=1,
+                 xlo=(math.log(5.0), 0.0, 0.0), xhi=(math.log(20.0), math.pi, 2.0 * math.pi))
+
+
 # Large single-GPU tilted thin disk: effective 1024x384x384 on r in [1.2, 1000] (disk_blocks)
 DISK5 = dict(KS_TORUS_BASE, name="disk-eff1024x384x384-tilt45-amr2-lat5", n=(1024, 384, 384),
              block=(32, 24, 24), ng=3, recon=1, riemann=1, cycles=100,

@@ -197,6 +197,18 @@ __device__ __forceinline__ double mc_lim(double dm, double dp) {
   return copysign(s, dm);
 }
 
+// the smaller one-sided difference (MINMOD), zero at an extremum
+__device__ __forceinline__ double mm_lim(double dm, double dp) {
+  if (dm * dp <= 0.0) return 0.0;
+  return fabs(dm) < fabs(dp) ? dm : dp;
+}
+
+// the piecewise-linear limiter of RECON (0: monotonised central, 2: MINMOD)
+template <int RECON>
+__device__ __forceinline__ double plm_lim(double dm, double dp) {
+  return RECON == 2 ? mm_lim(dm, dp) : mc_lim(dm, dp);
+}
+
 // monotonised parabola of one cell (Colella & Woodward 1984)
 __device__ __forceinline__ void ppm_limit(double a0, double& l, double& r) {
   if ((r - a0) * (a0 - l) <= 0.0) {
@@ -213,9 +225,9 @@ __device__ __forceinline__ void ppm_limit(double a0, double& l, double& r) {
 // face states of the face between s[2] and s[3] from the six-cell line s[0..5]
 template <int RECON>
 __device__ __forceinline__ void recon_face(const double s[6], double& left, double& right) {
-  if (RECON == 0) {
-    left = s[2] + 0.5 * mc_lim(s[2] - s[1], s[3] - s[2]);
-    right = s[3] - 0.5 * mc_lim(s[3] - s[2], s[4] - s[3]);
+  if (RECON != 1) {
+    left = s[2] + 0.5 * plm_lim<RECON>(s[2] - s[1], s[3] - s[2]);
+    right = s[3] - 0.5 * plm_lim<RECON>(s[3] - s[2], s[4] - s[3]);
   } else {
     const double d1 = mc_lim(s[1] - s[0], s[2] - s[1]);
     const double d2 = mc_lim(s[2] - s[1], s[3] - s[2]);
@@ -239,10 +251,10 @@ __device__ __forceinline__ void recon_face(const double s[6], double& left, doub
 template <int RECON>
 __device__ __forceinline__ void recon_pair(const double s[7], double& l0, double& r0, double& l1,
                                            double& r1) {
-  if (RECON == 0) {
-    const double d2 = mc_lim(s[2] - s[1], s[3] - s[2]);
-    const double d3 = mc_lim(s[3] - s[2], s[4] - s[3]);
-    const double d4 = mc_lim(s[4] - s[3], s[5] - s[4]);
+  if (RECON != 1) {
+    const double d2 = plm_lim<RECON>(s[2] - s[1], s[3] - s[2]);
+    const double d3 = plm_lim<RECON>(s[3] - s[2], s[4] - s[3]);
+    const double d4 = plm_lim<RECON>(s[4] - s[3], s[5] - s[4]);
     l0 = s[2] + 0.5 * d2;
     r0 = s[3] - 0.5 * d3;
     l1 = s[3] + 0.5 * d3;

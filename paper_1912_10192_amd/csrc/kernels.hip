@@ -229,7 +229,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   double* out = F + 24 * bi.off + (int64_t)(DIR - 1) * 8 * V + c.loc;
   constexpr int t1 = DIR == 1 ? 1 : 0;   // transverse field components (0-based)
   constexpr int t2 = DIR == 3 ? 1 : 2;
-  constexpr int k0 = RECON == 0 ? 1 : 0, k1 = RECON == 0 ? 5 : 6;   // stencil used
+  constexpr int k0 = RECON != 1 ? 1 : 0, k1 = RECON != 1 ? 5 : 6;   // stencil used
   double sp[5][6], sb[2][6];
   const double* p = P + 5 * bi.off + c.loc;
   const double* bc = Bc + 3 * bi.off + c.loc;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   double* out = F + 24 * bi.off + (int64_t)(DIR - 1) * 8 * V + loc;
   constexpr int t1 = DIR == 1 ? 1 : 0;
   constexpr int t2 = DIR == 3 ? 1 : 2;
-  constexpr int k0 = RECON == 0 ? 1 : 0, k1 = RECON == 0 ? 6 : 7;   // stencil used
+  constexpr int k0 = RECON != 1 ? 1 : 0, k1 = RECON != 1 ? 6 : 7;   // stencil used
   double sp[5][7], sb[2][7];
   const double* p = P + 5 * bi.off + loc;
   const double* bc = Bc + 3 * bi.off + loc;
@@ -1217,6 +1217,10 @@ static void flux_dir(const Launch& L, int recon, int riemann, const double* P, c
     GRMHD_FLUX_V(0, 0);
   } else if (recon == 0) {
     GRMHD_FLUX_V(0, 1);
+  } else if (recon == 2 && riemann == 0) {
+    GRMHD_FLUX_V(2, 0);
+  } else if (recon == 2) {
+    GRMHD_FLUX_V(2, 1);
   } else if (riemann == 0) {
     GRMHD_FLUX_V(1, 0);
   } else {

@@ -207,6 +207,65 @@ def torus_state(n, a=0.9375, rin_grid=1.2, rout_grid=50.0, rin=6.0, rmax=12.0,
     return P, B1, B2, B3
 
 
+# ------------------------------------------------------------------ off-centre explosion
+
+EXPLOSION_INIT = dict(a=0.9375, gam=4.0 / 3.0, centre=(3.0, 0.0, 10.0), r_s=2.0,
+                      rho_in=1e-4, p_in=3e-5, rho_out=1e-6, p_out=3e-8, width=0.25,
+                      magnetised=False, beta_max=10.0)
+
+
+def explosion_state(n, xlo, xhi, a=0.9375, gam=4.0 / 3.0, centre=(3.0, 0.0, 10.0), r_s=2.0,
+                    rho_in=1e-4, p_in=3e-5, rho_out=1e-6, p_out=3e-8, width=0.25,
+                    magnetised=False, beta_max=10.0):
+    """The off-centre spherical explosion of the paper's validation (Sec. 7.3) on a
+    log-spherical Kerr-Schild grid n over [xlo, xhi]: gas at rest (utilde = 0) with
+    rho = rho_in, p = p_in inside a sphere of radius r_s about `centre` (flat spherical
+    embedding x = r sin th cos ph, ...), falling exponentially to the ambient rho_out,
+    p_out over `width` outside it; optionally threaded by the field of the vector
+    potential A_phi = max(r_s - d, 0) (d the distance from the centre) taken at cell
+    corners, scaled so that max p_g / max (b^2/2) = beta_max.  Returns (P, B1, B2, B3)."""
+    N1, N2, N3 = n
+    dx = [(xhi[d] - xlo[d]) / n[d] for d in range(3)]
+
+    def dist(x1, x2, x3):
+        r = np.exp(x1)
+        X = r * np.sin(x2) * np.cos(x3) - centre[0]
+        Y = r * np.sin(x2) * np.sin(x3) - centre[1]
+        Z = r * np.cos(x2) - centre[2]
+        return np.sqrt(X * X + Y * Y + Z * Z)
+
+    c = [xlo[d] + (np.arange(n[d]) + 0.5) * dx[d] for d in range(3)]
+    X3, X2, X1 = np.meshgrid(c[2], c[1], c[0], indexing="ij")     # [N3][N2][N1]
+    dd = dist(X1, X2, X3)
+    s = np.exp(-np.maximum(dd - r_s, 0.0) / width)
+    P = np.zeros((5, N3, N2, N1))
+    P[0] = rho_out + (rho_in - rho_out) * s
+    P[1] = (p_out + (p_in - p_out) * s) / (gam - 1.0)
+    B1 = np.zeros((N3, N2, N1 + 1))
+    B2 = np.zeros((N3, N2 + 1, N1))
+    B3 = np.zeros((N3 + 1, N2, N1))
+    if magnetised:
+        # A_3 on the x3-directed edges (x1, x2 faces; x3 centres): B1 = d2 A3, B2 = -d1 A3
+        f1 = xlo[0] + np.arange(N1 + 1) * dx[0]
+        f2 = xlo[1] + np.arange(N2 + 1) * dx[1]
+        E3, E2, E1 = np.meshgrid(c[2], f2, f1, indexing="ij")       # [N3][N2+1][N1+1]
+        A = np.maximum(r_s - dist(E1, E2, E3), 0.0)
+        b1 = (A[:, 1:, :] - A[:, :-1, :]) / dx[1]
+        b2 = -(A[:, :, 1:] - A[:, :, :-1]) / dx[0]
+        R, TH = np.exp(X1), X2
+        sig = R * R + a * a * np.cos(TH) ** 2
+        gdet = R * sig * np.sin(TH)
+        Bc = np.stack([0.5 * (b1[..., 1:] + b1[..., :-1]) / gdet,
+                       0.5 * (b2[:, 1:, :] + b2[:, :-1, :]) / gdet, np.zeros_like(R)])
+        bsq = _bsq(P, Bc, R, TH, a)
+        pmax = float(np.max((gam - 1.0) * P[1]))
+        bmax = float(np.max(0.5 * bsq))
+        scale = math.sqrt(pmax / (beta_max * bmax)) if bmax > 0.0 else 0.0
+        B1 = scale * b1
+        B2 = scale * b2
+    return P, B1, B2, B3
+
+
 # --------------------------------------------------------------------------- block grids
 
 def coarsen_state(state, r):

@@ -182,7 +182,7 @@ def test_source_vanishes_in_minkowski():
 
 # ------------------------------------------------------------ reconstruction (Sec. 2.1)
 
-@pytest.mark.parametrize("recon", [oracle.PLM, oracle.PPM])
+@pytest.mark.parametrize("recon", [oracle.PLM, oracle.PPM, oracle.PLM_MINMOD])
 def test_reconstruction_exact_for_linear_data(recon):
     a = 0.3 + 1.7 * np.arange(6)
     l, r = oracle.recon_face(recon, a)
@@ -201,7 +201,7 @@ def test_ppm_exact_for_cubic_cell_averages():
     assert r == pytest.approx(f(2.5), rel=1e-14)
 
 
-@pytest.mark.parametrize("recon", [oracle.PLM, oracle.PPM])
+@pytest.mark.parametrize("recon", [oracle.PLM, oracle.PPM, oracle.PLM_MINMOD])
 def test_reconstruction_bounded_and_flat_at_extrema(recon):
     rng = np.random.default_rng(4)
     for _ in range(500):
@@ -212,6 +212,32 @@ def test_reconstruction_bounded_and_flat_at_extrema(recon):
     # cell 2 is a local maximum: its face value equals its mean
     l, r = oracle.recon_face(recon, np.array([0.0, 1.0, 3.0, 2.0, 1.0, 0.0]))
     assert l == 3.0
+
+
+def test_minmod_and_mc_slopes_closed_forms():
+    """the piecewise-linear face values against the limiters' definitions: MINMOD takes
+    the smaller one-sided difference, MC min(2|dm|, 2|dp|, |dm + dp|/2), both with the
+    common sign and zero where the differences disagree in sign"""
+    rng = np.random.default_rng(8)
+    for _ in range(300):
+        a = rng.normal(size=6)
+        for recon in (oracle.PLM, oracle.PLM_MINMOD):
+            l, r = oracle.recon_face(recon, a)
+            for got, c, sgn in ((l, 2, 0.5), (r, 3, -0.5)):
+                dm, dp = a[c] - a[c - 1], a[c + 1] - a[c]
+                if dm * dp <= 0:
+                    slope = 0.0
+                elif recon == oracle.PLM_MINMOD:
+                    slope = dm if abs(dm) < abs(dp) else dp
+                else:
+                    slope = math.copysign(min(2 * abs(dm), 2 * abs(dp), 0.5 * abs(dm + dp)), dm)
+                assert got == pytest.approx(a[c] + sgn * slope, rel=1e-15, abs=1e-15)
+    # MINMOD is the more diffusive limiter: its slope never exceeds MC's
+    for _ in range(300):
+        a = rng.normal(size=6)
+        lm, _ = oracle.recon_face(oracle.PLM_MINMOD, a)
+        lc, _ = oracle.recon_face(oracle.PLM, a)
+        assert abs(lm - a[2]) <= abs(lc - a[2]) + 1e-15
 
 
 # ----------------------------------------------------------------- inversion (Sec. 2.6)
