@@ -214,14 +214,16 @@ struct Launch {
   int32_t brick_upd;
 };
 
-// Update bricks of 256 cells: 64 (x1, x2) columns of 4 cells along x3, the columns as
-// 32 x 2 or 16 x 4 cells in x1 x x2.  brick_x1 is the brick's x1 width for a block of n
-// interior cells (32 where it divides, else 16), 0 if the block divides into neither;
-// the brick count then equals the number of 256-cell tiles.
+// Update bricks of 256 cells: BRICK_COLS (x1, x2) columns of BRICK_Z cells along x3, the
+// columns as BRICK_COLS x 1 or BRICK_COLS/2 x 2 cells in x1 x x2.  brick_x1 is the brick's
+// x1 width for a block of n interior cells (BRICK_COLS where it divides, else half of
+// it), 0 if the block divides into neither; the brick count then equals the number of
+// 256-cell tiles.
+constexpr int BRICK_Z = 8, BRICK_COLS = 256 / BRICK_Z;
 __host__ __device__ inline int brick_x1(const int32_t n[3]) {
-  if (n[2] % 4 != 0) return 0;
-  if (n[0] % 32 == 0 && n[1] % 2 == 0) return 32;
-  if (n[0] % 16 == 0 && n[1] % 4 == 0) return 16;
+  if (n[2] % BRICK_Z != 0) return 0;
+  if (n[0] % BRICK_COLS == 0) return BRICK_COLS;
+  if (n[0] % (BRICK_COLS / 2) == 0 && n[1] % 2 == 0) return BRICK_COLS / 2;
   return 0;
 }
 

@@ -568,12 +568,12 @@ __device__ __forceinline__ bool learned_guess(const MlpBlob* __restrict__ blob, 
 // compiler interleaves them with the arithmetic in small groups, and each group then
 // costs a full memory round trip.
 //
-// BRICK: the workgroup is a brick of 64 (x1, x2) columns of 4 cells along x3 (brick_x1),
-// so the four cells of each column share the column's centre geometry (metric,
-// connection coefficients, floors: NGEO_C values).  Each thread loads a quarter of its
-// column's values with the cell inputs, the workgroup stages them in LDS (sgeo,
-// [NGEO_C][64]), and the metric, the connection coefficients and the floors are read
-// from there: a quarter of the geometry loads, and no memory round trip for the
+// BRICK: the workgroup is a brick of BRICK_COLS (x1, x2) columns of BRICK_Z cells along
+// x3 (brick_x1), so the cells of each column share the column's centre geometry (metric,
+// connection coefficients, floors: NGEO_C values).  Each thread loads a 1/BRICK_Z share
+// of its column's values with the cell inputs, the workgroup stages them in LDS (sgeo,
+// [NGEO_C][BRICK_COLS]), and the metric, the connection coefficients and the floors are
+// read from there: 1/BRICK_Z of the geometry loads, and no memory round trip for the
 // connection coefficients.  Every thread of the workgroup must call it.  Without BRICK
 // the caller passes the metric in m.
 template <bool BRICK>
@@ -620,12 +620,13 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
   for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * V + l];
 #pragma unroll
   for (int i = 0; i < 3; i++) BS[i] = Bcs[3 * bi.off + (int64_t)i * V + l];
-  double gv[(NGEO_C + 3) / 4];   // BRICK: this thread's quarter of its column's geometry
-  const int cidx = threadIdx.x & 63, q0 = threadIdx.x >> 6;
+  constexpr int NG = (NGEO_C + BRICK_Z - 1) / BRICK_Z;
+  double gv[NG];   // BRICK: this thread's share of its column's geometry
+  const int cidx = threadIdx.x & (BRICK_COLS - 1), q0 = threadIdx.x / BRICK_COLS;
   if (BRICK) {
 #pragma unroll
-    for (int k = 0; k < (NGEO_C + 3) / 4; k++) {
-      const int q = q0 + 4 * k;
+    for (int k = 0; k < NG; k++) {
+      const int q = q0 + BRICK_Z * k;
       gv[k] = q < NGEO_C ? G.c[q * G.ncol + col] : 0.0;
     }
   } else {
@@ -635,14 +636,14 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
   __builtin_amdgcn_sched_barrier(0);
   if (BRICK) {
 #pragma unroll
-    for (int k = 0; k < (NGEO_C + 3) / 4; k++) {
-      const int q = q0 + 4 * k;
-      if (q < NGEO_C) sgeo[q * 64 + cidx] = gv[k];
+    for (int k = 0; k < NG; k++) {
+      const int q = q0 + BRICK_Z * k;
+      if (q < NGEO_C) sgeo[q * BRICK_COLS + cidx] = gv[k];
     }
     __syncthreads();
-    m = load_metric(sgeo + cidx, 64, 0);
-    fl[0] = sgeo[RHOFL * 64 + cidx];
-    fl[1] = sgeo[UFL * 64 + cidx];
+    m = load_metric(sgeo + cidx, BRICK_COLS, 0);
+    fl[0] = sgeo[RHOFL * BRICK_COLS + cidx];
+    fl[1] = sgeo[UFL * BRICK_COLS + cidx];
   }
 
   // constrained transport of the six faces of this cell (Sec. 2.5)
@@ -690,7 +691,7 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
       double conn[20];
 #pragma unroll
       for (int j = 0; j < 20; j++)
-        conn[j] = BRICK ? sgeo[(CONN0 + 20 * h + j) * 64 + cidx]
+        conn[j] = BRICK ? sgeo[(CONN0 + 20 * h + j) * BRICK_COLS + cidx]
                         : G.c[(CONN0 + 20 * h + j) * G.ncol + col];
       if (!BRICK) __builtin_amdgcn_sched_barrier(0);
       connection_contract(T, conn, 2 * h, q);
@@ -806,31 +807,33 @@ __global__ __launch_bounds__(128) void k_stats_fold(Counters* __restrict__ cnt,
 }
 
 // fused update: conserved update, optional learned guess, inversion, floors, next dt
-// BRICK: workgroups are bricks of 64 columns x 4 cells (every block of the launch divides
-// into them, brick_x1), with the geometry of their 64 columns staged in LDS (conserve_cell).
+// BRICK: workgroups are bricks of BRICK_COLS columns x BRICK_Z cells (every block of the
+// launch divides into them, brick_x1), with the geometry of their columns staged in LDS
+// (conserve_cell).
 template <bool STATS, bool NEXT_DT, bool MLP, int OCC, bool BRICK>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_update(
     Launch L, const double* __restrict__ Pn, const double* __restrict__ Bn,
     const double* __restrict__ Ps, const double* __restrict__ Bcs, const double* __restrict__ F,
     const double* __restrict__ E, double dt_factor, double* __restrict__ Pout,
     double* __restrict__ Bout, double* __restrict__ dt_part, const MlpBlob* __restrict__ mlp) {
-  __shared__ double sgeo[BRICK ? NGEO_C * 64 : 1];
+  __shared__ double sgeo[BRICK ? NGEO_C * BRICK_COLS : 1];
   const BlockTile bt = block_tile(L);
   const BlockInfo bi = L.blk[bt.blk];
   const int g = L.ph.ng;
   Cell c;
   bool valid;
   if (BRICK) {
-    // brick (b0, b1, b2) of the tile, x1 fastest, bx x by x 4 cells (bx by = 64, so the
-    // thread's column in the brick is t & 63); valid for the whole workgroup or none
-    const int bx = brick_x1(bi.n), by = 64 / bx;
-    const int nb0 = bi.n[0] / bx, nb1 = bi.n[1] / by, nb2 = bi.n[2] >> 2;
+    // brick (b0, b1, b2) of the tile, x1 fastest, bx x by x BRICK_Z cells (bx by =
+    // BRICK_COLS, so the thread's column in the brick is t % BRICK_COLS); valid for the
+    // whole workgroup or none
+    const int bx = brick_x1(bi.n), by = BRICK_COLS / bx;
+    const int nb0 = bi.n[0] / bx, nb1 = bi.n[1] / by, nb2 = bi.n[2] / BRICK_Z;
     const int t = threadIdx.x;
     valid = bt.tile < nb0 * nb1 * nb2;
     const int b0 = bt.tile % nb0, r = bt.tile / nb0, b1 = r % nb1, b2 = r / nb1;
     c.I = g + b0 * bx + (t & (bx - 1));
-    c.J = g + b1 * by + ((t & 63) / bx);
-    c.K = g + b2 * 4 + (t >> 6);
+    c.J = g + b1 * by + ((t & (BRICK_COLS - 1)) / bx);
+    c.K = g + b2 * BRICK_Z + t / BRICK_COLS;
     c.loc = ((int64_t)c.K * bi.np[1] + c.J) * bi.np[0] + c.I;
   } else {
     valid = region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g, g, g, c);
