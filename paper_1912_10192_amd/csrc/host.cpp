@@ -1562,7 +1562,7 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
       auto region = [&](int b, int cls) -> int64_t {
         const BlockInfo& bi = p.info[b];
         switch (cls) {
-          case WL_BCELL: return (int64_t)bi.np[0] * bi.np[1] * bi.np[2];
+          case WL_BCELL: return (int64_t)(bi.np[0] - 1) * (bi.np[1] - 1) * (bi.np[2] - 1);
           case WL_EMF: return (int64_t)(bi.n[0] + 1) * (bi.n[1] + 1) * (bi.n[2] + 1);
           case WL_CELLS: return (int64_t)bi.n[0] * bi.n[1] * bi.n[2];
           case WL_EREF: return (int64_t)(bi.n[0] + 2) * (bi.n[1] + 2) * (bi.n[2] + 2);
@@ -1963,9 +1963,16 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   L.ph.ng = desc->n_ghost;
   L.cnt = (Counters*)(w + p.o_cnt);
   L.stat_acc = (unsigned long long*)(w + p.o_stp);
-  L.brick_upd = 1;
-  for (const BlockInfo& b : p.info)
-    if (!brick_x1(b.n)) L.brick_upd = 0;
+  // the tallest update brick every block divides into (8 or 4 cells along x3), else none
+  L.brick_upd = 0;
+  for (int z : {8, 4}) {
+    bool all = true;
+    for (const BlockInfo& b : p.info) all = all && brick_x1(b.n, z) != 0;
+    if (all) {
+      L.brick_upd = z;
+      break;
+    }
+  }
   L.stream = c->stream;
   for (int k = 0; k < 3; k++) L.var_flux[k] = 2;   // 4 waves per SIMD
   L.var_upd = 0;

@@ -209,21 +209,22 @@ struct Launch {
   const int2* wl;
   // statistics accumulators of the update kernels, [STAT_COPIES][NSTAT]
   unsigned long long* stat_acc;
-  // 1: every block divides into update bricks (brick_x1): the fused update runs brick by
-  // brick with the column geometry staged in LDS
+  // 8 or 4: every block divides into update bricks of that many cells along x3
+  // (brick_x1): the fused update runs brick by brick with the column geometry staged in
+  // LDS; 0: cell tiles
   int32_t brick_upd;
 };
 
-// Update bricks of 256 cells: BRICK_COLS (x1, x2) columns of BRICK_Z cells along x3, the
-// columns as BRICK_COLS x 1 or BRICK_COLS/2 x 2 cells in x1 x x2.  brick_x1 is the brick's
-// x1 width for a block of n interior cells (BRICK_COLS where it divides, else half of
-// it), 0 if the block divides into neither; the brick count then equals the number of
-// 256-cell tiles.
-constexpr int BRICK_Z = 8, BRICK_COLS = 256 / BRICK_Z;
-__host__ __device__ inline int brick_x1(const int32_t n[3]) {
-  if (n[2] % BRICK_Z != 0) return 0;
-  if (n[0] % BRICK_COLS == 0) return BRICK_COLS;
-  if (n[0] % (BRICK_COLS / 2) == 0 && n[1] % 2 == 0) return BRICK_COLS / 2;
+// Update bricks of 256 cells: 256/z (x1, x2) columns of z cells along x3 (z = 8, or 4
+// where a block's x3 extent is not a multiple of 8), the columns as cols x 1, cols/2 x 2
+// or cols/4 x 4 cells in x1 x x2.  brick_x1 is the brick's x1 width for a block of n
+// interior cells (the widest that divides), 0 if the block divides into none; the brick
+// count then equals the number of 256-cell tiles.
+__host__ __device__ inline int brick_x1(const int32_t n[3], int z) {
+  const int cols = 256 / z;
+  if (n[2] % z != 0) return 0;
+  for (int by = 1; by <= 4; by *= 2)
+    if (n[0] % (cols / by) == 0 && n[1] % by == 0 && cols / by >= 16) return cols / by;
   return 0;
 }
 

@@ -132,22 +132,24 @@ __global__ __launch_bounds__(NT) void k_ghosts(GhostLists G, double* __restrict_
 // --------------------------------------------------------- cell-centred field
 
 // B^i at cell centres = average of the two face fields / sqrt(-g) (Sec. 2.5), for every
-// cell that has both faces in the padded block
+// cell but the last padding layer (which no stencil reads; its upper faces lie outside
+// the block's arrays)
 __global__ __launch_bounds__(NT) void k_bcell(Launch L, const double* __restrict__ B,
                                               double* __restrict__ Bc) {
   const BlockTile bt = block_tile(L);
   const BlockInfo bi = L.blk[bt.blk];
   Cell c;
-  if (!region_cell(bi, bt.tile * NT + threadIdx.x, bi.np[0], bi.np[1], bi.np[2], 0, 0, 0, c))
+  if (!region_cell(bi, bt.tile * NT + threadIdx.x, bi.np[0] - 1, bi.np[1] - 1, bi.np[2] - 1, 0,
+                   0, 0, c))
     return;
   const int64_t V = bi.vol;
   const double* b = B + 3 * bi.off;
   double* o = Bc + 3 * bi.off;
   const double gdet = L.geo.c[GDET * L.geo.ncol + geo_col(L.geo, bi, c.J, c.I)];
   const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
-  if (c.I + 1 < bi.np[0]) o[c.loc] = 0.5 * (b[c.loc] + b[c.loc + 1]) / gdet;
-  if (c.J + 1 < bi.np[1]) o[V + c.loc] = 0.5 * (b[V + c.loc] + b[V + c.loc + s2]) / gdet;
-  if (c.K + 1 < bi.np[2]) o[2 * V + c.loc] = 0.5 * (b[2 * V + c.loc] + b[2 * V + c.loc + s3]) / gdet;
+  o[c.loc] = 0.5 * (b[c.loc] + b[c.loc + 1]) / gdet;
+  o[V + c.loc] = 0.5 * (b[V + c.loc] + b[V + c.loc + s2]) / gdet;
+  o[2 * V + c.loc] = 0.5 * (b[2 * V + c.loc] + b[2 * V + c.loc + s3]) / gdet;
 }
 
 // ------------------------------------------------------------------ face fluxes
@@ -568,15 +570,15 @@ __device__ __forceinline__ bool learned_guess(const MlpBlob* __restrict__ blob, 
 // compiler interleaves them with the arithmetic in small groups, and each group then
 // costs a full memory round trip.
 //
-// BRICK: the workgroup is a brick of BRICK_COLS (x1, x2) columns of BRICK_Z cells along
-// x3 (brick_x1), so the cells of each column share the column's centre geometry (metric,
-// connection coefficients, floors: NGEO_C values).  Each thread loads a 1/BRICK_Z share
-// of its column's values with the cell inputs, the workgroup stages them in LDS (sgeo,
-// [NGEO_C][BRICK_COLS]), and the metric, the connection coefficients and the floors are
-// read from there: 1/BRICK_Z of the geometry loads, and no memory round trip for the
-// connection coefficients.  Every thread of the workgroup must call it.  Without BRICK
-// the caller passes the metric in m.
-template <bool BRICK>
+// BZ > 0: the workgroup is a brick of 256/BZ (x1, x2) columns of BZ cells along x3
+// (brick_x1), so the cells of each column share the column's centre geometry (metric,
+// connection coefficients, floors: NGEO_C values).  Each thread loads a 1/BZ share of its
+// column's values with the cell inputs, the workgroup stages them in LDS (sgeo,
+// [NGEO_C][256/BZ]), and the metric, the connection coefficients and the floors are read
+// from there: 1/BZ of the geometry loads, and no memory round trip for the connection
+// coefficients.  Every thread of the workgroup must call it.  With BZ = 0 the caller
+// passes the metric in m.
+template <int BZ>
 __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& bi, const Cell& c,
                                               Metric& m, double* sgeo, int64_t col,
                                               const double* __restrict__ Pn,
@@ -620,13 +622,15 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
   for (int v = 0; v < 5; v++) PS[v] = Ps[5 * bi.off + (int64_t)v * V + l];
 #pragma unroll
   for (int i = 0; i < 3; i++) BS[i] = Bcs[3 * bi.off + (int64_t)i * V + l];
-  constexpr int NG = (NGEO_C + BRICK_Z - 1) / BRICK_Z;
-  double gv[NG];   // BRICK: this thread's share of its column's geometry
-  const int cidx = threadIdx.x & (BRICK_COLS - 1), q0 = threadIdx.x / BRICK_COLS;
+  constexpr bool BRICK = BZ > 0;
+  constexpr int Z = BRICK ? BZ : 1, COLS = 256 / Z;
+  constexpr int NG = (NGEO_C + Z - 1) / Z;
+  double gv[BRICK ? NG : 1];   // this thread's share of its column's geometry
+  const int cidx = threadIdx.x & (COLS - 1), q0 = threadIdx.x / COLS;
   if (BRICK) {
 #pragma unroll
     for (int k = 0; k < NG; k++) {
-      const int q = q0 + BRICK_Z * k;
+      const int q = q0 + Z * k;
       gv[k] = q < NGEO_C ? G.c[q * G.ncol + col] : 0.0;
     }
   } else {
@@ -637,13 +641,13 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
   if (BRICK) {
 #pragma unroll
     for (int k = 0; k < NG; k++) {
-      const int q = q0 + BRICK_Z * k;
-      if (q < NGEO_C) sgeo[q * BRICK_COLS + cidx] = gv[k];
+      const int q = q0 + Z * k;
+      if (q < NGEO_C) sgeo[q * COLS + cidx] = gv[k];
     }
     __syncthreads();
-    m = load_metric(sgeo + cidx, BRICK_COLS, 0);
-    fl[0] = sgeo[RHOFL * BRICK_COLS + cidx];
-    fl[1] = sgeo[UFL * BRICK_COLS + cidx];
+    m = load_metric(sgeo + cidx, COLS, 0);
+    fl[0] = sgeo[RHOFL * COLS + cidx];
+    fl[1] = sgeo[UFL * COLS + cidx];
   }
 
   // constrained transport of the six faces of this cell (Sec. 2.5)
@@ -691,7 +695,7 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
       double conn[20];
 #pragma unroll
       for (int j = 0; j < 20; j++)
-        conn[j] = BRICK ? sgeo[(CONN0 + 20 * h + j) * BRICK_COLS + cidx]
+        conn[j] = BRICK ? sgeo[(CONN0 + 20 * h + j) * COLS + cidx]
                         : G.c[(CONN0 + 20 * h + j) * G.ncol + col];
       if (!BRICK) __builtin_amdgcn_sched_barrier(0);
       connection_contract(T, conn, 2 * h, q);
@@ -807,33 +811,35 @@ __global__ __launch_bounds__(128) void k_stats_fold(Counters* __restrict__ cnt,
 }
 
 // fused update: conserved update, optional learned guess, inversion, floors, next dt
-// BRICK: workgroups are bricks of BRICK_COLS columns x BRICK_Z cells (every block of the
-// launch divides into them, brick_x1), with the geometry of their columns staged in LDS
+// BZ > 0: workgroups are bricks of 256/BZ columns x BZ cells (every block of the launch
+// divides into them, brick_x1), with the geometry of their columns staged in LDS
 // (conserve_cell).
-template <bool STATS, bool NEXT_DT, bool MLP, int OCC, bool BRICK>
+template <bool STATS, bool NEXT_DT, bool MLP, int OCC, int BZ>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_update(
     Launch L, const double* __restrict__ Pn, const double* __restrict__ Bn,
     const double* __restrict__ Ps, const double* __restrict__ Bcs, const double* __restrict__ F,
     const double* __restrict__ E, double dt_factor, double* __restrict__ Pout,
     double* __restrict__ Bout, double* __restrict__ dt_part, const MlpBlob* __restrict__ mlp) {
-  __shared__ double sgeo[BRICK ? NGEO_C * BRICK_COLS : 1];
+  constexpr bool BRICK = BZ > 0;
+  __shared__ double sgeo[BRICK ? NGEO_C * (256 / BZ) : 1];
   const BlockTile bt = block_tile(L);
   const BlockInfo bi = L.blk[bt.blk];
   const int g = L.ph.ng;
   Cell c;
   bool valid;
   if (BRICK) {
-    // brick (b0, b1, b2) of the tile, x1 fastest, bx x by x BRICK_Z cells (bx by =
-    // BRICK_COLS, so the thread's column in the brick is t % BRICK_COLS); valid for the
-    // whole workgroup or none
-    const int bx = brick_x1(bi.n), by = BRICK_COLS / bx;
-    const int nb0 = bi.n[0] / bx, nb1 = bi.n[1] / by, nb2 = bi.n[2] / BRICK_Z;
+    // brick (b0, b1, b2) of the tile, x1 fastest, bx x by x BZ cells (bx by = 256/BZ,
+    // so the thread's column in the brick is t % (256/BZ)); valid for the whole
+    // workgroup or none
+    constexpr int Z = BRICK ? BZ : 1, COLS = 256 / Z;
+    const int bx = brick_x1(bi.n, Z), by = COLS / bx;
+    const int nb0 = bi.n[0] / bx, nb1 = bi.n[1] / by, nb2 = bi.n[2] / Z;
     const int t = threadIdx.x;
     valid = bt.tile < nb0 * nb1 * nb2;
     const int b0 = bt.tile % nb0, r = bt.tile / nb0, b1 = r % nb1, b2 = r / nb1;
     c.I = g + b0 * bx + (t & (bx - 1));
-    c.J = g + b1 * by + ((t & (BRICK_COLS - 1)) / bx);
-    c.K = g + b2 * BRICK_Z + t / BRICK_COLS;
+    c.J = g + b1 * by + ((t & (COLS - 1)) / bx);
+    c.K = g + b2 * Z + t / COLS;
     c.loc = ((int64_t)c.K * bi.np[1] + c.J) * bi.np[0] + c.I;
   } else {
     valid = region_cell(bi, bt.tile * NT + threadIdx.x, bi.n[0], bi.n[1], bi.n[2], g, g, g, c);
@@ -847,7 +853,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   if (valid) {
     if (!BRICK) m = load_metric(L.geo.c, L.geo.ncol, col);
     double U[9];
-    conserve_cell<BRICK>(L, bi, c, m, sgeo, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, U, PS,
+    conserve_cell<BZ>(L, bi, c, m, sgeo, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, U, PS,
                          fl);
     c2p_setup(U, m, L.ph.gam, cs);
   }
@@ -876,7 +882,7 @@ __global__ __launch_bounds__(NT) void k_conserve(Launch L, const double* __restr
   const Metric m = load_metric(L.geo.c, L.geo.ncol, col);
   double U[9], PS[5], fl[2];
   Metric mc = m;
-  conserve_cell<false>(L, bi, c, mc, nullptr, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, U, PS,
+  conserve_cell<0>(L, bi, c, mc, nullptr, col, Pn, Bn, Ps, Bcs, F, E, dt_factor, Bout, U, PS,
                        fl);
   double* u = ubuf + 9 * bi.off + c.loc;
 #pragma unroll
@@ -1186,7 +1192,7 @@ static dim3 stage_grid(const Launch& L, int cls, int64_t r, Launch& Lc) {
 }
 
 void launch_bcell(const Launch& L, const double* B, double* Bc) {
-  const int64_t r = (int64_t)L.max_np[0] * L.max_np[1] * L.max_np[2];
+  const int64_t r = (int64_t)(L.max_np[0] - 1) * (L.max_np[1] - 1) * (L.max_np[2] - 1);
   Launch Lc;
   const dim3 grid = stage_grid(L, WL_BCELL, r, Lc);
   hipLaunchKernelGGL(k_bcell, grid, dim3(NT), 0, L.stream, Lc, B, Bc);
@@ -1305,11 +1311,14 @@ int64_t launch_update(const Launch& L, const double* Pn, const double* Bn, const
     return (int64_t)grid.x * grid.y;
   }
 #define GRMHD_UPD(ND, ML, V)                                                                 \
-  if (L.brick_upd)                                                                          \
-    hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], true>), grid, dim3(NT), 0, L.stream, \
+  if (L.brick_upd == 8)                                                                     \
+    hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], 8>), grid, dim3(NT), 0, L.stream,  \
+                       Lc, Pn, Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob);      \
+  else if (L.brick_upd == 4)                                                                \
+    hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], 4>), grid, dim3(NT), 0, L.stream,  \
                        Lc, Pn, Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob);      \
   else                                                                                      \
-    hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], false>), grid, dim3(NT), 0,       \
+    hipLaunchKernelGGL((k_update<true, ND, ML, UPD_OCC[V], 0>), grid, dim3(NT), 0,           \
                        L.stream, Lc, Pn, Bn, Ps, Bcs, F, E, dt_factor, Pout, Bout, dt_part, blob)
 #define GRMHD_UPD_V(ND, ML)                                               \
   switch (L.var_upd) {                                                    \
