@@ -46,9 +46,11 @@ enum { GRMHD_OK = 0, GRMHD_EINVAL = -1, GRMHD_ENOMEM = -2, GRMHD_EHIP = -3,
        GRMHD_ESTATE = -4, GRMHD_EUNSUPPORTED = -5 };
 enum { GRMHD_MINK_CART = 0, GRMHD_KS_LOGSPH = 1 };
 /* reconstruction (Sec. 2.1): piecewise linear with the monotonised-central limiter, PPM
- * (Colella & Woodward), or piecewise linear with the MINMOD limiter (Sec. 7.2's shock
- * tubes compare MINMOD and PPM) */
-enum { GRMHD_PLM_MC = 0, GRMHD_PPM = 1, GRMHD_PLM_MINMOD = 2 };
+ * (Colella & Woodward), piecewise linear with the MINMOD limiter (Sec. 7.2's shock tubes
+ * compare MINMOD and PPM), or PPM with the optional shock flattener (Colella & Woodward's
+ * flattening coefficient from the pressure jump over a cell's neighbours where the flow
+ * compresses, pulling the cell's interface values toward its mean) */
+enum { GRMHD_PLM_MC = 0, GRMHD_PPM = 1, GRMHD_PLM_MINMOD = 2, GRMHD_PPM_FLAT = 3 };
 enum { GRMHD_LLF = 0, GRMHD_HLLE = 1 };
 enum { GRMHD_BC_OUTFLOW = 0, GRMHD_BC_POLAR = 1, GRMHD_BC_PERIODIC = 2 };
 enum { GRMHD_GUESS_PLAIN = 0, GRMHD_GUESS_MLP = 1 };

@@ -18,7 +18,7 @@ _SO = os.path.join(_HERE, "liborc.so")
 _lib = None
 
 MINK, KS = 0, 1
-PLM, PPM, PLM_MINMOD = 0, 1, 2
+PLM, PPM, PLM_MINMOD, PPM_FLAT = 0, 1, 2, 3
 LLF, HLLE = 0, 1
 EMF_AVERAGE, EMF_UPWIND = 0, 1
 BC_OUTFLOW, BC_POLAR, BC_PERIODIC = 0, 1, 2
@@ -72,6 +72,10 @@ def lib():
                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_source.argtypes = [_dp, _dp, _dp, _dp, C.c_double, C.c_double, _dp, C.c_double, _dp]
         L.orc_recon_face.argtypes = [C.c_int, _dp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.orc_recon_face_flat.argtypes = [_dp, C.c_double, C.c_double, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double)]
+        L.orc_flatten.restype = C.c_double
+        L.orc_flatten.argtypes = [_dp, _dp, C.c_int]
         L.orc_cons2prim.restype = C.c_int
         L.orc_cons2prim.argtypes = [_dp, _dp, _dp, C.c_double, C.c_double, C.c_double, _dp, _dp,
                                     C.c_double, C.c_int, _dp, C.POINTER(C.c_int)]
@@ -264,6 +268,17 @@ def recon_face(recon, a6):
     r = C.c_double()
     lib().orc_recon_face(recon, np.ascontiguousarray(a6, dtype=float), C.byref(l), C.byref(r))
     return l.value, r.value
+
+
+def recon_face_flat(a6, f2, f3):
+    l = C.c_double()
+    r = C.c_double()
+    lib().orc_recon_face_flat(np.ascontiguousarray(a6, dtype=float), f2, f3, C.byref(l), C.byref(r))
+    return l.value, r.value
+
+
+def flatten(u, v, c):
+    return lib().orc_flatten(np.ascontiguousarray(u, dtype=float), np.ascontiguousarray(v, dtype=float), c)
 
 
 def cons2prim(U, gcov, gcon, gdet, alpha, gam, guess, prev=None, tol=1e-12, maxit=50):

@@ -304,6 +304,34 @@ static double ppm_face(const double* a, int c) {
   return 0.5 * (a[c] + a[c + 1]) - (dc1 - dc) / 6.0;
 }
 
+/* Shock flattening (Colella & Woodward 1984): a cell whose pressure jump over its two
+ * neighbours is strong (relative jump above FLAT_EPS) where the flow compresses (the
+ * normal velocity falls across it) gets the coefficient clip(FLAT_W2 (dp1/dp2 - FLAT_W1),
+ * 0, 1), dp1 the jump over the neighbours and dp2 over the next ones (a steep jump:
+ * dp1 close to dp2); 0 elsewhere and where dp2 vanishes.  The pressure of an ideal gas
+ * is proportional to u_g, and the criteria are ratios, so the u_g line serves. */
+#define FLAT_EPS 0.33
+#define FLAT_W1 0.75
+#define FLAT_W2 10.0
+double orc_flatten(const double* u, const double* v, int c) {
+  double dp1 = u[c + 1] - u[c - 1], dp2 = u[c + 2] - u[c - 2];
+  double pmin = u[c + 1] < u[c - 1] ? u[c + 1] : u[c - 1];
+  if (!(fabs(dp1) > FLAT_EPS * pmin) || !(v[c - 1] - v[c + 1] > 0.0) || dp2 == 0.0) return 0.0;
+  double f = FLAT_W2 * (dp1 / dp2 - FLAT_W1);
+  return f < 0.0 ? 0.0 : (f > 1.0 ? 1.0 : f);
+}
+
+/* PPM with flattening: each cell's two interface values are pulled toward its mean by
+ * its coefficient, a = f a0 + (1 - f) a, before the monotonisation */
+void orc_recon_face_flat(const double* a, double f2, double f3, double* left, double* right) {
+  double f15 = ppm_face(a, 1), f25 = ppm_face(a, 2), f35 = ppm_face(a, 3);
+  double l2, r2, l3, r3;
+  ppm_cell(a[2], f2 * a[2] + (1.0 - f2) * f15, f2 * a[2] + (1.0 - f2) * f25, &l2, &r2);
+  ppm_cell(a[3], f3 * a[3] + (1.0 - f3) * f25, f3 * a[3] + (1.0 - f3) * f35, &l3, &r3);
+  *left = r2;
+  *right = l3;
+}
+
 void orc_recon_face(int recon, const double* a, double* left, double* right) {
   if (recon == ORC_PLM) {
     *left = a[2] + 0.5 * mc_slope(a[2] - a[1], a[3] - a[2]);
@@ -815,7 +843,7 @@ static void face_flux(orc_ctx* c, const double* P, const double* bc, const doubl
   int nmax = c->np[d] - 1;
   int pos = d == 0 ? I : (d == 1 ? J : K);
   double PL[5], PR[5], BL[3], BR[3];
-  double line[6];
+  double line[8][6];
   for (int v = 0; v < 8; v++) {
     if (v >= 5 && v - 5 == d) continue;
     for (int s = 0; s < 6; s++) {
@@ -823,10 +851,20 @@ static void face_flux(orc_ctx* c, const double* P, const double* bc, const doubl
       if (p < 0) p = 0;
       if (p > nmax) p = nmax;
       size_t q = IDX(c, K + st[2] * (p - pos), J + st[1] * (p - pos), I + st[0] * (p - pos));
-      line[s] = v < 5 ? P[v * nc + q] : bc[(v - 5) * nc + q];
+      line[v][s] = v < 5 ? P[v * nc + q] : bc[(v - 5) * nc + q];
     }
+  }
+  /* flattening of the two cells next to the face from u_g and the normal utilde */
+  double f2 = 0.0, f3 = 0.0;
+  if (c->d.recon == ORC_PPM_FLAT) {
+    f2 = orc_flatten(line[1], line[2 + d], 2);
+    f3 = orc_flatten(line[1], line[2 + d], 3);
+  }
+  for (int v = 0; v < 8; v++) {
+    if (v >= 5 && v - 5 == d) continue;
     double l, r;
-    orc_recon_face(c->d.recon, line, &l, &r);
+    if (c->d.recon == ORC_PPM_FLAT) orc_recon_face_flat(line[v], f2, f3, &l, &r);
+    else orc_recon_face(c->d.recon, line[v], &l, &r);
     if (v < 5) { PL[v] = l; PR[v] = r; }
     else { BL[v - 5] = l; BR[v - 5] = r; }
   }

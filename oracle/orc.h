@@ -34,8 +34,9 @@ extern "C" {
 
 enum { ORC_MINK = 0, ORC_KS = 1 };
 /* reconstruction (Sec. 2.1): piecewise linear with the monotonised-central limiter,
- * PPM, or piecewise linear with the MINMOD limiter (the shock tubes of Sec. 7.2) */
-enum { ORC_PLM = 0, ORC_PPM = 1, ORC_PLM_MINMOD = 2 };
+ * PPM, piecewise linear with the MINMOD limiter (the shock tubes of Sec. 7.2), or PPM
+ * with the optional shock flattener (Sec. 2.1; Colella & Woodward 1984) */
+enum { ORC_PLM = 0, ORC_PPM = 1, ORC_PLM_MINMOD = 2, ORC_PPM_FLAT = 3 };
 enum { ORC_LLF = 0, ORC_HLLE = 1 };
 /* edge EMFs: the average of the four neighbouring face fluxes of B (Sec. 2.5), or that
  * average corrected by the upwinded gradients of Gardiner & Stone (2005), which the
@@ -84,6 +85,11 @@ void orc_source(const double* P, const double* Bcon, const double* gcov,
 /* face states for one face from a 1D line of 6 cell values a[0..5], the face lying
  * between a[2] and a[3]. */
 void orc_recon_face(int recon, const double* a6, double* left, double* right);
+/* PPM face states with the cells next to the face flattened by f2 (cell a6[2]) and f3
+ * (cell a6[3]); orc_flatten gives the coefficient of cell c of a line from the u_g and
+ * normal-velocity lines (c - 2 .. c + 2 must lie in them) */
+void orc_recon_face_flat(const double* a6, double f2, double f3, double* left, double* right);
+double orc_flatten(const double* u, const double* v, int c);
 
 /* inversion of one cell.  U9 carries sqrt(-g); geometry as above.  guess5 is the
  * first guess, prev5 the plain guess (previous primitives).  Returns the tier. */

@@ -222,10 +222,31 @@ __device__ __forceinline__ void ppm_limit(double a0, double& l, double& r) {
   }
 }
 
-// face states of the face between s[2] and s[3] from the six-cell line s[0..5]
+// Shock flattening (Colella & Woodward 1984) of the cell at line index c (c - 2 .. c + 2
+// inside the lines): the u_g line u stands for the pressure (an ideal gas, ratios only),
+// v is the normal velocity.  Where the jump over the neighbours exceeds 0.33 of the lower
+// neighbour's value and the flow compresses, clip(10 (dp1/dp2 - 0.75), 0, 1) with dp1
+// the jump over the neighbours and dp2 over the next ones; 0 elsewhere and where dp2
+// vanishes
+__device__ __forceinline__ double flatten_coef(const double* u, const double* v, int c) {
+  const double dp1 = u[c + 1] - u[c - 1], dp2 = u[c + 2] - u[c - 2];
+  const double pmin = fmin(u[c + 1], u[c - 1]);
+  if (!(fabs(dp1) > 0.33 * pmin) || !(v[c - 1] - v[c + 1] > 0.0) || dp2 == 0.0) return 0.0;
+  return fmin(1.0, fmax(0.0, 10.0 * (dp1 / dp2 - 0.75)));
+}
+
+// a cell's interface values pulled toward its mean by its flattening coefficient f
+__device__ __forceinline__ void flatten_cell(double a0, double f, double& l, double& r) {
+  l = f * a0 + (1.0 - f) * l;
+  r = f * a0 + (1.0 - f) * r;
+}
+
+// face states of the face between s[2] and s[3] from the six-cell line s[0..5]; RECON 3
+// (PPM with flattening) takes the flattening coefficients fl[0], fl[1] of s[2], s[3]
 template <int RECON>
-__device__ __forceinline__ void recon_face(const double s[6], double& left, double& right) {
-  if (RECON != 1) {
+__device__ __forceinline__ void recon_face(const double s[6], double& left, double& right,
+                                           const double* fl = nullptr) {
+  if (RECON == 0 || RECON == 2) {
     left = s[2] + 0.5 * plm_lim<RECON>(s[2] - s[1], s[3] - s[2]);
     right = s[3] - 0.5 * plm_lim<RECON>(s[3] - s[2], s[4] - s[3]);
   } else {
@@ -238,6 +259,10 @@ __device__ __forceinline__ void recon_face(const double s[6], double& left, doub
     const double f25 = 0.5 * (s[2] + s[3]) - (d3 - d2) * sixth;
     const double f35 = 0.5 * (s[3] + s[4]) - (d4 - d3) * sixth;
     double l2 = f15, r2 = f25, l3 = f25, r3 = f35;
+    if (RECON == 3) {
+      flatten_cell(s[2], fl[0], l2, r2);
+      flatten_cell(s[3], fl[1], l3, r3);
+    }
     ppm_limit(s[2], l2, r2);
     ppm_limit(s[3], l3, r3);
     left = r2;
@@ -250,8 +275,8 @@ __device__ __forceinline__ void recon_face(const double s[6], double& left, doub
 // slopes, interface values and limited parabola of the shared cells computed once
 template <int RECON>
 __device__ __forceinline__ void recon_pair(const double s[7], double& l0, double& r0, double& l1,
-                                           double& r1) {
-  if (RECON != 1) {
+                                           double& r1, const double* fl = nullptr) {
+  if (RECON == 0 || RECON == 2) {
     const double d2 = plm_lim<RECON>(s[2] - s[1], s[3] - s[2]);
     const double d3 = plm_lim<RECON>(s[3] - s[2], s[4] - s[3]);
     const double d4 = plm_lim<RECON>(s[4] - s[3], s[5] - s[4]);
@@ -271,6 +296,11 @@ __device__ __forceinline__ void recon_pair(const double s[7], double& l0, double
     const double f35 = 0.5 * (s[3] + s[4]) - (d4 - d3) * sixth;
     const double f45 = 0.5 * (s[4] + s[5]) - (d5 - d4) * sixth;
     double l2 = f15, r2 = f25, l3 = f25, r3 = f35, l4 = f35, r4 = f45;
+    if (RECON == 3) {
+      flatten_cell(s[2], fl[0], l2, r2);
+      flatten_cell(s[3], fl[1], l3, r3);
+      flatten_cell(s[4], fl[2], l4, r4);
+    }
     ppm_limit(s[2], l2, r2);
     ppm_limit(s[3], l3, r3);
     ppm_limit(s[4], l4, r4);

@@ -273,9 +273,9 @@ int validate(const grmhd_grid_desc* d) {
   if (d->coords != GRMHD_MINK_CART && d->coords != GRMHD_KS_LOGSPH)
     return fail(GRMHD_EINVAL, "unknown coords");
   if (d->n_ghost < 2 || d->n_ghost > 4) return fail(GRMHD_EINVAL, "n_ghost must be 2..4");
-  if (d->recon == GRMHD_PPM && d->n_ghost < 3) return fail(GRMHD_EINVAL, "PPM needs n_ghost >= 3");
-  if (d->recon != GRMHD_PLM_MC && d->recon != GRMHD_PPM && d->recon != GRMHD_PLM_MINMOD)
-    return fail(GRMHD_EINVAL, "unknown recon");
+  if ((d->recon == GRMHD_PPM || d->recon == GRMHD_PPM_FLAT) && d->n_ghost < 3)
+    return fail(GRMHD_EINVAL, "PPM needs n_ghost >= 3");
+  if (d->recon < GRMHD_PLM_MC || d->recon > GRMHD_PPM_FLAT) return fail(GRMHD_EINVAL, "unknown recon");
   if (d->riemann != GRMHD_LLF && d->riemann != GRMHD_HLLE) return fail(GRMHD_EINVAL, "unknown riemann");
   if (d->n_blocks < 1 || !d->blocks) return fail(GRMHD_EINVAL, "no blocks");
   if (d->n_lat_levels < 1 || d->n_lat_levels > 8) return fail(GRMHD_EINVAL, "n_lat_levels must be 1..8");

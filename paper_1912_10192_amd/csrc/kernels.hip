@@ -231,7 +231,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   double* out = F + 24 * bi.off + (int64_t)(DIR - 1) * 8 * V + c.loc;
   constexpr int t1 = DIR == 1 ? 1 : 0;   // transverse field components (0-based)
   constexpr int t2 = DIR == 3 ? 1 : 2;
-  constexpr int k0 = RECON != 1 ? 1 : 0, k1 = RECON != 1 ? 5 : 6;   // stencil used
+  constexpr bool PLM = RECON == 0 || RECON == 2;
+  constexpr int k0 = PLM ? 1 : 0, k1 = PLM ? 5 : 6;   // stencil used
   double sp[5][6], sb[2][6];
   const double* p = P + 5 * bi.off + c.loc;
   const double* bc = Bc + 3 * bi.off + c.loc;
@@ -251,10 +252,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
     return;
   }
   double PL[5], PR[5], BL[3], BR[3];
+  double fl[2] = {0.0, 0.0};   // flattening of the two cells next to the face
+  if (RECON == 3) {
+    fl[0] = flatten_coef(sp[1], sp[1 + DIR], 2);
+    fl[1] = flatten_coef(sp[1], sp[1 + DIR], 3);
+  }
 #pragma unroll
-  for (int v = 0; v < 5; v++) recon_face<RECON>(sp[v], PL[v], PR[v]);
-  recon_face<RECON>(sb[0], BL[t1], BR[t1]);
-  recon_face<RECON>(sb[1], BL[t2], BR[t2]);
+  for (int v = 0; v < 5; v++) recon_face<RECON>(sp[v], PL[v], PR[v], fl);
+  recon_face<RECON>(sb[0], BL[t1], BR[t1], fl);
+  recon_face<RECON>(sb[1], BL[t2], BR[t2], fl);
   const double bn = bface * rcp_nr(m.gdet);
   BL[DIR - 1] = bn;
   BR[DIR - 1] = bn;
@@ -291,7 +297,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   double* out = F + 24 * bi.off + (int64_t)(DIR - 1) * 8 * V + loc;
   constexpr int t1 = DIR == 1 ? 1 : 0;
   constexpr int t2 = DIR == 3 ? 1 : 2;
-  constexpr int k0 = RECON != 1 ? 1 : 0, k1 = RECON != 1 ? 6 : 7;   // stencil used
+  constexpr bool PLM = RECON == 0 || RECON == 2;
+  constexpr int k0 = PLM ? 1 : 0, k1 = PLM ? 6 : 7;   // stencil used
   double sp[5][7], sb[2][7];
   const double* p = P + 5 * bi.off + loc;
   const double* bc = Bc + 3 * bi.off + loc;
@@ -307,10 +314,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   const double bface0 = bf[0], bface1 = bf[st];
   __builtin_amdgcn_sched_barrier(0);
   double PL0[5], PR0[5], PL1[5], PR1[5], BL0[3], BR0[3], BL1[3], BR1[3];
+  double fl[3] = {0.0, 0.0, 0.0};   // flattening of the cells s[2], s[3], s[4]
+  if (RECON == 3) {
 #pragma unroll
-  for (int v = 0; v < 5; v++) recon_pair<RECON>(sp[v], PL0[v], PR0[v], PL1[v], PR1[v]);
-  recon_pair<RECON>(sb[0], BL0[t1], BR0[t1], BL1[t1], BR1[t1]);
-  recon_pair<RECON>(sb[1], BL0[t2], BR0[t2], BL1[t2], BR1[t2]);
+    for (int q = 0; q < 3; q++) fl[q] = flatten_coef(sp[1], sp[1 + DIR], 2 + q);
+  }
+#pragma unroll
+  for (int v = 0; v < 5; v++) recon_pair<RECON>(sp[v], PL0[v], PR0[v], PL1[v], PR1[v], fl);
+  recon_pair<RECON>(sb[0], BL0[t1], BR0[t1], BL1[t1], BR1[t1], fl);
+  recon_pair<RECON>(sb[1], BL0[t2], BR0[t2], BL1[t2], BR1[t2], fl);
   const double gam = L.ph.gam;
   // The second face's states wait in LDS while the first face's physics runs, so the
   // registers hold one face's physics at a time (the compiler barrier keeps it from
@@ -1230,6 +1242,10 @@ static void flux_dir(const Launch& L, int recon, int riemann, const double* P, c
     GRMHD_FLUX_V(2, 0);
   } else if (recon == 2) {
     GRMHD_FLUX_V(2, 1);
+  } else if (recon == 3 && riemann == 0) {
+    GRMHD_FLUX_V(3, 0);
+  } else if (recon == 3) {
+    GRMHD_FLUX_V(3, 1);
   } else if (riemann == 0) {
     GRMHD_FLUX_V(1, 0);
   } else {

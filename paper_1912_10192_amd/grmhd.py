@@ -18,7 +18,7 @@ _lib = None
 ABI_VERSION = 3
 OK, EINVAL, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MINK_CART, KS_LOGSPH = 0, 1
-PLM_MC, PPM, PLM_MINMOD = 0, 1, 2
+PLM_MC, PPM, PLM_MINMOD, PPM_FLAT = 0, 1, 2, 3
 LLF, HLLE = 0, 1
 BC_OUTFLOW, BC_POLAR, BC_PERIODIC = 0, 1, 2
 GUESS_PLAIN, GUESS_MLP = 0, 1

@@ -1,13 +1,14 @@
-"""GPU parity on the validation workloads of Sec. 7.2 and 7.3 and on the MINMOD limiter:
-1D relativistic shock tubes on a Cartesian Minkowski grid (the exact-solution problems of
-the oracle's own test, and seeded magnetised Riemann problems with all three field and
-velocity components), with MINMOD and PPM reconstruction, split into blocks along x1;
-the torus with MINMOD; and the off-centre spherical explosion through the polar axis,
-hydrodynamic and magnetised, on uniform blocks and on coarse polar caps with time
-levels.  Same bar as every trajectory test.  At strong shocks the limiters' switches turn
-rounding-level differences (the kernels' reciprocals against the oracle's divisions)
-into differences that grow about tenfold every five steps on the colliding streams with
-PPM, so trajectories here run 25-30 steps."""
+"""GPU parity on the validation workloads of Sec. 7.2 and 7.3, on the MINMOD limiter and
+on PPM with the shock flattener: 1D relativistic shock tubes on a Cartesian Minkowski
+grid (the exact-solution problems of the oracle's own test, and seeded magnetised Riemann
+problems with all three field and velocity components), with MINMOD, PPM and flattened
+PPM reconstruction, split into blocks along x1; the torus with MINMOD and with the
+flattener; and the off-centre spherical explosion through the polar axis, hydrodynamic
+and magnetised, on uniform blocks and on coarse polar caps with time levels.  Same bar
+as every trajectory test.  At strong shocks the limiters' switches turn rounding-level
+differences (the kernels' reciprocals against the oracle's divisions) into differences
+that grow about tenfold every five steps on the colliding streams with PPM, so
+trajectories here run 25-30 steps."""
 import sys
 
 import numpy as np
@@ -27,7 +28,7 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-@pytest.mark.parametrize("recon", [oracle.PLM_MINMOD, oracle.PPM])
+@pytest.mark.parametrize("recon", [oracle.PLM_MINMOD, oracle.PPM, oracle.PPM_FLAT])
 @pytest.mark.parametrize("name", list(PROBLEMS))
 def test_hydro_shock_tube_matches_oracle(name, recon):
     N = 256
@@ -51,7 +52,8 @@ def _random_riemann(seed):
 
 
 @pytest.mark.parametrize("seed,recon,riemann", [(1, oracle.PLM_MINMOD, 1), (2, oracle.PPM, 1),
-                                                 (3, oracle.PLM_MINMOD, 0), (4, oracle.PPM, 0)])
+                                                 (3, oracle.PLM_MINMOD, 0), (4, oracle.PPM, 0),
+                                                 (5, oracle.PPM_FLAT, 1), (6, oracle.PPM_FLAT, 0)])
 def test_magnetised_riemann_problem_matches_oracle(seed, recon, riemann):
     N = 192
     left, right, bl, br = _random_riemann(seed)
@@ -61,8 +63,9 @@ def test_magnetised_riemann_problem_matches_oracle(seed, recon, riemann):
     check_trajectory(cfg, tube_state(N, left, right, bl, br), 25)
 
 
-def test_torus_with_minmod_matches_oracle():
-    cfg = dict(configs.TORUS_TINY, recon=oracle.PLM_MINMOD, block=(32, 32, 32))
+@pytest.mark.parametrize("recon", [oracle.PLM_MINMOD, oracle.PPM_FLAT])
+def test_torus_with_minmod_or_flattener_matches_oracle(recon):
+    cfg = dict(configs.TORUS_TINY, recon=recon, ng=3, block=(32, 32, 32))
     state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
     grid, _ = check_trajectory(cfg, state, 4)
     a, r = grid.divb()
