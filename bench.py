@@ -17,6 +17,7 @@ resident in HBM before the timed region.  Paths timed on the same initial state:
                     paper's launch structure), plain guess
   global_dt         the same blocks on one global time step, batched launches
   emf_upwind        the headline path with Gardiner & Stone's upwinded edge EMFs
+  floor_drift       the headline path with the floors in the drift frame
   disk5             the large tilted thin disk (effective 1024x384x384, density-refined,
                     five time levels), batched launches + learned guess
 The headline value is real zone-cycles/s (cells x their own steps / wall time), the
@@ -398,6 +399,8 @@ def main():
                            args.runs, sync, log, variants=tune)
         upw, _ = run_leg("emf_upwind", dict(cfg, emf=1), blocks, bs, 1, blob, args.steps,
                          args.warmup, args.runs, sync, log, variants=tune)
+        drift, _ = run_leg("floor_drift", dict(cfg, floor_frame=1), blocks, bs, 1, blob,
+                           args.steps, args.warmup, args.runs, sync, log, variants=tune)
         flat = [dict(b, lat=0) for b in blocks]
         gsteps = args.steps * head["substeps_per_cycle"]
         glob, _ = run_leg("global_dt", cfg, flat, bs, 2, None, gsteps, args.warmup, args.runs,
@@ -410,6 +413,8 @@ def main():
             "batched": batched, "plain": plain, "global_dt": glob, "disk5": disk,
             "emf_upwind": upw,
             "emf_upwind_cost": head["value_real"] / upw["value_real"],
+            "floor_drift": drift,
+            "floor_drift_cost": head["value_real"] / drift["value_real"],
             "speedup_vs_plain": head["value_real"] / plain["value_real"],
             "batching_gain": batched["value_real"] / plain["value_real"],
             "learned_gain": head["value_real"] / batched["value_real"],

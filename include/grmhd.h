@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define GRMHD_ABI_VERSION 3
+#define GRMHD_ABI_VERSION 4
 
 enum { GRMHD_OK = 0, GRMHD_EINVAL = -1, GRMHD_ENOMEM = -2, GRMHD_EHIP = -3,
        GRMHD_ESTATE = -4, GRMHD_EUNSUPPORTED = -5 };
@@ -62,6 +62,13 @@ enum { GRMHD_GUESS_PLAIN = 0, GRMHD_GUESS_MLP = 1 };
  * conserved density sqrt(-g) rho u^t of the edge's cells counts as zero and takes the
  * mean of both sides) */
 enum { GRMHD_EMF_AVERAGE = 0, GRMHD_EMF_UPWIND = 1 };
+/* floors (Sec. 2.7): after the Lorentz-factor ceiling, raise rho and u_g to their minima
+ * at fixed utilde, or add the missing mass and internal energy as a parcel moving with
+ * the drift frame of the field (Ressler et al. 2017; the paper's choice): u_D = g (u +
+ * beta b), beta = -b^t / (b^2 u^t), the summed conserved state inverted from the cell's
+ * primitives (cells whose inversion needs the entropy or keep-previous tier fall back to
+ * the fixed-utilde floors, which also restore the minima after rounding) */
+enum { GRMHD_FLOOR_FIXED = 0, GRMHD_FLOOR_DRIFT = 1 };
 
 /* One block of the grid (Sec. 3.3 block structure; Sec. 3.4 coarsening toward the
  * poles is refinement in some dimensions only).  The effective grid n_eff is the grid
@@ -117,6 +124,7 @@ typedef struct {
                                  batched launches without the graph */
   int32_t profile;            /* 1 = time each kernel class with HIP events on the stream */
   int32_t emf;                /* GRMHD_EMF_AVERAGE or GRMHD_EMF_UPWIND */
+  int32_t floor_frame;        /* GRMHD_FLOOR_FIXED or GRMHD_FLOOR_DRIFT */
 } grmhd_grid_desc;
 
 typedef struct {

@@ -21,6 +21,7 @@ MINK, KS = 0, 1
 PLM, PPM, PLM_MINMOD, PPM_FLAT = 0, 1, 2, 3
 LLF, HLLE = 0, 1
 EMF_AVERAGE, EMF_UPWIND = 0, 1
+FLOOR_FIXED, FLOOR_DRIFT = 0, 1
 BC_OUTFLOW, BC_POLAR, BC_PERIODIC = 0, 1, 2
 
 
@@ -42,7 +43,8 @@ class Desc(C.Structure):
                 ("xlo", C.c_double * 3), ("xhi", C.c_double * 3), ("courant", C.c_double),
                 ("rho_fl_c", C.c_double), ("rho_fl_p", C.c_double), ("u_fl_c", C.c_double),
                 ("u_fl_p", C.c_double), ("bsq_rho_max", C.c_double), ("bsq_u_max", C.c_double),
-                ("gamma_max", C.c_double), ("tol", C.c_double), ("emf", C.c_int32)]
+                ("gamma_max", C.c_double), ("tol", C.c_double), ("emf", C.c_int32),
+                ("floor_frame", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -74,6 +76,8 @@ def lib():
         L.orc_recon_face.argtypes = [C.c_int, _dp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.orc_recon_face_flat.argtypes = [_dp, C.c_double, C.c_double, C.POINTER(C.c_double),
                                           C.POINTER(C.c_double)]
+        L.orc_floors.restype = C.c_int
+        L.orc_floors.argtypes = [C.c_int, _dp, _dp, _dp, _dp] + [C.c_double] * 9 + [C.c_int]
         L.orc_flatten.restype = C.c_double
         L.orc_flatten.argtypes = [_dp, _dp, C.c_int]
         L.orc_cons2prim.restype = C.c_int
@@ -134,6 +138,7 @@ def make_desc(cfg: dict) -> Desc:
     d.gamma_max = cfg.get("gamma_max", 1e150)
     d.tol = cfg.get("tol", 1e-12)
     d.emf = cfg.get("emf", EMF_AVERAGE)
+    d.floor_frame = cfg.get("floor_frame", FLOOR_FIXED)
     return d
 
 
@@ -275,6 +280,17 @@ def recon_face_flat(a6, f2, f3):
     r = C.c_double()
     lib().orc_recon_face_flat(np.ascontiguousarray(a6, dtype=float), f2, f3, C.byref(l), C.byref(r))
     return l.value, r.value
+
+
+def floors(frame, P, Bcon, gcov, gcon, gdet, alpha, gam, rho_fl, u_fl, bsq_rho_max=50.0,
+           bsq_u_max=750.0, gamma_max=50.0, tol=1e-12, maxit=50):
+    """one cell's floors as the update applies them; returns (new primitives, limits)"""
+    P = np.array(P, dtype=float)
+    hits = lib().orc_floors(frame, P, np.ascontiguousarray(Bcon, dtype=float),
+                            np.ascontiguousarray(gcov, dtype=float).ravel(),
+                            np.ascontiguousarray(gcon, dtype=float).ravel(), gdet, alpha, gam,
+                            rho_fl, u_fl, bsq_rho_max, bsq_u_max, gamma_max, tol, maxit)
+    return P, hits
 
 
 def flatten(u, v, c):

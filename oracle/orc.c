@@ -894,13 +894,15 @@ static void face_flux(orc_ctx* c, const double* P, const double* bc, const doubl
   F[5 + d] = 0.0;
 }
 
-static int apply_floors(const orc_ctx* c, double* P, const double* Bcon, const double* gcov,
-                        const double* gcon, double alpha, size_t col) {
+/* Floors at fixed utilde (Sec. 2.7): Lorentz-factor ceiling, then rho >= max(rho_fl,
+ * b^2/bsq_rho_max) and u >= max(u_fl, b^2/bsq_u_max) */
+static int floors_fixed(double* P, const double* Bcon, const double* gcov, const double* gcon,
+                        double alpha, double rho_fl, double u_fl, double bsq_rho_max,
+                        double bsq_u_max, double gmax) {
   int hits = 0;
   double qsq = 0.0;
   for (int i = 0; i < 3; i++)
     for (int j = 0; j < 3; j++) qsq += gcov[(i + 1) * 4 + j + 1] * P[U1 + i] * P[U1 + j];
-  double gmax = c->d.gamma_max;
   if (1.0 + qsq > gmax * gmax) {
     double f = sqrt((gmax * gmax - 1.0) / qsq);
     for (int i = 0; i < 3; i++) P[U1 + i] *= f;
@@ -908,11 +910,92 @@ static int apply_floors(const orc_ctx* c, double* P, const double* Bcon, const d
   }
   ostate s;
   get_state(P, Bcon, gcov, gcon, alpha, &s);
-  double rmin = fmax(c->rho_fl[col], s.bsq / c->d.bsq_rho_max);
-  double umin = fmax(c->u_fl[col], s.bsq / c->d.bsq_u_max);
+  double rmin = fmax(rho_fl, s.bsq / bsq_rho_max);
+  double umin = fmax(u_fl, s.bsq / bsq_u_max);
   if (P[RHO] < rmin) { P[RHO] = rmin; hits++; }
   if (P[UU] < umin) { P[UU] = umin; hits++; }
   return hits;
+}
+
+/* Floors in the drift frame (Sec. 2.7, Ressler et al. 2017).  After the Lorentz-factor
+ * ceiling, the missing mass drho = rmin - rho and internal energy du = umin - u (where
+ * positive) are added as a parcel of gas moving with the drift frame of the field,
+ * u_D = g (u + beta b) with beta = -b^t / (b^2 u^t): the fluid four-velocity with its
+ * motion along the field removed, so the field lines feel no drag and the gas no kick
+ * along them.  (The parcel carries no field; g normalises u_D, with beta^2 b^2 capped at
+ * 1 - 1/gamma_max^2.)  The summed conserved state U(P) + U(parcel) is inverted from the
+ * previous primitives; the conserved entropy keeps the cell's specific value.  An
+ * inversion that needs the entropy or keep-previous tier leaves the cell to the fixed-
+ * utilde floors, which then apply in every case as the last guarantee of the minima. */
+static int floors_drift(double* P, const double* Bcon, const double* gcov, const double* gcon,
+                        double gdet, double alpha, double gam, double rho_fl, double u_fl,
+                        double bsq_rho_max, double bsq_u_max, double gmax, double tol,
+                        int maxit) {
+  int hits = 0;
+  double qsq = 0.0;
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) qsq += gcov[(i + 1) * 4 + j + 1] * P[U1 + i] * P[U1 + j];
+  if (1.0 + qsq > gmax * gmax) {
+    double f = sqrt((gmax * gmax - 1.0) / qsq);
+    for (int i = 0; i < 3; i++) P[U1 + i] *= f;
+    hits++;
+  }
+  ostate s;
+  get_state(P, Bcon, gcov, gcon, alpha, &s);
+  double rmin = fmax(rho_fl, s.bsq / bsq_rho_max);
+  double umin = fmax(u_fl, s.bsq / bsq_u_max);
+  double drho = fmax(rmin - P[RHO], 0.0), du = fmax(umin - P[UU], 0.0);
+  if (drho > 0.0 || du > 0.0) {
+    double ud[4];
+    if (s.bsq > 0.0) {
+      double bp = -s.bcon[0] / (s.bsq * s.ucon[0]);
+      double b2 = fmin(bp * bp * s.bsq, 1.0 - 1.0 / (gmax * gmax));
+      double g = 1.0 / sqrt(1.0 - b2);
+      for (int m = 0; m < 4; m++) ud[m] = g * (s.ucon[m] + bp * s.bcon[m]);
+    } else {
+      for (int m = 0; m < 4; m++) ud[m] = s.ucon[m];
+    }
+    /* the parcel's primitives: utilde^i = u^i + u^t beta^i, beta^i = alpha^2 g^{ti} */
+    double Pp[5] = {drho, du, 0.0, 0.0, 0.0}, B0[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 3; i++) Pp[U1 + i] = ud[i + 1] + ud[0] * alpha * alpha * gcon[i + 1];
+    double U[9], Up[9], Un[9];
+    orc_prim_to_flux(P, Bcon, gcov, gcon, gdet, alpha, gam, 0, U);
+    orc_prim_to_flux(Pp, B0, gcov, gcon, gdet, alpha, gam, 0, Up);
+    for (int q = 0; q < 8; q++) Un[q] = U[q] + Up[q];
+    Un[8] = U[8] / U[0] * Un[0];
+    double Pn[5];
+    int it = 0;
+    int tier = orc_cons2prim(Un, gcov, gcon, gdet, alpha, gam, P, P, tol, maxit, Pn, &it);
+    if (tier <= 2) {
+      for (int v = 0; v < 5; v++) P[v] = Pn[v];
+      /* the minima again at fixed utilde (rounding of the inversion), counted with the
+       * injection */
+      floors_fixed(P, Bcon, gcov, gcon, alpha, rho_fl, u_fl, bsq_rho_max, bsq_u_max, gmax);
+      return hits + (drho > 0.0) + (du > 0.0);
+    }
+    /* an inversion that needs the entropy or keep-previous tier: fixed-utilde floors */
+    return hits + floors_fixed(P, Bcon, gcov, gcon, alpha, rho_fl, u_fl, bsq_rho_max, bsq_u_max,
+                               gmax);
+  }
+  return hits;
+}
+
+int orc_floors(int floor_frame, double* P, const double* Bcon, const double* gcov,
+               const double* gcon, double gdet, double alpha, double gam, double rho_fl,
+               double u_fl, double bsq_rho_max, double bsq_u_max, double gamma_max, double tol,
+               int maxit) {
+  if (floor_frame == ORC_FLOOR_DRIFT)
+    return floors_drift(P, Bcon, gcov, gcon, gdet, alpha, gam, rho_fl, u_fl, bsq_rho_max,
+                        bsq_u_max, gamma_max, tol, maxit);
+  return floors_fixed(P, Bcon, gcov, gcon, alpha, rho_fl, u_fl, bsq_rho_max, bsq_u_max,
+                      gamma_max);
+}
+
+static int apply_floors(const orc_ctx* c, double* P, const double* Bcon, const double* gcov,
+                        const double* gcon, double gdet, double alpha, size_t col) {
+  return orc_floors(c->d.floor_frame, P, Bcon, gcov, gcon, gdet, alpha, c->d.gam, c->rho_fl[col],
+                    c->u_fl[col], c->d.bsq_rho_max, c->d.bsq_u_max, c->d.gamma_max, c->d.tol,
+                    c->d.maxit);
 }
 
 #define FL(d, q, K, J, I) c->flux[((size_t)(d) * 9 + (q)) * nc + IDX(c, K, J, I)]
@@ -1110,7 +1193,7 @@ void orc_stage_apply(orc_ctx* c, const double* Pn, const double* Bn, const doubl
         int tier = orc_cons2prim(U, gcov, gcon, gdet, alpha, c->d.gam, PS, PS, c->d.tol,
                                  c->d.maxit, Pnew, &it);
         for (int i = 0; i < 3; i++) Bnew[i] = U[5 + i] / gdet;
-        int hits = apply_floors(c, Pnew, Bnew, gcov, gcon, alpha, col);
+        int hits = apply_floors(c, Pnew, Bnew, gcov, gcon, gdet, alpha, col);
         for (int v = 0; v < 5; v++) Pout[v * nc + id] = Pnew[v];
         if (st) {
           st->tier[tier]++;
@@ -1228,7 +1311,7 @@ int orc_reinvert(orc_ctx* c, double* P, const double* Bold, const double* Bnew, 
   int tier = orc_cons2prim(U, gcov, gcon, gdet, alpha, c->d.gam, P0, P0, c->d.tol, c->d.maxit,
                            Pnew, &it);
   for (int i = 0; i < 3; i++) Bn[i] = U[5 + i] / gdet;
-  int hits = apply_floors(c, Pnew, Bn, gcov, gcon, alpha, col);
+  int hits = apply_floors(c, Pnew, Bn, gcov, gcon, gdet, alpha, col);
   for (int v = 0; v < 5; v++) P[v * nc + id] = Pnew[v];
   if (st) {
     st->tier[tier]++;

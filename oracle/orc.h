@@ -43,6 +43,10 @@ enum { ORC_LLF = 0, ORC_HLLE = 1 };
  * paper applies by default (Sec. 2.5, Fig. 1) */
 enum { ORC_EMF_AVERAGE = 0, ORC_EMF_UPWIND = 1 };
 enum { ORC_BC_OUTFLOW = 0, ORC_BC_POLAR = 1, ORC_BC_PERIODIC = 2 };
+/* floors (Sec. 2.7): raise rho and u_g at fixed utilde, or inject the missing mass and
+ * internal energy as a parcel moving with the drift frame of the field (Ressler et al.
+ * 2017), which the paper uses, then invert the summed conserved state */
+enum { ORC_FLOOR_FIXED = 0, ORC_FLOOR_DRIFT = 1 };
 
 typedef struct {
   int32_t coords, n[3], ng, recon, riemann, bc[6], maxit, guess_mode;
@@ -52,6 +56,7 @@ typedef struct {
   double rho_fl_c, rho_fl_p, u_fl_c, u_fl_p, bsq_rho_max, bsq_u_max, gamma_max;
   double tol;
   int32_t emf;   /* ORC_EMF_AVERAGE or ORC_EMF_UPWIND */
+  int32_t floor_frame;   /* ORC_FLOOR_FIXED or ORC_FLOOR_DRIFT */
 } orc_desc;
 
 typedef struct {
@@ -90,6 +95,13 @@ void orc_recon_face(int recon, const double* a6, double* left, double* right);
  * normal-velocity lines (c - 2 .. c + 2 must lie in them) */
 void orc_recon_face_flat(const double* a6, double f2, double f3, double* left, double* right);
 double orc_flatten(const double* u, const double* v, int c);
+/* floors of one cell's primitives P5 (in place) with the cell field Bcon3 and the floor
+ * values rho_fl, u_fl, as the update applies them for floor_frame; returns the limits
+ * applied */
+int orc_floors(int floor_frame, double* P5, const double* Bcon3, const double* gcov,
+               const double* gcon, double gdet, double alpha, double gam, double rho_fl,
+               double u_fl, double bsq_rho_max, double bsq_u_max, double gamma_max, double tol,
+               int maxit);
 
 /* inversion of one cell.  U9 carries sqrt(-g); geometry as above.  guess5 is the
  * first guess, prev5 the plain guess (previous primitives).  Returns the tier. */

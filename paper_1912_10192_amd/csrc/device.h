@@ -625,4 +625,71 @@ __device__ __forceinline__ int apply_floors(double P[5], const double B[3], cons
   return hits;
 }
 
+// Floors in the drift frame (Sec. 2.7, Ressler et al. 2017): after the Lorentz-factor
+// ceiling, the missing mass and internal energy (drho = rmin - rho, du = umin - u where
+// positive) are added as a parcel moving with the field's drift frame u_D = g (u + beta
+// b), beta = -b^t / (b^2 u^t) (the fluid four-velocity with its motion along the field
+// removed; beta^2 b^2 capped at 1 - 1/gamma_max^2), carrying no field.  The summed
+// conserved state U(P) + U(parcel), with the cell's specific entropy, is inverted from P;
+// the fixed-utilde floors then restore the minima after rounding (not counted), or act
+// alone where that inversion needs the entropy or keep-previous tier.
+__device__ __forceinline__ int drift_floors(double P[5], const double B[3], const Metric& m,
+                                         double rho_fl, double u_fl, double bsq_rho_max,
+                                         double bsq_u_max, double gamma_max, double gam,
+                                         double tol, int maxit) {
+  int hits = 0;
+  const double qsq = m.g11 * P[2] * P[2] + 2.0 * m.g13 * P[2] * P[4] + m.g22 * P[3] * P[3] +
+                     m.g33 * P[4] * P[4];
+  if (1.0 + qsq > gamma_max * gamma_max) {
+    const double f = sqrt((gamma_max * gamma_max - 1.0) / qsq);
+    P[2] *= f;
+    P[3] *= f;
+    P[4] *= f;
+    hits++;
+  }
+  Fluid fl;
+  fluid_state(P, B, m, fl);
+  const double rmin = fmax(rho_fl, fl.bsq / bsq_rho_max);
+  const double umin = fmax(u_fl, fl.bsq / bsq_u_max);
+  const double drho = fmax(rmin - P[0], 0.0), du = fmax(umin - P[1], 0.0);
+  if (!(drho > 0.0 || du > 0.0)) return hits;
+  double ud[4];
+  if (fl.bsq > 0.0) {
+    const double bp = -fl.bcon[0] / (fl.bsq * fl.ucon[0]);
+    const double b2 = fmin(bp * bp * fl.bsq, 1.0 - 1.0 / (gamma_max * gamma_max));
+    const double g = 1.0 / sqrt(1.0 - b2);
+#pragma unroll
+    for (int q = 0; q < 4; q++) ud[q] = g * (fl.ucon[q] + bp * fl.bcon[q]);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; q++) ud[q] = fl.ucon[q];
+  }
+  // the parcel's primitives: utilde^i = u^i + u^t beta^i, beta^i = alpha^2 g^{ti}
+  // (the shift of the Kerr-Schild metric has its x1 component only)
+  const double Pp[5] = {drho, du, ud[1] + ud[0] * m.alpha * m.alpha * m.h01, ud[2], ud[3]};
+  const double B0[3] = {0.0, 0.0, 0.0};
+  double U[9], Up[9], Un[9];
+  flux_vector<0>(P, fl, m, gam, entropy_kappa(P, gam), U);
+  {
+    Fluid fp;
+    fluid_state(Pp, B0, m, fp);
+    flux_vector<0>(Pp, fp, m, gam, 0.0, Up);
+  }
+#pragma unroll
+  for (int q = 0; q < 8; q++) Un[q] = U[q] + Up[q];
+  Un[8] = U[8] / U[0] * Un[0];
+  C2PIn cs;
+  c2p_setup(Un, m, gam, cs);
+  double Pn[5];
+  int it = 0;
+  const int tier = c2p_solve(cs, m, false, 0.0, 0.0, P, tol, maxit, Pn, it);
+  if (tier <= 2) {
+#pragma unroll
+    for (int v = 0; v < 5; v++) P[v] = Pn[v];
+    apply_floors(P, B, m, rho_fl, u_fl, bsq_rho_max, bsq_u_max, gamma_max);
+    return hits + (drho > 0.0) + (du > 0.0);
+  }
+  return hits + apply_floors(P, B, m, rho_fl, u_fl, bsq_rho_max, bsq_u_max, gamma_max);
+}
+
 }  // namespace grmhd

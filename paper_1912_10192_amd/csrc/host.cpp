@@ -295,6 +295,8 @@ int validate(const grmhd_grid_desc* d) {
   if (d->c2p_guess != GRMHD_GUESS_PLAIN && d->c2p_guess != GRMHD_GUESS_MLP)
     return fail(GRMHD_EINVAL, "unknown c2p_guess");
   if (d->emf != GRMHD_EMF_AVERAGE && d->emf != GRMHD_EMF_UPWIND) return fail(GRMHD_EINVAL, "unknown emf");
+  if (d->floor_frame != GRMHD_FLOOR_FIXED && d->floor_frame != GRMHD_FLOOR_DRIFT)
+    return fail(GRMHD_EINVAL, "unknown floor_frame");
   if (d->c2p_guess == GRMHD_GUESS_MLP && !d->mlp_weights)
     return fail(GRMHD_EINVAL, "learned guess needs mlp_weights");
   int lmax[3] = {0, 0, 0};
@@ -1961,6 +1963,7 @@ int grmhd_init_grid(const grmhd_grid_desc* desc, const grmhd_buffers* bufs, void
   L.ph.gamma_max = desc->gamma_max;
   L.ph.maxit = desc->c2p_maxit;
   L.ph.ng = desc->n_ghost;
+  L.ph.floor_drift = desc->floor_frame == GRMHD_FLOOR_DRIFT;
   L.cnt = (Counters*)(w + p.o_cnt);
   L.stat_acc = (unsigned long long*)(w + p.o_stp);
   // the tallest update brick every block divides into (8 or 4 cells along x3), else none

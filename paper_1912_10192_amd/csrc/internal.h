@@ -163,6 +163,8 @@ struct Phys {
   double bsq_rho_max, bsq_u_max, gamma_max;
   int32_t maxit;
   int32_t ng;
+  int32_t floor_drift;   // floors in the drift frame (else at fixed utilde)
+  int32_t pad;
 };
 
 __host__ __device__ inline int64_t geo_col(const GeoTab&, const BlockInfo& bi, int J, int I) {

@@ -744,10 +744,11 @@ __device__ __forceinline__ void conserve_cell(const Launch& L, const BlockInfo& 
   U[7] = 0.5 * (nb3lo + nb3hi);
 }
 
-// The inversion of one cell and its floors (Sec. 2.6, 2.7); writes the primitives and,
-// with NEXT_DT, returns the cell's Courant step of the next step in dtc; bad = 1 when the
-// result is not a physical state (a non-finite value, rho <= 0 or u <= 0)
-template <bool NEXT_DT>
+// The inversion of one cell and its floors (Sec. 2.6, 2.7; DRIFT: in the drift frame);
+// writes the primitives and, with NEXT_DT, returns the cell's Courant step of the next
+// step in dtc; bad = 1 when the result is not a physical state (a non-finite value,
+// rho <= 0 or u <= 0)
+template <bool NEXT_DT, bool DRIFT>
 __device__ __forceinline__ void invert_cell(const Launch& L, const BlockInfo& bi, const Cell& c,
                                             const Metric& m, int64_t col, const C2PIn& cs,
                                             bool first, double W0, double v0, const double PS[5],
@@ -759,7 +760,12 @@ __device__ __forceinline__ void invert_cell(const Launch& L, const BlockInfo& bi
   // B^i = Bbar^i / sqrt(-g) with Bbar^i the face average; c2p_setup holds alpha B^i
   const double ia = 1.0 / m.alpha;
   const double Bnew[3] = {cs.B1 * ia, cs.B2 * ia, cs.B3 * ia};
-  hits = apply_floors(Pnew, Bnew, m, fl[0], fl[1], L.ph.bsq_rho_max, L.ph.bsq_u_max, L.ph.gamma_max);
+  if (DRIFT)
+    hits = drift_floors(Pnew, Bnew, m, fl[0], fl[1], L.ph.bsq_rho_max, L.ph.bsq_u_max,
+                        L.ph.gamma_max, L.ph.gam, L.ph.tol, L.ph.maxit);
+  else
+    hits = apply_floors(Pnew, Bnew, m, fl[0], fl[1], L.ph.bsq_rho_max, L.ph.bsq_u_max,
+                        L.ph.gamma_max);
   bool ok = Pnew[0] > 0.0 && Pnew[1] > 0.0;
 #pragma unroll
   for (int v = 0; v < 5; v++) ok = ok && isfinite(Pnew[v]);
@@ -872,7 +878,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   bool first = false;
   double W0 = 0.0, v0 = 0.0;
   if (MLP) first = learned_guess(mlp, cs, m, valid, PS, W0, v0);
-  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters, hits, bad, dtc);
+  if (valid)
+    invert_cell<NEXT_DT, false>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters,
+                                hits, bad, dtc);
   update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, bad, first, dtc, dt_part);
 }
 
@@ -901,8 +909,9 @@ __global__ __launch_bounds__(NT) void k_conserve(Launch L, const double* __restr
   for (int q = 0; q < 9; q++) u[(int64_t)q * bi.vol] = U[q];
 }
 
-// split update, second half: inversion, floors, next dt from ubuf
-template <bool STATS, bool NEXT_DT, bool MLP, int OCC>
+// split update, second half: inversion, floors (DRIFT: in the drift frame; the fused
+// update has fixed-utilde floors only), next dt from ubuf
+template <bool STATS, bool NEXT_DT, bool MLP, int OCC, bool DRIFT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void k_invert(
     Launch L, const double* __restrict__ Ps, const double* __restrict__ ubuf,
     double* __restrict__ Pout, double* __restrict__ dt_part, const MlpBlob* __restrict__ mlp) {
@@ -933,7 +942,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(OCC))) void 
   bool first = false;
   double W0 = 0.0, v0 = 0.0;
   if (MLP) first = learned_guess(mlp, cs, m, valid, PS, W0, v0);
-  if (valid) invert_cell<NEXT_DT>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters, hits, bad, dtc);
+  if (valid)
+    invert_cell<NEXT_DT, DRIFT>(L, bi, c, m, col, cs, first, W0, v0, PS, fl, Pout, tier, iters,
+                                hits, bad, dtc);
   update_epilogue<STATS, NEXT_DT>(L, bt, valid, tier, iters, hits, bad, first, dtc, dt_part);
 }
 
@@ -1305,12 +1316,17 @@ int64_t launch_update(const Launch& L, const double* Pn, const double* Bn, const
   Launch Lc;
   const dim3 grid = stage_grid(L, dt_part ? -1 : WL_CELLS, r, Lc);
   const MlpBlob* blob = (const MlpBlob*)mlp;
-  if (L.split_upd && ubuf) {
+  // floors in the drift frame run in the split form only
+  if ((L.split_upd || L.ph.floor_drift) && ubuf) {
     hipLaunchKernelGGL(k_conserve, grid, dim3(NT), 0, L.stream, Lc, Pn, Bn, Ps, Bcs, F, E,
                        dt_factor, Bout, ubuf);
 #define GRMHD_INV(ND, ML, V)                                                                   \
-  hipLaunchKernelGGL((k_invert<true, ND, ML, UPD_OCC[V]>), grid, dim3(NT), 0, L.stream, Lc, Ps, \
-                     ubuf, Pout, dt_part, blob)
+  if (L.ph.floor_drift)                                                                         \
+    hipLaunchKernelGGL((k_invert<true, ND, ML, UPD_OCC[V], true>), grid, dim3(NT), 0, L.stream,   \
+                       Lc, Ps, ubuf, Pout, dt_part, blob);                                      \
+  else                                                                                          \
+    hipLaunchKernelGGL((k_invert<true, ND, ML, UPD_OCC[V], false>), grid, dim3(NT), 0, L.stream,  \
+                       Lc, Ps, ubuf, Pout, dt_part, blob)
 #define GRMHD_INV_V(ND, ML) \
   if (L.var_upd == 0) { GRMHD_INV(ND, ML, 0); } else { GRMHD_INV(ND, ML, 1); }
     if (dt_part && blob) {

@@ -238,6 +238,7 @@ __global__ __launch_bounds__(LT) void k_sync_faces(Launch L, const SyncFace* __r
 
 // New inversion of the listed cells (guess: their primitives) from the corrected
 // conserved state and the corrected faces, then floors.
+template <bool DRIFT>
 __global__ __launch_bounds__(LT) void k_sync_c2p(Launch L, const SyncCell* __restrict__ cells,
                                                  int64_t ncell, double* __restrict__ P,
                                                  const double* __restrict__ B,
@@ -268,9 +269,11 @@ __global__ __launch_bounds__(LT) void k_sync_c2p(Launch L, const SyncCell* __res
     int iters = 0;
     tier = c2p_solve(cs, m, false, 0.0, 0.0, p, L.ph.tol, L.ph.maxit, Pn, iters);
     const double Bn[3] = {U[5] / m.gdet, U[6] / m.gdet, U[7] / m.gdet};
-    hits = apply_floors(Pn, Bn, m, L.geo.c[RHOFL * L.geo.ncol + col],
-                        L.geo.c[UFL * L.geo.ncol + col], L.ph.bsq_rho_max, L.ph.bsq_u_max,
-                        L.ph.gamma_max);
+    const double rfl = L.geo.c[RHOFL * L.geo.ncol + col], ufl = L.geo.c[UFL * L.geo.ncol + col];
+    hits = DRIFT ? drift_floors(Pn, Bn, m, rfl, ufl, L.ph.bsq_rho_max, L.ph.bsq_u_max,
+                                L.ph.gamma_max, L.ph.gam, L.ph.tol, L.ph.maxit)
+                 : apply_floors(Pn, Bn, m, rfl, ufl, L.ph.bsq_rho_max, L.ph.bsq_u_max,
+                                L.ph.gamma_max);
     for (int v = 0; v < 5; v++) P[5 * bi.off + v * V + l] = Pn[v];
   }
   // one counter add per distinct value per wave (every lane of the wave takes part)
@@ -352,8 +355,12 @@ void launch_sync(const Launch& L, const SyncCell* cells, int64_t ncell, const Sy
     hipLaunchKernelGGL(k_sync_faces, dim3(cdv(nface, LT)), dim3(LT), 0, L.stream, L, faces, nface,
                        B, regE, ne);
   if (ncell > 0)
-    hipLaunchKernelGGL(k_sync_c2p, dim3(cdv(ncell, LT)), dim3(LT), 0, L.stream, L, cells, ncell,
-                       P, B, Ubuf);
+    if (L.ph.floor_drift)
+      hipLaunchKernelGGL(k_sync_c2p<true>, dim3(cdv(ncell, LT)), dim3(LT), 0, L.stream, L, cells,
+                         ncell, P, B, Ubuf);
+    else
+      hipLaunchKernelGGL(k_sync_c2p<false>, dim3(cdv(ncell, LT)), dim3(LT), 0, L.stream, L, cells,
+                         ncell, P, B, Ubuf);
 }
 
 void launch_dt_final_lat(const Launch& L, const double* part, int64_t n, int gridx,

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SO_PATH = os.environ.get("GRMHD_SO", os.path.join(_HERE, "libgrmhd.so"))
 _lib = None
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 OK, EINVAL, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 MINK_CART, KS_LOGSPH = 0, 1
 PLM_MC, PPM, PLM_MINMOD, PPM_FLAT = 0, 1, 2, 3
@@ -23,6 +23,7 @@ LLF, HLLE = 0, 1
 BC_OUTFLOW, BC_POLAR, BC_PERIODIC = 0, 1, 2
 GUESS_PLAIN, GUESS_MLP = 0, 1
 EMF_AVERAGE, EMF_UPWIND = 0, 1
+FLOOR_FIXED, FLOOR_DRIFT = 0, 1
 
 # every symbol declared in include/grmhd.h
 EXPORTS = ("grmhd_sizes", "grmhd_block_layout", "grmhd_init_grid", "grmhd_step",
@@ -48,7 +49,8 @@ class GridDesc(C.Structure):
                 ("u_fl_c", C.c_double), ("u_fl_p", C.c_double), ("bsq_rho_max", C.c_double),
                 ("bsq_u_max", C.c_double), ("gamma_max", C.c_double), ("c2p_guess", C.c_int32),
                 ("c2p_maxit", C.c_int32), ("c2p_tol", C.c_double), ("mlp_weights", C.c_void_p),
-                ("batched", C.c_int32), ("profile", C.c_int32), ("emf", C.c_int32)]
+                ("batched", C.c_int32), ("profile", C.c_int32), ("emf", C.c_int32),
+                ("floor_frame", C.c_int32)]
 
 
 KERNEL_CLASSES = ("ghost", "bcell", "flux1", "flux2", "flux3", "emf", "update", "dt")
@@ -194,6 +196,7 @@ class Desc:
         d.batched = int(batched) if not isinstance(batched, bool) else (1 if batched else 0)
         d.profile = 1 if profile else 0
         d.emf = int(cfg.get("emf", EMF_AVERAGE))
+        d.floor_frame = int(cfg.get("floor_frame", FLOOR_FIXED))
         self.d = d
 
     def sizes(self):
