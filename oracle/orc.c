@@ -946,14 +946,23 @@ static int floors_drift(double* P, const double* Bcon, const double* gcov, const
   double umin = fmax(u_fl, s.bsq / bsq_u_max);
   double drho = fmax(rmin - P[RHO], 0.0), du = fmax(umin - P[UU], 0.0);
   if (drho > 0.0 || du > 0.0) {
+    /* beta b does not change when the field is multiplied by a constant: it is formed
+     * from the field divided by its largest component, so that a weak field (b^2 below
+     * the smallest normal double) gives the same frame as a strong one of that direction;
+     * without a field the drift frame is the fluid frame */
     double ud[4];
-    if (s.bsq > 0.0) {
-      double bp = -s.bcon[0] / (s.bsq * s.ucon[0]);
-      double b2 = fmin(bp * bp * s.bsq, 1.0 - 1.0 / (gmax * gmax));
-      double g = 1.0 / sqrt(1.0 - b2);
-      for (int m = 0; m < 4; m++) ud[m] = g * (s.ucon[m] + bp * s.bcon[m]);
-    } else {
-      for (int m = 0; m < 4; m++) ud[m] = s.ucon[m];
+    for (int m = 0; m < 4; m++) ud[m] = s.ucon[m];
+    double bmax = fmax(fmax(fabs(Bcon[0]), fabs(Bcon[1])), fabs(Bcon[2]));
+    if (bmax > 0.0) {
+      double Bs[3] = {Bcon[0] / bmax, Bcon[1] / bmax, Bcon[2] / bmax};
+      ostate sb;
+      get_state(P, Bs, gcov, gcon, alpha, &sb);
+      if (sb.bsq > 0.0) {
+        double bp = -sb.bcon[0] / (sb.bsq * sb.ucon[0]);
+        double b2 = fmin(bp * bp * sb.bsq, 1.0 - 1.0 / (gmax * gmax));
+        double g = 1.0 / sqrt(1.0 - b2);
+        for (int m = 0; m < 4; m++) ud[m] = g * (s.ucon[m] + bp * sb.bcon[m]);
+      }
     }
     /* the parcel's primitives: utilde^i = u^i + u^t beta^i, beta^i = alpha^2 g^{ti} */
     double Pp[5] = {drho, du, 0.0, 0.0, 0.0}, B0[3] = {0.0, 0.0, 0.0};

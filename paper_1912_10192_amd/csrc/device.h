@@ -653,16 +653,29 @@ __device__ __forceinline__ int drift_floors(double P[5], const double B[3], cons
   const double umin = fmax(u_fl, fl.bsq / bsq_u_max);
   const double drho = fmax(rmin - P[0], 0.0), du = fmax(umin - P[1], 0.0);
   if (!(drho > 0.0 || du > 0.0)) return hits;
+  // beta b is the same for every multiple of the field: it is formed from the field over
+  // its largest component, which keeps weak fields (b^2 below the smallest normal double)
+  // clear of underflow; no field at all leaves the fluid frame
   double ud[4];
-  if (fl.bsq > 0.0) {
-    const double bp = -fl.bcon[0] / (fl.bsq * fl.ucon[0]);
-    const double b2 = fmin(bp * bp * fl.bsq, 1.0 - 1.0 / (gamma_max * gamma_max));
-    const double g = 1.0 / sqrt(1.0 - b2);
 #pragma unroll
-    for (int q = 0; q < 4; q++) ud[q] = g * (fl.ucon[q] + bp * fl.bcon[q]);
-  } else {
+  for (int q = 0; q < 4; q++) ud[q] = fl.ucon[q];
+  const double bmax = fmax(fmax(fabs(B[0]), fabs(B[1])), fabs(B[2]));
+  if (bmax > 0.0) {
+    const double Bs[3] = {B[0] / bmax, B[1] / bmax, B[2] / bmax};
+    double bc[4], bl[4];
+    bc[0] = Bs[0] * fl.ucov[1] + Bs[1] * fl.ucov[2] + Bs[2] * fl.ucov[3];
+    const double iut = 1.0 / fl.ucon[0];
 #pragma unroll
-    for (int q = 0; q < 4; q++) ud[q] = fl.ucon[q];
+    for (int i = 1; i < 4; i++) bc[i] = (Bs[i - 1] + bc[0] * fl.ucon[i]) * iut;
+    lower4(m, bc, bl);
+    const double bsq = bc[0] * bl[0] + bc[1] * bl[1] + bc[2] * bl[2] + bc[3] * bl[3];
+    if (bsq > 0.0) {
+      const double bp = -bc[0] * iut / bsq;
+      const double b2 = fmin(bp * bp * bsq, 1.0 - 1.0 / (gamma_max * gamma_max));
+      const double g = 1.0 / sqrt(1.0 - b2);
+#pragma unroll
+      for (int q = 0; q < 4; q++) ud[q] = g * (fl.ucon[q] + bp * bc[q]);
+    }
   }
   // the parcel's primitives: utilde^i = u^i + u^t beta^i, beta^i = alpha^2 g^{ti}
   // (the shift of the Kerr-Schild metric has its x1 component only)

@@ -2,7 +2,9 @@
 torus, whose atmosphere the floors hold; a magnetised box whose density and internal
 energy lie below the floors everywhere (every cell takes a parcel each stage); and the
 refined layout with time levels, where the re-inversion after refluxing applies the
-same floors.  Same bar as every trajectory test."""
+same floors; and a box whose field is too weak to hold energy (b^2 below the smallest
+double), where the drift frame still follows the field's direction.  Same bar as every
+trajectory test."""
 import sys
 
 import numpy as np
@@ -43,6 +45,30 @@ def _starved_box():
 def test_starved_box_with_drift_frame_floors_matches_oracle():
     cfg, state = _starved_box()
     check_trajectory(cfg, state, 3)
+
+
+def _weak_field_box(scale):
+    cfg, (P, B1, B2, B3) = _starved_box()
+    return cfg, (P, B1 * scale, B2 * scale, B3 * scale)
+
+
+def test_weak_field_box_with_drift_frame_floors_matches_oracle():
+    cfg, state = _weak_field_box(1e-170)
+    check_trajectory(cfg, state, 3)
+
+
+def test_drift_frame_of_a_weak_field_follows_its_direction():
+    """a field 1e-200 times the starved box's, whose b^2 underflows, still sets the drift
+    frame: the states after two steps differ widely from those of the same box without a
+    field, where the parcels move with the fluid"""
+    out = []
+    for scale in (1e-200, 0.0):
+        cfg, state = _weak_field_box(scale)
+        g = grmhd.Grid(cfg, state=state)
+        g.step(2)
+        out.append(g.get_state()[0])
+    assert np.isfinite(out[0]).all() and np.isfinite(out[1]).all()
+    assert np.abs(out[0] - out[1]).max() > 0.1 * np.abs(out[0]).max()
 
 
 def test_drift_frame_floors_change_the_solution():

@@ -123,3 +123,22 @@ def test_drift_floors_add_the_parcel_to_the_conserved_state_in_kerr_schild():
             assert np.abs(U1[:5] - (U0[:5] + Up[:5])).max() <= 1e-9 * scale
             checked += 1
     assert checked > 50
+
+
+@pytest.mark.parametrize("scale,tol", [(1e-100, 1e-13), (1e-160, 1e-13), (1e-200, 1e-13),
+                                       (1e-300, 1e-10)])
+def test_drift_frame_depends_on_the_field_direction_only(scale, tol):
+    """beta b = -b^t b / (b^2 u^t) is unchanged when the field is multiplied by a constant,
+    so a field whose b^2 lies below the smallest double (the traces that numerical
+    diffusion leaves in an empty funnel) gives the frame of a stronger field of its
+    direction; the field here carries no energy at the level of rounding either way.
+    At 1e-300 the field components are subnormal and hold fewer digits."""
+    g = _mink_point()
+    P = np.array([1e-8, 1e-10, 0.4, 0.3, -0.2])
+    B = np.array([0.7, -0.2, 0.4]) * 1e-12
+    ref, _ = _floors(oracle.FLOOR_DRIFT, P, B, g, 1e-6, 1e-7, **BIG)
+    weak, _ = _floors(oracle.FLOOR_DRIFT, P, B * scale, g, 1e-6, 1e-7, **BIG)
+    assert np.abs(weak - ref).max() <= tol * np.abs(ref).max()
+    # the direction matters: without a field the parcel moves with the fluid
+    none, _ = _floors(oracle.FLOOR_DRIFT, P, [0.0, 0.0, 0.0], g, 1e-6, 1e-7, **BIG)
+    assert np.abs(none[2:] - ref[2:]).max() > 1e-2
