@@ -1,0 +1,236 @@
+"""Regridding: a new block layout filled from the state of an old one (paper Sec. 3.3:
+blocks are refined and derefined during the run; new fine blocks are prolonged and new
+coarse blocks restricted from the blocks they replace, the face field by a
+divergence-free prolongation after Balsara 2001).
+
+TEST INFRASTRUCTURE ONLY.  Shares no code with the HIP path.
+
+Rules (readings stated in the design notes):
+  * Both layouts cover the same domain and have the same finest level in each dimension.
+    Every new block lies, in each dimension, at the level of each old block it overlaps,
+    one level finer, or one coarser, and never finer in one dimension and coarser in
+    another; where it is coarser, the old blocks' boundaries fall on its cell faces.
+  * The old state is taken at the end of a cycle (every block at the same time), with
+    every ghost value filled by the ghost rules of the old layout.
+  * A new cell takes its value from the old block that covers it: a copy at the same
+    level; for a coarser new cell, the sqrt(-g)-weighted mean of the primitives of the
+    fine cells it covers; for a finer new cell, the parent's value plus, per refined
+    dimension, +-1/4 of the minmod-limited slope (the neighbours at the parent's level,
+    ghosts included).
+  * A new face takes its value from the old block that covers the new cell whose lower
+    face it is (the cell below, for the upper face of the new block):
+      - same level: a copy;
+      - coarser: the mean of the fine sub-faces on it;
+      - finer, on a face of the parent cell: the parent face's value plus, per refined
+        transverse dimension, +-1/4 of its minmod-limited slope along that dimension (the
+        neighbouring parent faces in the face's plane);
+      - finer, inside the parent cell: the face average of Balsara's divergence-free
+        reconstruction of the parent cell.  In the cell (coordinates x_d from the centre,
+        widths D_d), B^d is quadratic in x_d and linear in the other two coordinates,
+        matches on its two faces the linear distributions above (face value plus slope
+        times position), and the x_d^2 coefficient follows from div B = 0:
+            c_dd = -(1/2) sum_{e != d} (S_{e+}^d - S_{e-}^d) / D_e,
+        with S_{e+-}^d the slope along x_d of B^e on the cell's upper and lower e faces.
+        The face in the middle of the cell (x_d = 0) at transverse offsets t_e then has
+            B^d = (B^d_+ + B^d_-)/2 - c_dd D_d^2/4 + sum_e t_e (S_{d+}^e + S_{d-}^e)/2.
+    Since the reconstruction is divergence-free and matches the prolonged faces on the
+    parent's faces, every fine cell inherits div B = 0 from its parent.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle.amr import AmrGrid
+
+
+def _minmod(a, b):
+    if a > 0.0 and b > 0.0:
+        return min(a, b)
+    if a < 0.0 and b < 0.0:
+        return max(a, b)
+    return 0.0
+
+
+def _covering(blocks, Lmax, lam, gcell):
+    """index of the block containing the cell gcell (indices at levels lam)"""
+    f = [gcell[d] << (Lmax[d] - lam[d]) for d in range(3)]
+    for n, b in enumerate(blocks):
+        s = [Lmax[d] - b["lev"][d] for d in range(3)]
+        if all((b["org"][d] << s[d]) <= f[d] < ((b["org"][d] + b["n"][d]) << s[d]) for d in range(3)):
+            return n
+    raise ValueError(f"cell {gcell} at levels {lam} is not covered by the old layout")
+
+
+def _relation(old_b, lam):
+    r = [lam[d] - old_b["lev"][d] for d in range(3)]
+    if max(abs(x) for x in r) > 1 or (max(r) > 0 and min(r) < 0):
+        raise ValueError(f"new levels {lam} against old {old_b['lev']}: not a one-level change")
+    return r
+
+
+class Regrid:
+    """the new layout's state from an old AmrGrid at the end of a cycle"""
+
+    def __init__(self, old: AmrGrid, new_blocks):
+        self.old = old
+        self.g = old.g
+        self.new = [dict(b, lev=tuple(int(x) for x in b.get("lev", (0, 0, 0)))) for b in new_blocks]
+        lm = tuple(max(b["lev"][d] for b in self.new) for d in range(3))
+        if lm != old.Lmax:
+            raise ValueError("both layouts must have the same finest level per dimension")
+        self.Lmax = old.Lmax
+        # the old state at the cycle's end, every ghost filled from it
+        for i in range(len(old.blocks)):
+            old.Pold[i] = old.P[i].copy()
+            old.Bold[i] = old.B[i].copy()
+        self.pads = [old.patch(i, "pred", 0) for i in range(len(old.blocks))]
+
+    # ------------------------------------------------------------------ helpers
+    def _loc(self, ob, gidx):
+        """padded local index tuple (k, j, i) in old block ob of global indices (x1, x2, x3)
+        at ob's levels"""
+        o = self.old.blocks[ob]["org"]
+        g = self.g
+        return (g + gidx[2] - o[2], g + gidx[1] - o[1], g + gidx[0] - o[0])
+
+    def _dx(self, ob):
+        return self.old.bdx[ob]
+
+    # ------------------------------------------------------------------ cells
+    def cell(self, lam, gc):
+        ob = _covering(self.old.blocks, self.Lmax, lam, gc)
+        r = _relation(self.old.blocks[ob], lam)
+        VP = self.pads[ob][0]
+        if max(r) == 0 and min(r) == 0:
+            return VP[(slice(None),) + self._loc(ob, gc)].copy()
+        if max(r) <= 0:
+            # coarser: sqrt(-g)-weighted mean of the covered fine cells (k, j, i order)
+            o = self.old.blocks[ob]["org"]
+            W = self.old.gdet[ob]
+            subs = [range(2) if r[d] < 0 else range(1) for d in range(3)]
+            num = np.zeros(5)
+            den = 0.0
+            for ok in subs[2]:
+                for oj in subs[1]:
+                    for oi in subs[0]:
+                        f = [(gc[d] << (-r[d])) + (oi, oj, ok)[d] for d in range(3)]
+                        w = W[f[1] - o[1], f[0] - o[0]]
+                        num = num + w * VP[(slice(None),) + self._loc(ob, f)]
+                        den = den + w
+            return num / den
+        # finer: parent plus limited slopes
+        pc = [gc[d] >> r[d] for d in range(3)]
+        c0 = VP[(slice(None),) + self._loc(ob, pc)]
+        val = c0.copy()
+        for d in range(3):
+            if not r[d]:
+                continue
+            e = [0, 0, 0]
+            e[d] = 1
+            cm = VP[(slice(None),) + self._loc(ob, [pc[x] - e[x] for x in range(3)])]
+            cp = VP[(slice(None),) + self._loc(ob, [pc[x] + e[x] for x in range(3)])]
+            t = 0.25 if gc[d] & 1 else -0.25
+            for v in range(5):
+                val[v] = val[v] + t * _minmod(c0[v] - cm[v], cp[v] - c0[v])
+        return val
+
+    # ------------------------------------------------------------------ faces
+    def _face_slope(self, ob, d, fidx, e):
+        """minmod slope along x_e (per parent cell) of the B^d faces at old global face
+        index fidx (normal index in d, cell indices in the others)"""
+        VB = self.pads[ob][1]
+        step = [0, 0, 0]
+        step[e] = 1
+        c = VB[(d,) + self._loc(ob, fidx)]
+        m = VB[(d,) + self._loc(ob, [fidx[x] - step[x] for x in range(3)])]
+        p = VB[(d,) + self._loc(ob, [fidx[x] + step[x] for x in range(3)])]
+        return _minmod(c - m, p - c)
+
+    def face(self, lam, d, gf, top):
+        """B^d on the new face gf (normal index in d) of a new block; top: the face is the
+        block's upper face in d (its owner is the cell below)"""
+        gc = list(gf)
+        if top:
+            gc[d] -= 1
+        ob = _covering(self.old.blocks, self.Lmax, lam, gc)
+        r = _relation(self.old.blocks[ob], lam)
+        VB = self.pads[ob][1]
+        if max(r) == 0 and min(r) == 0:
+            return VB[(d,) + self._loc(ob, gf)]
+        if max(r) <= 0:
+            subs = [range(1) if (x == d or r[x] == 0) else range(2) for x in range(3)]
+            acc = 0.0
+            cnt = 0
+            for ok in subs[2]:
+                for oj in subs[1]:
+                    for oi in subs[0]:
+                        f = [(gf[x] << (-r[x])) + (oi, oj, ok)[x] for x in range(3)]
+                        acc = acc + VB[(d,) + self._loc(ob, f)]
+                        cnt += 1
+            return acc * (1.0 / cnt)
+        # finer
+        pc = [gf[x] >> r[x] for x in range(3)]               # parent cell (transverse)
+        t = [0.0, 0.0, 0.0]
+        for x in range(3):
+            if x != d and r[x]:
+                t[x] = 0.25 if gf[x] & 1 else -0.25
+        tr = [x for x in range(3) if x != d]
+        if r[d] == 0 or gf[d] % 2 == 0:
+            F = list(pc)
+            F[d] = gf[d] >> r[d]
+            val = VB[(d,) + self._loc(ob, F)]
+            for e in tr:
+                if r[e]:
+                    val = val + t[e] * self._face_slope(ob, d, F, e)
+            return val
+        # inside the parent cell C (normal index gf[d] >> 1): Balsara's reconstruction
+        C = list(pc)
+        lo = list(C)
+        hi = list(C)
+        hi[d] += 1
+        bm, bp = VB[(d,) + self._loc(ob, lo)], VB[(d,) + self._loc(ob, hi)]
+        dx = self._dx(ob)
+        val = 0.5 * (bm + bp)
+        for e in tr:
+            # c_dd part from the B^e faces' slopes along x_d (slopes per parent cell:
+            # S = slope / D_d, so D_d^2/8 (S_+ - S_-)/D_e = D_d/(8 D_e) (s_+ - s_-))
+            em = list(C)
+            ep = list(C)
+            ep[e] += 1
+            s_lo = self._face_slope(ob, e, em, d)
+            s_hi = self._face_slope(ob, e, ep, d)
+            val = val + dx[d] / (8.0 * dx[e]) * (s_hi - s_lo)
+        for e in tr:
+            if r[e]:
+                val = val + t[e] * 0.5 * (self._face_slope(ob, d, lo, e) + self._face_slope(ob, d, hi, e))
+        return val
+
+    # ------------------------------------------------------------------ blocks
+    def states(self):
+        out = []
+        for b in self.new:
+            lam, o, n = b["lev"], b["org"], b["n"]
+            P = np.zeros((5, n[2], n[1], n[0]))
+            for k in range(n[2]):
+                for j in range(n[1]):
+                    for i in range(n[0]):
+                        P[:, k, j, i] = self.cell(lam, (o[0] + i, o[1] + j, o[2] + k))
+            Bs = []
+            for d in range(3):
+                shp = [n[x] + (1 if x == d else 0) for x in range(3)]
+                A = np.zeros((shp[2], shp[1], shp[0]))
+                for k in range(shp[2]):
+                    for j in range(shp[1]):
+                        for i in range(shp[0]):
+                            loc = (i, j, k)
+                            A[k, j, i] = self.face(lam, d, (o[0] + i, o[1] + j, o[2] + k),
+                                                   loc[d] == n[d])
+                Bs.append(A)
+            out.append((P, Bs[0], Bs[1], Bs[2]))
+        return out
+
+
+def regrid(old: AmrGrid, new_blocks):
+    """per-block interior states of the new layout (P, B1, B2, B3 as AmrGrid.set_blocks
+    takes them)"""
+    return Regrid(old, new_blocks).states()

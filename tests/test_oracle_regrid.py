@@ -1,0 +1,197 @@
+"""Pins of the oracle's regrid (Sec. 3.3 refinement and derefinement of blocks, with the
+divergence-free prolongation of Balsara 2001): the face field of every new block is
+divergence-free, for refinement in every combination of dimensions, on Minkowski and
+Kerr-Schild grids; a layout regridded to itself is unchanged; refining and derefining
+returns the original state; linear data are prolonged and restricted exactly; and the
+magnetic flux through every new coarse face is the sum over the fine faces it replaces."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.amr import AmrGrid
+from oracle.regrid import regrid
+from paper_1912_10192_amd import initdata
+from tests.helpers import mink_cfg, random_periodic_state
+
+PATTERNS = {"all": (1, 1, 1), "x1": (1, 0, 0), "x3": (0, 0, 1), "x1x2": (1, 1, 0),
+            "x2x3": (0, 1, 1)}
+
+
+def halves(N, fine, left_fine):
+    """two blocks splitting x1 in half: one at levels `fine`, one at level 0"""
+    out = []
+    for side in (0, 1):
+        lev = tuple(fine) if (side == 0) == left_fine else (0, 0, 0)
+        Nl = [N[d] >> (fine[d] - lev[d]) for d in range(3)]
+        out.append(dict(org=(side * Nl[0] // 2, 0, 0), n=(Nl[0] // 2, Nl[1], Nl[2]), lev=lev,
+                        lat=0))
+    return out
+
+
+def _grid(cfg, blocks, state):
+    og = AmrGrid(cfg, blocks)
+    lmax = [max(b["lev"][d] for b in blocks) for d in range(3)]
+    og.set_blocks(initdata.block_states(state, blocks, lmax))
+    return og
+
+
+def _spacing(cfg, b, Lmax):
+    N = cfg["n"]
+    return [(cfg["xhi"][d] - cfg["xlo"][d]) / (N[d] >> (Lmax[d] - b["lev"][d])) for d in range(3)]
+
+
+def _div(st, dx):
+    P, B1, B2, B3 = st
+    return ((B1[..., 1:] - B1[..., :-1]) / dx[0] + (B2[:, 1:] - B2[:, :-1]) / dx[1]
+            + (B3[1:] - B3[:-1]) / dx[2])
+
+
+def _mink(N):
+    return dict(mink_cfg(N), bc=(2, 2, 2, 2, 2, 2))
+
+
+@pytest.mark.parametrize("pattern", list(PATTERNS))
+def test_regridded_face_field_is_divergence_free(pattern):
+    fine = PATTERNS[pattern]
+    N = (16, 16, 8)
+    cfg = _mink(N)
+    state = random_periodic_state(N, seed=3, bamp=0.5)
+    old = halves(N, fine, left_fine=True)
+    new = halves(N, fine, left_fine=False)
+    out = regrid(_grid(cfg, old, state), new)
+    for b, st in zip(new, out):
+        dx = _spacing(cfg, b, fine)
+        scale = max(np.abs(x).max() for x in st[1:]) / min(dx)
+        assert np.abs(_div(st, dx)).max() <= 1e-13 * scale, (pattern, b["lev"])
+
+
+def test_regrid_on_kerr_schild_is_divergence_free():
+    N = (16, 16, 8)
+    cfg = dict(coords=1, a=0.9375, gam=4.0 / 3.0, n=N, ng=3, recon=1, riemann=1,
+               xlo=(math.log(2.0), 0.3, 0.0), xhi=(math.log(20.0), math.pi - 0.3, 2 * math.pi),
+               bc=(0, 0, 0, 0, 2, 2), courant=0.8, rho_fl_c=0.0, rho_fl_p=0.0, u_fl_c=0.0,
+               u_fl_p=0.0, bsq_rho_max=1e300, bsq_u_max=1e300, gamma_max=1e150, tol=1e-12,
+               maxit=50)
+    dx0 = [(cfg["xhi"][d] - cfg["xlo"][d]) / N[d] for d in range(3)]
+    state = random_periodic_state(N, seed=5, bamp=0.5, dx=dx0)
+    for fine in ((1, 1, 1), (0, 1, 1)):
+        out = regrid(_grid(cfg, halves(N, fine, True), state), halves(N, fine, False))
+        for b, st in zip(halves(N, fine, False), out):
+            dx = _spacing(cfg, b, fine)
+            scale = max(np.abs(x).max() for x in st[1:]) / min(dx)
+            assert np.abs(_div(st, dx)).max() <= 1e-13 * scale
+
+
+def test_regrid_to_the_same_layout_is_a_copy():
+    N = (16, 16, 8)
+    cfg = _mink(N)
+    state = random_periodic_state(N, seed=4)
+    blocks = halves(N, (1, 1, 1), True)
+    og = _grid(cfg, blocks, state)
+    before = og.get_blocks()
+    out = regrid(og, blocks)
+    for a, b in zip(before, out):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("pattern", ["all", "x3", "x1x2"])
+def test_refine_then_derefine_returns_the_original(pattern):
+    fine = PATTERNS[pattern]
+    N = (16, 16, 8)
+    cfg = _mink(N)
+    state = random_periodic_state(N, seed=6)
+    coarse_right = halves(N, fine, True)
+    fine_both = [coarse_right[0]]
+    # the right half refined in place (the layout's finest level is kept)
+    b = coarse_right[1]
+    fine_both.append(dict(org=tuple(b["org"][d] << fine[d] for d in range(3)),
+                          n=tuple(b["n"][d] << fine[d] for d in range(3)), lev=tuple(fine), lat=0))
+    og = _grid(cfg, coarse_right, state)
+    orig = og.get_blocks()
+    mid = regrid(og, fine_both)
+    og2 = AmrGrid(cfg, fine_both)
+    og2.set_blocks(mid)
+    back = regrid(og2, coarse_right)
+    for a, bb in zip(orig, back):
+        for x, y in zip(a, bb):
+            assert np.abs(x - y).max() <= 1e-14 * max(1.0, np.abs(x).max())
+
+
+def _cut(arrs, b):
+    o, n = b["org"], b["n"]
+    P, B1, B2, B3 = arrs
+    return (P[:, o[2]:o[2] + n[2], o[1]:o[1] + n[1], o[0]:o[0] + n[0]].copy(),
+            B1[o[2]:o[2] + n[2], o[1]:o[1] + n[1], o[0]:o[0] + n[0] + 1].copy(),
+            B2[o[2]:o[2] + n[2], o[1]:o[1] + n[1] + 1, o[0]:o[0] + n[0]].copy(),
+            B3[o[2]:o[2] + n[2] + 1, o[1]:o[1] + n[1], o[0]:o[0] + n[0]].copy())
+
+
+def test_linear_data_are_prolonged_and_restricted_exactly():
+    """primitives linear in the coordinates and the divergence-free linear field
+    B = (a x2 + b x3, c x3 + e x1, f x1 + h x2), given as exact cell and face averages,
+    come out as the exact averages at the new levels (away from the periodic seams,
+    where the data jump)"""
+    N = (16, 16, 16)
+    cfg = _mink(N)
+    L = [cfg["xhi"][d] - cfg["xlo"][d] for d in range(3)]
+    a, b_, c, e, f, h = 0.3, -0.2, 0.5, 0.1, -0.4, 0.25
+    pr = np.array([[1.0, 0.1, 0.2, -0.1], [0.5, -0.05, 0.1, 0.2], [0.1, 0.3, -0.2, 0.1],
+                   [-0.2, 0.1, 0.1, 0.3], [0.05, -0.1, 0.2, 0.1]])
+
+    def exact(lev):
+        Nl = [N[d] >> (1 - lev[d]) for d in range(3)]
+        dx = [L[d] / Nl[d] for d in range(3)]
+
+        def grid(ext):
+            k, j, i = np.meshgrid(np.arange(ext[2]), np.arange(ext[1]), np.arange(ext[0]),
+                                  indexing="ij")
+            return i, j, k
+
+        i, j, k = grid(Nl)
+        x = [(i + 0.5) * dx[0], (j + 0.5) * dx[1], (k + 0.5) * dx[2]]
+        P = np.array([p[0] + p[1] * x[0] + p[2] * x[1] + p[3] * x[2] for p in pr])
+        i, j, k = grid((Nl[0] + 1, Nl[1], Nl[2]))
+        B1 = a * (j + 0.5) * dx[1] + b_ * (k + 0.5) * dx[2]
+        i, j, k = grid((Nl[0], Nl[1] + 1, Nl[2]))
+        B2 = c * (k + 0.5) * dx[2] + e * (i + 0.5) * dx[0]
+        i, j, k = grid((Nl[0], Nl[1], Nl[2] + 1))
+        B3 = f * (i + 0.5) * dx[0] + h * (j + 0.5) * dx[1]
+        return (P, B1, B2, B3), Nl
+
+    old = halves(N, (1, 1, 1), True)
+    new = halves(N, (1, 1, 1), False)
+    og = AmrGrid(cfg, old)
+    og.set_blocks([_cut(exact(bl["lev"])[0], bl) for bl in old])
+    out = regrid(og, new)
+    for bl, st in zip(new, out):
+        ex, Nl = exact(bl["lev"])
+        want = _cut(ex, bl)
+        o = bl["org"]
+        for q in range(4):
+            got = st[q]
+            sel = []
+            for ax, d in enumerate((2, 1, 0)):
+                idx = np.arange(got.shape[got.ndim - 3 + ax]) + o[d]
+                sel.append((idx >= 3) & (idx <= Nl[d] - 3))
+            m = sel[0][:, None, None] & sel[1][None, :, None] & sel[2][None, None, :]
+            diff = np.abs(got - want[q])[..., m]
+            assert diff.size and diff.max() <= 1e-13, (bl["lev"], q, diff.max())
+
+
+def test_restriction_keeps_the_flux_through_every_coarse_face():
+    N = (16, 16, 8)
+    cfg = _mink(N)
+    state = random_periodic_state(N, seed=8, bamp=0.4)
+    old = halves(N, (1, 1, 1), True)
+    new = halves(N, (1, 1, 1), False)
+    og = _grid(cfg, old, state)
+    fineB = og.get_blocks()[0][1:]
+    out = regrid(og, new)
+    coarse = out[0]              # the left half, now at level 0
+    B1f, B2f, B3f = fineB
+    # flux through a coarse x1 face = mean of its 2x2 fine sub-faces (equal areas)
+    want = 0.25 * (B1f[0::2, 0::2, 0::2] + B1f[0::2, 1::2, 0::2] + B1f[1::2, 0::2, 0::2]
+                   + B1f[1::2, 1::2, 0::2])
+    assert np.abs(coarse[1] - want).max() <= 1e-15 * np.abs(want).max()
