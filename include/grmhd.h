@@ -239,6 +239,27 @@ int grmhd_cons2prim(grmhd_ctx* ctx, const grmhd_c2p_batch* batch, void* hip_stre
  * of variable 0. */
 int grmhd_divb(grmhd_ctx* ctx, double* max_abs, double* max_rel, double* field);
 
+/* Regrid (Sec. 3.3: blocks refined and derefined during a run): fills the interior
+ * cells and faces of context `to` (a new block layout over the same domain, created by
+ * grmhd_init_grid with its own buffers) from the state of context `from` at the end of
+ * its last step.  Both layouts have the same effective grid and finest level per
+ * dimension; each new block is, in every dimension, at the level of each old block it
+ * overlaps, one finer or one coarser (never finer in one dimension and coarser in
+ * another), and where it is coarser the old block boundaries fall on its cell faces.
+ * A new cell is copied from the old block covering it, restricted (sqrt(-g)-weighted
+ * mean of the covered primitives) or prolonged (the parent's primitives plus +-1/4 of
+ * the minmod-limited slope per refined dimension).  A new face is taken from the old
+ * block covering the cell above it (below it for a block's upper face): copied,
+ * restricted (mean of the fine sub-faces), or prolonged divergence-free (Balsara 2001):
+ * a fine face on a parent face is the parent face plus +-1/4 of its minmod slopes in the
+ * face's plane, a fine face inside a parent cell the face average of the parent cell's
+ * divergence-free reconstruction, so every new cell keeps div B = 0.  The old context's
+ * ghost values are refreshed first (its interior is not changed); the simulated time
+ * carries over.  Synchronises both contexts' streams; allocates and frees a small
+ * device table of boxes.  GRMHD_EINVAL for layouts that break the rules above,
+ * GRMHD_ESTATE when `from` holds its state outside the caller's buffers. */
+int grmhd_regrid(grmhd_ctx* from, grmhd_ctx* to);
+
 /* Host-only planner introspection for bit-exact checks (no device needed): copies the
  * ghost gather list for what = 0 (cell variables) or 1..3 (face component 1..3) as
  * int32 quadruples (dst block, dst local index, src block | flags << 24, src local

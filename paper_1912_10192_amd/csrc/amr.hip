@@ -253,4 +253,236 @@ void launch_means(const Launch& L, const MeanItem* items, int64_t n, double* X0,
   k_means<<<dim3((unsigned)((n + AT - 1) / AT)), dim3(AT), 0, L.stream>>>(items, n, X0, X1);
 }
 
+// ------------------------------------------------------------------ regrid
+// A new block layout filled from an old one (Sec. 3.3 refinement and derefinement; the
+// face field of new fine blocks by Balsara's 2001 divergence-free reconstruction).  Each
+// thread writes one interior cell (five primitives) or one face of a new block, reading
+// the old block that covers it in its padded arrays, ghosts included.
+
+// the box holding item t of a list (start: nops + 1 ascending offsets)
+__device__ __forceinline__ int regrid_box(const int64_t* __restrict__ start, int64_t nops,
+                                          int64_t t) {
+  int64_t lo = 0, hi = nops - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return (int)lo;
+}
+
+struct OldBlock {
+  BlockInfo bi;
+  int ng;
+  int o[3];
+  // element index in the padded arrays of global indices g (at the block's levels)
+  __device__ __forceinline__ int64_t at(int g0, int g1, int g2) const {
+    return ((int64_t)(g2 - o[2] + ng) * bi.np[1] + (g1 - o[1] + ng)) * bi.np[0] + (g0 - o[0] + ng);
+  }
+};
+
+__device__ __forceinline__ OldBlock old_block(const BlockInfo* __restrict__ blk, const RegridOp& op) {
+  OldBlock b;
+  b.bi = blk[op.ob];
+  b.ng = (b.bi.np[0] - b.bi.n[0] - 1) / 2;
+  b.o[0] = op.oo[0];
+  b.o[1] = op.oo[1];
+  b.o[2] = op.oo[2];
+  return b;
+}
+
+__global__ void __launch_bounds__(AT) k_regrid_cells(const BlockInfo* __restrict__ bf,
+                                                     const BlockInfo* __restrict__ bt, GeoTab G,
+                                                     const RegridOp* __restrict__ ops, int64_t nops,
+                                                     const int64_t* __restrict__ start,
+                                                     int64_t total, const double* __restrict__ Pf,
+                                                     double* __restrict__ Pt) {
+  const int64_t t = (int64_t)blockIdx.x * AT + threadIdx.x;
+  if (t >= total) return;
+  const int k = regrid_box(start, nops, t);
+  const RegridOp op = ops[k];
+  const int64_t q = t - start[k];
+  int l[3];
+  l[0] = op.lo[0] + (int)(q % op.ext[0]);
+  l[1] = op.lo[1] + (int)((q / op.ext[0]) % op.ext[1]);
+  l[2] = op.lo[2] + (int)(q / ((int64_t)op.ext[0] * op.ext[1]));
+  const int gc[3] = {op.on[0] + l[0], op.on[1] + l[1], op.on[2] + l[2]};
+  const BlockInfo bn = bt[op.nb];
+  const int ngn = (bn.np[0] - bn.n[0] - 1) / 2;
+  const int64_t dst = 5 * bn.off + ((int64_t)(l[2] + ngn) * bn.np[1] + (l[1] + ngn)) * bn.np[0] + (l[0] + ngn);
+  const OldBlock ob = old_block(bf, op);
+  const int64_t base = 5 * ob.bi.off;
+  const int rmin = min(op.r[0], min(op.r[1], op.r[2]));
+  const int rmax = max(op.r[0], max(op.r[1], op.r[2]));
+  double val[5];
+  if (rmin == 0 && rmax == 0) {
+    const int64_t s = ob.at(gc[0], gc[1], gc[2]);
+#pragma unroll
+    for (int v = 0; v < 5; v++) val[v] = Pf[base + (int64_t)v * ob.bi.vol + s];
+  } else if (rmax <= 0) {
+    // sqrt(-g)-weighted mean of the covered fine cells, k outermost, i innermost
+    double num[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, den = 0.0;
+    const int n0 = op.r[0] < 0 ? 2 : 1, n1 = op.r[1] < 0 ? 2 : 1, n2 = op.r[2] < 0 ? 2 : 1;
+    for (int ok = 0; ok < n2; ok++)
+      for (int oj = 0; oj < n1; oj++)
+        for (int oi = 0; oi < n0; oi++) {
+          const int f0 = (gc[0] << (-op.r[0])) + oi, f1 = (gc[1] << (-op.r[1])) + oj,
+                    f2 = (gc[2] << (-op.r[2])) + ok;
+          const int64_t s = ob.at(f0, f1, f2);
+          const double w = G.c[GDET * G.ncol + geo_col(G, ob.bi, f1 - ob.o[1] + ob.ng, f0 - ob.o[0] + ob.ng)];
+#pragma unroll
+          for (int v = 0; v < 5; v++)
+            num[v] = __dadd_rn(num[v], __dmul_rn(w, Pf[base + (int64_t)v * ob.bi.vol + s]));
+          den = __dadd_rn(den, w);
+        }
+#pragma unroll
+    for (int v = 0; v < 5; v++) val[v] = num[v] / den;
+  } else {
+    // parent plus +-1/4 of the minmod slope per refined dimension
+    const int pc[3] = {gc[0] >> op.r[0], gc[1] >> op.r[1], gc[2] >> op.r[2]};
+    const int64_t s0 = ob.at(pc[0], pc[1], pc[2]);
+    int64_t sm[3], sp[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      int a[3] = {pc[0], pc[1], pc[2]};
+      a[d] -= 1;
+      sm[d] = ob.at(a[0], a[1], a[2]);
+      a[d] += 2;
+      sp[d] = ob.at(a[0], a[1], a[2]);
+    }
+#pragma unroll
+    for (int v = 0; v < 5; v++) {
+      const double* X = Pf + base + (int64_t)v * ob.bi.vol;
+      const double c0 = X[s0];
+      double x = c0;
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        if (!op.r[d]) continue;
+        const double tw = (gc[d] & 1) ? 0.25 : -0.25;
+        x = __dadd_rn(x, __dmul_rn(tw, minmod(__dsub_rn(c0, X[sm[d]]), __dsub_rn(X[sp[d]], c0))));
+      }
+      val[v] = x;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 5; v++) Pt[dst + (int64_t)v * bn.vol] = val[v];
+}
+
+// minmod slope along x_e (per parent cell) of the B^c faces at global face index g
+__device__ __forceinline__ double face_slope(const OldBlock& ob, const double* __restrict__ X,
+                                             const int g[3], int e) {
+  int a[3] = {g[0], g[1], g[2]};
+  const double c = X[ob.at(a[0], a[1], a[2])];
+  a[e] -= 1;
+  const double m = X[ob.at(a[0], a[1], a[2])];
+  a[e] += 2;
+  const double p = X[ob.at(a[0], a[1], a[2])];
+  return minmod(__dsub_rn(c, m), __dsub_rn(p, c));
+}
+
+__global__ void __launch_bounds__(AT) k_regrid_faces(const BlockInfo* __restrict__ bf,
+                                                     const BlockInfo* __restrict__ bt,
+                                                     const RegridOp* __restrict__ ops, int64_t nops,
+                                                     const int64_t* __restrict__ start,
+                                                     int64_t t1, int64_t t2, int64_t t3,
+                                                     const double* __restrict__ Bf,
+                                                     double* __restrict__ Bt) {
+  int64_t t = (int64_t)blockIdx.x * AT + threadIdx.x;
+  int d;
+  if (t < t1) {
+    d = 0;
+  } else if (t < t1 + t2) {
+    d = 1;
+    t -= t1;
+  } else if (t < t1 + t2 + t3) {
+    d = 2;
+    t -= t1 + t2;
+  } else {
+    return;
+  }
+  const int64_t* st = start + (int64_t)(d + 1) * (nops + 1);
+  const int k = regrid_box(st, nops, t);
+  const RegridOp op = ops[k];
+  const int64_t q = t - st[k];
+  int ext[3] = {op.ext[0], op.ext[1], op.ext[2]};
+  ext[d] += op.top[d];
+  int l[3];
+  l[0] = op.lo[0] + (int)(q % ext[0]);
+  l[1] = op.lo[1] + (int)((q / ext[0]) % ext[1]);
+  l[2] = op.lo[2] + (int)(q / ((int64_t)ext[0] * ext[1]));
+  const int gf[3] = {op.on[0] + l[0], op.on[1] + l[1], op.on[2] + l[2]};
+  const BlockInfo bn = bt[op.nb];
+  const int ngn = (bn.np[0] - bn.n[0] - 1) / 2;
+  const int64_t dst = 3 * bn.off + (int64_t)d * bn.vol +
+                      ((int64_t)(l[2] + ngn) * bn.np[1] + (l[1] + ngn)) * bn.np[0] + (l[0] + ngn);
+  const OldBlock ob = old_block(bf, op);
+  const double* X = Bf + 3 * ob.bi.off + (int64_t)d * ob.bi.vol;
+  const int rmin = min(op.r[0], min(op.r[1], op.r[2]));
+  const int rmax = max(op.r[0], max(op.r[1], op.r[2]));
+  double val;
+  if (rmin == 0 && rmax == 0) {
+    val = X[ob.at(gf[0], gf[1], gf[2])];
+  } else if (rmax <= 0) {
+    // mean of the fine sub-faces, k outermost, i innermost
+    const int n0 = (d != 0 && op.r[0] < 0) ? 2 : 1, n1 = (d != 1 && op.r[1] < 0) ? 2 : 1,
+              n2 = (d != 2 && op.r[2] < 0) ? 2 : 1;
+    double acc = 0.0;
+    for (int ok = 0; ok < n2; ok++)
+      for (int oj = 0; oj < n1; oj++)
+        for (int oi = 0; oi < n0; oi++)
+          acc = __dadd_rn(acc, X[ob.at((gf[0] << (-op.r[0])) + oi, (gf[1] << (-op.r[1])) + oj,
+                                       (gf[2] << (-op.r[2])) + ok)]);
+    val = __dmul_rn(acc, 1.0 / (n0 * n1 * n2));
+  } else {
+    int pc[3] = {gf[0] >> op.r[0], gf[1] >> op.r[1], gf[2] >> op.r[2]};
+    double tw[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int x = 0; x < 3; x++)
+      if (x != d && op.r[x]) tw[x] = (gf[x] & 1) ? 0.25 : -0.25;
+    if (op.r[d] == 0 || (gf[d] & 1) == 0) {
+      // on a face of the parent cell: the parent face plus +-1/4 of its slopes
+      val = X[ob.at(pc[0], pc[1], pc[2])];
+#pragma unroll
+      for (int e = 0; e < 3; e++)
+        if (e != d && op.r[e]) val = __dadd_rn(val, __dmul_rn(tw[e], face_slope(ob, X, pc, e)));
+    } else {
+      // inside the parent cell: the face average of the divergence-free reconstruction
+      int hi[3] = {pc[0], pc[1], pc[2]};
+      hi[d] += 1;
+      const double bm = X[ob.at(pc[0], pc[1], pc[2])], bp = X[ob.at(hi[0], hi[1], hi[2])];
+      val = __dmul_rn(0.5, __dadd_rn(bm, bp));
+#pragma unroll
+      for (int e = 0; e < 3; e++) {
+        if (e == d) continue;
+        const double* Y = Bf + 3 * ob.bi.off + (int64_t)e * ob.bi.vol;
+        int ep[3] = {pc[0], pc[1], pc[2]};
+        ep[e] += 1;
+        const double s_lo = face_slope(ob, Y, pc, d), s_hi = face_slope(ob, Y, ep, d);
+        const double f = ob.bi.dx[d] / (8.0 * ob.bi.dx[e]);
+        val = __dadd_rn(val, __dmul_rn(f, __dsub_rn(s_hi, s_lo)));
+      }
+#pragma unroll
+      for (int e = 0; e < 3; e++) {
+        if (e == d || !op.r[e]) continue;
+        const double sl = __dadd_rn(face_slope(ob, X, pc, e), face_slope(ob, X, hi, e));
+        val = __dadd_rn(val, __dmul_rn(__dmul_rn(tw[e], 0.5), sl));
+      }
+    }
+  }
+  Bt[dst] = val;
+}
+
+void launch_regrid(const Launch& Lf, const Launch& Lt, const RegridOp* ops, int64_t nops,
+                   const int64_t* start, const int64_t total[4], const double* Pf,
+                   const double* Bf, double* Pt, double* Bt) {
+  if (nops <= 0) return;
+  if (total[0] > 0)
+    k_regrid_cells<<<dim3((unsigned)((total[0] + AT - 1) / AT)), dim3(AT), 0, Lf.stream>>>(
+        Lf.blk, Lt.blk, Lf.geo, ops, nops, start, total[0], Pf, Pt);
+  const int64_t nf = total[1] + total[2] + total[3];
+  if (nf > 0)
+    k_regrid_faces<<<dim3((unsigned)((nf + AT - 1) / AT)), dim3(AT), 0, Lf.stream>>>(
+        Lf.blk, Lt.blk, ops, nops, start, total[1], total[2], total[3], Bf, Bt);
+}
+
 }  // namespace grmhd

@@ -13,6 +13,7 @@
 #include <complex>
 #include <cstdint>
 #include <cstdlib>
+#include <cstddef>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -2482,6 +2483,122 @@ int grmhd_divb(grmhd_ctx* c, double* max_abs, double* max_rel, double* field) {
   if (max_abs) *max_abs = a;
   if (max_rel) *max_rel = r;
   return GRMHD_OK;
+}
+
+// The boxes of a regrid: every (new block, old block) overlap, in the new block's cells,
+// with the level relation checked (one level apart at most per dimension, never finer
+// in one dimension and coarser in another; where the new block is coarser, the old
+// block's boundaries fall on its cell faces)
+static int regrid_ops(const Plan& po, const Plan& pn, std::vector<RegridOp>& ops) {
+  for (int d = 0; d < 3; d++) {
+    if (po.d.n_eff[d] != pn.d.n_eff[d] || po.lmax[d] != pn.lmax[d] ||
+        po.d.xmin[d] != pn.d.xmin[d] || po.d.xmax[d] != pn.d.xmax[d])
+      return fail(GRMHD_EINVAL, "regrid: the layouts differ in domain, effective grid or finest levels");
+  }
+  if (po.d.coords != pn.d.coords || po.d.spin_a != pn.d.spin_a)
+    return fail(GRMHD_EINVAL, "regrid: the layouts differ in coordinates");
+  if (po.d.n_ghost < 2) return fail(GRMHD_EINVAL, "regrid needs at least two ghost layers");
+  for (size_t nb = 0; nb < pn.blocks.size(); nb++) {
+    const grmhd_block_desc& bn = pn.blocks[nb];
+    int64_t nlo[3], nhi[3];
+    for (int d = 0; d < 3; d++) {
+      const int sh = pn.lmax[d] - bn.lev[d];
+      nlo[d] = bn.org[d] << sh;
+      nhi[d] = (bn.org[d] + bn.n[d]) << sh;
+    }
+    int64_t covered = 0;
+    for (size_t ob = 0; ob < po.blocks.size(); ob++) {
+      const grmhd_block_desc& bo = po.blocks[ob];
+      int64_t lo[3], hi[3];
+      bool hit = true;
+      for (int d = 0; d < 3; d++) {
+        const int sh = po.lmax[d] - bo.lev[d];
+        lo[d] = std::max(nlo[d], bo.org[d] << sh);
+        hi[d] = std::min(nhi[d], (bo.org[d] + bo.n[d]) << sh);
+        hit = hit && lo[d] < hi[d];
+      }
+      if (!hit) continue;
+      RegridOp op;
+      op.nb = (int32_t)nb;
+      op.ob = (int32_t)ob;
+      int rmin = 0, rmax = 0;
+      int64_t vol = 1;
+      for (int d = 0; d < 3; d++) {
+        op.r[d] = bn.lev[d] - bo.lev[d];
+        rmin = std::min(rmin, op.r[d]);
+        rmax = std::max(rmax, op.r[d]);
+        const int sh = pn.lmax[d] - bn.lev[d];
+        const int64_t w = (int64_t)1 << sh;
+        if (lo[d] % w != 0 || hi[d] % w != 0)
+          return fail(GRMHD_EINVAL, "regrid: an old block boundary cuts a cell of a new block");
+        op.lo[d] = (int32_t)(lo[d] / w - bn.org[d]);
+        op.ext[d] = (int32_t)((hi[d] - lo[d]) / w);
+        op.top[d] = (op.lo[d] + op.ext[d] == bn.n[d]) ? 1 : 0;
+        op.on[d] = (int32_t)bn.org[d];
+        op.oo[d] = (int32_t)bo.org[d];
+        vol *= op.ext[d];
+      }
+      if (rmin < -1 || rmax > 1 || (rmin < 0 && rmax > 0))
+        return fail(GRMHD_EINVAL, "regrid: a new block is more than one level from an old block "
+                                  "it overlaps, or finer in one dimension and coarser in another");
+      covered += vol;
+      ops.push_back(op);
+    }
+    if (covered != (int64_t)bn.n[0] * bn.n[1] * bn.n[2])
+      return fail(GRMHD_EINVAL, "regrid: the old layout does not cover a new block");
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_regrid(grmhd_ctx* from, grmhd_ctx* to) {
+  if (!from || !to || from == to) return fail(GRMHD_EINVAL, "regrid needs two distinct contexts");
+  if (from->b_in_alt) return fail(GRMHD_ESTATE, "state not in the caller's buffers");
+  std::vector<RegridOp> ops;
+  if (int rc = regrid_ops(from->plan, to->plan, ops)) return rc;
+  const int64_t nops = (int64_t)ops.size();
+  std::vector<int64_t> start(4 * (nops + 1), 0);
+  int64_t total[4] = {0, 0, 0, 0};
+  for (int k = 0; k < 4; k++) {
+    int64_t run = 0;
+    for (int64_t q = 0; q < nops; q++) {
+      start[k * (nops + 1) + q] = run;
+      int64_t e[3] = {ops[q].ext[0], ops[q].ext[1], ops[q].ext[2]};
+      if (k > 0) e[k - 1] += ops[q].top[k - 1];
+      run += e[0] * e[1] * e[2];
+    }
+    start[k * (nops + 1) + nops] = run;
+    total[k] = run;
+  }
+  RegridOp* dops = nullptr;
+  int64_t* dstart = nullptr;
+  HIPCHK(hipMalloc(&dops, sizeof(RegridOp) * std::max<int64_t>(nops, 1)));
+  HIPCHK(hipMalloc(&dstart, sizeof(int64_t) * start.size()));
+  hipStream_t st = from->stream;
+  int rc = GRMHD_OK;
+  hipError_t e = hipMemcpyAsync(dops, ops.data(), sizeof(RegridOp) * nops, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dstart, start.data(), sizeof(int64_t) * start.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    // the new context's work must not overlap the copy: it starts on from's stream after
+    // everything queued on to's stream, and to's stream waits for the regrid
+    e = hipStreamSynchronize(to->stream);
+  }
+  if (e == hipSuccess) {
+    fill_ghosts(from, from->bufs.prim, from->bufs.bface);
+    launch_regrid(from->L, to->L, dops, nops, dstart, total, from->bufs.prim, from->bufs.bface,
+                  to->bufs.prim, to->bufs.bface);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess)   // the simulation time carries over
+    e = hipMemcpyAsync((char*)to->L.cnt + offsetof(Counters, t_sim),
+                       (const char*)from->L.cnt + offsetof(Counters, t_sim), sizeof(double),
+                       hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) rc = fail(GRMHD_EHIP, std::string("regrid: ") + hipGetErrorString(e));
+  (void)hipFree(dops);
+  (void)hipFree(dstart);
+  to->b_in_alt = false;
+  return rc;
 }
 
 int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, size_t* bytes) {

@@ -78,6 +78,16 @@ struct AmrLists {
 struct AmrSample {
   int32_t blkf, loc, mask, pad;
 };
+
+// One box of a regrid: the cells lo .. lo + ext - 1 (local, at the new block's levels)
+// of new block nb, all covered by old block ob; r = new level - old level per dimension
+// (-1: restricted, 0: copied, +1: prolonged); on, oo: the two blocks' origins, each at its
+// own levels; top: the box reaches nb's upper face in that dimension, whose faces it then
+// also fills
+struct RegridOp {
+  int32_t nb, ob;
+  int32_t lo[3], ext[3], r[3], on[3], oo[3], top[3];
+};
 enum { AM_PDIMS = 7, AM_UPPER_SHIFT = 4, AM_TWO = 256, AM_FLAGS_SHIFT = 16 };
 
 // A value that is the mean of n (1, 2 or 4) elements of one array, per component:
@@ -272,6 +282,12 @@ void launch_amr_ghosts(const Launch& L, const AmrLists& A, const AmrSample* samp
                        const double* Pmain, const double* Pold, const double* Pcur, double* Pdst,
                        const double* Bmain, const double* Bold, const double* Bcur, double* Bdst,
                        double w);
+// a regrid: the new layout's interior cells and faces (the boxes' cells, then faces of
+// each direction: start[k][op], k = 0 cells, 1..3 faces, with total[k] = start[k][nops])
+// from the old layout's padded state, whose ghosts are filled
+void launch_regrid(const Launch& Lf, const Launch& Lt, const RegridOp* ops, int64_t nops,
+                   const int64_t* start, const int64_t total[4], const double* Pf,
+                   const double* Bf, double* Pt, double* Bt);
 // the items of a mean list: kind 0 items on X0, the others on X1
 void launch_means(const Launch& L, const MeanItem* items, int64_t n, double* X0, double* X1);
 // local time stepping (lat.hip)

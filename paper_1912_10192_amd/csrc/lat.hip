@@ -354,13 +354,14 @@ void launch_sync(const Launch& L, const SyncCell* cells, int64_t ncell, const Sy
   if (nface > 0)
     hipLaunchKernelGGL(k_sync_faces, dim3(cdv(nface, LT)), dim3(LT), 0, L.stream, L, faces, nface,
                        B, regE, ne);
-  if (ncell > 0)
+  if (ncell > 0) {
     if (L.ph.floor_drift)
       hipLaunchKernelGGL(k_sync_c2p<true>, dim3(cdv(ncell, LT)), dim3(LT), 0, L.stream, L, cells,
                          ncell, P, B, Ubuf);
     else
       hipLaunchKernelGGL(k_sync_c2p<false>, dim3(cdv(ncell, LT)), dim3(LT), 0, L.stream, L, cells,
                          ncell, P, B, Ubuf);
+  }
 }
 
 void launch_dt_final_lat(const Launch& L, const double* part, int64_t n, int gridx,

@@ -31,7 +31,8 @@ EXPORTS = ("grmhd_sizes", "grmhd_block_layout", "grmhd_init_grid", "grmhd_step",
            "grmhd_mlp_sizes", "grmhd_mlp_train_step", "grmhd_mlp_gradients", "grmhd_mlp_pack",
            "grmhd_mlp_forward", "grmhd_prim2cons_batch", "grmhd_mlp_dataset",
            "grmhd_mlp_normalize", "grmhd_extract_cells", "grmhd_destroy", "grmhd_last_error",
-           "grmhd_autotune", "grmhd_set_variants", "grmhd_mlp_train_step_noalloc")
+           "grmhd_autotune", "grmhd_set_variants", "grmhd_mlp_train_step_noalloc",
+           "grmhd_regrid")
 
 
 class BlockDesc(C.Structure):
@@ -125,6 +126,7 @@ def lib():
         L.grmhd_mlp_normalize.argtypes = [vp, i64, i32, vp, vp, i32, vp]
         L.grmhd_extract_cells.argtypes = [vp, vp, vp, vp]
         L.grmhd_destroy.argtypes = [C.c_void_p]
+        L.grmhd_regrid.argtypes = [C.c_void_p, C.c_void_p]
         L.grmhd_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -337,6 +339,7 @@ class Grid:
         import torch
 
         self.torch = torch
+        self.cfg, self.batched, self.mlp_blob = dict(cfg), batched, mlp_blob
         self.desc = Desc(cfg, blocks=blocks, batched=batched, profile=profile, mlp_blob=mlp_blob)
         nprim, nbface, nwork = self.desc.sizes()
         self.device = torch.device(device)
@@ -415,6 +418,14 @@ class Grid:
     def set_variants(self, flux=(2, 2, 2), update=0, split=0):
         choice = (C.c_int32 * 5)(flux[0], flux[1], flux[2], update, split)
         _check(lib().grmhd_set_variants(self.ctx, choice))
+
+    def regrid(self, blocks, batched=None):
+        """a new Grid of the same workload on the block layout `blocks`, filled from this
+        grid's state (grmhd_regrid); this grid keeps its state"""
+        new = Grid(self.cfg, blocks=blocks, batched=self.batched if batched is None else batched,
+                   mlp_blob=self.mlp_blob)
+        _check(lib().grmhd_regrid(self.ctx, new.ctx))
+        return new
 
     def divb(self):
         a, r = C.c_double(), C.c_double()
