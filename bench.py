@@ -300,6 +300,51 @@ def roofline(cls_ms, cls_n, blocks, spl):
     return out
 
 
+def regrid_leg(cfg, blocks, bs, sync, log):
+    """Refinement during the run at full size (grmhd_regrid): the headline layout, after
+    two cycles, regridded to its polar caps refined in phi and back.  Times the new
+    layout's context set-up (planner and tables) and each regrid call; the round trip
+    must return the state (prolongation along x3 followed by restriction is exact up to
+    rounding, sqrt(-g) not varying along x3), and the refined layout runs a cycle."""
+    import numpy as np
+
+    from paper_1912_10192_amd import configs, grmhd
+
+    fine = configs.refine_caps_phi(blocks)
+    g = grmhd.Grid(cfg, blocks=blocks, batched=1)
+    g.set_blocks(bs)
+    g.step(2, stats=False)
+    sync()
+    t0 = time.perf_counter()
+    g2 = grmhd.Grid(cfg, blocks=fine, batched=1)
+    sync()
+    t_init = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    grmhd._check(grmhd.lib().grmhd_regrid(g.ctx, g2.ctx))
+    t_up = time.perf_counter() - t0
+    g3 = grmhd.Grid(cfg, blocks=blocks, batched=1)
+    sync()
+    t0 = time.perf_counter()
+    grmhd._check(grmhd.lib().grmhd_regrid(g2.ctx, g3.ctx))
+    t_down = time.perf_counter() - t0
+    a, b = g.get_blocks(), g3.get_blocks()
+    err = 0.0
+    for x, y in zip(a, b):
+        for u, v in zip(x, y):
+            err = max(err, float(np.abs(u - v).max() / max(np.abs(u).max(), 1e-300)))
+    _, div_rel = g2.divb()
+    st = g2.step(1, stats=True)
+    cells = sum(bb["n"][0] * bb["n"][1] * bb["n"][2] for bb in fine)
+    log(f"[bench] regrid: caps refined in {t_up * 1e3:.1f} ms, back in {t_down * 1e3:.1f} ms, "
+        f"new context {t_init:.2f} s, round trip {err:.1e}")
+    del g, g2, g3
+    return {"layout": "headline layout <-> polar caps refined in phi (levels (0,0,0) -> (0,0,1))",
+            "cells_refined_layout": cells, "context_setup_s": t_init,
+            "regrid_refine_ms": t_up * 1e3, "regrid_derefine_ms": t_down * 1e3,
+            "round_trip_max_rel": err, "divb_rel_refined": div_rel,
+            "bad_states_next_cycle": st.bad_states}
+
+
 def disk_leg(args, blob, sync, log):
     """the large tilted thin disk: effective 1024x384x384 on r in [1.2, 1000], density-
     refined blocks with phi-halved polar caps, five time levels (a cycle is 16 finest
@@ -405,13 +450,14 @@ def main():
         gsteps = args.steps * head["substeps_per_cycle"]
         glob, _ = run_leg("global_dt", cfg, flat, bs, 2, None, gsteps, args.warmup, args.runs,
                           sync, log)
+        rg = regrid_leg(cfg, blocks, bs, sync, log)
         disk = disk_leg(args, blob, sync, log)
         cls_ms, cls_n, spl = profiled_classes(cfg, blocks, bs, blob, tune, args.steps, sync, log)
         out.update({
             "roofline": roofline(cls_ms, cls_n, blocks, spl),
             "kernel_ms_per_cycle": {k: v / args.steps for k, v in cls_ms.items()},
             "batched": batched, "plain": plain, "global_dt": glob, "disk5": disk,
-            "emf_upwind": upw,
+            "emf_upwind": upw, "regrid": rg,
             "emf_upwind_cost": head["value_real"] / upw["value_real"],
             "floor_drift": drift,
             "floor_drift_cost": head["value_real"] / drift["value_real"],

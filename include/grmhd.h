@@ -242,8 +242,9 @@ int grmhd_divb(grmhd_ctx* ctx, double* max_abs, double* max_rel, double* field);
 /* Regrid (Sec. 3.3: blocks refined and derefined during a run): fills the interior
  * cells and faces of context `to` (a new block layout over the same domain, created by
  * grmhd_init_grid with its own buffers) from the state of context `from` at the end of
- * its last step.  Both layouts have the same effective grid and finest level per
- * dimension; each new block is, in every dimension, at the level of each old block it
+ * its last step.  Both layouts cover the same domain with the same level-0 grid
+ * (n_eff >> lmax per dimension); the new one may add or drop a finest level, its n_eff
+ * then doubled or halved.  Each new block is, in every dimension, at the level of each old block it
  * overlaps, one finer or one coarser (never finer in one dimension and coarser in
  * another), and where it is coarser the old block boundaries fall on its cell faces.
  * A new cell is copied from the old block covering it, restricted (sqrt(-g)-weighted

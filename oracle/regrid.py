@@ -6,10 +6,12 @@ divergence-free prolongation after Balsara 2001).
 TEST INFRASTRUCTURE ONLY.  Shares no code with the HIP path.
 
 Rules (readings stated in the design notes):
-  * Both layouts cover the same domain and have the same finest level in each dimension.
-    Every new block lies, in each dimension, at the level of each old block it overlaps,
-    one level finer, or one coarser, and never finer in one dimension and coarser in
-    another; where it is coarser, the old blocks' boundaries fall on its cell faces.
+  * Both layouts cover the same domain with the same level-0 grid; the new one may add or
+    drop a finest level (its effective grid cfg["n"] then doubles or halves: the property
+    `N` here).  Every new block lies, in each dimension, at the level of each old block it
+    overlaps, one level finer, or one coarser, and never finer in one dimension and
+    coarser in another; where it is coarser, the old blocks' boundaries fall on its cell
+    faces.
   * The old state is taken at the end of a cycle (every block at the same time), with
     every ghost value filled by the ghost rules of the old layout.
   * A new cell takes its value from the old block that covers it: a copy at the same
@@ -76,9 +78,10 @@ class Regrid:
         self.g = old.g
         self.new = [dict(b, lev=tuple(int(x) for x in b.get("lev", (0, 0, 0)))) for b in new_blocks]
         lm = tuple(max(b["lev"][d] for b in self.new) for d in range(3))
-        if lm != old.Lmax:
-            raise ValueError("both layouts must have the same finest level per dimension")
-        self.Lmax = old.Lmax
+        # cells are located at the finer of the two layouts' finest levels; the new layout
+        # may add or drop a finest level (its effective grid doubles or halves)
+        self.Lmax = tuple(max(lm[d], old.Lmax[d]) for d in range(3))
+        self.N = tuple((old.N[d] >> old.Lmax[d]) << lm[d] for d in range(3))
         # the old state at the cycle's end, every ghost filled from it
         for i in range(len(old.blocks)):
             old.Pold[i] = old.P[i].copy()

@@ -156,6 +156,45 @@ def amr_lat_blocks(n, shapes=None, lat_edges=(2.4, 4.8, 9.6), xlo=None, xhi=None
     return out
 
 
+def refine_caps_phi(blocks):
+    """the layout of amr_lat_blocks with the polar caps refined once in phi (levels
+    (0, 0, 0) -> (0, 0, 1), each cap block twice as many cells along x3), the caps then
+    matching the mid-latitude bands; time levels kept"""
+    out = []
+    for b in blocks:
+        if tuple(b["lev"]) == (0, 0, 0):
+            b = dict(b, lev=(0, 0, 1), org=(b["org"][0], b["org"][1], 2 * b["org"][2]),
+                     n=(b["n"][0], b["n"][1], 2 * b["n"][2]))
+        out.append(dict(b))
+    return out
+
+
+def split_block(b, n2_level, polar=None):
+    """the children of block b refined once (Sec. 3.3): eight, one level finer in every
+    dimension and each with b's cell counts; or, for a block touching the polar axis
+    (polar = "north" at x2 = 0, "south" at x2 = pi; n2_level: cells along x2 at b's x2
+    level), six: the two children along the axis keep b's phi level (refined in r and
+    theta, one per r half, spanning b's phi range) and the four further from the axis are
+    refined in all three dimensions, so cells near the axis stay close to cubic"""
+    l1, l2, l3 = b["lev"]
+    o1, o2, o3 = b["org"]
+    n1, n2, n3 = b["n"]
+    if polar == "north" and o2 != 0 or polar == "south" and o2 + n2 != n2_level:
+        raise ValueError("a six-child split needs a block on the polar axis")
+    out = []
+    for j in range(2):
+        on_axis = (polar == "north" and j == 0) or (polar == "south" and j == 1)
+        for h in range(2):
+            if on_axis:
+                out.append(dict(b, lev=(l1 + 1, l2 + 1, l3), org=(2 * o1 + h * n1, 2 * o2 + j * n2, o3),
+                                n=(n1, n2, n3)))
+                continue
+            for k in range(2):
+                out.append(dict(b, lev=(l1 + 1, l2 + 1, l3 + 1),
+                                org=(2 * o1 + h * n1, 2 * o2 + j * n2, 2 * o3 + k * n3), n=(n1, n2, n3)))
+    return out
+
+
 # Batched refinement + local time stepping as specified: effective 512x256x256 in 1344
 # blocks of 64x32x32, 32x16x16 and 16x8x8 (amr_lat_blocks), phi halved per level toward
 # each pole (3 levels), 4 time levels by radius, 25 cycles

@@ -2490,10 +2490,16 @@ int grmhd_divb(grmhd_ctx* c, double* max_abs, double* max_rel, double* field) {
 // in one dimension and coarser in another; where the new block is coarser, the old
 // block's boundaries fall on its cell faces)
 static int regrid_ops(const Plan& po, const Plan& pn, std::vector<RegridOp>& ops) {
+  // positions in cells of the finer of the two finest levels per dimension (the new
+  // layout may add or drop a finest level: its effective grid then doubles or halves)
+  int ls[3];
   for (int d = 0; d < 3; d++) {
-    if (po.d.n_eff[d] != pn.d.n_eff[d] || po.lmax[d] != pn.lmax[d] ||
+    if ((po.d.n_eff[d] >> po.lmax[d]) != (pn.d.n_eff[d] >> pn.lmax[d]) ||
+        ((int64_t)(po.d.n_eff[d] >> po.lmax[d]) << po.lmax[d]) != po.d.n_eff[d] ||
+        ((int64_t)(pn.d.n_eff[d] >> pn.lmax[d]) << pn.lmax[d]) != pn.d.n_eff[d] ||
         po.d.xmin[d] != pn.d.xmin[d] || po.d.xmax[d] != pn.d.xmax[d])
-      return fail(GRMHD_EINVAL, "regrid: the layouts differ in domain, effective grid or finest levels");
+      return fail(GRMHD_EINVAL, "regrid: the layouts differ in domain or in their level-0 grid");
+    ls[d] = std::max(po.lmax[d], pn.lmax[d]);
   }
   if (po.d.coords != pn.d.coords || po.d.spin_a != pn.d.spin_a)
     return fail(GRMHD_EINVAL, "regrid: the layouts differ in coordinates");
@@ -2502,7 +2508,7 @@ static int regrid_ops(const Plan& po, const Plan& pn, std::vector<RegridOp>& ops
     const grmhd_block_desc& bn = pn.blocks[nb];
     int64_t nlo[3], nhi[3];
     for (int d = 0; d < 3; d++) {
-      const int sh = pn.lmax[d] - bn.lev[d];
+      const int sh = ls[d] - bn.lev[d];
       nlo[d] = bn.org[d] << sh;
       nhi[d] = (bn.org[d] + bn.n[d]) << sh;
     }
@@ -2512,7 +2518,7 @@ static int regrid_ops(const Plan& po, const Plan& pn, std::vector<RegridOp>& ops
       int64_t lo[3], hi[3];
       bool hit = true;
       for (int d = 0; d < 3; d++) {
-        const int sh = po.lmax[d] - bo.lev[d];
+        const int sh = ls[d] - bo.lev[d];
         lo[d] = std::max(nlo[d], bo.org[d] << sh);
         hi[d] = std::min(nhi[d], (bo.org[d] + bo.n[d]) << sh);
         hit = hit && lo[d] < hi[d];
@@ -2527,7 +2533,7 @@ static int regrid_ops(const Plan& po, const Plan& pn, std::vector<RegridOp>& ops
         op.r[d] = bn.lev[d] - bo.lev[d];
         rmin = std::min(rmin, op.r[d]);
         rmax = std::max(rmax, op.r[d]);
-        const int sh = pn.lmax[d] - bn.lev[d];
+        const int sh = ls[d] - bn.lev[d];
         const int64_t w = (int64_t)1 << sh;
         if (lo[d] % w != 0 || hi[d] % w != 0)
           return fail(GRMHD_EINVAL, "regrid: an old block boundary cuts a cell of a new block");

@@ -421,9 +421,13 @@ class Grid:
 
     def regrid(self, blocks, batched=None):
         """a new Grid of the same workload on the block layout `blocks`, filled from this
-        grid's state (grmhd_regrid); this grid keeps its state"""
-        new = Grid(self.cfg, blocks=blocks, batched=self.batched if batched is None else batched,
-                   mlp_blob=self.mlp_blob)
+        grid's state (grmhd_regrid); this grid keeps its state.  Where the new layout adds
+        or drops a finest level, its effective grid doubles or halves in that dimension."""
+        old_l = [max(int(b.lev[d]) for b in self.desc.blocks) for d in range(3)]
+        new_l = [max(int(b.get("lev", (0, 0, 0))[d]) for b in blocks) for d in range(3)]
+        n = tuple((int(self.cfg["n"][d]) >> old_l[d]) << new_l[d] for d in range(3))
+        new = Grid(dict(self.cfg, n=n), blocks=blocks,
+                   batched=self.batched if batched is None else batched, mlp_blob=self.mlp_blob)
         _check(lib().grmhd_regrid(self.ctx, new.ctx))
         return new
 

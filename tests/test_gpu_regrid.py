@@ -117,14 +117,83 @@ def test_torus_regrid_after_lat_cycles_matches_oracle():
 
 
 def test_regrid_rejects_layouts_that_break_the_rules():
+    """a new block finer than the old block under it in one dimension and coarser in
+    another: the library refuses the regrid and leaves both grids as they were"""
     N = (16, 16, 8)
     cfg = _mink(N)
     state = random_periodic_state(N, seed=3)
-    old = halves(N, (1, 1, 1), True)
-    lmax = (1, 1, 1)
+    old = halves(N, (1, 1, 0), True)          # left (1, 1, 0), right (0, 0, 0)
     g = grmhd.Grid(cfg, blocks=old)
-    g.set_blocks(initdata.block_states(state, old, lmax))
-    # a different finest level
-    bad = halves(N, (1, 1, 0), False)
-    with pytest.raises(grmhd.GrmhdError, match="finest levels"):
-        g.regrid(bad)
+    g.set_blocks(initdata.block_states(state, old, (1, 1, 0)))
+    before = g.get_blocks()
+    new = [dict(org=(0, 0, 0), n=(4, 8, 16), lev=(0, 0, 1), lat=0),
+           dict(org=(4, 0, 0), n=(4, 8, 8), lev=(0, 0, 0), lat=0)]
+    with pytest.raises(grmhd.GrmhdError, match="one level"):
+        g.regrid(new)
+    for a, b in zip(before, g.get_blocks()):
+        for x, y in zip(a, b):
+            assert (x == y).all()
+
+
+def test_full_size_layout_regrid_round_trip():
+    """the 1344-block torus layout (effective 512x256x256, four time levels) after a
+    cycle, its polar caps refined in phi and derefined again: prolongation along x3 then
+    restriction returns every value to rounding (sqrt(-g) does not vary along x3), the
+    refined layout is divergence-free and runs a cycle with no unphysical state"""
+    cfg = dict(configs.TORUS_AMR3)
+    blocks = configs.amr_lat_blocks(cfg["n"], lat_edges=cfg["lat_edges"])
+    lmax = [max(b["lev"][d] for b in blocks) for d in range(3)]
+    say("[regrid] full-size torus layout: building the state")
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    bs = initdata.block_states(state, blocks, lmax)
+    del state
+    g = grmhd.Grid(cfg, blocks=blocks, batched=1)
+    g.set_blocks(bs)
+    g.step(1, stats=False)
+    say("[regrid] caps refined in phi")
+    g2 = g.regrid(configs.refine_caps_phi(blocks))
+    a, r = g2.divb()
+    say(f"  divB rel {r:.2e}")
+    assert r < 1e-12
+    say("[regrid] and back")
+    g3 = g2.regrid(blocks)
+    worst = 0.0
+    for x, y in zip(g.get_blocks(), g3.get_blocks()):
+        for u, v in zip(x, y):
+            worst = max(worst, float(abs(u - v).max() / max(abs(u).max(), 1e-300)))
+    say(f"  round trip {worst:.1e}")
+    assert worst <= 1e-14
+    del g, g3
+    st = g2.step(1, stats=True)
+    assert st.bad_states == 0
+
+
+def test_six_child_polar_split_matches_oracle():
+    """every block of a level-0 Kerr-Schild sphere (four blocks, each on a polar axis)
+    split into six children after a step, adding a finest level (the effective grid
+    doubles); parity after the regrid and after a further step on the new layout"""
+    from tests.test_oracle_regrid import ks_sphere, polar_quarters, polar_state, six_child_layout
+
+    N0 = (16, 16, 8)
+    cfg = dict(ks_sphere(N0), rho_fl_c=1e-6, u_fl_c=1e-8)
+    old = polar_quarters(N0)
+    bs = [tuple(x) for x in initdata.block_states(polar_state(cfg, 9), old, (0, 0, 0))]
+    grid, ref, worst = run_pair(cfg, old, None, 1, bs=bs)
+    assert max(worst.values()) <= TOL, worst
+    new = six_child_layout(N0)
+    say("[regrid] six-child polar splits")
+    want = regrid(ref, new)
+    g2 = grid.regrid(new)
+    e = block_err(g2.get_blocks(), want)
+    say("  after regrid " + " ".join(f"{k}={v:.1e}" for k, v in e.items()))
+    assert max(e.values()) <= TOL, e
+    a, r = g2.divb()
+    say(f"  divB rel {r:.2e}")
+    assert r < 1e-12
+    ref2 = AmrGrid(dict(cfg, n=tuple(2 * x for x in N0)), new)
+    ref2.set_blocks(want)
+    ref2.cycle()
+    g2.step(1)
+    e = block_err(g2.get_blocks(), ref2.get_blocks())
+    say("  step on the new layout " + " ".join(f"{k}={v:.1e}" for k, v in e.items()))
+    assert max(e.values()) <= TOL, e

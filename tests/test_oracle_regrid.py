@@ -195,3 +195,82 @@ def test_restriction_keeps_the_flux_through_every_coarse_face():
     want = 0.25 * (B1f[0::2, 0::2, 0::2] + B1f[0::2, 1::2, 0::2] + B1f[1::2, 0::2, 0::2]
                    + B1f[1::2, 1::2, 0::2])
     assert np.abs(coarse[1] - want).max() <= 1e-15 * np.abs(want).max()
+
+
+def polar_quarters(N0):
+    """four level-0 blocks over the whole sphere: x1 halves times theta halves, each
+    spanning all of phi"""
+    return [dict(org=(h * N0[0] // 2, j * N0[1] // 2, 0), n=(N0[0] // 2, N0[1] // 2, N0[2]),
+                 lev=(0, 0, 0), lat=0) for j in range(2) for h in range(2)]
+
+
+def six_child_layout(N0):
+    """polar_quarters with every block split into six children (each touches an axis; a
+    new finest level in every dimension)"""
+    from paper_1912_10192_amd import configs
+
+    q = polar_quarters(N0)
+    return (configs.split_block(q[0], N0[1], "north") + configs.split_block(q[1], N0[1], "north")
+            + configs.split_block(q[2], N0[1], "south") + configs.split_block(q[3], N0[1], "south"))
+
+
+def polar_state(cfg, seed):
+    """primitives of order one and a face field from a random edge potential that
+    vanishes on the polar axis (A_1, A_3 ~ sin^2 theta), so that the axis faces carry no
+    flux, as on a real spherical grid, and div B = 0 to rounding"""
+    rng = np.random.default_rng(seed)
+    N1, N2, N3 = cfg["n"]
+    d = [(cfg["xhi"][x] - cfg["xlo"][x]) / cfg["n"][x] for x in range(3)]
+
+    def smooth(x1, th, ph):
+        a = rng.normal(size=5)
+        return np.sin(th) ** 2 * (a[0] + a[1] * np.cos(ph + a[2]) + a[3] * np.sin(2 * x1 + a[4]) * np.cos(th))
+
+    x1c = cfg["xlo"][0] + (np.arange(N1) + 0.5) * d[0]
+    x1f = cfg["xlo"][0] + np.arange(N1 + 1) * d[0]
+    thf = cfg["xlo"][1] + np.arange(N2 + 1) * d[1]
+    phc = cfg["xlo"][2] + (np.arange(N3) + 0.5) * d[2]
+    phf = cfg["xlo"][2] + np.arange(N3 + 1) * d[2]
+    K, J, I = np.meshgrid(phf, thf, x1c, indexing="ij")
+    A1 = smooth(I, J, K)                                  # [N3+1][N2+1][N1]
+    K, J, I = np.meshgrid(phc, thf, x1f, indexing="ij")
+    A3 = smooth(I, J, K)                                  # [N3][N2+1][N1+1]
+    B1 = (A3[:, 1:, :] - A3[:, :-1, :]) / d[1]
+    B2 = (A1[1:] - A1[:-1]) / d[2] - (A3[:, :, 1:] - A3[:, :, :-1]) / d[0]
+    B3 = -(A1[:, 1:, :] - A1[:, :-1, :]) / d[1]
+    P = np.empty((5, N3, N2, N1))
+    P[0] = 1.0 + 0.1 * rng.random((N3, N2, N1))
+    P[1] = 0.5
+    P[2:] = 0.05 * rng.normal(size=(3, N3, N2, N1))
+    return P, B1, B2, B3
+
+
+def ks_sphere(N):
+    return dict(coords=1, a=0.9375, gam=4.0 / 3.0, n=N, ng=3, recon=1, riemann=1,
+                xlo=(math.log(1.5), 0.0, 0.0), xhi=(math.log(30.0), math.pi, 2 * math.pi),
+                bc=(0, 0, 1, 1, 2, 2), courant=0.8, rho_fl_c=0.0, rho_fl_p=0.0, u_fl_c=0.0,
+                u_fl_p=0.0, bsq_rho_max=1e300, bsq_u_max=1e300, gamma_max=1e150, tol=1e-12,
+                maxit=50)
+
+
+def test_six_child_polar_split_adds_a_level_divergence_free():
+    """blocks on the polar axis split into six children (Sec. 3.4: the two along the axis
+    keep the parent's phi level, the four further out are refined in all dimensions),
+    which adds a finest level: every new block's face field is divergence-free, and the
+    children along the axis take, along phi, their parent's values unrefined"""
+    N0 = (16, 16, 8)
+    cfg = ks_sphere(N0)
+    state = polar_state(cfg, 9)
+    old = polar_quarters(N0)
+    og = AmrGrid(cfg, old)
+    og.set_blocks(initdata.block_states(state, old, (0, 0, 0)))
+    new = six_child_layout(N0)
+    out = regrid(og, new)
+    cfg1 = dict(cfg, n=tuple(2 * x for x in N0))
+    for b, st in zip(new, out):
+        dx = _spacing(cfg1, b, (1, 1, 1))
+        scale = max(np.abs(x).max() for x in st[1:]) / min(dx)
+        assert np.abs(_div(st, dx)).max() <= 1e-13 * scale, b
+    # an axis child's x3 faces lie on its parent's x3 faces (no phi refinement): along
+    # phi they are the parent's own values, prolonged only in r and theta
+    assert new[0]["lev"] == (1, 1, 0) and out[0][3].shape[0] == N0[2] + 1
