@@ -1,0 +1,84 @@
+"""Host logic of refinement during the run (Sec. 3.3, the six-child polar split of Sec.
+3.4): flagged blocks split into eight children (six on the polar axis), the nesting rules
+then split what they need, and every layout produced is one the planner accepts; merging
+all children of a split returns the layout it came from."""
+import numpy as np
+import pytest
+
+from paper_1912_10192_amd import adapt, configs, grmhd
+from tests.test_oracle_regrid import ks_sphere, polar_quarters
+from tests.test_planner_amr_cpu import polar_bands
+
+
+def _accepts(cfg, layout, blocks):
+    plain = [{k: v for k, v in b.items() if k != "parent"} for b in blocks]
+    grmhd.Desc(dict(cfg, n=layout.n_eff(blocks)), blocks=plain).sizes()
+
+
+def _torus_bands():
+    eff = (32, 32, 16)
+    cfg = configs.scaled(configs.TORUS_UNIFORM, eff, ng=3)
+    return cfg, polar_bands(eff, (0, 1))
+
+
+def test_polar_block_splits_into_six_and_the_layout_is_valid():
+    N0 = (16, 16, 8)
+    cfg = ks_sphere(N0)
+    lay = adapt.Layout(cfg, polar_quarters(N0))
+    new = lay.refine([1, 0, 0, 0])
+    # the flagged block gives six children; the outer block on the same pole, which it
+    # touches across the axis, is split too
+    assert sum(1 for b in new if b.get("parent") is lay.blocks[0]) == 6
+    assert sum(1 for b in new if b.get("parent") is lay.blocks[1]) == 6
+    assert not lay.violations(new)
+    _accepts(cfg, lay, new)
+
+
+def test_refined_band_block_splits_into_eight():
+    cfg, blocks = _torus_bands()
+    lay = adapt.Layout(cfg, blocks)
+    i = next(k for k, b in enumerate(blocks) if b["lev"] == (1, 1, 1))
+    new = lay.refine([1 if k == i else 0 for k in range(len(blocks))])
+    kids = [b for b in new if b.get("parent") is lay.blocks[i]]
+    assert len(kids) == 8 and all(b["lev"] == (2, 2, 2) for b in kids)
+    assert not lay.violations(new)
+    _accepts(cfg, lay, new)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_flags_give_layouts_the_planner_accepts(seed):
+    rng = np.random.default_rng(seed)
+    for cfg, blocks in (_torus_bands(), (ks_sphere((16, 16, 8)), polar_quarters((16, 16, 8)))):
+        lay = adapt.Layout(cfg, blocks)
+        flags = list(rng.integers(0, 2, len(blocks)))
+        new = lay.refine(flags, max_level=3)
+        assert not lay.violations(new)
+        _accepts(cfg, lay, new)
+        # a second round on the refined layout
+        lay2 = adapt.Layout(dict(cfg, n=lay.n_eff(new)), new)
+        new2 = lay2.refine(list(rng.integers(0, 2, len(new))), max_level=3)
+        assert not lay2.violations(new2)
+        _accepts(cfg, lay2, new2)
+
+
+def test_merging_all_children_returns_the_layout():
+    cfg, blocks = _torus_bands()
+    lay = adapt.Layout(cfg, blocks)
+    new = lay.refine([1] * len(blocks))
+    back = lay.coarsen(new, [-1] * len(new))
+    key = lambda bl: sorted((b["lev"], b["org"], b["n"]) for b in bl)
+    assert key(back) == key(blocks)
+
+
+def test_merge_that_would_break_nesting_is_skipped():
+    cfg, blocks = _torus_bands()
+    lay = adapt.Layout(cfg, blocks)
+    i = next(k for k, b in enumerate(blocks) if b["lev"] == (1, 1, 1))
+    once = lay.refine([1 if k == i else 0 for k in range(len(blocks))])
+    lay2 = adapt.Layout(dict(cfg, n=lay.n_eff(once)), once)
+    # refine one grandchild, then ask every child of the first split to merge
+    j = next(k for k, b in enumerate(once) if b.get("parent") is lay.blocks[i])
+    twice = lay2.refine([1 if k == j else 0 for k in range(len(once))], max_level=3)
+    flags = [-1 if b.get("parent") is lay.blocks[i] else 0 for b in twice]
+    out = lay2.coarsen(twice, flags)
+    assert not lay2.violations(out)

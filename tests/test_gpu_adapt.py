@@ -1,0 +1,79 @@
+"""Refinement during the run on the GPU (Sec. 3.3): the torus on coarse polar caps with
+two time levels, regridded after every cycle on a density criterion (blocks whose densest
+cell exceeds 0.3 split, up to level 2), then every block asked to merge back; the oracle
+replays the same layouts with its own regrid and driver.  Parity after every cycle and
+every regrid, and div B at rounding level throughout (against the grid's field scale: in
+cells next to refinement faces whose own field is at rounding level, the EMF corrections
+leave differences of that size, on the oracle's grid alike)."""
+import sys
+
+import pytest
+
+from oracle.amr import AmrGrid
+from oracle.regrid import regrid
+from paper_1912_10192_amd import adapt, configs, initdata
+from tests.test_gpu_amr import block_err
+from tests.test_gpu_parity import TOL
+from tests.test_planner_amr_cpu import polar_bands
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _div_scaled(grid):
+    """max |div B| times the finest spacing over the largest face value"""
+    a, _ = grid.divb()
+    bmax = max(float(abs(x).max()) for st in grid.get_blocks() for x in st[1:])
+    dx = min((grid.cfg["xhi"][d] - grid.cfg["xlo"][d]) / grid.cfg["n"][d] for d in range(3))
+    return a * dx / bmax
+
+
+def test_density_driven_refinement_and_merge_match_oracle():
+    eff = (32, 32, 16)
+    cfg = configs.scaled(configs.TORUS_UNIFORM, eff, ng=3)
+    blocks = polar_bands(eff, (0, 1))
+    state = initdata.torus_state(eff, **configs.TORUS_INIT)
+    ref = AmrGrid(cfg, blocks)
+    bs = initdata.block_states(state, ref.blocks, ref.Lmax)
+    ref.set_blocks(bs)
+    ag = adapt.AdaptiveGrid(cfg, blocks, bs, rho_refine=0.3, rho_coarsen=-1.0, every=1,
+                            max_level=2, batched=1)
+    layouts = [blocks]
+    for c in range(3):
+        ref.cycle()
+        ag.step(1)
+        new = [{k: v for k, v in b.items() if k != "parent"} for b in ag.layout.blocks]
+        if len(ag.history) > len(layouts) - 1:
+            say(f"[adapt] cycle {c}: regrid to {len(new)} blocks, levels "
+                f"{sorted(set(tuple(b['lev']) for b in new))}")
+            want = regrid(ref, new)
+            ref = AmrGrid(dict(cfg, n=ag.grid.cfg["n"]), new)
+            ref.set_blocks(want)
+            layouts.append(new)
+        e = block_err(ag.grid.get_blocks(), ref.get_blocks())
+        say(f"  cycle {c}: " + " ".join(f"{k}={v:.1e}" for k, v in e.items()))
+        assert max(e.values()) <= TOL, e
+        assert _div_scaled(ag.grid) < 1e-13
+    assert len(layouts) >= 2, "the criterion refined nothing"
+    # every block asks to merge: the layout returns to the starting one
+    ag.rho_coarsen = 1e30
+    ag.rho_refine = 1e30
+    assert ag.adapt()
+    back = [{k: v for k, v in b.items() if k != "parent"} for b in ag.layout.blocks]
+    key = lambda bl: sorted((tuple(b["lev"]), tuple(b["org"]), tuple(b["n"])) for b in bl)
+    assert key(back) == key(blocks)
+    want = regrid(ref, back)
+    ref = AmrGrid(dict(cfg, n=ag.grid.cfg["n"]), back)
+    ref.set_blocks(want)
+    e = block_err(ag.grid.get_blocks(), ref.get_blocks())
+    say("  after the merge " + " ".join(f"{k}={v:.1e}" for k, v in e.items()))
+    assert max(e.values()) <= TOL, e
+    ref.cycle()
+    ag.step(1)
+    e = block_err(ag.grid.get_blocks(), ref.get_blocks())
+    say("  cycle after the merge " + " ".join(f"{k}={v:.1e}" for k, v in e.items()))
+    assert max(e.values()) <= TOL, e
+    assert _div_scaled(ag.grid) < 1e-13
