@@ -37,11 +37,24 @@ Rules (readings stated in the design notes):
             B^d = (B^d_+ + B^d_-)/2 - c_dd D_d^2/4 + sum_e t_e (S_{d+}^e + S_{d-}^e)/2.
     Since the reconstruction is divergence-free and matches the prolonged faces on the
     parent's faces, every fine cell inherits div B = 0 from its parent.
+  * Conserved option (Sec. 3.3 names both forms: primitives are fast and robust,
+    conserved quantities conservative): where a new cell is restricted or prolonged, the
+    conserved vector U = sqrt(-g)(rho u^t, T^t_t + rho u^t, T^t_i, kappa rho u^t) of each
+    old cell (from its primitives and cell-centred field) is averaged (restriction: the
+    plain mean, the coordinate volumes being equal) or prolonged (the densities
+    U / sqrt(-g) with +-1/4 of their minmod slopes, times the child's sqrt(-g), shifted
+    alike in all children so that they sum to the parent's U), so that the totals over
+    the new cells equal the old ones; the new cell's field is the mean of its new faces;
+    the primitives follow from the inversion (started from the primitive form's value),
+    then the floors, as after an update.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
+import oracle
 from oracle.amr import AmrGrid
 
 
@@ -73,14 +86,17 @@ def _relation(old_b, lam):
 class Regrid:
     """the new layout's state from an old AmrGrid at the end of a cycle"""
 
-    def __init__(self, old: AmrGrid, new_blocks):
+    def __init__(self, old: AmrGrid, new_blocks, conserved=False):
         self.old = old
+        self.conserved = conserved
+        self.cfg = old.cfg
         self.g = old.g
         self.new = [dict(b, lev=tuple(int(x) for x in b.get("lev", (0, 0, 0)))) for b in new_blocks]
         lm = tuple(max(b["lev"][d] for b in self.new) for d in range(3))
         # cells are located at the finer of the two layouts' finest levels; the new layout
         # may add or drop a finest level (its effective grid doubles or halves)
         self.Lmax = tuple(max(lm[d], old.Lmax[d]) for d in range(3))
+        self.Lnew = lm
         self.N = tuple((old.N[d] >> old.Lmax[d]) << lm[d] for d in range(3))
         # the old state at the cycle's end, every ghost filled from it
         for i in range(len(old.blocks)):
@@ -136,6 +152,117 @@ class Regrid:
             for v in range(5):
                 val[v] = val[v] + t * _minmod(c0[v] - cm[v], cp[v] - c0[v])
         return val
+
+    # ------------------------------------------------------------------ conserved form
+    def _x2(self, x2):
+        """x2 of a ghost cell beyond the polar axis, mirrored (its geometry)"""
+        lo, hi = self.cfg["xlo"][1], self.cfg["xhi"][1]
+        if self.cfg["bc"][2] == oracle.BC_POLAR:
+            if x2 < lo:
+                return 2.0 * lo - x2
+            if x2 > hi:
+                return 2.0 * hi - x2
+        return x2
+
+    def _cons_old(self, ob, gidx):
+        """U of the old cell gidx of block ob (padded state, ghosts included) and its
+        sqrt(-g)"""
+        VP, VB = self.pads[ob]
+        loc = self._loc(ob, gidx)
+        dx = self._dx(ob)
+        x1 = self.cfg["xlo"][0] + (gidx[0] + 0.5) * dx[0]
+        x2 = self._x2(self.cfg["xlo"][1] + (gidx[1] + 0.5) * dx[1])
+        gcov, gcon, gdet, alpha, _ = oracle.geom_point(self.cfg, x1, x2)
+        B = []
+        for d in range(3):
+            hi = list(loc)
+            hi[2 - d] += 1
+            B.append(0.5 * (VB[(d,) + loc] + VB[(d,) + tuple(hi)]) / gdet)
+        U = oracle.prim_to_flux(VP[(slice(None),) + loc], B, gcov, gcon, gdet, alpha,
+                                self.cfg["gam"], 0)
+        return U, gdet
+
+    def _gdet_new(self, lam, gc):
+        c = self.cfg
+        dx = [(c["xhi"][d] - c["xlo"][d]) / (self.N[d] >> (self.Lnew[d] - lam[d])) for d in range(2)]
+        x1 = c["xlo"][0] + (gc[0] + 0.5) * dx[0]
+        x2 = self._x2(c["xlo"][1] + (gc[1] + 0.5) * dx[1])
+        return oracle.geom_point(c, x1, x2)[2]
+
+    def _cons_cell(self, lam, gc, ob, r):
+        """U of a restricted new cell (the mean of the covered cells' U: the coordinate
+        volumes are equal) or of a prolonged one: the densities per unit sqrt(-g),
+        q = U / sqrt(-g), of the parent plus +-1/4 of their minmod slopes per refined
+        dimension, times the child's sqrt(-g), then shifted by the same amount in all
+        children of the parent so that they sum to the parent's U times their number"""
+        if max(r) <= 0:
+            subs = [range(2) if r[d] < 0 else range(1) for d in range(3)]
+            acc = np.zeros(9)
+            cnt = 0
+            for ok in subs[2]:
+                for oj in subs[1]:
+                    for oi in subs[0]:
+                        f = [(gc[d] << (-r[d])) + (oi, oj, ok)[d] for d in range(3)]
+                        acc = acc + self._cons_old(ob, f)[0]
+                        cnt += 1
+            return acc * (1.0 / cnt)
+        pc = [gc[d] >> r[d] for d in range(3)]
+        U0, g0 = self._cons_old(ob, pc)
+        q0 = U0 / g0
+        slope = np.zeros((3, 9))
+        for d in range(3):
+            if not r[d]:
+                continue
+            e = [0, 0, 0]
+            e[d] = 1
+            Um, gm = self._cons_old(ob, [pc[x] - e[x] for x in range(3)])
+            Up, gp = self._cons_old(ob, [pc[x] + e[x] for x in range(3)])
+            qm, qp = Um / gm, Up / gp
+            for v in range(9):
+                slope[d, v] = _minmod(q0[v] - qm[v], qp[v] - q0[v])
+
+        def child(cell):
+            q = q0.copy()
+            for d in range(3):
+                if r[d]:
+                    q = q + (0.25 if cell[d] & 1 else -0.25) * slope[d]
+            return self._gdet_new(lam, cell) * q
+
+        # the children of the parent, k outermost, i innermost
+        subs = [range(2) if r[d] else range(1) for d in range(3)]
+        acc = np.zeros(9)
+        cnt = 0
+        for ok in subs[2]:
+            for oj in subs[1]:
+                for oi in subs[0]:
+                    cell = [(pc[d] << r[d]) + (oi, oj, ok)[d] for d in range(3)]
+                    acc = acc + child(cell)
+                    cnt += 1
+        return child(list(gc)) + (U0 - acc * (1.0 / cnt))
+
+    def _invert_new(self, lam, gc, U, Bnew, guess):
+        """primitives of a new cell from its conserved vector and new faces: the inversion,
+        then the floors (as after an update)"""
+        c = self.cfg
+        dx = [(c["xhi"][d] - c["xlo"][d]) / (self.N[d] >> (self.Lnew[d] - lam[d])) for d in range(3)]
+        x1 = c["xlo"][0] + (gc[0] + 0.5) * dx[0]
+        x2 = c["xlo"][1] + (gc[1] + 0.5) * dx[1]
+        gcov, gcon, gdet, alpha, _ = oracle.geom_point(c, x1, x2)
+        U = U.copy()
+        B = [0.0, 0.0, 0.0]
+        for d in range(3):
+            U[5 + d] = 0.5 * (Bnew[d][0] + Bnew[d][1])
+            B[d] = U[5 + d] / gdet
+        P, tier, _ = oracle.cons2prim(U, gcov, gcon, gdet, alpha, c["gam"], guess, guess,
+                                      c.get("tol", 1e-12), c.get("maxit", 50))
+        r = math.exp(x1) if c["coords"] == 1 else 1.0
+        rho_fl = c.get("rho_fl_c", 0.0) * r ** c.get("rho_fl_p", 0.0)
+        u_fl = c.get("u_fl_c", 0.0) * r ** c.get("u_fl_p", 0.0)
+        P, _ = oracle.floors(c.get("floor_frame", oracle.FLOOR_FIXED), P, B, gcov, gcon, gdet,
+                             alpha, c["gam"], rho_fl, u_fl, c.get("bsq_rho_max", 1e300),
+                             c.get("bsq_u_max", 1e300), c.get("gamma_max", 1e150),
+                             c.get("tol", 1e-12), c.get("maxit", 50))
+        return P, tier
 
     # ------------------------------------------------------------------ faces
     def _face_slope(self, ob, d, fidx, e):
@@ -211,13 +338,9 @@ class Regrid:
     # ------------------------------------------------------------------ blocks
     def states(self):
         out = []
+        self.tiers = [0] * 5
         for b in self.new:
             lam, o, n = b["lev"], b["org"], b["n"]
-            P = np.zeros((5, n[2], n[1], n[0]))
-            for k in range(n[2]):
-                for j in range(n[1]):
-                    for i in range(n[0]):
-                        P[:, k, j, i] = self.cell(lam, (o[0] + i, o[1] + j, o[2] + k))
             Bs = []
             for d in range(3):
                 shp = [n[x] + (1 if x == d else 0) for x in range(3)]
@@ -229,11 +352,28 @@ class Regrid:
                             A[k, j, i] = self.face(lam, d, (o[0] + i, o[1] + j, o[2] + k),
                                                    loc[d] == n[d])
                 Bs.append(A)
+            P = np.zeros((5, n[2], n[1], n[0]))
+            for k in range(n[2]):
+                for j in range(n[1]):
+                    for i in range(n[0]):
+                        gc = (o[0] + i, o[1] + j, o[2] + k)
+                        val = self.cell(lam, gc)
+                        if self.conserved:
+                            ob = _covering(self.old.blocks, self.Lmax, lam, gc)
+                            r = _relation(self.old.blocks[ob], lam)
+                            if max(r) != 0 or min(r) != 0:
+                                U = self._cons_cell(lam, gc, ob, r)
+                                Bn = [(Bs[0][k, j, i], Bs[0][k, j, i + 1]),
+                                      (Bs[1][k, j, i], Bs[1][k, j + 1, i]),
+                                      (Bs[2][k, j, i], Bs[2][k + 1, j, i])]
+                                val, tier = self._invert_new(lam, gc, U, Bn, val)
+                                self.tiers[tier] += 1
+                        P[:, k, j, i] = val
             out.append((P, Bs[0], Bs[1], Bs[2]))
         return out
 
 
-def regrid(old: AmrGrid, new_blocks):
+def regrid(old: AmrGrid, new_blocks, conserved=False):
     """per-block interior states of the new layout (P, B1, B2, B3 as AmrGrid.set_blocks
-    takes them)"""
-    return Regrid(old, new_blocks).states()
+    takes them); conserved: restrict and prolong the conserved vector, then invert"""
+    return Regrid(old, new_blocks, conserved).states()

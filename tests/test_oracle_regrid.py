@@ -274,3 +274,49 @@ def test_six_child_polar_split_adds_a_level_divergence_free():
     # an axis child's x3 faces lie on its parent's x3 faces (no phi refinement): along
     # phi they are the parent's own values, prolonged only in r and theta
     assert new[0]["lev"] == (1, 1, 0) and out[0][3].shape[0] == N0[2] + 1
+
+
+def _totals(cfg, blocks, states, N):
+    """sum over interior cells of U (sqrt(-g) rho u^t, energy, momenta, entropy) times the
+    coordinate cell volume"""
+    import oracle
+
+    L = [max(b["lev"][d] for b in blocks) for d in range(3)]
+    tot = np.zeros(9)
+    for b, (P, B1, B2, B3) in zip(blocks, states):
+        dx = [(cfg["xhi"][d] - cfg["xlo"][d]) / (N[d] >> (L[d] - b["lev"][d])) for d in range(3)]
+        vol = dx[0] * dx[1] * dx[2]
+        for k in range(P.shape[1]):
+            for j in range(P.shape[2]):
+                x2 = cfg["xlo"][1] + (b["org"][1] + j + 0.5) * dx[1]
+                for i in range(P.shape[3]):
+                    x1 = cfg["xlo"][0] + (b["org"][0] + i + 0.5) * dx[0]
+                    gcov, gcon, gdet, alpha, _ = oracle.geom_point(cfg, x1, x2)
+                    B = [0.5 * (B1[k, j, i] + B1[k, j, i + 1]) / gdet,
+                         0.5 * (B2[k, j, i] + B2[k, j + 1, i]) / gdet,
+                         0.5 * (B3[k, j, i] + B3[k + 1, j, i]) / gdet]
+                    tot += vol * oracle.prim_to_flux(P[:, k, j, i], B, gcov, gcon, gdet, alpha,
+                                                     cfg["gam"], 0)
+    return tot
+
+
+def test_conserved_regrid_keeps_the_totals():
+    """the conserved form of the regrid keeps the sums of sqrt(-g) rho u^t, of the energy
+    and of the momenta over the grid, to the inversion's tolerance (the entropy tracer is
+    recomputed from the new primitives, as after an update); the primitive form, whose
+    children do not sum to their parent when sqrt(-g) varies across it, does not"""
+    N = (16, 16, 8)
+    cfg = ks_sphere(N)
+    st = polar_state(cfg, 11)
+    old = halves(N, (1, 1, 1), True)
+    new = halves(N, (1, 1, 1), False)
+    before = _totals(cfg, old, _grid(cfg, old, st).get_blocks(), N)
+    q = [0, 1, 2, 3, 4]
+    for conserved in (True, False):
+        out = regrid(_grid(cfg, old, st), new, conserved=conserved)
+        after = _totals(cfg, new, out, N)
+        rel = np.abs(after[q] - before[q]).max() / np.abs(before[q]).max()
+        if conserved:
+            assert rel <= 1e-12, rel
+        else:
+            assert rel > 1e-3, rel
