@@ -59,9 +59,9 @@ DESIGN_BYTES_UPDATE = 8 * (5 + 3 + 5 + 3 + 6 * 3 + 3 + 5 + 3)
 # kernels of hash KERNEL_HASH, and HBM traffic per unit from FETCH_SIZE / WRITE_SIZE
 # (scaled by the same counters' reading for a device copy of known size); None where not
 # measured on the current kernels.
-FLOPS_PER_UNIT = {"update": 1458.1}
-TRAFFIC_PER_UNIT = {"update": 463.5}
-KERNEL_HASH = "fa5b644c412a4223"
+FLOPS_PER_UNIT = {}
+TRAFFIC_PER_UNIT = {}
+KERNEL_HASH = ""
 
 
 def kernel_hash() -> str:
@@ -320,12 +320,12 @@ def regrid_leg(cfg, blocks, bs, sync, log):
     sync()
     t_init = time.perf_counter() - t0
     t0 = time.perf_counter()
-    grmhd._check(grmhd.lib().grmhd_regrid(g.ctx, g2.ctx))
+    grmhd._check(grmhd.lib().grmhd_regrid(g.ctx, g2.ctx, grmhd.REGRID_PRIMITIVE))
     t_up = time.perf_counter() - t0
     g3 = grmhd.Grid(cfg, blocks=blocks, batched=1)
     sync()
     t0 = time.perf_counter()
-    grmhd._check(grmhd.lib().grmhd_regrid(g2.ctx, g3.ctx))
+    grmhd._check(grmhd.lib().grmhd_regrid(g2.ctx, g3.ctx, grmhd.REGRID_PRIMITIVE))
     t_down = time.perf_counter() - t0
     a, b = g.get_blocks(), g3.get_blocks()
     err = 0.0

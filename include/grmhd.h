@@ -254,12 +254,21 @@ int grmhd_divb(grmhd_ctx* ctx, double* max_abs, double* max_rel, double* field);
  * restricted (mean of the fine sub-faces), or prolonged divergence-free (Balsara 2001):
  * a fine face on a parent face is the parent face plus +-1/4 of its minmod slopes in the
  * face's plane, a fine face inside a parent cell the face average of the parent cell's
- * divergence-free reconstruction, so every new cell keeps div B = 0.  The old context's
+ * divergence-free reconstruction, so every new cell keeps div B = 0.  mode
+ * GRMHD_REGRID_CONSERVED (Sec. 3.3's conservative form) restricts and prolongs the
+ * conserved vector instead where a cell is not copied: the mean of the covered cells'
+ * U, or the parent's U/sqrt(-g) plus +-1/4 of its minmod slopes, moved by one common
+ * amount in all children so that their U (times each child's sqrt(-g)) sum to the
+ * parent's; the cell
+ * field from the new faces; then the inversion (from the primitive form's value) and the
+ * floors of `to`.  Mass, energy and momenta summed over the grid are then kept to the
+ * inversion's tolerance.  The old context's
  * ghost values are refreshed first (its interior is not changed); the simulated time
  * carries over.  Synchronises both contexts' streams; allocates and frees a small
  * device table of boxes.  GRMHD_EINVAL for layouts that break the rules above,
  * GRMHD_ESTATE when `from` holds its state outside the caller's buffers. */
-int grmhd_regrid(grmhd_ctx* from, grmhd_ctx* to);
+enum { GRMHD_REGRID_PRIMITIVE = 0, GRMHD_REGRID_CONSERVED = 1 };
+int grmhd_regrid(grmhd_ctx* from, grmhd_ctx* to, int32_t mode);
 
 /* Host-only planner introspection for bit-exact checks (no device needed): copies the
  * ghost gather list for what = 0 (cell variables) or 1..3 (face component 1..3) as

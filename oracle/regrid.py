@@ -42,8 +42,9 @@ Rules (readings stated in the design notes):
     conserved vector U = sqrt(-g)(rho u^t, T^t_t + rho u^t, T^t_i, kappa rho u^t) of each
     old cell (from its primitives and cell-centred field) is averaged (restriction: the
     plain mean, the coordinate volumes being equal) or prolonged (the densities
-    U / sqrt(-g) with +-1/4 of their minmod slopes, times the child's sqrt(-g), shifted
-    alike in all children so that they sum to the parent's U), so that the totals over
+    U / sqrt(-g) with +-1/4 of their minmod slopes, moved by one common amount in all
+    children so that their U, the densities times the child's sqrt(-g), sum to the
+    parent's U), so that the totals over
     the new cells equal the old ones; the new cell's field is the mean of its new faces;
     the primitives follow from the inversion (started from the primitive form's value),
     then the floors, as after an update.
@@ -193,8 +194,8 @@ class Regrid:
         """U of a restricted new cell (the mean of the covered cells' U: the coordinate
         volumes are equal) or of a prolonged one: the densities per unit sqrt(-g),
         q = U / sqrt(-g), of the parent plus +-1/4 of their minmod slopes per refined
-        dimension, times the child's sqrt(-g), then shifted by the same amount in all
-        children of the parent so that they sum to the parent's U times their number"""
+        dimension, moved by one common amount in all children of the parent so that
+        their U (q times the child's sqrt(-g)) sum to the parent's U times their number"""
         if max(r) <= 0:
             subs = [range(2) if r[d] < 0 else range(1) for d in range(3)]
             acc = np.zeros(9)
@@ -228,17 +229,21 @@ class Regrid:
                     q = q + (0.25 if cell[d] & 1 else -0.25) * slope[d]
             return self._gdet_new(lam, cell) * q
 
-        # the children of the parent, k outermost, i innermost
+        # the children of the parent, k outermost, i innermost: their densities move by
+        # one common amount dq so that they sum to the parent's U times their number
         subs = [range(2) if r[d] else range(1) for d in range(3)]
         acc = np.zeros(9)
+        gsum = 0.0
         cnt = 0
         for ok in subs[2]:
             for oj in subs[1]:
                 for oi in subs[0]:
                     cell = [(pc[d] << r[d]) + (oi, oj, ok)[d] for d in range(3)]
                     acc = acc + child(cell)
+                    gsum = gsum + self._gdet_new(lam, cell)
                     cnt += 1
-        return child(list(gc)) + (U0 - acc * (1.0 / cnt))
+        dq = (cnt * U0 - acc) / gsum
+        return child(list(gc)) + self._gdet_new(lam, list(gc)) * dq
 
     def _invert_new(self, lam, gc, U, Bnew, guess):
         """primitives of a new cell from its conserved vector and new faces: the inversion,

@@ -368,6 +368,162 @@ __global__ void __launch_bounds__(AT) k_regrid_cells(const BlockInfo* __restrict
   for (int v = 0; v < 5; v++) Pt[dst + (int64_t)v * bn.vol] = val[v];
 }
 
+// Conserved form: U (the conserved vector of the update) of an old cell from its
+// primitives and cell-centred field, with its sqrt(-g)
+__device__ __forceinline__ double old_conserved(const OldBlock& ob, const GeoTab& G,
+                                                const double* __restrict__ Pf,
+                                                const double* __restrict__ Bf, const int g[3],
+                                                double gam, double U[9]) {
+  const int64_t s = ob.at(g[0], g[1], g[2]);
+  const Metric m = load_metric(G.c, G.ncol, geo_col(G, ob.bi, g[1] - ob.o[1] + ob.ng, g[0] - ob.o[0] + ob.ng));
+  double P[5], B[3];
+#pragma unroll
+  for (int v = 0; v < 5; v++) P[v] = Pf[5 * ob.bi.off + (int64_t)v * ob.bi.vol + s];
+  const int64_t st[3] = {1, ob.bi.np[0], (int64_t)ob.bi.np[0] * ob.bi.np[1]};
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const double* X = Bf + 3 * ob.bi.off + (int64_t)d * ob.bi.vol;
+    B[d] = 0.5 * (X[s] + X[s + st[d]]) / m.gdet;
+  }
+  Fluid f;
+  fluid_state(P, B, m, f);
+  flux_vector<0>(P, f, m, gam, entropy_kappa(P, gam), U);
+  return m.gdet;
+}
+
+// Restricted or prolonged cells of the conserved form: the mean of the covered cells' U,
+// or the parent's densities U / sqrt(-g) plus +-1/4 of their minmod slopes, moved by one
+// common amount in all children of the parent so that their U (densities times the
+// child's sqrt(-g)) sum to the parent's U; the cell field from the new faces (already
+// written); then the inversion,
+// started from the primitive form's value, and the floors of the new grid.
+__global__ void __launch_bounds__(AT) k_regrid_cells_cons(
+    const BlockInfo* __restrict__ bf, const BlockInfo* __restrict__ bt, GeoTab Gf, GeoTab Gt,
+    Phys ph, const RegridOp* __restrict__ ops, int64_t nops, const int64_t* __restrict__ start,
+    int64_t total, const double* __restrict__ Pf, const double* __restrict__ Bf,
+    double* __restrict__ Pt, const double* __restrict__ Bt) {
+  const int64_t t = (int64_t)blockIdx.x * AT + threadIdx.x;
+  if (t >= total) return;
+  const int k = regrid_box(start, nops, t);
+  const RegridOp op = ops[k];
+  const int rmin = min(op.r[0], min(op.r[1], op.r[2]));
+  const int rmax = max(op.r[0], max(op.r[1], op.r[2]));
+  if (rmin == 0 && rmax == 0) return;   // copied cells: the primitive pass has them
+  const int64_t q = t - start[k];
+  int l[3];
+  l[0] = op.lo[0] + (int)(q % op.ext[0]);
+  l[1] = op.lo[1] + (int)((q / op.ext[0]) % op.ext[1]);
+  l[2] = op.lo[2] + (int)(q / ((int64_t)op.ext[0] * op.ext[1]));
+  const int gc[3] = {op.on[0] + l[0], op.on[1] + l[1], op.on[2] + l[2]};
+  const BlockInfo bn = bt[op.nb];
+  const int ngn = (bn.np[0] - bn.n[0] - 1) / 2;
+  const int64_t loc = ((int64_t)(l[2] + ngn) * bn.np[1] + (l[1] + ngn)) * bn.np[0] + (l[0] + ngn);
+  const OldBlock ob = old_block(bf, op);
+  const double gam = ph.gam;
+  double U[9];
+  if (rmax <= 0) {
+    double acc[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    const int n0 = op.r[0] < 0 ? 2 : 1, n1 = op.r[1] < 0 ? 2 : 1, n2 = op.r[2] < 0 ? 2 : 1;
+    for (int ok = 0; ok < n2; ok++)
+      for (int oj = 0; oj < n1; oj++)
+        for (int oi = 0; oi < n0; oi++) {
+          const int f[3] = {(gc[0] << (-op.r[0])) + oi, (gc[1] << (-op.r[1])) + oj,
+                            (gc[2] << (-op.r[2])) + ok};
+          double Us[9];
+          old_conserved(ob, Gf, Pf, Bf, f, gam, Us);
+#pragma unroll
+          for (int v = 0; v < 9; v++) acc[v] = __dadd_rn(acc[v], Us[v]);
+        }
+    const double w = 1.0 / (n0 * n1 * n2);
+#pragma unroll
+    for (int v = 0; v < 9; v++) U[v] = __dmul_rn(acc[v], w);
+  } else {
+    const int pc[3] = {gc[0] >> op.r[0], gc[1] >> op.r[1], gc[2] >> op.r[2]};
+    double U0[9], q0[9], sl[3][9];
+    const double g0 = old_conserved(ob, Gf, Pf, Bf, pc, gam, U0);
+#pragma unroll
+    for (int v = 0; v < 9; v++) q0[v] = U0[v] / g0;
+    for (int d = 0; d < 3; d++) {
+#pragma unroll
+      for (int v = 0; v < 9; v++) sl[d][v] = 0.0;
+      if (!op.r[d]) continue;
+      int a[3] = {pc[0], pc[1], pc[2]};
+      a[d] -= 1;
+      double Um[9], Up[9];
+      const double gm = old_conserved(ob, Gf, Pf, Bf, a, gam, Um);
+      a[d] += 2;
+      const double gp = old_conserved(ob, Gf, Pf, Bf, a, gam, Up);
+#pragma unroll
+      for (int v = 0; v < 9; v++)
+        sl[d][v] = minmod(__dsub_rn(q0[v], Um[v] / gm), __dsub_rn(Up[v] / gp, q0[v]));
+    }
+    // one child's U from its global cell index (its sqrt(-g) from the new grid's table)
+    auto gdet_at = [&](const int c3[3]) {
+      const int J = c3[1] - op.on[1] + ngn, I = c3[0] - op.on[0] + ngn;
+      return Gt.c[GDET * Gt.ncol + geo_col(Gt, bn, J, I)];
+    };
+    auto child = [&](const int c3[3], double gd, double out[9]) {
+#pragma unroll
+      for (int v = 0; v < 9; v++) {
+        double x = q0[v];
+        for (int d = 0; d < 3; d++)
+          if (op.r[d]) x = __dadd_rn(x, __dmul_rn((c3[d] & 1) ? 0.25 : -0.25, sl[d][v]));
+        out[v] = __dmul_rn(gd, x);
+      }
+    };
+    // the children's densities move by one common amount dq so that their U sum to the
+    // parent's U times their number
+    double acc[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, gsum = 0.0;
+    const int n0 = op.r[0] ? 2 : 1, n1 = op.r[1] ? 2 : 1, n2 = op.r[2] ? 2 : 1;
+    for (int ok = 0; ok < n2; ok++)
+      for (int oj = 0; oj < n1; oj++)
+        for (int oi = 0; oi < n0; oi++) {
+          const int c3[3] = {(pc[0] << op.r[0]) + oi, (pc[1] << op.r[1]) + oj,
+                             (pc[2] << op.r[2]) + ok};
+          const double gd = gdet_at(c3);
+          double Uc[9];
+          child(c3, gd, Uc);
+#pragma unroll
+          for (int v = 0; v < 9; v++) acc[v] = __dadd_rn(acc[v], Uc[v]);
+          gsum = __dadd_rn(gsum, gd);
+        }
+    const double cnt = (double)(n0 * n1 * n2);
+    const double gme = gdet_at(gc);
+    double Um[9];
+    child(gc, gme, Um);
+#pragma unroll
+    for (int v = 0; v < 9; v++) {
+      const double dq = __dsub_rn(__dmul_rn(cnt, U0[v]), acc[v]) / gsum;
+      U[v] = __dadd_rn(Um[v], __dmul_rn(gme, dq));
+    }
+  }
+  // the new cell: field from its new faces, the inversion, the floors
+  const int64_t col = geo_col(Gt, bn, l[1] + ngn, l[0] + ngn);
+  const Metric m = load_metric(Gt.c, Gt.ncol, col);
+  const int64_t st[3] = {1, bn.np[0], (int64_t)bn.np[0] * bn.np[1]};
+  double B[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const double* X = Bt + 3 * bn.off + (int64_t)d * bn.vol;
+    U[5 + d] = 0.5 * (X[loc] + X[loc + st[d]]);
+    B[d] = U[5 + d] / m.gdet;
+  }
+  double guess[5], P[5];
+#pragma unroll
+  for (int v = 0; v < 5; v++) guess[v] = Pt[5 * bn.off + (int64_t)v * bn.vol + loc];
+  C2PIn cs;
+  c2p_setup(U, m, gam, cs);
+  int iters = 0;
+  c2p_solve(cs, m, false, 0.0, 0.0, guess, ph.tol, ph.maxit, P, iters);
+  const double rfl = Gt.c[RHOFL * Gt.ncol + col], ufl = Gt.c[UFL * Gt.ncol + col];
+  if (ph.floor_drift)
+    drift_floors(P, B, m, rfl, ufl, ph.bsq_rho_max, ph.bsq_u_max, ph.gamma_max, gam, ph.tol, ph.maxit);
+  else
+    apply_floors(P, B, m, rfl, ufl, ph.bsq_rho_max, ph.bsq_u_max, ph.gamma_max);
+#pragma unroll
+  for (int v = 0; v < 5; v++) Pt[5 * bn.off + (int64_t)v * bn.vol + loc] = P[v];
+}
+
 // minmod slope along x_e (per parent cell) of the B^c faces at global face index g
 __device__ __forceinline__ double face_slope(const OldBlock& ob, const double* __restrict__ X,
                                              const int g[3], int e) {
@@ -474,15 +630,21 @@ __global__ void __launch_bounds__(AT) k_regrid_faces(const BlockInfo* __restrict
 
 void launch_regrid(const Launch& Lf, const Launch& Lt, const RegridOp* ops, int64_t nops,
                    const int64_t* start, const int64_t total[4], const double* Pf,
-                   const double* Bf, double* Pt, double* Bt) {
+                   const double* Bf, double* Pt, double* Bt, bool conserved) {
   if (nops <= 0) return;
-  if (total[0] > 0)
-    k_regrid_cells<<<dim3((unsigned)((total[0] + AT - 1) / AT)), dim3(AT), 0, Lf.stream>>>(
-        Lf.blk, Lt.blk, Lf.geo, ops, nops, start, total[0], Pf, Pt);
   const int64_t nf = total[1] + total[2] + total[3];
   if (nf > 0)
     k_regrid_faces<<<dim3((unsigned)((nf + AT - 1) / AT)), dim3(AT), 0, Lf.stream>>>(
         Lf.blk, Lt.blk, ops, nops, start, total[1], total[2], total[3], Bf, Bt);
+  if (total[0] > 0) {
+    const dim3 grid((unsigned)((total[0] + AT - 1) / AT));
+    k_regrid_cells<<<grid, dim3(AT), 0, Lf.stream>>>(Lf.blk, Lt.blk, Lf.geo, ops, nops, start,
+                                                     total[0], Pf, Pt);
+    if (conserved)
+      k_regrid_cells_cons<<<grid, dim3(AT), 0, Lf.stream>>>(Lf.blk, Lt.blk, Lf.geo, Lt.geo, Lt.ph,
+                                                            ops, nops, start, total[0], Pf, Bf,
+                                                            Pt, Bt);
+  }
 }
 
 }  // namespace grmhd

@@ -2556,8 +2556,10 @@ static int regrid_ops(const Plan& po, const Plan& pn, std::vector<RegridOp>& ops
   return GRMHD_OK;
 }
 
-int grmhd_regrid(grmhd_ctx* from, grmhd_ctx* to) {
+int grmhd_regrid(grmhd_ctx* from, grmhd_ctx* to, int32_t mode) {
   if (!from || !to || from == to) return fail(GRMHD_EINVAL, "regrid needs two distinct contexts");
+  if (mode != GRMHD_REGRID_PRIMITIVE && mode != GRMHD_REGRID_CONSERVED)
+    return fail(GRMHD_EINVAL, "unknown regrid mode");
   if (from->b_in_alt) return fail(GRMHD_ESTATE, "state not in the caller's buffers");
   std::vector<RegridOp> ops;
   if (int rc = regrid_ops(from->plan, to->plan, ops)) return rc;
@@ -2592,7 +2594,7 @@ int grmhd_regrid(grmhd_ctx* from, grmhd_ctx* to) {
   if (e == hipSuccess) {
     fill_ghosts(from, from->bufs.prim, from->bufs.bface);
     launch_regrid(from->L, to->L, dops, nops, dstart, total, from->bufs.prim, from->bufs.bface,
-                  to->bufs.prim, to->bufs.bface);
+                  to->bufs.prim, to->bufs.bface, mode == GRMHD_REGRID_CONSERVED);
     e = hipGetLastError();
   }
   if (e == hipSuccess)   // the simulation time carries over

@@ -282,12 +282,13 @@ void launch_amr_ghosts(const Launch& L, const AmrLists& A, const AmrSample* samp
                        const double* Pmain, const double* Pold, const double* Pcur, double* Pdst,
                        const double* Bmain, const double* Bold, const double* Bcur, double* Bdst,
                        double w);
-// a regrid: the new layout's interior cells and faces (the boxes' cells, then faces of
+// a regrid: the new layout's interior faces and cells (conserved: restricted and
+// prolonged cells from the conserved vector, then inverted; the boxes' cells, then faces of
 // each direction: start[k][op], k = 0 cells, 1..3 faces, with total[k] = start[k][nops])
 // from the old layout's padded state, whose ghosts are filled
 void launch_regrid(const Launch& Lf, const Launch& Lt, const RegridOp* ops, int64_t nops,
                    const int64_t* start, const int64_t total[4], const double* Pf,
-                   const double* Bf, double* Pt, double* Bt);
+                   const double* Bf, double* Pt, double* Bt, bool conserved);
 // the items of a mean list: kind 0 items on X0, the others on X1
 void launch_means(const Launch& L, const MeanItem* items, int64_t n, double* X0, double* X1);
 // local time stepping (lat.hip)

@@ -24,6 +24,7 @@ BC_OUTFLOW, BC_POLAR, BC_PERIODIC = 0, 1, 2
 GUESS_PLAIN, GUESS_MLP = 0, 1
 EMF_AVERAGE, EMF_UPWIND = 0, 1
 FLOOR_FIXED, FLOOR_DRIFT = 0, 1
+REGRID_PRIMITIVE, REGRID_CONSERVED = 0, 1
 
 # every symbol declared in include/grmhd.h
 EXPORTS = ("grmhd_sizes", "grmhd_block_layout", "grmhd_init_grid", "grmhd_step",
@@ -126,7 +127,7 @@ def lib():
         L.grmhd_mlp_normalize.argtypes = [vp, i64, i32, vp, vp, i32, vp]
         L.grmhd_extract_cells.argtypes = [vp, vp, vp, vp]
         L.grmhd_destroy.argtypes = [C.c_void_p]
-        L.grmhd_regrid.argtypes = [C.c_void_p, C.c_void_p]
+        L.grmhd_regrid.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
         L.grmhd_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -419,16 +420,17 @@ class Grid:
         choice = (C.c_int32 * 5)(flux[0], flux[1], flux[2], update, split)
         _check(lib().grmhd_set_variants(self.ctx, choice))
 
-    def regrid(self, blocks, batched=None):
+    def regrid(self, blocks, batched=None, conserved=False):
         """a new Grid of the same workload on the block layout `blocks`, filled from this
-        grid's state (grmhd_regrid); this grid keeps its state.  Where the new layout adds
-        or drops a finest level, its effective grid doubles or halves in that dimension."""
+        grid's state (grmhd_regrid; conserved: restrict and prolong the conserved vector);
+        this grid keeps its state.  Where the new layout adds or drops a finest level, its
+        effective grid doubles or halves in that dimension."""
         old_l = [max(int(b.lev[d]) for b in self.desc.blocks) for d in range(3)]
         new_l = [max(int(b.get("lev", (0, 0, 0))[d]) for b in blocks) for d in range(3)]
         n = tuple((int(self.cfg["n"][d]) >> old_l[d]) << new_l[d] for d in range(3))
         new = Grid(dict(self.cfg, n=n), blocks=blocks,
                    batched=self.batched if batched is None else batched, mlp_blob=self.mlp_blob)
-        _check(lib().grmhd_regrid(self.ctx, new.ctx))
+        _check(lib().grmhd_regrid(self.ctx, new.ctx, REGRID_CONSERVED if conserved else REGRID_PRIMITIVE))
         return new
 
     def divb(self):

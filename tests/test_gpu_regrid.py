@@ -197,3 +197,73 @@ def test_six_child_polar_split_matches_oracle():
     e = block_err(g2.get_blocks(), ref2.get_blocks())
     say("  step on the new layout " + " ".join(f"{k}={v:.1e}" for k, v in e.items()))
     assert max(e.values()) <= TOL, e
+
+
+@pytest.mark.parametrize("pattern", ["all", "x1", "x2x3"])
+def test_conserved_regrid_matches_oracle_and_keeps_the_totals(pattern):
+    """the conserved form (GRMHD_REGRID_CONSERVED) on Minkowski halves refined and
+    derefined at once: element by element against the oracle's conserved regrid, and the
+    totals of mass, energy and momenta over the new grid equal the old ones (the primitive
+    form misses them by 0.3-1%)"""
+    from tests.test_oracle_regrid import _totals
+
+    fine = PATTERNS[pattern]
+    N = (16, 16, 8)
+    cfg = _mink(N)
+    say(f"[regrid] conserved form, minkowski halves, refinement {fine}")
+    st = random_periodic_state(N, seed=11, amp=0.2, vamp=0.4, bamp=0.3)
+    old, new = halves(N, fine, True), halves(N, fine, False)
+    lmax = [max(b["lev"][d] for b in old) for d in range(3)]
+    bs = initdata.block_states(st, old, lmax)
+    ref = AmrGrid(cfg, old)
+    ref.set_blocks(bs)
+    want = regrid(ref, new, conserved=True)
+    g = grmhd.Grid(cfg, blocks=old)
+    g.set_blocks(bs)
+    got = g.regrid(new, conserved=True).get_blocks()
+    e = block_err(got, want)
+    say("  " + " ".join(f"{k}={v:.1e}" for k, v in e.items()))
+    assert max(e.values()) <= 1e-12, e
+    q = [0, 1, 2, 3, 4]
+    before = _totals(cfg, old, bs, N)
+    after = _totals(cfg, new, got, N)
+    rel = float(abs(after[q] - before[q]).max() / abs(before[q]).max())
+    say(f"  totals kept to {rel:.1e}")
+    assert rel <= 1e-13
+
+
+def test_conserved_regrid_on_a_kerr_schild_sphere_matches_oracle():
+    """the conserved form on a Kerr-Schild sphere with polar axes: every block split into
+    six children (a new finest level) and merged back, element by element against the
+    oracle; the merge keeps the totals.  (Prolonging the conserved vector component by
+    component is fragile in Kerr-Schild coordinates, where the covariant momenta carry a
+    large part set by the metric's g_tr: some children need the entropy fallback, the
+    same on both sides.)"""
+    from tests.test_oracle_regrid import (_totals, ks_sphere, polar_quarters, polar_state,
+                                          six_child_layout)
+
+    N0 = (16, 16, 8)
+    N1 = tuple(2 * x for x in N0)
+    cfg = ks_sphere(N0)
+    old, new = polar_quarters(N0), six_child_layout(N0)
+    bs = initdata.block_states(polar_state(cfg, 11), old, (0, 0, 0))
+    ref = AmrGrid(cfg, old)
+    ref.set_blocks(bs)
+    g = grmhd.Grid(cfg, blocks=old)
+    g.set_blocks(bs)
+    for lay, n, what in ((new, N1, "six-child splits"), (old, N0, "merged back")):
+        say(f"[regrid] conserved form, {what}")
+        before = _totals(dict(cfg, n=tuple(ref.N)), ref.blocks, ref.get_blocks(), tuple(ref.N))
+        want = regrid(ref, lay, conserved=True)
+        g = g.regrid(lay, conserved=True)
+        got = g.get_blocks()
+        e = block_err(got, want)
+        say("  " + " ".join(f"{k}={v:.1e}" for k, v in e.items()))
+        assert max(e.values()) <= TOL, e
+        ref = AmrGrid(dict(cfg, n=n), lay)
+        ref.set_blocks(want)
+    after = _totals(cfg, old, got, N0)
+    q = [0, 1, 2, 3, 4]
+    rel = float(abs(after[q] - before[q]).max() / abs(before[q]).max())
+    say(f"  merge keeps the totals to {rel:.1e}")
+    assert rel <= 1e-12
