@@ -379,6 +379,8 @@ def main():
     ap.add_argument("--only-headline", action="store_true",
                     help="only the headline path (with its training) and the per-class profiled "
                          "run that gives the roofline, for profiling them alone")
+    ap.add_argument("--only-regrid", action="store_true",
+                    help="only the regrid leg on the headline layout (for profiling it alone)")
     ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--plain-guess", action="store_true",
                     help="no learned guess: the headline path with the previous-state guess "
@@ -418,6 +420,9 @@ def main():
     bs = initdata.block_states(state, blocks, lmax)
     del state
     cells = sum(b["n"][0] * b["n"][1] * b["n"][2] for b in blocks)
+    if args.only_regrid:
+        print(json.dumps({"regrid": regrid_leg(cfg, blocks, bs, sync, log)}), flush=True)
+        return
     blob, train = (None, None) if args.plain_guess else train_guess(args.train_steps, log)
     head, tune = run_leg("batched_learned", cfg, blocks, bs, 1, blob, args.steps, args.warmup,
                          args.runs, sync, log)
