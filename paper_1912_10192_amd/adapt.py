@@ -167,9 +167,24 @@ class AdaptiveGrid:
     densest cell lies below rho_coarsen are merged."""
 
     def __init__(self, cfg, blocks, states, rho_refine, rho_coarsen, every=1, max_level=2,
-                 batched=1):
+                 batched=1, pool_sizes=None):
+        """pool_sizes: (prim, bface, work) element counts of the largest layout to expect;
+        two buffer sets of that size are then allocated once, and the grid alternates
+        between them at every regrid (the old layout's set is free again once the regrid
+        has filled the new one), so regrids allocate no device memory for the state"""
         self.layout = Layout(cfg, blocks)
-        self.grid = grmhd.Grid(cfg, blocks=blocks, batched=batched)
+        self.pools = None
+        if pool_sizes is not None:
+            import torch
+
+            npr, nbf, nwk = pool_sizes
+            self.pools = [(torch.zeros(npr, dtype=torch.float64, device="cuda"),
+                           torch.zeros(nbf, dtype=torch.float64, device="cuda"),
+                           torch.empty(nwk + 256, dtype=torch.uint8, device="cuda"))
+                          for _ in range(2)]
+            self.active = 0
+        self.grid = grmhd.Grid(cfg, blocks=blocks, batched=batched,
+                               pool=self.pools[0] if self.pools else None)
         self.grid.set_blocks(states)
         self.rho_refine, self.rho_coarsen = rho_refine, rho_coarsen
         self.every, self.max_level = every, max_level
@@ -192,7 +207,13 @@ class AdaptiveGrid:
         if key(new) == key(self.layout.blocks):
             return False
         plain = [{k: v for k, v in b.items() if k != "parent"} for b in new]
-        self.grid = self.grid.regrid(plain)
+        if self.pools:
+            nxt = 1 - self.active
+            g = self.grid.regrid(plain, pool=self.pools[nxt])
+            self.grid.close()
+            self.grid, self.active = g, nxt
+        else:
+            self.grid = self.grid.regrid(plain)
         self.layout.blocks = list(new)
         self.layout.cfg = self.grid.cfg
         self.history.append(plain)

@@ -336,7 +336,11 @@ class Grid:
     """A grid on the GPU: caller-owned torch buffers plus the library context."""
 
     def __init__(self, cfg: dict, state=None, blocks=None, batched=False, profile=False,
-                 mlp_blob=None, device="cuda"):
+                 mlp_blob=None, device="cuda", pool=None):
+        """pool: (prim, bface, work) device tensors (float64, float64, uint8) to place the
+        grid's buffers in, in place of new allocations; each must hold at least what
+        grmhd_sizes asks (plus 256 bytes of alignment for work).  The grid's buffers are
+        then views of them, zeroed here."""
         import torch
 
         self.torch = torch
@@ -344,9 +348,17 @@ class Grid:
         self.desc = Desc(cfg, blocks=blocks, batched=batched, profile=profile, mlp_blob=mlp_blob)
         nprim, nbface, nwork = self.desc.sizes()
         self.device = torch.device(device)
-        self.prim = torch.zeros(nprim, dtype=torch.float64, device=self.device)
-        self.bface = torch.zeros(nbface, dtype=torch.float64, device=self.device)
-        self.work = torch.empty(nwork + 256, dtype=torch.uint8, device=self.device)
+        if pool is None:
+            self.prim = torch.zeros(nprim, dtype=torch.float64, device=self.device)
+            self.bface = torch.zeros(nbface, dtype=torch.float64, device=self.device)
+            self.work = torch.empty(nwork + 256, dtype=torch.uint8, device=self.device)
+        else:
+            pp, pb, pw = pool
+            if pp.numel() < nprim or pb.numel() < nbface or pw.numel() < nwork + 256:
+                raise GrmhdError("pool buffers smaller than the layout needs")
+            self.prim, self.bface, self.work = pp[:nprim], pb[:nbface], pw[:nwork + 256]
+            self.prim.zero_()
+            self.bface.zero_()
         if state is not None:
             self.set_state(*state)
         wp = self.work.data_ptr()
@@ -420,7 +432,7 @@ class Grid:
         choice = (C.c_int32 * 5)(flux[0], flux[1], flux[2], update, split)
         _check(lib().grmhd_set_variants(self.ctx, choice))
 
-    def regrid(self, blocks, batched=None, conserved=False):
+    def regrid(self, blocks, batched=None, conserved=False, pool=None):
         """a new Grid of the same workload on the block layout `blocks`, filled from this
         grid's state (grmhd_regrid; conserved: restrict and prolong the conserved vector);
         this grid keeps its state.  Where the new layout adds or drops a finest level, its
@@ -429,7 +441,8 @@ class Grid:
         new_l = [max(int(b.get("lev", (0, 0, 0))[d]) for b in blocks) for d in range(3)]
         n = tuple((int(self.cfg["n"][d]) >> old_l[d]) << new_l[d] for d in range(3))
         new = Grid(dict(self.cfg, n=n), blocks=blocks,
-                   batched=self.batched if batched is None else batched, mlp_blob=self.mlp_blob)
+                   batched=self.batched if batched is None else batched, mlp_blob=self.mlp_blob,
+                   pool=pool)
         _check(lib().grmhd_regrid(self.ctx, new.ctx, REGRID_CONSERVED if conserved else REGRID_PRIMITIVE))
         return new
 

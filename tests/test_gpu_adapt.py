@@ -77,3 +77,46 @@ def test_density_driven_refinement_and_merge_match_oracle():
     say("  cycle after the merge " + " ".join(f"{k}={v:.1e}" for k, v in e.items()))
     assert max(e.values()) <= TOL, e
     assert _div_scaled(ag.grid) < 1e-13
+
+
+def test_pooled_adaptive_run_is_identical_and_allocates_nothing():
+    """the same refine-run-merge-run sequence with the state in two preallocated buffer
+    sets (the grid alternating between them at each regrid): bit-identical to the run
+    with fresh buffers, and torch's device allocations do not grow across the regrids"""
+    import torch
+
+    from paper_1912_10192_amd import grmhd
+
+    eff = (32, 32, 16)
+    cfg = configs.scaled(configs.TORUS_UNIFORM, eff, ng=3)
+    blocks = polar_bands(eff, (0, 1))
+    state = initdata.torus_state(eff, **configs.TORUS_INIT)
+    lmax = [max(b["lev"][d] for b in blocks) for d in range(3)]
+    bs = initdata.block_states(state, blocks, lmax)
+
+    def run(pool_sizes, sizes_out=None):
+        ag = adapt.AdaptiveGrid(cfg, blocks, bs, rho_refine=0.3, rho_coarsen=-1.0,
+                                every=1000, max_level=2, batched=1, pool_sizes=pool_sizes)
+        ag.step(1)
+        torch.cuda.synchronize()
+        mem0 = torch.cuda.memory_allocated()
+        assert ag.adapt()
+        refined = [{k: v for k, v in b.items() if k != "parent"} for b in ag.layout.blocks]
+        if sizes_out is not None:
+            sizes_out.append(grmhd.Desc(ag.grid.cfg, blocks=refined, batched=1).sizes())
+        ag.step(1)
+        assert ag.adapt(blocks)
+        ag.step(1)
+        torch.cuda.synchronize()
+        return ag.grid.get_blocks(), torch.cuda.memory_allocated() - mem0
+
+    sizes = [grmhd.Desc(cfg, blocks=blocks, batched=1).sizes()]
+    fresh, _ = run(None, sizes)
+    pool = tuple(max(s[k] for s in sizes) for k in range(3))
+    say(f"[adapt] pool of {pool[0] + pool[1]} doubles and {pool[2]} work bytes, twice")
+    pooled, grown = run(pool)
+    say(f"  device allocations grew by {grown} bytes across the regrids")
+    for a, b in zip(fresh, pooled):
+        for x, y in zip(a, b):
+            assert (x == y).all()
+    assert grown <= 0
