@@ -384,7 +384,9 @@ int grmhd_mlp_normalize(float* A, int64_t n, int32_t cols, float* mean, float* s
 
 /* Every interior cell of the grid as flat batches (block order, then k, j, i):
  * P[5][n] primitives, B[3][n] cell-centred coordinate field, geom[15][n] metric as in
- * grmhd_c2p_batch; n = number of interior cells. */
+ * grmhd_c2p_batch; n = number of interior cells.  Blocks may differ in size (the first
+ * call then keeps a small device table of the blocks' output offsets until
+ * grmhd_destroy). */
 int grmhd_extract_cells(grmhd_ctx* ctx, double* P, double* B, double* geom);
 
 int grmhd_destroy(grmhd_ctx* ctx);

@@ -1744,6 +1744,7 @@ struct grmhd_ctx {
   // that fork them from the launch stream and join them back
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
+  int64_t* ext_off = nullptr;   // per-block output offsets of grmhd_extract_cells (uneven blocks)
 };
 
 // The plan of the last grmhd_sizes call, handed to grmhd_init_grid when it is called
@@ -2718,12 +2719,24 @@ int grmhd_plan_dump(const grmhd_grid_desc* desc, int32_t what, void* host_buf, s
 
 int grmhd_extract_cells(grmhd_ctx* c, double* P, double* B, double* geom) {
   if (!c || !P || !B || !geom) return fail(GRMHD_EINVAL, "NULL argument");
-  const auto& bl = c->plan.blocks;
-  for (const auto& b : bl)
-    for (int k = 0; k < 3; k++)
-      if (b.n[k] != bl[0].n[k]) return fail(GRMHD_EUNSUPPORTED, "extract needs equal block sizes");
   if (c->b_in_alt) return fail(GRMHD_ESTATE, "state not in the caller's buffers");
-  launch_extract(c->L, c->bufs.prim, c->bufs.bface, c->plan.n_interior, P, B, geom);
+  const auto& bl = c->plan.blocks;
+  bool uneven = false;
+  for (const auto& b : bl)
+    for (int k = 0; k < 3; k++) uneven = uneven || b.n[k] != bl[0].n[k];
+  if (uneven && !c->ext_off) {
+    // first output index of each block, kept on the device for later calls
+    std::vector<int64_t> off(bl.size());
+    int64_t run = 0;
+    for (size_t b = 0; b < bl.size(); b++) {
+      off[b] = run;
+      run += (int64_t)bl[b].n[0] * bl[b].n[1] * bl[b].n[2];
+    }
+    HIPCHK(hipMalloc(&c->ext_off, sizeof(int64_t) * off.size()));
+    HIPCHK(hipMemcpy(c->ext_off, off.data(), sizeof(int64_t) * off.size(), hipMemcpyHostToDevice));
+  }
+  launch_extract(c->L, c->bufs.prim, c->bufs.bface, c->plan.n_interior, uneven ? c->ext_off : nullptr,
+                 P, B, geom);
   HIPCHK(hipGetLastError());
   return GRMHD_OK;
 }
@@ -2741,6 +2754,7 @@ int grmhd_destroy(grmhd_ctx* c) {
     if (c->join_ev[k]) (void)hipEventDestroy(c->join_ev[k]);
   }
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->ext_off) (void)hipFree(c->ext_off);
   delete c;
   return GRMHD_OK;
 }

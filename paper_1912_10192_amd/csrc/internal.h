@@ -275,8 +275,9 @@ void launch_fill(const Launch& L, double* x, int64_t n, double v);
 // div B of the face field (field non-null: per cell), maxima through the per-workgroup
 // partials part [2][workgroups]
 void launch_divb(const Launch& L, const double* B, double* field, double* part);
-void launch_extract(const Launch& L, const double* Pin, const double* Bin, int64_t n, double* P,
-                    double* B, double* geom);
+// boff: first output index of each block, or null when all blocks have one size
+void launch_extract(const Launch& L, const double* Pin, const double* Bin, int64_t n,
+                    const int64_t* boff, double* P, double* B, double* geom);
 // refinement levels (amr.hip)
 void launch_amr_ghosts(const Launch& L, const AmrLists& A, const AmrSample* samp,
                        const double* Pmain, const double* Pold, const double* Pcur, double* Pdst,

@@ -1100,8 +1100,11 @@ __global__ __launch_bounds__(NT) void k_divb_final(Counters* __restrict__ cnt,
 
 // interior cells as flat batches: P[5][n], B[3][n] (coordinate field), geom[15][n]; the
 // cells of block b start at b * (cells per block), order k, j, i (uniform block sizes)
+// boff: first output index of each block (blocks of uneven sizes), or null for blocks of
+// one size
 __global__ __launch_bounds__(NT) void k_extract(Launch L, const double* __restrict__ Pin,
                                                 const double* __restrict__ Bin, int64_t n,
+                                                const int64_t* __restrict__ boff,
                                                 double* __restrict__ P, double* __restrict__ B,
                                                 double* __restrict__ geom) {
   const BlockInfo bi = L.blk[blockIdx.y];
@@ -1109,7 +1112,7 @@ __global__ __launch_bounds__(NT) void k_extract(Launch L, const double* __restri
   Cell c;
   const int t = blockIdx.x * NT + threadIdx.x;
   if (!region_cell(bi, t, bi.n[0], bi.n[1], bi.n[2], g, g, g, c)) return;
-  const int64_t o = (int64_t)blockIdx.y * bi.n[0] * bi.n[1] * bi.n[2] + t;
+  const int64_t o = (boff ? boff[blockIdx.y] : (int64_t)blockIdx.y * bi.n[0] * bi.n[1] * bi.n[2]) + t;
   const int64_t V = bi.vol, l = c.loc;
   const int64_t s2 = bi.np[0], s3 = (int64_t)bi.np[0] * bi.np[1];
   const int64_t col = geo_col(L.geo, bi, c.J, c.I);
@@ -1122,11 +1125,11 @@ __global__ __launch_bounds__(NT) void k_extract(Launch L, const double* __restri
   B[2 * n + o] = 0.5 * (b[2 * V + l] + b[2 * V + l + s3]) / gdet;
 }
 
-void launch_extract(const Launch& L, const double* Pin, const double* Bin, int64_t n, double* P,
-                    double* B, double* geom) {
+void launch_extract(const Launch& L, const double* Pin, const double* Bin, int64_t n,
+                    const int64_t* boff, double* P, double* B, double* geom) {
   const int64_t r = (int64_t)L.max_n[0] * L.max_n[1] * L.max_n[2];
   hipLaunchKernelGGL(k_extract, dim3((unsigned)((r + NT - 1) / NT), L.nblk), dim3(NT), 0, L.stream,
-                     L, Pin, Bin, n, P, B, geom);
+                     L, Pin, Bin, n, boff, P, B, geom);
 }
 
 // ------------------------------------------------------------ batch inversion

@@ -267,3 +267,63 @@ def test_conserved_regrid_on_a_kerr_schild_sphere_matches_oracle():
     rel = float(abs(after[q] - before[q]).max() / abs(before[q]).max())
     say(f"  merge keeps the totals to {rel:.1e}")
     assert rel <= 1e-12
+
+
+def _grid_totals(grid):
+    """sum over interior cells of the conserved vector (mass, energy, momenta) times the
+    coordinate cell volume, from the device state"""
+    import torch
+
+    P, B, G = grid.extract_cells()
+    U = grmhd.prim2cons_batch(P, B, G, grid.cfg["gam"])
+    vols = []
+    L = [max(int(b.lev[d]) for b in grid.desc.blocks) for d in range(3)]
+    for b in grid.desc.blocks:
+        dv = 1.0
+        for d in range(3):
+            nl = grid.cfg["n"][d] >> (L[d] - int(b.lev[d]))
+            dv *= (grid.cfg["xhi"][d] - grid.cfg["xlo"][d]) / nl
+        vols.append(torch.full((int(b.n[0]) * int(b.n[1]) * int(b.n[2]),), dv,
+                               dtype=torch.float64, device=P.device))
+    return (U[:5] * torch.cat(vols)).sum(dim=1).cpu().numpy()
+
+
+def test_full_size_conserved_regrid_keeps_the_totals():
+    """the 1344-block torus layout after a cycle, its polar caps refined in phi and
+    merged back with the conserved form: the totals of mass, energy and momenta over the
+    whole grid are kept to rounding both ways"""
+    cfg = dict(configs.TORUS_AMR3)
+    blocks = configs.amr_lat_blocks(cfg["n"], lat_edges=cfg["lat_edges"])
+    lmax = [max(b["lev"][d] for b in blocks) for d in range(3)]
+    say("[regrid] full-size conserved form: building the state")
+    state = initdata.torus_state(cfg["n"], **configs.TORUS_INIT)
+    bs = initdata.block_states(state, blocks, lmax)
+    del state
+    g = grmhd.Grid(cfg, blocks=blocks, batched=1)
+    g.set_blocks(bs)
+    g.step(1, stats=False)
+    t0 = _grid_totals(g)
+    g2 = g.regrid(configs.refine_caps_phi(blocks), conserved=True)
+    del g
+    t1 = _grid_totals(g2)
+    g3 = g2.regrid(blocks, conserved=True)
+    t2 = _grid_totals(g3)
+    for a, b, what in ((t0, t1, "refined"), (t1, t2, "merged back")):
+        rel = float(abs(b - a).max() / abs(a).max())
+        say(f"  {what}: totals kept to {rel:.1e}")
+        assert rel <= 1e-12
+
+
+def test_extract_cells_on_blocks_of_uneven_sizes():
+    """grmhd_extract_cells on a layout whose blocks differ in size: the primitives come out
+    in block order (k, j, i within a block), equal to the blocks' own interiors"""
+    import numpy as np
+
+    N = (16, 16, 8)
+    cfg = _mink(N)
+    old = halves(N, (1, 1, 1), True)      # 8x16x8 fine and 4x8x4 coarse cells
+    g = grmhd.Grid(cfg, blocks=old)
+    g.set_blocks(initdata.block_states(random_periodic_state(N, seed=4), old, (1, 1, 1)))
+    P, B, G = g.extract_cells()
+    want = np.concatenate([st[0].reshape(5, -1) for st in g.get_blocks()], axis=1)
+    assert np.array_equal(P.cpu().numpy(), want)
