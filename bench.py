@@ -337,12 +337,39 @@ def regrid_leg(cfg, blocks, bs, sync, log):
     cells = sum(bb["n"][0] * bb["n"][1] * bb["n"][2] for bb in fine)
     log(f"[bench] regrid: caps refined in {t_up * 1e3:.1f} ms, back in {t_down * 1e3:.1f} ms, "
         f"new context {t_init:.2f} s, round trip {err:.1e}")
-    del g, g2, g3
+    del g2, g3
+    # the density criterion on the evolved headline state: blocks whose densest cell
+    # exceeds 0.5 split (a new finest level), the nesting rules split more; the decision,
+    # the regrid and a cycle on the new layout
+    from paper_1912_10192_amd import adapt
+
+    t0 = time.perf_counter()
+    rho = adapt.block_max(g)
+    new = adapt.Layout(cfg, blocks).refine([1 if r > 0.5 else 0 for r in rho], max_level=3)
+    t_decide = time.perf_counter() - t0
+    plain = [{k: v for k, v in bb.items() if k != "parent"} for bb in new]
+    t0 = time.perf_counter()
+    g4 = g.regrid(plain)
+    sync()
+    t_adapt = time.perf_counter() - t0
+    st4 = g4.step(1, stats=True)
+    cells4 = sum(bb["n"][0] * bb["n"][1] * bb["n"][2] for bb in plain)
+    eff4 = list(g4.cfg["n"])
+    log(f"[bench] density criterion: {sum(1 for r in rho if r > 0.5)} blocks flagged, "
+        f"{len(plain)} blocks after nesting, decided in {t_decide:.2f} s, new context and "
+        f"regrid {t_adapt:.2f} s")
+    del g, g4
     return {"layout": "headline layout <-> polar caps refined in phi (levels (0,0,0) -> (0,0,1))",
             "cells_refined_layout": cells, "context_setup_s": t_init,
             "regrid_refine_ms": t_up * 1e3, "regrid_derefine_ms": t_down * 1e3,
             "round_trip_max_rel": err, "divb_rel_refined": div_rel,
-            "bad_states_next_cycle": st.bad_states}
+            "bad_states_next_cycle": st.bad_states,
+            "density_criterion": {"threshold": 0.5, "flagged": sum(1 for r in rho if r > 0.5),
+                                  "blocks_after": len(plain), "cells_after": cells4,
+                                  "effective_grid_after": eff4,
+                                  "decide_s": t_decide, "context_and_regrid_s": t_adapt,
+                                  "bad_states_next_cycle": st4.bad_states,
+                                  "dt_min_next_cycle": st4.dt_min}}
 
 
 def disk_leg(args, blob, sync, log):

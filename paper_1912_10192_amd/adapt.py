@@ -38,6 +38,71 @@ class Layout:
 
     # ------------------------------------------------------------------ contacts
     def violations(self, blocks):
+        """pairs (b, s) where block s meets block b's box grown by ng cells of b's levels
+        (across the polar axis mirrored to phi + pi, along phi periodic, clipped at the x1
+        ends) and the two are more than one level apart in a dimension, finer in one and
+        coarser in another, or at different levels across the axis.  The grown box holds
+        every ghost cell the planner builds, so these pairs include all it would refuse;
+        one pass over all blocks at once (violations_cells checks cell by cell)."""
+        import numpy as np
+
+        L = _lmax(blocks)
+        Nf = np.array([self.N0[d] << L[d] for d in range(3)])
+        lev = np.array([b["lev"] for b in blocks])
+        org = np.array([b["org"] for b in blocks])
+        n = np.array([b["n"] for b in blocks])
+        sh = np.array(L)[None, :] - lev
+        lo = org << sh
+        hi = (org + n) << sh
+        g = self.cfg["ng"]
+        glo = lo - (g << sh)
+        ghi = hi + (g << sh)
+        glo[:, 0] = np.maximum(glo[:, 0], 0)
+        ghi[:, 0] = np.minimum(ghi[:, 0], Nf[0])
+        polar = self.cfg["bc"][2] == BC_POLAR
+        bad = set()
+
+        def overlap(alo, ahi, axis_flag):
+            """blocks meeting the boxes [alo, ahi) (one per row of blocks), phi periodic"""
+            hit = np.ones((len(blocks), len(blocks)), dtype=bool)
+            for d in range(3):
+                a0, a1 = alo[:, d][:, None], ahi[:, d][:, None]
+                b0, b1 = lo[:, d][None, :], hi[:, d][None, :]
+                t = (a0 < b1) & (b0 < a1)
+                if d == 2 or self.cfg["bc"][2 * d] == BC_PERIODIC:
+                    N = Nf[d]
+                    t = t | ((a0 - N < b1) & (b0 < a1 - N)) | ((a0 + N < b1) & (b0 < a1 + N))
+                hit &= t
+            np.fill_diagonal(hit, False) if not axis_flag else None
+            for i, j in zip(*np.nonzero(hit)):
+                r = lev[j] - lev[i]
+                if (np.abs(r).max() > 1 or (r.max() > 0 and r.min() < 0)
+                        or (axis_flag and np.abs(r).max() > 0)):
+                    bad.add((int(i), int(j)))
+
+        if polar:
+            inner = (np.maximum(glo[:, 1], 0), np.minimum(ghi[:, 1], Nf[1]))
+            a_lo, a_hi = glo.copy(), ghi.copy()
+            a_lo[:, 1], a_hi[:, 1] = inner
+            overlap(a_lo, a_hi, False)
+            h = Nf[2] // 2
+            for side in (0, 1):
+                beyond = glo[:, 1] < 0 if side == 0 else ghi[:, 1] > Nf[1]
+                if not beyond.any():
+                    continue
+                m_lo, m_hi = glo.copy(), ghi.copy()
+                if side == 0:
+                    m_lo[:, 1], m_hi[:, 1] = 0, np.where(beyond, -glo[:, 1], 0)
+                else:
+                    m_lo[:, 1], m_hi[:, 1] = np.where(beyond, 2 * Nf[1] - ghi[:, 1], Nf[1]), Nf[1]
+                m_lo[:, 2] += h
+                m_hi[:, 2] += h
+                overlap(m_lo, m_hi, True)
+        else:
+            overlap(glo, ghi, False)
+        return sorted(bad)
+
+    def violations_cells(self, blocks):
         """pairs (b, s) where a ghost cell of block b (ng deep at b's levels; across the
         polar axis mirrored to phi + pi, along phi periodic, beyond the x1 ends clamped)
         lies in block s and the two are more than one level apart in a dimension, finer
@@ -110,10 +175,12 @@ class Layout:
             bad = self.violations(blocks)
             if not bad:
                 return blocks
-            # split the coarser block of the first offending pair
-            a, c = bad[0]
-            ca = sum(blocks[a]["lev"]) < sum(blocks[c]["lev"])
-            blocks = self.split(blocks, a if ca else c)
+            # split the coarser block of every offending pair (each once), then look again
+            coarse = set()
+            for a, c in bad:
+                coarse.add(a if sum(blocks[a]["lev"]) < sum(blocks[c]["lev"]) else c)
+            for i in sorted(coarse, reverse=True):
+                blocks = self.split(blocks, i)
         raise RuntimeError("nesting not reached")
 
     def coarsen(self, blocks, flags):

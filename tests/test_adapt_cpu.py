@@ -82,3 +82,19 @@ def test_merge_that_would_break_nesting_is_skipped():
     flags = [-1 if b.get("parent") is lay.blocks[i] else 0 for b in twice]
     out = lay2.coarsen(twice, flags)
     assert not lay2.violations(out)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_grown_box_check_covers_the_cell_by_cell_check(seed):
+    """the one-pass check (each block's box grown by its ghost depth) finds every pair the
+    cell-by-cell emulation of the planner's ghost rules finds, on layouts with nesting
+    violations planted by splitting random blocks twice without repair"""
+    rng = np.random.default_rng(seed)
+    for cfg, blocks in (_torus_bands(), (ks_sphere((16, 16, 8)), polar_quarters((16, 16, 8)))):
+        lay = adapt.Layout(cfg, blocks)
+        bl = list(lay.blocks)
+        for _ in range(2):
+            i = int(rng.integers(len(bl)))
+            bl = lay.split(bl, i)
+        fast, exact = set(lay.violations(bl)), set(lay.violations_cells(bl))
+        assert exact <= fast, (exact - fast)
