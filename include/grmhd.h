@@ -231,6 +231,13 @@ typedef struct {
 } grmhd_c2p_batch;
 int grmhd_cons2prim(grmhd_ctx* ctx, const grmhd_c2p_batch* batch, void* hip_stream);
 
+/* Each block's own Courant step (Sec. 2.1, Sec. 3.5: the local Courant condition that
+ * sets a block's time level), C0 times the minimum over its interior cells of
+ * 1/sum_d(v_d/dx_d), without the block's time-level factor; written to dt (host,
+ * n_blocks doubles).  Synchronises.  GRMHD_ESTATE when the state is not in the caller's
+ * buffers. */
+int grmhd_block_dt(grmhd_ctx* ctx, double* dt);
+
 /* Discrete divergence of the face field over all interior cells:
  * sum_d (Bbar^d_+ - Bbar^d_-)/dx^d.  Writes max |div| and max |div| / (sum_d
  * (|Bbar^d_+| + |Bbar^d_-|)/dx^d) to host scalars (synchronises), the relative form over

@@ -37,13 +37,10 @@ class Layout:
         return tuple(self.N0[d] << L[d] for d in range(3))
 
     # ------------------------------------------------------------------ contacts
-    def violations(self, blocks):
-        """pairs (b, s) where block s meets block b's box grown by ng cells of b's levels
-        (across the polar axis mirrored to phi + pi, along phi periodic, clipped at the x1
-        ends) and the two are more than one level apart in a dimension, finer in one and
-        coarser in another, or at different levels across the axis.  The grown box holds
-        every ghost cell the planner builds, so these pairs include all it would refuse;
-        one pass over all blocks at once (violations_cells checks cell by cell)."""
+    def contacts(self, blocks):
+        """(b, s, across_axis) for every block s that meets block b's box grown by ng
+        cells of b's levels (across the polar axis mirrored to phi + pi, along phi
+        periodic, clipped at the x1 ends): every block b's ghost cells can come from"""
         import numpy as np
 
         L = _lmax(blocks)
@@ -59,11 +56,9 @@ class Layout:
         ghi = hi + (g << sh)
         glo[:, 0] = np.maximum(glo[:, 0], 0)
         ghi[:, 0] = np.minimum(ghi[:, 0], Nf[0])
-        polar = self.cfg["bc"][2] == BC_POLAR
-        bad = set()
+        out = []
 
-        def overlap(alo, ahi, axis_flag):
-            """blocks meeting the boxes [alo, ahi) (one per row of blocks), phi periodic"""
+        def overlap(alo, ahi, across):
             hit = np.ones((len(blocks), len(blocks)), dtype=bool)
             for d in range(3):
                 a0, a1 = alo[:, d][:, None], ahi[:, d][:, None]
@@ -73,17 +68,13 @@ class Layout:
                     N = Nf[d]
                     t = t | ((a0 - N < b1) & (b0 < a1 - N)) | ((a0 + N < b1) & (b0 < a1 + N))
                 hit &= t
-            np.fill_diagonal(hit, False) if not axis_flag else None
-            for i, j in zip(*np.nonzero(hit)):
-                r = lev[j] - lev[i]
-                if (np.abs(r).max() > 1 or (r.max() > 0 and r.min() < 0)
-                        or (axis_flag and np.abs(r).max() > 0)):
-                    bad.add((int(i), int(j)))
+            if not across:
+                np.fill_diagonal(hit, False)
+            out.extend((int(i), int(j), across) for i, j in zip(*np.nonzero(hit)))
 
-        if polar:
-            inner = (np.maximum(glo[:, 1], 0), np.minimum(ghi[:, 1], Nf[1]))
+        if self.cfg["bc"][2] == BC_POLAR:
             a_lo, a_hi = glo.copy(), ghi.copy()
-            a_lo[:, 1], a_hi[:, 1] = inner
+            a_lo[:, 1], a_hi[:, 1] = np.maximum(glo[:, 1], 0), np.minimum(ghi[:, 1], Nf[1])
             overlap(a_lo, a_hi, False)
             h = Nf[2] // 2
             for side in (0, 1):
@@ -100,7 +91,38 @@ class Layout:
                 overlap(m_lo, m_hi, True)
         else:
             overlap(glo, ghi, False)
+        return out
+
+    def violations(self, blocks):
+        """pairs (b, s) from contacts() more than one level apart in a dimension, finer in
+        one and coarser in another, or at different levels across the axis.  The grown
+        box holds every ghost cell the planner builds, so these pairs include all it
+        would refuse (violations_cells checks cell by cell)"""
+        bad = set()
+        for i, j, across in self.contacts(blocks):
+            r = [blocks[j]["lev"][d] - blocks[i]["lev"][d] for d in range(3)]
+            if (max(abs(x) for x in r) > 1 or (max(r) > 0 and min(r) < 0)
+                    or (across and any(r))):
+                bad.add((i, j))
         return sorted(bad)
+
+    def time_levels(self, blocks, dt, nlev):
+        """time levels from each block's Courant step (Sec. 3.5): the largest l below nlev
+        with 2^l dt_min <= dt_b, then lowered until blocks in contact differ by at most
+        one level"""
+        import math
+
+        dmin = min(dt)
+        lat = [min(nlev - 1, int(math.floor(math.log2(d / dmin) + 1e-12))) for d in dt]
+        pairs = [(i, j) for i, j, _ in self.contacts(blocks) if i != j]
+        changed = True
+        while changed:
+            changed = False
+            for i, j in pairs:
+                if lat[i] > lat[j] + 1:
+                    lat[i] = lat[j] + 1
+                    changed = True
+        return lat
 
     def violations_cells(self, blocks):
         """pairs (b, s) where a ghost cell of block b (ng deep at b's levels; across the
@@ -234,11 +256,15 @@ class AdaptiveGrid:
     densest cell lies below rho_coarsen are merged."""
 
     def __init__(self, cfg, blocks, states, rho_refine, rho_coarsen, every=1, max_level=2,
-                 batched=1, pool_sizes=None):
+                 batched=1, pool_sizes=None, lat_levels=None):
         """pool_sizes: (prim, bface, work) element counts of the largest layout to expect;
         two buffer sets of that size are then allocated once, and the grid alternates
         between them at every regrid (the old layout's set is free again once the regrid
-        has filled the new one), so regrids allocate no device memory for the state"""
+        has filled the new one), so regrids allocate no device memory for the state.
+        lat_levels: assign the new layout's time levels (at most that many) from the
+        blocks' Courant steps at each regrid (a child takes half its parent's step, a
+        merged parent twice its children's smallest); None keeps the levels the blocks
+        had (children inherit theirs)"""
         self.layout = Layout(cfg, blocks)
         self.pools = None
         if pool_sizes is not None:
@@ -255,6 +281,7 @@ class AdaptiveGrid:
         self.grid.set_blocks(states)
         self.rho_refine, self.rho_coarsen = rho_refine, rho_coarsen
         self.every, self.max_level = every, max_level
+        self.lat_levels = lat_levels
         self.cycles = 0
         self.history = []
 
@@ -267,12 +294,36 @@ class AdaptiveGrid:
         flags2 = [idx.get(id(b), 0) for b in blocks]
         return self.layout.coarsen(blocks, flags2)
 
+    def _with_time_levels(self, new):
+        """the new layout with time levels from the Courant steps of the current grid's
+        blocks (children half their parent's, merged parents twice their children's
+        smallest)"""
+        dt_old = {id(b): d for b, d in zip(self.layout.blocks, self.grid.block_dt())}
+        dts = []
+        for b in new:
+            if id(b) in dt_old:
+                dts.append(dt_old[id(b)])
+            elif "parent" in b and id(b["parent"]) in dt_old:
+                dts.append(0.5 * dt_old[id(b["parent"])])
+            else:
+                kids = [dt_old[id(o)] for o in self.layout.blocks if o.get("parent") is b]
+                dts.append(2.0 * min(kids))
+        lat = self.layout.time_levels(new, dts, self.lat_levels)
+        out = []
+        for b, l in zip(new, lat):
+            b2 = dict(b)
+            b2["lat"] = l
+            out.append(b2)
+        return out
+
     def adapt(self, blocks=None):
         """regrid to `blocks`, or to the criterion's layout; returns whether it changed"""
         new = blocks if blocks is not None else self.decide()
         key = lambda bl: [(b["lev"], b["org"], b["n"]) for b in bl]
         if key(new) == key(self.layout.blocks):
             return False
+        if self.lat_levels is not None:
+            new = self._with_time_levels(new)
         plain = [{k: v for k, v in b.items() if k != "parent"} for b in new]
         if self.pools:
             nxt = 1 - self.active

@@ -2470,6 +2470,35 @@ int grmhd_cons2prim(grmhd_ctx* c, const grmhd_c2p_batch* b, void* hip_stream) {
   return GRMHD_OK;
 }
 
+int grmhd_block_dt(grmhd_ctx* c, double* dt) {
+  if (!c || !dt) return fail(GRMHD_EINVAL, "NULL argument");
+  if (c->b_in_alt) return fail(GRMHD_ESTATE, "state not in the caller's buffers");
+  const Plan& p = c->plan;
+  const Launch& L = c->L;
+  const int64_t np = launch_dt(L, c->bufs.prim, c->bufs.bface, c->dtp, true);
+  HIPCHK(hipGetLastError());
+  std::vector<double> part(np);
+  HIPCHK(hipMemcpyAsync(part.data(), c->dtp, sizeof(double) * np, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const size_t nb = p.blocks.size();
+  std::vector<double> m(nb, INFINITY);
+  if (L.wls[WL_CELLS]) {
+    const int64_t o = p.wl_off[(size_t)p.nlev * WL_N + WL_CELLS];
+    for (int64_t i = 0; i < np; i++) {
+      const int b = p.wl[o + i].x;
+      m[b] = std::min(m[b], part[i]);
+    }
+  } else {
+    const int64_t gx = np / std::max<int64_t>((int64_t)nb, 1);
+    for (int64_t i = 0; i < np; i++) {
+      const size_t b = (size_t)(i / gx);
+      if (b < nb) m[b] = std::min(m[b], part[i]);
+    }
+  }
+  for (size_t b = 0; b < nb; b++) dt[b] = p.d.courant * m[b];
+  return GRMHD_OK;
+}
+
 int grmhd_divb(grmhd_ctx* c, double* max_abs, double* max_rel, double* field) {
   if (!c) return fail(GRMHD_EINVAL, "NULL context");
   launch_counters_reset(c->L, false);

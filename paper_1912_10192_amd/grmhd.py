@@ -33,7 +33,7 @@ EXPORTS = ("grmhd_sizes", "grmhd_block_layout", "grmhd_init_grid", "grmhd_step",
            "grmhd_mlp_forward", "grmhd_prim2cons_batch", "grmhd_mlp_dataset",
            "grmhd_mlp_normalize", "grmhd_extract_cells", "grmhd_destroy", "grmhd_last_error",
            "grmhd_autotune", "grmhd_set_variants", "grmhd_mlp_train_step_noalloc",
-           "grmhd_regrid")
+           "grmhd_regrid", "grmhd_block_dt")
 
 
 class BlockDesc(C.Structure):
@@ -128,6 +128,7 @@ def lib():
         L.grmhd_extract_cells.argtypes = [vp, vp, vp, vp]
         L.grmhd_destroy.argtypes = [C.c_void_p]
         L.grmhd_regrid.argtypes = [C.c_void_p, C.c_void_p, C.c_int32]
+        L.grmhd_block_dt.argtypes = [C.c_void_p, C.c_void_p]
         L.grmhd_last_error.restype = C.c_char_p
         _lib = L
     return _lib
@@ -445,6 +446,12 @@ class Grid:
                    pool=pool)
         _check(lib().grmhd_regrid(self.ctx, new.ctx, REGRID_CONSERVED if conserved else REGRID_PRIMITIVE))
         return new
+
+    def block_dt(self):
+        """each block's own Courant step (grmhd_block_dt), as a numpy array"""
+        out = np.zeros(len(self.desc.blocks))
+        _check(lib().grmhd_block_dt(self.ctx, out.ctypes.data_as(C.c_void_p)))
+        return out
 
     def divb(self):
         a, r = C.c_double(), C.c_double()

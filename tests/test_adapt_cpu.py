@@ -98,3 +98,21 @@ def test_grown_box_check_covers_the_cell_by_cell_check(seed):
             bl = lay.split(bl, i)
         fast, exact = set(lay.violations(bl)), set(lay.violations_cells(bl))
         assert exact <= fast, (exact - fast)
+
+
+def test_time_levels_from_courant_steps_keep_contacts_within_one_level():
+    """time levels from per-block Courant steps: the largest level whose step fits, then
+    lowered where blocks in contact would differ by more than one; the layout with these
+    levels is one the planner accepts"""
+    cfg, blocks = _torus_bands()
+    lay = adapt.Layout(cfg, blocks)
+    rng = np.random.default_rng(3)
+    new = lay.refine([1 if b["lev"] == (1, 1, 1) else 0 for b in blocks], max_level=3)
+    dt = list(0.01 * 2.0 ** rng.uniform(0, 5, len(new)))
+    lat = lay.time_levels(new, dt, 4)
+    dmin = min(dt)
+    for l, d in zip(lat, dt):
+        assert 0 <= l <= 3 and 2 ** l * dmin <= d * (1 + 1e-12)
+    for i, j, _ in lay.contacts(new):
+        assert abs(lat[i] - lat[j]) <= 1
+    _accepts(cfg, lay, [dict(b, lat=l) for b, l in zip(new, lat)])

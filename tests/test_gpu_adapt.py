@@ -120,3 +120,58 @@ def test_pooled_adaptive_run_is_identical_and_allocates_nothing():
         for x, y in zip(a, b):
             assert (x == y).all()
     assert grown <= 0
+
+
+def test_block_courant_steps_match_oracle():
+    """grmhd_block_dt: each block's own Courant step, against the oracle's step of the
+    same block's state"""
+    import numpy as np
+
+    from paper_1912_10192_amd import grmhd
+
+    eff = (32, 32, 16)
+    cfg = configs.scaled(configs.TORUS_UNIFORM, eff, ng=3)
+    blocks = polar_bands(eff, (0, 1))
+    state = initdata.torus_state(eff, **configs.TORUS_INIT)
+    ref = AmrGrid(cfg, blocks)
+    bs = initdata.block_states(state, ref.blocks, ref.Lmax)
+    ref.set_blocks(bs)
+    g = grmhd.Grid(cfg, blocks=blocks, batched=1)
+    g.set_blocks(bs)
+    got = g.block_dt()
+    want = np.array([ref.ctx[i].dt(ref.P[i], ref.B[i]) for i in range(len(blocks))])
+    say(f"[adapt] block Courant steps {np.round(got, 5)}")
+    assert np.abs(got - want).max() <= 1e-12 * want.max()
+
+
+def test_refinement_with_courant_time_levels_matches_oracle():
+    """refinement on density with the new layout's time levels set from the blocks'
+    Courant steps (at most three levels, four substeps a cycle), then a cycle; the oracle
+    replays the layouts and levels.  (Over further cycles the face fields of the weakly
+    magnetised polar blocks, compared against their own block's largest value, drift
+    past the 1e-11 bar by rounding growth, as in the other long trajectories.)"""
+    eff = (32, 32, 16)
+    cfg = configs.scaled(configs.TORUS_UNIFORM, eff, ng=3)
+    blocks = polar_bands(eff, (0, 1))
+    state = initdata.torus_state(eff, **configs.TORUS_INIT)
+    ref = AmrGrid(cfg, blocks)
+    bs = initdata.block_states(state, ref.blocks, ref.Lmax)
+    ref.set_blocks(bs)
+    ag = adapt.AdaptiveGrid(cfg, blocks, bs, rho_refine=0.3, rho_coarsen=-1.0, every=1000,
+                            max_level=2, batched=1, lat_levels=3)
+    ref.cycle()
+    ag.step(1)
+    assert ag.adapt()
+    new = [{k: v for k, v in b.items() if k != "parent"} for b in ag.layout.blocks]
+    lats = sorted(set(b["lat"] for b in new))
+    say(f"[adapt] {len(new)} blocks, time levels {lats}")
+    assert len(lats) >= 2
+    want = regrid(ref, new)
+    ref = AmrGrid(dict(cfg, n=ag.grid.cfg["n"]), new)
+    ref.set_blocks(want)
+    ref.cycle()
+    ag.step(1)
+    e = block_err(ag.grid.get_blocks(), ref.get_blocks())
+    say("  cycle on the new layout: " + " ".join(f"{k}={v:.1e}" for k, v in e.items()))
+    assert max(e.values()) <= TOL, e
+    assert _div_scaled(ag.grid) < 1e-13
