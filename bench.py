@@ -345,9 +345,14 @@ def regrid_leg(cfg, blocks, bs, sync, log):
 
     t0 = time.perf_counter()
     rho = adapt.block_max(g)
-    new = adapt.Layout(cfg, blocks).refine([1 if r > 0.5 else 0 for r in rho], max_level=3)
+    lay = adapt.Layout(cfg, blocks)
+    new = lay.refine([1 if r > 0.5 else 0 for r in rho], max_level=3)
+    # time levels from the blocks' Courant steps (a child half its parent's), at most 5
+    dt_old = {id(b): d for b, d in zip(lay.blocks, g.block_dt())}
+    dts = [dt_old[id(b)] if id(b) in dt_old else 0.5 * dt_old[id(b["parent"])] for b in new]
+    lats = lay.time_levels(new, dts, 5)
     t_decide = time.perf_counter() - t0
-    plain = [{k: v for k, v in bb.items() if k != "parent"} for bb in new]
+    plain = [dict({k: v for k, v in bb.items() if k != "parent"}, lat=l) for bb, l in zip(new, lats)]
     t0 = time.perf_counter()
     g4 = g.regrid(plain)
     sync()
@@ -356,8 +361,8 @@ def regrid_leg(cfg, blocks, bs, sync, log):
     cells4 = sum(bb["n"][0] * bb["n"][1] * bb["n"][2] for bb in plain)
     eff4 = list(g4.cfg["n"])
     log(f"[bench] density criterion: {sum(1 for r in rho if r > 0.5)} blocks flagged, "
-        f"{len(plain)} blocks after nesting, decided in {t_decide:.2f} s, new context and "
-        f"regrid {t_adapt:.2f} s")
+        f"{len(plain)} blocks after nesting, time levels {sorted(set(lats))}, decided in "
+        f"{t_decide:.2f} s, new context and regrid {t_adapt:.2f} s")
     del g, g4
     return {"layout": "headline layout <-> polar caps refined in phi (levels (0,0,0) -> (0,0,1))",
             "cells_refined_layout": cells, "context_setup_s": t_init,
@@ -367,6 +372,7 @@ def regrid_leg(cfg, blocks, bs, sync, log):
             "density_criterion": {"threshold": 0.5, "flagged": sum(1 for r in rho if r > 0.5),
                                   "blocks_after": len(plain), "cells_after": cells4,
                                   "effective_grid_after": eff4,
+                                  "time_levels_after": [lats.count(l) for l in range(max(lats) + 1)],
                                   "decide_s": t_decide, "context_and_regrid_s": t_adapt,
                                   "bad_states_next_cycle": st4.bad_states,
                                   "dt_min_next_cycle": st4.dt_min}}
