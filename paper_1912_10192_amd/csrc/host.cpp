@@ -200,7 +200,7 @@ struct Plan {
   bool refined = false;         // blocks at more than one refinement level
   std::vector<GeoTable> tables;
   int64_t ncol = 0;
-  std::vector<int32_t> owner;   // block id per effective (finest-level) cell
+  BigVec<int32_t> owner;   // block id per effective (finest-level) cell
   BigVec<GhostOp> ops[4];  // cells, x1 faces, x2 faces, x3 faces (by dst level, then block)
   BigVec<AmrOp> aops[4];   // ghost values across refinement levels (ordered likewise)
   BigVec<AmrSample> samples;   // in block order
@@ -882,11 +882,15 @@ void build_slow(Plan& p) {
   p.slow_f.clear();
   p.slow_c_off.assign(L + 1, 0);
   p.slow_f_off.assign(L + 1, 0);
+  // the lists of each level and kind sorted side by side (independent of each other)
+  parallel_for(2 * L, [&](int64_t t) {
+    std::vector<uint32_t>& v = (t & 1) ? sf[t >> 1] : sc[t >> 1];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  });
   for (int l = 0; l < L; l++) {
     for (int w = 0; w < 2; w++) {
-      std::vector<uint32_t>& v = w ? sf[l] : sc[l];
-      std::sort(v.begin(), v.end());
-      v.erase(std::unique(v.begin(), v.end()), v.end());
+      const std::vector<uint32_t>& v = w ? sf[l] : sc[l];
       std::vector<uint32_t>& out = w ? p.slow_f : p.slow_c;
       out.insert(out.end(), v.begin(), v.end());
     }
@@ -1481,21 +1485,37 @@ int build_plan(const grmhd_grid_desc* desc, Plan& p, bool with_maps) {
   // ownership of effective cells; every cell must be covered exactly once
   const int64_t N1 = desc->n_eff[0], N2 = desc->n_eff[1], N3 = desc->n_eff[2];
   if (N1 * N2 * N3 > (int64_t(1) << 31)) return fail(GRMHD_EINVAL, "effective grid too large");
-  p.owner.assign((size_t)(N1 * N2 * N3), -1);
-  int64_t covered = 0;
+  // The blocks' volumes must add up to the grid's; the blocks then fill the map in
+  // parallel (rows of effective cells), and a cell left unfilled means that two blocks
+  // overlap or that one is missing.
+  int64_t vol = 0;
   for (int b = 0; b < nb; b++) {
     const grmhd_block_desc& bd = p.blocks[b];
-    const int s0 = p.lmax[0] - bd.lev[0], s1 = p.lmax[1] - bd.lev[1], s2 = p.lmax[2] - bd.lev[2];
-    for (int64_t k = bd.org[2] << s2; k < (bd.org[2] + bd.n[2]) << s2; k++)
-      for (int64_t j = bd.org[1] << s1; j < (bd.org[1] + bd.n[1]) << s1; j++)
-        for (int64_t i = bd.org[0] << s0; i < (bd.org[0] + bd.n[0]) << s0; i++) {
-          int32_t& o = p.owner[(size_t)((k * N2 + j) * N1 + i)];
-          if (o != -1) return fail(GRMHD_EINVAL, "blocks overlap");
-          o = b;
-          covered++;
-        }
+    int64_t v = 1;
+    for (int d = 0; d < 3; d++) v *= (int64_t)bd.n[d] << (p.lmax[d] - bd.lev[d]);
+    vol += v;
   }
-  if (covered != N1 * N2 * N3) return fail(GRMHD_EINVAL, "blocks do not tile the grid");
+  if (vol != N1 * N2 * N3) return fail(GRMHD_EINVAL, "blocks do not tile the grid");
+  p.owner.resize((size_t)(N1 * N2 * N3));
+  parallel_for(N3, [&](int64_t k) {
+    std::fill(p.owner.begin() + (size_t)(k * N2 * N1), p.owner.begin() + (size_t)((k + 1) * N2 * N1), -1);
+  });
+  parallel_for(nb, [&](int64_t b) {
+    const grmhd_block_desc& bd = p.blocks[b];
+    const int s0 = p.lmax[0] - bd.lev[0], s1 = p.lmax[1] - bd.lev[1], s2 = p.lmax[2] - bd.lev[2];
+    const int64_t i0 = bd.org[0] << s0, i1 = (bd.org[0] + bd.n[0]) << s0;
+    for (int64_t k = bd.org[2] << s2; k < (bd.org[2] + bd.n[2]) << s2; k++)
+      for (int64_t j = bd.org[1] << s1; j < (bd.org[1] + bd.n[1]) << s1; j++) {
+        const size_t row = (size_t)((k * N2 + j) * N1);
+        std::fill(p.owner.begin() + row + i0, p.owner.begin() + row + i1, (int32_t)b);
+      }
+  });
+  std::atomic<bool> hole{false};
+  parallel_for(N3, [&](int64_t k) {
+    const auto a = p.owner.begin() + (size_t)(k * N2 * N1);
+    if (std::find(a, a + (size_t)(N2 * N1), -1) != a + (size_t)(N2 * N1)) hole = true;
+  });
+  if (hole) return fail(GRMHD_EINVAL, "blocks overlap");
   if (with_maps) {
     if ((rc = build_ops(p))) return rc;
   }
