@@ -348,9 +348,7 @@ def regrid_leg(cfg, blocks, bs, sync, log):
     lay = adapt.Layout(cfg, blocks)
     new = lay.refine([1 if r > 0.5 else 0 for r in rho], max_level=3)
     # time levels from the blocks' Courant steps (a child half its parent's), at most 5
-    dt_old = {id(b): d for b, d in zip(lay.blocks, g.block_dt())}
-    dts = [dt_old[id(b)] if id(b) in dt_old else 0.5 * dt_old[id(b["parent"])] for b in new]
-    lats = lay.time_levels(new, dts, 5)
+    lats = lay.time_levels(new, adapt.estimate_steps(lay.blocks, g.block_dt(), new), 5)
     t_decide = time.perf_counter() - t0
     plain = [dict({k: v for k, v in bb.items() if k != "parent"}, lat=l) for bb, l in zip(new, lats)]
     t0 = time.perf_counter()

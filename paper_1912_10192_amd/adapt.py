@@ -236,6 +236,27 @@ class Layout:
         return out
 
 
+def estimate_steps(old, dt_old, new):
+    """Courant steps of the blocks of a new layout from those of the old one: a block
+    kept keeps its step, a child takes half of its nearest ancestor's in the old layout
+    per generation between them, a merged parent twice the smallest of its children's"""
+    by_id = {id(b): d for b, d in zip(old, dt_old)}
+    out = []
+    for b in new:
+        if id(b) in by_id:
+            out.append(by_id[id(b)])
+            continue
+        a, f = b, 1.0
+        while "parent" in a and id(a) not in by_id:
+            a, f = a["parent"], 0.5 * f
+        if id(a) in by_id:
+            out.append(f * by_id[id(a)])
+            continue
+        kids = [by_id[id(o)] for o in old if o.get("parent") is b]
+        out.append(2.0 * min(kids))
+    return out
+
+
 def block_max(grid, var=0):
     """per-block maximum of a primitive over the interior cells, from the device state"""
     torch = grid.torch
@@ -296,18 +317,8 @@ class AdaptiveGrid:
 
     def _with_time_levels(self, new):
         """the new layout with time levels from the Courant steps of the current grid's
-        blocks (children half their parent's, merged parents twice their children's
-        smallest)"""
-        dt_old = {id(b): d for b, d in zip(self.layout.blocks, self.grid.block_dt())}
-        dts = []
-        for b in new:
-            if id(b) in dt_old:
-                dts.append(dt_old[id(b)])
-            elif "parent" in b and id(b["parent"]) in dt_old:
-                dts.append(0.5 * dt_old[id(b["parent"])])
-            else:
-                kids = [dt_old[id(o)] for o in self.layout.blocks if o.get("parent") is b]
-                dts.append(2.0 * min(kids))
+        blocks (see estimate_steps)"""
+        dts = estimate_steps(self.layout.blocks, self.grid.block_dt(), new)
         lat = self.layout.time_levels(new, dts, self.lat_levels)
         out = []
         for b, l in zip(new, lat):

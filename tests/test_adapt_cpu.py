@@ -116,3 +116,25 @@ def test_time_levels_from_courant_steps_keep_contacts_within_one_level():
     for i, j, _ in lay.contacts(new):
         assert abs(lat[i] - lat[j]) <= 1
     _accepts(cfg, lay, [dict(b, lat=l) for b, l in zip(new, lat)])
+
+
+def test_step_estimates_follow_the_block_tree():
+    """kept blocks keep their Courant step, children (also grandchildren from nesting
+    splits) take half their ancestor's per generation, merged parents twice their
+    children's smallest"""
+    cfg, blocks = _torus_bands()
+    lay = adapt.Layout(cfg, blocks)
+    dt = [float(i + 1) for i in range(len(blocks))]
+    once = lay.refine([1 if i == 4 else 0 for i in range(len(blocks))], max_level=3)
+    est = adapt.estimate_steps(lay.blocks, dt, once)
+    for b, e in zip(once, est):
+        if b.get("parent") is lay.blocks[4]:
+            assert e == 0.5 * dt[4]
+        elif "parent" not in b:
+            assert e == dt[lay.blocks.index(b)]
+    kid = next(k for k, b in enumerate(once) if b.get("parent") is lay.blocks[4])
+    twice = lay.split(list(once), kid)
+    est2 = adapt.estimate_steps(lay.blocks, dt, twice)
+    assert 0.25 * dt[4] in est2
+    back = adapt.estimate_steps(once, est, lay.coarsen(once, [-1] * len(once)))
+    assert 2.0 * min(e for b, e in zip(once, est) if b.get("parent") is lay.blocks[4]) in back
