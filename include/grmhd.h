@@ -246,34 +246,36 @@ int grmhd_block_dt(grmhd_ctx* ctx, double* dt);
  * of variable 0. */
 int grmhd_divb(grmhd_ctx* ctx, double* max_abs, double* max_rel, double* field);
 
-/* Regrid (Sec. 3.3: blocks refined and derefined during a run): fills the interior
- * cells and faces of context `to` (a new block layout over the same domain, created by
- * grmhd_init_grid with its own buffers) from the state of context `from` at the end of
- * its last step.  Both layouts cover the same domain with the same level-0 grid
- * (n_eff >> lmax per dimension); the new one may add or drop a finest level, its n_eff
- * then doubled or halved.  Each new block is, in every dimension, at the level of each old block it
+/* Regrid (Sec. 3.3: blocks refined and derefined during a run).  Fills the interior
+ * cells and faces of context `to` (a new block layout, created by grmhd_init_grid with
+ * its own caller-owned buffers) from the state of context `from` at the end of its last
+ * step; both contexts stay the caller's.
+ * Layouts: both cover the same domain with the same level-0 grid (n_eff >> lmax per
+ * dimension); the new one may add or drop a finest level, its n_eff then doubled or
+ * halved.  Each new block is, in every dimension, at the level of each old block it
  * overlaps, one finer or one coarser (never finer in one dimension and coarser in
  * another), and where it is coarser the old block boundaries fall on its cell faces.
- * A new cell is copied from the old block covering it, restricted (sqrt(-g)-weighted
- * mean of the covered primitives) or prolonged (the parent's primitives plus +-1/4 of
- * the minmod-limited slope per refined dimension).  A new face is taken from the old
- * block covering the cell above it (below it for a block's upper face): copied,
- * restricted (mean of the fine sub-faces), or prolonged divergence-free (Balsara 2001):
- * a fine face on a parent face is the parent face plus +-1/4 of its minmod slopes in the
- * face's plane, a fine face inside a parent cell the face average of the parent cell's
- * divergence-free reconstruction, so every new cell keeps div B = 0.  mode
- * GRMHD_REGRID_CONSERVED (Sec. 3.3's conservative form) restricts and prolongs the
- * conserved vector instead where a cell is not copied: the mean of the covered cells'
- * U, or the parent's U/sqrt(-g) plus +-1/4 of its minmod slopes, moved by one common
- * amount in all children so that their U (times each child's sqrt(-g)) sum to the
- * parent's; the cell
- * field from the new faces; then the inversion (from the primitive form's value) and the
- * floors of `to`.  Mass, energy and momenta summed over the grid are then kept to the
- * inversion's tolerance.  The old context's
- * ghost values are refreshed first (its interior is not changed); the simulated time
- * carries over.  Synchronises both contexts' streams; allocates and frees a small
- * device table of boxes.  GRMHD_EINVAL for layouts that break the rules above,
- * GRMHD_ESTATE when `from` holds its state outside the caller's buffers. */
+ * Cells (mode GRMHD_REGRID_PRIMITIVE): copied from the old block covering the cell,
+ * restricted (sqrt(-g)-weighted mean of the covered primitives) or prolonged (the
+ * parent's primitives plus +-1/4 of the minmod-limited slope per refined dimension).
+ * Cells (mode GRMHD_REGRID_CONSERVED, the conservative form): where not copied, the
+ * conserved vector U is restricted (mean of the covered cells' U) or prolonged (the
+ * parent's U/sqrt(-g) plus +-1/4 of its minmod slopes, moved by one common amount in all
+ * children so that their U, times each child's sqrt(-g), sum to the parent's); the cell
+ * field comes from the new faces; then the inversion (from the primitive form's value)
+ * and the floors of `to`.  Mass, energy and momenta summed over the grid are then kept
+ * to the inversion's tolerance.
+ * Faces: taken from the old block covering the cell above the face (below it for a
+ * block's upper face): copied, restricted (mean of the fine sub-faces), or prolonged
+ * divergence-free (Balsara 2001): a fine face on a parent face is the parent face plus
+ * +-1/4 of its minmod slopes in the face's plane, a fine face inside a parent cell the
+ * face average of the parent cell's divergence-free reconstruction, so every new cell
+ * keeps div B = 0.
+ * The old context's ghost values are refreshed first (its interior is not changed); the
+ * simulated time carries over.  Synchronises both contexts' streams; allocates and frees
+ * a small device table of boxes.  GRMHD_EINVAL for layouts that break the rules above or
+ * an unknown mode, GRMHD_ESTATE when `from` holds its state outside the caller's
+ * buffers. */
 enum { GRMHD_REGRID_PRIMITIVE = 0, GRMHD_REGRID_CONSERVED = 1 };
 int grmhd_regrid(grmhd_ctx* from, grmhd_ctx* to, int32_t mode);
 
