@@ -97,6 +97,11 @@ def lib():
     if _lib is None:
         if not os.path.exists(SO_PATH):
             raise GrmhdError(f"{SO_PATH} is not built; run paper_1912_10192_amd.build.build()")
+        # torch first: the library then binds to the HIP runtime torch has loaded, so
+        # torch's streams and device memory are the library's (loaded the other way round,
+        # the process holds two runtimes and the library's calls on torch's streams fail)
+        import torch  # noqa: F401
+
         L = C.CDLL(SO_PATH)
         L.grmhd_sizes.argtypes = [C.POINTER(GridDesc), C.POINTER(C.c_size_t),
                                   C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]
@@ -356,7 +361,8 @@ class Grid:
         else:
             pp, pb, pw = pool
             if pp.numel() < nprim or pb.numel() < nbface or pw.numel() < nwork + 256:
-                raise GrmhdError("pool buffers smaller than the layout needs")
+                raise GrmhdError(f"pool buffers ({pp.numel()}, {pb.numel()}, {pw.numel()}) smaller "
+                                 f"than the layout needs ({nprim}, {nbface}, {nwork + 256})")
             self.prim, self.bface, self.work = pp[:nprim], pb[:nbface], pw[:nwork + 256]
             self.prim.zero_()
             self.bface.zero_()
